@@ -1,0 +1,320 @@
+"""Pins of the FP64 oracle against facts that do not come from the oracle.
+
+Each test names what fixes the expected value: a closed form, a brute-force or
+generic-QP solution, an identity of convex analysis, or a bound from Section 3
+/ Appendix C of the paper.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import kernel as kn
+from oracle import precond as pc
+from oracle import problem as pb
+from oracle import solver as sv
+from oracle import adjoint as adj
+from paper_2510_07929_amd import inputs
+from tests import pins
+
+
+def _tiny(n, p, seed, gamma=0.5):
+    X, y = inputs.smooth(n, p, (77, seed))
+    return X, y, kn.kernel_matrix(X, "rbf", gamma)
+
+
+# ------------------------------------------------------------------ kernels
+def test_kernel_closed_form_values():
+    # Section 1: k(x,x') = exp(-gamma ||x-x'||_2^2) and exp(-gamma ||x-x'||_1).
+    X = np.array([[0.0, 0.0], [3.0, 4.0], [1.0, -1.0]])
+    g = 0.1
+    K = kn.kernel_matrix(X, "rbf", g)
+    assert K[0, 1] == pytest.approx(math.exp(-0.1 * 25.0), rel=1e-15)
+    assert K[1, 2] == pytest.approx(math.exp(-0.1 * (4.0 + 25.0)), rel=1e-15)
+    L = kn.kernel_matrix(X, "laplacian", g)
+    assert L[0, 1] == pytest.approx(math.exp(-0.1 * 7.0), rel=1e-15)
+    assert L[1, 2] == pytest.approx(math.exp(-0.1 * (2.0 + 5.0)), rel=1e-15)
+    assert np.all(np.diag(K) == 1.0) and np.all(np.diag(L) == 1.0)
+
+
+@pytest.mark.parametrize("kind", ["rbf", "laplacian"])
+def test_kernel_symmetric_positive_definite(kind):
+    X, _ = inputs.smooth(300, 5, (5, 1))
+    K = kn.kernel_matrix(X, kind, 0.2, block=64)
+    assert np.array_equal(K, K.T)
+    np.linalg.cholesky(K)  # SPD (Section 1: K positive definite)
+    v = np.random.default_rng(0).standard_normal(300)
+    assert np.allclose(kn.kernel_apply(X, v, kind, 0.2, block=37), K @ v, rtol=1e-13, atol=1e-12)
+
+
+def test_kernel_expansion_agrees_with_direct_differences():
+    # ||x||^2 + ||x'||^2 - 2 x.x' is the same number up to rounding.
+    X, _ = inputs.additive(200, 20, (6, 0))
+    Xd = X.astype(np.float64)
+    q = (Xd * Xd).sum(1)
+    D2 = np.maximum(q[:, None] + q[None, :] - 2 * Xd @ Xd.T, 0)
+    assert np.allclose(kn.distance_block(Xd, Xd, "rbf"), D2, atol=1e-11)
+
+
+# ------------------------------------------------------------------ loss / phi
+def test_check_loss_conjugate_is_box_indicator():
+    # rho_tau^*(a) = sup_z (a z - rho_tau(z)) = 0 on [tau-1, tau], +inf outside.
+    tau = 0.3
+    zs = np.linspace(-50, 50, 20001)
+    rho = np.where(zs > 0, tau * zs, -(1 - tau) * zs)
+    for a in [tau - 1, -0.2, 0.0, 0.1, tau]:
+        assert np.max(a * zs - rho) == pytest.approx(0.0, abs=1e-12)
+    for a in [tau - 1.05, tau + 0.05]:
+        assert np.max(a * zs - rho) > 2.0
+    assert pb.check_loss(np.array([2.0, -1.0, 0.0]), tau) == pytest.approx(0.6 + 0.7)
+
+
+def test_grad_phi_is_gradient_of_phi():
+    # (2.3) is the gradient of (2.2); checked by central differences.
+    rng = np.random.default_rng(3)
+    X, y, K = _tiny(40, 3, 3)
+    lam, tau, beta, sigma = 0.7, 0.35, 0.2, 2.5
+    z = rng.standard_normal(40)
+    a = rng.uniform(-1, 1, 40)
+    g = pb.grad_phi(a, K @ a, y, lam, tau, beta, z, sigma)
+    h = 1e-6
+    for i in range(0, 40, 7):
+        e = np.zeros(40)
+        e[i] = h
+        fp = pb.phi(a + e, K @ (a + e), y, lam, tau, beta, z, sigma)
+        fm = pb.phi(a - e, K @ (a - e), y, lam, tau, beta, z, sigma)
+        assert (fp - fm) / (2 * h) == pytest.approx(g[i], rel=1e-6, abs=1e-6)
+
+
+def test_jacobian_mask_and_projection():
+    tau = 0.25
+    w = np.array([-2.0, -0.75, -0.1, 0.25, 0.9])
+    assert np.array_equal(pb.proj_box(w, tau), [-0.75, -0.75, -0.1, 0.25, 0.25])
+    assert np.array_equal(pb.jacobian_mask(w, tau), [0, 0, 1, 0, 0])  # boundary -> 0
+
+
+# ------------------------------------------------------------------ RPCholesky / Woodbury
+def test_sample_pivot_inverse_cdf_hand_cases():
+    d = np.array([0.0, 1.0, 0.0, 3.0])
+    assert pc.sample_pivot(d, 0.0) == 1
+    assert pc.sample_pivot(d, 0.1) == 1   # 0.4 < cumsum[1] = 1
+    assert pc.sample_pivot(d, 0.25) == 3  # 1.0 is not > 1.0
+    assert pc.sample_pivot(d, 0.99) == 3
+
+
+def test_rpcholesky_nystrom_properties():
+    X, _, K = _tiny(120, 4, 9, gamma=0.8)
+    op = kn.DenseKernel(X, "rbf", 0.8)
+    u = inputs.pivot_uniforms(40, (9, 0))
+    F, piv, d = pc.rpcholesky(op, 40, u)
+    R = K - F @ F.T
+    assert len(set(piv.tolist())) == piv.size  # without replacement
+    assert np.abs(R[np.ix_(piv, piv)]).max() < 1e-10   # interpolates pivot block
+    assert np.abs(R[:, piv]).max() < 1e-9              # and pivot columns
+    assert np.abs(d[piv]).max() == 0.0
+    assert np.linalg.eigvalsh(R).min() > -1e-10        # K - K_hat PSD
+    assert np.trace(R) == pytest.approx(d.sum(), rel=1e-8, abs=1e-10)
+    # rank n reproduces K (column Nystrom of all columns)
+    op2 = kn.DenseKernel(X[:30], "rbf", 0.8)
+    F2, _, _ = pc.rpcholesky(op2, 30, inputs.pivot_uniforms(30, (9, 1)), stop_rel=0.0)
+    assert np.abs(F2 @ F2.T - op2.K).max() < 1e-9
+
+
+def test_adaptive_rank_rule():
+    # F0 with orthogonal columns: eigenvalues of F0^T F0 are the squared norms.
+    Q, _ = np.linalg.qr(np.random.default_rng(1).standard_normal((50, 6)))
+    norms = np.array([10.0, 3.0, 1.0, 0.2, 0.05, 0.01])
+    F0 = Q * norms
+    # lambda = 100, 9, 1, 0.04, 0.0025, 1e-4 ; xi = 1e-3 -> lambda_r <= 0.1 first at r = 4
+    assert pc.adaptive_rank(F0, 1e-3) == 4
+    assert pc.adaptive_rank(F0, 1e-7) == 6  # none below: keep r0
+
+
+def test_woodbury_lemma1_inverse():
+    X, _, K = _tiny(150, 3, 4)
+    rng = np.random.default_rng(4)
+    F = rng.standard_normal((150, 12))
+    c = 0.7
+    L = rng.uniform(1e-3, 2.0, 150)
+    W = pc.Woodbury(F, c, L)
+    P = W.dense(F, c)
+    x = rng.standard_normal(150)
+    assert np.allclose(W.apply(P @ x), x, rtol=1e-9, atol=1e-9)
+    assert np.allclose(W.apply(x), np.linalg.solve(P, x), rtol=1e-9, atol=1e-9)
+
+
+def test_pcg_exact_preconditioner_converges_in_one_step():
+    X, y, K = _tiny(60, 3, 5)
+    op = kn.DenseKernel(X, "rbf", 0.5)
+    F, _, _ = pc.rpcholesky(op, 60, inputs.pivot_uniforms(60, (5, 0)), stop_rel=0.0)
+    c, L = 0.4, np.full(60, 0.3)
+    W = pc.Woodbury(F, c, L)
+    A = lambda v: K @ v + c * v.sum() + L * v
+    _, it, res = sv.pcg(A, y, np.zeros(60), 1e-8 * np.linalg.norm(y), W.apply)
+    assert it == 1
+
+
+def test_preconditioned_condition_number_bound():
+    # Appendix C, (C.1): kappa(P^-1/2 A P^-1/2) <= 1 + tr(K - K_hat)/mu, L >= mu I.
+    X, _, K = _tiny(200, 4, 6, gamma=0.3)
+    op = kn.DenseKernel(X, "rbf", 0.3)
+    F, _, d = pc.rpcholesky(op, 15, inputs.pivot_uniforms(15, (6, 0)))
+    rng = np.random.default_rng(6)
+    c = 0.5
+    L = rng.uniform(0.05, 1.0, 200)
+    A = K + c + np.diag(L)
+    P = F @ F.T + c + np.diag(L)
+    ev = np.linalg.eigvals(np.linalg.solve(P, A)).real
+    assert ev.min() > 1 - 1e-9  # A >= P
+    assert ev.max() / ev.min() <= 1 + np.trace(K - F @ F.T) / L.min() + 1e-8
+
+
+# ------------------------------------------------------------------ whole solution
+@pytest.mark.parametrize("seed,tau", [(0, 0.5), (1, 0.3), (2, 0.8), (3, 0.1)])
+def test_fit_equals_brute_force(seed, tau):
+    n = 8
+    X, y, K = _tiny(n, 2, 10 + seed, gamma=0.7)
+    lam = [0.2, 0.5, 1.0, 0.1][seed]
+    a_bf, blo, bhi = pins.brute_force(K, y, lam, tau)
+    r = sv.fit(X, y, tau, lam, "rbf", 0.7, sv.OracleOptions(tol=1e-10))
+    assert np.abs(r.alpha - a_bf).max() < 1e-7
+    assert blo - 1e-7 <= r.beta <= bhi + 1e-7
+    assert r.kkt["err"] < 1e-9
+
+
+def test_fit_equals_generic_qp():
+    n = 60
+    X, y, K = _tiny(n, 3, 21, gamma=1.0)
+    lam, tau = 0.6, 0.4
+    a_qp, f_qp = pins.slsqp_dual(K, y, lam, tau)
+    r = sv.fit(X, y, tau, lam, "rbf", 1.0, sv.OracleOptions(tol=1e-10))
+    f_or = r.alpha @ K @ r.alpha / (2 * lam) - y @ r.alpha
+    assert f_or <= f_qp + 1e-9                       # at least as good as SLSQP
+    assert f_or == pytest.approx(f_qp, rel=1e-7, abs=1e-8)
+    assert np.abs(r.alpha - a_qp).max() < 1e-4
+
+
+def test_identity_kernel_closed_form():
+    # Points 100 apart with gamma = 1: exp(-1e4) underflows, K = I exactly.
+    n = 40
+    rng = np.random.default_rng(7)
+    X = (100.0 * np.arange(n))[:, None].astype(np.float32)
+    y = rng.standard_normal(n)
+    lam, tau = 1.3, 0.3
+    assert np.array_equal(kn.kernel_matrix(X, "rbf", 1.0), np.eye(n))
+    a_cf, b_cf = pins.identity_kernel_solution(y, lam, tau)
+    r = sv.fit(X, y, tau, lam, "rbf", 1.0, sv.OracleOptions(tol=1e-11))
+    assert np.abs(r.alpha - a_cf).max() < 1e-8
+    assert r.beta == pytest.approx(b_cf, abs=1e-8)
+
+
+def test_large_lambda_gives_sample_quantile():
+    # lambda -> inf: f -> 0 and beta minimises sum rho_tau(y - beta).
+    X, y = inputs.smooth(101, 3, (8, 0))
+    for tau in (0.25, 0.5, 0.9):
+        r = sv.fit(X, y, tau, 1e7, "rbf", 0.5, sv.OracleOptions(tol=1e-12))
+        lo, hi = pins.sample_quantile_interval(y, tau)
+        assert lo - 1e-5 <= r.beta <= hi + 1e-5
+
+
+def test_quantile_count_and_duality_sandwich():
+    prob = inputs.workload("c0", n=400)
+    r = sv.fit(prob.X, prob.y, prob.tau, prob.lam, "rbf", prob.gamma, sv.OracleOptions(tol=1e-10))
+    n, tau, lam = 400, prob.tau, prob.lam
+    z = r.z
+    zt = np.where(np.abs(z) < 1e-9, 0.0, z)
+    assert np.sum(zt < 0) <= tau * n <= np.sum(zt <= 0)
+    # weak duality: any feasible alpha gives obj_D <= OPT <= obj_P of any (beta, f)
+    K = kn.kernel_matrix(prob.X, "rbf", prob.gamma)
+    opt = r.kkt["obj_p"]
+    rng = np.random.default_rng(0)
+    for _ in range(5):
+        a = np.clip(r.alpha + 0.05 * rng.standard_normal(n), tau - 1, tau)
+        lo, hi = -5.0, 5.0
+        for _ in range(100):  # shift to sum zero inside the box
+            m = 0.5 * (lo + hi)
+            if np.clip(a - m, tau - 1, tau).sum() > 0:
+                lo = m
+            else:
+                hi = m
+        a = np.clip(a - 0.5 * (lo + hi), tau - 1, tau)
+        assert abs(a.sum()) < 1e-9
+        assert pb.dual_objective(a, K @ a, prob.y, lam) <= opt + 1e-9
+        zz = prob.y - r.beta - K @ a / lam
+        assert pb.primal_objective(zz, a, K @ a, lam, tau) >= opt - 1e-9
+
+
+def test_alm_update_identities():
+    # After (beta, z) update: eta_c == 0 and ||grad phi|| = (1 + ||y||) eta_p.
+    prob = inputs.workload("c0", n=300)
+    o = sv.OracleOptions(tol=1e-8)
+    op = kn.DenseKernel(prob.X, "rbf", prob.gamma)
+    y, tau, lam = prob.y, prob.tau, prob.lam
+    st = sv.admm(op, y, tau, lam, None, o, True)
+    alpha, beta, z, sigma = st["alpha"], st["beta"], st["z"], 1.0
+    Ka = op.apply(alpha)
+    for _ in range(3):
+        alpha, v, Ka, _ = sv.ssn(op, y, tau, lam, beta, z, sigma, alpha, Ka, None, o, True, 1e-30)
+        g = pb.grad_phi(alpha, Ka, y, lam, tau, beta, z, sigma)
+        beta = beta + sigma * alpha.sum()
+        z = z + sigma * (alpha - v)
+        res = pb.kkt(alpha, v, beta, z, Ka, y, lam, tau)
+        assert res["eta_c"] == 0.0
+        assert np.linalg.norm(g) == pytest.approx((1 + np.linalg.norm(y)) * res["eta_p"], rel=1e-8, abs=1e-14)
+        sigma *= 3
+
+
+def test_ssn_directions_descend_superlinearly():
+    prob = inputs.workload("c0", n=300)
+    o = sv.OracleOptions()
+    op = kn.DenseKernel(prob.X, "rbf", prob.gamma)
+    y, tau, lam = prob.y, prob.tau, prob.lam
+    st = sv.admm(op, y, tau, lam, None, o, True)
+    alpha, beta, z, sigma = st["alpha"], st["beta"], st["z"], 1.0
+    Ka = op.apply(alpha)
+    norms = []
+    for _ in range(6):
+        g = pb.grad_phi(alpha, Ka, y, lam, tau, beta, z, sigma)
+        norms.append(np.linalg.norm(g))
+        if norms[-1] < 1e-12:
+            break
+        one = sv.OracleOptions(ssn_max_iter=1)
+        a2, _, Ka2, _ = sv.ssn(op, y, tau, lam, beta, z, sigma, alpha, Ka, None, one, True, 0.0)
+        assert g @ (a2 - alpha) < 0  # descent direction
+        alpha, Ka = a2, Ka2
+    # Theorem 4: local superlinear rate -> the last ratios collapse
+    ratios = [b / a for a, b in zip(norms, norms[1:]) if a > 1e-10]
+    assert min(ratios) < 1e-2
+
+
+def test_pcg_path_matches_direct_path():
+    prob = inputs.workload("c0", n=700)
+    u = inputs.pivot_uniforms(700, (0, 0))
+    rd = sv.fit(prob.X, prob.y, prob.tau, prob.lam, "rbf", prob.gamma, sv.OracleOptions(tol=1e-9))
+    rp = sv.fit(prob.X, prob.y, prob.tau, prob.lam, "rbf", prob.gamma,
+                sv.OracleOptions(tol=1e-9, direct_max=0, rank=0), uniforms=u)
+    assert not rp.info["direct"] and rp.info["rank"] > 0
+    assert rp.kkt["obj_p"] == pytest.approx(rd.kkt["obj_p"], rel=1e-10)
+    assert np.abs(rp.alpha - rd.alpha).max() < 1e-6
+
+
+def test_adjoint_matches_central_differences():
+    X, y = inputs.smooth(60, 2, (40, 0))
+    Xv, yv = inputs.smooth(30, 2, (41, 0))
+    tau = 0.5
+    lg, ll = math.log(0.8), math.log(0.5)
+
+    def J(lg_, ll_):
+        g_, l_ = math.exp(lg_), math.exp(ll_)
+        r = sv.fit(X, y, tau, l_, "rbf", g_, sv.OracleOptions(tol=1e-11))
+        assert r.info["polished"]
+        return r, adj.validation_loss(X, r.alpha, r.beta, Xv, yv, l_, tau, "rbf", g_)
+
+    r0, j0 = J(lg, ll)
+    _, dg, dl, m = adj.adjoint_gradient(X, r0.alpha, r0.beta, Xv, yv, math.exp(ll), tau, "rbf", math.exp(lg))
+    assert m > 0
+    h = 1e-5
+    fd_g = (J(lg + h, ll)[1] - J(lg - h, ll)[1]) / (2 * h)
+    fd_l = (J(lg, ll + h)[1] - J(lg, ll - h)[1]) / (2 * h)
+    assert dg == pytest.approx(fd_g, rel=1e-5, abs=1e-7)
+    assert dl == pytest.approx(fd_l, rel=1e-5, abs=1e-7)
