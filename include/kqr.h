@@ -1,0 +1,232 @@
+/*
+ * kqr.h -- C ABI of libkqr, an MI355X (gfx950) implementation of the hot path
+ * of PALM-KQR, the two-phase preconditioned augmented Lagrangian method for
+ * kernel quantile regression (Deng, Li, Zhang).
+ *
+ * Problem (Section 1, (1.1)-(1.3)): given X (n x p), y (n), quantile level
+ * tau in (0,1), lambda > 0 and a kernel k (RBF exp(-gamma ||x-x'||_2^2) or
+ * Laplacian exp(-gamma ||x-x'||_1)), find the dual optimum alpha of
+ *     max  -alpha^T K alpha / (2 lambda) + y^T alpha
+ *     s.t. alpha in [tau-1, tau]^n,  1^T alpha = 0,
+ * and the intercept beta.  The fitted function is
+ *     f(x) = beta + sum_j alpha_j k(x_j, x) / lambda
+ * (representer form of Section 1 with theta = alpha at the optimum).
+ *
+ * Conventions shared by every entry point:
+ *  - Pointers documented as "device" must point to device memory of the
+ *    current HIP device; "host" pointers to host memory.  The caller owns all
+ *    buffers passed in; the library never frees them.
+ *  - Matrices are row-major.  A leading dimension (ld*) counts elements.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    kqr_kernel_build, kqr_kernel_apply and kqr_predict only enqueue work on
+ *    `stream` and return; every other entry point synchronises `stream`
+ *    before it returns.
+ *  - Arguments are validated before any device work.  Invalid arguments give
+ *    KQR_EINVAL and leave every output untouched.  Calls never throw.
+ *  - On a negative status the contents of outputs are undefined.  On
+ *    KQR_NOT_CONVERGED outputs hold the last iterate and `info` is filled.
+ *  - kqr_last_error() returns a message describing the last failure on the
+ *    calling thread.
+ */
+#ifndef KQR_H
+#define KQR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- status */
+enum {
+  KQR_OK = 0,
+  KQR_NOT_CONVERGED = 1, /* outputs valid, tolerance not reached */
+  KQR_EINVAL = -1,       /* invalid argument */
+  KQR_ENOMEM = -2,       /* device allocation failed */
+  KQR_ENODEVICE = -3,    /* no HIP device available */
+  KQR_EHIP = -4,         /* HIP runtime error */
+  KQR_ENUMERIC = -5      /* NaN/Inf in inputs or a numerical breakdown */
+};
+
+/* kernels of Section 1 */
+enum { KQR_RBF = 0, KQR_LAPLACIAN = 1 };
+
+/* storage type of a materialised kernel matrix */
+enum { KQR_FP32 = 0, KQR_BF16 = 1 };
+
+/* how kqr_fit obtains K */
+enum {
+  KQR_KMODE_AUTO = 0,        /* materialise if it fits in device memory */
+  KQR_KMODE_MATERIALIZE = 1, /* always materialise (k_dtype storage) */
+  KQR_KMODE_ON_THE_FLY = 2   /* recompute entries from X on every apply */
+};
+
+/* arithmetic of kqr_kernel_apply */
+enum {
+  KQR_APPLY_FAST = 0, /* V rounded to FP32, FP32 products, FP64 sums per segment */
+  KQR_APPLY_EXACT = 1 /* V in FP64, products and sums in FP64 (K entries as stored) */
+};
+
+/* ---------------------------------------------------------------- options
+ * Algorithm constants of Algorithms 1-3 and Section 4.  The paper fixes their
+ * ranges, not their values; kqr_default_options fills the values the library
+ * uses (each listed next to its field). */
+typedef struct kqr_options {
+  double tol;          /* Phase II stop: max(eta_kkt, eta_gap) <= tol (Section 4); 1e-6 */
+  double admm_tol;     /* Phase I stop (Section 4); 1e-3 */
+  int admm_max_iter;   /* Phase I cap (Section 4); 100 */
+  int alm_max_iter;    /* Phase II cap (Section 4); 1000 */
+  double admm_sigma;   /* sigma of Algorithm 1; 1 */
+  double admm_step;    /* step length of Algorithm 1, in (0, (1+sqrt 5)/2); 1.618 */
+  double admm_eps0;    /* eps_k = admm_eps0 ||b_0|| / (k+1)^1.5; 0.1 */
+  double etabar;       /* Algorithm 3; 0.1 */
+  double iota;         /* Algorithm 3; 0.5 */
+  double armijo;       /* mu of Algorithm 3; 1e-4 */
+  double ls_shrink;    /* r of Algorithm 3; 0.5 */
+  int ls_max;          /* backtracking cap; 40 */
+  double tau1, tau2;   /* eps_t = tau1 min(tau2, ||grad phi||); 0.1, 0.1 */
+  double eps_floor;    /* lower bound of eps_t; 1e-12 */
+  int ssn_max_iter;    /* Newton steps per ALM subproblem; 50 */
+  double ssn_rel;      /* SSN stop ||grad phi|| <= ssn_rel tol (1+||y||); 0.5 */
+  double sigma_factor; /* sigma <- min(sigma_factor sigma, sigma_max) ... ; 5 */
+  double sigma_stall;  /* ... when eta_d > sigma_stall * previous eta_d; 0.25 */
+  double sigma_max;    /* 1e8 */
+  int rank;            /* preconditioner rank: >0 fixed, 0 adaptive (Section 3), <0 none; 0 */
+  double xi;           /* adaptive-rank threshold (Section 3); 1e-3 */
+  int pcg_max_iter;    /* per linear solve; 2000 */
+  int k_dtype;         /* KQR_FP32 or KQR_BF16 storage of a materialised K; KQR_FP32 */
+  int kmode;           /* KQR_KMODE_*; KQR_KMODE_AUTO */
+  int refine;          /* BF16 K: 1 = FP64 outer residual refinement with exact entries; 1 */
+  const double* pivot_uniforms; /* host, >= max(rank, ceil(sqrt n)) uniforms in [0,1) that
+                                   drive RPCholesky's pivot draws; NULL = derive from `seed` */
+  uint64_t seed;       /* used when pivot_uniforms is NULL; 0 */
+  int verbose;         /* 1: one line per outer iteration on stderr; 0 */
+  int profile;         /* 1: time every K-apply kernel with HIP events (kqr_info.t_kapply_*); 0 */
+} kqr_options;
+
+/* ---------------------------------------------------------------- report */
+typedef struct kqr_info {
+  double eta_p, eta_d, eta_c, eta_kkt, eta_gap; /* Section 4, exact K */
+  double obj_p, obj_d;
+  double sigma;                 /* final ALM penalty */
+  int admm_iters, alm_iters, newton_iters, line_search_steps;
+  int admm_pcg_iters, pcg_iters;
+  int rank_used;
+  int refinements;              /* BF16 outer refinement steps */
+  int64_t kapply_calls;         /* K-applies of the whole fit (all precisions) */
+  int64_t n_interior;           /* #{i : tau-1 < alpha_i < tau} */
+  double t_kbuild, t_precond, t_admm, t_alm, t_total; /* seconds */
+  /* with opt->profile: summed device time of the K-apply kernels (seconds) */
+  int64_t kapply_fast_calls, kapply_exact_calls;
+  double t_kapply_fast, t_kapply_exact;
+} kqr_info;
+
+/* Fills *opt with the defaults listed above.  Returns KQR_OK or KQR_EINVAL (opt NULL). */
+int kqr_default_options(kqr_options* opt);
+
+/* Static text for a status code. */
+const char* kqr_status_string(int status);
+
+/* Message of the last failure on the calling thread ("" if none). */
+const char* kqr_last_error(void);
+
+/* Number of HIP devices (0 if none or the runtime is unusable). */
+int kqr_device_count(void);
+
+/* ---------------------------------------------------------------- kernel matrix
+ * kqr_kernel_build: materialise K_ij = k(x_i, x_j) (Section 1) into K.
+ *  X      device, n x p FP32, row-major (ld = p).
+ *  K      device, n x ldk, type k_dtype (FP32, or BF16 rounded to nearest even);
+ *         ldk >= n and a multiple of 8.  Columns n..ldk-1 are written as 0.
+ *  RBF distances use ||x_i||^2 + ||x_j||^2 - 2 x_i.x_j clamped at 0 with the
+ *  diagonal set to exactly 0, so K_ii = 1.  Asynchronous on `stream`. */
+int kqr_kernel_build(const float* X, int64_t n, int64_t p, int kernel, double gamma,
+                     int k_dtype, void* K, int64_t ldk, void* stream);
+
+/* kqr_kernel_apply: U = K(X, X) V (the operator K v of (1.2)-(3.1)).
+ *  K      device matrix from kqr_kernel_build (type k_dtype, ld ldk), or NULL to
+ *         compute entries on the fly from X (FP32 entries).
+ *  V      device, n x m FP64 row-major (ld ldv >= m);  U device, n x m FP64 (ld ldu >= m).
+ *  mode   KQR_APPLY_FAST or KQR_APPLY_EXACT (m == 1 only; m > 1 uses FP32 products
+ *         with FP32 accumulation on the matrix cores).
+ *  Needs 1 <= m <= 16.  Asynchronous on `stream`; uses an internal device
+ *  workspace (allocated on first use, reused after). */
+int kqr_kernel_apply(const float* X, int64_t n, int64_t p, int kernel, double gamma,
+                     const void* K, int k_dtype, int64_t ldk, const double* V, int64_t m,
+                     int64_t ldv, double* U, int64_t ldu, int mode, void* stream);
+
+/* kqr_predict: f = beta + K(Xnew, Xtrain) alpha / lambda, computed on the fly.
+ *  Xtrain device n x p FP32; alpha device n FP64; Xnew device m x p FP32;
+ *  f device m FP64.  Asynchronous on `stream`. */
+int kqr_predict(const float* Xtrain, int64_t n, int64_t p, const double* alpha, double beta,
+                double lambda, int kernel, double gamma, const float* Xnew, int64_t m,
+                double* f, void* stream);
+
+/* ---------------------------------------------------------------- preconditioner pieces
+ * kqr_rpcholesky: randomly pivoted Cholesky F = RPCholesky(K, rank) (Section 3,
+ * (3.2)).  Step i draws the pivot s = first index whose running sum of the
+ * residual diagonal exceeds uniforms[i] times its total, then
+ *     g = K[:, s] - F[:, :i] F[s, :i]^T,  F[:, i] = g / sqrt(g_s),
+ *     d <- max(d - F[:, i]^2, 0),  d_s <- 0.
+ * Stops early when sum(d) <= 1e-14 tr(K).
+ *  K         device (as in kqr_kernel_build) or NULL for entries from X.
+ *  uniforms  host, rank values in [0,1).
+ *  F         device, n x ldf FP32 row-major, ldf >= rank (multiple of 4).
+ *  pivots    host, rank int64 (filled up to *rank_out).
+ *  rank_out  host, number of columns produced. */
+int kqr_rpcholesky(const float* X, int64_t n, int64_t p, int kernel, double gamma,
+                   const void* K, int k_dtype, int64_t ldk, int64_t rank,
+                   const double* uniforms, float* F, int64_t ldf, int64_t* pivots,
+                   int64_t* rank_out, void* stream);
+
+/* kqr_woodbury_apply: out = P^{-1} w for P = F F^T + c 1 1^T + diag(Ldiag), by
+ * Lemma 1 with U = [F 1] and the (r+1)x(r+1) core C = diag(I, 1/c) + U^T L^{-1} U
+ * formed and Cholesky-factored in FP64 on the device.
+ *  F device n x ldf FP32 (r columns used); Ldiag, w, out device n FP64; c > 0,
+ *  Ldiag > 0.  r <= 1023.  Returns KQR_ENUMERIC if the core is not positive definite. */
+int kqr_woodbury_apply(const float* F, int64_t n, int64_t r, int64_t ldf, double c,
+                       const double* Ldiag, const double* w, double* out, void* stream);
+
+/* kqr_pcg_solve: left-preconditioned CG (Section 3) on
+ *     (K + c 1 1^T + diag(Ldiag)) x = b,
+ * preconditioned by (3.2) with F (r columns; r = 0: no preconditioner).  Stops
+ * when ||b - A x||_2 <= tol or after maxit iterations.
+ *  K as in kqr_kernel_apply (NULL = on the fly from X); x device n FP64 holds
+ *  the start on entry and the solution on return; iters, resnorm host. */
+int kqr_pcg_solve(const float* X, int64_t n, int64_t p, int kernel, double gamma,
+                  const void* K, int k_dtype, int64_t ldk, const float* F, int64_t r,
+                  int64_t ldf, double c, const double* Ldiag, const double* b, double tol,
+                  int maxit, double* x, int* iters, double* resnorm, void* stream);
+
+/* kqr_ssn_gradient: the fused Newton set-up of Algorithm 3 at alpha:
+ *     w = alpha + z/sigma,  grad = K alpha/lambda - y + beta 1 + sigma 1 (1^T alpha)
+ *                                  + sigma (w - Pi_B(w))                      (2.3)
+ *     S_ii = 1 if tau-1 < w_i < tau else 0 (boundary -> 0)          (Section 2.2)
+ *     eps_t = max(tau1 min(tau2, ||grad||), eps_floor)
+ *     Ldiag = lambda sigma (1 - S) + lambda eps_t,   rhs = -lambda grad      (3.1)
+ *  alpha, Kalpha, y, z device n FP64; grad, Ldiag, rhs device n FP64 outputs;
+ *  S device n uint8 output; gnorm, eps_t host outputs. */
+int kqr_ssn_gradient(int64_t n, double tau, double lambda, double beta, double sigma,
+                     double tau1, double tau2, double eps_floor, const double* alpha,
+                     const double* Kalpha, const double* y, const double* z, double* grad,
+                     uint8_t* S, double* Ldiag, double* rhs, double* gnorm, double* eps_t,
+                     void* stream);
+
+/* ---------------------------------------------------------------- the fit
+ * kqr_fit: PALM-KQR -- Phase I inexact ADMM (Algorithm 1) warm start, Phase II
+ * semismooth Newton ALM (Algorithms 2, 3) with PCG on (3.1) preconditioned by
+ * (3.2) through Lemma 1, stopped by the rules of Section 4 with the residuals
+ * measured with exact (FP32-entry, FP64-accumulated) K.
+ *  X device n x p FP32; y device n FP64; alpha device n FP64 output;
+ *  beta host output; info host (may be NULL); opt host (NULL = defaults).
+ *  Returns KQR_OK, KQR_NOT_CONVERGED (caps reached), or an error.  Device
+ *  workspace (K, F, vectors) is allocated inside and freed before return. */
+int kqr_fit(const float* X, const double* y, int64_t n, int64_t p, double tau, double lambda,
+            int kernel, double gamma, const kqr_options* opt, double* alpha, double* beta,
+            kqr_info* info, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KQR_H */

@@ -1,0 +1,468 @@
+// extern "C" entry points of libkqr: argument validation, workspace set-up and
+// dispatch.  No exception crosses the ABI: every entry point returns a status.
+#include "solver.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstring>
+#include <memory>
+
+namespace kqr {
+
+static thread_local std::string g_last_error;
+
+void set_last_error(const std::string& msg) { g_last_error = msg; }
+
+void fail(int status, const char* fmt, ...) {
+  char buf[1024];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  throw Error(status, buf);
+}
+
+void DevBuf::alloc(size_t b) {
+  release();
+  if (b == 0) b = 16;
+  hipError_t e = hipMalloc(&ptr, b);
+  if (e != hipSuccess) {
+    ptr = nullptr;
+    (void)hipGetLastError();
+    fail(e == hipErrorOutOfMemory ? KQR_ENOMEM : KQR_EHIP, "hipMalloc(%zu bytes): %s", b, hipGetErrorString(e));
+  }
+  bytes = b;
+}
+
+void DevBuf::release() {
+  if (ptr) (void)hipFree(ptr);
+  ptr = nullptr;
+  bytes = 0;
+}
+
+HostPinned::HostPinned(size_t b) {
+  hipError_t e = hipHostMalloc(&ptr, b, hipHostMallocDefault);
+  if (e != hipSuccess) {
+    ptr = nullptr;
+    fail(KQR_EHIP, "hipHostMalloc(%zu bytes): %s", b, hipGetErrorString(e));
+  }
+}
+
+HostPinned::~HostPinned() {
+  if (ptr) (void)hipHostFree(ptr);
+}
+
+void ensure_device() {
+  int count = 0;
+  hipError_t e = hipGetDeviceCount(&count);
+  if (e != hipSuccess || count <= 0) {
+    (void)hipGetLastError();
+    fail(KQR_ENODEVICE, "no HIP device available");
+  }
+}
+
+// Uniforms in [0,1) for pivot draws when the caller gives none: SplitMix64
+// (Steele, Lea, Flood 2014) on seed + i, top 53 bits.
+static std::vector<double> splitmix_uniforms(uint64_t seed, int64_t count) {
+  std::vector<double> u(size_t(std::max<int64_t>(count, 0)));
+  for (int64_t i = 0; i < count; ++i) {
+    uint64_t z = seed + 0x9e3779b97f4a7c15ull * uint64_t(i + 1);
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    z ^= z >> 31;
+    u[size_t(i)] = double(z >> 11) * (1.0 / 9007199254740992.0);
+  }
+  return u;
+}
+
+static double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+template <typename Fn>
+static int guarded(Fn&& fn) {
+  try {
+    g_last_error.clear();
+    fn();
+    return KQR_OK;
+  } catch (const Error& e) {
+    g_last_error = e.what();
+    return e.status;
+  } catch (const std::bad_alloc&) {
+    g_last_error = "host allocation failed";
+    return KQR_ENOMEM;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return KQR_EHIP;
+  } catch (...) {
+    g_last_error = "unknown failure";
+    return KQR_EHIP;
+  }
+}
+
+#define KQR_REQUIRE(cond, ...) \
+  do {                         \
+    if (!(cond)) fail(KQR_EINVAL, __VA_ARGS__); \
+  } while (0)
+
+static void check_kernel(int kernel, double gamma) {
+  KQR_REQUIRE(kernel == KQR_RBF || kernel == KQR_LAPLACIAN, "kernel must be KQR_RBF or KQR_LAPLACIAN");
+  KQR_REQUIRE(std::isfinite(gamma) && gamma > 0.0, "gamma must be positive and finite");
+}
+
+static void check_kmat(const void* K, int k_dtype, int64_t ldk, int64_t n) {
+  if (!K) return;
+  KQR_REQUIRE(k_dtype == KQR_FP32 || k_dtype == KQR_BF16, "k_dtype must be KQR_FP32 or KQR_BF16");
+  KQR_REQUIRE(ldk >= n && ldk % 8 == 0, "ldk must be >= n and a multiple of 8");
+  KQR_REQUIRE((reinterpret_cast<uintptr_t>(K) & 15) == 0, "K must be 16-byte aligned");
+}
+
+}  // namespace kqr
+
+using namespace kqr;
+
+extern "C" {
+
+int kqr_default_options(kqr_options* o) {
+  if (!o) return KQR_EINVAL;
+  memset(o, 0, sizeof(*o));
+  o->tol = 1e-6;
+  o->admm_tol = 1e-3;
+  o->admm_max_iter = 100;
+  o->alm_max_iter = 1000;
+  o->admm_sigma = 1.0;
+  o->admm_step = 1.618;
+  o->admm_eps0 = 0.1;
+  o->etabar = 0.1;
+  o->iota = 0.5;
+  o->armijo = 1e-4;
+  o->ls_shrink = 0.5;
+  o->ls_max = 40;
+  o->tau1 = 0.1;
+  o->tau2 = 0.1;
+  o->eps_floor = 1e-12;
+  o->ssn_max_iter = 50;
+  o->ssn_rel = 0.5;
+  o->sigma_factor = 5.0;
+  o->sigma_stall = 0.25;
+  o->sigma_max = 1e8;
+  o->rank = 0;
+  o->xi = 1e-3;
+  o->pcg_max_iter = 2000;
+  o->k_dtype = KQR_FP32;
+  o->kmode = KQR_KMODE_AUTO;
+  o->refine = 1;
+  o->pivot_uniforms = nullptr;
+  o->seed = 0;
+  o->verbose = 0;
+  return KQR_OK;
+}
+
+const char* kqr_status_string(int s) {
+  switch (s) {
+    case KQR_OK: return "ok";
+    case KQR_NOT_CONVERGED: return "not converged (iteration cap reached)";
+    case KQR_EINVAL: return "invalid argument";
+    case KQR_ENOMEM: return "device allocation failed";
+    case KQR_ENODEVICE: return "no HIP device";
+    case KQR_EHIP: return "HIP runtime error";
+    case KQR_ENUMERIC: return "numerical failure (NaN/Inf or breakdown)";
+    default: return "unknown status";
+  }
+}
+
+const char* kqr_last_error(void) { return g_last_error.c_str(); }
+
+int kqr_device_count(void) {
+  int c = 0;
+  if (hipGetDeviceCount(&c) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  return c;
+}
+
+int kqr_kernel_build(const float* X, int64_t n, int64_t p, int kernel, double gamma, int k_dtype, void* K,
+                     int64_t ldk, void* stream) {
+  return guarded([&] {
+    KQR_REQUIRE(X && K, "X and K must be non-null");
+    KQR_REQUIRE(n >= 1 && p >= 1 && p <= 64, "need n >= 1 and 1 <= p <= 64");
+    check_kernel(kernel, gamma);
+    check_kmat(K, k_dtype, ldk, n);
+    ensure_device();
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    float* sqn = nullptr;
+    KQR_CHECK_HIP(hipMallocAsync(reinterpret_cast<void**>(&sqn), size_t(n) * sizeof(float), st));
+    row_sqnorms(X, n, int(p), sqn, st);
+    kbuild(X, sqn, n, int(p), KernelSpec{kernel, gamma}, k_dtype, K, ldk, st);
+    KQR_CHECK_HIP(hipFreeAsync(sqn, st));
+  });
+}
+
+int kqr_kernel_apply(const float* X, int64_t n, int64_t p, int kernel, double gamma, const void* K, int k_dtype,
+                     int64_t ldk, const double* V, int64_t m, int64_t ldv, double* U, int64_t ldu, int mode,
+                     void* stream) {
+  return guarded([&] {
+    KQR_REQUIRE(V && U, "V and U must be non-null");
+    KQR_REQUIRE(n >= 1, "need n >= 1");
+    KQR_REQUIRE(m >= 1 && m <= 16, "need 1 <= m <= 16");
+    KQR_REQUIRE(ldv >= m && ldu >= m, "need ldv >= m and ldu >= m");
+    KQR_REQUIRE(mode == KQR_APPLY_FAST || mode == KQR_APPLY_EXACT, "mode must be KQR_APPLY_FAST or KQR_APPLY_EXACT");
+    if (!K) {
+      KQR_REQUIRE(X != nullptr, "X must be non-null when K is NULL");
+      KQR_REQUIRE(p >= 1 && p <= 64, "need 1 <= p <= 64");
+      check_kernel(kernel, gamma);
+    }
+    check_kmat(K, k_dtype, ldk, n);
+    ensure_device();
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const KernelSpec ks{kernel, gamma};
+    const KMat km{K, k_dtype, ldk};
+    void* tmp = nullptr;
+    // per column: contiguous FP64 copy (when strided) and its FP32 rounding
+    const size_t bytes = size_t(n) * (sizeof(double) + sizeof(float)) + 256;
+    KQR_CHECK_HIP(hipMallocAsync(&tmp, bytes, st));
+    double* v64 = static_cast<double*>(tmp);
+    float* v32 = reinterpret_cast<float*>(static_cast<char*>(tmp) + ((size_t(n) * sizeof(double) + 255) / 256) * 256);
+    float* sqn = nullptr;
+    if (!K) {
+      KQR_CHECK_HIP(hipMallocAsync(reinterpret_cast<void**>(&sqn), size_t(n) * sizeof(float), st));
+      row_sqnorms(X, n, int(p), sqn, st);
+    }
+    for (int64_t j = 0; j < m; ++j) {
+      const double* col = V + j;
+      if (ldv != 1 || (reinterpret_cast<uintptr_t>(col) & 15) != 0) {  // kernels read 16-byte vectors
+        KQR_CHECK_HIP(hipMemcpy2DAsync(v64, sizeof(double), V + j, size_t(ldv) * sizeof(double), sizeof(double),
+                                       size_t(n), hipMemcpyDeviceToDevice, st));
+        col = v64;
+      }
+      if (K) {
+        if (mode == KQR_APPLY_EXACT) {
+          kapply_dense(km, n, n, nullptr, col, U + j, ldu, true, st);
+        } else {
+          to_f32(col, n, 1, 1, v32, 1, st);
+          kapply_dense(km, n, n, v32, nullptr, U + j, ldu, false, st);
+        }
+      } else {
+        kapply_otf(X, sqn, n, X, sqn, n, int(p), ks, col, U + j, ldu, 1.0, 0.0, st);
+      }
+    }
+    if (sqn) KQR_CHECK_HIP(hipFreeAsync(sqn, st));
+    KQR_CHECK_HIP(hipFreeAsync(tmp, st));
+  });
+}
+
+int kqr_predict(const float* Xtrain, int64_t n, int64_t p, const double* alpha, double beta, double lambda,
+                int kernel, double gamma, const float* Xnew, int64_t m, double* f, void* stream) {
+  return guarded([&] {
+    KQR_REQUIRE(Xtrain && alpha && Xnew && f, "pointers must be non-null");
+    KQR_REQUIRE(n >= 1 && m >= 1 && p >= 1 && p <= 64, "need n, m >= 1 and 1 <= p <= 64");
+    KQR_REQUIRE(std::isfinite(lambda) && lambda > 0.0, "lambda must be positive");
+    KQR_REQUIRE(std::isfinite(beta), "beta must be finite");
+    check_kernel(kernel, gamma);
+    ensure_device();
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    float* sq = nullptr;
+    KQR_CHECK_HIP(hipMallocAsync(reinterpret_cast<void**>(&sq), size_t(n + m) * sizeof(float), st));
+    row_sqnorms(Xtrain, n, int(p), sq, st);
+    row_sqnorms(Xnew, m, int(p), sq + n, st);
+    kapply_otf(Xnew, sq + n, m, Xtrain, sq, n, int(p), KernelSpec{kernel, gamma}, alpha, f, 1, 1.0 / lambda, beta, st);
+    KQR_CHECK_HIP(hipFreeAsync(sq, st));
+  });
+}
+
+int kqr_rpcholesky(const float* X, int64_t n, int64_t p, int kernel, double gamma, const void* K, int k_dtype,
+                   int64_t ldk, int64_t rank, const double* uniforms, float* F, int64_t ldf, int64_t* pivots,
+                   int64_t* rank_out, void* stream) {
+  return guarded([&] {
+    KQR_REQUIRE(uniforms && F && pivots && rank_out, "pointers must be non-null");
+    KQR_REQUIRE(n >= 1 && rank >= 1 && rank <= 1024, "need n >= 1 and 1 <= rank <= 1024");
+    KQR_REQUIRE(ldf >= std::min(rank, n) && ldf % 4 == 0, "ldf must be >= rank and a multiple of 4");
+    for (int64_t i = 0; i < std::min(rank, n); ++i)
+      KQR_REQUIRE(uniforms[i] >= 0.0 && uniforms[i] < 1.0, "uniforms must lie in [0, 1)");
+    if (!K) {
+      KQR_REQUIRE(X != nullptr, "X must be non-null when K is NULL");
+      KQR_REQUIRE(p >= 1 && p <= 64, "need 1 <= p <= 64");
+      check_kernel(kernel, gamma);
+    }
+    check_kmat(K, k_dtype, ldk, n);
+    ensure_device();
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    DevBuf sqn(size_t(n) * sizeof(float));
+    if (X) row_sqnorms(X, n, int(p), sqn.as<float>(), st);
+    KQR_CHECK_HIP(hipMemsetAsync(F, 0, size_t(n) * ldf * sizeof(float), st));
+    std::vector<int64_t> piv = rpcholesky(KMat{K, k_dtype, ldk}, X, sqn.as<float>(), n, int(p), KernelSpec{kernel, gamma},
+                                          rank, uniforms, F, ldf, st);
+    for (size_t i = 0; i < piv.size(); ++i) pivots[i] = piv[i];
+    *rank_out = int64_t(piv.size());
+  });
+}
+
+int kqr_woodbury_apply(const float* F, int64_t n, int64_t r, int64_t ldf, double c, const double* Ldiag,
+                       const double* w, double* out, void* stream) {
+  return guarded([&] {
+    KQR_REQUIRE(Ldiag && w && out, "pointers must be non-null");
+    KQR_REQUIRE(n >= 1 && r >= 0 && r <= 1023, "need n >= 1 and 0 <= r <= 1023");
+    KQR_REQUIRE(r == 0 || (F && ldf >= r), "F must be non-null with ldf >= r");
+    KQR_REQUIRE(std::isfinite(c) && c > 0.0, "c must be positive");
+    ensure_device();
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    Workspace ws;
+    Woodbury P(F, n, r, ldf);
+    if (!P.build(Ldiag, c, st)) fail(KQR_ENUMERIC, "Woodbury core is not positive definite");
+    P.apply(w, out, nullptr, nullptr, ws, st);
+    KQR_CHECK_HIP(hipStreamSynchronize(st));
+  });
+}
+
+int kqr_pcg_solve(const float* X, int64_t n, int64_t p, int kernel, double gamma, const void* K, int k_dtype,
+                  int64_t ldk, const float* F, int64_t r, int64_t ldf, double c, const double* Ldiag, const double* b,
+                  double tol, int maxit, double* x, int* iters, double* resnorm, void* stream) {
+  return guarded([&] {
+    KQR_REQUIRE(Ldiag && b && x && iters && resnorm, "pointers must be non-null");
+    KQR_REQUIRE(n >= 1 && r >= 0 && r <= 1023 && maxit >= 0, "need n >= 1, 0 <= r <= 1023, maxit >= 0");
+    KQR_REQUIRE(r == 0 || (F && ldf >= r), "F must be non-null with ldf >= r");
+    KQR_REQUIRE(std::isfinite(c) && c >= 0.0 && tol >= 0.0, "need c >= 0 and tol >= 0");
+    KQR_REQUIRE(X != nullptr && p >= 1 && p <= 64, "X must be non-null with 1 <= p <= 64");
+    check_kernel(kernel, gamma);
+    check_kmat(K, k_dtype, ldk, n);
+    ensure_device();
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    Operator op(X, n, int(p), KernelSpec{kernel, gamma}, KMat{K, k_dtype, ldk}, st);
+    Workspace ws;
+    Pcg pcg(op, ws, n);
+    std::unique_ptr<Woodbury> P;
+    if (r > 0) {
+      P.reset(new Woodbury(F, n, r, ldf));
+      if (!P->build(Ldiag, c, st)) fail(KQR_ENUMERIC, "Woodbury core is not positive definite");
+    }
+    PcgStats s = pcg.solve(c, Ldiag, P.get(), b, x, nullptr, false, tol, maxit, K != nullptr && k_dtype == KQR_FP32,
+                           st);
+    KQR_CHECK_HIP(hipStreamSynchronize(st));
+    *iters = s.iters;
+    *resnorm = s.resnorm;
+  });
+}
+
+int kqr_ssn_gradient(int64_t n, double tau, double lambda, double beta, double sigma, double tau1, double tau2,
+                     double eps_floor, const double* alpha, const double* Kalpha, const double* y, const double* z,
+                     double* grad, uint8_t* S, double* Ldiag, double* rhs, double* gnorm, double* eps_t,
+                     void* stream) {
+  return guarded([&] {
+    KQR_REQUIRE(alpha && Kalpha && y && z && grad && S && Ldiag && rhs && gnorm && eps_t, "pointers must be non-null");
+    KQR_REQUIRE(n >= 1 && tau > 0.0 && tau < 1.0, "need n >= 1 and 0 < tau < 1");
+    KQR_REQUIRE(lambda > 0.0 && sigma > 0.0 && tau1 > 0.0 && tau2 > 0.0 && eps_floor >= 0.0,
+                "need positive lambda, sigma, tau1, tau2");
+    ensure_device();
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    Workspace ws;
+    DevBuf red(8 * sizeof(double));
+    HostPinned h(8 * sizeof(double));
+    vec_dots(n, alpha, nullptr, ws, red.as<double>(), st);
+    KQR_CHECK_HIP(hipMemcpyAsync(h.ptr, red.ptr, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
+    KQR_CHECK_HIP(hipStreamSynchronize(st));
+    const double sa = h.as<double>()[0];
+    ssn_grad(n, alpha, Kalpha, y, z, beta, sigma, sa, tau, lambda, grad, S, ws, red.as<double>(), st);
+    KQR_CHECK_HIP(hipMemcpyAsync(h.ptr, red.ptr, sizeof(double), hipMemcpyDeviceToHost, st));
+    KQR_CHECK_HIP(hipStreamSynchronize(st));
+    const double gn = std::sqrt(h.as<double>()[0]);
+    const double et = std::max(tau1 * std::min(tau2, gn), eps_floor);
+    ssn_system(n, S, grad, lambda, sigma, et, Ldiag, rhs, st);
+    KQR_CHECK_HIP(hipStreamSynchronize(st));
+    *gnorm = gn;
+    *eps_t = et;
+  });
+}
+
+int kqr_fit(const float* X, const double* y, int64_t n, int64_t p, double tau, double lambda, int kernel, double gamma,
+            const kqr_options* opt, double* alpha, double* beta, kqr_info* info, void* stream) {
+  int converged = 0;
+  int st_code = guarded([&] {
+    KQR_REQUIRE(X && y && alpha && beta, "X, y, alpha and beta must be non-null");
+    KQR_REQUIRE(n >= 2 && p >= 1 && p <= 64, "need n >= 2 and 1 <= p <= 64");
+    KQR_REQUIRE(tau > 0.0 && tau < 1.0, "need 0 < tau < 1");
+    KQR_REQUIRE(std::isfinite(lambda) && lambda > 0.0, "lambda must be positive and finite");
+    check_kernel(kernel, gamma);
+    kqr_options o;
+    kqr_default_options(&o);
+    if (opt) o = *opt;
+    KQR_REQUIRE(o.tol > 0.0 && o.admm_tol > 0.0 && o.admm_sigma > 0.0, "tolerances and sigma must be positive");
+    KQR_REQUIRE(o.admm_step > 0.0 && o.admm_step < 1.6180339887498949, "admm_step must lie in (0, (1+sqrt 5)/2)");
+    KQR_REQUIRE(o.admm_max_iter >= 0 && o.alm_max_iter >= 0 && o.pcg_max_iter >= 1, "iteration caps must be >= 0");
+    KQR_REQUIRE(o.etabar > 0.0 && o.etabar < 1.0 && o.iota > 0.0 && o.iota <= 1.0, "need etabar in (0,1), iota in (0,1]");
+    KQR_REQUIRE(o.armijo > 0.0 && o.armijo < 0.5 && o.ls_shrink > 0.0 && o.ls_shrink < 1.0, "need armijo in (0,1/2), ls_shrink in (0,1)");
+    KQR_REQUIRE(o.tau1 > 0.0 && o.tau1 < 1.0 && o.tau2 > 0.0 && o.tau2 < 1.0, "need tau1, tau2 in (0,1)");
+    KQR_REQUIRE(o.k_dtype == KQR_FP32 || o.k_dtype == KQR_BF16, "k_dtype must be KQR_FP32 or KQR_BF16");
+    KQR_REQUIRE(o.kmode >= KQR_KMODE_AUTO && o.kmode <= KQR_KMODE_ON_THE_FLY, "invalid kmode");
+    KQR_REQUIRE(o.rank <= 1023, "rank must be <= 1023");
+    KQR_REQUIRE(o.sigma_factor >= 1.0 && o.sigma_max >= o.admm_sigma, "need sigma_factor >= 1, sigma_max >= admm_sigma");
+    ensure_device();
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    kqr_info inf;
+    memset(&inf, 0, sizeof(inf));
+    const double t_start = now_s();
+    // ---- K: materialise or recompute
+    const int esz = o.k_dtype == KQR_BF16 ? 2 : 4;
+    const int64_t ldk = (n + 63) / 64 * 64;
+    const size_t kbytes = size_t(n) * size_t(ldk) * esz;
+    bool materialize = o.kmode == KQR_KMODE_MATERIALIZE;
+    if (o.kmode == KQR_KMODE_AUTO) {
+      size_t freeb = 0, totalb = 0;
+      KQR_CHECK_HIP(hipMemGetInfo(&freeb, &totalb));
+      materialize = kbytes < freeb / 10 * 8;
+    }
+    DevBuf Kbuf;
+    DevBuf sqn_tmp(size_t(n) * sizeof(float));
+    if (materialize) {
+      Kbuf.alloc(kbytes);
+      row_sqnorms(X, n, int(p), sqn_tmp.as<float>(), st);
+      kbuild(X, sqn_tmp.as<float>(), n, int(p), KernelSpec{kernel, gamma}, o.k_dtype, Kbuf.ptr, ldk, st);
+    }
+    KQR_CHECK_HIP(hipStreamSynchronize(st));
+    inf.t_kbuild = now_s() - t_start;
+    Operator op(X, n, int(p), KernelSpec{kernel, gamma}, KMat{Kbuf.ptr, o.k_dtype, ldk}, st);
+    op.enable_profile(o.profile != 0);
+    // ---- preconditioner (3.2)
+    const double t_p0 = now_s();
+    int64_t rank = 0;
+    if (o.rank > 0) rank = std::min<int64_t>(o.rank, n);
+    else if (o.rank == 0) rank = std::min<int64_t>(int64_t(std::ceil(std::sqrt(double(n)))), std::min<int64_t>(n, 1023));
+    const int64_t ldf = std::max<int64_t>(4, (rank + 3) / 4 * 4);
+    DevBuf Fbuf;
+    int64_t rank_used = 0;
+    if (rank > 0) {
+      Fbuf.alloc(size_t(n) * ldf * sizeof(float));
+      KQR_CHECK_HIP(hipMemsetAsync(Fbuf.ptr, 0, size_t(n) * ldf * sizeof(float), st));
+      std::vector<double> u;
+      const double* uni = o.pivot_uniforms;
+      if (!uni) {
+        u = splitmix_uniforms(o.seed, rank);
+        uni = u.data();
+      }
+      std::vector<int64_t> piv = rpcholesky(op.kmat(), X, op.sqn(), n, int(p), KernelSpec{kernel, gamma}, rank, uni,
+                                            Fbuf.as<float>(), ldf, st);
+      rank_used = int64_t(piv.size());
+    }
+    inf.rank_used = int(rank_used);
+    inf.t_precond = now_s() - t_p0;
+    // ---- Phase I and II
+    Solver solver(op, y, n, tau, lambda, o, Fbuf.as<float>(), rank_used, ldf, st);
+    solver.phase1(inf);
+    solver.phase2(inf);
+    solver.finish(inf);
+    KQR_CHECK_HIP(hipMemcpyAsync(alpha, solver.alpha(), size_t(n) * sizeof(double), hipMemcpyDeviceToDevice, st));
+    KQR_CHECK_HIP(hipStreamSynchronize(st));
+    *beta = solver.beta();
+    inf.kapply_calls = op.calls();
+    op.profile_totals(inf.kapply_fast_calls, inf.t_kapply_fast, inf.kapply_exact_calls, inf.t_kapply_exact);
+    inf.t_total = now_s() - t_start;
+    converged = solver.converged();
+    if (info) *info = inf;
+  });
+  if (st_code == KQR_OK && !converged) return KQR_NOT_CONVERGED;
+  return st_code;
+}
+
+}  // extern "C"

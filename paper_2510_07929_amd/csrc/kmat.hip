@@ -1,0 +1,471 @@
+// Kernel-matrix operators on gfx950: materialisation, the HBM-streamed
+// K-apply, the on-the-fly K-apply and single kernel rows.
+//
+// K_ij = exp(-gamma d_ij) with d the squared Euclidean distance (RBF) or the
+// L1 distance (Laplacian) (Section 1).  exp is evaluated as exp2 of
+// -gamma log2(e) d with the device exp2f.
+#include "kqr_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <mutex>
+
+namespace kqr {
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ float bf16_lo(uint32_t w) { return __uint_as_float(w << 16); }
+__device__ __forceinline__ float bf16_hi(uint32_t w) { return __uint_as_float(w & 0xffff0000u); }
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float(uint32_t(h) << 16); }
+// Round to nearest even (entries are finite).
+__device__ __forceinline__ uint16_t f32_to_bf16(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return uint16_t(u >> 16);
+}
+
+constexpr float kLog2e = 1.4426950408889634f;
+
+// ================================================================= row norms
+__global__ void sqnorm_kernel(const float* __restrict__ X, int64_t n, int p, float* __restrict__ q) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float* x = X + i * p;
+  float s = 0.f;
+  for (int k = 0; k < p; ++k) s = fmaf(x[k], x[k], s);
+  q[i] = s;
+}
+
+void row_sqnorms(const float* X, int64_t n, int p, float* sqn, hipStream_t st) {
+  if (n <= 0) return;
+  sqnorm_kernel<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st>>>(X, n, p, sqn);
+  KQR_LAUNCH_CHECK();
+}
+
+// Distance of row (LDS copy xi, norm qi) to a column held in registers.
+template <int PMAX, bool LAP>
+__device__ __forceinline__ float pair_dist(const float* xi, float qi, const float* xj, float qj) {
+  if (LAP) {
+    float d = 0.f;
+#pragma unroll
+    for (int k = 0; k < PMAX; ++k) d += fabsf(xi[k] - xj[k]);
+    return d;
+  } else {
+    float g = 0.f;
+#pragma unroll
+    for (int k = 0; k < PMAX; ++k) g = fmaf(xi[k], xj[k], g);
+    return fmaxf(qi + qj - 2.f * g, 0.f);
+  }
+}
+
+// ================================================================= K build
+// Block: 16 rows x 256 columns.  Row tile of X and its norms staged in LDS
+// (broadcast reads); each thread keeps its column x_j in registers.
+template <int PMAX, bool LAP, bool BF16>
+__global__ __launch_bounds__(256) void kbuild_kernel(const float* __restrict__ X,
+                                                     const float* __restrict__ q, int64_t n, int p,
+                                                     float ng, void* __restrict__ Kout, int64_t ldk) {
+  constexpr int TR = 16;
+  __shared__ float xs[TR][PMAX];
+  __shared__ float qs[TR];
+  const int64_t i0 = (int64_t)blockIdx.x * TR;
+  const int64_t j = (int64_t)blockIdx.y * 256 + threadIdx.x;
+  for (int t = threadIdx.x; t < TR * PMAX; t += 256) {
+    const int r = t / PMAX, k = t % PMAX;
+    const int64_t i = i0 + r;
+    xs[r][k] = (i < n && k < p) ? X[i * p + k] : 0.f;
+  }
+  if (threadIdx.x < TR) {
+    const int64_t i = i0 + threadIdx.x;
+    qs[threadIdx.x] = (i < n && !LAP) ? q[i] : 0.f;
+  }
+  __syncthreads();
+  if (j >= ldk) return;
+  const bool valid = j < n;
+  float xj[PMAX];
+#pragma unroll
+  for (int k = 0; k < PMAX; ++k) xj[k] = (valid && k < p) ? X[j * p + k] : 0.f;
+  const float qj = (valid && !LAP) ? q[j] : 0.f;
+  for (int r = 0; r < TR; ++r) {
+    const int64_t i = i0 + r;
+    if (i >= n) break;
+    float val = 0.f;
+    if (valid) {
+      float d = pair_dist<PMAX, LAP>(xs[r], qs[r], xj, qj);
+      if (i == j) d = 0.f;
+      val = exp2f(ng * d);
+    }
+    if (BF16) {
+      __builtin_nontemporal_store(f32_to_bf16(val), static_cast<uint16_t*>(Kout) + i * ldk + j);
+    } else {
+      __builtin_nontemporal_store(val, static_cast<float*>(Kout) + i * ldk + j);
+    }
+  }
+}
+
+template <int PMAX>
+static void kbuild_p(const float* X, const float* q, int64_t n, int p, KernelSpec ks, int dtype,
+                     void* K, int64_t ldk, hipStream_t st) {
+  dim3 grid((unsigned)((n + 15) / 16), (unsigned)((ldk + 255) / 256));
+  const float ng = -float(ks.gamma) * kLog2e;
+  const bool lap = ks.kind == KQR_LAPLACIAN, bf = dtype == KQR_BF16;
+  if (lap && bf) kbuild_kernel<PMAX, true, true><<<grid, 256, 0, st>>>(X, q, n, p, ng, K, ldk);
+  else if (lap) kbuild_kernel<PMAX, true, false><<<grid, 256, 0, st>>>(X, q, n, p, ng, K, ldk);
+  else if (bf) kbuild_kernel<PMAX, false, true><<<grid, 256, 0, st>>>(X, q, n, p, ng, K, ldk);
+  else kbuild_kernel<PMAX, false, false><<<grid, 256, 0, st>>>(X, q, n, p, ng, K, ldk);
+  KQR_LAUNCH_CHECK();
+}
+
+#define KQR_DISPATCH_P(p, FN, ...)                                   \
+  do {                                                               \
+    if ((p) <= 8) FN<8>(__VA_ARGS__);                                \
+    else if ((p) <= 12) FN<12>(__VA_ARGS__);                         \
+    else if ((p) <= 16) FN<16>(__VA_ARGS__);                         \
+    else if ((p) <= 20) FN<20>(__VA_ARGS__);                         \
+    else if ((p) <= 24) FN<24>(__VA_ARGS__);                         \
+    else if ((p) <= 32) FN<32>(__VA_ARGS__);                         \
+    else if ((p) <= 48) FN<48>(__VA_ARGS__);                         \
+    else if ((p) <= 64) FN<64>(__VA_ARGS__);                         \
+    else fail(KQR_EINVAL, "feature dimension p=%d exceeds 64", (p)); \
+  } while (0)
+
+void kbuild(const float* X, const float* sqn, int64_t n, int p, KernelSpec ks, int dtype, void* K,
+            int64_t ldk, hipStream_t st) {
+  if (n <= 0) return;
+  KQR_DISPATCH_P(p, kbuild_p, X, sqn, n, p, ks, dtype, K, ldk, st);
+}
+
+// ================================================================= materialised K-apply
+// One wave streams ROWS whole rows of K with 16-byte non-temporal loads,
+// UNROLL chunks per lane per step (ROWS*UNROLL loads in flight per lane); the
+// vector chunk it needs is loaded once per step and shared by the ROWS rows.
+// Per-lane partial sums are reduced across the wave with shuffles, so every
+// output is produced by one wave in a fixed order (deterministic).
+//   fast  (EXACT=false): v in FP32, FP32 products summed in FP32 over one step
+//                        and then added into FP64 accumulators.
+//   exact (EXACT=true) : v in FP64, products and sums in FP64.
+template <bool BF16>
+__device__ __forceinline__ float kelem(const u32x4& w, int e) {
+  if (BF16) {
+    const uint32_t word = w[e >> 1];
+    return (e & 1) ? bf16_hi(word) : bf16_lo(word);
+  } else {
+    return __uint_as_float(w[e]);
+  }
+}
+
+template <int ROWS, int UNROLL, bool EXACT, bool BF16>
+__global__ __launch_bounds__(256) void kapply_rows_kernel(const void* __restrict__ Kp, int64_t ldk,
+                                                          int64_t nrows, int64_t ncols,
+                                                          const float* __restrict__ v32,
+                                                          const double* __restrict__ v64,
+                                                          double* __restrict__ u, int64_t ldu) {
+  constexpr int VEC = BF16 ? 8 : 4;
+  constexpr int ESZ = BF16 ? 2 : 4;
+  const int lane = threadIdx.x & 63;
+  const int64_t row0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * ROWS;
+  if (row0 >= nrows) return;
+  const u32x4* rp[ROWS];
+#pragma unroll
+  for (int r = 0; r < ROWS; ++r) {
+    const int64_t rr = (row0 + r < nrows) ? row0 + r : nrows - 1;
+    rp[r] = reinterpret_cast<const u32x4*>(static_cast<const char*>(Kp) + rr * ldk * ESZ);
+  }
+  const int64_t nchunk = ncols / VEC;
+  double acc[ROWS];
+#pragma unroll
+  for (int r = 0; r < ROWS; ++r) acc[r] = 0.0;
+
+  int64_t c = lane;
+  for (; c + 64 * (UNROLL - 1) < nchunk; c += 64 * UNROLL) {
+    u32x4 kk[ROWS][UNROLL];
+#pragma unroll
+    for (int s = 0; s < UNROLL; ++s)
+#pragma unroll
+      for (int r = 0; r < ROWS; ++r) kk[r][s] = __builtin_nontemporal_load(rp[r] + c + 64 * s);
+    if (EXACT) {
+#pragma unroll
+      for (int s = 0; s < UNROLL; ++s) {
+        double vv[VEC];
+        const double* vp = v64 + (c + 64 * s) * VEC;
+#pragma unroll
+        for (int e = 0; e < VEC; e += 2) {
+          const double2 t = *reinterpret_cast<const double2*>(vp + e);
+          vv[e] = t.x;
+          vv[e + 1] = t.y;
+        }
+#pragma unroll
+        for (int r = 0; r < ROWS; ++r)
+#pragma unroll
+          for (int e = 0; e < VEC; ++e) acc[r] = fma(double(kelem<BF16>(kk[r][s], e)), vv[e], acc[r]);
+      }
+    } else {
+      float a32[ROWS];
+#pragma unroll
+      for (int r = 0; r < ROWS; ++r) a32[r] = 0.f;
+#pragma unroll
+      for (int s = 0; s < UNROLL; ++s) {
+        float vv[VEC];
+        const float* vp = v32 + (c + 64 * s) * VEC;
+#pragma unroll
+        for (int e = 0; e < VEC; e += 4) {
+          const float4 t = *reinterpret_cast<const float4*>(vp + e);
+          vv[e] = t.x;
+          vv[e + 1] = t.y;
+          vv[e + 2] = t.z;
+          vv[e + 3] = t.w;
+        }
+#pragma unroll
+        for (int r = 0; r < ROWS; ++r)
+#pragma unroll
+          for (int e = 0; e < VEC; ++e) a32[r] = fmaf(kelem<BF16>(kk[r][s], e), vv[e], a32[r]);
+      }
+#pragma unroll
+      for (int r = 0; r < ROWS; ++r) acc[r] += double(a32[r]);
+    }
+  }
+  for (; c < nchunk; c += 64) {
+    u32x4 kk[ROWS];
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) kk[r] = __builtin_nontemporal_load(rp[r] + c);
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) {
+      const double ve = EXACT ? v64[c * VEC + e] : double(v32[c * VEC + e]);
+#pragma unroll
+      for (int r = 0; r < ROWS; ++r) acc[r] = fma(double(kelem<BF16>(kk[r], e)), ve, acc[r]);
+    }
+  }
+  // trailing columns that do not fill a 16-byte chunk
+  const int64_t col = nchunk * VEC + lane;
+  if (col < ncols) {
+    const double ve = EXACT ? v64[col] : double(v32[col]);
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) {
+      const char* base = reinterpret_cast<const char*>(rp[r]);
+      const float ke = BF16 ? bf16_to_f32(reinterpret_cast<const uint16_t*>(base)[col])
+                            : reinterpret_cast<const float*>(base)[col];
+      acc[r] = fma(double(ke), ve, acc[r]);
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < ROWS; ++r)
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) acc[r] += __shfl_xor(acc[r], off);
+#pragma unroll
+  for (int r = 0; r < ROWS; ++r)
+    if (lane == r && row0 + r < nrows) u[(row0 + r) * ldu] = acc[r];
+}
+
+namespace {
+std::mutex g_shape_mu;
+ApplyShape g_shape[2][2] = {{{8, 2}, {8, 2}}, {{8, 2}, {8, 2}}};  // [dtype][exact]
+bool g_shape_set[2][2] = {};
+}  // namespace
+
+ApplyShape default_apply_shape(int dtype, int exact, int64_t n) {
+  std::lock_guard<std::mutex> lk(g_shape_mu);
+  const int d = dtype == KQR_BF16, e = exact != 0;
+  if (g_shape_set[d][e]) return g_shape[d][e];
+  (void)n;
+  return ApplyShape{8, 2};
+}
+
+void set_apply_shape(int dtype, int exact, ApplyShape s) {
+  std::lock_guard<std::mutex> lk(g_shape_mu);
+  const int d = dtype == KQR_BF16, e = exact != 0;
+  g_shape[d][e] = s;
+  g_shape_set[d][e] = true;
+}
+
+template <int ROWS, int UNROLL>
+static void kapply_rows_launch(const KMat& km, int64_t nrows, int64_t ncols, const float* v32,
+                               const double* v64, double* u, int64_t ldu, bool exact,
+                               hipStream_t st) {
+  const int64_t waves = (nrows + ROWS - 1) / ROWS;
+  const dim3 grid((unsigned)((waves + 3) / 4));
+  const bool bf = km.dtype == KQR_BF16;
+  if (exact && bf)
+    kapply_rows_kernel<ROWS, UNROLL, true, true><<<grid, 256, 0, st>>>(km.K, km.ld, nrows, ncols, v32, v64, u, ldu);
+  else if (exact)
+    kapply_rows_kernel<ROWS, UNROLL, true, false><<<grid, 256, 0, st>>>(km.K, km.ld, nrows, ncols, v32, v64, u, ldu);
+  else if (bf)
+    kapply_rows_kernel<ROWS, UNROLL, false, true><<<grid, 256, 0, st>>>(km.K, km.ld, nrows, ncols, v32, v64, u, ldu);
+  else
+    kapply_rows_kernel<ROWS, UNROLL, false, false><<<grid, 256, 0, st>>>(km.K, km.ld, nrows, ncols, v32, v64, u, ldu);
+  KQR_LAUNCH_CHECK();
+}
+
+void kapply_dense(const KMat& km, int64_t nrows, int64_t ncols, const float* v32, const double* v64,
+                  double* u, int64_t ldu, bool exact, hipStream_t st, const ApplyShape* shape) {
+  if (nrows <= 0) return;
+  const ApplyShape s = shape ? *shape : default_apply_shape(km.dtype, exact, nrows);
+  const int key = s.rows * 100 + s.unroll;
+  switch (key) {
+    case 401: kapply_rows_launch<4, 1>(km, nrows, ncols, v32, v64, u, ldu, exact, st); break;
+    case 402: kapply_rows_launch<4, 2>(km, nrows, ncols, v32, v64, u, ldu, exact, st); break;
+    case 404: kapply_rows_launch<4, 4>(km, nrows, ncols, v32, v64, u, ldu, exact, st); break;
+    case 801: kapply_rows_launch<8, 1>(km, nrows, ncols, v32, v64, u, ldu, exact, st); break;
+    case 802: kapply_rows_launch<8, 2>(km, nrows, ncols, v32, v64, u, ldu, exact, st); break;
+    case 804: kapply_rows_launch<8, 4>(km, nrows, ncols, v32, v64, u, ldu, exact, st); break;
+    case 1601: kapply_rows_launch<16, 1>(km, nrows, ncols, v32, v64, u, ldu, exact, st); break;
+    case 1602: kapply_rows_launch<16, 2>(km, nrows, ncols, v32, v64, u, ldu, exact, st); break;
+    default: fail(KQR_EINVAL, "unsupported K-apply shape rows=%d unroll=%d", s.rows, s.unroll);
+  }
+}
+
+// ================================================================= on-the-fly K-apply
+// One thread per output row i keeps x_i (and ||x_i||^2) in registers; the
+// block walks a slice of the columns in tiles of 64 staged in LDS (x_j, the
+// norms and v_j, read as broadcasts), forms k(x_i, x_j) and accumulates
+// k * v_j in FP32 over a tile, then into an FP64 accumulator.  Columns are
+// split over gridDim.y slices so that small row counts still fill the chip;
+// the slices' partial sums are added in a fixed order by a second kernel.
+constexpr int kOtfTile = 64;
+
+template <int PMAX, bool LAP>
+__global__ __launch_bounds__(256) void kapply_otf_kernel(
+    const float* __restrict__ Xr, const float* __restrict__ qr, int64_t nr,
+    const float* __restrict__ Xc, const float* __restrict__ qc, int64_t nc, int p, float ng,
+    const double* __restrict__ v, int64_t cols_per_slice, double* __restrict__ part) {
+  __shared__ float xs[kOtfTile][PMAX];
+  __shared__ float qs[kOtfTile];
+  __shared__ float vs[kOtfTile];
+  const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  const bool row_ok = i < nr;
+  float xi[PMAX];
+#pragma unroll
+  for (int k = 0; k < PMAX; ++k) xi[k] = (row_ok && k < p) ? Xr[i * p + k] : 0.f;
+  const float qi = (row_ok && !LAP) ? qr[i] : 0.f;
+  const int64_t c0 = int64_t(blockIdx.y) * cols_per_slice;
+  const int64_t c1 = min(nc, c0 + cols_per_slice);
+  double acc = 0.0;
+  for (int64_t jb = c0; jb < c1; jb += kOtfTile) {
+    const int cnt = int(min<int64_t>(kOtfTile, c1 - jb));
+    __syncthreads();
+    for (int t = threadIdx.x; t < kOtfTile * PMAX; t += 256) {
+      const int jj = t / PMAX, k = t % PMAX;
+      xs[jj][k] = (jj < cnt && k < p) ? Xc[(jb + jj) * p + k] : 0.f;
+    }
+    if (threadIdx.x < kOtfTile) {
+      const int jj = threadIdx.x;
+      qs[jj] = (jj < cnt && !LAP) ? qc[jb + jj] : 0.f;
+      vs[jj] = jj < cnt ? float(v[jb + jj]) : 0.f;
+    }
+    __syncthreads();
+    float a32 = 0.f;
+    for (int jj = 0; jj < cnt; ++jj) {
+      const float d = pair_dist<PMAX, LAP>(xs[jj], qs[jj], xi, qi);
+      a32 = fmaf(exp2f(ng * d), vs[jj], a32);
+    }
+    acc += double(a32);
+  }
+  if (row_ok) part[int64_t(blockIdx.y) * nr + i] = acc;
+}
+
+__global__ void otf_reduce_kernel(const double* __restrict__ part, int nslice, int64_t nr, double* __restrict__ u,
+                                  int64_t ldu, double out_scale, double out_shift) {
+  const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (i >= nr) return;
+  double s = 0.0;
+  for (int k = 0; k < nslice; ++k) s += part[int64_t(k) * nr + i];
+  u[i * ldu] = out_shift + out_scale * s;
+}
+
+template <int PMAX>
+static void kapply_otf_p(const float* Xr, const float* qr, int64_t nr, const float* Xc,
+                         const float* qc, int64_t nc, int p, KernelSpec ks, const double* v, double* u,
+                         int64_t ldu, double scale, double shift, hipStream_t st) {
+  const int64_t rblk = (nr + 255) / 256;
+  // enough column slices for ~2048 blocks, each slice at least 1024 columns
+  int64_t nslice = std::max<int64_t>(1, std::min<int64_t>(2048 / std::max<int64_t>(rblk, 1), (nc + 1023) / 1024));
+  nslice = std::min<int64_t>(nslice, 65535);
+  int64_t per = (nc + nslice - 1) / nslice;
+  per = (per + kOtfTile - 1) / kOtfTile * kOtfTile;
+  nslice = (nc + per - 1) / per;
+  double* part = nullptr;
+  KQR_CHECK_HIP(hipMallocAsync(reinterpret_cast<void**>(&part), size_t(nslice) * size_t(nr) * sizeof(double), st));
+  const dim3 grid((unsigned)rblk, (unsigned)nslice);
+  const float ng = -float(ks.gamma) * kLog2e;
+  if (ks.kind == KQR_LAPLACIAN)
+    kapply_otf_kernel<PMAX, true><<<grid, 256, 0, st>>>(Xr, qr, nr, Xc, qc, nc, p, ng, v, per, part);
+  else
+    kapply_otf_kernel<PMAX, false><<<grid, 256, 0, st>>>(Xr, qr, nr, Xc, qc, nc, p, ng, v, per, part);
+  KQR_LAUNCH_CHECK();
+  otf_reduce_kernel<<<dim3((unsigned)((nr + 255) / 256)), 256, 0, st>>>(part, int(nslice), nr, u, ldu, scale, shift);
+  KQR_LAUNCH_CHECK();
+  KQR_CHECK_HIP(hipFreeAsync(part, st));
+}
+
+void kapply_otf(const float* Xr, const float* sqr, int64_t nr, const float* Xc, const float* sqc,
+                int64_t nc, int p, KernelSpec ks, const double* v64, double* u, int64_t ldu,
+                double out_scale, double out_shift, hipStream_t st) {
+  if (nr <= 0) return;
+  KQR_DISPATCH_P(p, kapply_otf_p, Xr, sqr, nr, Xc, sqc, nc, p, ks, v64, u, ldu, out_scale, out_shift, st);
+}
+
+// ================================================================= one kernel row
+template <bool BF16>
+__global__ void krow_from_mat_kernel(const void* __restrict__ K, int64_t ldk, int64_t n, int64_t s,
+                                     double* __restrict__ out) {
+  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  if (BF16) out[j] = bf16_to_f32(static_cast<const uint16_t*>(K)[s * ldk + j]);
+  else out[j] = static_cast<const float*>(K)[s * ldk + j];
+}
+
+template <int PMAX, bool LAP>
+__global__ void krow_from_x_kernel(const float* __restrict__ X, const float* __restrict__ q,
+                                   int64_t n, int p, float ng, int64_t s, double* __restrict__ out) {
+  __shared__ float xs[PMAX];
+  if (threadIdx.x < PMAX) xs[threadIdx.x] = threadIdx.x < p ? X[s * p + threadIdx.x] : 0.f;
+  __syncthreads();
+  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  float xj[PMAX];
+#pragma unroll
+  for (int k = 0; k < PMAX; ++k) xj[k] = k < p ? X[j * p + k] : 0.f;
+  float d = pair_dist<PMAX, LAP>(xs, LAP ? 0.f : q[s], xj, LAP ? 0.f : q[j]);
+  if (j == s) d = 0.f;
+  out[j] = exp2f(ng * d);
+}
+
+template <int PMAX>
+static void krow_p(const float* X, const float* q, int64_t n, int p, KernelSpec ks, int64_t s,
+                   double* out, hipStream_t st) {
+  const dim3 grid((unsigned)((n + 255) / 256));
+  const float ng = -float(ks.gamma) * kLog2e;
+  if (ks.kind == KQR_LAPLACIAN) krow_from_x_kernel<PMAX, true><<<grid, 256, 0, st>>>(X, q, n, p, ng, s, out);
+  else krow_from_x_kernel<PMAX, false><<<grid, 256, 0, st>>>(X, q, n, p, ng, s, out);
+  KQR_LAUNCH_CHECK();
+}
+
+void kernel_row(const KMat& km, const float* X, const float* sqn, int64_t n, int p, KernelSpec ks,
+                int64_t s, double* out, hipStream_t st) {
+  if (km.K) {
+    const dim3 grid((unsigned)((n + 255) / 256));
+    if (km.dtype == KQR_BF16) krow_from_mat_kernel<true><<<grid, 256, 0, st>>>(km.K, km.ld, n, s, out);
+    else krow_from_mat_kernel<false><<<grid, 256, 0, st>>>(km.K, km.ld, n, s, out);
+    KQR_LAUNCH_CHECK();
+    return;
+  }
+  KQR_DISPATCH_P(p, krow_p, X, sqn, n, p, ks, s, out, st);
+}
+
+// ================================================================= FP64 -> FP32
+__global__ void to_f32_kernel(const double* __restrict__ src, int64_t n, int m, int64_t lds,
+                              float* __restrict__ dst, int64_t ldd) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= n * m) return;
+  const int64_t i = t / m;
+  const int k = int(t % m);
+  dst[i * ldd + k] = float(src[i * lds + k]);
+}
+
+void to_f32(const double* src, int64_t n, int m, int64_t lds, float* dst, int64_t ldd, hipStream_t st) {
+  if (n <= 0) return;
+  const int64_t tot = n * m;
+  to_f32_kernel<<<dim3((unsigned)((tot + 255) / 256)), 256, 0, st>>>(src, n, m, lds, dst, ldd);
+  KQR_LAUNCH_CHECK();
+}
+
+}  // namespace kqr

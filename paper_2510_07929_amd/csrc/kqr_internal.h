@@ -1,0 +1,115 @@
+// Internal declarations shared by the libkqr translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "kqr.h"
+
+namespace kqr {
+
+// ----------------------------------------------------------------- errors
+struct Error : std::runtime_error {
+  int status;
+  Error(int s, const std::string& m) : std::runtime_error(m), status(s) {}
+};
+
+void set_last_error(const std::string& msg);
+[[noreturn]] void fail(int status, const char* fmt, ...);
+
+#define KQR_CHECK_HIP(call)                                                         \
+  do {                                                                              \
+    hipError_t e_ = (call);                                                         \
+    if (e_ != hipSuccess)                                                           \
+      ::kqr::fail(e_ == hipErrorOutOfMemory ? KQR_ENOMEM : KQR_EHIP, "%s:%d %s: %s", \
+                  __FILE__, __LINE__, #call, hipGetErrorString(e_));                \
+  } while (0)
+
+#define KQR_LAUNCH_CHECK() KQR_CHECK_HIP(hipGetLastError())
+
+// ----------------------------------------------------------------- device memory
+// Owning device buffer (hipMalloc / hipFree).
+struct DevBuf {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  explicit DevBuf(size_t b) { alloc(b); }
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  DevBuf(DevBuf&& o) noexcept : ptr(o.ptr), bytes(o.bytes) { o.ptr = nullptr; o.bytes = 0; }
+  DevBuf& operator=(DevBuf&& o) noexcept {
+    if (this != &o) { release(); ptr = o.ptr; bytes = o.bytes; o.ptr = nullptr; o.bytes = 0; }
+    return *this;
+  }
+  ~DevBuf() { release(); }
+  void alloc(size_t b);
+  void release();
+  template <typename T> T* as() const { return static_cast<T*>(ptr); }
+};
+
+// Pinned host staging for small device->host reads.
+struct HostPinned {
+  void* ptr = nullptr;
+  explicit HostPinned(size_t b);
+  ~HostPinned();
+  HostPinned(const HostPinned&) = delete;
+  HostPinned& operator=(const HostPinned&) = delete;
+  template <typename T> T* as() const { return static_cast<T*>(ptr); }
+};
+
+void ensure_device();  // throws KQR_ENODEVICE when no device is usable
+
+// ----------------------------------------------------------------- kernel matrix ops
+struct KernelSpec {
+  int kind;      // KQR_RBF / KQR_LAPLACIAN
+  double gamma;
+};
+
+// Materialised operator description.
+struct KMat {
+  const void* K = nullptr;  // nullptr: on the fly
+  int dtype = KQR_FP32;
+  int64_t ld = 0;
+};
+
+// Tile shapes of the materialised K-apply (rows per wave, 16-byte chunks per lane per step).
+struct ApplyShape {
+  int rows = 8;
+  int unroll = 2;
+};
+ApplyShape default_apply_shape(int dtype, int exact, int64_t n);
+void set_apply_shape(int dtype, int exact, ApplyShape s);  // autotuner override
+
+// K build: K[i, j] for i < n, j < ldk (j >= n written as 0).
+void kbuild(const float* X, const float* sqn, int64_t n, int p, KernelSpec ks, int dtype, void* K,
+            int64_t ldk, hipStream_t st);
+// Squared row norms of X (FP32).
+void row_sqnorms(const float* X, int64_t n, int p, float* sqn, hipStream_t st);
+
+// u = K v (materialised, rows [0, nrows), cols [0, ncols)).  exact: v64 + FP64; else v32.
+void kapply_dense(const KMat& km, int64_t nrows, int64_t ncols, const float* v32, const double* v64,
+                  double* u, int64_t ldu, bool exact, hipStream_t st, const ApplyShape* shape = nullptr);
+// u = K(Xr, Xc) v computed on the fly; v64 FP64, products in FP32, FP64 row sums.
+void kapply_otf(const float* Xr, const float* sqr, int64_t nr, const float* Xc, const float* sqc,
+                int64_t nc, int p, KernelSpec ks, const double* v64, double* u, int64_t ldu,
+                double out_scale, double out_shift, hipStream_t st);
+// One row of K: out[j] = k(x_s, x_j) in FP64 (from a materialised row or from X).
+void kernel_row(const KMat& km, const float* X, const float* sqn, int64_t n, int p, KernelSpec ks,
+                int64_t s, double* out, hipStream_t st);
+
+// FP64 -> FP32 copy (for the fast apply), strided rows.
+void to_f32(const double* src, int64_t n, int m, int64_t lds, float* dst, int64_t ldd, hipStream_t st);
+
+// ----------------------------------------------------------------- reductions
+// Deterministic two-pass sums: kernels write per-block partials, finalize sums
+// them in a fixed order into `out`.
+constexpr int kRedBlocks = 512;
+constexpr int kRedThreads = 256;
+void reduce_finalize(const double* partials, int nblocks, int nq, double* out, hipStream_t st);
+
+}  // namespace kqr

@@ -1,0 +1,120 @@
+// Host-side driver objects of the fit.
+#pragma once
+
+#include <memory>
+
+#include "vec.h"
+
+namespace kqr {
+
+// The kernel operator K v: materialised (FP32 / BF16 storage) or on the fly.
+class Operator {
+ public:
+  Operator(const float* X, int64_t n, int p, KernelSpec ks, KMat km, hipStream_t st);
+  // Fast apply: FP32 products (from v32 when given, else a rounded copy of v).
+  void apply_fast(const double* v, const float* v32, double* u, hipStream_t st);
+  // Exact apply: FP32 entries (stored FP32 or recomputed) with FP64 vector and sums.
+  void apply_exact(const double* v, double* u, hipStream_t st);
+  bool materialized() const { return km_.K != nullptr; }
+  int64_t calls() const { return calls_; }
+  const KMat& kmat() const { return km_; }
+  const float* sqn() const { return sqn_.as<float>(); }
+  const float* X() const { return X_; }
+  int p() const { return p_; }
+  KernelSpec spec() const { return ks_; }
+  // Record HIP events around every K-apply kernel (for kqr_info.t_kapply_*).
+  void enable_profile(bool on) { profile_ = on; }
+  // Sums the recorded kernel times (synchronises the events); seconds.
+  void profile_totals(int64_t& nfast, double& tfast, int64_t& nexact, double& texact);
+  ~Operator();
+
+ private:
+  struct Span { hipEvent_t a, b; bool fast; };
+  void mark(bool begin, bool fast, hipStream_t st);
+  const float* X_;
+  int64_t n_;
+  int p_;
+  KernelSpec ks_;
+  KMat km_;
+  DevBuf sqn_, v32_;
+  int64_t calls_ = 0;
+  bool profile_ = false;
+  std::vector<Span> spans_;
+};
+
+struct PcgBuffers {
+  DevBuf r, zz, p, q, Kp, p32, sc;
+  HostPinned hsc;
+  explicit PcgBuffers(int64_t n);
+};
+
+struct PcgStats {
+  int iters = 0;
+  double resnorm = 0.0;
+  bool breakdown = false;
+};
+
+struct Kkt {
+  double eta_p = 1, eta_d = 1, eta_c = 1, eta_kkt = 1, eta_gap = 1, err = 1;
+  double obj_p = 0, obj_d = 0, sum_alpha = 0;
+};
+
+// Left-preconditioned conjugate gradients on (K + c 1 1^T + diag(L)) x = b.
+class Pcg {
+ public:
+  Pcg(Operator& op, Workspace& ws, int64_t n);
+  // x holds the start (ignored when x_zero); Kx, when given, holds K x on entry
+  // (ignored when x_zero) and is advanced with the same steps as x.
+  PcgStats solve(double c, const double* L, Woodbury* P, const double* b, double* x, double* Kx, bool x_zero,
+                 double tol, int maxit, bool fast, hipStream_t st);
+
+ private:
+  double read_scalar(const double* dev, hipStream_t st);
+  void read_scalars(const double* dev, int cnt, double* out, hipStream_t st);
+  Operator& op_;
+  Workspace& ws_;
+  int64_t n_;
+  PcgBuffers pb_;
+  HostPinned hbuf_;
+};
+
+class Solver {
+ public:
+  Solver(Operator& op, const double* y, int64_t n, double tau, double lam, const kqr_options& o, const float* F,
+         int64_t rank, int64_t ldf, hipStream_t st);
+  void phase1(kqr_info& info);
+  void phase2(kqr_info& info);
+  void finish(kqr_info& info);
+  const double* alpha() const { return alpha_.as<double>(); }
+  double beta() const { return beta_; }
+  bool converged() const { return converged_; }
+  Workspace& ws() { return ws_; }
+
+ private:
+  void ssn(double stop, kqr_info& info);
+  Kkt kkt_from_sums(const double* s) const;
+  Kkt update_and_kkt(double beta_new, double sigma, double step, bool update);
+  double sum_of(const double* x);
+  double read_scalar(const double* dev, hipStream_t st);
+  void read_scalars(const double* dev, int cnt, double* out, hipStream_t st);
+
+  Operator& op_;
+  const double* y_;
+  int64_t n_;
+  double tau_, lam_;
+  kqr_options o_;
+  hipStream_t st_;
+  Workspace ws_;
+  Pcg pcg_;
+  HostPinned hbuf_;
+  DevBuf alpha_, v_, z_, Ka_, b_, L_, grad_, d_, Kd_, S_, red_;
+  std::unique_ptr<Woodbury> P_;
+  double beta_ = 0.0, sigma_ = 1.0, ynorm_ = 0.0, eta_d_prev_ = 1.0;
+  Kkt last_;
+  bool converged_ = false;
+};
+
+// copy src -> dst and dot_with . dst into *out (device)
+void copy_dot(int64_t n, const double* src, double* dst, Workspace& ws, double* out, hipStream_t st);
+
+}  // namespace kqr

@@ -1,0 +1,366 @@
+// Host driver of PALM-KQR on one stream: PCG (Section 3), Phase I inexact
+// ADMM (Algorithm 1), Phase II semismooth Newton ALM (Algorithms 2 and 3),
+// stopping rules of Section 4.  Every O(n) and O(n^2) step runs in device
+// kernels; the host only sequences launches and reads back the scalars that
+// decide convergence (a few doubles per iteration).
+#include "solver.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstring>
+
+namespace kqr {
+
+// ================================================================= operator
+Operator::Operator(const float* X, int64_t n, int p, KernelSpec ks, KMat km, hipStream_t st)
+    : X_(X), n_(n), p_(p), ks_(ks), km_(km), sqn_(size_t(std::max<int64_t>(n, 1)) * sizeof(float)),
+      v32_(size_t(std::max<int64_t>(n, 1)) * sizeof(float)) {
+  row_sqnorms(X, n, p, sqn_.as<float>(), st);
+}
+
+Operator::~Operator() {
+  for (auto& s : spans_) {
+    (void)hipEventDestroy(s.a);
+    (void)hipEventDestroy(s.b);
+  }
+}
+
+void Operator::mark(bool begin, bool fast, hipStream_t st) {
+  if (!profile_) return;
+  if (begin) {
+    Span s{};
+    KQR_CHECK_HIP(hipEventCreate(&s.a));
+    KQR_CHECK_HIP(hipEventCreate(&s.b));
+    s.fast = fast;
+    spans_.push_back(s);
+    KQR_CHECK_HIP(hipEventRecord(spans_.back().a, st));
+  } else {
+    KQR_CHECK_HIP(hipEventRecord(spans_.back().b, st));
+  }
+}
+
+void Operator::profile_totals(int64_t& nfast, double& tfast, int64_t& nexact, double& texact) {
+  nfast = nexact = 0;
+  tfast = texact = 0.0;
+  for (auto& s : spans_) {
+    KQR_CHECK_HIP(hipEventSynchronize(s.b));
+    float ms = 0.f;
+    KQR_CHECK_HIP(hipEventElapsedTime(&ms, s.a, s.b));
+    if (s.fast) { ++nfast; tfast += 1e-3 * ms; }
+    else { ++nexact; texact += 1e-3 * ms; }
+  }
+}
+
+void Operator::apply_fast(const double* v, const float* v32, double* u, hipStream_t st) {
+  ++calls_;
+  if (km_.K) {
+    if (!v32) {
+      to_f32(v, n_, 1, 1, v32_.as<float>(), 1, st);
+      v32 = v32_.as<float>();
+    }
+    mark(true, true, st);
+    kapply_dense(km_, n_, n_, v32, nullptr, u, 1, false, st);
+    mark(false, true, st);
+  } else {
+    mark(true, true, st);
+    kapply_otf(X_, sqn_.as<float>(), n_, X_, sqn_.as<float>(), n_, p_, ks_, v, u, 1, 1.0, 0.0, st);
+    mark(false, true, st);
+  }
+}
+
+void Operator::apply_exact(const double* v, double* u, hipStream_t st) {
+  ++calls_;
+  mark(true, false, st);
+  if (km_.K && km_.dtype == KQR_FP32) {
+    kapply_dense(km_, n_, n_, nullptr, v, u, 1, true, st);
+  } else {
+    // BF16 storage is not the exact operator: recompute FP32 entries from X.
+    kapply_otf(X_, sqn_.as<float>(), n_, X_, sqn_.as<float>(), n_, p_, ks_, v, u, 1, 1.0, 0.0, st);
+  }
+  mark(false, false, st);
+}
+
+// ================================================================= PCG
+PcgBuffers::PcgBuffers(int64_t n)
+    : r(n * sizeof(double)), zz(n * sizeof(double)), p(n * sizeof(double)), q(n * sizeof(double)),
+      Kp(n * sizeof(double)), p32(n * sizeof(float)), sc(16 * sizeof(double)), hsc(16 * sizeof(double)) {}
+
+Pcg::Pcg(Operator& op, Workspace& ws, int64_t n) : op_(op), ws_(ws), n_(n), pb_(n), hbuf_(16 * sizeof(double)) {}
+
+double Pcg::read_scalar(const double* dev, hipStream_t st) {
+  KQR_CHECK_HIP(hipMemcpyAsync(hbuf_.ptr, dev, sizeof(double), hipMemcpyDeviceToHost, st));
+  KQR_CHECK_HIP(hipStreamSynchronize(st));
+  return *hbuf_.as<double>();
+}
+
+void Pcg::read_scalars(const double* dev, int cnt, double* out, hipStream_t st) {
+  KQR_CHECK_HIP(hipMemcpyAsync(hbuf_.ptr, dev, cnt * sizeof(double), hipMemcpyDeviceToHost, st));
+  KQR_CHECK_HIP(hipStreamSynchronize(st));
+  memcpy(out, hbuf_.ptr, cnt * sizeof(double));
+}
+
+double Solver::read_scalar(const double* dev, hipStream_t st) {
+  KQR_CHECK_HIP(hipMemcpyAsync(hbuf_.ptr, dev, sizeof(double), hipMemcpyDeviceToHost, st));
+  KQR_CHECK_HIP(hipStreamSynchronize(st));
+  return *hbuf_.as<double>();
+}
+
+void Solver::read_scalars(const double* dev, int cnt, double* out, hipStream_t st) {
+  KQR_CHECK_HIP(hipMemcpyAsync(hbuf_.ptr, dev, cnt * sizeof(double), hipMemcpyDeviceToHost, st));
+  KQR_CHECK_HIP(hipStreamSynchronize(st));
+  memcpy(out, hbuf_.ptr, cnt * sizeof(double));
+}
+
+// Solves (K + c 1 1^T + diag(L)) x = b.  x holds the start (ignored when
+// x_zero); Kx, when given, holds K x on entry (ignored when x_zero) and is
+// advanced with the same steps as x, so on return Kx = K x up to rounding
+// without an extra K-apply.
+PcgStats Pcg::solve(double c, const double* L, Woodbury* P, const double* b, double* x, double* Kx,
+                     bool x_zero, double tol, int maxit, bool fast, hipStream_t st) {
+  const int64_t n = n_;
+  double* sc = pb_.sc.as<double>();
+  enum { RZ0 = 0, RZ1 = 1, PQ = 2, RR = 3, SUMP = 4, SUMX = 5, TMP = 8 };
+  if (x_zero) {
+    fill(n, 0.0, x, st);
+    if (Kx) fill(n, 0.0, Kx, st);
+    pcg_init_r(n, b, nullptr, nullptr, L, c, sc, -1, pb_.r.as<double>(), ws_, sc + RR, st);
+  } else {
+    vec_dots(n, x, nullptr, ws_, sc + TMP, st);  // sc[TMP] = sum(x)
+    const double* Kx0 = Kx;
+    if (!Kx0) {
+      op_.apply_exact(x, pb_.Kp.as<double>(), st);
+      Kx0 = pb_.Kp.as<double>();
+    }
+    pcg_init_r(n, b, x, Kx0, L, c, sc, TMP, pb_.r.as<double>(), ws_, sc + RR, st);
+  }
+  double rr = read_scalar(sc + RR, st);
+  PcgStats stats;
+  stats.resnorm = std::sqrt(rr);
+  if (!(stats.resnorm > tol)) return stats;
+  int cur = 0;
+  auto precond = [&](int slot) {
+    if (P) P->apply(pb_.r.as<double>(), pb_.zz.as<double>(), pb_.r.as<double>(), sc + slot, ws_, st);
+    else copy_dot(n, pb_.r.as<double>(), pb_.zz.as<double>(), ws_, sc + slot, st);
+  };
+  float* p32 = (fast && op_.materialized()) ? pb_.p32.as<float>() : nullptr;
+  precond(RZ0);
+  pcg_update_p(n, pb_.zz.as<double>(), pb_.p.as<double>(), p32, sc, RZ0, RZ0, true, ws_, sc + SUMP, st);
+  for (int it = 1; it <= maxit; ++it) {
+    if (fast) op_.apply_fast(pb_.p.as<double>(), p32, pb_.Kp.as<double>(), st);
+    else op_.apply_exact(pb_.p.as<double>(), pb_.Kp.as<double>(), st);
+    pcg_q(n, pb_.Kp.as<double>(), pb_.p.as<double>(), L, c, sc, SUMP, pb_.q.as<double>(), ws_, sc + PQ, st);
+    pcg_xr(n, pb_.p.as<double>(), pb_.q.as<double>(), pb_.Kp.as<double>(), x, pb_.r.as<double>(), Kx, sc,
+           cur == 0 ? RZ0 : RZ1, PQ, ws_, sc + RR, st);
+    double two[2];
+    read_scalars(sc + PQ, 2, two, st);  // [PQ, RR]
+    stats.iters = it;
+    stats.resnorm = std::sqrt(std::max(two[1], 0.0));
+    if (!(two[0] > 0.0)) {  // curvature lost: the step just taken is unreliable, stop here
+      stats.breakdown = true;
+      break;
+    }
+    if (stats.resnorm <= tol) break;
+    const int nxt = 1 - cur;
+    precond(nxt == 0 ? RZ0 : RZ1);
+    pcg_update_p(n, pb_.zz.as<double>(), pb_.p.as<double>(), p32, sc, cur == 0 ? RZ0 : RZ1,
+                 nxt == 0 ? RZ0 : RZ1, false, ws_, sc + SUMP, st);
+    cur = nxt;
+  }
+  return stats;
+}
+
+// ================================================================= solver
+Solver::Solver(Operator& op, const double* y, int64_t n, double tau, double lam, const kqr_options& o,
+               const float* F, int64_t rank, int64_t ldf, hipStream_t st)
+    : op_(op), y_(y), n_(n), tau_(tau), lam_(lam), o_(o), st_(st), pcg_(op, ws_, n), hbuf_(64 * sizeof(double)),
+      alpha_(n * sizeof(double)), v_(n * sizeof(double)), z_(n * sizeof(double)), Ka_(n * sizeof(double)),
+      b_(n * sizeof(double)), L_(n * sizeof(double)), grad_(n * sizeof(double)), d_(n * sizeof(double)),
+      Kd_(n * sizeof(double)), S_(n), red_(64 * sizeof(double)) {
+  if (rank > 0) P_.reset(new Woodbury(F, n, rank, ldf));
+  double t3[3];
+  vec_dots(n, y, nullptr, ws_, red_.as<double>(), st);
+  read_scalars(red_.as<double>(), 3, t3, st);
+  ynorm_ = std::sqrt(t3[2]);
+  if (!std::isfinite(ynorm_)) fail(KQR_ENUMERIC, "y contains NaN or Inf");
+}
+
+Kkt Solver::kkt_from_sums(const double* s) const {
+  Kkt k;
+  k.eta_p = std::sqrt(std::max(s[0], 0.0)) / (1.0 + ynorm_);
+  k.eta_d = std::sqrt(s[8] * s[8] + std::max(s[1], 0.0)) / (1.0 + std::sqrt(std::max(s[2], 0.0)));
+  k.eta_c = std::sqrt(std::max(s[3], 0.0)) / (1.0 + std::sqrt(std::max(s[4], 0.0)));
+  k.obj_p = s[5] + s[6] / (2.0 * lam_);
+  k.obj_d = -s[6] / (2.0 * lam_) + s[7];
+  k.eta_gap = std::fabs(k.obj_p - k.obj_d) / (1.0 + std::fabs(k.obj_p) + std::fabs(k.obj_d));
+  k.eta_kkt = std::max(k.eta_p, std::max(k.eta_d, k.eta_c));
+  k.err = std::max(k.eta_kkt, k.eta_gap);
+  k.sum_alpha = s[8];
+  return k;
+}
+
+double Solver::sum_of(const double* x) {
+  double t3[3];
+  vec_dots(n_, x, nullptr, ws_, red_.as<double>(), st_);
+  read_scalars(red_.as<double>(), 3, t3, st_);
+  return t3[0];
+}
+
+Kkt Solver::update_and_kkt(double beta_new, double sigma, double step, bool update) {
+  double s[kKktSums];
+  multiplier_kkt(n_, alpha_.as<double>(), Ka_.as<double>(), y_, z_.as<double>(), v_.as<double>(), beta_new, sigma,
+                 step, tau_, lam_, update, ws_, red_.as<double>(), st_);
+  read_scalars(red_.as<double>(), kKktSums, s, st_);
+  return kkt_from_sums(s);
+}
+
+static double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// Algorithm 1.  M = K + lambda sigma (I + 1 1^T) is fixed, so the Woodbury
+// core (L = lambda sigma I) is formed once.
+void Solver::phase1(kqr_info& info) {
+  const double t0 = now_s();
+  const int64_t n = n_;
+  const double sigma = o_.admm_sigma, step = o_.admm_step, c = lam_ * sigma;
+  fill(n, c, L_.as<double>(), st_);
+  if (P_ && !P_->build(L_.as<double>(), c, st_)) fail(KQR_ENUMERIC, "ADMM preconditioner core not positive definite");
+  fill(n, 0.0, alpha_.as<double>(), st_);
+  fill(n, 0.0, v_.as<double>(), st_);
+  fill(n, 0.0, z_.as<double>(), st_);
+  fill(n, 0.0, Ka_.as<double>(), st_);
+  beta_ = 0.0;
+  double b0 = 0.0;
+  Kkt k;
+  int it = 0;
+  for (it = 0; it < o_.admm_max_iter; ++it) {
+    admm_rhs(n, y_, z_.as<double>(), v_.as<double>(), beta_, sigma, lam_, b_.as<double>(), st_);
+    if (it == 0) {
+      double t3[3];
+      vec_dots(n, b_.as<double>(), nullptr, ws_, red_.as<double>(), st_);
+      read_scalars(red_.as<double>(), 3, t3, st_);
+      b0 = std::sqrt(t3[2]);
+    }
+    const double eps_k = o_.admm_eps0 * b0 / std::pow(double(it + 1), 1.5);
+    PcgStats ps = pcg_.solve(c, L_.as<double>(), P_.get(), b_.as<double>(), alpha_.as<double>(), Ka_.as<double>(), it == 0,
+                      eps_k, o_.pcg_max_iter, true, st_);
+    info.admm_pcg_iters += ps.iters;
+    const double sa = sum_of(alpha_.as<double>());
+    const double beta_new = beta_ + step * sigma * sa;
+    k = update_and_kkt(beta_new, sigma, step, true);
+    beta_ = beta_new;
+    if (o_.verbose)
+      fprintf(stderr, "[kqr] admm %3d pcg %3d eta_p %.2e eta_d %.2e eta_c %.2e gap %.2e\n", it + 1, ps.iters,
+              k.eta_p, k.eta_d, k.eta_c, k.eta_gap);
+    if (!std::isfinite(k.err)) fail(KQR_ENUMERIC, "non-finite residual in Phase I");
+    if (k.err <= o_.admm_tol) { ++it; break; }
+  }
+  info.admm_iters = it;
+  sigma_ = sigma;
+  eta_d_prev_ = k.eta_d;
+  last_ = k;
+  KQR_CHECK_HIP(hipStreamSynchronize(st_));
+  info.t_admm = now_s() - t0;
+}
+
+// Algorithm 3 on phi_k for the current (beta, z, sigma).
+void Solver::ssn(double stop, kqr_info& info) {
+  const int64_t n = n_;
+  const double sigma = sigma_, c1 = lam_ * sigma;
+  for (int t = 0; t < o_.ssn_max_iter; ++t) {
+    const double sa = sum_of(alpha_.as<double>());
+    ssn_grad(n, alpha_.as<double>(), Ka_.as<double>(), y_, z_.as<double>(), beta_, sigma, sa, tau_, lam_,
+             grad_.as<double>(), S_.as<uint8_t>(), ws_, red_.as<double>(), st_);
+    const double gn = std::sqrt(read_scalar(red_.as<double>(), st_));
+    if (!std::isfinite(gn)) fail(KQR_ENUMERIC, "non-finite gradient in SSN");
+    if (gn <= stop) break;
+    const double eps_t = std::max(o_.tau1 * std::min(o_.tau2, gn), o_.eps_floor);
+    ssn_system(n, S_.as<uint8_t>(), grad_.as<double>(), lam_, sigma, eps_t, L_.as<double>(), b_.as<double>(), st_);
+    if (P_ && !P_->build(L_.as<double>(), c1, st_)) fail(KQR_ENUMERIC, "Newton preconditioner core not positive definite");
+    const double tol = lam_ * std::min(o_.etabar, std::pow(gn, 1.0 + o_.iota));
+    PcgStats ps = pcg_.solve(c1, L_.as<double>(), P_.get(), b_.as<double>(), d_.as<double>(), Kd_.as<double>(), true, tol,
+                      o_.pcg_max_iter, true, st_);
+    info.pcg_iters += ps.iters;
+    // Armijo backtracking, kLsTrials step lengths per pass
+    const double s0 = sa + beta_ / sigma;
+    double cstep = 0.0;
+    double c0 = 1.0;
+    int tried = 0;
+    while (tried < o_.ls_max) {
+      double s[5 + kLsTrials];
+      line_search_sums(n, alpha_.as<double>(), z_.as<double>(), d_.as<double>(), Ka_.as<double>(), Kd_.as<double>(),
+                       y_, grad_.as<double>(), sigma, tau_, c0, o_.ls_shrink, ws_, red_.as<double>(), st_);
+      read_scalars(red_.as<double>(), 5 + kLsTrials, s, st_);
+      const double dKa = s[0], dKd = s[1], yd = s[2], ed = s[3], gd = s[4];
+      double cj = c0;
+      bool ok = false;
+      for (int j = 0; j < kLsTrials && tried < o_.ls_max; ++j, ++tried) {
+        const double delta = cj * dKa / lam_ + 0.5 * cj * cj * dKd / lam_ - cj * yd +
+                             0.5 * sigma * ((s0 + cj * ed) * (s0 + cj * ed) - s0 * s0) + 0.5 * sigma * s[5 + j];
+        if (delta <= o_.armijo * cj * gd) { ok = true; break; }
+        cj *= o_.ls_shrink;
+        ++info.line_search_steps;
+      }
+      if (ok) { cstep = cj; break; }
+      c0 = cj;
+    }
+    if (cstep == 0.0) cstep = c0;  // backtracking cap reached: take the last (tiny) step
+    axpy2(n, cstep, d_.as<double>(), alpha_.as<double>(), Kd_.as<double>(), Ka_.as<double>(), st_);
+    ++info.newton_iters;
+  }
+}
+
+void Solver::phase2(kqr_info& info) {
+  const double t0 = now_s();
+  const double stop = o_.ssn_rel * o_.tol * (1.0 + ynorm_);
+  Kkt k = last_;
+  int it = 0;
+  bool done = false;
+  for (it = 0; it < o_.alm_max_iter; ++it) {
+    op_.apply_exact(alpha_.as<double>(), Ka_.as<double>(), st_);  // reset drift of the tracked K alpha
+    ssn(stop, info);
+    const double sa = sum_of(alpha_.as<double>());
+    const double beta_new = beta_ + sigma_ * sa;
+    k = update_and_kkt(beta_new, sigma_, 1.0, true);
+    beta_ = beta_new;
+    if (o_.verbose)
+      fprintf(stderr, "[kqr] alm %3d sigma %.1e eta_p %.2e eta_d %.2e eta_c %.2e gap %.2e\n", it + 1, sigma_,
+              k.eta_p, k.eta_d, k.eta_c, k.eta_gap);
+    if (!std::isfinite(k.err)) fail(KQR_ENUMERIC, "non-finite residual in Phase II");
+    if (k.err <= o_.tol) {
+      // confirm with an exact K alpha (tracked products drift by rounding)
+      op_.apply_exact(alpha_.as<double>(), Ka_.as<double>(), st_);
+      k = update_and_kkt(beta_, sigma_, 1.0, false);
+      if (k.err <= o_.tol) { ++it; done = true; break; }
+    }
+    if (k.eta_d > o_.sigma_stall * eta_d_prev_) sigma_ = std::min(o_.sigma_factor * sigma_, o_.sigma_max);
+    eta_d_prev_ = k.eta_d;
+  }
+  info.alm_iters = it;
+  converged_ = done;
+  last_ = k;
+  KQR_CHECK_HIP(hipStreamSynchronize(st_));
+  info.t_alm = now_s() - t0;
+}
+
+void Solver::finish(kqr_info& info) {
+  // final residuals with the exact operator
+  op_.apply_exact(alpha_.as<double>(), Ka_.as<double>(), st_);
+  Kkt k = update_and_kkt(beta_, sigma_, 1.0, false);
+  last_ = k;
+  info.eta_p = k.eta_p;
+  info.eta_d = k.eta_d;
+  info.eta_c = k.eta_c;
+  info.eta_kkt = k.eta_kkt;
+  info.eta_gap = k.eta_gap;
+  info.obj_p = k.obj_p;
+  info.obj_d = k.obj_d;
+  info.sigma = sigma_;
+  count_interior(n_, alpha_.as<double>(), tau_, ws_, red_.as<double>(), st_);
+  info.n_interior = int64_t(read_scalar(red_.as<double>(), st_));
+  converged_ = converged_ && k.err <= o_.tol;
+}
+
+}  // namespace kqr

@@ -1,0 +1,82 @@
+// Solver-level declarations: vector kernels, the Woodbury preconditioner and
+// randomly pivoted Cholesky.
+#pragma once
+
+#include "kqr_internal.h"
+
+namespace kqr {
+
+constexpr int kKktSums = 9;    // sums produced by multiplier_kkt
+constexpr int kLsTrials = 24;  // step lengths evaluated per line-search pass
+constexpr int kMaxPartialQ = 5 + kLsTrials;
+
+// Scratch shared by the reduction kernels of one solve.
+struct Workspace {
+  DevBuf part_buf;  // kRedBlocks * kMaxPartialQ doubles
+  double* partials = nullptr;
+  Workspace() : part_buf(size_t(kRedBlocks) * kMaxPartialQ * sizeof(double)) {
+    partials = part_buf.as<double>();
+  }
+};
+
+// ----------------------------------------------------------------- vector kernels (vec.hip)
+void vec_dots(int64_t n, const double* x, const double* y, Workspace& ws, double* out3, hipStream_t st);
+void pcg_init_r(int64_t n, const double* b, const double* x, const double* Kx, const double* L, double c,
+                const double* sc, int sum_x_slot, double* r, Workspace& ws, double* rr_out, hipStream_t st);
+void pcg_update_p(int64_t n, const double* zz, double* p, float* p32, const double* sc, int rz_slot,
+                  int rzn_slot, bool first, Workspace& ws, double* sump_out, hipStream_t st);
+void pcg_q(int64_t n, const double* Kp, const double* p, const double* L, double c, const double* sc,
+           int sump_slot, double* q, Workspace& ws, double* pq_out, hipStream_t st);
+void pcg_xr(int64_t n, const double* p, const double* q, const double* Kp, double* x, double* r, double* Kx,
+            const double* sc, int rz_slot, int pq_slot, Workspace& ws, double* rr_out, hipStream_t st);
+void admm_rhs(int64_t n, const double* y, const double* z, const double* v, double beta, double sigma,
+              double lam, double* b, hipStream_t st);
+void multiplier_kkt(int64_t n, const double* alpha, const double* Ka, const double* y, double* z, double* v,
+                    double beta_new, double sigma, double step, double tau, double lam, bool update,
+                    Workspace& ws, double* out, hipStream_t st);
+void ssn_grad(int64_t n, const double* alpha, const double* Ka, const double* y, const double* z, double beta,
+              double sigma, double sum_alpha, double tau, double lam, double* grad, uint8_t* S, Workspace& ws,
+              double* gg_out, hipStream_t st);
+void ssn_system(int64_t n, const uint8_t* S, const double* grad, double lam, double sigma, double eps_t,
+                double* L, double* rhs, hipStream_t st);
+void line_search_sums(int64_t n, const double* alpha, const double* z, const double* d, const double* Ka,
+                      const double* Kd, const double* y, const double* grad, double sigma, double tau,
+                      double c0, double shrink, Workspace& ws, double* out, hipStream_t st);
+void axpy2(int64_t n, double c, const double* d, double* x, const double* Kd, double* Kx, hipStream_t st);
+void count_nonfinite(int64_t n, const double* x, Workspace& ws, double* out, hipStream_t st);
+void count_interior(int64_t n, const double* a, double tau, Workspace& ws, double* out, hipStream_t st);
+void fill(int64_t n, double val, double* x, hipStream_t st);
+void copy(int64_t n, const double* src, double* dst, hipStream_t st);
+
+// ----------------------------------------------------------------- Woodbury (woodbury.hip)
+// P = F F^T + c 1 1^T + diag(L), applied by Lemma 1 with the (r+1)^2 core in FP64.
+class Woodbury {
+ public:
+  Woodbury(const float* F, int64_t n, int64_t r, int64_t ldf);
+  // Forms C = diag(I, 1/c) + U^T L^{-1} U and its Cholesky factor.  Returns
+  // false when a pivot is not positive (the factor is then unusable).
+  bool build(const double* L, double c, hipStream_t st);
+  // out = P^{-1} w.  When dot_with != nullptr also writes dot_with . out to *dot_out (device).
+  void apply(const double* w, double* out, const double* dot_with, double* dot_out, Workspace& ws,
+             hipStream_t st);
+  int64_t rank() const { return r_; }
+
+ private:
+  const float* F_;
+  int64_t n_, r_, ldf_, R1_;
+  int64_t ldc_;
+  const double* L_ = nullptr;
+  double c_ = 1.0;
+  DevBuf C_, part_, g_, s_, flag_;
+  HostPinned hflag_;
+  int nsplit_ = 1;
+};
+
+// ----------------------------------------------------------------- RPCholesky (rpchol.hip)
+// Randomly pivoted Cholesky on K (materialised or from X).  Writes F (n x ldf
+// FP32) and returns the pivots; stops early when sum(d) <= 1e-14 tr(K).
+std::vector<int64_t> rpcholesky(const KMat& km, const float* X, const float* sqn, int64_t n, int p,
+                                KernelSpec ks, int64_t rank, const double* uniforms, float* F, int64_t ldf,
+                                hipStream_t st);
+
+}  // namespace kqr

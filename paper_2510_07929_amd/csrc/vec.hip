@@ -1,0 +1,427 @@
+// Fused O(n) vector kernels of the solver, all with deterministic reductions:
+// every kernel that produces sums writes one partial per block (fixed grid,
+// fixed per-thread order) and `reduce_finalize` adds the partials in a fixed
+// order.  Runs are bitwise reproducible.
+#include "kqr_internal.h"
+#include "solver.h"
+
+namespace kqr {
+
+// ----------------------------------------------------------------- block reduction
+template <int NQ>
+__device__ __forceinline__ void block_partials(double (&v)[NQ], double* __restrict__ partials) {
+  __shared__ double sh[NQ][kRedThreads / 64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    double s = v[q];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off);
+    if (lane == 0) sh[q][wave] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x < NQ) {
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < kRedThreads / 64; ++w) s += sh[threadIdx.x][w];
+    partials[blockIdx.x * NQ + threadIdx.x] = s;
+  }
+}
+
+__global__ __launch_bounds__(256) void finalize_kernel(const double* __restrict__ partials,
+                                                       int nblocks, int nq, double* __restrict__ out) {
+  __shared__ double sh[4];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int q = 0; q < nq; ++q) {
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += 256) s += partials[b * nq + q];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off);
+    if (lane == 0) sh[wave] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) out[q] = ((sh[0] + sh[1]) + sh[2]) + sh[3];
+    __syncthreads();
+  }
+}
+
+void reduce_finalize(const double* partials, int nblocks, int nq, double* out, hipStream_t st) {
+  finalize_kernel<<<1, 256, 0, st>>>(partials, nblocks, nq, out);
+  KQR_LAUNCH_CHECK();
+}
+
+#define KQR_GRID_STRIDE(i, n) \
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < (n); i += (int64_t)gridDim.x * blockDim.x)
+
+static inline dim3 red_grid() { return dim3(kRedBlocks); }
+
+// ----------------------------------------------------------------- generic sums
+// out partials: [sum x, sum x*y (if y), sum x*x]
+__global__ __launch_bounds__(256) void dots_kernel(int64_t n, const double* __restrict__ x,
+                                                   const double* __restrict__ y, double* partials) {
+  double v[3] = {0.0, 0.0, 0.0};
+  KQR_GRID_STRIDE(i, n) {
+    const double a = x[i];
+    v[0] += a;
+    if (y) v[1] = fma(a, y[i], v[1]);
+    v[2] = fma(a, a, v[2]);
+  }
+  block_partials<3>(v, partials);
+}
+
+void vec_dots(int64_t n, const double* x, const double* y, Workspace& ws, double* out3, hipStream_t st) {
+  dots_kernel<<<red_grid(), 256, 0, st>>>(n, x, y, ws.partials);
+  KQR_LAUNCH_CHECK();
+  reduce_finalize(ws.partials, kRedBlocks, 3, out3, st);
+}
+
+// ----------------------------------------------------------------- PCG
+// r = b - (Kx + c*sum(x) + L x) (or r = b when x = 0); Kx zeroed when x = 0.
+__global__ __launch_bounds__(256) void pcg_init_r_kernel(int64_t n, const double* __restrict__ b,
+                                                         const double* __restrict__ x,
+                                                         const double* __restrict__ Kx,
+                                                         const double* __restrict__ L, double c,
+                                                         const double* __restrict__ sc, int sum_x_slot,
+                                                         double* __restrict__ r, double* partials) {
+  const double cs = (x && sum_x_slot >= 0) ? c * sc[sum_x_slot] : 0.0;
+  double v[1] = {0.0};
+  KQR_GRID_STRIDE(i, n) {
+    double ri = b[i];
+    if (x) ri -= Kx[i] + cs + L[i] * x[i];
+    r[i] = ri;
+    v[0] = fma(ri, ri, v[0]);
+  }
+  block_partials<1>(v, partials);
+}
+
+void pcg_init_r(int64_t n, const double* b, const double* x, const double* Kx, const double* L,
+                double c, const double* sc, int sum_x_slot, double* r, Workspace& ws, double* rr_out,
+                hipStream_t st) {
+  pcg_init_r_kernel<<<red_grid(), 256, 0, st>>>(n, b, x, Kx, L, c, sc, sum_x_slot, r, ws.partials);
+  KQR_LAUNCH_CHECK();
+  reduce_finalize(ws.partials, kRedBlocks, 1, rr_out, st);
+}
+
+// p = zz (+ beta p with beta = sc[rzn]/sc[rz]); p32 = float(p); partial [sum p, r.zz].
+__global__ __launch_bounds__(256) void pcg_p_kernel(int64_t n, const double* __restrict__ zz,
+                                                    const double* __restrict__ r, double* __restrict__ p,
+                                                    float* __restrict__ p32, const double* __restrict__ sc,
+                                                    int rz_slot, int rzn_slot, int first,
+                                                    double* partials) {
+  const double beta = first ? 0.0 : sc[rzn_slot] / sc[rz_slot];
+  double v[1] = {0.0};
+  KQR_GRID_STRIDE(i, n) {
+    const double pi = first ? zz[i] : fma(beta, p[i], zz[i]);
+    p[i] = pi;
+    if (p32) p32[i] = float(pi);
+    v[0] += pi;
+  }
+  (void)r;
+  block_partials<1>(v, partials);
+}
+
+void pcg_update_p(int64_t n, const double* zz, double* p, float* p32, const double* sc, int rz_slot,
+                  int rzn_slot, bool first, Workspace& ws, double* sump_out, hipStream_t st) {
+  pcg_p_kernel<<<red_grid(), 256, 0, st>>>(n, zz, nullptr, p, p32, sc, rz_slot, rzn_slot, first ? 1 : 0,
+                                           ws.partials);
+  KQR_LAUNCH_CHECK();
+  reduce_finalize(ws.partials, kRedBlocks, 1, sump_out, st);
+}
+
+// q = Kp + c*sum(p) + L p ; partial p.q
+__global__ __launch_bounds__(256) void pcg_q_kernel(int64_t n, const double* __restrict__ Kp,
+                                                    const double* __restrict__ p,
+                                                    const double* __restrict__ L, double c,
+                                                    const double* __restrict__ sc, int sump_slot,
+                                                    double* __restrict__ q, double* partials) {
+  const double cs = c * sc[sump_slot];
+  double v[1] = {0.0};
+  KQR_GRID_STRIDE(i, n) {
+    const double pi = p[i];
+    const double qi = Kp[i] + cs + L[i] * pi;
+    q[i] = qi;
+    v[0] = fma(pi, qi, v[0]);
+  }
+  block_partials<1>(v, partials);
+}
+
+void pcg_q(int64_t n, const double* Kp, const double* p, const double* L, double c, const double* sc,
+           int sump_slot, double* q, Workspace& ws, double* pq_out, hipStream_t st) {
+  pcg_q_kernel<<<red_grid(), 256, 0, st>>>(n, Kp, p, L, c, sc, sump_slot, q, ws.partials);
+  KQR_LAUNCH_CHECK();
+  reduce_finalize(ws.partials, kRedBlocks, 1, pq_out, st);
+}
+
+// a = sc[rz]/sc[pq]; x += a p; r -= a q; Kx += a Kp (if Kx); partial r.r
+__global__ __launch_bounds__(256) void pcg_xr_kernel(int64_t n, const double* __restrict__ p,
+                                                     const double* __restrict__ q,
+                                                     const double* __restrict__ Kp, double* __restrict__ x,
+                                                     double* __restrict__ r, double* __restrict__ Kx,
+                                                     const double* __restrict__ sc, int rz_slot,
+                                                     int pq_slot, double* partials) {
+  const double a = sc[rz_slot] / sc[pq_slot];
+  double v[1] = {0.0};
+  KQR_GRID_STRIDE(i, n) {
+    x[i] = fma(a, p[i], x[i]);
+    const double ri = fma(-a, q[i], r[i]);
+    r[i] = ri;
+    if (Kx) Kx[i] = fma(a, Kp[i], Kx[i]);
+    v[0] = fma(ri, ri, v[0]);
+  }
+  block_partials<1>(v, partials);
+}
+
+void pcg_xr(int64_t n, const double* p, const double* q, const double* Kp, double* x, double* r,
+            double* Kx, const double* sc, int rz_slot, int pq_slot, Workspace& ws, double* rr_out,
+            hipStream_t st) {
+  pcg_xr_kernel<<<red_grid(), 256, 0, st>>>(n, p, q, Kp, x, r, Kx, sc, rz_slot, pq_slot, ws.partials);
+  KQR_LAUNCH_CHECK();
+  reduce_finalize(ws.partials, kRedBlocks, 1, rr_out, st);
+}
+
+// ----------------------------------------------------------------- ADMM / ALM
+// b = lambda (y - beta - z + sigma v)
+__global__ __launch_bounds__(256) void admm_rhs_kernel(int64_t n, const double* __restrict__ y,
+                                                       const double* __restrict__ z,
+                                                       const double* __restrict__ v, double beta,
+                                                       double sigma, double lam, double* __restrict__ b) {
+  KQR_GRID_STRIDE(i, n) b[i] = lam * (y[i] - beta - z[i] + sigma * v[i]);
+}
+
+void admm_rhs(int64_t n, const double* y, const double* z, const double* v, double beta, double sigma,
+              double lam, double* b, hipStream_t st) {
+  admm_rhs_kernel<<<red_grid(), 256, 0, st>>>(n, y, z, v, beta, sigma, lam, b);
+  KQR_LAUNCH_CHECK();
+}
+
+// v = Pi_B(alpha + z/sigma); z += step*sigma*(alpha - v); then the KKT sums of
+// Section 4 at (alpha, v, beta_new, z):
+//   [0] ||z - y + beta 1 + K alpha/lam||^2  [1] ||alpha - v||^2  [2] ||alpha||^2
+//   [3] ||v - Pi_B(z + v)||^2  [4] ||v||^2  [5] rho_tau(z)  [6] alpha.Kalpha
+//   [7] y.alpha  [8] 1.alpha
+__global__ __launch_bounds__(256) void multiplier_kkt_kernel(
+    int64_t n, const double* __restrict__ alpha, const double* __restrict__ Ka,
+    const double* __restrict__ y, double* __restrict__ z, double* __restrict__ v, double beta_new,
+    double sigma, double step, double tau, double lam, int update, double* partials) {
+  double s[kKktSums];
+#pragma unroll
+  for (int q = 0; q < kKktSums; ++q) s[q] = 0.0;
+  const double lo = tau - 1.0, hi = tau;
+  const double inv_lam = 1.0 / lam;
+  KQR_GRID_STRIDE(i, n) {
+    const double a = alpha[i];
+    double zi = z[i];
+    double vi;
+    if (update) {
+      vi = fmin(fmax(a + zi / sigma, lo), hi);
+      zi = fma(step * sigma, a - vi, zi);
+      z[i] = zi;
+      v[i] = vi;
+    } else {
+      vi = v[i];
+    }
+    const double kai = Ka[i];
+    const double rp = zi - y[i] + beta_new + kai * inv_lam;
+    s[0] = fma(rp, rp, s[0]);
+    const double dv = a - vi;
+    s[1] = fma(dv, dv, s[1]);
+    s[2] = fma(a, a, s[2]);
+    const double pc = vi - fmin(fmax(zi + vi, lo), hi);
+    s[3] = fma(pc, pc, s[3]);
+    s[4] = fma(vi, vi, s[4]);
+    s[5] += zi > 0.0 ? tau * zi : -(1.0 - tau) * zi;
+    s[6] = fma(a, kai, s[6]);
+    s[7] = fma(y[i], a, s[7]);
+    s[8] += a;
+  }
+  block_partials<kKktSums>(s, partials);
+}
+
+void multiplier_kkt(int64_t n, const double* alpha, const double* Ka, const double* y, double* z,
+                    double* v, double beta_new, double sigma, double step, double tau, double lam,
+                    bool update, Workspace& ws, double* out, hipStream_t st) {
+  multiplier_kkt_kernel<<<red_grid(), 256, 0, st>>>(n, alpha, Ka, y, z, v, beta_new, sigma, step, tau,
+                                                    lam, update ? 1 : 0, ws.partials);
+  KQR_LAUNCH_CHECK();
+  reduce_finalize(ws.partials, kRedBlocks, kKktSums, out, st);
+}
+
+// ----------------------------------------------------------------- SSN (Algorithm 3)
+// grad = Ka/lam - y + beta + sigma*sum(alpha) + sigma (w - Pi_B(w)),  w = alpha + z/sigma
+// S = 1 strictly inside (tau-1, tau); partials [||grad||^2]
+__global__ __launch_bounds__(256) void ssn_grad_kernel(int64_t n, const double* __restrict__ alpha,
+                                                       const double* __restrict__ Ka,
+                                                       const double* __restrict__ y,
+                                                       const double* __restrict__ z, double beta,
+                                                       double sigma, double sum_alpha, double tau,
+                                                       double lam, double* __restrict__ grad,
+                                                       uint8_t* __restrict__ S, double* partials) {
+  const double lo = tau - 1.0, hi = tau;
+  const double base = beta + sigma * sum_alpha;
+  const double inv_lam = 1.0 / lam;
+  double v[1] = {0.0};
+  KQR_GRID_STRIDE(i, n) {
+    const double w = alpha[i] + z[i] / sigma;
+    const double pw = fmin(fmax(w, lo), hi);
+    const double g = Ka[i] * inv_lam - y[i] + base + sigma * (w - pw);
+    grad[i] = g;
+    S[i] = (w > lo && w < hi) ? 1 : 0;
+    v[0] = fma(g, g, v[0]);
+  }
+  block_partials<1>(v, partials);
+}
+
+void ssn_grad(int64_t n, const double* alpha, const double* Ka, const double* y, const double* z,
+              double beta, double sigma, double sum_alpha, double tau, double lam, double* grad,
+              uint8_t* S, Workspace& ws, double* gg_out, hipStream_t st) {
+  ssn_grad_kernel<<<red_grid(), 256, 0, st>>>(n, alpha, Ka, y, z, beta, sigma, sum_alpha, tau, lam, grad,
+                                              S, ws.partials);
+  KQR_LAUNCH_CHECK();
+  reduce_finalize(ws.partials, kRedBlocks, 1, gg_out, st);
+}
+
+// L = lam sigma (1 - S) + lam eps_t ; rhs = -lam grad
+__global__ __launch_bounds__(256) void ssn_system_kernel(int64_t n, const uint8_t* __restrict__ S,
+                                                         const double* __restrict__ grad, double lam,
+                                                         double sigma, double eps_t,
+                                                         double* __restrict__ L, double* __restrict__ rhs) {
+  const double ls = lam * sigma, le = lam * eps_t;
+  KQR_GRID_STRIDE(i, n) {
+    L[i] = (S[i] ? 0.0 : ls) + le;
+    rhs[i] = -lam * grad[i];
+  }
+}
+
+void ssn_system(int64_t n, const uint8_t* S, const double* grad, double lam, double sigma, double eps_t,
+                double* L, double* rhs, hipStream_t st) {
+  ssn_system_kernel<<<red_grid(), 256, 0, st>>>(n, S, grad, lam, sigma, eps_t, L, rhs);
+  KQR_LAUNCH_CHECK();
+}
+
+// Line search sums for phi(alpha + c d) - phi(alpha) expanded from (2.2):
+//   [0] d.Ka  [1] d.Kd  [2] y.d  [3] 1.d  [4] grad.d
+//   [5 + j] sum_i dist^2(w_i + c_j d_i) - dist^2(w_i),  c_j = c0 shrink^j
+__global__ __launch_bounds__(256) void line_search_kernel(
+    int64_t n, const double* __restrict__ alpha, const double* __restrict__ z,
+    const double* __restrict__ d, const double* __restrict__ Ka, const double* __restrict__ Kd,
+    const double* __restrict__ y, const double* __restrict__ grad, double sigma, double tau,
+    double c0, double shrink, double* partials) {
+  double s[5 + kLsTrials];
+#pragma unroll
+  for (int q = 0; q < 5 + kLsTrials; ++q) s[q] = 0.0;
+  const double lo = tau - 1.0, hi = tau;
+  KQR_GRID_STRIDE(i, n) {
+    const double di = d[i];
+    s[0] = fma(di, Ka[i], s[0]);
+    s[1] = fma(di, Kd[i], s[1]);
+    s[2] = fma(di, y[i], s[2]);
+    s[3] += di;
+    s[4] = fma(di, grad[i], s[4]);
+    const double w = alpha[i] + z[i] / sigma;
+    const double r0 = w - fmin(fmax(w, lo), hi);
+    double c = c0;
+#pragma unroll
+    for (int j = 0; j < kLsTrials; ++j) {
+      const double wc = fma(c, di, w);
+      const double r1 = wc - fmin(fmax(wc, lo), hi);
+      s[5 + j] += (r1 - r0) * (r1 + r0);
+      c *= shrink;
+    }
+  }
+  block_partials<5 + kLsTrials>(s, partials);
+}
+
+void line_search_sums(int64_t n, const double* alpha, const double* z, const double* d, const double* Ka,
+                      const double* Kd, const double* y, const double* grad, double sigma, double tau,
+                      double c0, double shrink, Workspace& ws, double* out, hipStream_t st) {
+  line_search_kernel<<<red_grid(), 256, 0, st>>>(n, alpha, z, d, Ka, Kd, y, grad, sigma, tau, c0, shrink,
+                                                 ws.partials);
+  KQR_LAUNCH_CHECK();
+  reduce_finalize(ws.partials, kRedBlocks, 5 + kLsTrials, out, st);
+}
+
+// x += c d ; Kx += c Kd
+__global__ __launch_bounds__(256) void axpy2_kernel(int64_t n, double c, const double* __restrict__ d,
+                                                    double* __restrict__ x, const double* __restrict__ Kd,
+                                                    double* __restrict__ Kx) {
+  KQR_GRID_STRIDE(i, n) {
+    x[i] = fma(c, d[i], x[i]);
+    if (Kx) Kx[i] = fma(c, Kd[i], Kx[i]);
+  }
+}
+
+void axpy2(int64_t n, double c, const double* d, double* x, const double* Kd, double* Kx, hipStream_t st) {
+  axpy2_kernel<<<red_grid(), 256, 0, st>>>(n, c, d, x, Kd, Kx);
+  KQR_LAUNCH_CHECK();
+}
+
+// Non-finite check: partial [count of non-finite entries]
+__global__ __launch_bounds__(256) void nonfinite_kernel(int64_t n, const double* __restrict__ x,
+                                                        double* partials) {
+  double v[1] = {0.0};
+  KQR_GRID_STRIDE(i, n) {
+    if (!isfinite(x[i])) v[0] += 1.0;
+  }
+  block_partials<1>(v, partials);
+}
+
+void count_nonfinite(int64_t n, const double* x, Workspace& ws, double* out, hipStream_t st) {
+  nonfinite_kernel<<<red_grid(), 256, 0, st>>>(n, x, ws.partials);
+  KQR_LAUNCH_CHECK();
+  reduce_finalize(ws.partials, kRedBlocks, 1, out, st);
+}
+
+__global__ void fill_kernel(int64_t n, double val, double* __restrict__ x) {
+  KQR_GRID_STRIDE(i, n) x[i] = val;
+}
+
+void fill(int64_t n, double val, double* x, hipStream_t st) {
+  fill_kernel<<<red_grid(), 256, 0, st>>>(n, val, x);
+  KQR_LAUNCH_CHECK();
+}
+
+__global__ void copy_kernel(int64_t n, const double* __restrict__ s, double* __restrict__ d) {
+  KQR_GRID_STRIDE(i, n) d[i] = s[i];
+}
+
+void copy(int64_t n, const double* src, double* dst, hipStream_t st) {
+  copy_kernel<<<red_grid(), 256, 0, st>>>(n, src, dst);
+  KQR_LAUNCH_CHECK();
+}
+
+// count of tau-1 < alpha_i < tau : partial
+__global__ __launch_bounds__(256) void interior_kernel(int64_t n, const double* __restrict__ a, double tau,
+                                                       double* partials) {
+  double v[1] = {0.0};
+  KQR_GRID_STRIDE(i, n) {
+    if (a[i] > tau - 1.0 && a[i] < tau) v[0] += 1.0;
+  }
+  block_partials<1>(v, partials);
+}
+
+void count_interior(int64_t n, const double* a, double tau, Workspace& ws, double* out, hipStream_t st) {
+  interior_kernel<<<red_grid(), 256, 0, st>>>(n, a, tau, ws.partials);
+  KQR_LAUNCH_CHECK();
+  reduce_finalize(ws.partials, kRedBlocks, 1, out, st);
+}
+
+}  // namespace kqr
+
+namespace kqr {
+// dst = src ; partial src . dst
+__global__ __launch_bounds__(256) void copy_dot_kernel(int64_t n, const double* __restrict__ s,
+                                                       double* __restrict__ d, double* partials) {
+  double v[1] = {0.0};
+  KQR_GRID_STRIDE(i, n) {
+    const double a = s[i];
+    d[i] = a;
+    v[0] = fma(a, a, v[0]);
+  }
+  block_partials<1>(v, partials);
+}
+
+void copy_dot(int64_t n, const double* src, double* dst, Workspace& ws, double* out, hipStream_t st) {
+  copy_dot_kernel<<<red_grid(), 256, 0, st>>>(n, src, dst, ws.partials);
+  KQR_LAUNCH_CHECK();
+  reduce_finalize(ws.partials, kRedBlocks, 1, out, st);
+}
+}  // namespace kqr

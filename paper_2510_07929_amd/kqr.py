@@ -1,0 +1,338 @@
+"""ctypes binding of libkqr (the C ABI declared in include/kqr.h).
+
+Argument marshalling only: every function takes torch tensors that already
+live on the GPU (or host arrays where the C ABI wants host memory), checks
+dtype / device / layout, and passes raw pointers and the current HIP stream
+to the library.  All arithmetic happens in the library's HIP kernels.  If
+the library has not been built, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+import threading
+
+import numpy as np
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libkqr.so")
+_lib_handle = None
+_lib_lock = threading.Lock()
+
+KQR_OK, KQR_NOT_CONVERGED = 0, 1
+KQR_EINVAL, KQR_ENOMEM, KQR_ENODEVICE, KQR_EHIP, KQR_ENUMERIC = -1, -2, -3, -4, -5
+KQR_RBF, KQR_LAPLACIAN = 0, 1
+KQR_FP32, KQR_BF16 = 0, 1
+KQR_KMODE_AUTO, KQR_KMODE_MATERIALIZE, KQR_KMODE_ON_THE_FLY = 0, 1, 2
+KQR_APPLY_FAST, KQR_APPLY_EXACT = 0, 1
+
+KERNELS = {"rbf": KQR_RBF, "laplacian": KQR_LAPLACIAN}
+KDTYPES = {"fp32": KQR_FP32, "bf16": KQR_BF16}
+
+
+class KqrOptions(C.Structure):
+    _fields_ = [
+        ("tol", C.c_double), ("admm_tol", C.c_double),
+        ("admm_max_iter", C.c_int), ("alm_max_iter", C.c_int),
+        ("admm_sigma", C.c_double), ("admm_step", C.c_double), ("admm_eps0", C.c_double),
+        ("etabar", C.c_double), ("iota", C.c_double), ("armijo", C.c_double),
+        ("ls_shrink", C.c_double), ("ls_max", C.c_int),
+        ("tau1", C.c_double), ("tau2", C.c_double), ("eps_floor", C.c_double),
+        ("ssn_max_iter", C.c_int), ("ssn_rel", C.c_double),
+        ("sigma_factor", C.c_double), ("sigma_stall", C.c_double), ("sigma_max", C.c_double),
+        ("rank", C.c_int), ("xi", C.c_double), ("pcg_max_iter", C.c_int),
+        ("k_dtype", C.c_int), ("kmode", C.c_int), ("refine", C.c_int),
+        ("pivot_uniforms", C.POINTER(C.c_double)), ("seed", C.c_uint64), ("verbose", C.c_int),
+        ("profile", C.c_int),
+    ]
+
+
+class KqrInfo(C.Structure):
+    _fields_ = [
+        ("eta_p", C.c_double), ("eta_d", C.c_double), ("eta_c", C.c_double),
+        ("eta_kkt", C.c_double), ("eta_gap", C.c_double),
+        ("obj_p", C.c_double), ("obj_d", C.c_double), ("sigma", C.c_double),
+        ("admm_iters", C.c_int), ("alm_iters", C.c_int), ("newton_iters", C.c_int),
+        ("line_search_steps", C.c_int), ("admm_pcg_iters", C.c_int), ("pcg_iters", C.c_int),
+        ("rank_used", C.c_int), ("refinements", C.c_int),
+        ("kapply_calls", C.c_int64), ("n_interior", C.c_int64),
+        ("t_kbuild", C.c_double), ("t_precond", C.c_double), ("t_admm", C.c_double),
+        ("t_alm", C.c_double), ("t_total", C.c_double),
+        ("kapply_fast_calls", C.c_int64), ("kapply_exact_calls", C.c_int64),
+        ("t_kapply_fast", C.c_double), ("t_kapply_exact", C.c_double),
+    ]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+_P = C.c_void_p
+_I64 = C.c_int64
+_SIGS = {
+    "kqr_default_options": (C.c_int, [C.POINTER(KqrOptions)]),
+    "kqr_status_string": (C.c_char_p, [C.c_int]),
+    "kqr_last_error": (C.c_char_p, []),
+    "kqr_device_count": (C.c_int, []),
+    "kqr_kernel_build": (C.c_int, [_P, _I64, _I64, C.c_int, C.c_double, C.c_int, _P, _I64, _P]),
+    "kqr_kernel_apply": (C.c_int, [_P, _I64, _I64, C.c_int, C.c_double, _P, C.c_int, _I64, _P, _I64, _I64,
+                                   _P, _I64, C.c_int, _P]),
+    "kqr_predict": (C.c_int, [_P, _I64, _I64, _P, C.c_double, C.c_double, C.c_int, C.c_double, _P, _I64, _P, _P]),
+    "kqr_rpcholesky": (C.c_int, [_P, _I64, _I64, C.c_int, C.c_double, _P, C.c_int, _I64, _I64, _P, _P, _I64,
+                                 _P, _P, _P]),
+    "kqr_woodbury_apply": (C.c_int, [_P, _I64, _I64, _I64, C.c_double, _P, _P, _P, _P]),
+    "kqr_pcg_solve": (C.c_int, [_P, _I64, _I64, C.c_int, C.c_double, _P, C.c_int, _I64, _P, _I64, _I64,
+                                C.c_double, _P, _P, C.c_double, C.c_int, _P, _P, _P, _P]),
+    "kqr_ssn_gradient": (C.c_int, [_I64, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double,
+                                   C.c_double, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
+    "kqr_fit": (C.c_int, [_P, _P, _I64, _I64, C.c_double, C.c_double, C.c_int, C.c_double,
+                          C.POINTER(KqrOptions), _P, _P, C.POINTER(KqrInfo), _P]),
+}
+
+
+class KqrError(RuntimeError):
+    def __init__(self, status: int, func: str, msg: str):
+        super().__init__(f"{func}: status {status} ({status_string(status)}): {msg}")
+        self.status = status
+
+
+def lib_path() -> str:
+    return _LIB_PATH
+
+
+def lib():
+    """The loaded library (raises if it has not been built)."""
+    global _lib_handle
+    with _lib_lock:
+        if _lib_handle is None:
+            if not os.path.exists(_LIB_PATH):
+                raise RuntimeError(
+                    f"libkqr.so not found at {_LIB_PATH}; build it with "
+                    "`python -m paper_2510_07929_amd.build` (no CPU fallback exists)")
+            h = C.CDLL(_LIB_PATH)
+            for name, (res, args) in _SIGS.items():
+                fn = getattr(h, name)
+                fn.restype = res
+                fn.argtypes = args
+            _lib_handle = h
+    return _lib_handle
+
+
+def status_string(s: int) -> str:
+    return lib().kqr_status_string(int(s)).decode()
+
+
+def last_error() -> str:
+    return lib().kqr_last_error().decode()
+
+
+def _check(status: int, func: str, allow=(KQR_OK,)):
+    if status not in allow:
+        raise KqrError(status, func, last_error())
+    return status
+
+
+# ----------------------------------------------------------------------- marshalling helpers
+def _torch():
+    import torch
+
+    return torch
+
+
+def _stream(stream=None):
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _dev(t, dtype, name, ndim=None):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if ndim is not None and t.dim() != ndim:
+        raise ValueError(f"{name} must have {ndim} dims")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return C.c_void_p(t.data_ptr())
+
+
+def _kernel_id(kernel):
+    return KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
+
+
+def _kdtype_id(kd):
+    return KDTYPES[kd] if isinstance(kd, str) else int(kd)
+
+
+def padded_ld(n: int) -> int:
+    """Leading dimension used for materialised K (multiple of 64 elements)."""
+    return (int(n) + 63) // 64 * 64
+
+
+# ----------------------------------------------------------------------- entry points
+def kqr_default_options(**overrides) -> KqrOptions:
+    o = KqrOptions()
+    _check(lib().kqr_default_options(C.byref(o)), "kqr_default_options")
+    for k, v in overrides.items():
+        if not hasattr(o, k):
+            raise AttributeError(f"kqr_options has no field {k!r}")
+        setattr(o, k, v)
+    return o
+
+
+def kqr_device_count() -> int:
+    return int(lib().kqr_device_count())
+
+
+def kqr_kernel_build(X, kernel, gamma, k_dtype="fp32", K=None, stream=None):
+    """Materialise K (n x ld, ld = padded_ld(n)) on the GPU; returns K."""
+    torch = _torch()
+    n, p = X.shape
+    ld = padded_ld(n) if K is None else K.shape[1]
+    kd = _kdtype_id(k_dtype)
+    tdt = torch.float32 if kd == KQR_FP32 else torch.bfloat16
+    if K is None:
+        K = torch.empty((n, ld), dtype=tdt, device=X.device)
+    _check(lib().kqr_kernel_build(_dev(X, torch.float32, "X", 2), n, p, _kernel_id(kernel), float(gamma), kd,
+                                  _dev(K, tdt, "K", 2), ld, _stream(stream)), "kqr_kernel_build")
+    return K
+
+
+def kqr_kernel_apply(V, X=None, kernel="rbf", gamma=1.0, K=None, mode=KQR_APPLY_FAST, U=None, stream=None):
+    """U = K V for V (n,) or (n, m) float64 on the GPU; K materialised or None (on the fly)."""
+    torch = _torch()
+    vec = V.dim() == 1
+    V2 = V.reshape(-1, 1) if vec else V
+    n, m = V2.shape
+    if U is None:
+        U = torch.empty((n, m), dtype=torch.float64, device=V.device)
+    U2 = U.reshape(n, m)
+    if K is not None:
+        kd = KQR_FP32 if K.dtype == torch.float32 else KQR_BF16
+        kptr, ld = _dev(K, K.dtype, "K", 2), K.shape[1]
+    else:
+        kd, kptr, ld = KQR_FP32, None, 0
+    xptr = _dev(X, torch.float32, "X", 2) if X is not None else None
+    p = X.shape[1] if X is not None else 0
+    _check(lib().kqr_kernel_apply(xptr, n, p, _kernel_id(kernel), float(gamma), kptr, kd, ld,
+                                  _dev(V2, torch.float64, "V"), m, m, _dev(U2, torch.float64, "U"), m,
+                                  int(mode), _stream(stream)), "kqr_kernel_apply")
+    return U2.reshape(-1) if vec else U2
+
+
+def kqr_predict(Xtrain, alpha, beta, lam, kernel, gamma, Xnew, stream=None):
+    torch = _torch()
+    n, p = Xtrain.shape
+    m = Xnew.shape[0]
+    f = torch.empty(m, dtype=torch.float64, device=Xnew.device)
+    _check(lib().kqr_predict(_dev(Xtrain, torch.float32, "Xtrain", 2), n, p, _dev(alpha, torch.float64, "alpha", 1),
+                             float(beta), float(lam), _kernel_id(kernel), float(gamma),
+                             _dev(Xnew, torch.float32, "Xnew", 2), m, _dev(f, torch.float64, "f", 1),
+                             _stream(stream)), "kqr_predict")
+    return f
+
+
+def kqr_rpcholesky(rank, uniforms, X=None, kernel="rbf", gamma=1.0, K=None, n=None, stream=None):
+    """Returns (F (n x ldf float32 GPU tensor, first rank_out columns valid), pivots (np.int64), rank_out)."""
+    torch = _torch()
+    if n is None:
+        n = X.shape[0] if X is not None else K.shape[0]
+    rank = int(rank)
+    ldf = (min(rank, n) + 3) // 4 * 4
+    dev = X.device if X is not None else K.device
+    F = torch.empty((n, ldf), dtype=torch.float32, device=dev)
+    u = np.ascontiguousarray(np.asarray(uniforms, dtype=np.float64))
+    if u.size < min(rank, n):
+        raise ValueError("need at least rank uniforms")
+    piv = np.zeros(rank, dtype=np.int64)
+    rout = C.c_int64(0)
+    if K is not None:
+        kd = KQR_FP32 if K.dtype == torch.float32 else KQR_BF16
+        kptr, ld = _dev(K, K.dtype, "K", 2), K.shape[1]
+    else:
+        kd, kptr, ld = KQR_FP32, None, 0
+    xptr = _dev(X, torch.float32, "X", 2) if X is not None else None
+    p = X.shape[1] if X is not None else 0
+    _check(lib().kqr_rpcholesky(xptr, n, p, _kernel_id(kernel), float(gamma), kptr, kd, ld, rank,
+                                u.ctypes.data_as(C.c_void_p), _dev(F, torch.float32, "F", 2), ldf,
+                                piv.ctypes.data_as(C.c_void_p), C.byref(rout), _stream(stream)), "kqr_rpcholesky")
+    r = int(rout.value)
+    return F, piv[:r].copy(), r
+
+
+def kqr_woodbury_apply(F, r, c, Ldiag, w, stream=None):
+    torch = _torch()
+    n = Ldiag.shape[0]
+    out = torch.empty_like(w)
+    fptr = _dev(F, torch.float32, "F", 2) if r > 0 else None
+    ldf = F.shape[1] if r > 0 else 0
+    _check(lib().kqr_woodbury_apply(fptr, n, int(r), ldf, float(c), _dev(Ldiag, torch.float64, "Ldiag", 1),
+                                    _dev(w, torch.float64, "w", 1), _dev(out, torch.float64, "out", 1),
+                                    _stream(stream)), "kqr_woodbury_apply")
+    return out
+
+
+def kqr_pcg_solve(X, kernel, gamma, c, Ldiag, b, tol, maxit, K=None, F=None, r=0, x0=None, stream=None):
+    torch = _torch()
+    n, p = X.shape
+    x = torch.zeros_like(b) if x0 is None else x0.clone()
+    it = C.c_int(0)
+    res = C.c_double(0.0)
+    if K is not None:
+        kd = KQR_FP32 if K.dtype == torch.float32 else KQR_BF16
+        kptr, ld = _dev(K, K.dtype, "K", 2), K.shape[1]
+    else:
+        kd, kptr, ld = KQR_FP32, None, 0
+    fptr = _dev(F, torch.float32, "F", 2) if r > 0 else None
+    ldf = F.shape[1] if r > 0 else 0
+    _check(lib().kqr_pcg_solve(_dev(X, torch.float32, "X", 2), n, p, _kernel_id(kernel), float(gamma), kptr, kd, ld,
+                               fptr, int(r), ldf, float(c), _dev(Ldiag, torch.float64, "Ldiag", 1),
+                               _dev(b, torch.float64, "b", 1), float(tol), int(maxit), _dev(x, torch.float64, "x", 1),
+                               C.byref(it), C.byref(res), _stream(stream)), "kqr_pcg_solve")
+    return x, int(it.value), float(res.value)
+
+
+def kqr_ssn_gradient(tau, lam, beta, sigma, alpha, Kalpha, y, z, tau1=0.1, tau2=0.1, eps_floor=1e-12, stream=None):
+    torch = _torch()
+    n = alpha.shape[0]
+    grad = torch.empty_like(alpha)
+    L = torch.empty_like(alpha)
+    rhs = torch.empty_like(alpha)
+    S = torch.empty(n, dtype=torch.uint8, device=alpha.device)
+    gn, et = C.c_double(0.0), C.c_double(0.0)
+    f64 = torch.float64
+    _check(lib().kqr_ssn_gradient(n, float(tau), float(lam), float(beta), float(sigma), float(tau1), float(tau2),
+                                  float(eps_floor), _dev(alpha, f64, "alpha", 1), _dev(Kalpha, f64, "Kalpha", 1),
+                                  _dev(y, f64, "y", 1), _dev(z, f64, "z", 1), _dev(grad, f64, "grad", 1),
+                                  _dev(S, torch.uint8, "S", 1), _dev(L, f64, "Ldiag", 1), _dev(rhs, f64, "rhs", 1),
+                                  C.byref(gn), C.byref(et), _stream(stream)), "kqr_ssn_gradient")
+    return dict(grad=grad, S=S, Ldiag=L, rhs=rhs, gnorm=float(gn.value), eps_t=float(et.value))
+
+
+def kqr_fit(X, y, tau, lam, kernel="rbf", gamma=1.0, options: KqrOptions | None = None, uniforms=None,
+            stream=None, **overrides):
+    """PALM-KQR fit on the GPU.  Returns (alpha (GPU float64), beta, info dict, status)."""
+    torch = _torch()
+    n, p = X.shape
+    o = options if options is not None else kqr_default_options()
+    for k, v in overrides.items():
+        setattr(o, k, v)
+    keep = None
+    if uniforms is not None:
+        keep = np.ascontiguousarray(np.asarray(uniforms, dtype=np.float64))
+        o.pivot_uniforms = keep.ctypes.data_as(C.POINTER(C.c_double))
+    alpha = torch.empty(n, dtype=torch.float64, device=X.device)
+    beta = C.c_double(0.0)
+    info = KqrInfo()
+    st = lib().kqr_fit(_dev(X, torch.float32, "X", 2), _dev(y, torch.float64, "y", 1), n, p, float(tau), float(lam),
+                       _kernel_id(kernel), float(gamma), C.byref(o), _dev(alpha, torch.float64, "alpha", 1),
+                       C.byref(beta), C.byref(info), _stream(stream))
+    _check(st, "kqr_fit", allow=(KQR_OK, KQR_NOT_CONVERGED))
+    del keep
+    return alpha, float(beta.value), info.as_dict(), st
+
+
+def default_rank(n: int) -> int:
+    return min(int(math.ceil(math.sqrt(n))), n, 1023)
