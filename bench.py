@@ -43,6 +43,7 @@ def parse():
     ap.add_argument("--kdtype", default=None, choices=[None, "fp32", "bf16"])
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the CPU oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="skip the K-apply shape sweep before the warm-up")
     ap.add_argument("--traffic", default=None, help="JSON file with measured HBM bytes per K-apply launch")
     return ap.parse_args()
 
@@ -106,6 +107,16 @@ def main():
     def one_fit():
         return kqr.kqr_fit(X, y, prob.tau, prob.lam, prob.kernel, prob.gamma, uniforms=uni, **opts)
 
+    tuned = {}
+    if not args.no_tune:
+        # untimed: pick the K-apply tile shapes on this problem's own K
+        K = kqr.kqr_kernel_build(X, prob.kernel, prob.gamma, kdtype)
+        for mode, name in ((kqr.KQR_APPLY_FAST, "fast"), (kqr.KQR_APPLY_EXACT, "exact")):
+            rep = kqr.kqr_autotune_apply(K, mode, reps=3)
+            tuned[name] = rep["best"]
+        del K
+        torch.cuda.empty_cache()
+
     for _ in range(args.warmup):
         one_fit()
     torch.cuda.synchronize()
@@ -152,7 +163,7 @@ def main():
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "kernel": "kapply_rows_kernel (fast, materialised %s K)" % kdtype,
             "avg_launch_us": round(avg * 1e6, 2), "launches": int(nfast),
-            "bytes_per_launch": kbytes,
+            "bytes_per_launch": kbytes, "tile_shapes": tuned or "default",
         },
         "fit": {
             "status": st, "eta_kkt": last["eta_kkt"], "eta_gap": last["eta_gap"], "obj_p": last["obj_p"],

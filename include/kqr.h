@@ -179,6 +179,30 @@ int kqr_rpcholesky(const float* X, int64_t n, int64_t p, int kernel, double gamm
                    const double* uniforms, float* F, int64_t ldf, int64_t* pivots,
                    int64_t* rank_out, void* stream);
 
+/* kqr_adaptive_rank: the rank heuristic of Section 3.  Given the first r0
+ * columns of an RPCholesky factor F0 (device, n x ldf FP32, ldf multiple of 4),
+ * returns in *rank the smallest r with lambda_r(F0^T F0) <= xi lambda_1 (r0 if
+ * none), eigenvalues in decreasing order, and lambda_1 in *lambda1 (may be
+ * NULL).  F0^T F0 is formed in FP64 and reduced to tridiagonal form on the
+ * device; eigenvalues are located by Sturm bisection.  r0 <= 1023, 0 < xi < 1. */
+int kqr_adaptive_rank(const float* F0, int64_t n, int64_t r0, int64_t ldf, double xi, int64_t* rank,
+                      double* lambda1, void* stream);
+
+/* kqr_autotune_apply: times the materialised K-apply on the caller's K
+ * (device, as in kqr_kernel_build) for every supported tile shape -- rows per
+ * wave {2,4,8} x 16-byte loads in flight per row {1,2,4} x column segments
+ * {1,2,4,8,16} -- with `reps` timed launches each, and keeps the fastest shape
+ * for (k_dtype, mode, size class of n) for the rest of the process.  Writes a
+ * JSON report (every shape's average launch time and the choice) into
+ * `report` (host, `cap` bytes, NUL-terminated; may be NULL).  Synchronises. */
+int kqr_autotune_apply(const void* K, int k_dtype, int64_t n, int64_t ldk, int mode, int reps, char* report,
+                       int64_t cap, void* stream);
+
+/* kqr_set_apply_shape: installs a K-apply tile shape (e.g. one recorded by
+ * kqr_autotune_apply) for (k_dtype, mode, size class of n).  rows in {2,4,8},
+ * unroll in {1,2,4}, 1 <= segs <= 64; otherwise KQR_EINVAL. */
+int kqr_set_apply_shape(int k_dtype, int mode, int64_t n, int rows, int unroll, int segs);
+
 /* kqr_woodbury_apply: out = P^{-1} w for P = F F^T + c 1 1^T + diag(Ldiag), by
  * Lemma 1 with U = [F 1] and the (r+1)x(r+1) core C = diag(I, 1/c) + U^T L^{-1} U
  * formed and Cholesky-factored in FP64 on the device.

@@ -300,12 +300,107 @@ int kqr_rpcholesky(const float* X, int64_t n, int64_t p, int kernel, double gamm
   });
 }
 
+int kqr_adaptive_rank(const float* F0, int64_t n, int64_t r0, int64_t ldf, double xi, int64_t* rank,
+                      double* lambda1, void* stream) {
+  return guarded([&] {
+    KQR_REQUIRE(F0 && rank, "F0 and rank must be non-null");
+    KQR_REQUIRE(n >= 1 && r0 >= 1 && r0 <= 1023, "need n >= 1 and 1 <= r0 <= 1023");
+    KQR_REQUIRE(ldf >= r0 && ldf % 4 == 0, "ldf must be >= r0 and a multiple of 4");
+    KQR_REQUIRE(xi > 0.0 && xi < 1.0, "need 0 < xi < 1");
+    ensure_device();
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    double l1 = 0.0;
+    *rank = r0 <= 1 ? r0 : adaptive_rank(F0, n, r0, ldf, xi, st, &l1);
+    if (lambda1) *lambda1 = l1;
+  });
+}
+
+int kqr_autotune_apply(const void* K, int k_dtype, int64_t n, int64_t ldk, int mode, int reps, char* report,
+                       int64_t cap, void* stream) {
+  return guarded([&] {
+    KQR_REQUIRE(K != nullptr, "K must be non-null");
+    KQR_REQUIRE(n >= 1 && reps >= 1, "need n >= 1 and reps >= 1");
+    KQR_REQUIRE(mode == KQR_APPLY_FAST || mode == KQR_APPLY_EXACT, "invalid mode");
+    check_kmat(K, k_dtype, ldk, n);
+    ensure_device();
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const KMat km{K, k_dtype, ldk};
+    DevBuf v64(size_t(n) * sizeof(double)), v32(size_t(n) * sizeof(float)), u(size_t(n) * sizeof(double));
+    fill(n, 1.0 / double(n), v64.as<double>(), st);
+    to_f32(v64.as<double>(), n, 1, 1, v32.as<float>(), 1, st);
+    hipEvent_t e0, e1;
+    KQR_CHECK_HIP(hipEventCreate(&e0));
+    KQR_CHECK_HIP(hipEventCreate(&e1));
+    std::string rep = "{\"n\": " + std::to_string(n) + ", \"k_dtype\": " + std::to_string(k_dtype) +
+                      ", \"mode\": " + std::to_string(mode) + ", \"shapes\": [";
+    ApplyShape best;
+    double best_us = 1e300;
+    bool first = true;
+    const int rows_c[] = {2, 4, 8}, unroll_c[] = {1, 2, 4}, segs_c[] = {1, 2, 4, 8, 16};
+    try {
+      for (int rw : rows_c)
+        for (int un : unroll_c)
+          for (int sg : segs_c) {
+            ApplyShape s;
+            s.rows = rw;
+            s.unroll = un;
+            s.segs = sg;
+            const bool ex = mode == KQR_APPLY_EXACT;
+            kapply_dense(km, n, n, v32.as<float>(), v64.as<double>(), u.as<double>(), 1, ex, st, &s);  // warm-up
+            KQR_CHECK_HIP(hipEventRecord(e0, st));
+            for (int k = 0; k < reps; ++k)
+              kapply_dense(km, n, n, v32.as<float>(), v64.as<double>(), u.as<double>(), 1, ex, st, &s);
+            KQR_CHECK_HIP(hipEventRecord(e1, st));
+            KQR_CHECK_HIP(hipEventSynchronize(e1));
+            float ms = 0.f;
+            KQR_CHECK_HIP(hipEventElapsedTime(&ms, e0, e1));
+            const double us = 1e3 * ms / reps;
+            char buf[128];
+            snprintf(buf, sizeof(buf), "%s{\"rows\": %d, \"unroll\": %d, \"segs\": %d, \"us\": %.2f}", first ? "" : ", ",
+                     rw, un, sg, us);
+            first = false;
+            rep += buf;
+            if (us < best_us) { best_us = us; best = s; }
+          }
+    } catch (...) {
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      throw;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    set_apply_shape(k_dtype, mode == KQR_APPLY_EXACT, n, best);
+    char buf[160];
+    snprintf(buf, sizeof(buf), "], \"best\": {\"rows\": %d, \"unroll\": %d, \"segs\": %d, \"us\": %.2f}}", best.rows,
+             best.unroll, best.segs, best_us);
+    rep += buf;
+    if (report && cap > 0) {
+      const size_t nb = std::min<size_t>(size_t(cap) - 1, rep.size());
+      memcpy(report, rep.data(), nb);
+      report[nb] = '\0';
+    }
+  });
+}
+
+int kqr_set_apply_shape(int k_dtype, int mode, int64_t n, int rows, int unroll, int segs) {
+  return guarded([&] {
+    KQR_REQUIRE(k_dtype == KQR_FP32 || k_dtype == KQR_BF16, "invalid k_dtype");
+    KQR_REQUIRE(mode == KQR_APPLY_FAST || mode == KQR_APPLY_EXACT, "invalid mode");
+    ApplyShape s;
+    s.rows = rows;
+    s.unroll = unroll;
+    s.segs = segs;
+    KQR_REQUIRE(apply_shape_supported(s), "unsupported shape (rows in {2,4,8}, unroll in {1,2,4}, 1 <= segs <= 64)");
+    set_apply_shape(k_dtype, mode == KQR_APPLY_EXACT, n, s);
+  });
+}
+
 int kqr_woodbury_apply(const float* F, int64_t n, int64_t r, int64_t ldf, double c, const double* Ldiag,
                        const double* w, double* out, void* stream) {
   return guarded([&] {
     KQR_REQUIRE(Ldiag && w && out, "pointers must be non-null");
     KQR_REQUIRE(n >= 1 && r >= 0 && r <= 1023, "need n >= 1 and 0 <= r <= 1023");
-    KQR_REQUIRE(r == 0 || (F && ldf >= r), "F must be non-null with ldf >= r");
+    KQR_REQUIRE(r == 0 || (F && ldf >= r && ldf % 4 == 0), "F must be non-null with ldf >= r, ldf a multiple of 4");
     KQR_REQUIRE(std::isfinite(c) && c > 0.0, "c must be positive");
     ensure_device();
     hipStream_t st = static_cast<hipStream_t>(stream);
@@ -323,7 +418,7 @@ int kqr_pcg_solve(const float* X, int64_t n, int64_t p, int kernel, double gamma
   return guarded([&] {
     KQR_REQUIRE(Ldiag && b && x && iters && resnorm, "pointers must be non-null");
     KQR_REQUIRE(n >= 1 && r >= 0 && r <= 1023 && maxit >= 0, "need n >= 1, 0 <= r <= 1023, maxit >= 0");
-    KQR_REQUIRE(r == 0 || (F && ldf >= r), "F must be non-null with ldf >= r");
+    KQR_REQUIRE(r == 0 || (F && ldf >= r && ldf % 4 == 0), "F must be non-null with ldf >= r, ldf a multiple of 4");
     KQR_REQUIRE(std::isfinite(c) && c >= 0.0 && tol >= 0.0, "need c >= 0 and tol >= 0");
     KQR_REQUIRE(X != nullptr && p >= 1 && p <= 64, "X must be non-null with 1 <= p <= 64");
     check_kernel(kernel, gamma);
@@ -444,6 +539,9 @@ int kqr_fit(const float* X, const double* y, int64_t n, int64_t p, double tau, d
       std::vector<int64_t> piv = rpcholesky(op.kmat(), X, op.sqn(), n, int(p), KernelSpec{kernel, gamma}, rank, uni,
                                             Fbuf.as<float>(), ldf, st);
       rank_used = int64_t(piv.size());
+      // Section 3 heuristic: keep the first r columns (the first r steps of
+      // RPCholesky are RPCholesky(K, r) on the same draws)
+      if (o.rank == 0 && rank_used > 1) rank_used = adaptive_rank(Fbuf.as<float>(), n, rank_used, ldf, o.xi, st, nullptr);
     }
     inf.rank_used = int(rank_used);
     inf.t_precond = now_s() - t_p0;

@@ -4,6 +4,7 @@
 // K_ij = exp(-gamma d_ij) with d the squared Euclidean distance (RBF) or the
 // L1 distance (Laplacian) (Section 1).  exp is evaluated as exp2 of
 // -gamma log2(e) d with the device exp2f.
+#include "kernel_entry.h"
 #include "kqr_internal.h"
 
 #include <algorithm>
@@ -24,8 +25,6 @@ __device__ __forceinline__ uint16_t f32_to_bf16(float f) {
   return uint16_t(u >> 16);
 }
 
-constexpr float kLog2e = 1.4426950408889634f;
-
 // ================================================================= row norms
 __global__ void sqnorm_kernel(const float* __restrict__ X, int64_t n, int p, float* __restrict__ q) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -40,22 +39,6 @@ void row_sqnorms(const float* X, int64_t n, int p, float* sqn, hipStream_t st) {
   if (n <= 0) return;
   sqnorm_kernel<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st>>>(X, n, p, sqn);
   KQR_LAUNCH_CHECK();
-}
-
-// Distance of row (LDS copy xi, norm qi) to a column held in registers.
-template <int PMAX, bool LAP>
-__device__ __forceinline__ float pair_dist(const float* xi, float qi, const float* xj, float qj) {
-  if (LAP) {
-    float d = 0.f;
-#pragma unroll
-    for (int k = 0; k < PMAX; ++k) d += fabsf(xi[k] - xj[k]);
-    return d;
-  } else {
-    float g = 0.f;
-#pragma unroll
-    for (int k = 0; k < PMAX; ++k) g = fmaf(xi[k], xj[k], g);
-    return fmaxf(qi + qj - 2.f * g, 0.f);
-  }
 }
 
 // ================================================================= K build
@@ -154,12 +137,16 @@ __device__ __forceinline__ float kelem(const u32x4& w, int e) {
   }
 }
 
+// Columns can be split into gridDim.y segments (smaller work items balance the
+// tail of the launch); each segment then writes a partial sum per row and
+// kapply_seg_reduce adds the segments in order.
 template <int ROWS, int UNROLL, bool EXACT, bool BF16>
 __global__ __launch_bounds__(256) void kapply_rows_kernel(const void* __restrict__ Kp, int64_t ldk,
                                                           int64_t nrows, int64_t ncols,
                                                           const float* __restrict__ v32,
                                                           const double* __restrict__ v64,
-                                                          double* __restrict__ u, int64_t ldu) {
+                                                          double* __restrict__ u, int64_t ldu,
+                                                          int64_t seg_chunks, double* __restrict__ part) {
   constexpr int VEC = BF16 ? 8 : 4;
   constexpr int ESZ = BF16 ? 2 : 4;
   const int lane = threadIdx.x & 63;
@@ -171,12 +158,15 @@ __global__ __launch_bounds__(256) void kapply_rows_kernel(const void* __restrict
     const int64_t rr = (row0 + r < nrows) ? row0 + r : nrows - 1;
     rp[r] = reinterpret_cast<const u32x4*>(static_cast<const char*>(Kp) + rr * ldk * ESZ);
   }
-  const int64_t nchunk = ncols / VEC;
+  const int64_t nchunk_all = ncols / VEC;
+  const int64_t cbeg = int64_t(blockIdx.y) * seg_chunks;
+  const int64_t nchunk = min(nchunk_all, cbeg + seg_chunks);
+  const bool last_seg = blockIdx.y == gridDim.y - 1;
   double acc[ROWS];
 #pragma unroll
   for (int r = 0; r < ROWS; ++r) acc[r] = 0.0;
 
-  int64_t c = lane;
+  int64_t c = cbeg + lane;
   for (; c + 64 * (UNROLL - 1) < nchunk; c += 64 * UNROLL) {
     u32x4 kk[ROWS][UNROLL];
 #pragma unroll
@@ -235,9 +225,9 @@ __global__ __launch_bounds__(256) void kapply_rows_kernel(const void* __restrict
       for (int r = 0; r < ROWS; ++r) acc[r] = fma(double(kelem<BF16>(kk[r], e)), ve, acc[r]);
     }
   }
-  // trailing columns that do not fill a 16-byte chunk
-  const int64_t col = nchunk * VEC + lane;
-  if (col < ncols) {
+  // trailing columns that do not fill a 16-byte chunk (last segment)
+  const int64_t col = nchunk_all * VEC + lane;
+  if (last_seg && col < ncols) {
     const double ve = EXACT ? v64[col] : double(v32[col]);
 #pragma unroll
     for (int r = 0; r < ROWS; ++r) {
@@ -251,48 +241,96 @@ __global__ __launch_bounds__(256) void kapply_rows_kernel(const void* __restrict
   for (int r = 0; r < ROWS; ++r)
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) acc[r] += __shfl_xor(acc[r], off);
+  if (part) {
 #pragma unroll
-  for (int r = 0; r < ROWS; ++r)
-    if (lane == r && row0 + r < nrows) u[(row0 + r) * ldu] = acc[r];
+    for (int r = 0; r < ROWS; ++r)
+      if (lane == r && row0 + r < nrows) part[int64_t(blockIdx.y) * nrows + row0 + r] = acc[r];
+  } else {
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r)
+      if (lane == r && row0 + r < nrows) u[(row0 + r) * ldu] = acc[r];
+  }
 }
 
+__global__ void kapply_seg_reduce(const double* __restrict__ part, int nseg, int64_t nrows,
+                                  double* __restrict__ u, int64_t ldu) {
+  const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (i >= nrows) return;
+  double s = 0.0;
+  for (int k = 0; k < nseg; ++k) s += part[int64_t(k) * nrows + i];
+  u[i * ldu] = s;
+}
+
+// ----------------------------------------------------------------- shapes
 namespace {
 std::mutex g_shape_mu;
-ApplyShape g_shape[2][2] = {{{8, 2}, {8, 2}}, {{8, 2}, {8, 2}}};  // [dtype][exact]
-bool g_shape_set[2][2] = {};
+// tuned shapes per [dtype][exact][size bucket]
+ApplyShape g_shape[2][2][3];
+bool g_shape_set[2][2][3] = {};
+
+int size_bucket(int64_t n) { return n < 8192 ? 0 : (n < 65536 ? 1 : 2); }
 }  // namespace
 
 ApplyShape default_apply_shape(int dtype, int exact, int64_t n) {
   std::lock_guard<std::mutex> lk(g_shape_mu);
-  const int d = dtype == KQR_BF16, e = exact != 0;
-  if (g_shape_set[d][e]) return g_shape[d][e];
-  (void)n;
-  return ApplyShape{8, 2};
+  const int d = dtype == KQR_BF16, e = exact != 0, b = size_bucket(n);
+  if (g_shape_set[d][e][b]) return g_shape[d][e][b];
+  ApplyShape s;
+  s.rows = 8;
+  s.unroll = 2;
+  s.segs = n >= 16384 ? 4 : 1;  // keeps work items ~n/4 columns long on large matrices
+  return s;
 }
 
-void set_apply_shape(int dtype, int exact, ApplyShape s) {
+void set_apply_shape(int dtype, int exact, int64_t n, ApplyShape s) {
   std::lock_guard<std::mutex> lk(g_shape_mu);
-  const int d = dtype == KQR_BF16, e = exact != 0;
-  g_shape[d][e] = s;
-  g_shape_set[d][e] = true;
+  const int d = dtype == KQR_BF16, e = exact != 0, b = size_bucket(n);
+  g_shape[d][e][b] = s;
+  g_shape_set[d][e][b] = true;
+}
+
+bool apply_shape_supported(const ApplyShape& s) {
+  const int key = s.rows * 100 + s.unroll;
+  const bool ok = key == 201 || key == 202 || key == 204 || key == 401 || key == 402 || key == 404 ||
+                  key == 801 || key == 802 || key == 804;
+  return ok && s.segs >= 1 && s.segs <= 64;
 }
 
 template <int ROWS, int UNROLL>
 static void kapply_rows_launch(const KMat& km, int64_t nrows, int64_t ncols, const float* v32,
-                               const double* v64, double* u, int64_t ldu, bool exact,
+                               const double* v64, double* u, int64_t ldu, bool exact, int segs,
                                hipStream_t st) {
+  const int vec = km.dtype == KQR_BF16 ? 8 : 4;
+  const int64_t nchunk = ncols / vec;
+  segs = int(std::max<int64_t>(1, std::min<int64_t>(segs, nchunk / 64)));
+  int64_t seg_chunks = (nchunk + segs - 1) / segs;
+  seg_chunks = (seg_chunks + 63) / 64 * 64;
+  if (seg_chunks == 0) seg_chunks = 64;
+  segs = int(std::max<int64_t>(1, (nchunk + seg_chunks - 1) / seg_chunks));
   const int64_t waves = (nrows + ROWS - 1) / ROWS;
-  const dim3 grid((unsigned)((waves + 3) / 4));
+  const dim3 grid((unsigned)((waves + 3) / 4), (unsigned)segs);
+  double* part = nullptr;
+  if (segs > 1)
+    KQR_CHECK_HIP(hipMallocAsync(reinterpret_cast<void**>(&part), size_t(segs) * nrows * sizeof(double), st));
   const bool bf = km.dtype == KQR_BF16;
   if (exact && bf)
-    kapply_rows_kernel<ROWS, UNROLL, true, true><<<grid, 256, 0, st>>>(km.K, km.ld, nrows, ncols, v32, v64, u, ldu);
+    kapply_rows_kernel<ROWS, UNROLL, true, true><<<grid, 256, 0, st>>>(km.K, km.ld, nrows, ncols, v32, v64, u, ldu,
+                                                                        seg_chunks, part);
   else if (exact)
-    kapply_rows_kernel<ROWS, UNROLL, true, false><<<grid, 256, 0, st>>>(km.K, km.ld, nrows, ncols, v32, v64, u, ldu);
+    kapply_rows_kernel<ROWS, UNROLL, true, false><<<grid, 256, 0, st>>>(km.K, km.ld, nrows, ncols, v32, v64, u, ldu,
+                                                                         seg_chunks, part);
   else if (bf)
-    kapply_rows_kernel<ROWS, UNROLL, false, true><<<grid, 256, 0, st>>>(km.K, km.ld, nrows, ncols, v32, v64, u, ldu);
+    kapply_rows_kernel<ROWS, UNROLL, false, true><<<grid, 256, 0, st>>>(km.K, km.ld, nrows, ncols, v32, v64, u, ldu,
+                                                                         seg_chunks, part);
   else
-    kapply_rows_kernel<ROWS, UNROLL, false, false><<<grid, 256, 0, st>>>(km.K, km.ld, nrows, ncols, v32, v64, u, ldu);
+    kapply_rows_kernel<ROWS, UNROLL, false, false><<<grid, 256, 0, st>>>(km.K, km.ld, nrows, ncols, v32, v64, u, ldu,
+                                                                          seg_chunks, part);
   KQR_LAUNCH_CHECK();
+  if (part) {
+    kapply_seg_reduce<<<dim3((unsigned)((nrows + 255) / 256)), 256, 0, st>>>(part, segs, nrows, u, ldu);
+    KQR_LAUNCH_CHECK();
+    KQR_CHECK_HIP(hipFreeAsync(part, st));
+  }
 }
 
 void kapply_dense(const KMat& km, int64_t nrows, int64_t ncols, const float* v32, const double* v64,
@@ -301,14 +339,15 @@ void kapply_dense(const KMat& km, int64_t nrows, int64_t ncols, const float* v32
   const ApplyShape s = shape ? *shape : default_apply_shape(km.dtype, exact, nrows);
   const int key = s.rows * 100 + s.unroll;
   switch (key) {
-    case 401: kapply_rows_launch<4, 1>(km, nrows, ncols, v32, v64, u, ldu, exact, st); break;
-    case 402: kapply_rows_launch<4, 2>(km, nrows, ncols, v32, v64, u, ldu, exact, st); break;
-    case 404: kapply_rows_launch<4, 4>(km, nrows, ncols, v32, v64, u, ldu, exact, st); break;
-    case 801: kapply_rows_launch<8, 1>(km, nrows, ncols, v32, v64, u, ldu, exact, st); break;
-    case 802: kapply_rows_launch<8, 2>(km, nrows, ncols, v32, v64, u, ldu, exact, st); break;
-    case 804: kapply_rows_launch<8, 4>(km, nrows, ncols, v32, v64, u, ldu, exact, st); break;
-    case 1601: kapply_rows_launch<16, 1>(km, nrows, ncols, v32, v64, u, ldu, exact, st); break;
-    case 1602: kapply_rows_launch<16, 2>(km, nrows, ncols, v32, v64, u, ldu, exact, st); break;
+    case 201: kapply_rows_launch<2, 1>(km, nrows, ncols, v32, v64, u, ldu, exact, s.segs, st); break;
+    case 202: kapply_rows_launch<2, 2>(km, nrows, ncols, v32, v64, u, ldu, exact, s.segs, st); break;
+    case 204: kapply_rows_launch<2, 4>(km, nrows, ncols, v32, v64, u, ldu, exact, s.segs, st); break;
+    case 401: kapply_rows_launch<4, 1>(km, nrows, ncols, v32, v64, u, ldu, exact, s.segs, st); break;
+    case 402: kapply_rows_launch<4, 2>(km, nrows, ncols, v32, v64, u, ldu, exact, s.segs, st); break;
+    case 404: kapply_rows_launch<4, 4>(km, nrows, ncols, v32, v64, u, ldu, exact, s.segs, st); break;
+    case 801: kapply_rows_launch<8, 1>(km, nrows, ncols, v32, v64, u, ldu, exact, s.segs, st); break;
+    case 802: kapply_rows_launch<8, 2>(km, nrows, ncols, v32, v64, u, ldu, exact, s.segs, st); break;
+    case 804: kapply_rows_launch<8, 4>(km, nrows, ncols, v32, v64, u, ldu, exact, s.segs, st); break;
     default: fail(KQR_EINVAL, "unsupported K-apply shape rows=%d unroll=%d", s.rows, s.unroll);
   }
 }

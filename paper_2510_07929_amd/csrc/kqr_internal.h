@@ -77,13 +77,16 @@ struct KMat {
   int64_t ld = 0;
 };
 
-// Tile shapes of the materialised K-apply (rows per wave, 16-byte chunks per lane per step).
+// Tile shape of the materialised K-apply: rows per wave, 16-byte chunks per
+// lane per step, column segments per row.
 struct ApplyShape {
   int rows = 8;
   int unroll = 2;
+  int segs = 1;
 };
 ApplyShape default_apply_shape(int dtype, int exact, int64_t n);
-void set_apply_shape(int dtype, int exact, ApplyShape s);  // autotuner override
+void set_apply_shape(int dtype, int exact, int64_t n, ApplyShape s);  // autotuner override
+bool apply_shape_supported(const ApplyShape& s);
 
 // K build: K[i, j] for i < n, j < ldk (j >= n written as 0).
 void kbuild(const float* X, const float* sqn, int64_t n, int p, KernelSpec ks, int dtype, void* K,

@@ -226,7 +226,8 @@ void Solver::phase1(kqr_info& info) {
   const int64_t n = n_;
   const double sigma = o_.admm_sigma, step = o_.admm_step, c = lam_ * sigma;
   fill(n, c, L_.as<double>(), st_);
-  if (P_ && !P_->build(L_.as<double>(), c, st_)) fail(KQR_ENUMERIC, "ADMM preconditioner core not positive definite");
+  if (P_ && !P_->build_scaled_identity(L_.as<double>(), c, c, st_))
+    fail(KQR_ENUMERIC, "ADMM preconditioner core not positive definite");
   fill(n, 0.0, alpha_.as<double>(), st_);
   fill(n, 0.0, v_.as<double>(), st_);
   fill(n, 0.0, z_.as<double>(), st_);
@@ -278,7 +279,9 @@ void Solver::ssn(double stop, kqr_info& info) {
     if (gn <= stop) break;
     const double eps_t = std::max(o_.tau1 * std::min(o_.tau2, gn), o_.eps_floor);
     ssn_system(n, S_.as<uint8_t>(), grad_.as<double>(), lam_, sigma, eps_t, L_.as<double>(), b_.as<double>(), st_);
-    if (P_ && !P_->build(L_.as<double>(), c1, st_)) fail(KQR_ENUMERIC, "Newton preconditioner core not positive definite");
+    if (P_ && !P_->build_two_level(L_.as<double>(), S_.as<uint8_t>(), lam_ * eps_t, lam_ * sigma + lam_ * eps_t, c1,
+                                   st_))
+      fail(KQR_ENUMERIC, "Newton preconditioner core not positive definite");
     const double tol = lam_ * std::min(o_.etabar, std::pow(gn, 1.0 + o_.iota));
     PcgStats ps = pcg_.solve(c1, L_.as<double>(), P_.get(), b_.as<double>(), d_.as<double>(), Kd_.as<double>(), true, tol,
                       o_.pcg_max_iter, true, st_);

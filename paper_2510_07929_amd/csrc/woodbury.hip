@@ -1,8 +1,19 @@
 // Preconditioner (3.2) applied through Lemma 1 (Sherman-Morrison-Woodbury):
 //   P = F F^T + c 1 1^T + L,  U = [F 1],  C = diag(I_r, 1/c) + U^T L^{-1} U,
 //   P^{-1} w = L^{-1} w - L^{-1} U C^{-1} U^T L^{-1} w.
-// The (r+1) x (r+1) core is formed (split-n SYRK with FP64 products of the
-// FP32 factor), Cholesky-factored and solved in FP64 on the device.
+//
+// Device-side, all FP64:
+//  * the core C is formed by a split-n SYRK of the FP32 factor (FP64
+//    products).  In the Newton systems (3.1) L takes two values,
+//    l_in = lambda eps_t on the interior set E and l_out = lambda sigma +
+//    lambda eps_t elsewhere, so U^T L^{-1} U = G_all / l_out +
+//    (1/l_in - 1/l_out) U_E^T U_E with G_all = U^T U formed once per fit; a
+//    Newton step then only sums over the |E| interior rows.
+//  * C = Lc Lc^T by a blocked Cholesky; W = Lc^{-1} is formed explicitly, so
+//    an application needs two triangular mat-vecs (many workgroups) instead
+//    of sequential substitutions, and s = W^T (W t) stays a symmetric
+//    positive definite map for any nonsingular W.
+//  * U s uses the streamed mat-vec of the K-apply with F as the matrix.
 #include "vec.h"
 
 #include <algorithm>
@@ -11,15 +22,16 @@
 namespace kqr {
 
 namespace {
-constexpr int kT = 64;        // core tile edge
+constexpr int kT = 64;        // SYRK / update tile edge
 constexpr int kSubRows = 32;  // rows staged per LDS step of the SYRK
-constexpr int kGtBlocks = 256;
+constexpr int kCb = 32;       // Cholesky block
+constexpr int kIb = 64;       // inverse block
+constexpr int kGtBlocks = 512;
+constexpr int kGtStage = 256;
 }  // namespace
 
-// U(i, a) = F(i, a) for a < r, 1 for a == r, 0 beyond; 0 for i >= n.
-__device__ __forceinline__ double u_at(const float* __restrict__ F, int64_t ldf, int64_t n, int r,
-                                       int64_t i, int a) {
-  if (i >= n) return 0.0;
+// U(i, a) = F(i, a) for a < r, 1 for a == r, 0 beyond.
+__device__ __forceinline__ double u_at(const float* __restrict__ F, int64_t ldf, int r, int64_t i, int a) {
   if (a < r) return double(F[i * ldf + a]);
   return a == r ? 1.0 : 0.0;
 }
@@ -32,10 +44,12 @@ __device__ __forceinline__ void tile_coords(int t, int& ta, int& tb) {
   tb = t - a * (a + 1) / 2;
 }
 
-// part[s][tile][64x64] = sum over rows of chunk s of (U_ia / L_i) U_ib.
-__global__ __launch_bounds__(256) void syrk_kernel(const float* __restrict__ F, int64_t n, int r,
+// part[s][tile][64x64] = sum over rows of chunk s of w_i U_ia U_ib, where the
+// rows are idx[k] (or k itself when idx is null) and w_i = 1/L_i (or 1).
+__global__ __launch_bounds__(256) void syrk_kernel(const float* __restrict__ F, int64_t nrows, int r,
                                                    int64_t ldf, const double* __restrict__ L,
-                                                   int ntile, int64_t chunk, double* __restrict__ part) {
+                                                   const int* __restrict__ idx, int ntile, int64_t chunk,
+                                                   double* __restrict__ part) {
   __shared__ double A[kSubRows][kT + 1];
   __shared__ double B[kSubRows][kT + 1];
   int ta, tb;
@@ -47,16 +61,21 @@ __global__ __launch_bounds__(256) void syrk_kernel(const float* __restrict__ F, 
   for (int p = 0; p < 4; ++p)
 #pragma unroll
     for (int q = 0; q < 4; ++q) acc[p][q] = 0.0;
-  const int64_t i0 = int64_t(s) * chunk;
-  const int64_t i1 = min(n, i0 + chunk);
-  for (int64_t ib = i0; ib < i1; ib += kSubRows) {
+  const int64_t k0 = int64_t(s) * chunk;
+  const int64_t k1 = min(nrows, k0 + chunk);
+  for (int64_t kb = k0; kb < k1; kb += kSubRows) {
     for (int e = threadIdx.x; e < kSubRows * kT; e += 256) {
       const int ii = e / kT, k = e % kT;
-      const int64_t i = ib + ii;
-      const bool ok = i < i1;
-      const double w = ok ? 1.0 / L[i] : 0.0;
-      A[ii][k] = ok ? u_at(F, ldf, n, r, i, ta * kT + k) * w : 0.0;
-      B[ii][k] = ok ? u_at(F, ldf, n, r, i, tb * kT + k) : 0.0;
+      const int64_t kk = kb + ii;
+      double av = 0.0, bv = 0.0;
+      if (kk < k1) {
+        const int64_t i = idx ? int64_t(idx[kk]) : kk;
+        const double w = L ? 1.0 / L[i] : 1.0;
+        av = u_at(F, ldf, r, i, ta * kT + k) * w;
+        bv = u_at(F, ldf, r, i, tb * kT + k);
+      }
+      A[ii][k] = av;
+      B[ii][k] = bv;
     }
     __syncthreads();
 #pragma unroll 4
@@ -80,33 +99,82 @@ __global__ __launch_bounds__(256) void syrk_kernel(const float* __restrict__ F, 
     for (int q = 0; q < 4; ++q) out[(ty * 4 + p) * kT + tx * 4 + q] = acc[p][q];
 }
 
-// C[a][b] (a >= b, inside R1) = identity/core diagonal + sum_s part[s][tile]
-__global__ __launch_bounds__(256) void syrk_reduce_kernel(const double* __restrict__ part, int nsplit,
-                                                          int ntile, int r, int R1, double c,
-                                                          double* __restrict__ C, int64_t ldc) {
+// C[a][b] (b <= a < R1) = diag(I_r, 1/c)[a][b] + alpha G[a][b] + beta sum_s part[s][tile]
+// G (optional) is a lower-triangular R1 x R1 matrix with leading dimension ldc.
+__global__ __launch_bounds__(256) void syrk_combine_kernel(const double* __restrict__ part, int nsplit, int ntile,
+                                                           int r, int R1, double diag_r, double diag_last,
+                                                           const double* __restrict__ G, double alpha, double beta,
+                                                           double* __restrict__ C, int64_t ldc) {
   int ta, tb;
   tile_coords(blockIdx.x, ta, tb);
   for (int e = threadIdx.x; e < kT * kT; e += 256) {
     const int a = ta * kT + e / kT, b = tb * kT + e % kT;
-    if (a >= R1 || b >= R1 || b > a) continue;
+    if (a >= R1 || b > a) continue;
     double s = 0.0;
     for (int k = 0; k < nsplit; ++k) s += part[(int64_t(k) * ntile + blockIdx.x) * (kT * kT) + e];
-    if (a == b) s += (a < r) ? 1.0 : 1.0 / c;
-    C[int64_t(a) * ldc + b] = s;
+    double v = beta * s;
+    if (G) v = fma(alpha, G[int64_t(a) * ldc + b], v);
+    if (a == b) v += (a < r) ? diag_r : diag_last;
+    C[int64_t(a) * ldc + b] = v;
+  }
+}
+
+// ---------------------------------------------------------------- interior index list
+__global__ __launch_bounds__(256) void flag_count_kernel(const uint8_t* __restrict__ S, int64_t n, int64_t chunk,
+                                                         int* __restrict__ counts) {
+  __shared__ int sh[256];
+  const int64_t i0 = int64_t(blockIdx.x) * chunk, i1 = min(n, i0 + chunk);
+  int c = 0;
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += 256) c += S[i] ? 1 : 0;
+  sh[threadIdx.x] = c;
+  __syncthreads();
+  for (int off = 128; off >= 1; off >>= 1) {
+    if (threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) counts[blockIdx.x] = sh[0];
+}
+
+__global__ void flag_scan_kernel(int* __restrict__ counts, int nblk, int* __restrict__ total) {
+  if (threadIdx.x == 0) {
+    int acc = 0;
+    for (int b = 0; b < nblk; ++b) {
+      const int c = counts[b];
+      counts[b] = acc;
+      acc += c;
+    }
+    total[0] = acc;
+  }
+}
+
+// Each block writes the indices of its chunk in increasing order (one wave scans).
+__global__ __launch_bounds__(64) void flag_scatter_kernel(const uint8_t* __restrict__ S, int64_t n, int64_t chunk,
+                                                          const int* __restrict__ offsets, int* __restrict__ idx) {
+  const int lane = threadIdx.x;
+  const int64_t i0 = int64_t(blockIdx.x) * chunk, i1 = min(n, i0 + chunk);
+  int base = offsets[blockIdx.x];
+  for (int64_t b = i0; b < i1; b += 64) {
+    const int64_t i = b + lane;
+    const bool f = i < i1 && S[i];
+    const unsigned long long m = __ballot(f);
+    if (f) idx[base + __popcll(m & ((1ull << lane) - 1ull))] = int(i);
+    base += __popcll(m);
   }
 }
 
 // ---------------------------------------------------------------- blocked Cholesky (lower)
-// Diagonal block: one wave factors C[kb:kb+nb, kb:kb+nb] in LDS.
+// Diagonal block kCb x kCb in LDS, one wave.
 __global__ __launch_bounds__(64) void chol_diag_kernel(double* __restrict__ C, int64_t ldc, int kb, int nb,
                                                        int* __restrict__ flag) {
-  __shared__ double A[kT][kT + 1];
-  const int l = threadIdx.x;
-  for (int i = 0; i < nb; ++i)
-    if (l < nb) A[i][l] = C[int64_t(kb + i) * ldc + kb + l];
+  __shared__ double A[kCb][kCb + 1];
+  const int t = threadIdx.x;
+  for (int e = t; e < kCb * kCb; e += 64) {
+    const int i = e / kCb, k = e % kCb;
+    A[i][k] = (i < nb && k <= i) ? C[int64_t(kb + i) * ldc + kb + k] : 0.0;
+  }
   __syncthreads();
   for (int j = 0; j < nb; ++j) {
-    if (l == 0) {
+    if (t == 0) {
       double piv = A[j][j];
       if (!(piv > 0.0) || !isfinite(piv)) {
         flag[0] = 1;
@@ -115,55 +183,54 @@ __global__ __launch_bounds__(64) void chol_diag_kernel(double* __restrict__ C, i
       A[j][j] = sqrt(piv);
     }
     __syncthreads();
-    if (l > j && l < nb) A[l][j] /= A[j][j];
+    if (t > j && t < nb) A[t][j] /= A[j][j];
     __syncthreads();
-    if (l > j && l < nb)
-      for (int k = j + 1; k <= l; ++k) A[l][k] = fma(-A[l][j], A[k][j], A[l][k]);
+    for (int e = t; e < kCb * kCb; e += 64) {
+      const int l = e / kCb, k = e % kCb;
+      if (k > j && k <= l && l < nb) A[l][k] = fma(-A[l][j], A[k][j], A[l][k]);
+    }
     __syncthreads();
   }
-  for (int i = 0; i < nb; ++i)
-    if (l <= i) C[int64_t(kb + i) * ldc + kb + l] = A[i][l];
+  for (int e = t; e < kCb * kCb; e += 64) {
+    const int i = e / kCb, k = e % kCb;
+    if (i < nb && k <= i) C[int64_t(kb + i) * ldc + kb + k] = A[i][k];
+  }
 }
 
-// Panel: rows i >= kb+nb solve x L_kk^T = C[i, kb:kb+nb] (one thread per row).
-__global__ __launch_bounds__(64) void chol_panel_kernel(double* __restrict__ C, int64_t ldc, int kb, int nb,
-                                                        int R1) {
-  __shared__ double Lk[kT][kT + 1];
-  for (int e = threadIdx.x; e < kT * kT; e += 64) {
-    const int i = e / kT, k = e % kT;
-    Lk[i][k] = (i < nb && k <= i) ? C[int64_t(kb + i) * ldc + kb + k] : 0.0;
+// Panel: rows i >= kb+nb solve x L_kk^T = C[i, kb:kb+nb].  A row is held by
+// 32 lanes (lane k owns x_k); column j is finished by lane j and broadcast.
+__global__ __launch_bounds__(256) void chol_panel_kernel(double* __restrict__ C, int64_t ldc, int kb, int nb,
+                                                         int R1) {
+  __shared__ double Lk[kCb][kCb + 1];
+  for (int e = threadIdx.x; e < kCb * kCb; e += 256) {
+    const int i = e / kCb, k = e % kCb;
+    Lk[i][k] = (i < nb && k <= i) ? C[int64_t(kb + i) * ldc + kb + k] : (i == k ? 1.0 : 0.0);
   }
   __syncthreads();
-  const int64_t i = int64_t(kb) + nb + int64_t(blockIdx.x) * 64 + threadIdx.x;
-  if (i >= R1) return;
-  double x[kT];
-  double* row = C + i * ldc + kb;
-#pragma unroll
-  for (int k = 0; k < kT; ++k) x[k] = k < nb ? row[k] : 0.0;
-#pragma unroll
-  for (int j = 0; j < kT; ++j) {
-    if (j < nb) {
-      x[j] /= Lk[j][j];
-#pragma unroll
-      for (int k = j + 1; k < kT; ++k) x[k] = fma(-x[j], Lk[k][j], x[k]);
-    }
+  const int k = threadIdx.x & (kCb - 1);
+  const int64_t i = int64_t(kb) + nb + int64_t(blockIdx.x) * (256 / kCb) + (threadIdx.x / kCb);
+  const bool ok = i < R1;
+  double* row = C + (ok ? i : 0) * ldc + kb;
+  double x = (ok && k < nb) ? row[k] : 0.0;
+  for (int j = 0; j < kCb; ++j) {
+    if (k == j) x /= Lk[j][j];
+    const double xj = __shfl(x, j, kCb);
+    if (k > j) x = fma(-xj, Lk[k][j], x);
   }
-#pragma unroll
-  for (int k = 0; k < kT; ++k)
-    if (k < nb) row[k] = x[k];
+  if (ok && k < nb) row[k] = x;
 }
 
 // Trailing update of the lower part: C[i][j] -= sum_k P[i][k] P[j][k], j <= i.
 __global__ __launch_bounds__(256) void chol_update_kernel(double* __restrict__ C, int64_t ldc, int kb, int nb,
                                                           int R1) {
-  __shared__ double Pi[kT][kT + 1];
-  __shared__ double Pj[kT][kT + 1];
+  __shared__ double Pi[kT][kCb + 1];
+  __shared__ double Pj[kT][kCb + 1];
   int ta, tb;
   tile_coords(blockIdx.x, ta, tb);
   const int base = kb + nb;
   const int i0 = base + ta * kT, j0 = base + tb * kT;
-  for (int e = threadIdx.x; e < kT * kT; e += 256) {
-    const int a = e / kT, k = e % kT;
+  for (int e = threadIdx.x; e < kT * kCb; e += 256) {
+    const int a = e / kCb, k = e % kCb;
     Pi[a][k] = (i0 + a < R1 && k < nb) ? C[int64_t(i0 + a) * ldc + kb + k] : 0.0;
     Pj[a][k] = (j0 + a < R1 && k < nb) ? C[int64_t(j0 + a) * ldc + kb + k] : 0.0;
   }
@@ -174,7 +241,8 @@ __global__ __launch_bounds__(256) void chol_update_kernel(double* __restrict__ C
   for (int p = 0; p < 4; ++p)
 #pragma unroll
     for (int q = 0; q < 4; ++q) acc[p][q] = 0.0;
-  for (int k = 0; k < nb; ++k) {
+#pragma unroll 4
+  for (int k = 0; k < kCb; ++k) {
     double av[4], bv[4];
 #pragma unroll
     for (int p = 0; p < 4; ++p) av[p] = Pi[ty * 4 + p][k];
@@ -194,10 +262,100 @@ __global__ __launch_bounds__(256) void chol_update_kernel(double* __restrict__ C
     }
 }
 
+// ---------------------------------------------------------------- W = Lc^{-1}
+// Inverse of each kIb x kIb diagonal block; lane j forms column j by forward
+// substitution.  Blocks are independent (one workgroup each).
+__global__ __launch_bounds__(64) void trinv_diag_kernel(const double* __restrict__ C, int64_t ldc, int R1,
+                                                        double* __restrict__ W, double* __restrict__ WT) {
+  __shared__ double Lk[kIb][kIb + 1];
+  __shared__ double X[kIb][kIb + 1];
+  const int kb = blockIdx.x * kIb;
+  const int nb = min(kIb, R1 - kb);
+  const int j = threadIdx.x;
+  for (int e = j; e < kIb * kIb; e += 64) {
+    const int i = e / kIb, k = e % kIb;
+    Lk[i][k] = (i < nb && k <= i) ? C[int64_t(kb + i) * ldc + kb + k] : (i == k ? 1.0 : 0.0);
+  }
+  __syncthreads();
+  for (int i = 0; i < kIb; ++i) {
+    double s = (i == j) ? 1.0 : 0.0;
+    for (int k = j; k < i; ++k) s = fma(-Lk[i][k], X[k][j], s);
+    X[i][j] = (i >= j) ? s / Lk[i][i] : 0.0;
+  }
+  __syncthreads();
+  for (int e = j; e < kIb * kIb; e += 64) {
+    const int i = e / kIb, k = e % kIb;
+    if (i < nb && k < nb) {
+      W[int64_t(kb + i) * ldc + kb + k] = X[i][k];
+      WT[int64_t(kb + k) * ldc + kb + i] = X[i][k];
+    }
+  }
+}
+
+// Block row bi (> 0): W_ik = -W_ii sum_{m=k}^{i-1} L_im W_mk for the column
+// block k = blockIdx.x < bi.  W blocks of rows < bi are final.
+__global__ __launch_bounds__(256) void trinv_row_kernel(const double* __restrict__ C, int64_t ldc, int R1, int bi,
+                                                        double* __restrict__ W, double* __restrict__ WT) {
+  __shared__ double A[kIb][kIb + 1];
+  __shared__ double B[kIb][kIb + 1];
+  const int bk = blockIdx.x;
+  const int i0 = bi * kIb, k0 = bk * kIb;
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  double acc[4][4];
+#pragma unroll
+  for (int p = 0; p < 4; ++p)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[p][q] = 0.0;
+  // T = sum_m L_im W_mk
+  for (int bm = bk; bm < bi; ++bm) {
+    const int m0 = bm * kIb;
+    __syncthreads();
+    for (int e = threadIdx.x; e < kIb * kIb; e += 256) {
+      const int a = e / kIb, b = e % kIb;
+      A[a][b] = (i0 + a < R1) ? C[int64_t(i0 + a) * ldc + m0 + b] : 0.0;                    // L_im (full block, m < i)
+      B[a][b] = (m0 + a < R1 && k0 + b <= m0 + a) ? W[int64_t(m0 + a) * ldc + k0 + b] : 0.0;  // W_mk
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int kk = 0; kk < kIb; ++kk) {
+      double av[4], bv[4];
+#pragma unroll
+      for (int p = 0; p < 4; ++p) av[p] = A[ty * 4 + p][kk];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) bv[q] = B[kk][tx * 4 + q];
+#pragma unroll
+      for (int p = 0; p < 4; ++p)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[p][q] = fma(av[p], bv[q], acc[p][q]);
+    }
+  }
+  // W_ik = -W_ii T
+  __syncthreads();
+#pragma unroll
+  for (int p = 0; p < 4; ++p)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) B[ty * 4 + p][tx * 4 + q] = acc[p][q];
+  for (int e = threadIdx.x; e < kIb * kIb; e += 256) {
+    const int a = e / kIb, b = e % kIb;
+    A[a][b] = (i0 + a < R1 && i0 + b < R1 && b <= a) ? W[int64_t(i0 + a) * ldc + i0 + b] : 0.0;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int p = 0; p < 4; ++p)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int a = ty * 4 + p, b = tx * 4 + q;
+      double s = 0.0;
+      for (int kk = 0; kk <= a; ++kk) s = fma(A[a][kk], B[kk][b], s);
+      if (i0 + a < R1) {
+        W[int64_t(i0 + a) * ldc + k0 + b] = -s;
+        WT[int64_t(k0 + b) * ldc + i0 + a] = -s;
+      }
+    }
+}
+
 // ---------------------------------------------------------------- apply
-// g = w / L ; partial t[a] = sum_{rows of this block} U_ia g_i.  Rows of the
-// block's chunk are staged in LDS 1024 at a time.
-constexpr int kGtStage = 1024;
+// g = w / L ; part[blk][a] = sum_{rows of this block} U_ia g_i
 __global__ __launch_bounds__(256) void wood_gt_kernel(const float* __restrict__ F, int64_t n, int r,
                                                       int64_t ldf, int R1, const double* __restrict__ L,
                                                       const double* __restrict__ w, double* __restrict__ g,
@@ -219,9 +377,23 @@ __global__ __launch_bounds__(256) void wood_gt_kernel(const float* __restrict__ 
     for (int q = 0; q < 4; ++q) {
       const int a = threadIdx.x + 256 * q;
       if (a < r) {
-        for (int k = 0; k < cnt; ++k) acc[q] = fma(double(F[(sb + k) * ldf + a]), gs[k], acc[q]);
+        const float* col = F + sb * ldf + a;
+        int k = 0;
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        for (; k + 4 <= cnt; k += 4) {
+          const float f0 = col[(k + 0) * ldf], f1 = col[(k + 1) * ldf];
+          const float f2 = col[(k + 2) * ldf], f3 = col[(k + 3) * ldf];
+          s0 = fma(double(f0), gs[k + 0], s0);
+          s1 = fma(double(f1), gs[k + 1], s1);
+          s2 = fma(double(f2), gs[k + 2], s2);
+          s3 = fma(double(f3), gs[k + 3], s3);
+        }
+        for (; k < cnt; ++k) s0 = fma(double(col[k * ldf]), gs[k], s0);
+        acc[q] += (s0 + s1) + (s2 + s3);
       } else if (a == r) {
-        for (int k = 0; k < cnt; ++k) acc[q] += gs[k];
+        double s = 0.0;
+        for (int k = 0; k < cnt; ++k) s += gs[k];
+        acc[q] += s;
       }
     }
   }
@@ -232,115 +404,63 @@ __global__ __launch_bounds__(256) void wood_gt_kernel(const float* __restrict__ 
   }
 }
 
-// t = sum of partials ; s = C^{-1} t = Lc^{-T} Lc^{-1} t (one workgroup, FP64).
-__global__ __launch_bounds__(256) void wood_solve_kernel(const double* __restrict__ part, int nblk, int R1,
-                                                         const double* __restrict__ C, int64_t ldc,
-                                                         double* __restrict__ s_out) {
-  __shared__ double y[1024];
-  __shared__ double D[kT][kT + 1];
-  const int tid = threadIdx.x;
-  for (int a = tid; a < R1; a += 256) {
-    double acc = 0.0;
-    for (int b = 0; b < nblk; ++b) acc += part[int64_t(b) * R1 + a];
-    y[a] = acc;
-  }
-  __syncthreads();
-  // forward: Lc y = t
-  for (int kb = 0; kb < R1; kb += kT) {
-    const int nb = min(kT, R1 - kb);
-    for (int e = tid; e < kT * kT; e += 256) {
-      const int i = e / kT, k = e % kT;
-      D[i][k] = (i < nb && k <= i) ? C[int64_t(kb + i) * ldc + kb + k] : 0.0;
-    }
-    __syncthreads();
-    if (tid < 64) {
-      double yl = tid < nb ? y[kb + tid] : 0.0;
-      for (int j = 0; j < nb; ++j) {
-        if (tid == j) yl /= D[j][j];
-        const double yj = __shfl(yl, j);
-        if (tid > j && tid < nb) yl = fma(-D[tid][j], yj, yl);
-      }
-      if (tid < nb) y[kb + tid] = yl;
-    }
-    __syncthreads();
-    for (int i = kb + nb + tid; i < R1; i += 256) {
-      const double* row = C + int64_t(i) * ldc + kb;
-      double acc = y[i];
-      for (int k = 0; k < nb; ++k) acc = fma(-row[k], y[kb + k], acc);
-      y[i] = acc;
-    }
-    __syncthreads();
-  }
-  // backward: Lc^T x = y
-  const int nblocks = (R1 + kT - 1) / kT;
-  for (int bi = nblocks - 1; bi >= 0; --bi) {
-    const int kb = bi * kT;
-    const int nb = min(kT, R1 - kb);
-    for (int e = tid; e < kT * kT; e += 256) {
-      const int i = e / kT, k = e % kT;
-      D[i][k] = (i < nb && k <= i) ? C[int64_t(kb + i) * ldc + kb + k] : 0.0;
-    }
-    __syncthreads();
-    if (tid < 64) {
-      double xl = tid < nb ? y[kb + tid] : 0.0;
-      for (int j = nb - 1; j >= 0; --j) {
-        if (tid == j) xl /= D[j][j];
-        const double xj = __shfl(xl, j);
-        if (tid < j) xl = fma(-D[j][tid], xj, xl);
-      }
-      if (tid < nb) y[kb + tid] = xl;
-    }
-    __syncthreads();
-    for (int i = tid; i < kb; i += 256) {
-      double acc = y[i];
-      for (int k = 0; k < nb; ++k) acc = fma(-C[int64_t(kb + k) * ldc + i], y[kb + k], acc);
-      y[i] = acc;
-    }
-    __syncthreads();
-  }
-  for (int a = tid; a < R1; a += 256) s_out[a] = y[a];
+__global__ void wood_treduce_kernel(const double* __restrict__ part, int nblk, int R1, double* __restrict__ t) {
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= R1) return;
+  double s = 0.0;
+  for (int b = 0; b < nblk; ++b) s += part[int64_t(b) * R1 + a];
+  t[a] = s;
 }
 
-// out_i = g_i - (sum_a F_ia s_a + s_r) / L_i ; optional partial dot_with . out
-__global__ __launch_bounds__(256) void wood_out_kernel(const float* __restrict__ F, int64_t n, int r,
-                                                       int64_t ldf, const double* __restrict__ L,
-                                                       const double* __restrict__ g,
-                                                       const double* __restrict__ s,
-                                                       double* __restrict__ out,
+// out[i] = sum_{k in [lo(i), hi(i)]} M[i][k] x[k]  for a triangular M (one wave per row).
+template <bool LOWER>
+__global__ __launch_bounds__(256) void trmv_kernel(const double* __restrict__ M, int64_t ldm, int R1,
+                                                   const double* __restrict__ x, double* __restrict__ out) {
+  const int lane = threadIdx.x & 63;
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= R1) return;
+  const int lo = LOWER ? 0 : row, hi = LOWER ? row : R1 - 1;
+  const double* mr = M + int64_t(row) * ldm;
+  double s = 0.0;
+  for (int k = lo + lane; k <= hi; k += 64) s = fma(mr[k], x[k], s);
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off);
+  if (lane == 0) out[row] = s;
+}
+
+// out_i = g_i - (Fs_i + s_r) / L_i ; optional partial dot_with . out
+__global__ __launch_bounds__(256) void wood_out_kernel(int64_t n, int r, const double* __restrict__ L,
+                                                       const double* __restrict__ g, const double* __restrict__ Fs,
+                                                       const double* __restrict__ s, double* __restrict__ out,
                                                        const double* __restrict__ dot_with,
                                                        double* __restrict__ partials) {
-  extern __shared__ double ss[];
-  __shared__ double wsum[4];
-  for (int a = threadIdx.x; a <= r; a += 256) ss[a] = s[a];
-  __syncthreads();
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int64_t nw = int64_t(gridDim.x) * 4;
-  double dacc = 0.0;
-  for (int64_t i = int64_t(blockIdx.x) * 4 + wave; i < n; i += nw) {
-    const float* row = F + i * ldf;
-    double acc = 0.0;
-    for (int a = lane; a < r; a += 64) acc = fma(double(row[a]), ss[a], acc);
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off);
-    const double o = g[i] - (acc + ss[r]) / L[i];
-    if (lane == 0) {
-      out[i] = o;
-      if (dot_with) dacc = fma(o, dot_with[i], dacc);
-    }
+  __shared__ double sh[4];
+  const double sr = s[r];
+  double acc = 0.0;
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) {
+    const double fs = r > 0 ? Fs[i] : 0.0;
+    const double o = g[i] - (fs + sr) / L[i];
+    out[i] = o;
+    if (dot_with) acc = fma(o, dot_with[i], acc);
   }
   if (partials) {
-    if (lane == 0) wsum[wave] = dacc;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
     __syncthreads();
-    if (threadIdx.x == 0) partials[blockIdx.x] = ((wsum[0] + wsum[1]) + wsum[2]) + wsum[3];
+    if (threadIdx.x == 0) partials[blockIdx.x] = ((sh[0] + sh[1]) + sh[2]) + sh[3];
   }
 }
 
 // ---------------------------------------------------------------- class
 Woodbury::Woodbury(const float* F, int64_t n, int64_t r, int64_t ldf)
-    : F_(F), n_(n), r_(r), ldf_(ldf), R1_(r + 1), hflag_(sizeof(int)) {
+    : F_(F), n_(n), r_(r), ldf_(ldf), R1_(r + 1), hbuf_(4 * sizeof(int)) {
   if (R1_ > 1024) fail(KQR_EINVAL, "preconditioner rank %lld exceeds 1023", (long long)r);
   ldc_ = R1_;
-  C_.alloc(size_t(R1_) * ldc_ * sizeof(double));
+  const size_t core = size_t(R1_) * ldc_ * sizeof(double);
+  C_.alloc(core);
+  W_.alloc(core);
+  WT_.alloc(core);
   const int nt = int((R1_ + kT - 1) / kT);
   const int ntile = nt * (nt + 1) / 2;
   nsplit_ = std::max(1, std::min(32, 1024 / ntile));
@@ -348,55 +468,136 @@ Woodbury::Woodbury(const float* F, int64_t n, int64_t r, int64_t ldf)
   const size_t gt_part = size_t(kGtBlocks) * R1_;
   part_.alloc(std::max(syrk_part, gt_part) * sizeof(double));
   g_.alloc(size_t(std::max<int64_t>(n, 1)) * sizeof(double));
+  Fs_.alloc(size_t(std::max<int64_t>(n, 1)) * sizeof(double));
+  t_.alloc(size_t(R1_) * sizeof(double));
+  y_.alloc(size_t(R1_) * sizeof(double));
   s_.alloc(size_t(R1_) * sizeof(double));
-  flag_.alloc(sizeof(int));
+  flag_.alloc(4 * sizeof(int));
+}
+
+void Woodbury::syrk(const double* L, const int* idx, int64_t nrows, double* G, double alpha, double beta,
+                    double diag_r, double diag_last, double* out, hipStream_t st) {
+  const int R1 = int(R1_);
+  const int nt = (R1 + kT - 1) / kT;
+  const int ntile = nt * (nt + 1) / 2;
+  int nsplit = 0;
+  if (nrows > 0) {
+    nsplit = nsplit_;
+    if (nrows < int64_t(nsplit) * kSubRows) nsplit = int(std::max<int64_t>(1, (nrows + kSubRows - 1) / kSubRows));
+    int64_t chunk = (nrows + nsplit - 1) / nsplit;
+    chunk = std::max<int64_t>(kSubRows, (chunk + kSubRows - 1) / kSubRows * kSubRows);
+    nsplit = int(std::max<int64_t>(1, (nrows + chunk - 1) / chunk));
+    syrk_kernel<<<dim3(ntile, nsplit), 256, 0, st>>>(F_, nrows, int(r_), ldf_, L, idx, ntile, chunk,
+                                                     part_.as<double>());
+    KQR_LAUNCH_CHECK();
+  }
+  syrk_combine_kernel<<<ntile, 256, 0, st>>>(part_.as<double>(), nsplit, ntile, int(r_), R1, diag_r, diag_last, G,
+                                             alpha, beta, out, ldc_);
+  KQR_LAUNCH_CHECK();
+}
+
+bool Woodbury::factor(hipStream_t st) {
+  const int R1 = int(R1_);
+  KQR_CHECK_HIP(hipMemsetAsync(flag_.ptr, 0, sizeof(int), st));
+  double* C = C_.as<double>();
+  for (int kb = 0; kb < R1; kb += kCb) {
+    const int nb = std::min(kCb, R1 - kb);
+    chol_diag_kernel<<<1, 64, 0, st>>>(C, ldc_, kb, nb, flag_.as<int>());
+    KQR_LAUNCH_CHECK();
+    const int rest = R1 - kb - nb;
+    if (rest > 0) {
+      chol_panel_kernel<<<(rest + 256 / kCb - 1) / (256 / kCb), 256, 0, st>>>(C, ldc_, kb, nb, R1);
+      KQR_LAUNCH_CHECK();
+      const int mt = (rest + kT - 1) / kT;
+      chol_update_kernel<<<mt * (mt + 1) / 2, 256, 0, st>>>(C, ldc_, kb, nb, R1);
+      KQR_LAUNCH_CHECK();
+    }
+  }
+  const int nib = (R1 + kIb - 1) / kIb;
+  trinv_diag_kernel<<<nib, 64, 0, st>>>(C, ldc_, R1, W_.as<double>(), WT_.as<double>());
+  KQR_LAUNCH_CHECK();
+  for (int bi = 1; bi < nib; ++bi) {
+    trinv_row_kernel<<<bi, 256, 0, st>>>(C, ldc_, R1, bi, W_.as<double>(), WT_.as<double>());
+    KQR_LAUNCH_CHECK();
+  }
+  KQR_CHECK_HIP(hipMemcpyAsync(hbuf_.ptr, flag_.ptr, sizeof(int), hipMemcpyDeviceToHost, st));
+  KQR_CHECK_HIP(hipStreamSynchronize(st));
+  return *hbuf_.as<int>() == 0;
 }
 
 bool Woodbury::build(const double* L, double c, hipStream_t st) {
   L_ = L;
-  c_ = c;
-  const int R1 = int(R1_);
-  const int nt = (R1 + kT - 1) / kT;
-  const int ntile = nt * (nt + 1) / 2;
-  int64_t chunk = (n_ + nsplit_ - 1) / nsplit_;
-  chunk = (chunk + kSubRows - 1) / kSubRows * kSubRows;
-  syrk_kernel<<<dim3(ntile, nsplit_), 256, 0, st>>>(F_, n_, int(r_), ldf_, L, ntile, chunk, part_.as<double>());
-  KQR_LAUNCH_CHECK();
-  syrk_reduce_kernel<<<ntile, 256, 0, st>>>(part_.as<double>(), nsplit_, ntile, int(r_), R1, c, C_.as<double>(),
-                                            ldc_);
-  KQR_LAUNCH_CHECK();
-  KQR_CHECK_HIP(hipMemsetAsync(flag_.ptr, 0, sizeof(int), st));
-  for (int kb = 0; kb < R1; kb += kT) {
-    const int nb = std::min(kT, R1 - kb);
-    chol_diag_kernel<<<1, 64, 0, st>>>(C_.as<double>(), ldc_, kb, nb, flag_.as<int>());
-    KQR_LAUNCH_CHECK();
-    const int rest = R1 - kb - nb;
-    if (rest > 0) {
-      chol_panel_kernel<<<(rest + 63) / 64, 64, 0, st>>>(C_.as<double>(), ldc_, kb, nb, R1);
-      KQR_LAUNCH_CHECK();
-      const int mt = (rest + kT - 1) / kT;
-      chol_update_kernel<<<mt * (mt + 1) / 2, 256, 0, st>>>(C_.as<double>(), ldc_, kb, nb, R1);
-      KQR_LAUNCH_CHECK();
-    }
+  syrk(L, nullptr, n_, nullptr, 0.0, 1.0, 1.0, 1.0 / c, C_.as<double>(), st);
+  return factor(st);
+}
+
+void Woodbury::prepare_gram(hipStream_t st) {
+  if (G_.ptr) return;
+  G_.alloc(size_t(R1_) * ldc_ * sizeof(double));
+  syrk(nullptr, nullptr, n_, nullptr, 0.0, 1.0, 0.0, 0.0, G_.as<double>(), st);
+}
+
+bool Woodbury::build_scaled_identity(const double* L, double l, double c, hipStream_t st) {
+  prepare_gram(st);
+  L_ = L;
+  syrk(nullptr, nullptr, 0, G_.as<double>(), 1.0 / l, 0.0, 1.0, 1.0 / c, C_.as<double>(), st);
+  return factor(st);
+}
+
+bool Woodbury::build_two_level(const double* L, const uint8_t* S, double l_in, double l_out, double c,
+                               hipStream_t st) {
+  L_ = L;
+  const int64_t n = n_;
+  // interior index list
+  constexpr int nblk = 256;
+  const int64_t chunk = (n + nblk - 1) / nblk;
+  if (!idx_.ptr) {
+    idx_.alloc(size_t(std::max<int64_t>(n, 1)) * sizeof(int));
+    cnt_.alloc((nblk + 1) * sizeof(int));
   }
-  KQR_CHECK_HIP(hipMemcpyAsync(hflag_.ptr, flag_.ptr, sizeof(int), hipMemcpyDeviceToHost, st));
+  flag_count_kernel<<<nblk, 256, 0, st>>>(S, n, chunk, cnt_.as<int>());
+  KQR_LAUNCH_CHECK();
+  flag_scan_kernel<<<1, 64, 0, st>>>(cnt_.as<int>(), nblk, cnt_.as<int>() + nblk);
+  KQR_LAUNCH_CHECK();
+  KQR_CHECK_HIP(hipMemcpyAsync(hbuf_.ptr, cnt_.as<int>() + nblk, sizeof(int), hipMemcpyDeviceToHost, st));
   KQR_CHECK_HIP(hipStreamSynchronize(st));
-  return *hflag_.as<int>() == 0;
+  const int64_t m = *hbuf_.as<int>();
+  if (m > n / 2) {  // the interior is most of the data: one weighted pass is cheaper
+    syrk(L, nullptr, n, nullptr, 0.0, 1.0, 1.0, 1.0 / c, C_.as<double>(), st);
+    return factor(st);
+  }
+  prepare_gram(st);
+  flag_scatter_kernel<<<nblk, 64, 0, st>>>(S, n, chunk, cnt_.as<int>(), idx_.as<int>());
+  KQR_LAUNCH_CHECK();
+  // C = diag(I, 1/c) + G_all / l_out + (1/l_in - 1/l_out) U_E^T U_E
+  syrk(nullptr, idx_.as<int>(), m, G_.as<double>(), 1.0 / l_out, 1.0 / l_in - 1.0 / l_out, 1.0, 1.0 / c,
+       C_.as<double>(), st);
+  return factor(st);
 }
 
 void Woodbury::apply(const double* w, double* out, const double* dot_with, double* dot_out, Workspace& ws,
                      hipStream_t st) {
   const int R1 = int(R1_);
   const int64_t chunk = (n_ + kGtBlocks - 1) / kGtBlocks;
-  wood_gt_kernel<<<kGtBlocks, 256, 0, st>>>(
-      F_, n_, int(r_), ldf_, R1, L_, w, g_.as<double>(), chunk, part_.as<double>());
+  wood_gt_kernel<<<kGtBlocks, 256, 0, st>>>(F_, n_, int(r_), ldf_, R1, L_, w, g_.as<double>(), chunk,
+                                            part_.as<double>());
   KQR_LAUNCH_CHECK();
-  wood_solve_kernel<<<1, 256, 0, st>>>(part_.as<double>(), kGtBlocks, R1, C_.as<double>(), ldc_,
-                                       s_.as<double>());
+  wood_treduce_kernel<<<(R1 + 255) / 256, 256, 0, st>>>(part_.as<double>(), kGtBlocks, R1, t_.as<double>());
   KQR_LAUNCH_CHECK();
-  wood_out_kernel<<<kRedBlocks, 256, size_t(R1) * sizeof(double), st>>>(
-      F_, n_, int(r_), ldf_, L_, g_.as<double>(), s_.as<double>(), out, dot_with,
-      dot_with ? ws.partials : nullptr);
+  trmv_kernel<true><<<(R1 + 3) / 4, 256, 0, st>>>(W_.as<double>(), ldc_, R1, t_.as<double>(), y_.as<double>());
+  KQR_LAUNCH_CHECK();
+  trmv_kernel<false><<<(R1 + 3) / 4, 256, 0, st>>>(WT_.as<double>(), ldc_, R1, y_.as<double>(), s_.as<double>());
+  KQR_LAUNCH_CHECK();
+  if (r_ > 0) {
+    const KMat fm{F_, KQR_FP32, ldf_};
+    ApplyShape sh;
+    sh.rows = 8;
+    sh.unroll = 1;
+    sh.segs = 1;
+    kapply_dense(fm, n_, r_, nullptr, s_.as<double>(), Fs_.as<double>(), 1, true, st, &sh);
+  }
+  wood_out_kernel<<<kRedBlocks, 256, 0, st>>>(n_, int(r_), L_, g_.as<double>(), Fs_.as<double>(), s_.as<double>(),
+                                              out, dot_with, dot_with ? ws.partials : nullptr);
   KQR_LAUNCH_CHECK();
   if (dot_with) reduce_finalize(ws.partials, kRedBlocks, 1, dot_out, st);
 }

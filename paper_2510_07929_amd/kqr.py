@@ -80,6 +80,9 @@ _SIGS = {
     "kqr_rpcholesky": (C.c_int, [_P, _I64, _I64, C.c_int, C.c_double, _P, C.c_int, _I64, _I64, _P, _P, _I64,
                                  _P, _P, _P]),
     "kqr_woodbury_apply": (C.c_int, [_P, _I64, _I64, _I64, C.c_double, _P, _P, _P, _P]),
+    "kqr_adaptive_rank": (C.c_int, [_P, _I64, _I64, _I64, C.c_double, _P, _P, _P]),
+    "kqr_autotune_apply": (C.c_int, [_P, C.c_int, _I64, _I64, C.c_int, C.c_int, C.c_char_p, _I64, _P]),
+    "kqr_set_apply_shape": (C.c_int, [C.c_int, C.c_int, _I64, C.c_int, C.c_int, C.c_int]),
     "kqr_pcg_solve": (C.c_int, [_P, _I64, _I64, C.c_int, C.c_double, _P, C.c_int, _I64, _P, _I64, _I64,
                                 C.c_double, _P, _P, C.c_double, C.c_int, _P, _P, _P, _P]),
     "kqr_ssn_gradient": (C.c_int, [_I64, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double,
@@ -104,6 +107,10 @@ def lib():
     global _lib_handle
     with _lib_lock:
         if _lib_handle is None:
+            # torch ships its own HIP runtime (same soname); loading torch first
+            # makes libkqr bind to that runtime, so one runtime owns the device
+            # memory and streams that are passed across.
+            import torch  # noqa: F401
             if not os.path.exists(_LIB_PATH):
                 raise RuntimeError(
                     f"libkqr.so not found at {_LIB_PATH}; build it with "
@@ -260,6 +267,34 @@ def kqr_rpcholesky(rank, uniforms, X=None, kernel="rbf", gamma=1.0, K=None, n=No
                                 piv.ctypes.data_as(C.c_void_p), C.byref(rout), _stream(stream)), "kqr_rpcholesky")
     r = int(rout.value)
     return F, piv[:r].copy(), r
+
+
+def kqr_adaptive_rank(F0, r0, xi=1e-3, stream=None):
+    """Section 3 rank rule on the first r0 columns of F0 (GPU float32 n x ldf); returns (r, lambda_1)."""
+    torch = _torch()
+    n, ldf = F0.shape
+    r = C.c_int64(0)
+    l1 = C.c_double(0.0)
+    _check(lib().kqr_adaptive_rank(_dev(F0, torch.float32, "F0", 2), n, int(r0), ldf, float(xi), C.byref(r),
+                                   C.byref(l1), _stream(stream)), "kqr_adaptive_rank")
+    return int(r.value), float(l1.value)
+
+
+def kqr_autotune_apply(K, mode=KQR_APPLY_FAST, reps=5, stream=None):
+    """Sweep the K-apply tile shapes on K (GPU, from kqr_kernel_build); returns the JSON report (dict)."""
+    import json
+
+    torch = _torch()
+    kd = KQR_FP32 if K.dtype == torch.float32 else KQR_BF16
+    buf = C.create_string_buffer(1 << 16)
+    _check(lib().kqr_autotune_apply(_dev(K, K.dtype, "K", 2), kd, K.shape[0], K.shape[1], int(mode), int(reps), buf,
+                                    len(buf), _stream(stream)), "kqr_autotune_apply")
+    return json.loads(buf.value.decode())
+
+
+def kqr_set_apply_shape(k_dtype, mode, n, rows, unroll, segs):
+    _check(lib().kqr_set_apply_shape(_kdtype_id(k_dtype), int(mode), int(n), int(rows), int(unroll), int(segs)),
+           "kqr_set_apply_shape")
 
 
 def kqr_woodbury_apply(F, r, c, Ldiag, w, stream=None):
