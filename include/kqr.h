@@ -249,6 +249,34 @@ int kqr_fit(const float* X, const double* y, int64_t n, int64_t p, double tau, d
             int kernel, double gamma, const kqr_options* opt, double* alpha, double* beta,
             kqr_info* info, void* stream);
 
+/* kqr_fit_multi_tau: kqr_fit for ntau quantile levels taus[0..ntau-1] on the
+ * same (X, y, lambda, kernel, gamma), solved jointly.  K and the RPCholesky
+ * factor are built once; each level runs its own PALM-KQR iteration (one host
+ * thread and stream per level) and the fast K-applies of all levels still
+ * running are coalesced into one K V launch on the matrix cores (V: n x up to
+ * 16 columns), so one pass over K serves every level.
+ *  alpha   device, ntau x n FP64 (row t = alpha of taus[t]);  beta host ntau;
+ *  info    host ntau (may be NULL); for the coalesced applies
+ *          kapply_fast_calls / t_kapply_fast count the shared launches;
+ *  status  host ntau: KQR_OK or KQR_NOT_CONVERGED per level.
+ *  1 <= ntau <= 16.  Returns KQR_OK when every level ran (see status[]), else
+ *  the first error. */
+int kqr_fit_multi_tau(const float* X, const double* y, int64_t n, int64_t p, const double* taus, int ntau,
+                      double lambda, int kernel, double gamma, const kqr_options* opt, double* alpha,
+                      double* beta, kqr_info* info, int* status, void* stream);
+
+/* kqr_fit_batch: nprob independent fits (sizes n[i], common p and kernel
+ * type, per-problem tau, lambda, gamma).  Each problem gets its own K and
+ * preconditioner; the fast K-applies of all problems still running go out as
+ * one launch whose workgroups are dealt over the (problem, row block) pairs.
+ *  X, y, alpha: host arrays of nprob device pointers (n[i] x p FP32, n[i] FP64,
+ *  n[i] FP64); tau, lambda, gamma, n: host arrays; beta, status: host nprob;
+ *  info: host nprob (may be NULL).  1 <= nprob <= 256. */
+int kqr_fit_batch(int nprob, const float* const* X, const double* const* y, const int64_t* n, int64_t p,
+                  const double* tau, const double* lambda, int kernel, const double* gamma,
+                  const kqr_options* opt, double* const* alpha, double* beta, kqr_info* info, int* status,
+                  void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,6 +1,6 @@
 // extern "C" entry points of libkqr: argument validation, workspace set-up and
 // dispatch.  No exception crosses the ABI: every entry point returns a status.
-#include "solver.h"
+#include "fit.h"
 
 #include <algorithm>
 #include <chrono>
@@ -61,24 +61,6 @@ void ensure_device() {
     (void)hipGetLastError();
     fail(KQR_ENODEVICE, "no HIP device available");
   }
-}
-
-// Uniforms in [0,1) for pivot draws when the caller gives none: SplitMix64
-// (Steele, Lea, Flood 2014) on seed + i, top 53 bits.
-static std::vector<double> splitmix_uniforms(uint64_t seed, int64_t count) {
-  std::vector<double> u(size_t(std::max<int64_t>(count, 0)));
-  for (int64_t i = 0; i < count; ++i) {
-    uint64_t z = seed + 0x9e3779b97f4a7c15ull * uint64_t(i + 1);
-    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
-    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
-    z ^= z >> 31;
-    u[size_t(i)] = double(z >> 11) * (1.0 / 9007199254740992.0);
-  }
-  return u;
-}
-
-static double now_s() {
-  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
 template <typename Fn>
@@ -230,6 +212,18 @@ int kqr_kernel_apply(const float* X, int64_t n, int64_t p, int kernel, double ga
     if (!K) {
       KQR_CHECK_HIP(hipMallocAsync(reinterpret_cast<void**>(&sqn), size_t(n) * sizeof(float), st));
       row_sqnorms(X, n, int(p), sqn, st);
+    }
+    if (K && m > 1) {  // all columns in one pass over K on the matrix cores
+      const int segs = 4;
+      float* V16 = nullptr;
+      double* part = nullptr;
+      KQR_CHECK_HIP(hipMallocAsync(reinterpret_cast<void**>(&V16), size_t(n) * 16 * sizeof(float), st));
+      KQR_CHECK_HIP(hipMallocAsync(reinterpret_cast<void**>(&part), size_t(segs) * n * 16 * sizeof(double), st));
+      kv_gather_strided(V, ldv, int(m), n, n, V16, st);
+      kapply_kv(km, n, V16, int(m), U, ldu, part, segs, st);
+      KQR_CHECK_HIP(hipFreeAsync(part, st));
+      KQR_CHECK_HIP(hipFreeAsync(V16, st));
+      m = 0;  // done
     }
     for (int64_t j = 0; j < m; ++j) {
       const double* col = V + j;
@@ -483,84 +477,65 @@ int kqr_fit(const float* X, const double* y, int64_t n, int64_t p, double tau, d
     kqr_options o;
     kqr_default_options(&o);
     if (opt) o = *opt;
-    KQR_REQUIRE(o.tol > 0.0 && o.admm_tol > 0.0 && o.admm_sigma > 0.0, "tolerances and sigma must be positive");
-    KQR_REQUIRE(o.admm_step > 0.0 && o.admm_step < 1.6180339887498949, "admm_step must lie in (0, (1+sqrt 5)/2)");
-    KQR_REQUIRE(o.admm_max_iter >= 0 && o.alm_max_iter >= 0 && o.pcg_max_iter >= 1, "iteration caps must be >= 0");
-    KQR_REQUIRE(o.etabar > 0.0 && o.etabar < 1.0 && o.iota > 0.0 && o.iota <= 1.0, "need etabar in (0,1), iota in (0,1]");
-    KQR_REQUIRE(o.armijo > 0.0 && o.armijo < 0.5 && o.ls_shrink > 0.0 && o.ls_shrink < 1.0, "need armijo in (0,1/2), ls_shrink in (0,1)");
-    KQR_REQUIRE(o.tau1 > 0.0 && o.tau1 < 1.0 && o.tau2 > 0.0 && o.tau2 < 1.0, "need tau1, tau2 in (0,1)");
-    KQR_REQUIRE(o.k_dtype == KQR_FP32 || o.k_dtype == KQR_BF16, "k_dtype must be KQR_FP32 or KQR_BF16");
-    KQR_REQUIRE(o.kmode >= KQR_KMODE_AUTO && o.kmode <= KQR_KMODE_ON_THE_FLY, "invalid kmode");
-    KQR_REQUIRE(o.rank <= 1023, "rank must be <= 1023");
-    KQR_REQUIRE(o.sigma_factor >= 1.0 && o.sigma_max >= o.admm_sigma, "need sigma_factor >= 1, sigma_max >= admm_sigma");
+    validate_options(o);
     ensure_device();
     hipStream_t st = static_cast<hipStream_t>(stream);
-    kqr_info inf;
-    memset(&inf, 0, sizeof(inf));
-    const double t_start = now_s();
-    // ---- K: materialise or recompute
-    const int esz = o.k_dtype == KQR_BF16 ? 2 : 4;
-    const int64_t ldk = (n + 63) / 64 * 64;
-    const size_t kbytes = size_t(n) * size_t(ldk) * esz;
-    bool materialize = o.kmode == KQR_KMODE_MATERIALIZE;
-    if (o.kmode == KQR_KMODE_AUTO) {
-      size_t freeb = 0, totalb = 0;
-      KQR_CHECK_HIP(hipMemGetInfo(&freeb, &totalb));
-      materialize = kbytes < freeb / 10 * 8;
-    }
-    DevBuf Kbuf;
-    DevBuf sqn_tmp(size_t(n) * sizeof(float));
-    if (materialize) {
-      Kbuf.alloc(kbytes);
-      row_sqnorms(X, n, int(p), sqn_tmp.as<float>(), st);
-      kbuild(X, sqn_tmp.as<float>(), n, int(p), KernelSpec{kernel, gamma}, o.k_dtype, Kbuf.ptr, ldk, st);
-    }
-    KQR_CHECK_HIP(hipStreamSynchronize(st));
-    inf.t_kbuild = now_s() - t_start;
-    Operator op(X, n, int(p), KernelSpec{kernel, gamma}, KMat{Kbuf.ptr, o.k_dtype, ldk}, st);
+    const KernelSpec ks{kernel, gamma};
+    Prepared pr = prepare_fit(X, n, int(p), ks, o, st);
+    Operator op(X, n, int(p), ks, pr.kmat(), st);
     op.enable_profile(o.profile != 0);
-    // ---- preconditioner (3.2)
-    const double t_p0 = now_s();
-    int64_t rank = 0;
-    if (o.rank > 0) rank = std::min<int64_t>(o.rank, n);
-    else if (o.rank == 0) rank = std::min<int64_t>(int64_t(std::ceil(std::sqrt(double(n)))), std::min<int64_t>(n, 1023));
-    const int64_t ldf = std::max<int64_t>(4, (rank + 3) / 4 * 4);
-    DevBuf Fbuf;
-    int64_t rank_used = 0;
-    if (rank > 0) {
-      Fbuf.alloc(size_t(n) * ldf * sizeof(float));
-      KQR_CHECK_HIP(hipMemsetAsync(Fbuf.ptr, 0, size_t(n) * ldf * sizeof(float), st));
-      std::vector<double> u;
-      const double* uni = o.pivot_uniforms;
-      if (!uni) {
-        u = splitmix_uniforms(o.seed, rank);
-        uni = u.data();
-      }
-      std::vector<int64_t> piv = rpcholesky(op.kmat(), X, op.sqn(), n, int(p), KernelSpec{kernel, gamma}, rank, uni,
-                                            Fbuf.as<float>(), ldf, st);
-      rank_used = int64_t(piv.size());
-      // Section 3 heuristic: keep the first r columns (the first r steps of
-      // RPCholesky are RPCholesky(K, r) on the same draws)
-      if (o.rank == 0 && rank_used > 1) rank_used = adaptive_rank(Fbuf.as<float>(), n, rank_used, ldf, o.xi, st, nullptr);
-    }
-    inf.rank_used = int(rank_used);
-    inf.t_precond = now_s() - t_p0;
-    // ---- Phase I and II
-    Solver solver(op, y, n, tau, lambda, o, Fbuf.as<float>(), rank_used, ldf, st);
-    solver.phase1(inf);
-    solver.phase2(inf);
-    solver.finish(inf);
-    KQR_CHECK_HIP(hipMemcpyAsync(alpha, solver.alpha(), size_t(n) * sizeof(double), hipMemcpyDeviceToDevice, st));
-    KQR_CHECK_HIP(hipStreamSynchronize(st));
-    *beta = solver.beta();
-    inf.kapply_calls = op.calls();
-    op.profile_totals(inf.kapply_fast_calls, inf.t_kapply_fast, inf.kapply_exact_calls, inf.t_kapply_exact);
-    inf.t_total = now_s() - t_start;
-    converged = solver.converged();
-    if (info) *info = inf;
+    FitOutcome out = run_fit(op, pr, y, n, tau, lambda, o, alpha, st);
+    *beta = out.beta;
+    converged = out.converged;
+    if (info) *info = out.info;
   });
   if (st_code == KQR_OK && !converged) return KQR_NOT_CONVERGED;
   return st_code;
+}
+
+int kqr_fit_multi_tau(const float* X, const double* y, int64_t n, int64_t p, const double* taus, int ntau,
+                      double lambda, int kernel, double gamma, const kqr_options* opt, double* alpha, double* beta,
+                      kqr_info* info, int* status, void* stream) {
+  return guarded([&] {
+    KQR_REQUIRE(X && y && taus && alpha && beta && status, "pointers must be non-null");
+    KQR_REQUIRE(n >= 2 && p >= 1 && p <= 64, "need n >= 2 and 1 <= p <= 64");
+    KQR_REQUIRE(ntau >= 1 && ntau <= 16, "need 1 <= ntau <= 16");
+    for (int t = 0; t < ntau; ++t) KQR_REQUIRE(taus[t] > 0.0 && taus[t] < 1.0, "need 0 < tau < 1 for every level");
+    KQR_REQUIRE(std::isfinite(lambda) && lambda > 0.0, "lambda must be positive and finite");
+    check_kernel(kernel, gamma);
+    kqr_options o;
+    kqr_default_options(&o);
+    if (opt) o = *opt;
+    validate_options(o);
+    ensure_device();
+    fit_multi_tau(X, y, n, int(p), KernelSpec{kernel, gamma}, taus, ntau, lambda, o, alpha, beta, info, status,
+                  static_cast<hipStream_t>(stream));
+  });
+}
+
+int kqr_fit_batch(int nprob, const float* const* X, const double* const* y, const int64_t* n, int64_t p,
+                  const double* tau, const double* lambda, int kernel, const double* gamma, const kqr_options* opt,
+                  double* const* alpha, double* beta, kqr_info* info, int* status, void* stream) {
+  return guarded([&] {
+    KQR_REQUIRE(X && y && n && tau && lambda && gamma && alpha && beta && status, "pointers must be non-null");
+    KQR_REQUIRE(nprob >= 1 && nprob <= 256, "need 1 <= nprob <= 256");
+    KQR_REQUIRE(p >= 1 && p <= 64, "need 1 <= p <= 64");
+    KQR_REQUIRE(kernel == KQR_RBF || kernel == KQR_LAPLACIAN, "kernel must be KQR_RBF or KQR_LAPLACIAN");
+    for (int i = 0; i < nprob; ++i) {
+      KQR_REQUIRE(X[i] && y[i] && alpha[i], "per-problem pointers must be non-null");
+      KQR_REQUIRE(n[i] >= 2, "need n_i >= 2");
+      KQR_REQUIRE(tau[i] > 0.0 && tau[i] < 1.0, "need 0 < tau_i < 1");
+      KQR_REQUIRE(std::isfinite(lambda[i]) && lambda[i] > 0.0, "lambda_i must be positive");
+      KQR_REQUIRE(std::isfinite(gamma[i]) && gamma[i] > 0.0, "gamma_i must be positive");
+    }
+    kqr_options o;
+    kqr_default_options(&o);
+    if (opt) o = *opt;
+    validate_options(o);
+    ensure_device();
+    fit_batch(nprob, X, y, n, int(p), KernelSpec{kernel, gamma[0]}, tau, lambda, gamma, o, alpha, beta, info, status,
+              static_cast<hipStream_t>(stream));
+  });
 }
 
 }  // extern "C"

@@ -1,0 +1,53 @@
+// The fit drivers: one problem, a batch of quantile levels on one K, and a
+// batch of independent problems.
+#pragma once
+
+#include "kmulti.h"
+#include "solver.h"
+
+namespace kqr {
+
+void validate_options(const kqr_options& o);  // fails with KQR_EINVAL
+
+// Kernel matrix (materialised or not) and RPCholesky factor of one problem.
+struct Prepared {
+  DevBuf K;
+  int64_t ldk = 0;
+  int dtype = KQR_FP32;
+  DevBuf F;
+  int64_t ldf = 4;
+  int64_t rank = 0;
+  double t_kbuild = 0.0, t_precond = 0.0;
+  KMat kmat() const { return KMat{K.ptr, dtype, ldk}; }
+};
+
+// Materialises K (per o.kmode / o.k_dtype) and builds F (fixed rank, the
+// Section 3 heuristic, or none).  `op` is created by the caller afterwards.
+Prepared prepare_fit(const float* X, int64_t n, int p, KernelSpec ks, const kqr_options& o, hipStream_t st);
+
+struct FitOutcome {
+  bool converged = false;
+  double beta = 0.0;
+  kqr_info info{};
+};
+
+// Runs Phase I, Phase II and the final residuals; copies alpha to alpha_out.
+FitOutcome run_fit(Operator& op, const Prepared& pr, const double* y, int64_t n, double tau, double lam,
+                   const kqr_options& o, double* alpha_out, hipStream_t st);
+
+// tau batch: every level shares K and F; fast K-applies of all levels are
+// coalesced into one K V launch on the matrix cores.
+void fit_multi_tau(const float* X, const double* y, int64_t n, int p, KernelSpec ks, const double* taus, int ntau,
+                   double lam, const kqr_options& o, double* alpha, double* beta, kqr_info* info, int* status,
+                   hipStream_t st);
+
+// independent problems: fast K-applies of all running problems go out in one
+// launch over (problem, row block) pairs.
+void fit_batch(int nprob, const float* const* X, const double* const* y, const int64_t* n, int p, KernelSpec ks,
+               const double* tau, const double* lam, const double* gamma, const kqr_options& o,
+               double* const* alpha, double* beta, kqr_info* info, int* status, hipStream_t st);
+
+std::vector<double> default_uniforms(uint64_t seed, int64_t count);
+double wall_seconds();
+
+}  // namespace kqr

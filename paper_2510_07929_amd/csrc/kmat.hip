@@ -490,6 +490,66 @@ void kernel_row(const KMat& km, const float* X, const float* sqn, int64_t n, int
   KQR_DISPATCH_P(p, krow_p, X, sqn, n, p, ks, s, out, st);
 }
 
+// ================================================================= skinny mat-vec
+// 16 lanes per row (4 rows per wave at a time, 4 such row slots per wave):
+// a lane reads 16-byte pieces of its row 64 columns apart, x sits in LDS, and
+// a 4-step shuffle reduction inside each 16-lane group finishes 4 rows at once.
+__global__ __launch_bounds__(256) void gemv_skinny_kernel(const float* __restrict__ A, int64_t lda, int64_t nrows,
+                                                          int ncols, const double* __restrict__ x,
+                                                          double* __restrict__ y) {
+  __shared__ double xs[1024 + 4];
+  for (int k = threadIdx.x; k < ncols; k += 256) xs[k] = x[k];
+  for (int k = ncols + threadIdx.x; k < ((ncols + 3) & ~3); k += 256) xs[k] = 0.0;
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g = lane >> 4, t = lane & 15;
+  const int64_t wrow0 = (int64_t(blockIdx.x) * 4 + wave) * 16;
+  const int nvec = ncols >> 2;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  const float* rows[4];
+#pragma unroll
+  for (int sl = 0; sl < 4; ++sl) {
+    const int64_t r = min(wrow0 + sl * 4 + g, nrows - 1);
+    rows[sl] = A + r * lda;
+  }
+  for (int c = t; c < nvec; c += 16) {
+    float4 v[4];
+#pragma unroll
+    for (int sl = 0; sl < 4; ++sl) v[sl] = reinterpret_cast<const float4*>(rows[sl])[c];
+    const double x0 = xs[4 * c], x1 = xs[4 * c + 1], x2 = xs[4 * c + 2], x3 = xs[4 * c + 3];
+#pragma unroll
+    for (int sl = 0; sl < 4; ++sl) {
+      acc[sl] = fma(double(v[sl].x), x0, acc[sl]);
+      acc[sl] = fma(double(v[sl].y), x1, acc[sl]);
+      acc[sl] = fma(double(v[sl].z), x2, acc[sl]);
+      acc[sl] = fma(double(v[sl].w), x3, acc[sl]);
+    }
+  }
+  for (int c = nvec * 4 + t; c < ncols; c += 16) {
+#pragma unroll
+    for (int sl = 0; sl < 4; ++sl) acc[sl] = fma(double(rows[sl][c]), xs[c], acc[sl]);
+  }
+#pragma unroll
+  for (int sl = 0; sl < 4; ++sl)
+#pragma unroll
+    for (int off = 8; off >= 1; off >>= 1) acc[sl] += __shfl_xor(acc[sl], off, 16);
+  if (t == 0) {
+#pragma unroll
+    for (int sl = 0; sl < 4; ++sl) {
+      const int64_t r = wrow0 + sl * 4 + g;
+      if (r < nrows) y[r] = acc[sl];
+    }
+  }
+}
+
+void gemv_skinny(const float* A, int64_t lda, int64_t nrows, int64_t ncols, const double* x, double* y,
+                 hipStream_t st) {
+  if (nrows <= 0) return;
+  if (ncols > 1024 || (lda & 3)) fail(KQR_EINVAL, "gemv_skinny: ncols <= 1024 and lda % 4 == 0 required");
+  gemv_skinny_kernel<<<dim3((unsigned)((nrows + 63) / 64)), 256, 0, st>>>(A, lda, nrows, int(ncols), x, y);
+  KQR_LAUNCH_CHECK();
+}
+
 // ================================================================= FP64 -> FP32
 __global__ void to_f32_kernel(const double* __restrict__ src, int64_t n, int m, int64_t lds,
                               float* __restrict__ dst, int64_t ldd) {

@@ -1,0 +1,40 @@
+// Batched kernel operators (K V on the matrix cores; many K_i v_i in one launch).
+#pragma once
+
+#include "kqr_internal.h"
+
+namespace kqr {
+
+// U[:, j] = K V[:, j] for j < m <= 16.  V16: n_pad x 16 FP32 row-major (rows >= n
+// and columns >= m zero); U: n x m FP64 (ld ldu); part: scratch of
+// segs * n * 16 doubles.
+void kapply_kv(const KMat& km, int64_t n, const float* V16, int m, double* U, int64_t ldu, double* part, int segs,
+               hipStream_t st);
+struct SrcTable16 {
+  const double* p[16];
+};
+struct DstTable16 {
+  double* p[16];
+};
+// V16[i][j] = float(src.p[j][i]) for j < m, zero elsewhere (rows up to n_pad)
+void kv_gather(SrcTable16 src, int m, int64_t n, int64_t n_pad, float* V16, hipStream_t st);
+// V16[i][j] = float(V[i ldv + j]) for j < m, zero elsewhere
+void kv_gather_strided(const double* V, int64_t ldv, int m, int64_t n, int64_t n_pad, float* V16, hipStream_t st);
+// dst.p[j][i] = U16[i][j]
+void kv_scatter(const double* U16, int m, int64_t n, DstTable16 dst, hipStream_t st);
+
+// One problem of an uneven batch.
+struct ProblemTask {
+  const void* K;  // n x ld, FP32 or BF16
+  int64_t ld;
+  int64_t n;
+  int dtype;
+  const float* v;  // n (FP32)
+  double* u;       // n (FP64)
+};
+int problem_blocks(int64_t n);  // workgroups one problem needs
+// One launch: u_t = K_t v_t for every task; first_block = exclusive prefix of problem_blocks.
+void kapply_problems(const ProblemTask* tasks_dev, int ntasks, const int* first_block_dev, int total_blocks,
+                     hipStream_t st);
+
+}  // namespace kqr

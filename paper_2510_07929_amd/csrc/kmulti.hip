@@ -1,0 +1,275 @@
+// Batched kernel operators:
+//  * K V for up to 16 right-hand sides on the matrix cores (one pass over K
+//    serves every column: the tau-batch of kqr_fit_multi_tau);
+//  * K_i v_i for many independent problems of different sizes in one launch
+//    (the uneven batch of kqr_fit_batch): workgroups are dealt out over the
+//    (problem, row block) pairs of all problems.
+#include "kqr_internal.h"
+#include "kmulti.h"
+
+#include <algorithm>
+
+namespace kqr {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+namespace {
+constexpr int kKC = 256;       // columns of K per LDS stage of V
+constexpr int kVpad = kKC + 8; // padded LDS row (bank spread)
+}  // namespace
+
+__device__ __forceinline__ uint16_t f2bf(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return uint16_t(u >> 16);
+}
+
+// U[seg] rows = K[rows, cols of segment] V[cols, 0:16].  Block = 4 waves, each
+// wave a 16-row strip.  V (row-major, 16 FP32 columns, rows padded with zeros
+// up to ld_rows) is staged transposed in LDS per kKC columns.  The MFMA
+// accumulator (FP32) is flushed into FP64 after every stage.
+//  FP32 K: v_mfma_f32_16x16x4f32, a lane loads 8 consecutive entries of its
+//          row (128 contiguous bytes per row over 4 lane groups) for 8 MFMAs.
+//  BF16 K: v_mfma_f32_16x16x32_bf16 with V split into hi + lo BF16 parts.
+template <bool BF16>
+__global__ __launch_bounds__(256) void kv_mfma_kernel(const void* __restrict__ K, int64_t ldk, int64_t n,
+                                                      int64_t ncols, const float* __restrict__ V,
+                                                      int64_t seg_cols, double* __restrict__ out) {
+  __shared__ float vs[BF16 ? 1 : 16][BF16 ? 1 : kVpad];
+  __shared__ uint16_t vh[BF16 ? 16 : 1][BF16 ? kVpad : 1];
+  __shared__ uint16_t vl[BF16 ? 16 : 1][BF16 ? kVpad : 1];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lg = lane >> 4;
+  const int64_t row0 = int64_t(blockIdx.x) * 64 + wave * 16;
+  const int64_t my_row = min(row0 + li, n - 1);
+  const int64_t c0 = int64_t(blockIdx.y) * seg_cols;
+  const int64_t c1 = min(ncols, c0 + seg_cols);
+  double acc64[4] = {0.0, 0.0, 0.0, 0.0};
+  const char* krow = static_cast<const char*>(K) + my_row * ldk * (BF16 ? 2 : 4);
+  for (int64_t cb = c0; cb < c1; cb += kKC) {
+    const int cnt = int(min<int64_t>(kKC, c1 - cb));
+    __syncthreads();
+    for (int e = threadIdx.x; e < kKC * 16; e += 256) {
+      const int kk = e >> 4, j = e & 15;
+      const float val = kk < cnt ? V[(cb + kk) * 16 + j] : 0.f;
+      if (BF16) {
+        const uint16_t h = f2bf(val);
+        vh[j][kk] = h;
+        vl[j][kk] = f2bf(val - __uint_as_float(uint32_t(h) << 16));
+      } else {
+        vs[j][kk] = val;
+      }
+    }
+    __syncthreads();
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    if (BF16) {
+      for (int kk = 0; kk < cnt; kk += 32) {
+        const int64_t col = cb + kk + 8 * lg;
+        bf16x8 a;
+        if (col + 8 <= ncols) {
+          a = *reinterpret_cast<const bf16x8*>(krow + col * 2);
+        } else {
+          const uint16_t* kr = reinterpret_cast<const uint16_t*>(krow);
+          uint16_t tmp[8];
+#pragma unroll
+          for (int e = 0; e < 8; ++e) tmp[e] = (col + e < ncols) ? kr[col + e] : uint16_t(0);
+          a = *reinterpret_cast<const bf16x8*>(tmp);
+        }
+        const bf16x8 bh = *reinterpret_cast<const bf16x8*>(&vh[li][kk + 8 * lg]);
+        const bf16x8 bl = *reinterpret_cast<const bf16x8*>(&vl[li][kk + 8 * lg]);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bh, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bl, acc, 0, 0, 0);
+      }
+    } else {
+      for (int kk = 0; kk < cnt; kk += 32) {
+        const int64_t col = cb + kk + 8 * lg;
+        float a[8];
+        if (col + 8 <= ncols) {
+          const f32x4 a0 = *reinterpret_cast<const f32x4*>(krow + col * 4);
+          const f32x4 a1 = *reinterpret_cast<const f32x4*>(krow + col * 4 + 16);
+          a[0] = a0[0]; a[1] = a0[1]; a[2] = a0[2]; a[3] = a0[3];
+          a[4] = a1[0]; a[5] = a1[1]; a[6] = a1[2]; a[7] = a1[3];
+        } else {
+          const float* kr = reinterpret_cast<const float*>(krow);
+#pragma unroll
+          for (int e = 0; e < 8; ++e) a[e] = (col + e < ncols) ? kr[col + e] : 0.f;
+        }
+        const f32x4 b0 = *reinterpret_cast<const f32x4*>(&vs[li][kk + 8 * lg]);
+        const f32x4 b1 = *reinterpret_cast<const f32x4*>(&vs[li][kk + 8 * lg + 4]);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[q], b0[q], acc, 0, 0, 0);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[4 + q], b1[q], acc, 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc64[r] += double(acc[r]);
+  }
+  // accumulator layout of a 16x16 MFMA: lane holds rows 4*(lane/16)+r, column lane%16
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int64_t row = row0 + 4 * lg + r;
+    if (row < n) out[(int64_t(blockIdx.y) * n + row) * 16 + li] = acc64[r];
+  }
+}
+
+__global__ void kv_reduce_kernel(const double* __restrict__ part, int nseg, int64_t n, int m, double* __restrict__ U,
+                                 int64_t ldu) {
+  const int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (t >= n * 16) return;
+  const int64_t i = t >> 4;
+  const int j = int(t & 15);
+  if (j >= m) return;
+  double s = 0.0;
+  for (int k = 0; k < nseg; ++k) s += part[int64_t(k) * n * 16 + t];
+  U[i * ldu + j] = s;
+}
+
+void kapply_kv(const KMat& km, int64_t n, const float* V16, int m, double* U, int64_t ldu, double* part, int segs,
+               hipStream_t st) {
+  if (n <= 0) return;
+  segs = std::max(1, segs);
+  int64_t seg_cols = (n + segs - 1) / segs;
+  seg_cols = (seg_cols + kKC - 1) / kKC * kKC;
+  segs = int((n + seg_cols - 1) / seg_cols);
+  const dim3 grid((unsigned)((n + 63) / 64), (unsigned)segs);
+  if (km.dtype == KQR_BF16)
+    kv_mfma_kernel<true><<<grid, 256, 0, st>>>(km.K, km.ld, n, n, V16, seg_cols, part);
+  else
+    kv_mfma_kernel<false><<<grid, 256, 0, st>>>(km.K, km.ld, n, n, V16, seg_cols, part);
+  KQR_LAUNCH_CHECK();
+  kv_reduce_kernel<<<dim3((unsigned)((n * 16 + 255) / 256)), 256, 0, st>>>(part, segs, n, m, U, ldu);
+  KQR_LAUNCH_CHECK();
+}
+
+// V16[i][j] = float(src_j[i]) for j < m, 0 for m <= j < 16 (rows < n_pad; rows >= n are 0)
+__global__ void kv_gather_kernel(SrcTable16 src, int m, int64_t n, int64_t n_pad, float* __restrict__ V16) {
+  const int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (t >= n_pad * 16) return;
+  const int64_t i = t >> 4;
+  const int j = int(t & 15);
+  V16[t] = (j < m && i < n) ? float(src.p[j][i]) : 0.f;
+}
+
+// dst_j[i] = U[i][j]
+__global__ void kv_scatter_kernel(const double* __restrict__ U, int m, int64_t n, DstTable16 dst) {
+  const int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (t >= n * 16) return;
+  const int64_t i = t >> 4;
+  const int j = int(t & 15);
+  if (j < m) dst.p[j][i] = U[t];
+}
+
+__global__ void kv_gather_strided_kernel(const double* __restrict__ V, int64_t ldv, int m, int64_t n, int64_t n_pad,
+                                         float* __restrict__ V16) {
+  const int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (t >= n_pad * 16) return;
+  const int64_t i = t >> 4;
+  const int j = int(t & 15);
+  V16[t] = (j < m && i < n) ? float(V[i * ldv + j]) : 0.f;
+}
+
+void kv_gather_strided(const double* V, int64_t ldv, int m, int64_t n, int64_t n_pad, float* V16, hipStream_t st) {
+  kv_gather_strided_kernel<<<dim3((unsigned)((n_pad * 16 + 255) / 256)), 256, 0, st>>>(V, ldv, m, n, n_pad, V16);
+  KQR_LAUNCH_CHECK();
+}
+
+void kv_gather(SrcTable16 src, int m, int64_t n, int64_t n_pad, float* V16, hipStream_t st) {
+  kv_gather_kernel<<<dim3((unsigned)((n_pad * 16 + 255) / 256)), 256, 0, st>>>(src, m, n, n_pad, V16);
+  KQR_LAUNCH_CHECK();
+}
+
+void kv_scatter(const double* U16, int m, int64_t n, DstTable16 dst, hipStream_t st) {
+  kv_scatter_kernel<<<dim3((unsigned)((n * 16 + 255) / 256)), 256, 0, st>>>(U16, m, n, dst);
+  KQR_LAUNCH_CHECK();
+}
+
+// ----------------------------------------------------------------- many problems, one launch
+// Task t: K_t (n_t x ld_t, FP32 or BF16), v_t (FP32, n_t), u_t (FP64, n_t).
+// first_block[t] = prefix sum of row blocks (8 rows per wave, 4 waves per block).
+__global__ __launch_bounds__(256) void kapply_problems_kernel(const ProblemTask* __restrict__ tasks, int ntasks,
+                                                              const int* __restrict__ first_block) {
+  // locate the task of this block
+  int lo = 0, hi = ntasks - 1;
+  const int b = blockIdx.x;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (first_block[mid] <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  const ProblemTask tk = tasks[lo];
+  constexpr int ROWS = 8;
+  const int lane = threadIdx.x & 63;
+  const int64_t row0 = (int64_t(b - first_block[lo]) * 4 + (threadIdx.x >> 6)) * ROWS;
+  if (row0 >= tk.n) return;
+  const bool bf = tk.dtype == KQR_BF16;
+  const int vec = bf ? 8 : 4;
+  const int64_t nchunk = tk.n / vec;
+  double acc[ROWS];
+#pragma unroll
+  for (int r = 0; r < ROWS; ++r) acc[r] = 0.0;
+  const char* base = static_cast<const char*>(tk.K);
+  const int64_t rstride = tk.ld * (bf ? 2 : 4);
+  for (int64_t c = lane; c < nchunk; c += 64) {
+    float vv[8];
+    const float* vp = tk.v + c * vec;
+    const float4 t0 = *reinterpret_cast<const float4*>(vp);
+    vv[0] = t0.x; vv[1] = t0.y; vv[2] = t0.z; vv[3] = t0.w;
+    if (bf) {
+      const float4 t1 = *reinterpret_cast<const float4*>(vp + 4);
+      vv[4] = t1.x; vv[5] = t1.y; vv[6] = t1.z; vv[7] = t1.w;
+    }
+    u32x4 kk[ROWS];
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) {
+      const int64_t rr = min(row0 + r, tk.n - 1);
+      kk[r] = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(base + rr * rstride) + c);
+    }
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) {
+      float a = 0.f;
+      if (bf) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const uint32_t w = kk[r][e >> 1];
+          a = fmaf(__uint_as_float((e & 1) ? (w & 0xffff0000u) : (w << 16)), vv[e], a);
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) a = fmaf(__uint_as_float(kk[r][e]), vv[e], a);
+      }
+      acc[r] += double(a);
+    }
+  }
+  const int64_t col = nchunk * vec + lane;
+  if (col < tk.n) {
+    const double ve = tk.v[col];
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) {
+      const int64_t rr = min(row0 + r, tk.n - 1);
+      const float ke = bf ? __uint_as_float(uint32_t(reinterpret_cast<const uint16_t*>(base + rr * rstride)[col]) << 16)
+                          : reinterpret_cast<const float*>(base + rr * rstride)[col];
+      acc[r] = fma(double(ke), ve, acc[r]);
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < ROWS; ++r)
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) acc[r] += __shfl_xor(acc[r], off);
+#pragma unroll
+  for (int r = 0; r < ROWS; ++r)
+    if (lane == r && row0 + r < tk.n) tk.u[row0 + r] = acc[r];
+}
+
+int problem_blocks(int64_t n) { return int((n + 31) / 32); }
+
+void kapply_problems(const ProblemTask* tasks_dev, int ntasks, const int* first_block_dev, int total_blocks,
+                     hipStream_t st) {
+  if (ntasks <= 0 || total_blocks <= 0) return;
+  kapply_problems_kernel<<<total_blocks, 256, 0, st>>>(tasks_dev, ntasks, first_block_dev);
+  KQR_LAUNCH_CHECK();
+}
+
+}  // namespace kqr

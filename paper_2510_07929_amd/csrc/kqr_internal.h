@@ -101,6 +101,10 @@ void kapply_dense(const KMat& km, int64_t nrows, int64_t ncols, const float* v32
 void kapply_otf(const float* Xr, const float* sqr, int64_t nr, const float* Xc, const float* sqc,
                 int64_t nc, int p, KernelSpec ks, const double* v64, double* u, int64_t ldu,
                 double out_scale, double out_shift, hipStream_t st);
+// y = A x for a skinny FP32 matrix A (nrows x ncols, ncols <= 1024, lda a
+// multiple of 4) and FP64 x, y; FP64 products and sums.
+void gemv_skinny(const float* A, int64_t lda, int64_t nrows, int64_t ncols, const double* x, double* y,
+                 hipStream_t st);
 // One row of K: out[j] = k(x_s, x_j) in FP64 (from a materialised row or from X).
 void kernel_row(const KMat& km, const float* X, const float* sqn, int64_t n, int p, KernelSpec ks,
                 int64_t s, double* out, hipStream_t st);

@@ -186,11 +186,6 @@ std::vector<int64_t> rpcholesky(const KMat& km, const float* X, const float* sqn
   KQR_LAUNCH_CHECK();
   const float ng = -float(ks.gamma) * kLog2e;
   const bool lap = ks.kind == KQR_LAPLACIAN;
-  const KMat fm{F, KQR_FP32, ldf};
-  ApplyShape sh;
-  sh.rows = 8;
-  sh.unroll = 1;
-  sh.segs = 1;
   for (int64_t i = 0; i < rank; ++i) {
     rpc_select_kernel<<<1, 64, 0, st>>>(d.as<double>(), n, chunk, bsum.as<double>(), kSelBlocks, uniforms[i],
                                         int(i), piv.as<int64_t>(), state.as<double>());
@@ -199,7 +194,7 @@ std::vector<int64_t> rpcholesky(const KMat& km, const float* X, const float* sqn
       rpc_pivrow_kernel<<<(unsigned)((i + 255) / 256), 256, 0, st>>>(F, ldf, int(i), piv.as<int64_t>(), int(i),
                                                                       fs.as<double>());
       KQR_LAUNCH_CHECK();
-      kapply_dense(fm, n, i, nullptr, fs.as<double>(), u.as<double>(), 1, true, st, &sh);
+      gemv_skinny(F, ldf, n, i, fs.as<double>(), u.as<double>(), st);
     }
     rpc_update_kernel<<<kSelBlocks, 256, 0, st>>>(km, X, lap ? nullptr : sqn, p, lap ? 1 : 0, ng, F, n, ldf, int(i),
                                                   piv.as<int64_t>(), int(i), u.as<double>(), d.as<double>(), chunk,

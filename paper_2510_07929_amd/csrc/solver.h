@@ -7,10 +7,25 @@
 
 namespace kqr {
 
+// Coalesces the fast K-applies of several solvers running in their own host
+// threads into one launch (see batch.hip).  submit() blocks until the batch
+// holding the request has been enqueued; the caller's stream then waits for it.
+class ApplyBatcher {
+ public:
+  virtual ~ApplyBatcher() = default;
+  virtual void submit(int slot, const double* v, double* out, hipStream_t st) = 0;
+  virtual void leave(int slot) = 0;
+};
+
 // The kernel operator K v: materialised (FP32 / BF16 storage) or on the fly.
 class Operator {
  public:
   Operator(const float* X, int64_t n, int p, KernelSpec ks, KMat km, hipStream_t st);
+  // Route fast applies through a batcher (slot = this solver's index).
+  void attach_batcher(ApplyBatcher* b, int slot) {
+    batcher_ = b;
+    slot_ = slot;
+  }
   // Fast apply: FP32 products (from v32 when given, else a rounded copy of v).
   void apply_fast(const double* v, const float* v32, double* u, hipStream_t st);
   // Exact apply: FP32 entries (stored FP32 or recomputed) with FP64 vector and sums.
@@ -40,6 +55,8 @@ class Operator {
   int64_t calls_ = 0;
   bool profile_ = false;
   std::vector<Span> spans_;
+  ApplyBatcher* batcher_ = nullptr;
+  int slot_ = -1;
 };
 
 struct PcgBuffers {

@@ -55,6 +55,10 @@ void Operator::profile_totals(int64_t& nfast, double& tfast, int64_t& nexact, do
 
 void Operator::apply_fast(const double* v, const float* v32, double* u, hipStream_t st) {
   ++calls_;
+  if (batcher_) {
+    batcher_->submit(slot_, v, u, st);
+    return;
+  }
   if (km_.K) {
     if (!v32) {
       to_f32(v, n_, 1, 1, v32_.as<float>(), 1, st);

@@ -80,7 +80,7 @@ class Woodbury {
   int64_t n_, r_, ldf_, R1_;
   int64_t ldc_;
   const double* L_ = nullptr;
-  DevBuf C_, W_, WT_, G_, part_, g_, Fs_, t_, y_, s_, flag_, idx_, cnt_;
+  DevBuf C_, W_, WT_, T_, G_, part_, g_, Fs_, t_, y_, s_, flag_, idx_, cnt_;
   HostPinned hbuf_;
   int nsplit_ = 1;
 };

@@ -9,11 +9,13 @@
 //    lambda eps_t elsewhere, so U^T L^{-1} U = G_all / l_out +
 //    (1/l_in - 1/l_out) U_E^T U_E with G_all = U^T U formed once per fit; a
 //    Newton step then only sums over the |E| interior rows.
-//  * C = Lc Lc^T by a blocked Cholesky; W = Lc^{-1} is formed explicitly, so
-//    an application needs two triangular mat-vecs (many workgroups) instead
-//    of sequential substitutions, and s = W^T (W t) stays a symmetric
-//    positive definite map for any nonsingular W.
-//  * U s uses the streamed mat-vec of the K-apply with F as the matrix.
+//  * C = Lc Lc^T by a blocked right-looking Cholesky (64-column panels; the
+//    diagonal block is factored by one wave with one row per lane);
+//    W = Lc^{-1} is formed explicitly by recursive doubling
+//    (W21 = -W22 L21 W11), so an application needs two triangular mat-vecs
+//    over many workgroups instead of sequential substitutions, and
+//    s = W^T (W t) stays a symmetric positive definite map.
+//  * U s uses a skinny streamed mat-vec with F as the matrix.
 #include "vec.h"
 
 #include <algorithm>
@@ -22,10 +24,9 @@
 namespace kqr {
 
 namespace {
-constexpr int kT = 64;        // SYRK / update tile edge
+constexpr int kT = 64;        // SYRK / update / GEMM tile edge
 constexpr int kSubRows = 32;  // rows staged per LDS step of the SYRK
-constexpr int kCb = 32;       // Cholesky block
-constexpr int kIb = 64;       // inverse block
+constexpr int kNb = 64;       // Cholesky panel width = inverse leaf block
 constexpr int kGtBlocks = 512;
 constexpr int kGtStage = 256;
 }  // namespace
@@ -163,95 +164,103 @@ __global__ __launch_bounds__(64) void flag_scatter_kernel(const uint8_t* __restr
 }
 
 // ---------------------------------------------------------------- blocked Cholesky (lower)
-// Diagonal block kCb x kCb in LDS, one wave.
+// Diagonal block (nb <= 64): one wave, lane l holds row l in registers.  At
+// column j lane j takes the square root of its (already updated) diagonal,
+// every lane scales its entry of column j, and lane l updates its entries
+// k in (j, l] with the column-j entries of lanes k (shuffles).
 __global__ __launch_bounds__(64) void chol_diag_kernel(double* __restrict__ C, int64_t ldc, int kb, int nb,
                                                        int* __restrict__ flag) {
-  __shared__ double A[kCb][kCb + 1];
-  const int t = threadIdx.x;
-  for (int e = t; e < kCb * kCb; e += 64) {
-    const int i = e / kCb, k = e % kCb;
-    A[i][k] = (i < nb && k <= i) ? C[int64_t(kb + i) * ldc + kb + k] : 0.0;
-  }
-  __syncthreads();
-  for (int j = 0; j < nb; ++j) {
-    if (t == 0) {
-      double piv = A[j][j];
-      if (!(piv > 0.0) || !isfinite(piv)) {
-        flag[0] = 1;
-        piv = 1e-300;
-      }
-      A[j][j] = sqrt(piv);
+  const int l = threadIdx.x;
+  double a[kNb];
+  const double* row = C + int64_t(kb + (l < nb ? l : 0)) * ldc + kb;
+#pragma unroll
+  for (int k = 0; k < kNb; ++k) a[k] = (l < nb && k <= l && k < nb) ? row[k] : (k == l ? 1.0 : 0.0);
+  bool bad = false;
+#pragma unroll
+  for (int j = 0; j < kNb; ++j) {
+    double piv = __shfl(a[j], j);
+    if (!(piv > 0.0) || !isfinite(piv)) {
+      bad = true;
+      piv = 1e-300;
     }
-    __syncthreads();
-    if (t > j && t < nb) A[t][j] /= A[j][j];
-    __syncthreads();
-    for (int e = t; e < kCb * kCb; e += 64) {
-      const int l = e / kCb, k = e % kCb;
-      if (k > j && k <= l && l < nb) A[l][k] = fma(-A[l][j], A[k][j], A[l][k]);
+    const double d = sqrt(piv);
+    if (l == j) a[j] = d;
+    if (l > j) a[j] /= d;
+#pragma unroll
+    for (int k = j + 1; k < kNb; ++k) {
+      const double ckj = __shfl(a[j], k);
+      if (l >= k) a[k] = fma(-a[j], ckj, a[k]);
     }
-    __syncthreads();
   }
-  for (int e = t; e < kCb * kCb; e += 64) {
-    const int i = e / kCb, k = e % kCb;
-    if (i < nb && k <= i) C[int64_t(kb + i) * ldc + kb + k] = A[i][k];
+  if (bad && l == 0 && nb > 0) flag[0] = 1;
+  if (l < nb) {
+    double* w = C + int64_t(kb + l) * ldc + kb;
+#pragma unroll
+    for (int k = 0; k < kNb; ++k)
+      if (k <= l) w[k] = a[k];
   }
 }
 
-// Panel: rows i >= kb+nb solve x L_kk^T = C[i, kb:kb+nb].  A row is held by
-// 32 lanes (lane k owns x_k); column j is finished by lane j and broadcast.
+// Panel: rows i >= kb+nb solve x L_kk^T = C[i, kb:kb+nb].  One wave per row,
+// lane k owns x_k; column j is finished by lane j and broadcast.
 __global__ __launch_bounds__(256) void chol_panel_kernel(double* __restrict__ C, int64_t ldc, int kb, int nb,
                                                          int R1) {
-  __shared__ double Lk[kCb][kCb + 1];
-  for (int e = threadIdx.x; e < kCb * kCb; e += 256) {
-    const int i = e / kCb, k = e % kCb;
+  __shared__ double Lk[kNb][kNb + 1];
+  for (int e = threadIdx.x; e < kNb * kNb; e += 256) {
+    const int i = e / kNb, k = e % kNb;
     Lk[i][k] = (i < nb && k <= i) ? C[int64_t(kb + i) * ldc + kb + k] : (i == k ? 1.0 : 0.0);
   }
   __syncthreads();
-  const int k = threadIdx.x & (kCb - 1);
-  const int64_t i = int64_t(kb) + nb + int64_t(blockIdx.x) * (256 / kCb) + (threadIdx.x / kCb);
+  const int k = threadIdx.x & 63;
+  const int64_t i = int64_t(kb) + nb + int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
   const bool ok = i < R1;
   double* row = C + (ok ? i : 0) * ldc + kb;
   double x = (ok && k < nb) ? row[k] : 0.0;
-  for (int j = 0; j < kCb; ++j) {
+  for (int j = 0; j < kNb; ++j) {
     if (k == j) x /= Lk[j][j];
-    const double xj = __shfl(x, j, kCb);
+    const double xj = __shfl(x, j);
     if (k > j) x = fma(-xj, Lk[k][j], x);
   }
   if (ok && k < nb) row[k] = x;
 }
 
-// Trailing update of the lower part: C[i][j] -= sum_k P[i][k] P[j][k], j <= i.
+// Trailing update of the lower part: C[i][j] -= sum_k P[i][k] P[j][k], j <= i,
+// with the 64-wide panel staged 32 columns at a time.
 __global__ __launch_bounds__(256) void chol_update_kernel(double* __restrict__ C, int64_t ldc, int kb, int nb,
                                                           int R1) {
-  __shared__ double Pi[kT][kCb + 1];
-  __shared__ double Pj[kT][kCb + 1];
+  __shared__ double Pi[kT][33];
+  __shared__ double Pj[kT][33];
   int ta, tb;
   tile_coords(blockIdx.x, ta, tb);
   const int base = kb + nb;
   const int i0 = base + ta * kT, j0 = base + tb * kT;
-  for (int e = threadIdx.x; e < kT * kCb; e += 256) {
-    const int a = e / kCb, k = e % kCb;
-    Pi[a][k] = (i0 + a < R1 && k < nb) ? C[int64_t(i0 + a) * ldc + kb + k] : 0.0;
-    Pj[a][k] = (j0 + a < R1 && k < nb) ? C[int64_t(j0 + a) * ldc + kb + k] : 0.0;
-  }
-  __syncthreads();
   const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
   double acc[4][4];
 #pragma unroll
   for (int p = 0; p < 4; ++p)
 #pragma unroll
     for (int q = 0; q < 4; ++q) acc[p][q] = 0.0;
+  for (int h = 0; h < nb; h += 32) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < kT * 32; e += 256) {
+      const int a = e / 32, k = e % 32;
+      const bool kk = h + k < nb;
+      Pi[a][k] = (i0 + a < R1 && kk) ? C[int64_t(i0 + a) * ldc + kb + h + k] : 0.0;
+      Pj[a][k] = (j0 + a < R1 && kk) ? C[int64_t(j0 + a) * ldc + kb + h + k] : 0.0;
+    }
+    __syncthreads();
 #pragma unroll 4
-  for (int k = 0; k < kCb; ++k) {
-    double av[4], bv[4];
+    for (int k = 0; k < 32; ++k) {
+      double av[4], bv[4];
 #pragma unroll
-    for (int p = 0; p < 4; ++p) av[p] = Pi[ty * 4 + p][k];
+      for (int p = 0; p < 4; ++p) av[p] = Pi[ty * 4 + p][k];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) bv[q] = Pj[tx * 4 + q][k];
+      for (int q = 0; q < 4; ++q) bv[q] = Pj[tx * 4 + q][k];
 #pragma unroll
-    for (int p = 0; p < 4; ++p)
+      for (int p = 0; p < 4; ++p)
 #pragma unroll
-      for (int q = 0; q < 4; ++q) acc[p][q] = fma(av[p], bv[q], acc[p][q]);
+        for (int q = 0; q < 4; ++q) acc[p][q] = fma(av[p], bv[q], acc[p][q]);
+    }
   }
 #pragma unroll
   for (int p = 0; p < 4; ++p)
@@ -263,95 +272,118 @@ __global__ __launch_bounds__(256) void chol_update_kernel(double* __restrict__ C
 }
 
 // ---------------------------------------------------------------- W = Lc^{-1}
-// Inverse of each kIb x kIb diagonal block; lane j forms column j by forward
-// substitution.  Blocks are independent (one workgroup each).
+// Inverse of each 64 x 64 diagonal block; lane j forms column j by forward
+// substitution.  Blocks are independent (one workgroup each).  W must be zero
+// outside the blocks written here before the doubling steps run.
 __global__ __launch_bounds__(64) void trinv_diag_kernel(const double* __restrict__ C, int64_t ldc, int R1,
-                                                        double* __restrict__ W, double* __restrict__ WT) {
-  __shared__ double Lk[kIb][kIb + 1];
-  __shared__ double X[kIb][kIb + 1];
-  const int kb = blockIdx.x * kIb;
-  const int nb = min(kIb, R1 - kb);
+                                                        double* __restrict__ W) {
+  __shared__ double Lk[kNb][kNb + 1];
+  __shared__ double X[kNb][kNb + 1];
+  const int kb = blockIdx.x * kNb;
+  const int nb = min(kNb, R1 - kb);
   const int j = threadIdx.x;
-  for (int e = j; e < kIb * kIb; e += 64) {
-    const int i = e / kIb, k = e % kIb;
+  for (int e = j; e < kNb * kNb; e += 64) {
+    const int i = e / kNb, k = e % kNb;
     Lk[i][k] = (i < nb && k <= i) ? C[int64_t(kb + i) * ldc + kb + k] : (i == k ? 1.0 : 0.0);
   }
   __syncthreads();
-  for (int i = 0; i < kIb; ++i) {
+  for (int i = 0; i < kNb; ++i) {
     double s = (i == j) ? 1.0 : 0.0;
     for (int k = j; k < i; ++k) s = fma(-Lk[i][k], X[k][j], s);
     X[i][j] = (i >= j) ? s / Lk[i][i] : 0.0;
   }
   __syncthreads();
-  for (int e = j; e < kIb * kIb; e += 64) {
-    const int i = e / kIb, k = e % kIb;
-    if (i < nb && k < nb) {
-      W[int64_t(kb + i) * ldc + kb + k] = X[i][k];
-      WT[int64_t(kb + k) * ldc + kb + i] = X[i][k];
-    }
+  for (int e = j; e < kNb * kNb; e += 64) {
+    const int i = e / kNb, k = e % kNb;
+    if (i < nb && k < nb) W[int64_t(kb + i) * ldc + kb + k] = X[i][k];
   }
 }
 
-// Block row bi (> 0): W_ik = -W_ii sum_{m=k}^{i-1} L_im W_mk for the column
-// block k = blockIdx.x < bi.  W blocks of rows < bi are final.
-__global__ __launch_bounds__(256) void trinv_row_kernel(const double* __restrict__ C, int64_t ldc, int R1, int bi,
-                                                        double* __restrict__ W, double* __restrict__ WT) {
-  __shared__ double A[kIb][kIb + 1];
-  __shared__ double B[kIb][kIb + 1];
-  const int bk = blockIdx.x;
-  const int i0 = bi * kIb, k0 = bk * kIb;
+// One doubling level with blocks of s rows: for every pair (top = [i0, i0+s),
+// bottom = [i0+s, min(i0+2s, R1))), computes Out[bottom, top] =
+// alpha * A[bottom, A-cols] * B[B-rows, top] where
+//   stage 0: A = Lc[bottom, top]   (K = s),        B = W[top, top],   Out = T
+//   stage 1: A = W[bottom, bottom] (K = |bottom|),  B = T[bottom, top], Out = W (alpha = -1)
+// Grid: (pair, output tile); 64 x 64 tiles, K staged 32 at a time.
+__global__ __launch_bounds__(256) void trinv_level_kernel(const double* __restrict__ Lc, const double* __restrict__ W,
+                                                          const double* __restrict__ T, double* __restrict__ out,
+                                                          int64_t ldc, int R1, int s, int stage, int tiles_per_pair) {
+  __shared__ double As[kT][33];
+  __shared__ double Bs[32][kT + 1];
+  const int pair = blockIdx.x / tiles_per_pair;
+  const int tile = blockIdx.x % tiles_per_pair;
+  const int i0 = pair * 2 * s;
+  const int bot0 = i0 + s;
+  const int bot_len = min(s, R1 - bot0);
+  if (bot_len <= 0) return;
+  const int tiles_n = s / kT;  // columns of the output block (top) in tiles
+  const int tm = tile / tiles_n, tn = tile % tiles_n;
+  const int r0 = tm * kT;  // row offset inside bottom
+  const int c0 = tn * kT;  // column offset inside top
+  if (r0 >= bot_len) return;
+  const int K = stage == 0 ? s : bot_len;
   const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
   double acc[4][4];
 #pragma unroll
   for (int p = 0; p < 4; ++p)
 #pragma unroll
     for (int q = 0; q < 4; ++q) acc[p][q] = 0.0;
-  // T = sum_m L_im W_mk
-  for (int bm = bk; bm < bi; ++bm) {
-    const int m0 = bm * kIb;
+  for (int kb = 0; kb < K; kb += 32) {
     __syncthreads();
-    for (int e = threadIdx.x; e < kIb * kIb; e += 256) {
-      const int a = e / kIb, b = e % kIb;
-      A[a][b] = (i0 + a < R1) ? C[int64_t(i0 + a) * ldc + m0 + b] : 0.0;                    // L_im (full block, m < i)
-      B[a][b] = (m0 + a < R1 && k0 + b <= m0 + a) ? W[int64_t(m0 + a) * ldc + k0 + b] : 0.0;  // W_mk
+    for (int e = threadIdx.x; e < kT * 32; e += 256) {
+      const int a = e / 32, k = e % 32;
+      const int row = r0 + a, kk = kb + k;
+      double v = 0.0;
+      if (row < bot_len && kk < K) {
+        v = stage == 0 ? Lc[int64_t(bot0 + row) * ldc + i0 + kk] : W[int64_t(bot0 + row) * ldc + bot0 + kk];
+      }
+      As[a][k] = v;
+    }
+    for (int e = threadIdx.x; e < 32 * kT; e += 256) {
+      const int k = e / kT, b = e % kT;
+      const int kk = kb + k, col = c0 + b;
+      double v = 0.0;
+      if (kk < K) v = stage == 0 ? W[int64_t(i0 + kk) * ldc + i0 + col] : T[int64_t(bot0 + kk) * ldc + i0 + col];
+      Bs[k][b] = v;
     }
     __syncthreads();
 #pragma unroll 4
-    for (int kk = 0; kk < kIb; ++kk) {
+    for (int k = 0; k < 32; ++k) {
       double av[4], bv[4];
 #pragma unroll
-      for (int p = 0; p < 4; ++p) av[p] = A[ty * 4 + p][kk];
+      for (int p = 0; p < 4; ++p) av[p] = As[ty * 4 + p][k];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) bv[q] = B[kk][tx * 4 + q];
+      for (int q = 0; q < 4; ++q) bv[q] = Bs[k][tx * 4 + q];
 #pragma unroll
       for (int p = 0; p < 4; ++p)
 #pragma unroll
         for (int q = 0; q < 4; ++q) acc[p][q] = fma(av[p], bv[q], acc[p][q]);
     }
   }
-  // W_ik = -W_ii T
-  __syncthreads();
-#pragma unroll
-  for (int p = 0; p < 4; ++p)
-#pragma unroll
-    for (int q = 0; q < 4; ++q) B[ty * 4 + p][tx * 4 + q] = acc[p][q];
-  for (int e = threadIdx.x; e < kIb * kIb; e += 256) {
-    const int a = e / kIb, b = e % kIb;
-    A[a][b] = (i0 + a < R1 && i0 + b < R1 && b <= a) ? W[int64_t(i0 + a) * ldc + i0 + b] : 0.0;
-  }
-  __syncthreads();
+  const double alpha = stage == 0 ? 1.0 : -1.0;
 #pragma unroll
   for (int p = 0; p < 4; ++p)
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const int a = ty * 4 + p, b = tx * 4 + q;
-      double s = 0.0;
-      for (int kk = 0; kk <= a; ++kk) s = fma(A[a][kk], B[kk][b], s);
-      if (i0 + a < R1) {
-        W[int64_t(i0 + a) * ldc + k0 + b] = -s;
-        WT[int64_t(k0 + b) * ldc + i0 + a] = -s;
-      }
+      const int row = r0 + ty * 4 + p, col = c0 + tx * 4 + q;
+      if (row < bot_len) out[int64_t(bot0 + row) * ldc + i0 + col] = alpha * acc[p][q];
     }
+}
+
+// WT = W^T (lower triangle of W, R1 x R1)
+__global__ void transpose_lower_kernel(const double* __restrict__ W, int64_t ldc, int R1, double* __restrict__ WT) {
+  __shared__ double tileb[32][33];
+  const int bi = blockIdx.y * 32, bj = blockIdx.x * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8 threads
+  for (int k = ty; k < 32; k += 8) {
+    const int i = bi + k, j = bj + tx;
+    tileb[k][tx] = (i < R1 && j < R1 && j <= i) ? W[int64_t(i) * ldc + j] : 0.0;
+  }
+  __syncthreads();
+  for (int k = ty; k < 32; k += 8) {
+    const int j = bj + k, i = bi + tx;  // WT[j][i] = W[i][j]
+    if (i < R1 && j < R1) WT[int64_t(j) * ldc + i] = tileb[tx][k];
+  }
 }
 
 // ---------------------------------------------------------------- apply
@@ -404,12 +436,29 @@ __global__ __launch_bounds__(256) void wood_gt_kernel(const float* __restrict__ 
   }
 }
 
-__global__ void wood_treduce_kernel(const double* __restrict__ part, int nblk, int R1, double* __restrict__ t) {
-  const int a = blockIdx.x * blockDim.x + threadIdx.x;
-  if (a >= R1) return;
-  double s = 0.0;
-  for (int b = 0; b < nblk; ++b) s += part[int64_t(b) * R1 + a];
-  t[a] = s;
+// t[a] = sum_b part[b][a]: a block per 64 columns, 16 thread rows split the
+// partials, then a fixed-order sum over the 16 rows.
+__global__ __launch_bounds__(1024) void wood_treduce_kernel(const double* __restrict__ part, int nblk, int R1,
+                                                            double* __restrict__ t) {
+  __shared__ double sh[16][65];
+  const int ca = threadIdx.x & 63, rb = threadIdx.x >> 6;
+  const int a = blockIdx.x * 64 + ca;
+  double s0 = 0.0, s1 = 0.0;
+  if (a < R1) {
+    int b = rb;
+    for (; b + 16 < nblk; b += 32) {
+      s0 += part[int64_t(b) * R1 + a];
+      s1 += part[int64_t(b + 16) * R1 + a];
+    }
+    for (; b < nblk; b += 16) s0 += part[int64_t(b) * R1 + a];
+  }
+  sh[rb][ca] = s0 + s1;
+  __syncthreads();
+  if (rb == 0 && a < R1) {
+    double s = 0.0;
+    for (int k = 0; k < 16; ++k) s += sh[k][ca];
+    t[a] = s;
+  }
 }
 
 // out[i] = sum_{k in [lo(i), hi(i)]} M[i][k] x[k]  for a triangular M (one wave per row).
@@ -461,6 +510,7 @@ Woodbury::Woodbury(const float* F, int64_t n, int64_t r, int64_t ldf)
   C_.alloc(core);
   W_.alloc(core);
   WT_.alloc(core);
+  T_.alloc(core);
   const int nt = int((R1_ + kT - 1) / kT);
   const int ntile = nt * (nt + 1) / 2;
   nsplit_ = std::max(1, std::min(32, 1024 / ntile));
@@ -500,26 +550,38 @@ bool Woodbury::factor(hipStream_t st) {
   const int R1 = int(R1_);
   KQR_CHECK_HIP(hipMemsetAsync(flag_.ptr, 0, sizeof(int), st));
   double* C = C_.as<double>();
-  for (int kb = 0; kb < R1; kb += kCb) {
-    const int nb = std::min(kCb, R1 - kb);
+  for (int kb = 0; kb < R1; kb += kNb) {
+    const int nb = std::min(kNb, R1 - kb);
     chol_diag_kernel<<<1, 64, 0, st>>>(C, ldc_, kb, nb, flag_.as<int>());
     KQR_LAUNCH_CHECK();
     const int rest = R1 - kb - nb;
     if (rest > 0) {
-      chol_panel_kernel<<<(rest + 256 / kCb - 1) / (256 / kCb), 256, 0, st>>>(C, ldc_, kb, nb, R1);
+      chol_panel_kernel<<<(rest + 3) / 4, 256, 0, st>>>(C, ldc_, kb, nb, R1);
       KQR_LAUNCH_CHECK();
       const int mt = (rest + kT - 1) / kT;
       chol_update_kernel<<<mt * (mt + 1) / 2, 256, 0, st>>>(C, ldc_, kb, nb, R1);
       KQR_LAUNCH_CHECK();
     }
   }
-  const int nib = (R1 + kIb - 1) / kIb;
-  trinv_diag_kernel<<<nib, 64, 0, st>>>(C, ldc_, R1, W_.as<double>(), WT_.as<double>());
+  // W = Lc^{-1}: diagonal blocks, then doubling levels
+  const size_t core = size_t(R1_) * ldc_ * sizeof(double);
+  KQR_CHECK_HIP(hipMemsetAsync(W_.ptr, 0, core, st));
+  const int nib = (R1 + kNb - 1) / kNb;
+  trinv_diag_kernel<<<nib, 64, 0, st>>>(C, ldc_, R1, W_.as<double>());
   KQR_LAUNCH_CHECK();
-  for (int bi = 1; bi < nib; ++bi) {
-    trinv_row_kernel<<<bi, 256, 0, st>>>(C, ldc_, R1, bi, W_.as<double>(), WT_.as<double>());
-    KQR_LAUNCH_CHECK();
+  for (int s = kNb; s < R1; s *= 2) {
+    const int pairs = (R1 + 2 * s - 1) / (2 * s);
+    const int tiles = (s / kT) * (s / kT);
+    for (int stage = 0; stage < 2; ++stage) {
+      double* out = stage == 0 ? T_.as<double>() : W_.as<double>();
+      trinv_level_kernel<<<pairs * tiles, 256, 0, st>>>(C, W_.as<double>(), T_.as<double>(), out, ldc_, R1, s, stage,
+                                                        tiles);
+      KQR_LAUNCH_CHECK();
+    }
   }
+  transpose_lower_kernel<<<dim3((R1 + 31) / 32, (R1 + 31) / 32), 256, 0, st>>>(W_.as<double>(), ldc_, R1,
+                                                                             WT_.as<double>());
+  KQR_LAUNCH_CHECK();
   KQR_CHECK_HIP(hipMemcpyAsync(hbuf_.ptr, flag_.ptr, sizeof(int), hipMemcpyDeviceToHost, st));
   KQR_CHECK_HIP(hipStreamSynchronize(st));
   return *hbuf_.as<int>() == 0;
@@ -548,7 +610,6 @@ bool Woodbury::build_two_level(const double* L, const uint8_t* S, double l_in, d
                                hipStream_t st) {
   L_ = L;
   const int64_t n = n_;
-  // interior index list
   constexpr int nblk = 256;
   const int64_t chunk = (n + nblk - 1) / nblk;
   if (!idx_.ptr) {
@@ -582,20 +643,13 @@ void Woodbury::apply(const double* w, double* out, const double* dot_with, doubl
   wood_gt_kernel<<<kGtBlocks, 256, 0, st>>>(F_, n_, int(r_), ldf_, R1, L_, w, g_.as<double>(), chunk,
                                             part_.as<double>());
   KQR_LAUNCH_CHECK();
-  wood_treduce_kernel<<<(R1 + 255) / 256, 256, 0, st>>>(part_.as<double>(), kGtBlocks, R1, t_.as<double>());
+  wood_treduce_kernel<<<(R1 + 63) / 64, 1024, 0, st>>>(part_.as<double>(), kGtBlocks, R1, t_.as<double>());
   KQR_LAUNCH_CHECK();
   trmv_kernel<true><<<(R1 + 3) / 4, 256, 0, st>>>(W_.as<double>(), ldc_, R1, t_.as<double>(), y_.as<double>());
   KQR_LAUNCH_CHECK();
   trmv_kernel<false><<<(R1 + 3) / 4, 256, 0, st>>>(WT_.as<double>(), ldc_, R1, y_.as<double>(), s_.as<double>());
   KQR_LAUNCH_CHECK();
-  if (r_ > 0) {
-    const KMat fm{F_, KQR_FP32, ldf_};
-    ApplyShape sh;
-    sh.rows = 8;
-    sh.unroll = 1;
-    sh.segs = 1;
-    kapply_dense(fm, n_, r_, nullptr, s_.as<double>(), Fs_.as<double>(), 1, true, st, &sh);
-  }
+  if (r_ > 0) gemv_skinny(F_, ldf_, n_, r_, s_.as<double>(), Fs_.as<double>(), st);
   wood_out_kernel<<<kRedBlocks, 256, 0, st>>>(n_, int(r_), L_, g_.as<double>(), Fs_.as<double>(), s_.as<double>(),
                                               out, dot_with, dot_with ? ws.partials : nullptr);
   KQR_LAUNCH_CHECK();

@@ -89,6 +89,10 @@ _SIGS = {
                                    C.c_double, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "kqr_fit": (C.c_int, [_P, _P, _I64, _I64, C.c_double, C.c_double, C.c_int, C.c_double,
                           C.POINTER(KqrOptions), _P, _P, C.POINTER(KqrInfo), _P]),
+    "kqr_fit_multi_tau": (C.c_int, [_P, _P, _I64, _I64, _P, C.c_int, C.c_double, C.c_int, C.c_double,
+                                    C.POINTER(KqrOptions), _P, _P, _P, _P, _P]),
+    "kqr_fit_batch": (C.c_int, [C.c_int, _P, _P, _P, _I64, _P, _P, C.c_int, _P, C.POINTER(KqrOptions), _P, _P, _P,
+                                _P, _P]),
 }
 
 
@@ -367,6 +371,63 @@ def kqr_fit(X, y, tau, lam, kernel="rbf", gamma=1.0, options: KqrOptions | None 
     _check(st, "kqr_fit", allow=(KQR_OK, KQR_NOT_CONVERGED))
     del keep
     return alpha, float(beta.value), info.as_dict(), st
+
+
+def _options(options, uniforms, overrides):
+    o = options if options is not None else kqr_default_options()
+    for k, v in overrides.items():
+        setattr(o, k, v)
+    keep = None
+    if uniforms is not None:
+        keep = np.ascontiguousarray(np.asarray(uniforms, dtype=np.float64))
+        o.pivot_uniforms = keep.ctypes.data_as(C.POINTER(C.c_double))
+    return o, keep
+
+
+def kqr_fit_multi_tau(X, y, taus, lam, kernel="rbf", gamma=1.0, options: KqrOptions | None = None, uniforms=None,
+                      stream=None, **overrides):
+    """Joint fit of several quantile levels.  Returns (alpha (ntau x n GPU), betas, infos, statuses)."""
+    torch = _torch()
+    n, p = X.shape
+    taus = np.ascontiguousarray(np.asarray(taus, dtype=np.float64))
+    m = int(taus.size)
+    o, keep = _options(options, uniforms, overrides)
+    alpha = torch.empty((m, n), dtype=torch.float64, device=X.device)
+    beta = np.zeros(m)
+    info = (KqrInfo * m)()
+    status = np.zeros(m, dtype=np.int32)
+    _check(lib().kqr_fit_multi_tau(_dev(X, torch.float32, "X", 2), _dev(y, torch.float64, "y", 1), n, p,
+                                   taus.ctypes.data_as(C.c_void_p), m, float(lam), _kernel_id(kernel), float(gamma),
+                                   C.byref(o), _dev(alpha, torch.float64, "alpha", 2), beta.ctypes.data_as(C.c_void_p),
+                                   info, status.ctypes.data_as(C.c_void_p), _stream(stream)), "kqr_fit_multi_tau")
+    del keep
+    return alpha, beta, [info[i].as_dict() for i in range(m)], status.tolist()
+
+
+def kqr_fit_batch(Xs, ys, taus, lams, gammas, kernel="rbf", options: KqrOptions | None = None, uniforms=None,
+                  stream=None, **overrides):
+    """Independent fits in one batch.  Returns (alphas (list of GPU tensors), betas, infos, statuses)."""
+    torch = _torch()
+    k = len(Xs)
+    p = Xs[0].shape[1]
+    ns = np.array([x.shape[0] for x in Xs], dtype=np.int64)
+    alphas = [torch.empty(int(ni), dtype=torch.float64, device=Xs[0].device) for ni in ns]
+    xp = (C.c_void_p * k)(*[_dev(x, torch.float32, "X", 2).value for x in Xs])
+    yp = (C.c_void_p * k)(*[_dev(y, torch.float64, "y", 1).value for y in ys])
+    ap = (C.c_void_p * k)(*[_dev(a, torch.float64, "alpha", 1).value for a in alphas])
+    taus = np.ascontiguousarray(np.asarray(taus, dtype=np.float64))
+    lams = np.ascontiguousarray(np.asarray(lams, dtype=np.float64))
+    gammas = np.ascontiguousarray(np.asarray(gammas, dtype=np.float64))
+    o, keep = _options(options, uniforms, overrides)
+    beta = np.zeros(k)
+    info = (KqrInfo * k)()
+    status = np.zeros(k, dtype=np.int32)
+    _check(lib().kqr_fit_batch(k, xp, yp, ns.ctypes.data_as(C.c_void_p), p, taus.ctypes.data_as(C.c_void_p),
+                               lams.ctypes.data_as(C.c_void_p), _kernel_id(kernel), gammas.ctypes.data_as(C.c_void_p),
+                               C.byref(o), ap, beta.ctypes.data_as(C.c_void_p), info,
+                               status.ctypes.data_as(C.c_void_p), _stream(stream)), "kqr_fit_batch")
+    del keep
+    return alphas, beta, [info[i].as_dict() for i in range(k)], status.tolist()
 
 
 def default_rank(n: int) -> int:

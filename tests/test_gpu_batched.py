@@ -1,0 +1,133 @@
+"""GPU parity of the batched forms: K V on the matrix cores, the joint
+multi-tau fit, and the uneven batch of independent problems."""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import kernel as okernel
+from oracle import problem as oproblem
+from oracle import solver as osolver
+from paper_2510_07929_amd import inputs, kqr
+
+pytestmark = pytest.mark.gpu
+U32 = 2.0 ** -24
+
+
+def say(*a):
+    print("[gpu-test]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    kqr.lib()
+    return torch.device("cuda:0")
+
+
+def entry_bound(X, gamma):
+    Xd = X.astype(np.float64)
+    p = X.shape[1]
+    D = okernel.distance_block(Xd, Xd, "rbf")
+    K = np.exp(-gamma * D)
+    q = (Xd * Xd).sum(1)
+    dd = 4.0 * (p + 2) * U32 * (q[:, None] + q[None, :]) + 2.0 * U32 * D
+    return K, K * (gamma * dd + 8.0 * U32)
+
+
+@pytest.mark.parametrize("kd", ["fp32", "bf16"])
+@pytest.mark.parametrize("n,m", [(3001, 9), (700, 16), (1500, 2)])
+def test_kv_multi_rhs_matches_oracle(dev, kd, n, m):
+    p = 8
+    X, _ = inputs.additive(n, p, (130, n))
+    gamma = 1.0 / p
+    V = np.random.default_rng(m).standard_normal((n, m))
+    say("K V", kd, n, m)
+    K = kqr.kqr_kernel_build(torch.from_numpy(X).to(dev), "rbf", gamma, kd)
+    U = kqr.kqr_kernel_apply(torch.from_numpy(V).to(dev), K=K).cpu().numpy()
+    Kref, Kb = entry_bound(X, gamma)
+    A = np.abs(V)
+    if kd == "fp32":
+        # FP32 entries, V rounded to FP32, FP32 accumulation over 256-column stages
+        bound = Kb @ A + 300 * U32 * (Kref @ A)
+    else:
+        # BF16 entries (2^-8 relative), V split into hi + lo BF16 parts (2^-16)
+        bound = (2.0 ** -8 * (Kref + Kb) + Kb) @ A + (2.0 ** -15 + 300 * U32) * (Kref @ A)
+    err = np.abs(U - Kref @ V)
+    assert np.all(err <= bound + 1e-12), float((err / (bound + 1e-12)).max())
+
+
+def _oracle_obj(prob, tau, alpha, beta):
+    K = okernel.kernel_matrix(prob.X, prob.kernel, prob.gamma)
+    Ka = K @ alpha
+    z = prob.y - beta - Ka / prob.lam
+    return oproblem.primal_objective(z, alpha, Ka, prob.lam, tau)
+
+
+def test_fit_multi_tau_matches_oracle(dev):
+    prob = inputs.workload("c3a", n=2500)
+    taus = prob.extras["taus"]
+    say("multi-tau", prob.n, len(taus))
+    X = torch.from_numpy(prob.X).to(dev)
+    y = torch.from_numpy(prob.y).to(dev)
+    A, betas, infos, st = kqr.kqr_fit_multi_tau(X, y, taus, prob.lam, prob.kernel, prob.gamma, profile=1,
+                                                uniforms=inputs.pivot_uniforms(128, (3, 1)))
+    A = A.cpu().numpy()
+    assert all(s == kqr.KQR_OK for s in st), st
+    # every level used the shared K V launches
+    assert infos[0]["kapply_fast_calls"] > 0 and infos[0]["t_kapply_fast"] > 0
+    for t, tau in enumerate(taus):
+        ref = osolver.fit(prob.X, prob.y, tau, prob.lam, prob.kernel, prob.gamma, osolver.OracleOptions(tol=1e-10))
+        opt = ref.kkt["obj_p"]
+        rel = abs(_oracle_obj(prob, tau, A[t], betas[t]) - opt) / (1 + abs(opt))
+        say(f"  tau={tau} rel_obj={rel:.2e} kkt={infos[t]['eta_kkt']:.2e}")
+        assert max(infos[t]["eta_kkt"], infos[t]["eta_gap"]) <= 1e-6
+        assert rel <= 1e-6
+
+
+def test_fit_multi_tau_single_level_equals_fit(dev):
+    prob = inputs.workload("c0", n=1200)
+    X = torch.from_numpy(prob.X).to(dev)
+    y = torch.from_numpy(prob.y).to(dev)
+    uni = inputs.pivot_uniforms(64, (4, 2))
+    say("multi-tau with one level")
+    A, b, _, st = kqr.kqr_fit_multi_tau(X, y, [prob.tau], prob.lam, "rbf", prob.gamma, uniforms=uni)
+    a1, b1, _, st1 = kqr.kqr_fit(X, y, prob.tau, prob.lam, "rbf", prob.gamma, uniforms=uni)
+    # one level has nothing to coalesce: the same code path, bitwise
+    assert st == [st1] and torch.equal(A[0], a1) and b[0] == b1
+
+
+def test_fit_batch_matches_oracle(dev):
+    probs = inputs.uneven_batch(count=6, lo=300, hi=1400, seed=3)
+    say("uneven batch", [p.n for p in probs])
+    Xs = [torch.from_numpy(p.X).to(dev) for p in probs]
+    ys = [torch.from_numpy(p.y).to(dev) for p in probs]
+    alphas, betas, infos, st = kqr.kqr_fit_batch(Xs, ys, [p.tau for p in probs], [p.lam for p in probs],
+                                                 [p.gamma for p in probs], profile=1,
+                                                 uniforms=inputs.pivot_uniforms(64, (5, 1)))
+    assert all(s == kqr.KQR_OK for s in st), st
+    assert infos[0]["kapply_fast_calls"] > 0
+    for i, prob in enumerate(probs):
+        a = alphas[i].cpu().numpy()
+        ref = osolver.fit(prob.X, prob.y, prob.tau, prob.lam, "rbf", prob.gamma, osolver.OracleOptions(tol=1e-10))
+        opt = ref.kkt["obj_p"]
+        rel = abs(_oracle_obj(prob, prob.tau, a, betas[i]) - opt) / (1 + abs(opt))
+        say(f"  n={prob.n} rel_obj={rel:.2e} kkt={infos[i]['eta_kkt']:.2e}")
+        assert max(infos[i]["eta_kkt"], infos[i]["eta_gap"]) <= 1e-6
+        assert rel <= 1e-6
+
+
+def test_batched_entry_points_validate(dev):
+    prob = inputs.workload("c0", n=100)
+    X = torch.from_numpy(prob.X).to(dev)
+    y = torch.from_numpy(prob.y).to(dev)
+    with pytest.raises(kqr.KqrError) as e:
+        kqr.kqr_fit_multi_tau(X, y, [0.5, 1.5], prob.lam, "rbf", prob.gamma)
+    assert e.value.status == kqr.KQR_EINVAL
+    with pytest.raises(kqr.KqrError) as e:
+        kqr.kqr_fit_multi_tau(X, y, [0.5] * 17, prob.lam, "rbf", prob.gamma)
+    assert e.value.status == kqr.KQR_EINVAL
