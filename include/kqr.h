@@ -277,6 +277,30 @@ int kqr_fit_batch(int nprob, const float* const* X, const double* const* y, cons
                   const kqr_options* opt, double* const* alpha, double* beta, kqr_info* info, int* status,
                   void* stream);
 
+/* kqr_fit_grad: kqr_fit followed by the implicit gradient of the validation
+ * check loss J = sum_i rho_tau(yval_i - beta - K(Xval_i, X) alpha / lambda)
+ * with respect to log(gamma) and log(lambda).  The gradient is not part of the
+ * paper: it differentiates the KKT conditions of the dual (1.3) on the active
+ * partition R (alpha = tau), L (alpha = tau - 1), E (interior), which requires
+ * E to be non-empty (beta is otherwise not differentiable) and the partition
+ * to be locally constant (strict complementarity); dK/dlog(gamma) = K o ln K
+ * holds for both kernels.  Before the gradient the fit is polished: E is read
+ * from the final multipliers (|z_i| below a threshold), alpha_N is put on its
+ * bound and (alpha_E, beta) solve the bordered KKT system with the FP64
+ * Cholesky of K_EE (entries from FP32 X as in the K build); the polish is kept
+ * when alpha_E stays in the box and every residual sign matches the
+ * partition, and alpha / beta are then the polished values.
+ *  Xval device nval x p FP32; yval device nval FP64; other arguments as kqr_fit.
+ *  val_loss, grad (host, 2: dJ/dlog gamma, dJ/dlog lambda), n_interior and
+ *  polished are host outputs (n_interior and polished may be NULL).
+ *  Errors: KQR_ENUMERIC when E is empty or K_EE is not positive definite in
+ *  FP64, KQR_EINVAL when |E| exceeds 8192 (the dense factor's limit).
+ *  Returns KQR_OK or KQR_NOT_CONVERGED (gradient still computed). */
+int kqr_fit_grad(const float* X, const double* y, int64_t n, int64_t p, double tau, double lambda, int kernel,
+                 double gamma, const float* Xval, const double* yval, int64_t nval, const kqr_options* opt,
+                 double* alpha, double* beta, double* val_loss, double* grad, int64_t* n_interior, int* polished,
+                 kqr_info* info, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

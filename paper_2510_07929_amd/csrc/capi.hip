@@ -1,5 +1,6 @@
 // extern "C" entry points of libkqr: argument validation, workspace set-up and
 // dispatch.  No exception crosses the ABI: every entry point returns a status.
+#include "adjoint.h"
 #include "fit.h"
 
 #include <algorithm>
@@ -536,6 +537,54 @@ int kqr_fit_batch(int nprob, const float* const* X, const double* const* y, cons
     fit_batch(nprob, X, y, n, int(p), KernelSpec{kernel, gamma[0]}, tau, lambda, gamma, o, alpha, beta, info, status,
               static_cast<hipStream_t>(stream));
   });
+}
+
+int kqr_fit_grad(const float* X, const double* y, int64_t n, int64_t p, double tau, double lambda, int kernel,
+                 double gamma, const float* Xval, const double* yval, int64_t nval, const kqr_options* opt,
+                 double* alpha, double* beta, double* val_loss, double* grad, int64_t* n_interior, int* polished,
+                 kqr_info* info, void* stream) {
+  int converged = 0;
+  int st_code = guarded([&] {
+    KQR_REQUIRE(X && y && Xval && yval && alpha && beta && val_loss && grad, "pointers must be non-null");
+    KQR_REQUIRE(n >= 2 && p >= 1 && p <= 64, "need n >= 2 and 1 <= p <= 64");
+    KQR_REQUIRE(nval >= 1, "need nval >= 1");
+    KQR_REQUIRE(tau > 0.0 && tau < 1.0, "need 0 < tau < 1");
+    KQR_REQUIRE(std::isfinite(lambda) && lambda > 0.0, "lambda must be positive and finite");
+    check_kernel(kernel, gamma);
+    kqr_options o;
+    kqr_default_options(&o);
+    if (opt) o = *opt;
+    validate_options(o);
+    ensure_device();
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const KernelSpec ks{kernel, gamma};
+    DevBuf z(size_t(n) * sizeof(double));
+    double b = 0.0;
+    kqr_info inf{};
+    {
+      Prepared pr = prepare_fit(X, n, int(p), ks, o, st);
+      Operator op(X, n, int(p), ks, pr.kmat(), st);
+      op.enable_profile(o.profile != 0);
+      FitOutcome out = run_fit(op, pr, y, n, tau, lambda, o, alpha, st, z.as<double>());
+      b = out.beta;
+      converged = out.converged;
+      inf = out.info;
+    }  // K and F are released before the adjoint
+    const double level = std::max(inf.eta_kkt, inf.eta_gap);
+    GradOutcome g = adjoint_gradient(X, n, int(p), ks, tau, lambda, alpha, &b, z.as<double>(), y, Xval, nval, yval,
+                                     std::max(level, 1e-16), st);
+    KQR_CHECK_HIP(hipStreamSynchronize(st));
+    *beta = b;
+    *val_loss = g.J;
+    grad[0] = g.dgam;
+    grad[1] = g.dlam;
+    if (n_interior) *n_interior = g.n_interior;
+    if (polished) *polished = g.polished ? 1 : 0;
+    inf.n_interior = g.n_interior;
+    if (info) *info = inf;
+  });
+  if (st_code == KQR_OK && !converged) return KQR_NOT_CONVERGED;
+  return st_code;
 }
 
 }  // extern "C"

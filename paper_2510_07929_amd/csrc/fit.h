@@ -31,9 +31,10 @@ struct FitOutcome {
   kqr_info info{};
 };
 
-// Runs Phase I, Phase II and the final residuals; copies alpha to alpha_out.
+// Runs Phase I, Phase II and the final residuals; copies alpha to alpha_out
+// and, when z_out is given, the final multipliers z to z_out (device, n).
 FitOutcome run_fit(Operator& op, const Prepared& pr, const double* y, int64_t n, double tau, double lam,
-                   const kqr_options& o, double* alpha_out, hipStream_t st);
+                   const kqr_options& o, double* alpha_out, hipStream_t st, double* z_out = nullptr);
 
 // tau batch: every level shares K and F; fast K-applies of all levels are
 // coalesced into one K V launch on the matrix cores.

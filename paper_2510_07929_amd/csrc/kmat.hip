@@ -361,7 +361,7 @@ void kapply_dense(const KMat& km, int64_t nrows, int64_t ncols, const float* v32
 // the slices' partial sums are added in a fixed order by a second kernel.
 constexpr int kOtfTile = 64;
 
-template <int PMAX, bool LAP>
+template <int PMAX, bool LAP, bool DK>
 __global__ __launch_bounds__(256) void kapply_otf_kernel(
     const float* __restrict__ Xr, const float* __restrict__ qr, int64_t nr,
     const float* __restrict__ Xc, const float* __restrict__ qc, int64_t nc, int p, float ng,
@@ -394,7 +394,8 @@ __global__ __launch_bounds__(256) void kapply_otf_kernel(
     float a32 = 0.f;
     for (int jj = 0; jj < cnt; ++jj) {
       const float d = pair_dist<PMAX, LAP>(xs[jj], qs[jj], xi, qi);
-      a32 = fmaf(exp2f(ng * d), vs[jj], a32);
+      const float kv = exp2f(ng * d);
+      a32 = fmaf(DK ? d * kv : kv, vs[jj], a32);  // DK: entries d_ij k_ij
     }
     acc += double(a32);
   }
@@ -413,7 +414,7 @@ __global__ void otf_reduce_kernel(const double* __restrict__ part, int nslice, i
 template <int PMAX>
 static void kapply_otf_p(const float* Xr, const float* qr, int64_t nr, const float* Xc,
                          const float* qc, int64_t nc, int p, KernelSpec ks, const double* v, double* u,
-                         int64_t ldu, double scale, double shift, hipStream_t st) {
+                         int64_t ldu, double scale, double shift, bool dk, hipStream_t st) {
   const int64_t rblk = (nr + 255) / 256;
   // enough column slices for ~2048 blocks, each slice at least 1024 columns
   int64_t nslice = std::max<int64_t>(1, std::min<int64_t>(2048 / std::max<int64_t>(rblk, 1), (nc + 1023) / 1024));
@@ -425,10 +426,11 @@ static void kapply_otf_p(const float* Xr, const float* qr, int64_t nr, const flo
   KQR_CHECK_HIP(hipMallocAsync(reinterpret_cast<void**>(&part), size_t(nslice) * size_t(nr) * sizeof(double), st));
   const dim3 grid((unsigned)rblk, (unsigned)nslice);
   const float ng = -float(ks.gamma) * kLog2e;
-  if (ks.kind == KQR_LAPLACIAN)
-    kapply_otf_kernel<PMAX, true><<<grid, 256, 0, st>>>(Xr, qr, nr, Xc, qc, nc, p, ng, v, per, part);
-  else
-    kapply_otf_kernel<PMAX, false><<<grid, 256, 0, st>>>(Xr, qr, nr, Xc, qc, nc, p, ng, v, per, part);
+  const bool lap = ks.kind == KQR_LAPLACIAN;
+  if (lap && dk) kapply_otf_kernel<PMAX, true, true><<<grid, 256, 0, st>>>(Xr, qr, nr, Xc, qc, nc, p, ng, v, per, part);
+  else if (lap) kapply_otf_kernel<PMAX, true, false><<<grid, 256, 0, st>>>(Xr, qr, nr, Xc, qc, nc, p, ng, v, per, part);
+  else if (dk) kapply_otf_kernel<PMAX, false, true><<<grid, 256, 0, st>>>(Xr, qr, nr, Xc, qc, nc, p, ng, v, per, part);
+  else kapply_otf_kernel<PMAX, false, false><<<grid, 256, 0, st>>>(Xr, qr, nr, Xc, qc, nc, p, ng, v, per, part);
   KQR_LAUNCH_CHECK();
   otf_reduce_kernel<<<dim3((unsigned)((nr + 255) / 256)), 256, 0, st>>>(part, int(nslice), nr, u, ldu, scale, shift);
   KQR_LAUNCH_CHECK();
@@ -437,9 +439,9 @@ static void kapply_otf_p(const float* Xr, const float* qr, int64_t nr, const flo
 
 void kapply_otf(const float* Xr, const float* sqr, int64_t nr, const float* Xc, const float* sqc,
                 int64_t nc, int p, KernelSpec ks, const double* v64, double* u, int64_t ldu,
-                double out_scale, double out_shift, hipStream_t st) {
+                double out_scale, double out_shift, hipStream_t st, bool dk) {
   if (nr <= 0) return;
-  KQR_DISPATCH_P(p, kapply_otf_p, Xr, sqr, nr, Xc, sqc, nc, p, ks, v64, u, ldu, out_scale, out_shift, st);
+  KQR_DISPATCH_P(p, kapply_otf_p, Xr, sqr, nr, Xc, sqc, nc, p, ks, v64, u, ldu, out_scale, out_shift, dk, st);
 }
 
 // ================================================================= one kernel row

@@ -103,11 +103,14 @@ class Solver {
   void phase2(kqr_info& info);
   void finish(kqr_info& info);
   const double* alpha() const { return alpha_.as<double>(); }
+  const double* z() const { return z_.as<double>(); }  // ALM multipliers
   double beta() const { return beta_; }
   bool converged() const { return converged_; }
   Workspace& ws() { return ws_; }
 
  private:
+  PcgStats linsolve(double c, const double* L, const double* b, double* x, double* Kx, bool x_zero, double tol,
+                    kqr_info& info);
   void ssn(double stop, kqr_info& info);
   Kkt kkt_from_sums(const double* s) const;
   Kkt update_and_kkt(double beta_new, double sigma, double step, bool update);
@@ -125,6 +128,7 @@ class Solver {
   Pcg pcg_;
   HostPinned hbuf_;
   DevBuf alpha_, v_, z_, Ka_, b_, L_, grad_, d_, Kd_, S_, red_;
+  DevBuf rf_r_, rf_dx_, rf_kdx_;  // refinement workspace (BF16 storage)
   std::unique_ptr<Woodbury> P_;
   double beta_ = 0.0, sigma_ = 1.0, ynorm_ = 0.0, eta_d_prev_ = 1.0;
   Kkt last_;

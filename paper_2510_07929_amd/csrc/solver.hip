@@ -223,6 +223,64 @@ static double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
+// Linear solve of (K + c 1 1^T + diag(L)) x = b to ||b - A x|| <= tol, with K x
+// kept in Kx.  With an FP32 (or on-the-fly) operator this is PCG on the
+// operator itself.  With BF16 storage it is iterative refinement: the
+// residual r = b - A x is formed with the exact operator (FP32 entries
+// recomputed from X, FP64 vectors and sums), PCG on the BF16 operator solves
+// A_bf16 dx = r to a modest relative accuracy, x += dx and K x += K_exact dx.
+// When a refinement step fails to reduce the exact residual by a tenth, the
+// solve finishes with PCG on the exact operator.
+PcgStats Solver::linsolve(double c, const double* L, const double* b, double* x, double* Kx, bool x_zero, double tol,
+                          kqr_info& info) {
+  if (!(op_.materialized() && op_.kmat().dtype == KQR_BF16 && o_.refine)) {
+    return pcg_.solve(c, L, P_.get(), b, x, Kx, x_zero, tol, o_.pcg_max_iter, true, st_);
+  }
+  const int64_t n = n_;
+  if (!rf_r_.ptr) {
+    rf_r_.alloc(size_t(n) * sizeof(double));
+    rf_dx_.alloc(size_t(n) * sizeof(double));
+    rf_kdx_.alloc(size_t(n) * sizeof(double));
+  }
+  double* r = rf_r_.as<double>();
+  double* dx = rf_dx_.as<double>();
+  double* kdx = rf_kdx_.as<double>();
+  if (x_zero) {
+    fill(n, 0.0, x, st_);
+    fill(n, 0.0, Kx, st_);
+  }
+  double sums[3];
+  auto residual = [&]() -> double {  // r = b - (Kx + c sum(x) + L x); returns ||r||
+    vec_dots(n, x, nullptr, ws_, red_.as<double>(), st_);
+    pcg_init_r(n, b, x, Kx, L, c, red_.as<double>(), 0, r, ws_, red_.as<double>() + 8, st_);
+    read_scalars(red_.as<double>() + 8, 1, sums, st_);
+    return std::sqrt(std::max(sums[0], 0.0));
+  };
+  PcgStats total;
+  double rn = residual();
+  total.resnorm = rn;
+  for (int step = 0; step < 30 && rn > tol; ++step) {
+    const double inner_tol = std::max(0.5 * tol, 0.05 * rn);
+    PcgStats ps = pcg_.solve(c, L, P_.get(), r, dx, nullptr, true, inner_tol, o_.pcg_max_iter, true, st_);
+    total.iters += ps.iters;
+    op_.apply_exact(dx, kdx, st_);
+    axpy2(n, 1.0, dx, x, kdx, Kx, st_);
+    ++info.refinements;
+    const double rn_new = residual();
+    total.resnorm = rn_new;
+    const bool stalled = !(rn_new < 0.9 * rn);
+    rn = rn_new;
+    if (stalled && rn > tol) {  // BF16 operator too far from the exact one here
+      PcgStats pe = pcg_.solve(c, L, P_.get(), b, x, Kx, false, tol, o_.pcg_max_iter, false, st_);
+      total.iters += pe.iters;
+      total.resnorm = pe.resnorm;
+      // exact K x after the exact solve (Kx was advanced with exact products)
+      break;
+    }
+  }
+  return total;
+}
+
 // Algorithm 1.  M = K + lambda sigma (I + 1 1^T) is fixed, so the Woodbury
 // core (L = lambda sigma I) is formed once.
 void Solver::phase1(kqr_info& info) {
@@ -249,8 +307,8 @@ void Solver::phase1(kqr_info& info) {
       b0 = std::sqrt(t3[2]);
     }
     const double eps_k = o_.admm_eps0 * b0 / std::pow(double(it + 1), 1.5);
-    PcgStats ps = pcg_.solve(c, L_.as<double>(), P_.get(), b_.as<double>(), alpha_.as<double>(), Ka_.as<double>(), it == 0,
-                      eps_k, o_.pcg_max_iter, true, st_);
+    PcgStats ps = linsolve(c, L_.as<double>(), b_.as<double>(), alpha_.as<double>(), Ka_.as<double>(), it == 0, eps_k,
+                           info);
     info.admm_pcg_iters += ps.iters;
     const double sa = sum_of(alpha_.as<double>());
     const double beta_new = beta_ + step * sigma * sa;
@@ -287,8 +345,7 @@ void Solver::ssn(double stop, kqr_info& info) {
                                    st_))
       fail(KQR_ENUMERIC, "Newton preconditioner core not positive definite");
     const double tol = lam_ * std::min(o_.etabar, std::pow(gn, 1.0 + o_.iota));
-    PcgStats ps = pcg_.solve(c1, L_.as<double>(), P_.get(), b_.as<double>(), d_.as<double>(), Kd_.as<double>(), true, tol,
-                      o_.pcg_max_iter, true, st_);
+    PcgStats ps = linsolve(c1, L_.as<double>(), b_.as<double>(), d_.as<double>(), Kd_.as<double>(), true, tol, info);
     info.pcg_iters += ps.iters;
     // Armijo backtracking, kLsTrials step lengths per pass
     const double s0 = sa + beta_ / sigma;

@@ -48,6 +48,19 @@ void count_interior(int64_t n, const double* a, double tau, Workspace& ws, doubl
 void fill(int64_t n, double val, double* x, hipStream_t st);
 void copy(int64_t n, const double* src, double* dst, hipStream_t st);
 
+// ----------------------------------------------------------------- dense SPD (woodbury.hip)
+// In place Cholesky C = Lc Lc^T of the lower triangle of an m x m FP64 matrix
+// (leading dimension ldc), then W = Lc^{-1} and WT = W^T (both m x ldc; T is
+// scratch of the same size).  *flag (device) becomes nonzero on a
+// non-positive pivot.  Asynchronous.
+void spd_factor_inverse(double* C, int64_t ldc, int m, double* W, double* WT, double* T, int* flag, hipStream_t st);
+// idx[0..m) = increasing indices i with S[i] != 0; returns m (synchronises).
+// cnt: device scratch of 257 ints.
+int64_t index_list(const uint8_t* S, int64_t n, int* idx, int* cnt, hipStream_t st);
+// s = C^{-1} t = W^T (W t); y is scratch of m doubles.
+void spd_solve(const double* W, const double* WT, int64_t ldc, int m, const double* t, double* y, double* s,
+               hipStream_t st);
+
 // ----------------------------------------------------------------- Woodbury (woodbury.hip)
 // P = F F^T + c 1 1^T + diag(L), applied by Lemma 1 with the (r+1)^2 core in FP64.
 class Woodbury {

@@ -546,42 +546,65 @@ void Woodbury::syrk(const double* L, const int* idx, int64_t nrows, double* G, d
   KQR_LAUNCH_CHECK();
 }
 
-bool Woodbury::factor(hipStream_t st) {
-  const int R1 = int(R1_);
-  KQR_CHECK_HIP(hipMemsetAsync(flag_.ptr, 0, sizeof(int), st));
-  double* C = C_.as<double>();
+void spd_factor_inverse(double* C, int64_t ldc, int R1, double* W, double* WT, double* T, int* flag, hipStream_t st) {
+  KQR_CHECK_HIP(hipMemsetAsync(flag, 0, sizeof(int), st));
   for (int kb = 0; kb < R1; kb += kNb) {
     const int nb = std::min(kNb, R1 - kb);
-    chol_diag_kernel<<<1, 64, 0, st>>>(C, ldc_, kb, nb, flag_.as<int>());
+    chol_diag_kernel<<<1, 64, 0, st>>>(C, ldc, kb, nb, flag);
     KQR_LAUNCH_CHECK();
     const int rest = R1 - kb - nb;
     if (rest > 0) {
-      chol_panel_kernel<<<(rest + 3) / 4, 256, 0, st>>>(C, ldc_, kb, nb, R1);
+      chol_panel_kernel<<<(rest + 3) / 4, 256, 0, st>>>(C, ldc, kb, nb, R1);
       KQR_LAUNCH_CHECK();
       const int mt = (rest + kT - 1) / kT;
-      chol_update_kernel<<<mt * (mt + 1) / 2, 256, 0, st>>>(C, ldc_, kb, nb, R1);
+      chol_update_kernel<<<mt * (mt + 1) / 2, 256, 0, st>>>(C, ldc, kb, nb, R1);
       KQR_LAUNCH_CHECK();
     }
   }
   // W = Lc^{-1}: diagonal blocks, then doubling levels
-  const size_t core = size_t(R1_) * ldc_ * sizeof(double);
-  KQR_CHECK_HIP(hipMemsetAsync(W_.ptr, 0, core, st));
+  KQR_CHECK_HIP(hipMemsetAsync(W, 0, size_t(R1) * ldc * sizeof(double), st));
   const int nib = (R1 + kNb - 1) / kNb;
-  trinv_diag_kernel<<<nib, 64, 0, st>>>(C, ldc_, R1, W_.as<double>());
+  trinv_diag_kernel<<<nib, 64, 0, st>>>(C, ldc, R1, W);
   KQR_LAUNCH_CHECK();
   for (int s = kNb; s < R1; s *= 2) {
     const int pairs = (R1 + 2 * s - 1) / (2 * s);
     const int tiles = (s / kT) * (s / kT);
     for (int stage = 0; stage < 2; ++stage) {
-      double* out = stage == 0 ? T_.as<double>() : W_.as<double>();
-      trinv_level_kernel<<<pairs * tiles, 256, 0, st>>>(C, W_.as<double>(), T_.as<double>(), out, ldc_, R1, s, stage,
-                                                        tiles);
+      double* out = stage == 0 ? T : W;
+      trinv_level_kernel<<<pairs * tiles, 256, 0, st>>>(C, W, T, out, ldc, R1, s, stage, tiles);
       KQR_LAUNCH_CHECK();
     }
   }
-  transpose_lower_kernel<<<dim3((R1 + 31) / 32, (R1 + 31) / 32), 256, 0, st>>>(W_.as<double>(), ldc_, R1,
-                                                                             WT_.as<double>());
+  transpose_lower_kernel<<<dim3((R1 + 31) / 32, (R1 + 31) / 32), 256, 0, st>>>(W, ldc, R1, WT);
   KQR_LAUNCH_CHECK();
+}
+
+int64_t index_list(const uint8_t* S, int64_t n, int* idx, int* cnt, hipStream_t st) {
+  constexpr int nblk = 256;
+  const int64_t chunk = (n + nblk - 1) / nblk;
+  flag_count_kernel<<<nblk, 256, 0, st>>>(S, n, chunk, cnt);
+  KQR_LAUNCH_CHECK();
+  flag_scan_kernel<<<1, 64, 0, st>>>(cnt, nblk, cnt + nblk);
+  KQR_LAUNCH_CHECK();
+  flag_scatter_kernel<<<nblk, 64, 0, st>>>(S, n, chunk, cnt, idx);
+  KQR_LAUNCH_CHECK();
+  int m = 0;
+  KQR_CHECK_HIP(hipMemcpyAsync(&m, cnt + nblk, sizeof(int), hipMemcpyDeviceToHost, st));
+  KQR_CHECK_HIP(hipStreamSynchronize(st));
+  return m;
+}
+
+void spd_solve(const double* W, const double* WT, int64_t ldc, int R1, const double* t, double* y, double* s,
+               hipStream_t st) {
+  trmv_kernel<true><<<(R1 + 3) / 4, 256, 0, st>>>(W, ldc, R1, t, y);
+  KQR_LAUNCH_CHECK();
+  trmv_kernel<false><<<(R1 + 3) / 4, 256, 0, st>>>(WT, ldc, R1, y, s);
+  KQR_LAUNCH_CHECK();
+}
+
+bool Woodbury::factor(hipStream_t st) {
+  spd_factor_inverse(C_.as<double>(), ldc_, int(R1_), W_.as<double>(), WT_.as<double>(), T_.as<double>(),
+                     flag_.as<int>(), st);
   KQR_CHECK_HIP(hipMemcpyAsync(hbuf_.ptr, flag_.ptr, sizeof(int), hipMemcpyDeviceToHost, st));
   KQR_CHECK_HIP(hipStreamSynchronize(st));
   return *hbuf_.as<int>() == 0;
@@ -645,10 +668,7 @@ void Woodbury::apply(const double* w, double* out, const double* dot_with, doubl
   KQR_LAUNCH_CHECK();
   wood_treduce_kernel<<<(R1 + 63) / 64, 1024, 0, st>>>(part_.as<double>(), kGtBlocks, R1, t_.as<double>());
   KQR_LAUNCH_CHECK();
-  trmv_kernel<true><<<(R1 + 3) / 4, 256, 0, st>>>(W_.as<double>(), ldc_, R1, t_.as<double>(), y_.as<double>());
-  KQR_LAUNCH_CHECK();
-  trmv_kernel<false><<<(R1 + 3) / 4, 256, 0, st>>>(WT_.as<double>(), ldc_, R1, y_.as<double>(), s_.as<double>());
-  KQR_LAUNCH_CHECK();
+  spd_solve(W_.as<double>(), WT_.as<double>(), ldc_, R1, t_.as<double>(), y_.as<double>(), s_.as<double>(), st);
   if (r_ > 0) gemv_skinny(F_, ldf_, n_, r_, s_.as<double>(), Fs_.as<double>(), st);
   wood_out_kernel<<<kRedBlocks, 256, 0, st>>>(n_, int(r_), L_, g_.as<double>(), Fs_.as<double>(), s_.as<double>(),
                                               out, dot_with, dot_with ? ws.partials : nullptr);

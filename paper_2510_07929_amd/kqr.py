@@ -93,6 +93,8 @@ _SIGS = {
                                     C.POINTER(KqrOptions), _P, _P, _P, _P, _P]),
     "kqr_fit_batch": (C.c_int, [C.c_int, _P, _P, _P, _I64, _P, _P, C.c_int, _P, C.POINTER(KqrOptions), _P, _P, _P,
                                 _P, _P]),
+    "kqr_fit_grad": (C.c_int, [_P, _P, _I64, _I64, C.c_double, C.c_double, C.c_int, C.c_double, _P, _P, _I64,
+                               C.POINTER(KqrOptions), _P, _P, _P, _P, _P, _P, C.POINTER(KqrInfo), _P]),
 }
 
 
@@ -428,6 +430,74 @@ def kqr_fit_batch(Xs, ys, taus, lams, gammas, kernel="rbf", options: KqrOptions 
                                status.ctypes.data_as(C.c_void_p), _stream(stream)), "kqr_fit_batch")
     del keep
     return alphas, beta, [info[i].as_dict() for i in range(k)], status.tolist()
+
+
+def kqr_fit_grad(X, y, tau, lam, kernel, gamma, Xval, yval, options: KqrOptions | None = None, uniforms=None,
+                 stream=None, **overrides):
+    """Fit, then the implicit gradient of the validation check loss.
+
+    Returns (alpha (GPU float64), beta, J, (dJ/dlog gamma, dJ/dlog lambda), |E|, polished, info, status).
+    """
+    torch = _torch()
+    n, p = X.shape
+    nv = Xval.shape[0]
+    if Xval.shape[1] != p:
+        raise ValueError("Xval must have the columns of X")
+    o, keep = _options(options, uniforms, overrides)
+    alpha = torch.empty(n, dtype=torch.float64, device=X.device)
+    beta = C.c_double(0.0)
+    loss = C.c_double(0.0)
+    grad = (C.c_double * 2)()
+    m = C.c_int64(0)
+    pol = C.c_int(0)
+    info = KqrInfo()
+    st = lib().kqr_fit_grad(_dev(X, torch.float32, "X", 2), _dev(y, torch.float64, "y", 1), n, p, float(tau),
+                            float(lam), _kernel_id(kernel), float(gamma), _dev(Xval, torch.float32, "Xval", 2),
+                            _dev(yval, torch.float64, "yval", 1), nv, C.byref(o), _dev(alpha, torch.float64, "alpha", 1),
+                            C.byref(beta), C.byref(loss), grad, C.byref(m), C.byref(pol), C.byref(info),
+                            _stream(stream))
+    _check(st, "kqr_fit_grad", allow=(KQR_OK, KQR_NOT_CONVERGED))
+    del keep
+    return (alpha, float(beta.value), float(loss.value), (float(grad[0]), float(grad[1])), int(m.value),
+            bool(pol.value), info.as_dict(), st)
+
+
+def _make_fit_loss():
+    torch = _torch()
+
+    class KQRFitLoss(torch.autograd.Function):
+        """(log gamma, log lambda) -> validation check loss of the KQR fit.
+
+        Forward fits on the GPU and computes the implicit gradient in the same
+        call; backward scales it by the incoming gradient.
+        """
+
+        @staticmethod
+        def forward(ctx, log_gamma, log_lambda, X, y, Xval, yval, tau, kernel, fit_kwargs):
+            gam = float(torch.exp(log_gamma.detach().double()).item())
+            lam = float(torch.exp(log_lambda.detach().double()).item())
+            out = kqr_fit_grad(X, y, tau, lam, kernel, gam, Xval, yval, **(fit_kwargs or {}))
+            ctx.grads = out[3]
+            return torch.tensor(out[2], dtype=torch.float64)
+
+        @staticmethod
+        def backward(ctx, gout):
+            dg, dl = ctx.grads
+            gout = gout.double()
+            return gout * dg, gout * dl, None, None, None, None, None, None, None
+
+    return KQRFitLoss
+
+
+_FIT_LOSS = None
+
+
+def kqr_validation_loss(log_gamma, log_lambda, X, y, Xval, yval, tau, kernel="rbf", **fit_kwargs):
+    """Differentiable validation loss: autograd Function over (log gamma, log lambda)."""
+    global _FIT_LOSS
+    if _FIT_LOSS is None:
+        _FIT_LOSS = _make_fit_loss()
+    return _FIT_LOSS.apply(log_gamma, log_lambda, X, y, Xval, yval, tau, kernel, fit_kwargs)
 
 
 def default_rank(n: int) -> int:

@@ -1,0 +1,91 @@
+"""GPU parity of the BF16-stored K path: the inner PCG runs on BF16 K and every
+linear system is refined with FP64 residuals of the exact (FP32-entry,
+FP64-accumulated) operator, so the converged fit must meet the same bars as the
+FP32 path: KKT and gap <= 1e-6 and relative objective difference <= 1e-6
+against the FP64 oracle.  Also the on-the-fly (nothing stored) path.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import kernel as okernel
+from oracle import problem as oproblem
+from oracle import solver as osolver
+from paper_2510_07929_amd import inputs, kqr
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[gpu-test]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    kqr.lib()
+    return torch.device("cuda:0")
+
+
+def _check_against_oracle(prob, a, beta, info):
+    ref = osolver.fit(prob.X, prob.y, prob.tau, prob.lam, prob.kernel, prob.gamma, osolver.OracleOptions(tol=1e-10))
+    K = okernel.kernel_matrix(prob.X, prob.kernel, prob.gamma)
+    Ka = K @ a
+    cert = oproblem.kkt(a, oproblem.proj_box(a, prob.tau), beta, prob.y - beta - Ka / prob.lam, Ka, prob.y,
+                        prob.lam, prob.tau)
+    opt = ref.kkt["obj_p"]
+    rel_obj = abs(cert["obj_p"] - opt) / (1 + abs(opt))
+    say(f"  rel_obj={rel_obj:.2e} cert_kkt={cert['eta_kkt']:.2e} info_kkt={info['eta_kkt']:.2e} "
+        f"gap={info['eta_gap']:.2e} refinements={info['refinements']} pcg={info['pcg_iters']} "
+        f"admm_pcg={info['admm_pcg_iters']} exact_applies={info['kapply_exact_calls']}")
+    assert max(info["eta_kkt"], info["eta_gap"]) <= 1e-6
+    assert rel_obj <= 1e-6
+    assert cert["eta_d"] <= 2e-6 and cert["eta_c"] <= 1e-5
+
+
+@pytest.mark.parametrize("name,n,rank", [("c2", 3000, 0), ("c2", 4100, 300), ("c2lap", 2500, 0)])
+def test_bf16_refined_fit_matches_oracle(dev, name, n, rank):
+    prob = inputs.workload(name, n=n)
+    say("bf16 fit", name, n, rank)
+    X = torch.from_numpy(prob.X).to(dev)
+    y = torch.from_numpy(prob.y).to(dev)
+    alpha, beta, info, st = kqr.kqr_fit(X, y, prob.tau, prob.lam, prob.kernel, prob.gamma, rank=rank,
+                                        k_dtype=kqr.KQR_BF16, kmode=kqr.KQR_KMODE_MATERIALIZE, profile=1,
+                                        uniforms=inputs.pivot_uniforms(max(rank, 64), (n, 6)))
+    assert st == kqr.KQR_OK
+    assert info["refinements"] > 0
+    _check_against_oracle(prob, alpha.cpu().numpy(), beta, info)
+
+
+def test_on_the_fly_fit_matches_oracle(dev):
+    prob = inputs.workload("c2lap", n=2200)
+    say("on-the-fly fit")
+    X = torch.from_numpy(prob.X).to(dev)
+    y = torch.from_numpy(prob.y).to(dev)
+    alpha, beta, info, st = kqr.kqr_fit(X, y, prob.tau, prob.lam, prob.kernel, prob.gamma, rank=0,
+                                        kmode=kqr.KQR_KMODE_ON_THE_FLY, profile=1,
+                                        uniforms=inputs.pivot_uniforms(64, (2200, 7)))
+    assert st == kqr.KQR_OK
+    _check_against_oracle(prob, alpha.cpu().numpy(), beta, info)
+
+
+def test_bf16_without_refinement_reports_its_level(dev):
+    # refine = 0: the fit runs on the BF16 operator alone; the residuals are
+    # still measured with exact K, so the status reports honestly whether the
+    # tolerance was reached.
+    prob = inputs.workload("c2", n=1500)
+    X = torch.from_numpy(prob.X).to(dev)
+    y = torch.from_numpy(prob.y).to(dev)
+    say("bf16 no refinement")
+    alpha, beta, info, st = kqr.kqr_fit(X, y, prob.tau, prob.lam, prob.kernel, prob.gamma, rank=0,
+                                        k_dtype=kqr.KQR_BF16, kmode=kqr.KQR_KMODE_MATERIALIZE, refine=0,
+                                        alm_max_iter=60)
+    assert info["refinements"] == 0
+    level = max(info["eta_kkt"], info["eta_gap"])
+    say(f"  status={st} level={level:.2e}")
+    assert (st == kqr.KQR_OK) == (level <= 1e-6)
