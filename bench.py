@@ -17,11 +17,22 @@ Printed (one JSON line):
                its average duration, against the 8 TB/s HBM peak;
   cpu_baseline the FP64 oracle's K-apply on a bounded row sample of the same
                K on this host's cores.
+
+The default workload is c1 (n=50000, FP32 K, rank 500).  Other workloads
+print one line of the same shape for their own comparison:
+  c2     BF16-stored K with FP64 refinement against FP32 K, same problem;
+  c2lap  on-the-fly Laplacian K (nothing stored), VALU-bound;
+  c3a    nine quantile levels fitted jointly (K V on the matrix cores)
+         against nine separate fits;
+  c3b    64 uneven problems in one batch against one at a time;
+  c4     fit + implicit adjoint of the validation loss (and, with --fd,
+         central differences of polished fits).
 """
 from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -31,6 +42,9 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# Non-packed FP32 VALU: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz lane-ops/s.
+VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9
+METRIC = "K-apply GB/s (% HBM peak) + wall time to rel KKT 1e-6, FP32 vs BF16/batched"
 
 
 def parse():
@@ -45,6 +59,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="skip the K-apply shape sweep before the warm-up")
     ap.add_argument("--traffic", default=None, help="JSON file with measured HBM bytes per K-apply launch")
+    ap.add_argument("--fd", action="store_true", help="c4: also time central differences of the gradient")
+    ap.add_argument("--verbose", action="store_true", help="per-iteration solver log on stderr")
     return ap.parse_args()
 
 
@@ -83,100 +99,358 @@ def cpu_baseline(prob, budget_s):
     }
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
-                          "n_gpus": args.gpus}))
-        sys.exit(2)
-    import numpy as np
+def fit_summary(info, st):
+    return {
+        "status": st, "eta_kkt": info["eta_kkt"], "eta_gap": info["eta_gap"], "obj_p": info["obj_p"],
+        "admm_iters": info["admm_iters"], "alm_iters": info["alm_iters"], "newton_iters": info["newton_iters"],
+        "admm_pcg_iters": info["admm_pcg_iters"], "pcg_iters": info["pcg_iters"],
+        "refinements": info["refinements"], "rank": info["rank_used"],
+        "kapply_calls": info["kapply_calls"], "kapply_exact_calls": info["kapply_exact_calls"],
+        "t_kbuild_s": round(info["t_kbuild"], 4), "t_precond_s": round(info["t_precond"], 4),
+        "t_admm_s": round(info["t_admm"], 4), "t_alm_s": round(info["t_alm"], 4),
+        "t_total_s": round(info["t_total"], 4),
+        "t_kapply_exact_avg_us": round(info["t_kapply_exact"] / max(info["kapply_exact_calls"], 1) * 1e6, 2),
+    }
+
+
+def base_line(args, prob, dtype, config_extra=None):
+    cfg = {
+        "workload": f"{prob.name}: {inputs_mod().WORKLOADS[prob.name][1]}",
+        "n": prob.n, "p": prob.p, "tau": prob.tau, "lambda": prob.lam, "gamma": prob.gamma,
+        "kernel": prob.kernel, "tol": 1e-6,
+    }
+    cfg.update(config_extra or {})
+    return {
+        "metric": METRIC, "value": None, "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dtype,
+        "data": "synthetic", "config": cfg,
+    }
+
+
+def inputs_mod():
+    from paper_2510_07929_amd import inputs
+
+    return inputs
+
+
+def timed_fits(args, one_fit):
+    import torch
+
+    for _ in range(args.warmup):
+        one_fit()
+    torch.cuda.synchronize()
+    outs = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        outs.append(one_fit())
+    torch.cuda.synchronize()
+    return outs, time.perf_counter() - t0
+
+
+def run_materialised(args, prob, kdtype, tune):
+    """Timed single-problem fits with K stored (fp32 or bf16); returns (line pieces)."""
     import torch
 
     from paper_2510_07929_amd import inputs, kqr
 
-    prob = inputs.workload(args.workload, n=args.n)
-    kdtype = args.kdtype or prob.kdtype
     esz = 4 if kdtype == "fp32" else 2
     dev = torch.device("cuda:0")
     X = torch.from_numpy(prob.X).to(dev)
     y = torch.from_numpy(prob.y).to(dev)
     rank = prob.rank if prob.rank > 0 else 0
     uni = inputs.pivot_uniforms(1024, (sum(map(ord, prob.name)), 0))
-    opts = dict(rank=rank, k_dtype=kqr.KDTYPES[kdtype], kmode=kqr.KQR_KMODE_MATERIALIZE, profile=1)
+    opts = dict(rank=rank, k_dtype=kqr.KDTYPES[kdtype], kmode=kqr.KQR_KMODE_MATERIALIZE, profile=1,
+                verbose=1 if args.verbose else 0)
 
     def one_fit():
-        return kqr.kqr_fit(X, y, prob.tau, prob.lam, prob.kernel, prob.gamma, uniforms=uni, **opts)
+        _, beta, info, st = kqr.kqr_fit(X, y, prob.tau, prob.lam, prob.kernel, prob.gamma, uniforms=uni, **opts)
+        return info, st
 
     tuned = {}
-    if not args.no_tune:
+    if tune:
         # untimed: pick the K-apply tile shapes on this problem's own K
         K = kqr.kqr_kernel_build(X, prob.kernel, prob.gamma, kdtype)
-        for mode, name in ((kqr.KQR_APPLY_FAST, "fast"), (kqr.KQR_APPLY_EXACT, "exact")):
+        modes = [(kqr.KQR_APPLY_FAST, "fast")]
+        if kdtype == "fp32":
+            modes.append((kqr.KQR_APPLY_EXACT, "exact"))
+        for mode, name in modes:
             rep = kqr.kqr_autotune_apply(K, mode, reps=3)
             tuned[name] = rep["best"]
         del K
         torch.cuda.empty_cache()
-
-    for _ in range(args.warmup):
-        one_fit()
-    torch.cuda.synchronize()
-    infos = []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        _, beta, info, st = one_fit()
-        infos.append((info, st))
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-
+    outs, elapsed = timed_fits(args, one_fit)
     n = prob.n
     kbytes = float(n) * n * esz
-    total_applies = sum(i["kapply_calls"] for i, _ in infos)
-    value = total_applies * kbytes / elapsed / 1e9
-    last, st = infos[-1]
-    nfast = sum(i["kapply_fast_calls"] for i, _ in infos)
-    tfast = sum(i["t_kapply_fast"] for i, _ in infos)
+    nfast = sum(i["kapply_fast_calls"] for i, _ in outs)
+    tfast = sum(i["t_kapply_fast"] for i, _ in outs)
+    value = nfast * kbytes / elapsed / 1e9
     avg = tfast / max(nfast, 1)
     achieved = kbytes / avg / 1e9 if avg > 0 else 0.0
     traffic = None
     if args.traffic and os.path.exists(args.traffic):
         traffic = json.load(open(args.traffic)).get("bytes_per_launch")
-    out = {
-        "metric": "K-apply GB/s (% HBM peak) + wall time to rel KKT 1e-6, FP32 vs BF16/batched",
-        "value": round(value, 2),
-        "unit": "GB/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(elapsed / args.steps * 1e3, 3),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32" if kdtype == "fp32" else "bf16",
-        "data": "synthetic",
-        "config": {
-            "workload": f"{prob.name}: {inputs.WORKLOADS[prob.name][1]}",
-            "n": n, "p": prob.p, "tau": prob.tau, "lambda": prob.lam, "gamma": prob.gamma,
-            "kernel": prob.kernel, "k_storage": kdtype, "rank": last["rank_used"], "tol": 1e-6,
-        },
-        "roofline": {
-            "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "kernel": "kapply_rows_kernel (fast, materialised %s K)" % kdtype,
-            "avg_launch_us": round(avg * 1e6, 2), "launches": int(nfast),
-            "bytes_per_launch": kbytes, "tile_shapes": tuned or "default",
-        },
-        "fit": {
-            "status": st, "eta_kkt": last["eta_kkt"], "eta_gap": last["eta_gap"], "obj_p": last["obj_p"],
-            "admm_iters": last["admm_iters"], "alm_iters": last["alm_iters"], "newton_iters": last["newton_iters"],
-            "admm_pcg_iters": last["admm_pcg_iters"], "pcg_iters": last["pcg_iters"],
-            "kapply_calls": last["kapply_calls"], "t_kbuild_s": round(last["t_kbuild"], 4),
-            "t_precond_s": round(last["t_precond"], 4), "t_admm_s": round(last["t_admm"], 4),
-            "t_alm_s": round(last["t_alm"], 4), "t_total_s": round(last["t_total"], 4),
-            "t_kapply_exact_avg_us": round(last["t_kapply_exact"] / max(last["kapply_exact_calls"], 1) * 1e6, 2),
-        },
+    last, st = outs[-1]
+    roof = {
+        "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+        "kernel": "kapply_rows_kernel (fast, materialised %s K)" % kdtype,
+        "avg_launch_us": round(avg * 1e6, 2), "launches": int(nfast),
+        "bytes_per_launch": kbytes, "tile_shapes": tuned or "default",
     }
+    del X, y
+    torch.cuda.empty_cache()
+    return value, elapsed / args.steps * 1e3, roof, fit_summary(last, st)
+
+
+def bench_single(args, prob):
+    kdtype = args.kdtype or prob.kdtype
+    value, ms, roof, fit = run_materialised(args, prob, kdtype, not args.no_tune)
+    out = base_line(args, prob, "f32" if kdtype == "fp32" else "bf16", {"k_storage": kdtype, "rank": fit["rank"]})
+    out.update(value=round(value, 2), ms_per_step=round(ms, 3), roofline=roof, fit=fit)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(prob, args.cpu_seconds)
+    return out
+
+
+def bench_c2(args, prob):
+    """BF16-stored K (+ FP64 refinement) against FP32 K on the same problem and GPU."""
+    v16, ms16, roof16, fit16 = run_materialised(args, prob, "bf16", not args.no_tune)
+    v32, ms32, roof32, fit32 = run_materialised(args, prob, "fp32", not args.no_tune)
+    out = base_line(args, prob, "bf16", {"k_storage": "bf16 (inner) + exact FP32 entries (residuals)",
+                                         "rank": fit16["rank"]})
+    out.update(value=round(v16, 2), ms_per_step=round(ms16, 3), roofline=roof16, fit=fit16)
+    out["compare_fp32"] = {"value": round(v32, 2), "ms_per_step": round(ms32, 3), "roofline": roof32, "fit": fit32,
+                           "bf16_speedup": round(ms32 / ms16, 3)}
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(prob, args.cpu_seconds)
+    return out
+
+
+def bench_otf(args, prob):
+    """Nothing stored: every K-apply recomputes the entries (VALU-bound)."""
+    import torch
+
+    from paper_2510_07929_amd import inputs, kqr
+
+    dev = torch.device("cuda:0")
+    X = torch.from_numpy(prob.X).to(dev)
+    y = torch.from_numpy(prob.y).to(dev)
+    uni = inputs.pivot_uniforms(1024, (sum(map(ord, prob.name)), 0))
+
+    def one_fit():
+        _, beta, info, st = kqr.kqr_fit(X, y, prob.tau, prob.lam, prob.kernel, prob.gamma, uniforms=uni, rank=0,
+                                        kmode=kqr.KQR_KMODE_ON_THE_FLY, profile=1, verbose=1 if args.verbose else 0)
+        return info, st
+
+    outs, elapsed = timed_fits(args, one_fit)
+    n = prob.n
+    pairs = float(n) * n
+    nfast = sum(i["kapply_fast_calls"] for i, _ in outs)
+    tfast = sum(i["t_kapply_fast"] for i, _ in outs)
+    avg = tfast / max(nfast, 1)
+    # lane operations per pair of the fast on-the-fly apply: p differences,
+    # p abs-adds (Laplacian) or p FMAs + 3 (RBF), exp2 (4 ops), 1 scale, 1 FMA
+    ops = (2 * prob.p if prob.kernel == "laplacian" else prob.p + 3) + 6
+    peak_pairs = VALU_LANE_OPS / ops
+    achieved = pairs / avg if avg > 0 else 0.0
+    last, st = outs[-1]
+    out = base_line(args, prob, "f32", {"k_storage": "none (on the fly)", "rank": last["rank_used"]})
+    out.update(unit="Gpair/s", value=round(nfast * pairs / elapsed / 1e9, 2), ms_per_step=round(elapsed / args.steps * 1e3, 3))
+    out["roofline"] = {
+        "bound": "alu", "achieved": round(achieved / 1e9, 2), "peak": round(peak_pairs / 1e9, 2), "unit": "Gpair/s",
+        "frac": round(achieved / peak_pairs, 4), "traffic": None,
+        "kernel": "kapply_otf_kernel (fast, %s, p=%d)" % (prob.kernel, prob.p), "avg_launch_us": round(avg * 1e6, 2),
+        "launches": int(nfast), "lane_ops_per_pair": ops,
+        "peak_note": "non-packed FP32 VALU lane-ops/s of 256 CUs at 2.4 GHz divided by lane ops per pair",
+    }
+    out["fit"] = fit_summary(last, st)
+    return out
+
+
+def bench_multi_tau(args, prob):
+    """Nine quantile levels jointly (one K, K V launches) against nine separate fits."""
+    import numpy as np
+    import torch
+
+    from paper_2510_07929_amd import inputs, kqr
+
+    dev = torch.device("cuda:0")
+    X = torch.from_numpy(prob.X).to(dev)
+    y = torch.from_numpy(prob.y).to(dev)
+    taus = prob.extras["taus"]
+    uni = inputs.pivot_uniforms(1024, (sum(map(ord, prob.name)), 0))
+    kd = args.kdtype or "fp32"
+    esz = 4 if kd == "fp32" else 2
+    opts = dict(rank=0, k_dtype=kqr.KDTYPES[kd], kmode=kqr.KQR_KMODE_MATERIALIZE, profile=1)
+
+    def joint():
+        _, betas, infos, sts = kqr.kqr_fit_multi_tau(X, y, taus, prob.lam, prob.kernel, prob.gamma, uniforms=uni,
+                                                     **opts)
+        return infos, sts
+
+    outs, elapsed = timed_fits(args, joint)
+    t_sep0 = time.perf_counter()
+    sep = [kqr.kqr_fit(X, y, t, prob.lam, prob.kernel, prob.gamma, uniforms=uni, **opts) for t in taus]
+    torch.cuda.synchronize()
+    t_sep = time.perf_counter() - t_sep0
+    infos, sts = outs[-1]
+    nl = infos[0]["kapply_fast_calls"]
+    tl = infos[0]["t_kapply_fast"]
+    avg = tl / max(nl, 1)
+    n = prob.n
+    kbytes = float(n) * n * esz
+    achieved = kbytes / avg / 1e9 if avg > 0 else 0.0
+    out = base_line(args, prob, "f32" if kd == "fp32" else "bf16", {"k_storage": kd, "taus": taus})
+    out.update(value=round(nl * kbytes * args.steps / elapsed / 1e9, 2), ms_per_step=round(elapsed / args.steps * 1e3, 3))
+    out["roofline"] = {
+        "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+        "kernel": "kv_mfma_kernel (K V, V n x 16, %s K)" % kd, "avg_launch_us": round(avg * 1e6, 2),
+        "launches": int(nl), "bytes_per_launch": kbytes,
+    }
+    out["fit"] = {"status": sts, "eta_kkt_max": max(i["eta_kkt"] for i in infos),
+                  "eta_gap_max": max(i["eta_gap"] for i in infos),
+                  "alm_iters": [i["alm_iters"] for i in infos], "kapply_calls": [i["kapply_calls"] for i in infos]}
+    out["compare_separate"] = {
+        "ms_total": round(t_sep * 1e3, 3), "status": [s for _, _, _, s in sep],
+        "eta_kkt_max": max(i["eta_kkt"] for _, _, i, _ in sep),
+        "kapply_calls": int(np.sum([i["kapply_calls"] for _, _, i, _ in sep])),
+        "joint_speedup": round(t_sep / (elapsed / args.steps), 3),
+    }
+    return out
+
+
+def bench_batch(args):
+    """64 uneven problems in one batched fit against the same fits one at a time."""
+    import numpy as np
+    import torch
+
+    from paper_2510_07929_amd import inputs, kqr
+
+    dev = torch.device("cuda:0")
+    probs = inputs.uneven_batch()
+    Xs = [torch.from_numpy(p.X).to(dev) for p in probs]
+    ys = [torch.from_numpy(p.y).to(dev) for p in probs]
+    taus = [p.tau for p in probs]
+    lams = [p.lam for p in probs]
+    gams = [p.gamma for p in probs]
+    opts = dict(rank=0, kmode=kqr.KQR_KMODE_MATERIALIZE, profile=1)
+
+    def batch():
+        _, betas, infos, sts = kqr.kqr_fit_batch(Xs, ys, taus, lams, gams, "rbf", **opts)
+        return infos, sts
+
+    outs, elapsed = timed_fits(args, batch)
+    t0 = time.perf_counter()
+    sep = [kqr.kqr_fit(Xs[i], ys[i], taus[i], lams[i], "rbf", gams[i], **opts) for i in range(len(probs))]
+    torch.cuda.synchronize()
+    t_sep = time.perf_counter() - t0
+    infos, sts = outs[-1]
+    nl = infos[0]["kapply_fast_calls"]
+    tl = infos[0]["t_kapply_fast"]
+    ns = [p.n for p in probs]
+    out = {
+        "metric": METRIC, "value": None, "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(elapsed / args.steps * 1e3, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "c3b: 64 uneven problems, n_i ~ U{500..8000}, p=10, RBF gamma=1/p, tau=0.5, "
+                               "lambda_i=1e-3 n_i", "n_min": min(ns), "n_max": max(ns), "sum_n2": int(sum(n * n for n in ns))},
+    }
+    kapply_sep = int(np.sum([i["kapply_calls"] for _, _, i, _ in sep]))
+    # every apply of a problem streams that problem's K once; the batched launches carry them all
+    per_problem_calls = [i["kapply_calls"] for i in infos]
+    streamed = float(sum(c * p.n * p.n * 4 for c, p in zip(per_problem_calls, probs)))
+    out["value"] = round(streamed / (elapsed / args.steps) / 1e9, 2)
+    out["roofline"] = {
+        "bound": "hbm", "achieved": round(streamed / max(tl, 1e-12) / 1e9, 1) if tl > 0 else None, "peak": HBM_PEAK_GBS,
+        "unit": "GB/s", "frac": round(streamed / max(tl, 1e-12) / 1e9 / HBM_PEAK_GBS, 4) if tl > 0 else None,
+        "traffic": None, "kernel": "kapply_problems_kernel (one launch over (problem, row block) pairs)",
+        "launches": int(nl), "avg_launch_us": round(tl / max(nl, 1) * 1e6, 2),
+        "note": "achieved = bytes of every problem's K over all its applies / device time of the batched launches; "
+                "K matrices of up to 256 MB sit partly in the 256 MB last-level cache",
+    }
+    out["fit"] = {"status_ok": int(sum(1 for s in sts if s == 0)), "eta_kkt_max": max(i["eta_kkt"] for i in infos),
+                  "eta_gap_max": max(i["eta_gap"] for i in infos), "kapply_calls_total": int(sum(per_problem_calls))}
+    out["compare_separate"] = {"ms_total": round(t_sep * 1e3, 3), "kapply_calls_total": kapply_sep,
+                               "batch_speedup": round(t_sep / (elapsed / args.steps), 3)}
+    return out
+
+
+def bench_grad(args, prob):
+    """Fit + implicit adjoint of the validation check loss (c4)."""
+    import torch
+
+    from paper_2510_07929_amd import inputs, kqr
+
+    dev = torch.device("cuda:0")
+    X = torch.from_numpy(prob.X).to(dev)
+    y = torch.from_numpy(prob.y).to(dev)
+    Xv = torch.from_numpy(prob.extras["Xval"]).to(dev)
+    yv = torch.from_numpy(prob.extras["yval"]).to(dev)
+    uni = inputs.pivot_uniforms(1024, (sum(map(ord, prob.name)), 0))
+    opts = dict(rank=0, kmode=kqr.KQR_KMODE_MATERIALIZE, profile=1, uniforms=uni)
+
+    def grad_at(gam, lam):
+        return kqr.kqr_fit_grad(X, y, prob.tau, lam, prob.kernel, gam, Xv, yv, **opts)
+
+    def step():
+        return grad_at(prob.gamma, prob.lam)
+
+    outs, elapsed = timed_fits(args, step)
+    t0 = time.perf_counter()
+    _, _, info_fit, st_fit = kqr.kqr_fit(X, y, prob.tau, prob.lam, prob.kernel, prob.gamma, **opts)
+    torch.cuda.synchronize()
+    t_fit = time.perf_counter() - t0
+    alpha, beta, J, (dg, dl), m, pol, info, st = outs[-1]
+    n = prob.n
+    out = base_line(args, prob, "f32", {"k_storage": "fp32", "nval": int(Xv.shape[0])})
+    out.update(unit="GB/s", ms_per_step=round(elapsed / args.steps * 1e3, 3))
+    nfast, tfast = info["kapply_fast_calls"], info["t_kapply_fast"]
+    kbytes = float(n) * n * 4
+    avg = tfast / max(nfast, 1)
+    out["value"] = round(nfast * kbytes / (elapsed / args.steps) / 1e9, 2)
+    out["roofline"] = {"bound": "hbm", "achieved": round(kbytes / avg / 1e9, 1) if avg > 0 else None,
+                       "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(kbytes / avg / 1e9 / HBM_PEAK_GBS, 4)
+                       if avg > 0 else None, "traffic": None, "kernel": "kapply_rows_kernel (fit part)",
+                       "avg_launch_us": round(avg * 1e6, 2), "launches": int(nfast)}
+    out["grad"] = {"J": J, "dJ_dlog_gamma": dg, "dJ_dlog_lambda": dl, "n_interior": m, "polished": pol,
+                   "status": st, "ms_fit_only": round(t_fit * 1e3, 3),
+                   "ms_adjoint": round(elapsed / args.steps * 1e3 - t_fit * 1e3, 3)}
+    if args.fd:
+        h = 1e-4
+        t0 = time.perf_counter()
+        fd_g = (grad_at(prob.gamma * math.exp(h), prob.lam)[2] - grad_at(prob.gamma * math.exp(-h), prob.lam)[2]) / (2 * h)
+        fd_l = (grad_at(prob.gamma, prob.lam * math.exp(h))[2] - grad_at(prob.gamma, prob.lam * math.exp(-h))[2]) / (2 * h)
+        out["grad"]["fd"] = {"h": h, "dJ_dlog_gamma": fd_g, "dJ_dlog_lambda": fd_l,
+                             "rel_gamma": abs(fd_g - dg) / max(abs(dg), 1e-300),
+                             "rel_lambda": abs(fd_l - dl) / max(abs(dl), 1e-300),
+                             "seconds": round(time.perf_counter() - t0, 3)}
+    return out
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    from paper_2510_07929_amd import inputs
+
+    w = args.workload
+    if w == "c3b":
+        out = bench_batch(args)
+    else:
+        prob = inputs.workload(w, n=args.n)
+        if w == "c2" and args.kdtype is None:
+            out = bench_c2(args, prob)
+        elif w == "c2lap":
+            out = bench_otf(args, prob)
+        elif w == "c3a":
+            out = bench_multi_tau(args, prob)
+        elif w == "c4":
+            out = bench_grad(args, prob)
+        else:
+            out = bench_single(args, prob)
     print(json.dumps(out), flush=True)
 
 

@@ -263,7 +263,8 @@ int kqr_predict(const float* Xtrain, int64_t n, int64_t p, const double* alpha, 
     KQR_CHECK_HIP(hipMallocAsync(reinterpret_cast<void**>(&sq), size_t(n + m) * sizeof(float), st));
     row_sqnorms(Xtrain, n, int(p), sq, st);
     row_sqnorms(Xnew, m, int(p), sq + n, st);
-    kapply_otf(Xnew, sq + n, m, Xtrain, sq, n, int(p), KernelSpec{kernel, gamma}, alpha, f, 1, 1.0 / lambda, beta, st);
+    kapply_otf(Xnew, sq + n, m, Xtrain, sq, n, int(p), KernelSpec{kernel, gamma}, alpha, f, 1, 1.0 / lambda, beta, st,
+               true);
     KQR_CHECK_HIP(hipFreeAsync(sq, st));
   });
 }

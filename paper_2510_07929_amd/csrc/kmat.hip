@@ -355,13 +355,17 @@ void kapply_dense(const KMat& km, int64_t nrows, int64_t ncols, const float* v32
 // ================================================================= on-the-fly K-apply
 // One thread per output row i keeps x_i (and ||x_i||^2) in registers; the
 // block walks a slice of the columns in tiles of 64 staged in LDS (x_j, the
-// norms and v_j, read as broadcasts), forms k(x_i, x_j) and accumulates
-// k * v_j in FP32 over a tile, then into an FP64 accumulator.  Columns are
-// split over gridDim.y slices so that small row counts still fill the chip;
-// the slices' partial sums are added in a fixed order by a second kernel.
+// norms and v_j, read as broadcasts) and forms k(x_i, x_j) in FP32.
+//   fast  (EX=false): k * v_j accumulated in FP32 over a tile (v rounded to
+//                     FP32), then into an FP64 accumulator;
+//   exact (EX=true) : the FP32 entry times the FP64 v_j, FP64 products and
+//                     sums (the exact operator of the residuals).
+// Columns are split over gridDim.y slices so that small row counts still fill
+// the chip; the slices' partial sums are added in a fixed order by a second
+// kernel.
 constexpr int kOtfTile = 64;
 
-template <int PMAX, bool LAP, bool DK>
+template <int PMAX, bool LAP, bool EX>
 __global__ __launch_bounds__(256) void kapply_otf_kernel(
     const float* __restrict__ Xr, const float* __restrict__ qr, int64_t nr,
     const float* __restrict__ Xc, const float* __restrict__ qc, int64_t nc, int p, float ng,
@@ -369,6 +373,7 @@ __global__ __launch_bounds__(256) void kapply_otf_kernel(
   __shared__ float xs[kOtfTile][PMAX];
   __shared__ float qs[kOtfTile];
   __shared__ float vs[kOtfTile];
+  __shared__ double vd[kOtfTile];
   const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
   const bool row_ok = i < nr;
   float xi[PMAX];
@@ -388,16 +393,24 @@ __global__ __launch_bounds__(256) void kapply_otf_kernel(
     if (threadIdx.x < kOtfTile) {
       const int jj = threadIdx.x;
       qs[jj] = (jj < cnt && !LAP) ? qc[jb + jj] : 0.f;
-      vs[jj] = jj < cnt ? float(v[jb + jj]) : 0.f;
+      const double vj = jj < cnt ? v[jb + jj] : 0.0;
+      if (EX) vd[jj] = vj;
+      else vs[jj] = float(vj);
     }
     __syncthreads();
-    float a32 = 0.f;
-    for (int jj = 0; jj < cnt; ++jj) {
-      const float d = pair_dist<PMAX, LAP>(xs[jj], qs[jj], xi, qi);
-      const float kv = exp2f(ng * d);
-      a32 = fmaf(DK ? d * kv : kv, vs[jj], a32);  // DK: entries d_ij k_ij
+    if (EX) {
+      for (int jj = 0; jj < cnt; ++jj) {
+        const float d = pair_dist<PMAX, LAP>(xs[jj], qs[jj], xi, qi);
+        acc = fma(double(exp2f(ng * d)), vd[jj], acc);
+      }
+    } else {
+      float a32 = 0.f;
+      for (int jj = 0; jj < cnt; ++jj) {
+        const float d = pair_dist<PMAX, LAP>(xs[jj], qs[jj], xi, qi);
+        a32 = fmaf(exp2f(ng * d), vs[jj], a32);
+      }
+      acc += double(a32);
     }
-    acc += double(a32);
   }
   if (row_ok) part[int64_t(blockIdx.y) * nr + i] = acc;
 }
@@ -414,7 +427,7 @@ __global__ void otf_reduce_kernel(const double* __restrict__ part, int nslice, i
 template <int PMAX>
 static void kapply_otf_p(const float* Xr, const float* qr, int64_t nr, const float* Xc,
                          const float* qc, int64_t nc, int p, KernelSpec ks, const double* v, double* u,
-                         int64_t ldu, double scale, double shift, bool dk, hipStream_t st) {
+                         int64_t ldu, double scale, double shift, bool exact, hipStream_t st) {
   const int64_t rblk = (nr + 255) / 256;
   // enough column slices for ~2048 blocks, each slice at least 1024 columns
   int64_t nslice = std::max<int64_t>(1, std::min<int64_t>(2048 / std::max<int64_t>(rblk, 1), (nc + 1023) / 1024));
@@ -427,9 +440,9 @@ static void kapply_otf_p(const float* Xr, const float* qr, int64_t nr, const flo
   const dim3 grid((unsigned)rblk, (unsigned)nslice);
   const float ng = -float(ks.gamma) * kLog2e;
   const bool lap = ks.kind == KQR_LAPLACIAN;
-  if (lap && dk) kapply_otf_kernel<PMAX, true, true><<<grid, 256, 0, st>>>(Xr, qr, nr, Xc, qc, nc, p, ng, v, per, part);
+  if (lap && exact) kapply_otf_kernel<PMAX, true, true><<<grid, 256, 0, st>>>(Xr, qr, nr, Xc, qc, nc, p, ng, v, per, part);
   else if (lap) kapply_otf_kernel<PMAX, true, false><<<grid, 256, 0, st>>>(Xr, qr, nr, Xc, qc, nc, p, ng, v, per, part);
-  else if (dk) kapply_otf_kernel<PMAX, false, true><<<grid, 256, 0, st>>>(Xr, qr, nr, Xc, qc, nc, p, ng, v, per, part);
+  else if (exact) kapply_otf_kernel<PMAX, false, true><<<grid, 256, 0, st>>>(Xr, qr, nr, Xc, qc, nc, p, ng, v, per, part);
   else kapply_otf_kernel<PMAX, false, false><<<grid, 256, 0, st>>>(Xr, qr, nr, Xc, qc, nc, p, ng, v, per, part);
   KQR_LAUNCH_CHECK();
   otf_reduce_kernel<<<dim3((unsigned)((nr + 255) / 256)), 256, 0, st>>>(part, int(nslice), nr, u, ldu, scale, shift);
@@ -439,9 +452,9 @@ static void kapply_otf_p(const float* Xr, const float* qr, int64_t nr, const flo
 
 void kapply_otf(const float* Xr, const float* sqr, int64_t nr, const float* Xc, const float* sqc,
                 int64_t nc, int p, KernelSpec ks, const double* v64, double* u, int64_t ldu,
-                double out_scale, double out_shift, hipStream_t st, bool dk) {
+                double out_scale, double out_shift, hipStream_t st, bool exact) {
   if (nr <= 0) return;
-  KQR_DISPATCH_P(p, kapply_otf_p, Xr, sqr, nr, Xc, sqc, nc, p, ks, v64, u, ldu, out_scale, out_shift, dk, st);
+  KQR_DISPATCH_P(p, kapply_otf_p, Xr, sqr, nr, Xc, sqc, nc, p, ks, v64, u, ldu, out_scale, out_shift, exact, st);
 }
 
 // ================================================================= one kernel row

@@ -97,12 +97,12 @@ void row_sqnorms(const float* X, int64_t n, int p, float* sqn, hipStream_t st);
 // u = K v (materialised, rows [0, nrows), cols [0, ncols)).  exact: v64 + FP64; else v32.
 void kapply_dense(const KMat& km, int64_t nrows, int64_t ncols, const float* v32, const double* v64,
                   double* u, int64_t ldu, bool exact, hipStream_t st, const ApplyShape* shape = nullptr);
-// u = shift + scale K(Xr, Xc) v computed on the fly; v64 FP64, products in
-// FP32, FP64 row sums.  dk: use the entries d_ij k_ij (d the kernel's distance)
-// instead of k_ij, so that scale = -gamma gives (K o ln K) v.
+// u = shift + scale K(Xr, Xc) v computed on the fly from FP32 entries.
+// exact = false: v rounded to FP32, FP32 products summed in FP32 over tiles
+// of 64 columns, FP64 across tiles; exact = true: FP64 v, products and sums.
 void kapply_otf(const float* Xr, const float* sqr, int64_t nr, const float* Xc, const float* sqc,
                 int64_t nc, int p, KernelSpec ks, const double* v64, double* u, int64_t ldu,
-                double out_scale, double out_shift, hipStream_t st, bool dk = false);
+                double out_scale, double out_shift, hipStream_t st, bool exact = false);
 // y = A x for a skinny FP32 matrix A (nrows x ncols, ncols <= 1024, lda a
 // multiple of 4) and FP64 x, y; FP64 products and sums.
 void gemv_skinny(const float* A, int64_t lda, int64_t nrows, int64_t ncols, const double* x, double* y,

@@ -81,7 +81,7 @@ void Operator::apply_exact(const double* v, double* u, hipStream_t st) {
     kapply_dense(km_, n_, n_, nullptr, v, u, 1, true, st);
   } else {
     // BF16 storage is not the exact operator: recompute FP32 entries from X.
-    kapply_otf(X_, sqn_.as<float>(), n_, X_, sqn_.as<float>(), n_, p_, ks_, v, u, 1, 1.0, 0.0, st);
+    kapply_otf(X_, sqn_.as<float>(), n_, X_, sqn_.as<float>(), n_, p_, ks_, v, u, 1, 1.0, 0.0, st, true);
   }
   mark(false, false, st);
 }
@@ -373,6 +373,9 @@ void Solver::ssn(double stop, kqr_info& info) {
     if (cstep == 0.0) cstep = c0;  // backtracking cap reached: take the last (tiny) step
     axpy2(n, cstep, d_.as<double>(), alpha_.as<double>(), Kd_.as<double>(), Ka_.as<double>(), st_);
     ++info.newton_iters;
+    if (o_.verbose)
+      fprintf(stderr, "[kqr]   newton %2d |grad| %.3e (stop %.1e) pcg %3d res %.2e tol %.2e step %.3g\n", t + 1, gn,
+              stop, ps.iters, ps.resnorm, tol, cstep);
   }
 }
 

@@ -136,16 +136,31 @@ __global__ __launch_bounds__(256) void flag_count_kernel(const uint8_t* __restri
   if (threadIdx.x == 0) counts[blockIdx.x] = sh[0];
 }
 
-__global__ void flag_scan_kernel(int* __restrict__ counts, int nblk, int* __restrict__ total) {
-  if (threadIdx.x == 0) {
-    int acc = 0;
-    for (int b = 0; b < nblk; ++b) {
-      const int c = counts[b];
-      counts[b] = acc;
-      acc += c;
-    }
-    total[0] = acc;
+// Exclusive scan of nblk <= 256 counts in place by one wave (4 per lane).
+__global__ __launch_bounds__(64) void flag_scan_kernel(int* __restrict__ counts, int nblk, int* __restrict__ total) {
+  const int l = threadIdx.x;
+  int c[4];
+  int s = 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int b = l * 4 + q;
+    c[q] = b < nblk ? counts[b] : 0;
+    s += c[q];
   }
+  int incl = s;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int t = __shfl_up(incl, off);
+    if (l >= off) incl += t;
+  }
+  int excl = incl - s;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int b = l * 4 + q;
+    if (b < nblk) counts[b] = excl;
+    excl += c[q];
+  }
+  if (l == 63) total[0] = incl;
 }
 
 // Each block writes the indices of its chunk in increasing order (one wave scans).
@@ -165,11 +180,14 @@ __global__ __launch_bounds__(64) void flag_scatter_kernel(const uint8_t* __restr
 
 // ---------------------------------------------------------------- blocked Cholesky (lower)
 // Diagonal block (nb <= 64): one wave, lane l holds row l in registers.  At
-// column j lane j takes the square root of its (already updated) diagonal,
-// every lane scales its entry of column j, and lane l updates its entries
-// k in (j, l] with the column-j entries of lanes k (shuffles).
+// column j lane j takes the square root of its (already updated) diagonal and
+// every lane publishes its column-j entry to LDS; lanes then scale by the
+// broadcast reciprocal and update their entries k in (j, l] with the
+// column-j entries read back as LDS broadcasts.  Stored and applied factors
+// use the same product, so the result does not depend on the lane.
 __global__ __launch_bounds__(64) void chol_diag_kernel(double* __restrict__ C, int64_t ldc, int kb, int nb,
                                                        int* __restrict__ flag) {
+  __shared__ double col[kNb];
   const int l = threadIdx.x;
   double a[kNb];
   const double* row = C + int64_t(kb + (l < nb ? l : 0)) * ldc + kb;
@@ -178,21 +196,26 @@ __global__ __launch_bounds__(64) void chol_diag_kernel(double* __restrict__ C, i
   bool bad = false;
 #pragma unroll
   for (int j = 0; j < kNb; ++j) {
-    double piv = __shfl(a[j], j);
-    if (!(piv > 0.0) || !isfinite(piv)) {
-      bad = true;
-      piv = 1e-300;
+    if (l == j) {
+      double piv = a[j];
+      if (!(piv > 0.0) || !isfinite(piv)) {
+        bad = true;
+        piv = 1e-300;
+      }
+      a[j] = sqrt(piv);
     }
-    const double d = sqrt(piv);
-    if (l == j) a[j] = d;
-    if (l > j) a[j] /= d;
+    col[l] = a[j];
+    __syncthreads();
+    const double rinv = 1.0 / col[j];
+    if (l > j) a[j] *= rinv;
 #pragma unroll
     for (int k = j + 1; k < kNb; ++k) {
-      const double ckj = __shfl(a[j], k);
+      const double ckj = col[k] * rinv;
       if (l >= k) a[k] = fma(-a[j], ckj, a[k]);
     }
+    __syncthreads();
   }
-  if (bad && l == 0 && nb > 0) flag[0] = 1;
+  if (bad && nb > 0) flag[0] = 1;
   if (l < nb) {
     double* w = C + int64_t(kb + l) * ldc + kb;
 #pragma unroll
@@ -201,27 +224,39 @@ __global__ __launch_bounds__(64) void chol_diag_kernel(double* __restrict__ C, i
   }
 }
 
-// Panel: rows i >= kb+nb solve x L_kk^T = C[i, kb:kb+nb].  One wave per row,
-// lane k owns x_k; column j is finished by lane j and broadcast.
-__global__ __launch_bounds__(256) void chol_panel_kernel(double* __restrict__ C, int64_t ldc, int kb, int nb,
-                                                         int R1) {
+// Panel: rows i >= kb+nb solve x L_kk^T = C[i, kb:kb+nb].  One lane per row
+// with the row in registers (staged through LDS so the global reads are
+// coalesced); L_kk entries are LDS broadcasts.
+__global__ __launch_bounds__(64) void chol_panel_kernel(double* __restrict__ C, int64_t ldc, int kb, int nb,
+                                                        int R1) {
   __shared__ double Lk[kNb][kNb + 1];
-  for (int e = threadIdx.x; e < kNb * kNb; e += 256) {
+  __shared__ double Rw[64][kNb + 1];
+  const int l = threadIdx.x;
+  const int64_t r0 = int64_t(kb) + nb + int64_t(blockIdx.x) * 64;
+  for (int e = l; e < kNb * kNb; e += 64) {
     const int i = e / kNb, k = e % kNb;
     Lk[i][k] = (i < nb && k <= i) ? C[int64_t(kb + i) * ldc + kb + k] : (i == k ? 1.0 : 0.0);
+    const int64_t ri = r0 + i;
+    Rw[i][k] = (ri < R1 && k < nb) ? C[ri * ldc + kb + k] : 0.0;
   }
   __syncthreads();
-  const int k = threadIdx.x & 63;
-  const int64_t i = int64_t(kb) + nb + int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
-  const bool ok = i < R1;
-  double* row = C + (ok ? i : 0) * ldc + kb;
-  double x = (ok && k < nb) ? row[k] : 0.0;
+  double x[kNb];
+#pragma unroll
+  for (int k = 0; k < kNb; ++k) x[k] = Rw[l][k];
+#pragma unroll
   for (int j = 0; j < kNb; ++j) {
-    if (k == j) x /= Lk[j][j];
-    const double xj = __shfl(x, j);
-    if (k > j) x = fma(-xj, Lk[k][j], x);
+    x[j] /= Lk[j][j];
+#pragma unroll
+    for (int k = j + 1; k < kNb; ++k) x[k] = fma(-x[j], Lk[k][j], x[k]);
   }
-  if (ok && k < nb) row[k] = x;
+#pragma unroll
+  for (int k = 0; k < kNb; ++k) Rw[l][k] = x[k];
+  __syncthreads();
+  for (int e = l; e < 64 * kNb; e += 64) {
+    const int i = e / kNb, k = e % kNb;
+    const int64_t ri = r0 + i;
+    if (ri < R1 && k < nb) C[ri * ldc + kb + k] = Rw[i][k];
+  }
 }
 
 // Trailing update of the lower part: C[i][j] -= sum_k P[i][k] P[j][k], j <= i,
@@ -272,13 +307,13 @@ __global__ __launch_bounds__(256) void chol_update_kernel(double* __restrict__ C
 }
 
 // ---------------------------------------------------------------- W = Lc^{-1}
-// Inverse of each 64 x 64 diagonal block; lane j forms column j by forward
-// substitution.  Blocks are independent (one workgroup each).  W must be zero
-// outside the blocks written here before the doubling steps run.
+// Inverse of each 64 x 64 diagonal block by forward substitution; lane j
+// holds column j of the inverse in registers and reads the factor's rows as
+// LDS broadcasts.  Blocks are independent (one workgroup each).  W must be
+// zero outside the blocks written here before the doubling steps run.
 __global__ __launch_bounds__(64) void trinv_diag_kernel(const double* __restrict__ C, int64_t ldc, int R1,
                                                         double* __restrict__ W) {
   __shared__ double Lk[kNb][kNb + 1];
-  __shared__ double X[kNb][kNb + 1];
   const int kb = blockIdx.x * kNb;
   const int nb = min(kNb, R1 - kb);
   const int j = threadIdx.x;
@@ -287,15 +322,18 @@ __global__ __launch_bounds__(64) void trinv_diag_kernel(const double* __restrict
     Lk[i][k] = (i < nb && k <= i) ? C[int64_t(kb + i) * ldc + kb + k] : (i == k ? 1.0 : 0.0);
   }
   __syncthreads();
+  double x[kNb];
+#pragma unroll
   for (int i = 0; i < kNb; ++i) {
     double s = (i == j) ? 1.0 : 0.0;
-    for (int k = j; k < i; ++k) s = fma(-Lk[i][k], X[k][j], s);
-    X[i][j] = (i >= j) ? s / Lk[i][i] : 0.0;
+#pragma unroll
+    for (int k = 0; k < i; ++k) s = fma(-Lk[i][k], x[k], s);
+    x[i] = s / Lk[i][i];
   }
-  __syncthreads();
-  for (int e = j; e < kNb * kNb; e += 64) {
-    const int i = e / kNb, k = e % kNb;
-    if (i < nb && k < nb) W[int64_t(kb + i) * ldc + kb + k] = X[i][k];
+  if (j < nb) {
+#pragma unroll
+    for (int i = 0; i < kNb; ++i)
+      if (i < nb) W[int64_t(kb + i) * ldc + kb + j] = x[i];
   }
 }
 
@@ -554,7 +592,7 @@ void spd_factor_inverse(double* C, int64_t ldc, int R1, double* W, double* WT, d
     KQR_LAUNCH_CHECK();
     const int rest = R1 - kb - nb;
     if (rest > 0) {
-      chol_panel_kernel<<<(rest + 3) / 4, 256, 0, st>>>(C, ldc, kb, nb, R1);
+      chol_panel_kernel<<<(rest + 63) / 64, 64, 0, st>>>(C, ldc, kb, nb, R1);
       KQR_LAUNCH_CHECK();
       const int mt = (rest + kT - 1) / kT;
       chol_update_kernel<<<mt * (mt + 1) / 2, 256, 0, st>>>(C, ldc, kb, nb, R1);

@@ -116,8 +116,11 @@ def test_autograd_function(dev):
     say("autograd function")
     loss = kqr.kqr_validation_loss(lg, ll, X, y, Xv, yv, prob.tau, "rbf", tol=1e-8)
     (3.0 * loss).backward()
-    _, _, J, (dg, dl), _, _, _, _ = _gpu(prob, dev, "rbf", gamma, tol=1e-8)
-    assert float(loss) == J
+    # same (gamma, lambda) as the Function saw after the exp of the logs: bitwise the same fit
+    g_in = float(torch.exp(lg.detach()))
+    l_in = float(torch.exp(ll.detach()))
+    _, _, J, (dg, dl), _, _, _, _ = _gpu(prob, dev, "rbf", g_in, lam=l_in, tol=1e-8)
+    assert float(loss.detach()) == J
     assert float(lg.grad) == pytest.approx(3.0 * dg, rel=1e-12)
     assert float(ll.grad) == pytest.approx(3.0 * dl, rel=1e-12)
 
