@@ -147,7 +147,7 @@ def timed_fits(args, one_fit):
     return outs, time.perf_counter() - t0
 
 
-def run_materialised(args, prob, kdtype, tune):
+def run_materialised(args, prob, kdtype, tune, **extra):
     """Timed single-problem fits with K stored (fp32 or bf16); returns (line pieces)."""
     import torch
 
@@ -160,7 +160,7 @@ def run_materialised(args, prob, kdtype, tune):
     rank = prob.rank if prob.rank > 0 else 0
     uni = inputs.pivot_uniforms(1024, (sum(map(ord, prob.name)), 0))
     opts = dict(rank=rank, k_dtype=kqr.KDTYPES[kdtype], kmode=kqr.KQR_KMODE_MATERIALIZE, profile=1,
-                verbose=1 if args.verbose else 0)
+                verbose=1 if args.verbose else 0, **extra)
 
     def one_fit():
         _, beta, info, st = kqr.kqr_fit(X, y, prob.tau, prob.lam, prob.kernel, prob.gamma, uniforms=uni, **opts)
@@ -215,10 +215,14 @@ def bench_single(args, prob):
 def bench_c2(args, prob):
     """BF16-stored K (+ FP64 refinement) against FP32 K on the same problem and GPU."""
     v16, ms16, roof16, fit16 = run_materialised(args, prob, "bf16", not args.no_tune)
+    v16c, ms16c, roof16c, fit16c = run_materialised(args, prob, "bf16", False, exact_k=1)
     v32, ms32, roof32, fit32 = run_materialised(args, prob, "fp32", not args.no_tune)
-    out = base_line(args, prob, "bf16", {"k_storage": "bf16 (inner) + exact FP32 entries (residuals)",
+    out = base_line(args, prob, "bf16", {"k_storage": "bf16 (inner) + exact FP32 entries recomputed from X",
                                          "rank": fit16["rank"]})
     out.update(value=round(v16, 2), ms_per_step=round(ms16, 3), roofline=roof16, fit=fit16)
+    out["compare_bf16_fp32_copy"] = {"k_storage": "bf16 (inner) + FP32 copy of K (exact applies)",
+                                     "value": round(v16c, 2), "ms_per_step": round(ms16c, 3), "roofline": roof16c,
+                                     "fit": fit16c, "speedup_vs_fp32": round(ms32 / ms16c, 3)}
     out["compare_fp32"] = {"value": round(v32, 2), "ms_per_step": round(ms32, 3), "roofline": roof32, "fit": fit32,
                            "bf16_speedup": round(ms32 / ms16, 3)}
     if not args.no_cpu:

@@ -96,12 +96,17 @@ typedef struct kqr_options {
   int pcg_max_iter;    /* per linear solve; 2000 */
   int k_dtype;         /* KQR_FP32 or KQR_BF16 storage of a materialised K; KQR_FP32 */
   int kmode;           /* KQR_KMODE_*; KQR_KMODE_AUTO */
-  int refine;          /* BF16 K: 1 = FP64 outer residual refinement with exact entries; 1 */
+  int refine;          /* BF16 K: 1 = every Phase II linear system is refined with FP64 residuals of the
+                          exact operator (Phase I, a warm start, runs on the BF16 operator alone and
+                          K alpha is recomputed exactly when Phase II starts); 1 */
   const double* pivot_uniforms; /* host, >= max(rank, ceil(sqrt n)) uniforms in [0,1) that
                                    drive RPCholesky's pivot draws; NULL = derive from `seed` */
   uint64_t seed;       /* used when pivot_uniforms is NULL; 0 */
   int verbose;         /* 1: one line per outer iteration on stderr; 0 */
   int profile;         /* 1: time every K-apply kernel with HIP events (kqr_info.t_kapply_*); 0 */
+  int exact_k;         /* BF16 storage: source of the exact operator of the residuals and refinement.
+                          0 = FP32 entries recomputed from X on every exact apply (no extra memory);
+                          1 = an FP32 copy of K kept beside the BF16 one (n*ld*4 more bytes, streamed). 0 */
 } kqr_options;
 
 /* ---------------------------------------------------------------- report */

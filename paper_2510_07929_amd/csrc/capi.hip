@@ -485,6 +485,7 @@ int kqr_fit(const float* X, const double* y, int64_t n, int64_t p, double tau, d
     const KernelSpec ks{kernel, gamma};
     Prepared pr = prepare_fit(X, n, int(p), ks, o, st);
     Operator op(X, n, int(p), ks, pr.kmat(), st);
+    pr.attach(op);
     op.enable_profile(o.profile != 0);
     FitOutcome out = run_fit(op, pr, y, n, tau, lambda, o, alpha, st);
     *beta = out.beta;
@@ -565,6 +566,7 @@ int kqr_fit_grad(const float* X, const double* y, int64_t n, int64_t p, double t
     {
       Prepared pr = prepare_fit(X, n, int(p), ks, o, st);
       Operator op(X, n, int(p), ks, pr.kmat(), st);
+      pr.attach(op);
       op.enable_profile(o.profile != 0);
       FitOutcome out = run_fit(op, pr, y, n, tau, lambda, o, alpha, st, z.as<double>());
       b = out.beta;

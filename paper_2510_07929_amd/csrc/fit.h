@@ -14,11 +14,17 @@ struct Prepared {
   DevBuf K;
   int64_t ldk = 0;
   int dtype = KQR_FP32;
+  DevBuf K32;  // FP32 copy beside a BF16 K (exact applies), when requested
   DevBuf F;
   int64_t ldf = 4;
   int64_t rank = 0;
   double t_kbuild = 0.0, t_precond = 0.0;
   KMat kmat() const { return KMat{K.ptr, dtype, ldk}; }
+  KMat kmat_exact() const { return KMat{K32.ptr, KQR_FP32, ldk}; }
+  // Operator over this K (and its FP32 copy for the exact applies, if any).
+  void attach(Operator& op) const {
+    if (K32.ptr) op.set_exact(kmat_exact());
+  }
 };
 
 // Materialises K (per o.kmode / o.k_dtype) and builds F (fixed rank, the

@@ -47,6 +47,7 @@ void validate_options(const kqr_options& o) {
   KQR_OPT_REQUIRE(o.tau1 > 0.0 && o.tau1 < 1.0 && o.tau2 > 0.0 && o.tau2 < 1.0, "need tau1, tau2 in (0,1)");
   KQR_OPT_REQUIRE(o.k_dtype == KQR_FP32 || o.k_dtype == KQR_BF16, "k_dtype must be KQR_FP32 or KQR_BF16");
   KQR_OPT_REQUIRE(o.kmode >= KQR_KMODE_AUTO && o.kmode <= KQR_KMODE_ON_THE_FLY, "invalid kmode");
+  KQR_OPT_REQUIRE(o.exact_k == 0 || o.exact_k == 1, "exact_k must be 0 or 1");
   KQR_OPT_REQUIRE(o.rank <= 1023, "rank must be <= 1023");
   KQR_OPT_REQUIRE(o.xi > 0.0 && o.xi < 1.0, "need 0 < xi < 1");
   KQR_OPT_REQUIRE(o.sigma_factor >= 1.0 && o.sigma_max >= o.admm_sigma,
@@ -72,6 +73,10 @@ Prepared prepare_fit(const float* X, int64_t n, int p, KernelSpec ks, const kqr_
   if (materialize) {
     pr.K.alloc(kbytes);
     kbuild(X, sqn.as<float>(), n, p, ks, o.k_dtype, pr.K.ptr, pr.ldk, st);
+    if (o.k_dtype == KQR_BF16 && o.exact_k == 1) {
+      pr.K32.alloc(size_t(n) * size_t(pr.ldk) * 4);
+      kbuild(X, sqn.as<float>(), n, p, ks, KQR_FP32, pr.K32.ptr, pr.ldk, st);
+    }
   }
   KQR_CHECK_HIP(hipStreamSynchronize(st));
   pr.t_kbuild = wall_seconds() - t0;
@@ -362,6 +367,7 @@ void fit_multi_tau(const float* X, const double* y, int64_t n, int p, KernelSpec
       hipStream_t s = streams.s[size_t(t)];
       try {
         Operator op(X, n, p, ks, pr.kmat(), s);
+        pr.attach(op);
         op.enable_profile(o.profile != 0);
         if (batcher) op.attach_batcher(batcher.get(), t);
         outs[size_t(t)] = run_fit(op, pr, y, n, taus[t], lam, o, alpha + int64_t(t) * n, s);
@@ -423,6 +429,7 @@ void fit_batch(int nprob, const float* const* X, const double* const* y, const i
       hipStream_t s = streams.s[size_t(i)];
       try {
         Operator op(X[i], n[i], p, KernelSpec{ks.kind, gamma[i]}, kms[size_t(i)], s);
+        prs[size_t(i)].attach(op);
         op.enable_profile(o.profile != 0);
         if (batcher) op.attach_batcher(batcher.get(), i);
         outs[size_t(i)] = run_fit(op, prs[size_t(i)], y[i], n[i], tau[i], lam[i], o, alpha[i], s);

@@ -26,6 +26,8 @@ class Operator {
     batcher_ = b;
     slot_ = slot;
   }
+  // FP32 copy of K for the exact applies when the fast operator is stored in BF16.
+  void set_exact(KMat k) { kexact_ = k; }
   // Fast apply: FP32 products (from v32 when given, else a rounded copy of v).
   void apply_fast(const double* v, const float* v32, double* u, hipStream_t st);
   // Exact apply: FP32 entries (stored FP32 or recomputed) with FP64 vector and sums.
@@ -51,6 +53,7 @@ class Operator {
   int p_;
   KernelSpec ks_;
   KMat km_;
+  KMat kexact_;
   DevBuf sqn_, v32_;
   int64_t calls_ = 0;
   bool profile_ = false;
@@ -110,7 +113,7 @@ class Solver {
 
  private:
   PcgStats linsolve(double c, const double* L, const double* b, double* x, double* Kx, bool x_zero, double tol,
-                    kqr_info& info);
+                    bool refine, kqr_info& info);
   void ssn(double stop, kqr_info& info);
   Kkt kkt_from_sums(const double* s) const;
   Kkt update_and_kkt(double beta_new, double sigma, double step, bool update);

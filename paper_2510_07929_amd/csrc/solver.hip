@@ -79,6 +79,8 @@ void Operator::apply_exact(const double* v, double* u, hipStream_t st) {
   mark(true, false, st);
   if (km_.K && km_.dtype == KQR_FP32) {
     kapply_dense(km_, n_, n_, nullptr, v, u, 1, true, st);
+  } else if (kexact_.K) {
+    kapply_dense(kexact_, n_, n_, nullptr, v, u, 1, true, st);
   } else {
     // BF16 storage is not the exact operator: recompute FP32 entries from X.
     kapply_otf(X_, sqn_.as<float>(), n_, X_, sqn_.as<float>(), n_, p_, ks_, v, u, 1, 1.0, 0.0, st, true);
@@ -224,16 +226,17 @@ static double now_s() {
 }
 
 // Linear solve of (K + c 1 1^T + diag(L)) x = b to ||b - A x|| <= tol, with K x
-// kept in Kx.  With an FP32 (or on-the-fly) operator this is PCG on the
-// operator itself.  With BF16 storage it is iterative refinement: the
-// residual r = b - A x is formed with the exact operator (FP32 entries
-// recomputed from X, FP64 vectors and sums), PCG on the BF16 operator solves
-// A_bf16 dx = r to a modest relative accuracy, x += dx and K x += K_exact dx.
+// kept in Kx.  With an FP32 (or on-the-fly) operator, or when refine is off,
+// this is PCG on the fast operator itself.  With BF16 storage and refine on it
+// is iterative refinement: the residual r = b - A x is formed with the exact
+// operator (FP32 entries, stored or recomputed from X, FP64 vectors and sums),
+// PCG on the BF16 operator solves A_bf16 dx = r to a relative accuracy matched
+// to the contraction the previous step achieved, x += dx and K x += K_exact dx.
 // When a refinement step fails to reduce the exact residual by a tenth, the
 // solve finishes with PCG on the exact operator.
 PcgStats Solver::linsolve(double c, const double* L, const double* b, double* x, double* Kx, bool x_zero, double tol,
-                          kqr_info& info) {
-  if (!(op_.materialized() && op_.kmat().dtype == KQR_BF16 && o_.refine)) {
+                          bool refine, kqr_info& info) {
+  if (!(refine && op_.materialized() && op_.kmat().dtype == KQR_BF16 && o_.refine)) {
     return pcg_.solve(c, L, P_.get(), b, x, Kx, x_zero, tol, o_.pcg_max_iter, true, st_);
   }
   const int64_t n = n_;
@@ -259,8 +262,11 @@ PcgStats Solver::linsolve(double c, const double* L, const double* b, double* x,
   PcgStats total;
   double rn = residual();
   total.resnorm = rn;
+  // relative accuracy of the inner solve: solving far below the contraction
+  // the BF16 operator allows only costs iterations
+  double inner_rel = 0.05;
   for (int step = 0; step < 30 && rn > tol; ++step) {
-    const double inner_tol = std::max(0.5 * tol, 0.05 * rn);
+    const double inner_tol = std::max(0.5 * tol, inner_rel * rn);
     PcgStats ps = pcg_.solve(c, L, P_.get(), r, dx, nullptr, true, inner_tol, o_.pcg_max_iter, true, st_);
     total.iters += ps.iters;
     op_.apply_exact(dx, kdx, st_);
@@ -269,6 +275,7 @@ PcgStats Solver::linsolve(double c, const double* L, const double* b, double* x,
     const double rn_new = residual();
     total.resnorm = rn_new;
     const bool stalled = !(rn_new < 0.9 * rn);
+    inner_rel = std::min(0.3, std::max(0.05, 0.5 * rn_new / rn));
     rn = rn_new;
     if (stalled && rn > tol) {  // BF16 operator too far from the exact one here
       PcgStats pe = pcg_.solve(c, L, P_.get(), b, x, Kx, false, tol, o_.pcg_max_iter, false, st_);
@@ -307,8 +314,10 @@ void Solver::phase1(kqr_info& info) {
       b0 = std::sqrt(t3[2]);
     }
     const double eps_k = o_.admm_eps0 * b0 / std::pow(double(it + 1), 1.5);
+    // Phase I is a warm start: with BF16 storage it runs on the BF16 operator
+    // alone (K alpha is recomputed exactly when Phase II starts)
     PcgStats ps = linsolve(c, L_.as<double>(), b_.as<double>(), alpha_.as<double>(), Ka_.as<double>(), it == 0, eps_k,
-                           info);
+                           false, info);
     info.admm_pcg_iters += ps.iters;
     const double sa = sum_of(alpha_.as<double>());
     const double beta_new = beta_ + step * sigma * sa;
@@ -345,7 +354,8 @@ void Solver::ssn(double stop, kqr_info& info) {
                                    st_))
       fail(KQR_ENUMERIC, "Newton preconditioner core not positive definite");
     const double tol = lam_ * std::min(o_.etabar, std::pow(gn, 1.0 + o_.iota));
-    PcgStats ps = linsolve(c1, L_.as<double>(), b_.as<double>(), d_.as<double>(), Kd_.as<double>(), true, tol, info);
+    PcgStats ps =
+        linsolve(c1, L_.as<double>(), b_.as<double>(), d_.as<double>(), Kd_.as<double>(), true, tol, true, info);
     info.pcg_iters += ps.iters;
     // Armijo backtracking, kLsTrials step lengths per pass
     const double s0 = sa + beta_ / sigma;

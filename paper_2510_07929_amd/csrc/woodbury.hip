@@ -179,84 +179,80 @@ __global__ __launch_bounds__(64) void flag_scatter_kernel(const uint8_t* __restr
 }
 
 // ---------------------------------------------------------------- blocked Cholesky (lower)
-// Diagonal block (nb <= 64): one wave, lane l holds row l in registers.  At
-// column j lane j takes the square root of its (already updated) diagonal and
-// every lane publishes its column-j entry to LDS; lanes then scale by the
-// broadcast reciprocal and update their entries k in (j, l] with the
-// column-j entries read back as LDS broadcasts.  Stored and applied factors
-// use the same product, so the result does not depend on the lane.
+// Diagonal block (nb <= 64), left-looking, one wave: the block sits in LDS
+// and lane l owns row l.  Column j: every lane l >= j forms
+// A[l][j] - sum_{k<j} L[l][k] L[j][k] (its own row against the broadcast row
+// j, four independent partial sums), lane j takes the square root, and the
+// lanes below scale by the broadcast reciprocal.  The loops are not unrolled
+// over j, so the kernel stays small in the instruction cache.
 __global__ __launch_bounds__(64) void chol_diag_kernel(double* __restrict__ C, int64_t ldc, int kb, int nb,
                                                        int* __restrict__ flag) {
-  __shared__ double col[kNb];
+  __shared__ double A[kNb][kNb + 1];
+  __shared__ double rdiag;
   const int l = threadIdx.x;
-  double a[kNb];
-  const double* row = C + int64_t(kb + (l < nb ? l : 0)) * ldc + kb;
-#pragma unroll
-  for (int k = 0; k < kNb; ++k) a[k] = (l < nb && k <= l && k < nb) ? row[k] : (k == l ? 1.0 : 0.0);
+  for (int e = l; e < kNb * kNb; e += 64) {
+    const int i = e / kNb, k = e % kNb;
+    A[i][k] = (i < nb && k <= i) ? C[int64_t(kb + i) * ldc + kb + k] : (i == k ? 1.0 : 0.0);
+  }
+  __syncthreads();
   bool bad = false;
-#pragma unroll
   for (int j = 0; j < kNb; ++j) {
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int k = 0;
+    for (; k + 4 <= j; k += 4) {
+      s0 = fma(A[l][k], A[j][k], s0);
+      s1 = fma(A[l][k + 1], A[j][k + 1], s1);
+      s2 = fma(A[l][k + 2], A[j][k + 2], s2);
+      s3 = fma(A[l][k + 3], A[j][k + 3], s3);
+    }
+    for (; k < j; ++k) s0 = fma(A[l][k], A[j][k], s0);
+    const double v = A[l][j] - ((s0 + s1) + (s2 + s3));
     if (l == j) {
-      double piv = a[j];
+      double piv = v;
       if (!(piv > 0.0) || !isfinite(piv)) {
         bad = true;
         piv = 1e-300;
       }
-      a[j] = sqrt(piv);
+      const double d = sqrt(piv);
+      A[j][j] = d;
+      rdiag = 1.0 / d;
     }
-    col[l] = a[j];
     __syncthreads();
-    const double rinv = 1.0 / col[j];
-    if (l > j) a[j] *= rinv;
-#pragma unroll
-    for (int k = j + 1; k < kNb; ++k) {
-      const double ckj = col[k] * rinv;
-      if (l >= k) a[k] = fma(-a[j], ckj, a[k]);
-    }
+    if (l > j) A[l][j] = v * rdiag;
     __syncthreads();
   }
   if (bad && nb > 0) flag[0] = 1;
-  if (l < nb) {
-    double* w = C + int64_t(kb + l) * ldc + kb;
-#pragma unroll
-    for (int k = 0; k < kNb; ++k)
-      if (k <= l) w[k] = a[k];
+  for (int e = l; e < kNb * kNb; e += 64) {
+    const int i = e / kNb, k = e % kNb;
+    if (i < nb && k <= i) C[int64_t(kb + i) * ldc + kb + k] = A[i][k];
   }
 }
 
-// Panel: rows i >= kb+nb solve x L_kk^T = C[i, kb:kb+nb].  One lane per row
-// with the row in registers (staged through LDS so the global reads are
-// coalesced); L_kk entries are LDS broadcasts.
-__global__ __launch_bounds__(64) void chol_panel_kernel(double* __restrict__ C, int64_t ldc, int kb, int nb,
-                                                        int R1) {
+// Panel: rows i >= kb+nb solve x L_kk^T = C[i, kb:kb+nb].  One wave per row,
+// lane k owns x_k; column j is finished by lane j (times the reciprocal of
+// the pivot) and broadcast.
+__global__ __launch_bounds__(256) void chol_panel_kernel(double* __restrict__ C, int64_t ldc, int kb, int nb,
+                                                         int R1) {
   __shared__ double Lk[kNb][kNb + 1];
-  __shared__ double Rw[64][kNb + 1];
-  const int l = threadIdx.x;
-  const int64_t r0 = int64_t(kb) + nb + int64_t(blockIdx.x) * 64;
-  for (int e = l; e < kNb * kNb; e += 64) {
+  __shared__ double rinv[kNb];
+  for (int e = threadIdx.x; e < kNb * kNb; e += 256) {
     const int i = e / kNb, k = e % kNb;
-    Lk[i][k] = (i < nb && k <= i) ? C[int64_t(kb + i) * ldc + kb + k] : (i == k ? 1.0 : 0.0);
-    const int64_t ri = r0 + i;
-    Rw[i][k] = (ri < R1 && k < nb) ? C[ri * ldc + kb + k] : 0.0;
+    const double v = (i < nb && k <= i) ? C[int64_t(kb + i) * ldc + kb + k] : (i == k ? 1.0 : 0.0);
+    Lk[i][k] = v;
+    if (i == k) rinv[i] = 1.0 / v;
   }
   __syncthreads();
-  double x[kNb];
-#pragma unroll
-  for (int k = 0; k < kNb; ++k) x[k] = Rw[l][k];
-#pragma unroll
+  const int k = threadIdx.x & 63;
+  const int64_t i = int64_t(kb) + nb + int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+  const bool ok = i < R1;
+  double* row = C + (ok ? i : 0) * ldc + kb;
+  double x = (ok && k < nb) ? row[k] : 0.0;
   for (int j = 0; j < kNb; ++j) {
-    x[j] /= Lk[j][j];
-#pragma unroll
-    for (int k = j + 1; k < kNb; ++k) x[k] = fma(-x[j], Lk[k][j], x[k]);
+    if (k == j) x *= rinv[j];
+    const double xj = __shfl(x, j);
+    if (k > j) x = fma(-xj, Lk[k][j], x);
   }
-#pragma unroll
-  for (int k = 0; k < kNb; ++k) Rw[l][k] = x[k];
-  __syncthreads();
-  for (int e = l; e < 64 * kNb; e += 64) {
-    const int i = e / kNb, k = e % kNb;
-    const int64_t ri = r0 + i;
-    if (ri < R1 && k < nb) C[ri * ldc + kb + k] = Rw[i][k];
-  }
+  if (ok && k < nb) row[k] = x;
 }
 
 // Trailing update of the lower part: C[i][j] -= sum_k P[i][k] P[j][k], j <= i,
@@ -307,13 +303,16 @@ __global__ __launch_bounds__(256) void chol_update_kernel(double* __restrict__ C
 }
 
 // ---------------------------------------------------------------- W = Lc^{-1}
-// Inverse of each 64 x 64 diagonal block by forward substitution; lane j
-// holds column j of the inverse in registers and reads the factor's rows as
-// LDS broadcasts.  Blocks are independent (one workgroup each).  W must be
-// zero outside the blocks written here before the doubling steps run.
+// Inverse of each 64 x 64 diagonal block by forward substitution: lane j
+// forms column j of the inverse in LDS, reading the factor's rows as LDS
+// broadcasts (four independent partial sums per entry; entries above the
+// diagonal are zero, so every lane runs the same trip counts).  Blocks are
+// independent (one workgroup each).  W must be zero outside the blocks
+// written here before the doubling steps run.
 __global__ __launch_bounds__(64) void trinv_diag_kernel(const double* __restrict__ C, int64_t ldc, int R1,
                                                         double* __restrict__ W) {
   __shared__ double Lk[kNb][kNb + 1];
+  __shared__ double X[kNb][kNb + 1];
   const int kb = blockIdx.x * kNb;
   const int nb = min(kNb, R1 - kb);
   const int j = threadIdx.x;
@@ -322,18 +321,22 @@ __global__ __launch_bounds__(64) void trinv_diag_kernel(const double* __restrict
     Lk[i][k] = (i < nb && k <= i) ? C[int64_t(kb + i) * ldc + kb + k] : (i == k ? 1.0 : 0.0);
   }
   __syncthreads();
-  double x[kNb];
-#pragma unroll
   for (int i = 0; i < kNb; ++i) {
-    double s = (i == j) ? 1.0 : 0.0;
-#pragma unroll
-    for (int k = 0; k < i; ++k) s = fma(-Lk[i][k], x[k], s);
-    x[i] = s / Lk[i][i];
+    double s0 = (i == j) ? 1.0 : 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int k = 0;
+    for (; k + 4 <= i; k += 4) {
+      s0 = fma(-Lk[i][k], X[k][j], s0);
+      s1 = fma(-Lk[i][k + 1], X[k + 1][j], s1);
+      s2 = fma(-Lk[i][k + 2], X[k + 2][j], s2);
+      s3 = fma(-Lk[i][k + 3], X[k + 3][j], s3);
+    }
+    for (; k < i; ++k) s0 = fma(-Lk[i][k], X[k][j], s0);
+    X[i][j] = (i >= j) ? ((s0 + s1) + (s2 + s3)) / Lk[i][i] : 0.0;
   }
-  if (j < nb) {
-#pragma unroll
-    for (int i = 0; i < kNb; ++i)
-      if (i < nb) W[int64_t(kb + i) * ldc + kb + j] = x[i];
+  __syncthreads();
+  for (int e = j; e < kNb * kNb; e += 64) {
+    const int i = e / kNb, k = e % kNb;
+    if (i < nb && k < nb) W[int64_t(kb + i) * ldc + kb + k] = X[i][k];
   }
 }
 
@@ -592,7 +595,7 @@ void spd_factor_inverse(double* C, int64_t ldc, int R1, double* W, double* WT, d
     KQR_LAUNCH_CHECK();
     const int rest = R1 - kb - nb;
     if (rest > 0) {
-      chol_panel_kernel<<<(rest + 63) / 64, 64, 0, st>>>(C, ldc, kb, nb, R1);
+      chol_panel_kernel<<<(rest + 3) / 4, 256, 0, st>>>(C, ldc, kb, nb, R1);
       KQR_LAUNCH_CHECK();
       const int mt = (rest + kT - 1) / kT;
       chol_update_kernel<<<mt * (mt + 1) / 2, 256, 0, st>>>(C, ldc, kb, nb, R1);

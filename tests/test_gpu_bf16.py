@@ -48,15 +48,17 @@ def _check_against_oracle(prob, a, beta, info):
     assert cert["eta_d"] <= 2e-6 and cert["eta_c"] <= 1e-5
 
 
-@pytest.mark.parametrize("name,n,rank", [("c2", 3000, 0), ("c2", 4100, 300), ("c2lap", 2500, 0)])
-def test_bf16_refined_fit_matches_oracle(dev, name, n, rank):
+@pytest.mark.parametrize("name,n,rank,exact_k", [("c2", 3000, 0, 0), ("c2", 4100, 300, 0), ("c2lap", 2500, 0, 0),
+                                                 ("c2", 3000, 0, 1), ("c2lap", 2049, 0, 1)])
+def test_bf16_refined_fit_matches_oracle(dev, name, n, rank, exact_k):
+    # exact_k = 0: exact entries recomputed from X; 1: an FP32 copy of K beside the BF16 one
     prob = inputs.workload(name, n=n)
-    say("bf16 fit", name, n, rank)
+    say("bf16 fit", name, n, rank, exact_k)
     X = torch.from_numpy(prob.X).to(dev)
     y = torch.from_numpy(prob.y).to(dev)
     alpha, beta, info, st = kqr.kqr_fit(X, y, prob.tau, prob.lam, prob.kernel, prob.gamma, rank=rank,
                                         k_dtype=kqr.KQR_BF16, kmode=kqr.KQR_KMODE_MATERIALIZE, profile=1,
-                                        uniforms=inputs.pivot_uniforms(max(rank, 64), (n, 6)))
+                                        exact_k=exact_k, uniforms=inputs.pivot_uniforms(max(rank, 64), (n, 6)))
     assert st == kqr.KQR_OK
     assert info["refinements"] > 0
     _check_against_oracle(prob, alpha.cpu().numpy(), beta, info)
