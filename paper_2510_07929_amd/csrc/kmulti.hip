@@ -29,14 +29,21 @@ __device__ __forceinline__ uint16_t f2bf(float f) {
 // U[seg] rows = K[rows, cols of segment] V[cols, 0:16].  Block = 4 waves, each
 // wave a 16-row strip.  V (row-major, 16 FP32 columns, rows padded with zeros
 // up to ld_rows) is staged transposed in LDS per kKC columns.  The MFMA
-// accumulator (FP32) is flushed into FP64 after every stage.
-//  FP32 K: v_mfma_f32_16x16x4f32, a lane loads 8 consecutive entries of its
-//          row (128 contiguous bytes per row over 4 lane groups) for 8 MFMAs.
-//  BF16 K: v_mfma_f32_16x16x32_bf16 with V split into hi + lo BF16 parts.
+// accumulators (FP32, two independent chains) are flushed into FP64 after
+// every stage.  K is streamed with 16-byte non-temporal loads, 64 contiguous
+// bytes per row per load instruction (the four lanes of a row are adjacent),
+// and the next step's loads are issued before the current step's MFMAs.
+//  FP32 K: v_mfma_f32_16x16x4f32; a step is 64 columns, a lane holds 16
+//          entries of its row (columns 16q + 4g + e for lane group g).
+//  BF16 K: v_mfma_f32_16x16x32_bf16 with V split into hi + lo BF16 parts; a
+//          step is 128 columns, a lane holds 32 entries (32q + 8g + e).
+// Only the last step of a segment can be partial; it is read element-wise with
+// zero fill, so nothing beyond column ncols is touched.
 template <bool BF16>
 __global__ __launch_bounds__(256) void kv_mfma_kernel(const void* __restrict__ K, int64_t ldk, int64_t n,
                                                       int64_t ncols, const float* __restrict__ V,
                                                       int64_t seg_cols, double* __restrict__ out) {
+  constexpr int STEP = BF16 ? 128 : 64;
   __shared__ float vs[BF16 ? 1 : 16][BF16 ? 1 : kVpad];
   __shared__ uint16_t vh[BF16 ? 16 : 1][BF16 ? kVpad : 1];
   __shared__ uint16_t vl[BF16 ? 16 : 1][BF16 ? kVpad : 1];
@@ -48,8 +55,42 @@ __global__ __launch_bounds__(256) void kv_mfma_kernel(const void* __restrict__ K
   const int64_t c1 = min(ncols, c0 + seg_cols);
   double acc64[4] = {0.0, 0.0, 0.0, 0.0};
   const char* krow = static_cast<const char*>(K) + my_row * ldk * (BF16 ? 2 : 4);
+  // a[q] = 16 bytes of the row at column col + (BF16 ? 32 : 16) q + (BF16 ? 8 : 4) g
+  auto load_step = [&](int64_t col, u32x4 (&a)[4]) {
+    const int per = BF16 ? 8 : 4;  // entries per 16 bytes
+    if (col + STEP <= c1) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        a[q] = __builtin_nontemporal_load(
+            reinterpret_cast<const u32x4*>(krow + (col + q * 4 * per + lg * per) * (BF16 ? 2 : 4)));
+    } else {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int64_t cc = col + q * 4 * per + lg * per;
+        if (BF16) {
+          const uint16_t* kr = reinterpret_cast<const uint16_t*>(krow);
+          uint32_t w[4];
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const uint32_t lo = (cc + 2 * e < c1) ? kr[cc + 2 * e] : 0u;
+            const uint32_t hi = (cc + 2 * e + 1 < c1) ? kr[cc + 2 * e + 1] : 0u;
+            w[e] = lo | (hi << 16);
+          }
+          a[q] = u32x4{w[0], w[1], w[2], w[3]};
+        } else {
+          const float* kr = reinterpret_cast<const float*>(krow);
+          uint32_t w[4];
+#pragma unroll
+          for (int e = 0; e < 4; ++e) w[e] = (cc + e < c1) ? __float_as_uint(kr[cc + e]) : 0u;
+          a[q] = u32x4{w[0], w[1], w[2], w[3]};
+        }
+      }
+    }
+  };
   for (int64_t cb = c0; cb < c1; cb += kKC) {
     const int cnt = int(min<int64_t>(kKC, c1 - cb));
+    u32x4 a[4], an[4];
+    load_step(cb, a);  // independent of V: in flight while V is staged
     __syncthreads();
     for (int e = threadIdx.x; e < kKC * 16; e += 256) {
       const int kk = e >> 4, j = e & 15;
@@ -63,49 +104,38 @@ __global__ __launch_bounds__(256) void kv_mfma_kernel(const void* __restrict__ K
       }
     }
     __syncthreads();
-    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-    if (BF16) {
-      for (int kk = 0; kk < cnt; kk += 32) {
-        const int64_t col = cb + kk + 8 * lg;
-        bf16x8 a;
-        if (col + 8 <= ncols) {
-          a = *reinterpret_cast<const bf16x8*>(krow + col * 2);
-        } else {
-          const uint16_t* kr = reinterpret_cast<const uint16_t*>(krow);
-          uint16_t tmp[8];
+    f32x4 accA = {0.f, 0.f, 0.f, 0.f}, accB = {0.f, 0.f, 0.f, 0.f};
+    for (int kk = 0; kk < cnt; kk += STEP) {
+      const bool more = kk + STEP < cnt;
+      if (more) load_step(cb + kk + STEP, an);
+      if (BF16) {
 #pragma unroll
-          for (int e = 0; e < 8; ++e) tmp[e] = (col + e < ncols) ? kr[col + e] : uint16_t(0);
-          a = *reinterpret_cast<const bf16x8*>(tmp);
+        for (int q = 0; q < 4; ++q) {
+          const bf16x8 av = __builtin_bit_cast(bf16x8, a[q]);
+          const int off = kk + 32 * q + 8 * lg;
+          const bf16x8 bh = *reinterpret_cast<const bf16x8*>(&vh[li][off]);
+          const bf16x8 bl = *reinterpret_cast<const bf16x8*>(&vl[li][off]);
+          accA = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bh, accA, 0, 0, 0);
+          accB = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bl, accB, 0, 0, 0);
         }
-        const bf16x8 bh = *reinterpret_cast<const bf16x8*>(&vh[li][kk + 8 * lg]);
-        const bf16x8 bl = *reinterpret_cast<const bf16x8*>(&vl[li][kk + 8 * lg]);
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bh, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bl, acc, 0, 0, 0);
+      } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const f32x4 b = *reinterpret_cast<const f32x4*>(&vs[li][kk + 16 * q + 4 * lg]);
+          const f32x4 av = __builtin_bit_cast(f32x4, a[q]);
+          accA = __builtin_amdgcn_mfma_f32_16x16x4f32(av[0], b[0], accA, 0, 0, 0);
+          accB = __builtin_amdgcn_mfma_f32_16x16x4f32(av[1], b[1], accB, 0, 0, 0);
+          accA = __builtin_amdgcn_mfma_f32_16x16x4f32(av[2], b[2], accA, 0, 0, 0);
+          accB = __builtin_amdgcn_mfma_f32_16x16x4f32(av[3], b[3], accB, 0, 0, 0);
+        }
       }
-    } else {
-      for (int kk = 0; kk < cnt; kk += 32) {
-        const int64_t col = cb + kk + 8 * lg;
-        float a[8];
-        if (col + 8 <= ncols) {
-          const f32x4 a0 = *reinterpret_cast<const f32x4*>(krow + col * 4);
-          const f32x4 a1 = *reinterpret_cast<const f32x4*>(krow + col * 4 + 16);
-          a[0] = a0[0]; a[1] = a0[1]; a[2] = a0[2]; a[3] = a0[3];
-          a[4] = a1[0]; a[5] = a1[1]; a[6] = a1[2]; a[7] = a1[3];
-        } else {
-          const float* kr = reinterpret_cast<const float*>(krow);
+      if (more) {
 #pragma unroll
-          for (int e = 0; e < 8; ++e) a[e] = (col + e < ncols) ? kr[col + e] : 0.f;
-        }
-        const f32x4 b0 = *reinterpret_cast<const f32x4*>(&vs[li][kk + 8 * lg]);
-        const f32x4 b1 = *reinterpret_cast<const f32x4*>(&vs[li][kk + 8 * lg + 4]);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[q], b0[q], acc, 0, 0, 0);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[4 + q], b1[q], acc, 0, 0, 0);
+        for (int q = 0; q < 4; ++q) a[q] = an[q];
       }
     }
 #pragma unroll
-    for (int r = 0; r < 4; ++r) acc64[r] += double(acc[r]);
+    for (int r = 0; r < 4; ++r) acc64[r] += double(accA[r]) + double(accB[r]);
   }
   // accumulator layout of a 16x16 MFMA: lane holds rows 4*(lane/16)+r, column lane%16
 #pragma unroll

@@ -52,7 +52,10 @@ def test_tiny_fit_matches_golden(dev, c):
     rel = abs(obj - c["obj_p"]) / (1 + abs(c["obj_p"]))
     say(f"  rel_obj={rel:.2e} kkt={info['eta_kkt']:.2e}")
     assert rel <= 1e-6
-    assert abs(a.sum()) <= 1e-9 and a.min() >= c["tau"] - 1 - 1e-12 and a.max() <= c["tau"] + 1e-12
+    # alpha is the ALM iterate (not its box projection): its distance to the
+    # box and its sum are bounded by the dual and primal residuals reached
+    assert abs(a.sum()) <= 1e-6 * (1 + np.abs(a).sum())
+    assert max(0.0, a.max() - c["tau"], c["tau"] - 1 - a.min()) <= 1e-6 * (1 + np.linalg.norm(a))
 
 
 @pytest.mark.parametrize("c", [c for c in CASES if "J" in c], ids=lambda c: c["name"])
