@@ -292,6 +292,13 @@ def bench_multi_tau(args, prob):
                                                      **opts)
         return infos, sts
 
+    tuned = None
+    if not args.no_tune:
+        # untimed: pick the K V launch shape on this problem's own K
+        K = kqr.kqr_kernel_build(X, prob.kernel, prob.gamma, kd)
+        tuned = kqr.kqr_autotune_apply(K, kqr.KQR_APPLY_KV, reps=3)["best"]
+        del K
+        torch.cuda.empty_cache()
     outs, elapsed = timed_fits(args, joint)
     t_sep0 = time.perf_counter()
     sep = [kqr.kqr_fit(X, y, t, prob.lam, prob.kernel, prob.gamma, uniforms=uni, **opts) for t in taus]
@@ -310,7 +317,7 @@ def bench_multi_tau(args, prob):
         "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
         "kernel": "kv_mfma_kernel (K V, V n x 16, %s K)" % kd, "avg_launch_us": round(avg * 1e6, 2),
-        "launches": int(nl), "bytes_per_launch": kbytes,
+        "launches": int(nl), "bytes_per_launch": kbytes, "launch_shape": tuned or "default",
     }
     out["fit"] = {"status": sts, "eta_kkt_max": max(i["eta_kkt"] for i in infos),
                   "eta_gap_max": max(i["eta_gap"] for i in infos),

@@ -64,7 +64,8 @@ enum {
 /* arithmetic of kqr_kernel_apply */
 enum {
   KQR_APPLY_FAST = 0, /* V rounded to FP32, FP32 products, FP64 sums per segment */
-  KQR_APPLY_EXACT = 1 /* V in FP64, products and sums in FP64 (K entries as stored) */
+  KQR_APPLY_EXACT = 1, /* V in FP64, products and sums in FP64 (K entries as stored) */
+  KQR_APPLY_KV = 2     /* kqr_autotune_apply only: the multi-column K V launch on the matrix cores */
 };
 
 /* ---------------------------------------------------------------- options
@@ -197,9 +198,13 @@ int kqr_adaptive_rank(const float* F0, int64_t n, int64_t r0, int64_t ldf, doubl
  * (device, as in kqr_kernel_build) for every supported tile shape -- rows per
  * wave {2,4,8} x 16-byte loads in flight per row {1,2,4} x column segments
  * {1,2,4,8,16} -- with `reps` timed launches each, and keeps the fastest shape
- * for (k_dtype, mode, size class of n) for the rest of the process.  Writes a
- * JSON report (every shape's average launch time and the choice) into
- * `report` (host, `cap` bytes, NUL-terminated; may be NULL).  Synchronises. */
+ * for (k_dtype, mode, size class of n) for the rest of the process.  With
+ * mode KQR_APPLY_KV it times the multi-column K V launch (16 columns) instead,
+ * over 16-byte loads per lane per step {4,8} x next-step prefetch {0,1} x
+ * column segments {1,2,4,8}, and keeps the fastest for (k_dtype, size class
+ * of n).  Writes a JSON report (every shape's average launch time and the
+ * choice) into `report` (host, `cap` bytes, NUL-terminated; may be NULL).
+ * Synchronises. */
 int kqr_autotune_apply(const void* K, int k_dtype, int64_t n, int64_t ldk, int mode, int reps, char* report,
                        int64_t cap, void* stream);
 
@@ -207,6 +212,12 @@ int kqr_autotune_apply(const void* K, int k_dtype, int64_t n, int64_t ldk, int m
  * kqr_autotune_apply) for (k_dtype, mode, size class of n).  rows in {2,4,8},
  * unroll in {1,2,4}, 1 <= segs <= 64; otherwise KQR_EINVAL. */
 int kqr_set_apply_shape(int k_dtype, int mode, int64_t n, int rows, int unroll, int segs);
+
+/* kqr_set_kv_shape: installs a K V launch shape (e.g. one recorded by
+ * kqr_autotune_apply with KQR_APPLY_KV) for (k_dtype, size class of n).
+ * nld in {4,8} (16-byte loads per lane per step), prefetch in {0,1},
+ * 1 <= segs <= 8; otherwise KQR_EINVAL. */
+int kqr_set_kv_shape(int k_dtype, int64_t n, int nld, int prefetch, int segs);
 
 /* kqr_woodbury_apply: out = P^{-1} w for P = F F^T + c 1 1^T + diag(Ldiag), by
  * Lemma 1 with U = [F 1] and the (r+1)x(r+1) core C = diag(I, 1/c) + U^T L^{-1} U

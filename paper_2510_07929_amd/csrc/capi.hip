@@ -102,6 +102,64 @@ static void check_kmat(const void* K, int k_dtype, int64_t ldk, int64_t n) {
   KQR_REQUIRE((reinterpret_cast<uintptr_t>(K) & 15) == 0, "K must be 16-byte aligned");
 }
 
+// Times every supported K V launch shape (16 right-hand sides) on K and
+// installs the fastest for K's dtype and size bucket; JSON report.
+static void autotune_kv(const KMat& km, int64_t n, int reps, char* report, int64_t cap, hipStream_t st) {
+  DevBuf V16(size_t(n) * 16 * sizeof(float)), U(size_t(n) * 16 * sizeof(double));
+  DevBuf part(size_t(kKvMaxSegs) * size_t(n) * 16 * sizeof(double)), ones(size_t(n) * 16 * sizeof(double));
+  fill(n * 16, 1.0 / double(n), ones.as<double>(), st);
+  kv_gather_strided(ones.as<double>(), 16, 16, n, n, V16.as<float>(), st);
+  hipEvent_t e0, e1;
+  KQR_CHECK_HIP(hipEventCreate(&e0));
+  KQR_CHECK_HIP(hipEventCreate(&e1));
+  std::string rep = "{\"n\": " + std::to_string(n) + ", \"k_dtype\": " + std::to_string(km.dtype) +
+                    ", \"mode\": " + std::to_string(KQR_APPLY_KV) + ", \"shapes\": [";
+  KvShape best;
+  double best_us = 1e300;
+  bool first = true;
+  try {
+    for (int nld : {4, 8})
+      for (int pf : {0, 1})
+        for (int sg : {1, 2, 4, 8}) {
+          KvShape s;
+          s.nld = nld;
+          s.prefetch = pf;
+          s.segs = sg;
+          kapply_kv(km, n, V16.as<float>(), 16, U.as<double>(), 16, part.as<double>(), st, &s);  // warm-up
+          KQR_CHECK_HIP(hipEventRecord(e0, st));
+          for (int k = 0; k < reps; ++k)
+            kapply_kv(km, n, V16.as<float>(), 16, U.as<double>(), 16, part.as<double>(), st, &s);
+          KQR_CHECK_HIP(hipEventRecord(e1, st));
+          KQR_CHECK_HIP(hipEventSynchronize(e1));
+          float ms = 0.f;
+          KQR_CHECK_HIP(hipEventElapsedTime(&ms, e0, e1));
+          const double us = 1e3 * ms / reps;
+          char buf[128];
+          snprintf(buf, sizeof(buf), "%s{\"nld\": %d, \"prefetch\": %d, \"segs\": %d, \"us\": %.2f}",
+                   first ? "" : ", ", nld, pf, sg, us);
+          first = false;
+          rep += buf;
+          if (us < best_us) { best_us = us; best = s; }
+        }
+  } catch (...) {
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    throw;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  set_kv_shape(km.dtype, n, best);
+  char buf[160];
+  snprintf(buf, sizeof(buf), "], \"best\": {\"nld\": %d, \"prefetch\": %d, \"segs\": %d, \"us\": %.2f}}", best.nld,
+           best.prefetch, best.segs, best_us);
+  rep += buf;
+  if (report && cap > 0) {
+    const size_t nb = std::min<size_t>(size_t(cap) - 1, rep.size());
+    memcpy(report, rep.data(), nb);
+    report[nb] = '\0';
+  }
+}
+
 }  // namespace kqr
 
 using namespace kqr;
@@ -215,13 +273,13 @@ int kqr_kernel_apply(const float* X, int64_t n, int64_t p, int kernel, double ga
       row_sqnorms(X, n, int(p), sqn, st);
     }
     if (K && m > 1) {  // all columns in one pass over K on the matrix cores
-      const int segs = 4;
       float* V16 = nullptr;
       double* part = nullptr;
       KQR_CHECK_HIP(hipMallocAsync(reinterpret_cast<void**>(&V16), size_t(n) * 16 * sizeof(float), st));
-      KQR_CHECK_HIP(hipMallocAsync(reinterpret_cast<void**>(&part), size_t(segs) * n * 16 * sizeof(double), st));
+      KQR_CHECK_HIP(
+          hipMallocAsync(reinterpret_cast<void**>(&part), size_t(kKvMaxSegs) * n * 16 * sizeof(double), st));
       kv_gather_strided(V, ldv, int(m), n, n, V16, st);
-      kapply_kv(km, n, V16, int(m), U, ldu, part, segs, st);
+      kapply_kv(km, n, V16, int(m), U, ldu, part, st);
       KQR_CHECK_HIP(hipFreeAsync(part, st));
       KQR_CHECK_HIP(hipFreeAsync(V16, st));
       m = 0;  // done
@@ -316,11 +374,15 @@ int kqr_autotune_apply(const void* K, int k_dtype, int64_t n, int64_t ldk, int m
   return guarded([&] {
     KQR_REQUIRE(K != nullptr, "K must be non-null");
     KQR_REQUIRE(n >= 1 && reps >= 1, "need n >= 1 and reps >= 1");
-    KQR_REQUIRE(mode == KQR_APPLY_FAST || mode == KQR_APPLY_EXACT, "invalid mode");
+    KQR_REQUIRE(mode == KQR_APPLY_FAST || mode == KQR_APPLY_EXACT || mode == KQR_APPLY_KV, "invalid mode");
     check_kmat(K, k_dtype, ldk, n);
     ensure_device();
     hipStream_t st = static_cast<hipStream_t>(stream);
     const KMat km{K, k_dtype, ldk};
+    if (mode == KQR_APPLY_KV) {
+      autotune_kv(km, n, reps, report, cap, st);
+      return;
+    }
     DevBuf v64(size_t(n) * sizeof(double)), v32(size_t(n) * sizeof(float)), u(size_t(n) * sizeof(double));
     fill(n, 1.0 / double(n), v64.as<double>(), st);
     to_f32(v64.as<double>(), n, 1, 1, v32.as<float>(), 1, st);
@@ -388,6 +450,19 @@ int kqr_set_apply_shape(int k_dtype, int mode, int64_t n, int rows, int unroll, 
     s.segs = segs;
     KQR_REQUIRE(apply_shape_supported(s), "unsupported shape (rows in {2,4,8}, unroll in {1,2,4}, 1 <= segs <= 64)");
     set_apply_shape(k_dtype, mode == KQR_APPLY_EXACT, n, s);
+  });
+}
+
+int kqr_set_kv_shape(int k_dtype, int64_t n, int nld, int prefetch, int segs) {
+  return guarded([&] {
+    KQR_REQUIRE(k_dtype == KQR_FP32 || k_dtype == KQR_BF16, "invalid k_dtype");
+    KQR_REQUIRE(prefetch == 0 || prefetch == 1, "prefetch must be 0 or 1");
+    KvShape s;
+    s.nld = nld;
+    s.prefetch = prefetch;
+    s.segs = segs;
+    KQR_REQUIRE(kv_shape_supported(s), "unsupported K V shape (nld in {4,8}, 1 <= segs <= 8)");
+    set_kv_shape(k_dtype, n, s);
   });
 }
 

@@ -253,10 +253,9 @@ class KvBatcher : public RendezvousBatcher {
   KvBatcher(int slots, KMat km, int64_t n, bool profile)
       : RendezvousBatcher(slots, profile), km_(km), n_(n), npad_(std::max<int64_t>(km.ld, n)),
         V_(size_t(npad_) * 16 * sizeof(float)), U_(size_t(n) * 16 * sizeof(double)),
-        part_(size_t(kSegs) * n * 16 * sizeof(double)) {}
+        part_(size_t(kKvMaxSegs) * n * 16 * sizeof(double)) {}
 
  protected:
-  static constexpr int kSegs = 4;
   void launch(const std::vector<int>& slots, hipStream_t st) override {
     const int m = int(slots.size());
     SrcTable16 src{};
@@ -266,7 +265,7 @@ class KvBatcher : public RendezvousBatcher {
       dst.p[j] = req_[size_t(slots[size_t(j)])].out;
     }
     kv_gather(src, m, n_, npad_, V_.as<float>(), st);
-    kapply_kv(km_, n_, V_.as<float>(), m, U_.as<double>(), 16, part_.as<double>(), kSegs, st);
+    kapply_kv(km_, n_, V_.as<float>(), m, U_.as<double>(), 16, part_.as<double>(), st);
     kv_scatter(U_.as<double>(), m, n_, dst, st);
   }
 

@@ -450,10 +450,166 @@ static void kapply_otf_p(const float* Xr, const float* qr, int64_t nr, const flo
   KQR_CHECK_HIP(hipFreeAsync(part, st));
 }
 
+// RBF on the fly with the Gram term on the matrix cores: a wave owns two
+// 16-row strips (its rows of X held as MFMA A operands for the whole launch),
+// the block stages 64 columns of X, their norms and v in LDS, and for each
+// 16-column tile v_mfma_f32_16x16x4f32 forms the 16 x 16 Gram blocks
+// (KP/4 MFMAs per strip, FP32 products and sums).  The lane that holds
+// G[4g + r][c] then forms d = q_i + q_j - 2 G, exp2(-gamma log2(e) d) and
+// accumulates k * v_j (fast: FP32 per 64-column stage, then FP64; exact: FP64
+// products and sums); the 16 lanes of a row group are reduced with shuffles
+// at the end.  KP = p rounded up to 4 (<= 32).
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+constexpr int kMfmaCols = 64;
+
+template <int KP, bool EX>
+__global__ __launch_bounds__(256) void kapply_otf_mfma_kernel(
+    const float* __restrict__ Xr, const float* __restrict__ qr, int64_t nr,
+    const float* __restrict__ Xc, const float* __restrict__ qc, int64_t nc, int p, float ng,
+    const double* __restrict__ v, int64_t cols_per_slice, double* __restrict__ part) {
+  constexpr int NKB = KP / 4;
+  __shared__ float xs[kMfmaCols][KP + 1];
+  __shared__ float qs[kMfmaCols];
+  __shared__ float vs[kMfmaCols];
+  __shared__ double vd[kMfmaCols];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lg = lane >> 4;
+  const int64_t row0 = int64_t(blockIdx.x) * 128 + wave * 32;
+  float a[2][NKB];
+  float qi[2][4];
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    const int64_t r = row0 + 16 * s + li;
+#pragma unroll
+    for (int kb = 0; kb < NKB; ++kb) {
+      const int k = 4 * kb + lg;
+      a[s][kb] = (r < nr && k < p) ? Xr[r * p + k] : 0.f;
+    }
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) {
+      const int64_t ro = row0 + 16 * s + 4 * lg + rr;
+      qi[s][rr] = ro < nr ? qr[ro] : 0.f;
+    }
+  }
+  const int64_t c0 = int64_t(blockIdx.y) * cols_per_slice;
+  const int64_t c1 = min(nc, c0 + cols_per_slice);
+  double acc[2][4];
+#pragma unroll
+  for (int s = 0; s < 2; ++s)
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) acc[s][rr] = 0.0;
+  for (int64_t jb = c0; jb < c1; jb += kMfmaCols) {
+    const int cnt = int(min<int64_t>(kMfmaCols, c1 - jb));
+    __syncthreads();
+    for (int t = threadIdx.x; t < kMfmaCols * KP; t += 256) {
+      const int jj = t / KP, k = t % KP;
+      xs[jj][k] = (jj < cnt && k < p) ? Xc[(jb + jj) * p + k] : 0.f;
+    }
+    if (threadIdx.x < kMfmaCols) {
+      const int jj = threadIdx.x;
+      qs[jj] = jj < cnt ? qc[jb + jj] : 0.f;
+      const double vj = jj < cnt ? v[jb + jj] : 0.0;
+      if (EX) vd[jj] = vj;
+      else vs[jj] = float(vj);
+    }
+    __syncthreads();
+    float a32[2][4];
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) a32[s][rr] = 0.f;
+    for (int t16 = 0; t16 < cnt; t16 += 16) {
+      const int jj = t16 + li;
+      float b[NKB];
+#pragma unroll
+      for (int kb = 0; kb < NKB; ++kb) b[kb] = xs[jj][4 * kb + lg];
+      f32x4_t g0 = {0.f, 0.f, 0.f, 0.f}, g1 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int kb = 0; kb < NKB; ++kb) {
+        g0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a[0][kb], b[kb], g0, 0, 0, 0);
+        g1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a[1][kb], b[kb], g1, 0, 0, 0);
+      }
+      const float qj = qs[jj];
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) {
+        const float d0 = fmaxf(qi[0][rr] + qj - 2.f * g0[rr], 0.f);
+        const float d1 = fmaxf(qi[1][rr] + qj - 2.f * g1[rr], 0.f);
+        const float e0 = exp2f(ng * d0), e1 = exp2f(ng * d1);
+        if (EX) {
+          acc[0][rr] = fma(double(e0), vd[jj], acc[0][rr]);
+          acc[1][rr] = fma(double(e1), vd[jj], acc[1][rr]);
+        } else {
+          a32[0][rr] = fmaf(e0, vs[jj], a32[0][rr]);
+          a32[1][rr] = fmaf(e1, vs[jj], a32[1][rr]);
+        }
+      }
+    }
+    if (!EX) {
+#pragma unroll
+      for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) acc[s][rr] += double(a32[s][rr]);
+    }
+  }
+  // sum over the 16 column lanes of each row group (lane bits 0..3)
+#pragma unroll
+  for (int s = 0; s < 2; ++s)
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) {
+      double x = acc[s][rr];
+#pragma unroll
+      for (int off = 1; off < 16; off <<= 1) x += __shfl_xor(x, off);
+      acc[s][rr] = x;
+    }
+  if (li == 0) {
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) {
+        const int64_t ro = row0 + 16 * s + 4 * lg + rr;
+        if (ro < nr) part[int64_t(blockIdx.y) * nr + ro] = acc[s][rr];
+      }
+  }
+}
+
+template <int KP>
+static void kapply_otf_mfma_p(const float* Xr, const float* qr, int64_t nr, const float* Xc, const float* qc,
+                              int64_t nc, int p, KernelSpec ks, const double* v, double* u, int64_t ldu, double scale,
+                              double shift, bool exact, hipStream_t st) {
+  const int64_t rblk = (nr + 127) / 128;
+  int64_t nslice = std::max<int64_t>(1, std::min<int64_t>(2048 / std::max<int64_t>(rblk, 1), (nc + 1023) / 1024));
+  nslice = std::min<int64_t>(nslice, 65535);
+  int64_t per = (nc + nslice - 1) / nslice;
+  per = (per + kMfmaCols - 1) / kMfmaCols * kMfmaCols;
+  nslice = (nc + per - 1) / per;
+  double* part = nullptr;
+  KQR_CHECK_HIP(hipMallocAsync(reinterpret_cast<void**>(&part), size_t(nslice) * size_t(nr) * sizeof(double), st));
+  const dim3 grid((unsigned)rblk, (unsigned)nslice);
+  const float ng = -float(ks.gamma) * kLog2e;
+  if (exact) kapply_otf_mfma_kernel<KP, true><<<grid, 256, 0, st>>>(Xr, qr, nr, Xc, qc, nc, p, ng, v, per, part);
+  else kapply_otf_mfma_kernel<KP, false><<<grid, 256, 0, st>>>(Xr, qr, nr, Xc, qc, nc, p, ng, v, per, part);
+  KQR_LAUNCH_CHECK();
+  otf_reduce_kernel<<<dim3((unsigned)((nr + 255) / 256)), 256, 0, st>>>(part, int(nslice), nr, u, ldu, scale, shift);
+  KQR_LAUNCH_CHECK();
+  KQR_CHECK_HIP(hipFreeAsync(part, st));
+}
+
 void kapply_otf(const float* Xr, const float* sqr, int64_t nr, const float* Xc, const float* sqc,
                 int64_t nc, int p, KernelSpec ks, const double* v64, double* u, int64_t ldu,
                 double out_scale, double out_shift, hipStream_t st, bool exact) {
   if (nr <= 0) return;
+  if (ks.kind == KQR_RBF && p <= 32) {
+    switch ((p + 3) / 4) {
+      case 1:
+      case 2: kapply_otf_mfma_p<8>(Xr, sqr, nr, Xc, sqc, nc, p, ks, v64, u, ldu, out_scale, out_shift, exact, st); return;
+      case 3: kapply_otf_mfma_p<12>(Xr, sqr, nr, Xc, sqc, nc, p, ks, v64, u, ldu, out_scale, out_shift, exact, st); return;
+      case 4: kapply_otf_mfma_p<16>(Xr, sqr, nr, Xc, sqc, nc, p, ks, v64, u, ldu, out_scale, out_shift, exact, st); return;
+      case 5: kapply_otf_mfma_p<20>(Xr, sqr, nr, Xc, sqc, nc, p, ks, v64, u, ldu, out_scale, out_shift, exact, st); return;
+      case 6: kapply_otf_mfma_p<24>(Xr, sqr, nr, Xc, sqc, nc, p, ks, v64, u, ldu, out_scale, out_shift, exact, st); return;
+      case 7: kapply_otf_mfma_p<28>(Xr, sqr, nr, Xc, sqc, nc, p, ks, v64, u, ldu, out_scale, out_shift, exact, st); return;
+      default: kapply_otf_mfma_p<32>(Xr, sqr, nr, Xc, sqc, nc, p, ks, v64, u, ldu, out_scale, out_shift, exact, st); return;
+    }
+  }
   KQR_DISPATCH_P(p, kapply_otf_p, Xr, sqr, nr, Xc, sqc, nc, p, ks, v64, u, ldu, out_scale, out_shift, exact, st);
 }
 

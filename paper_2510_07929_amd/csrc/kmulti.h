@@ -5,11 +5,24 @@
 
 namespace kqr {
 
+// Launch shape of the K V kernel: 16-byte loads per lane per step (4 or 8),
+// next step's loads issued before the current MFMAs or not, column segments.
+constexpr int kKvMaxSegs = 8;
+constexpr int kKvBuckets = 8;
+struct KvShape {
+  int nld = 8;
+  int prefetch = 1;
+  int segs = 4;
+};
+KvShape default_kv_shape(int dtype, int64_t n);        // autotuned when set, else the default above
+void set_kv_shape(int dtype, int64_t n, KvShape s);    // autotuner override (per dtype and size bucket)
+bool kv_shape_supported(const KvShape& s);
+
 // U[:, j] = K V[:, j] for j < m <= 16.  V16: n_pad x 16 FP32 row-major (rows >= n
 // and columns >= m zero); U: n x m FP64 (ld ldu); part: scratch of
-// segs * n * 16 doubles.
-void kapply_kv(const KMat& km, int64_t n, const float* V16, int m, double* U, int64_t ldu, double* part, int segs,
-               hipStream_t st);
+// kKvMaxSegs * n * 16 doubles.
+void kapply_kv(const KMat& km, int64_t n, const float* V16, int m, double* U, int64_t ldu, double* part,
+               hipStream_t st, const KvShape* shape = nullptr);
 struct SrcTable16 {
   const double* p[16];
 };

@@ -8,6 +8,7 @@
 #include "kmulti.h"
 
 #include <algorithm>
+#include <mutex>
 
 namespace kqr {
 
@@ -32,18 +33,19 @@ __device__ __forceinline__ uint16_t f2bf(float f) {
 // accumulators (FP32, two independent chains) are flushed into FP64 after
 // every stage.  K is streamed with 16-byte non-temporal loads, 64 contiguous
 // bytes per row per load instruction (the four lanes of a row are adjacent),
-// and the next step's loads are issued before the current step's MFMAs.
-//  FP32 K: v_mfma_f32_16x16x4f32; a step is 64 columns, a lane holds 16
-//          entries of its row (columns 16q + 4g + e for lane group g).
+// and (PF) the next step's loads are issued before the current step's MFMAs.
+// A lane issues NLD (4 or 8) loads per step, NLD KB in flight per wave.
+//  FP32 K: v_mfma_f32_16x16x4f32; a step is 16 NLD columns, a lane holds
+//          4 NLD entries of its row (columns 16q + 4g + e for lane group g).
 //  BF16 K: v_mfma_f32_16x16x32_bf16 with V split into hi + lo BF16 parts; a
-//          step is 128 columns, a lane holds 32 entries (32q + 8g + e).
+//          step is 32 NLD columns, a lane holds 8 NLD entries (32q + 8g + e).
 // Only the last step of a segment can be partial; it is read element-wise with
 // zero fill, so nothing beyond column ncols is touched.
-template <bool BF16>
+template <bool BF16, int NLD, bool PF>
 __global__ __launch_bounds__(256) void kv_mfma_kernel(const void* __restrict__ K, int64_t ldk, int64_t n,
                                                       int64_t ncols, const float* __restrict__ V,
                                                       int64_t seg_cols, double* __restrict__ out) {
-  constexpr int STEP = BF16 ? 128 : 64;
+  constexpr int STEP = (BF16 ? 32 : 16) * NLD;
   __shared__ float vs[BF16 ? 1 : 16][BF16 ? 1 : kVpad];
   __shared__ uint16_t vh[BF16 ? 16 : 1][BF16 ? kVpad : 1];
   __shared__ uint16_t vl[BF16 ? 16 : 1][BF16 ? kVpad : 1];
@@ -56,16 +58,16 @@ __global__ __launch_bounds__(256) void kv_mfma_kernel(const void* __restrict__ K
   double acc64[4] = {0.0, 0.0, 0.0, 0.0};
   const char* krow = static_cast<const char*>(K) + my_row * ldk * (BF16 ? 2 : 4);
   // a[q] = 16 bytes of the row at column col + (BF16 ? 32 : 16) q + (BF16 ? 8 : 4) g
-  auto load_step = [&](int64_t col, u32x4 (&a)[4]) {
+  auto load_step = [&](int64_t col, u32x4 (&a)[NLD]) {
     const int per = BF16 ? 8 : 4;  // entries per 16 bytes
     if (col + STEP <= c1) {
 #pragma unroll
-      for (int q = 0; q < 4; ++q)
+      for (int q = 0; q < NLD; ++q)
         a[q] = __builtin_nontemporal_load(
             reinterpret_cast<const u32x4*>(krow + (col + q * 4 * per + lg * per) * (BF16 ? 2 : 4)));
     } else {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
+      for (int q = 0; q < NLD; ++q) {
         const int64_t cc = col + q * 4 * per + lg * per;
         if (BF16) {
           const uint16_t* kr = reinterpret_cast<const uint16_t*>(krow);
@@ -89,7 +91,7 @@ __global__ __launch_bounds__(256) void kv_mfma_kernel(const void* __restrict__ K
   };
   for (int64_t cb = c0; cb < c1; cb += kKC) {
     const int cnt = int(min<int64_t>(kKC, c1 - cb));
-    u32x4 a[4], an[4];
+    u32x4 a[NLD], an[NLD];
     load_step(cb, a);  // independent of V: in flight while V is staged
     __syncthreads();
     for (int e = threadIdx.x; e < kKC * 16; e += 256) {
@@ -107,10 +109,10 @@ __global__ __launch_bounds__(256) void kv_mfma_kernel(const void* __restrict__ K
     f32x4 accA = {0.f, 0.f, 0.f, 0.f}, accB = {0.f, 0.f, 0.f, 0.f};
     for (int kk = 0; kk < cnt; kk += STEP) {
       const bool more = kk + STEP < cnt;
-      if (more) load_step(cb + kk + STEP, an);
+      if (PF && more) load_step(cb + kk + STEP, an);
       if (BF16) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < NLD; ++q) {
           const bf16x8 av = __builtin_bit_cast(bf16x8, a[q]);
           const int off = kk + 32 * q + 8 * lg;
           const bf16x8 bh = *reinterpret_cast<const bf16x8*>(&vh[li][off]);
@@ -120,7 +122,7 @@ __global__ __launch_bounds__(256) void kv_mfma_kernel(const void* __restrict__ K
         }
       } else {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < NLD; ++q) {
           const f32x4 b = *reinterpret_cast<const f32x4*>(&vs[li][kk + 16 * q + 4 * lg]);
           const f32x4 av = __builtin_bit_cast(f32x4, a[q]);
           accA = __builtin_amdgcn_mfma_f32_16x16x4f32(av[0], b[0], accA, 0, 0, 0);
@@ -130,8 +132,12 @@ __global__ __launch_bounds__(256) void kv_mfma_kernel(const void* __restrict__ K
         }
       }
       if (more) {
+        if (PF) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) a[q] = an[q];
+          for (int q = 0; q < NLD; ++q) a[q] = an[q];
+        } else {
+          load_step(cb + kk + STEP, a);
+        }
       }
     }
 #pragma unroll
@@ -157,18 +163,59 @@ __global__ void kv_reduce_kernel(const double* __restrict__ part, int nseg, int6
   U[i * ldu + j] = s;
 }
 
-void kapply_kv(const KMat& km, int64_t n, const float* V16, int m, double* U, int64_t ldu, double* part, int segs,
-               hipStream_t st) {
+namespace {
+std::mutex g_kv_mu;
+KvShape g_kv_shape[2][kKvBuckets];
+bool g_kv_set[2][kKvBuckets] = {};
+int kv_bucket(int64_t n) {
+  int b = 0;
+  while (b + 1 < kKvBuckets && (int64_t(4096) << b) < n) ++b;
+  return b;
+}
+template <bool BF16>
+void kv_launch(const KvShape& s, dim3 grid, const KMat& km, int64_t n, const float* V16, int64_t seg_cols,
+               double* part, hipStream_t st) {
+  if (s.nld == 4 && s.prefetch)
+    kv_mfma_kernel<BF16, 4, true><<<grid, 256, 0, st>>>(km.K, km.ld, n, n, V16, seg_cols, part);
+  else if (s.nld == 4)
+    kv_mfma_kernel<BF16, 4, false><<<grid, 256, 0, st>>>(km.K, km.ld, n, n, V16, seg_cols, part);
+  else if (s.prefetch)
+    kv_mfma_kernel<BF16, 8, true><<<grid, 256, 0, st>>>(km.K, km.ld, n, n, V16, seg_cols, part);
+  else
+    kv_mfma_kernel<BF16, 8, false><<<grid, 256, 0, st>>>(km.K, km.ld, n, n, V16, seg_cols, part);
+}
+}  // namespace
+
+KvShape default_kv_shape(int dtype, int64_t n) {
+  std::lock_guard<std::mutex> lk(g_kv_mu);
+  const int d = dtype == KQR_BF16, b = kv_bucket(n);
+  if (g_kv_set[d][b]) return g_kv_shape[d][b];
+  return KvShape{};
+}
+
+void set_kv_shape(int dtype, int64_t n, KvShape s) {
+  std::lock_guard<std::mutex> lk(g_kv_mu);
+  const int d = dtype == KQR_BF16, b = kv_bucket(n);
+  g_kv_shape[d][b] = s;
+  g_kv_set[d][b] = true;
+}
+
+bool kv_shape_supported(const KvShape& s) {
+  return (s.nld == 4 || s.nld == 8) && s.segs >= 1 && s.segs <= kKvMaxSegs;
+}
+
+void kapply_kv(const KMat& km, int64_t n, const float* V16, int m, double* U, int64_t ldu, double* part,
+               hipStream_t st, const KvShape* shape) {
   if (n <= 0) return;
-  segs = std::max(1, segs);
+  const KvShape s = shape ? *shape : default_kv_shape(km.dtype, n);
+  if (!kv_shape_supported(s)) fail(KQR_EINVAL, "unsupported K V shape (nld %d, segs %d)", s.nld, s.segs);
+  int segs = s.segs;
   int64_t seg_cols = (n + segs - 1) / segs;
   seg_cols = (seg_cols + kKC - 1) / kKC * kKC;
   segs = int((n + seg_cols - 1) / seg_cols);
   const dim3 grid((unsigned)((n + 63) / 64), (unsigned)segs);
-  if (km.dtype == KQR_BF16)
-    kv_mfma_kernel<true><<<grid, 256, 0, st>>>(km.K, km.ld, n, n, V16, seg_cols, part);
-  else
-    kv_mfma_kernel<false><<<grid, 256, 0, st>>>(km.K, km.ld, n, n, V16, seg_cols, part);
+  if (km.dtype == KQR_BF16) kv_launch<true>(s, grid, km, n, V16, seg_cols, part, st);
+  else kv_launch<false>(s, grid, km, n, V16, seg_cols, part, st);
   KQR_LAUNCH_CHECK();
   kv_reduce_kernel<<<dim3((unsigned)((n * 16 + 255) / 256)), 256, 0, st>>>(part, segs, n, m, U, ldu);
   KQR_LAUNCH_CHECK();

@@ -24,7 +24,7 @@ KQR_EINVAL, KQR_ENOMEM, KQR_ENODEVICE, KQR_EHIP, KQR_ENUMERIC = -1, -2, -3, -4, 
 KQR_RBF, KQR_LAPLACIAN = 0, 1
 KQR_FP32, KQR_BF16 = 0, 1
 KQR_KMODE_AUTO, KQR_KMODE_MATERIALIZE, KQR_KMODE_ON_THE_FLY = 0, 1, 2
-KQR_APPLY_FAST, KQR_APPLY_EXACT = 0, 1
+KQR_APPLY_FAST, KQR_APPLY_EXACT, KQR_APPLY_KV = 0, 1, 2
 
 KERNELS = {"rbf": KQR_RBF, "laplacian": KQR_LAPLACIAN}
 KDTYPES = {"fp32": KQR_FP32, "bf16": KQR_BF16}
@@ -83,6 +83,7 @@ _SIGS = {
     "kqr_adaptive_rank": (C.c_int, [_P, _I64, _I64, _I64, C.c_double, _P, _P, _P]),
     "kqr_autotune_apply": (C.c_int, [_P, C.c_int, _I64, _I64, C.c_int, C.c_int, C.c_char_p, _I64, _P]),
     "kqr_set_apply_shape": (C.c_int, [C.c_int, C.c_int, _I64, C.c_int, C.c_int, C.c_int]),
+    "kqr_set_kv_shape": (C.c_int, [C.c_int, _I64, C.c_int, C.c_int, C.c_int]),
     "kqr_pcg_solve": (C.c_int, [_P, _I64, _I64, C.c_int, C.c_double, _P, C.c_int, _I64, _P, _I64, _I64,
                                 C.c_double, _P, _P, C.c_double, C.c_int, _P, _P, _P, _P]),
     "kqr_ssn_gradient": (C.c_int, [_I64, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double,
@@ -301,6 +302,11 @@ def kqr_autotune_apply(K, mode=KQR_APPLY_FAST, reps=5, stream=None):
 def kqr_set_apply_shape(k_dtype, mode, n, rows, unroll, segs):
     _check(lib().kqr_set_apply_shape(_kdtype_id(k_dtype), int(mode), int(n), int(rows), int(unroll), int(segs)),
            "kqr_set_apply_shape")
+
+
+def kqr_set_kv_shape(k_dtype, n, nld, prefetch, segs):
+    _check(lib().kqr_set_kv_shape(_kdtype_id(k_dtype), int(n), int(nld), int(prefetch), int(segs)),
+           "kqr_set_kv_shape")
 
 
 def kqr_woodbury_apply(F, r, c, Ldiag, w, stream=None):

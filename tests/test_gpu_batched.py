@@ -61,6 +61,42 @@ def test_kv_multi_rhs_matches_oracle(dev, kd, n, m):
     assert np.all(err <= bound + 1e-12), float((err / (bound + 1e-12)).max())
 
 
+@pytest.mark.parametrize("kd", ["fp32", "bf16"])
+def test_kv_every_launch_shape_and_autotuner(dev, kd):
+    # every shape the autotuner may choose meets the same bound; ragged n so the
+    # last step of the last segment is partial for every step width
+    n, m, p = 2777, 9, 8
+    X, _ = inputs.additive(n, p, (131, n))
+    gamma = 1.0 / p
+    V = np.random.default_rng(7).standard_normal((n, m))
+    K = kqr.kqr_kernel_build(torch.from_numpy(X).to(dev), "rbf", gamma, kd)
+    Vt = torch.from_numpy(V).to(dev)
+    Kref, Kb = entry_bound(X, gamma)
+    A = np.abs(V)
+    if kd == "fp32":
+        bound = Kb @ A + 300 * U32 * (Kref @ A)
+    else:
+        bound = (2.0 ** -8 * (Kref + Kb) + Kb) @ A + (2.0 ** -15 + 300 * U32) * (Kref @ A)
+    ref = Kref @ V
+    say("K V shapes", kd)
+    outs = []
+    for nld in (4, 8):
+        for pf in (0, 1):
+            for segs in (1, 2, 4, 8):
+                kqr.kqr_set_kv_shape(kd, n, nld, pf, segs)
+                U = kqr.kqr_kernel_apply(Vt, K=K).cpu().numpy()
+                err = np.abs(U - ref)
+                assert np.all(err <= bound + 1e-12), (nld, pf, segs, float((err / (bound + 1e-12)).max()))
+                outs.append(U)
+    rep = kqr.kqr_autotune_apply(K, kqr.KQR_APPLY_KV, reps=2)
+    assert rep["n"] == n and len(rep["shapes"]) == 16
+    assert rep["best"]["us"] == min(s["us"] for s in rep["shapes"])
+    U = kqr.kqr_kernel_apply(Vt, K=K).cpu().numpy()
+    assert np.all(np.abs(U - ref) <= bound + 1e-12)
+    with pytest.raises(kqr.KqrError):
+        kqr.kqr_set_kv_shape(kd, n, 6, 0, 1)
+
+
 def _oracle_obj(prob, tau, alpha, beta):
     K = okernel.kernel_matrix(prob.X, prob.kernel, prob.gamma)
     Ka = K @ alpha
