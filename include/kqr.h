@@ -108,6 +108,11 @@ typedef struct kqr_options {
   int exact_k;         /* BF16 storage: source of the exact operator of the residuals and refinement.
                           0 = FP32 entries recomputed from X on every exact apply (no extra memory);
                           1 = an FP32 copy of K kept beside the BF16 one (n*ld*4 more bytes, streamed). 0 */
+  double ssn_adapt;    /* Phase II subproblem accuracy (the summable tolerances of Algorithm 2's
+                          criterion (A)): SSN of outer iteration k stops at ||grad phi_k|| <=
+                          (1+||y||) max(ssn_rel tol, min(ssn_adapt e_{k-1}, 1)), e_{k-1} =
+                          max(eta_kkt, eta_gap) of the previous outer iterate (Phase I's for k = 0);
+                          0 = always ssn_rel tol.  0.3 */
 } kqr_options;
 
 /* ---------------------------------------------------------------- report */

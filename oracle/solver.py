@@ -41,7 +41,8 @@ class OracleOptions:
     tau2: float = 0.1
     eps_floor: float = 1e-12      # keeps L invertible when ||grad|| underflows
     ssn_max_iter: int = 50
-    ssn_rel: float = 0.5          # SSN stop: ||grad phi|| <= ssn_rel * tol * (1 + ||y||)
+    ssn_rel: float = 0.5          # SSN stop: ||grad phi|| <= (1 + ||y||) max(ssn_rel tol, ssn_adapt e_prev)
+    ssn_adapt: float = 0.3        # e_prev = max(eta_kkt, eta_gap) of the previous outer iterate
     sigma_factor: float = 5.0     # sigma <- min(sigma_factor sigma, sigma_max) when eta_d stalls
     sigma_stall: float = 0.25
     sigma_max: float = 1e8
@@ -216,11 +217,16 @@ def alm(op, y, tau, lam, F, start: dict, opts: OracleOptions, direct: bool, hist
     sigma = float(start["sigma"])
     Ka = op.apply(alpha)
     eta_d_prev = start["kkt"]["eta_d"] if start.get("kkt") else None
-    stop = opts.ssn_rel * opts.tol * (1.0 + float(np.linalg.norm(y)))
+    # Subproblem accuracy: the summable tolerances of criterion (A) are read as
+    # a fraction of the previous outer residual, floored at the final target
+    # (after the multiplier update ||grad phi_k|| = (1 + ||y||) eta_p).
+    scale = 1.0 + float(np.linalg.norm(y))
+    e_prev = start["kkt"]["err"] if start.get("kkt") else np.inf
     tot = dict(newton=0, pcg=0, ls=0)
     res, v = None, start.get("v", alpha).copy()
     k = 0
     for k in range(opts.alm_max_iter):
+        stop = scale * max(opts.ssn_rel * opts.tol, min(opts.ssn_adapt * e_prev, 1.0))
         alpha, v, Ka, info = ssn(op, y, tau, lam, beta, z, sigma, alpha, Ka, F, opts, direct, stop)
         for key in tot:
             tot[key] += info[key]
@@ -234,6 +240,7 @@ def alm(op, y, tau, lam, F, start: dict, opts: OracleOptions, direct: bool, hist
         if eta_d_prev is not None and res["eta_d"] > opts.sigma_stall * eta_d_prev:
             sigma = min(opts.sigma_factor * sigma, opts.sigma_max)
         eta_d_prev = res["eta_d"]
+        e_prev = res["err"]
     return dict(alpha=alpha, v=v, beta=beta, z=z, Kalpha=Ka, sigma=sigma,
                 iters=k + 1, kkt=res, **tot)
 

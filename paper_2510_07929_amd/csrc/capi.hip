@@ -195,6 +195,7 @@ int kqr_default_options(kqr_options* o) {
   o->k_dtype = KQR_FP32;
   o->kmode = KQR_KMODE_AUTO;
   o->refine = 1;
+  o->ssn_adapt = 0.3;
   o->pivot_uniforms = nullptr;
   o->seed = 0;
   o->verbose = 0;

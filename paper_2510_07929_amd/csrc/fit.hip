@@ -48,6 +48,7 @@ void validate_options(const kqr_options& o) {
   KQR_OPT_REQUIRE(o.k_dtype == KQR_FP32 || o.k_dtype == KQR_BF16, "k_dtype must be KQR_FP32 or KQR_BF16");
   KQR_OPT_REQUIRE(o.kmode >= KQR_KMODE_AUTO && o.kmode <= KQR_KMODE_ON_THE_FLY, "invalid kmode");
   KQR_OPT_REQUIRE(o.exact_k == 0 || o.exact_k == 1, "exact_k must be 0 or 1");
+  KQR_OPT_REQUIRE(o.ssn_adapt >= 0.0 && o.ssn_adapt <= 10.0, "need 0 <= ssn_adapt <= 10");
   KQR_OPT_REQUIRE(o.rank <= 1023, "rank must be <= 1023");
   KQR_OPT_REQUIRE(o.xi > 0.0 && o.xi < 1.0, "need 0 < xi < 1");
   KQR_OPT_REQUIRE(o.sigma_factor >= 1.0 && o.sigma_max >= o.admm_sigma,

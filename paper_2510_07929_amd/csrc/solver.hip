@@ -391,11 +391,16 @@ void Solver::ssn(double stop, kqr_info& info) {
 
 void Solver::phase2(kqr_info& info) {
   const double t0 = now_s();
-  const double stop = o_.ssn_rel * o_.tol * (1.0 + ynorm_);
+  // Subproblem accuracy: the summable tolerances of criterion (A) are taken
+  // as a fraction of the previous outer residual, floored at the final target
+  // (after the multiplier update ||grad phi_k|| = (1 + ||y||) eta_p).
+  const double scale = 1.0 + ynorm_;
   Kkt k = last_;
+  double e_prev = last_.err;
   int it = 0;
   bool done = false;
   for (it = 0; it < o_.alm_max_iter; ++it) {
+    const double stop = scale * std::max(o_.ssn_rel * o_.tol, std::min(o_.ssn_adapt * e_prev, 1.0));
     op_.apply_exact(alpha_.as<double>(), Ka_.as<double>(), st_);  // reset drift of the tracked K alpha
     ssn(stop, info);
     const double sa = sum_of(alpha_.as<double>());
@@ -414,6 +419,7 @@ void Solver::phase2(kqr_info& info) {
     }
     if (k.eta_d > o_.sigma_stall * eta_d_prev_) sigma_ = std::min(o_.sigma_factor * sigma_, o_.sigma_max);
     eta_d_prev_ = k.eta_d;
+    e_prev = k.err;
   }
   info.alm_iters = it;
   converged_ = done;

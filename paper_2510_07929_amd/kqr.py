@@ -43,7 +43,7 @@ class KqrOptions(C.Structure):
         ("rank", C.c_int), ("xi", C.c_double), ("pcg_max_iter", C.c_int),
         ("k_dtype", C.c_int), ("kmode", C.c_int), ("refine", C.c_int),
         ("pivot_uniforms", C.POINTER(C.c_double)), ("seed", C.c_uint64), ("verbose", C.c_int),
-        ("profile", C.c_int), ("exact_k", C.c_int),
+        ("profile", C.c_int), ("exact_k", C.c_int), ("ssn_adapt", C.c_double),
     ]
 
 
