@@ -58,7 +58,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the CPU oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="skip the K-apply shape sweep before the warm-up")
-    ap.add_argument("--traffic", default=None, help="JSON file with measured HBM bytes per K-apply launch")
+    ap.add_argument("--traffic", default=None,
+                    help="counter summary (profiles/*_traffic.md) with the measured HBM bytes per K-apply launch")
     ap.add_argument("--fd", action="store_true", help="c4: also time central differences of the gradient")
     ap.add_argument("--verbose", action="store_true", help="per-iteration solver log on stderr")
     return ap.parse_args()
@@ -97,6 +98,20 @@ def cpu_baseline(prob, budget_s):
         "full_apply_s_extrapolated": round(t_apply / reps * n / rows, 3),
         "affinity_cores": len(os.sched_getaffinity(0)),
     }
+
+
+def measured_traffic(args, prob, kdtype):
+    """HBM bytes per launch of the fast K-apply from the committed counter
+    summary of this workload (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy
+    calibrated), or None when there is none or the kernel source changed
+    since the counters were taken."""
+    from paper_2510_07929_amd import traffic as tr
+
+    path = args.traffic or os.path.join(ROOT, "profiles", f"kapply_rows_{prob.name}_{kdtype}_traffic.md")
+    got = tr.read_summary(path)
+    if got is None or got[1] != tr.source_digest():
+        return None
+    return got[0]
 
 
 def fit_summary(info, st):
@@ -186,9 +201,7 @@ def run_materialised(args, prob, kdtype, tune, **extra):
     value = nfast * kbytes / elapsed / 1e9
     avg = tfast / max(nfast, 1)
     achieved = kbytes / avg / 1e9 if avg > 0 else 0.0
-    traffic = None
-    if args.traffic and os.path.exists(args.traffic):
-        traffic = json.load(open(args.traffic)).get("bytes_per_launch")
+    traffic = measured_traffic(args, prob, kdtype)
     last, st = outs[-1]
     roof = {
         "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
