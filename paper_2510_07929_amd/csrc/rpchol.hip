@@ -48,17 +48,23 @@ __global__ __launch_bounds__(64) void rpc_select_kernel(const double* __restrict
                                                         const double* __restrict__ bsum, int nblk, double u, int step,
                                                         int64_t* __restrict__ piv, double* __restrict__ state) {
   const int lane = threadIdx.x;
-  __shared__ double pref[kSelBlocks + 1];
-  if (lane == 0) {
-    double acc = 0.0;
-    pref[0] = 0.0;
-    for (int b = 0; b < nblk; ++b) {
-      acc += bsum[b];
-      pref[b + 1] = acc;
-    }
+  // prefix sums of the block sums: lane l owns blocks [PER l, PER l + PER)
+  constexpr int PER = kSelBlocks / 64;
+  double bs[PER];
+  double own = 0.0;
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int b = lane * PER + q;
+    bs[q] = b < nblk ? bsum[b] : 0.0;
+    own += bs[q];
   }
-  __syncthreads();
-  const double total = pref[nblk];
+  double incl = own;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const double t = __shfl_up(incl, off);
+    if (lane >= off) incl += t;
+  }
+  const double total = __shfl(incl, 63);
   bool stop = state[1] != 0.0;
   if (step == 0) stop = false;
   const double tr0 = step == 0 ? total : state[0];
@@ -66,13 +72,31 @@ __global__ __launch_bounds__(64) void rpc_select_kernel(const double* __restrict
   int64_t found = -1;
   if (!stop) {
     const double target = u * total;
+    // first block whose running sum passes the target
+    int mine = -1;
+    double before = 0.0;
+    double run_b = incl - own;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const double next = run_b + bs[q];
+      if (mine < 0 && next > target && bs[q] > 0.0) {
+        mine = lane * PER + q;
+        before = run_b;
+      }
+      run_b = next;
+    }
+    const unsigned long long hitm = __ballot(mine >= 0);
     int bsel = -1;
-    for (int b = 0; b < nblk; ++b)
-      if (pref[b + 1] > target && bsum[b] > 0.0) { bsel = b; break; }
+    double pref_sel = 0.0;
+    if (hitm) {
+      const int src = __ffsll((long long)hitm) - 1;
+      bsel = __shfl(mine, src);
+      pref_sel = __shfl(before, src);
+    }
     if (bsel >= 0) {
       // scan from the selected block on (a later block only when the rounding
       // of block sums and running sum disagree next to the target)
-      double run = pref[bsel];
+      double run = pref_sel;
       for (int64_t base = int64_t(bsel) * chunk; base < n && found < 0; base += 64) {
         const int64_t i = base + lane;
         const double di = i < n ? d[i] : 0.0;
