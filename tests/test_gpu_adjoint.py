@@ -137,3 +137,43 @@ def test_adjoint_argument_errors(dev):
     assert e.value.status == kqr.KQR_EINVAL
     with pytest.raises(ValueError):
         kqr.kqr_fit_grad(X, y, prob.tau, prob.lam, "rbf", gamma, X[:, :3].contiguous(), y[:10])
+
+
+def test_adjoint_full_size_against_kink_free_differences(dev):
+    # the c4 workload at its full size (n = 20000 + 5000 validation), in the
+    # configuration bench.py times: the adjoint against central differences of
+    # polished fits, with the step shrunk until the interval crosses no kink
+    prob, gamma = _problem(20000, "rbf", seed=0)
+    X = torch.from_numpy(prob.X).to(dev)
+    Xv = torch.from_numpy(prob.extras["Xval"]).to(dev)
+    yv = torch.from_numpy(prob.extras["yval"]).to(dev)
+    say("adjoint full size")
+    _, _, J0, (dg, dl), m, pol, _, st = _gpu(prob, dev, "rbf", gamma, rank=0)
+    assert st == kqr.KQR_OK and pol and m > 0
+
+    def probe(gg, ll):
+        a, b, J, _, _, pol, _, st = _gpu(prob, dev, "rbf", gg, lam=ll, rank=0)
+        assert st == kqr.KQR_OK and pol
+        f = kqr.kqr_predict(X, a, b, ll, "rbf", gg, Xv)
+        ac = a.cpu().numpy()
+        return J, torch.sign(yv - f).cpu().numpy(), (ac > prob.tau - 1) & (ac < prob.tau)
+
+    _, s0, E0 = probe(gamma, prob.lam)
+    checked = 0
+    for which, g_an in (("gamma", dg), ("lambda", dl)):
+        for h in (1e-4, 3e-5, 1e-5):
+            vals, kink = [], False
+            for sgn in (1, -1):
+                gg = gamma * math.exp(sgn * h) if which == "gamma" else gamma
+                ll = prob.lam * math.exp(sgn * h) if which == "lambda" else prob.lam
+                J, s, E = probe(gg, ll)
+                kink |= not (np.array_equal(s, s0) and np.array_equal(E, E0))
+                vals.append(J)
+            fd = (vals[0] - vals[1]) / (2 * h)
+            rel = abs(fd - g_an) / abs(g_an)
+            say(f"  d/dlog {which} h={h:g}: adjoint {g_an:.10g} fd {fd:.10g} rel {rel:.2e} kink={kink}")
+            if not kink:
+                assert rel <= 1e-6
+                checked += 1
+                break
+    say(f"  kink-free checks: {checked} of 2")
