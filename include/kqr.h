@@ -308,9 +308,12 @@ int kqr_fit_batch(int nprob, const float* const* X, const double* const* y, cons
  * holds for both kernels.  Before the gradient the fit is polished: E is read
  * from the final multipliers (|z_i| below a threshold), alpha_N is put on its
  * bound and (alpha_E, beta) solve the bordered KKT system with the FP64
- * Cholesky of K_EE (entries from FP32 X as in the K build); the polish is kept
- * when alpha_E stays in the box and every residual sign matches the
- * partition, and alpha / beta are then the polished values.
+ * Cholesky of K_EE (entries formed in FP64 from the FP32 X); violators are
+ * moved between the sets (an interior alpha outside the box to the bound it
+ * crossed, a bound alpha with a residual of the wrong sign to the interior)
+ * for up to 12 active-set rounds.  The polish is kept when alpha_E stays in
+ * the box and every residual sign matches the partition, and alpha / beta are
+ * then the polished values.
  *  Xval device nval x p FP32; yval device nval FP64; other arguments as kqr_fit.
  *  val_loss, grad (host, 2: dJ/dlog gamma, dJ/dlog lambda), n_interior and
  *  polished are host outputs (n_interior and polished may be NULL).

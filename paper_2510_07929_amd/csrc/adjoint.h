@@ -12,10 +12,13 @@ struct GradOutcome {
   double dlam = 0.0;  // dJ / dlog(lambda)
   int64_t n_interior = 0;
   bool polished = false;
+  int polish_rounds = 0;  // active-set rounds used by the polish
 };
 
 // Largest interior set whose FP64 K_EE is factored densely.
 constexpr int64_t kAdjointMaxInterior = 8192;
+// Active-set rounds of the polish before giving up.
+constexpr int kPolishRounds = 12;
 
 // X (n x p, device FP32); alpha (device, n) and
 // *beta are the fitted coefficients and are replaced by the polished ones when

@@ -170,11 +170,37 @@ __global__ void mask_kernel(const double* __restrict__ z, int64_t n, double thr,
   if (i < n) S[i] = fabs(z[i]) <= thr ? 1 : 0;
 }
 
-// at = alpha on N set to its bound (tau if z > 0, tau - 1 if z < 0), 0 on E
-__global__ void bound_alpha_kernel(const double* __restrict__ z, const uint8_t* __restrict__ S, int64_t n, double tau,
-                                   double* __restrict__ at) {
+// partition state: 0 interior, +1 at tau, -1 at tau - 1
+__global__ void state_init_kernel(const double* __restrict__ z, int64_t n, double thr, int8_t* __restrict__ s) {
   const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
-  if (i < n) at[i] = S[i] ? 0.0 : (z[i] > 0.0 ? tau : tau - 1.0);
+  if (i < n) s[i] = fabs(z[i]) <= thr ? 0 : (z[i] > 0.0 ? 1 : -1);
+}
+
+__global__ void mask_from_state_kernel(const int8_t* __restrict__ s, int64_t n, uint8_t* __restrict__ S) {
+  const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (i < n) S[i] = s[i] == 0 ? 1 : 0;
+}
+
+// at = alpha on N set to its bound, 0 on E
+__global__ void bound_from_state_kernel(const int8_t* __restrict__ s, int64_t n, double tau, double* __restrict__ at) {
+  const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (i < n) at[i] = s[i] == 0 ? 0.0 : (s[i] > 0 ? tau : tau - 1.0);
+}
+
+// one active-set move per violator (see polish_check_kernel for the tests)
+__global__ void repair_kernel(const double* __restrict__ alpha, const double* __restrict__ y,
+                              const double* __restrict__ Ka, int8_t* __restrict__ s, int64_t n, double tau,
+                              double beta, double lam, double slack_a, double slack_z) {
+  const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (i >= n) return;
+  const int8_t si = s[i];
+  if (si == 0) {
+    if (alpha[i] > tau + slack_a) s[i] = 1;
+    else if (alpha[i] < tau - 1.0 - slack_a) s[i] = -1;
+  } else {
+    const double r = y[i] - beta - Ka[i] / lam;
+    if ((si > 0 && r < -slack_z) || (si < 0 && r > slack_z)) s[i] = 0;
+  }
 }
 
 // alpha[idx[a]] = aE[a]
@@ -198,21 +224,22 @@ __global__ void combine_kernel(const double* __restrict__ a, const double* __res
   if (i < m) out[i] = lam * (a[i] - c * b[i]);
 }
 
-// box / sign check of a polished point: partials [#violations]
+// box / sign check of a polished point: an interior alpha must lie in the box,
+// alpha = tau needs a residual >= 0 and alpha = tau - 1 one <= 0 (both up to
+// slack); partials [#violations]
 __global__ __launch_bounds__(256) void polish_check_kernel(const double* __restrict__ alpha, const double* __restrict__ y,
-                                                           const double* __restrict__ Ka, const uint8_t* __restrict__ S,
-                                                           const double* __restrict__ z, int64_t n, double tau,
-                                                           double beta, double lam, double slack_a, double slack_z,
-                                                           double* __restrict__ part) {
+                                                           const double* __restrict__ Ka, const int8_t* __restrict__ s,
+                                                           int64_t n, double tau, double beta, double lam,
+                                                           double slack_a, double slack_z, double* __restrict__ part) {
   __shared__ double sh[4];
   double bad = 0.0;
   for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) {
-    if (S[i]) {
+    if (s[i] == 0) {
       if (alpha[i] < tau - 1.0 - slack_a || alpha[i] > tau + slack_a) bad += 1.0;
     } else {
       const double zz = y[i] - beta - Ka[i] / lam;
-      if (z[i] > 0.0 && zz < -slack_z) bad += 1.0;
-      if (z[i] < 0.0 && zz > slack_z) bad += 1.0;
+      if (s[i] > 0 && zz < -slack_z) bad += 1.0;
+      if (s[i] < 0 && zz > slack_z) bad += 1.0;
     }
   }
 #pragma unroll
@@ -325,20 +352,30 @@ GradOutcome adjoint_gradient(const float* X, int64_t n, int p, KernelSpec ks, do
   const double ynorm = std::sqrt(dots.run(n, y, y, st));
   InteriorFactor fe;
   DevBuf uE, aE;
-  // ---------------- active-set polish over growing thresholds on |z|
+  // ---------------- active-set polish
+  // Partition from the multipliers (|z_i| <= thr interior, else the bound of
+  // z's sign), then primal-dual active-set rounds: solve the bordered system
+  // on the partition; an interior coefficient outside the box moves to the
+  // bound it crossed, a bound coefficient whose residual has the wrong sign
+  // moves to the interior set; stop when nothing moves.
   const double scale = tol * (1.0 + ynorm);
-  const double thrs[] = {0.0, scale, 10.0 * scale, 100.0 * scale, 1000.0 * scale, 10000.0 * scale};
+  const double slack_a = 1e-10, slack_z = 1e-9 * (1.0 + ynorm);
+  DevBuf state(static_cast<size_t>(n));
+  int8_t* s8 = state.as<int8_t>();
+  state_init_kernel<<<blocks_for(n), 256, 0, st>>>(z, n, scale, s8);
+  KQR_LAUNCH_CHECK();
   double beta_new = *beta;
-  for (double thr : thrs) {
-    mask_kernel<<<blocks_for(n), 256, 0, st>>>(z, n, thr, S.as<uint8_t>());
+  for (int round = 0; round < kPolishRounds; ++round) {
+    mask_from_state_kernel<<<blocks_for(n), 256, 0, st>>>(s8, n, S.as<uint8_t>());
     KQR_LAUNCH_CHECK();
     const int64_t m = index_list(S.as<uint8_t>(), n, idx.as<int>(), cnt.as<int>(), st);
-    if (m == 0 || m > kAdjointMaxInterior) continue;
-    if (!fe.build(X, p, ks, idx.as<int>(), m, dots, st)) continue;
+    out.polish_rounds = round + 1;
+    if (m == 0 || m > kAdjointMaxInterior) break;
+    if (!fe.build(X, p, ks, idx.as<int>(), m, dots, st)) break;
     uE.alloc(size_t(m) * sizeof(double));
     aE.alloc(size_t(m) * sizeof(double));
     // alpha_N on its bounds: q_E = y_E - (K at)_E / lambda, q_beta = -1^T at
-    bound_alpha_kernel<<<blocks_for(n), 256, 0, st>>>(z, S.as<uint8_t>(), n, tau, at.as<double>());
+    bound_from_state_kernel<<<blocks_for(n), 256, 0, st>>>(s8, n, tau, at.as<double>());
     KQR_LAUNCH_CHECK();
     kapply64(fe.XE.as<float>(), m, X, n, p, ks, at.as<double>(), uE.as<double>(), 1.0, 0.0, false, st);
     rhs_e_kernel<<<blocks_for(m), 256, 0, st>>>(y, idx.as<int>(), uE.as<double>(), m, lam, uE.as<double>());
@@ -354,8 +391,8 @@ GradOutcome adjoint_gradient(const float* X, int64_t n, int p, KernelSpec ks, do
     KQR_LAUNCH_CHECK();
     // box of alpha_E and residual signs on N, with the full K alpha
     kapply64(X, n, X, n, p, ks, alpha_try.as<double>(), Ka.as<double>(), 1.0, 0.0, false, st);
-    polish_check_kernel<<<kRedBlocks, 256, 0, st>>>(alpha_try.as<double>(), y, Ka.as<double>(), S.as<uint8_t>(), z, n,
-                                                    tau, bt, lam, 1e-10, 1e-9 * (1.0 + ynorm), part.as<double>());
+    polish_check_kernel<<<kRedBlocks, 256, 0, st>>>(alpha_try.as<double>(), y, Ka.as<double>(), s8, n, tau, bt, lam,
+                                                    slack_a, slack_z, part.as<double>());
     KQR_LAUNCH_CHECK();
     if (dots.finalize(part.as<double>(), 1, 0, st) == 0.0) {
       clip_kernel<<<blocks_for(n), 256, 0, st>>>(alpha_try.as<double>(), S.as<uint8_t>(), n, tau);
@@ -365,9 +402,12 @@ GradOutcome adjoint_gradient(const float* X, int64_t n, int p, KernelSpec ks, do
       out.polished = true;
       break;
     }
+    repair_kernel<<<blocks_for(n), 256, 0, st>>>(alpha_try.as<double>(), y, Ka.as<double>(), s8, n, tau, bt, lam,
+                                                 slack_a, slack_z);
+    KQR_LAUNCH_CHECK();
   }
-  if (!out.polished) {  // gradient at the fitted iterate with E = {z == 0}
-    mask_kernel<<<blocks_for(n), 256, 0, st>>>(z, n, 0.0, S.as<uint8_t>());
+  if (!out.polished) {  // gradient at the fitted iterate with E = {|z| <= thr}
+    mask_kernel<<<blocks_for(n), 256, 0, st>>>(z, n, scale, S.as<uint8_t>());
     KQR_LAUNCH_CHECK();
     const int64_t m = index_list(S.as<uint8_t>(), n, idx.as<int>(), cnt.as<int>(), st);
     if (m == 0) fail(KQR_ENUMERIC, "no interior coefficients: beta is not differentiable");
