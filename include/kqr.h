@@ -205,9 +205,10 @@ int kqr_adaptive_rank(const float* F0, int64_t n, int64_t r0, int64_t ldf, doubl
  * {1,2,4,8,16} -- with `reps` timed launches each, and keeps the fastest shape
  * for (k_dtype, mode, size class of n) for the rest of the process.  With
  * mode KQR_APPLY_KV it times the multi-column K V launch (16 columns) instead,
- * over 16-byte loads per lane per step {4,8} x next-step prefetch {0,1} x
- * column segments {1,2,4,8}, and keeps the fastest for (k_dtype, size class
- * of n).  Writes a JSON report (every shape's average launch time and the
+ * over {64-row tiles streamed through LDS} and {direct loads in the MFMA
+ * layout: 16-byte loads per lane per step {4,8} x next-step prefetch {0,1}},
+ * each with column segments {1,2,4,8} (20 shapes), and keeps the fastest for
+ * (k_dtype, size class of n).  Writes a JSON report (every shape's average launch time and the
  * choice) into `report` (host, `cap` bytes, NUL-terminated; may be NULL).
  * Synchronises. */
 int kqr_autotune_apply(const void* K, int k_dtype, int64_t n, int64_t ldk, int mode, int reps, char* report,
@@ -220,8 +221,9 @@ int kqr_set_apply_shape(int k_dtype, int mode, int64_t n, int rows, int unroll, 
 
 /* kqr_set_kv_shape: installs a K V launch shape (e.g. one recorded by
  * kqr_autotune_apply with KQR_APPLY_KV) for (k_dtype, size class of n).
- * nld in {4,8} (16-byte loads per lane per step), prefetch in {0,1},
- * 1 <= segs <= 8; otherwise KQR_EINVAL. */
+ * nld = 0 (64-row tiles streamed through LDS; prefetch is ignored) or
+ * nld in {4,8} (direct loads, 16-byte loads per lane per step) with prefetch
+ * in {0,1}; 1 <= segs <= 8; otherwise KQR_EINVAL. */
 int kqr_set_kv_shape(int k_dtype, int64_t n, int nld, int prefetch, int segs);
 
 /* kqr_woodbury_apply: out = P^{-1} w for P = F F^T + c 1 1^T + diag(Ldiag), by

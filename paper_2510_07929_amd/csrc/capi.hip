@@ -118,9 +118,10 @@ static void autotune_kv(const KMat& km, int64_t n, int reps, char* report, int64
   double best_us = 1e300;
   bool first = true;
   try {
-    for (int nld : {4, 8})
+    for (int nld : {0, 4, 8})
       for (int pf : {0, 1})
         for (int sg : {1, 2, 4, 8}) {
+          if (nld == 0 && pf == 0) continue;  // the staged kernel always prefetches
           KvShape s;
           s.nld = nld;
           s.prefetch = pf;
@@ -462,7 +463,7 @@ int kqr_set_kv_shape(int k_dtype, int64_t n, int nld, int prefetch, int segs) {
     s.nld = nld;
     s.prefetch = prefetch;
     s.segs = segs;
-    KQR_REQUIRE(kv_shape_supported(s), "unsupported K V shape (nld in {4,8}, 1 <= segs <= 8)");
+    KQR_REQUIRE(kv_shape_supported(s), "unsupported K V shape (nld in {0,4,8}, 1 <= segs <= 8)");
     set_kv_shape(k_dtype, n, s);
   });
 }

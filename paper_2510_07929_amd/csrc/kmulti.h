@@ -5,12 +5,14 @@
 
 namespace kqr {
 
-// Launch shape of the K V kernel: 16-byte loads per lane per step (4 or 8),
-// next step's loads issued before the current MFMAs or not, column segments.
+// Launch shape of the K V kernel: nld = 0 streams 64-row tiles of K through
+// LDS (row-contiguous loads); nld = 4 or 8 loads each strip's rows directly
+// in the MFMA operand layout (16-byte loads per lane per step), with or
+// without the next step's loads issued ahead; column segments.
 constexpr int kKvMaxSegs = 8;
 constexpr int kKvBuckets = 8;
 struct KvShape {
-  int nld = 8;
+  int nld = 0;
   int prefetch = 1;
   int segs = 4;
 };

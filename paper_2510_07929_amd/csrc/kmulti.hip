@@ -151,6 +151,119 @@ __global__ __launch_bounds__(256) void kv_mfma_kernel(const void* __restrict__ K
   }
 }
 
+// Row-streamed K V: the block owns 64 rows; per stage it reads a 64-row tile
+// of K (FP32: 128 columns, BF16: 256 columns; 32 KB) with 16-byte
+// non-temporal loads, 512 contiguous bytes per row and load instruction (the
+// access pattern of the single-vector K-apply), writes it to LDS, and each
+// wave forms its 16-row strip on the matrix cores from LDS.  The next stage's
+// tile is loaded into registers while the current one is multiplied.  Lane
+// group g of a strip takes the columns [g C/4, (g+1) C/4) of the stage, so
+// every lane reads contiguous 16-byte pieces of K and V from LDS.
+template <bool BF16>
+__global__ __launch_bounds__(256) void kv_staged_kernel(const void* __restrict__ K, int64_t ldk, int64_t n,
+                                                        int64_t ncols, const float* __restrict__ V,
+                                                        int64_t seg_cols, double* __restrict__ out) {
+  constexpr int COLS = BF16 ? 256 : 128;   // columns per stage
+  constexpr int PER = BF16 ? 8 : 4;        // entries per 16 bytes
+  constexpr int ESZ = BF16 ? 2 : 4;
+  constexpr int KPAD = COLS + (BF16 ? 8 : 4);  // LDS row length in entries (row start bank = 4 i mod 64)
+  constexpr int QCOL = COLS / 4;               // columns per lane group
+  __shared__ __attribute__((aligned(16))) unsigned char ks[64 * KPAD * ESZ];
+  __shared__ __attribute__((aligned(16))) float vs[BF16 ? 1 : 16][BF16 ? 4 : COLS + 4];
+  __shared__ __attribute__((aligned(16))) uint16_t vh[BF16 ? 16 : 1][BF16 ? COLS + 8 : 8];
+  __shared__ __attribute__((aligned(16))) uint16_t vl[BF16 ? 16 : 1][BF16 ? COLS + 8 : 8];
+  const int t = threadIdx.x;
+  const int lane = t & 63, wave = t >> 6;
+  const int li = lane & 15, lg = lane >> 4;
+  const int64_t row_base = int64_t(blockIdx.x) * 64;
+  const int64_t c0 = int64_t(blockIdx.y) * seg_cols;
+  const int64_t c1 = min(ncols, c0 + seg_cols);
+  const char* Kb = static_cast<const char*>(K);
+  const int tr = t >> 5, tc = t & 31;  // loader: row offset in a group of 8 rows, 16-byte chunk in the row
+  auto load_stage = [&](int64_t cb, u32x4 (&r)[8]) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int64_t row = min(row_base + q * 8 + tr, n - 1);
+      const int64_t cc = cb + tc * PER;
+      const char* src = Kb + (row * ldk + cc) * ESZ;
+      if (cc + PER <= c1) {
+        r[q] = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(src));
+      } else {
+        uint32_t w[4];
+        if (BF16) {
+          const uint16_t* kr = reinterpret_cast<const uint16_t*>(Kb) + row * ldk;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const uint32_t lo = (cc + 2 * e < c1) ? kr[cc + 2 * e] : 0u;
+            const uint32_t hi = (cc + 2 * e + 1 < c1) ? kr[cc + 2 * e + 1] : 0u;
+            w[e] = lo | (hi << 16);
+          }
+        } else {
+          const float* kr = reinterpret_cast<const float*>(Kb) + row * ldk;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) w[e] = (cc + e < c1) ? __float_as_uint(kr[cc + e]) : 0u;
+        }
+        r[q] = u32x4{w[0], w[1], w[2], w[3]};
+      }
+    }
+  };
+  double acc64[4] = {0.0, 0.0, 0.0, 0.0};
+  u32x4 pre[8];
+  if (c0 < c1) load_stage(c0, pre);
+  const int srow = 16 * wave + li;  // this lane's row in the tile (MFMA A operand)
+  for (int64_t cb = c0; cb < c1; cb += COLS) {
+    const int cnt = int(min<int64_t>(COLS, c1 - cb));
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+      *reinterpret_cast<u32x4*>(&ks[((q * 8 + tr) * KPAD + tc * PER) * ESZ]) = pre[q];
+    for (int e = t; e < COLS * 16; e += 256) {
+      const int kk = e >> 4, j = e & 15;
+      const float val = kk < cnt ? V[(cb + kk) * 16 + j] : 0.f;
+      if (BF16) {
+        const uint16_t h = f2bf(val);
+        vh[j][kk] = h;
+        vl[j][kk] = f2bf(val - __uint_as_float(uint32_t(h) << 16));
+      } else {
+        vs[j][kk] = val;
+      }
+    }
+    __syncthreads();
+    if (cb + COLS < c1) load_stage(cb + COLS, pre);
+    f32x4 accA = {0.f, 0.f, 0.f, 0.f}, accB = {0.f, 0.f, 0.f, 0.f};
+    if (BF16) {
+      const uint16_t* arow = reinterpret_cast<const uint16_t*>(ks) + srow * KPAD + lg * QCOL;
+#pragma unroll
+      for (int kk = 0; kk < QCOL / 8; ++kk) {
+        const bf16x8 a = *reinterpret_cast<const bf16x8*>(arow + 8 * kk);
+        const bf16x8 bh = *reinterpret_cast<const bf16x8*>(&vh[li][lg * QCOL + 8 * kk]);
+        const bf16x8 bl = *reinterpret_cast<const bf16x8*>(&vl[li][lg * QCOL + 8 * kk]);
+        accA = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bh, accA, 0, 0, 0);
+        accB = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bl, accB, 0, 0, 0);
+      }
+    } else {
+      const float* arow = reinterpret_cast<const float*>(ks) + srow * KPAD + lg * QCOL;
+#pragma unroll
+      for (int kk = 0; kk < QCOL / 4; ++kk) {
+        const f32x4 a = *reinterpret_cast<const f32x4*>(arow + 4 * kk);
+        const f32x4 b = *reinterpret_cast<const f32x4*>(&vs[li][lg * QCOL + 4 * kk]);
+        accA = __builtin_amdgcn_mfma_f32_16x16x4f32(a[0], b[0], accA, 0, 0, 0);
+        accB = __builtin_amdgcn_mfma_f32_16x16x4f32(a[1], b[1], accB, 0, 0, 0);
+        accA = __builtin_amdgcn_mfma_f32_16x16x4f32(a[2], b[2], accA, 0, 0, 0);
+        accB = __builtin_amdgcn_mfma_f32_16x16x4f32(a[3], b[3], accB, 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc64[r] += double(accA[r]) + double(accB[r]);
+  }
+  const int64_t row0 = row_base + 16 * wave;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int64_t row = row0 + 4 * lg + r;
+    if (row < n) out[(int64_t(blockIdx.y) * n + row) * 16 + li] = acc64[r];
+  }
+}
+
 __global__ void kv_reduce_kernel(const double* __restrict__ part, int nseg, int64_t n, int m, double* __restrict__ U,
                                  int64_t ldu) {
   const int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
@@ -175,7 +288,9 @@ int kv_bucket(int64_t n) {
 template <bool BF16>
 void kv_launch(const KvShape& s, dim3 grid, const KMat& km, int64_t n, const float* V16, int64_t seg_cols,
                double* part, hipStream_t st) {
-  if (s.nld == 4 && s.prefetch)
+  if (s.nld == 0)
+    kv_staged_kernel<BF16><<<grid, 256, 0, st>>>(km.K, km.ld, n, n, V16, seg_cols, part);
+  else if (s.nld == 4 && s.prefetch)
     kv_mfma_kernel<BF16, 4, true><<<grid, 256, 0, st>>>(km.K, km.ld, n, n, V16, seg_cols, part);
   else if (s.nld == 4)
     kv_mfma_kernel<BF16, 4, false><<<grid, 256, 0, st>>>(km.K, km.ld, n, n, V16, seg_cols, part);
@@ -201,7 +316,7 @@ void set_kv_shape(int dtype, int64_t n, KvShape s) {
 }
 
 bool kv_shape_supported(const KvShape& s) {
-  return (s.nld == 4 || s.nld == 8) && s.segs >= 1 && s.segs <= kKvMaxSegs;
+  return (s.nld == 0 || s.nld == 4 || s.nld == 8) && s.segs >= 1 && s.segs <= kKvMaxSegs;
 }
 
 void kapply_kv(const KMat& km, int64_t n, const float* V16, int m, double* U, int64_t ldu, double* part,

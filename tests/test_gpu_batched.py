@@ -80,16 +80,18 @@ def test_kv_every_launch_shape_and_autotuner(dev, kd):
     ref = Kref @ V
     say("K V shapes", kd)
     outs = []
-    for nld in (4, 8):
+    for nld in (0, 4, 8):
         for pf in (0, 1):
             for segs in (1, 2, 4, 8):
+                if nld == 0 and pf == 0:
+                    continue
                 kqr.kqr_set_kv_shape(kd, n, nld, pf, segs)
                 U = kqr.kqr_kernel_apply(Vt, K=K).cpu().numpy()
                 err = np.abs(U - ref)
                 assert np.all(err <= bound + 1e-12), (nld, pf, segs, float((err / (bound + 1e-12)).max()))
                 outs.append(U)
     rep = kqr.kqr_autotune_apply(K, kqr.KQR_APPLY_KV, reps=2)
-    assert rep["n"] == n and len(rep["shapes"]) == 16
+    assert rep["n"] == n and len(rep["shapes"]) == 20
     assert rep["best"]["us"] == min(s["us"] for s in rep["shapes"])
     U = kqr.kqr_kernel_apply(Vt, K=K).cpu().numpy()
     assert np.all(np.abs(U - ref) <= bound + 1e-12)
