@@ -133,10 +133,11 @@ def admm(op, y, tau, lam, F, opts: OracleOptions, direct: bool, history=None):
     c = lam * sigma
     sysM = _System(op, c, np.full(n, c), F, direct)
     alpha, v, z, beta = np.zeros(n), np.zeros(n), np.zeros(n), 0.0
+    Ka = np.zeros(n)
     b0 = None
     res = None
     pcg_total = 0
-    k = 0
+    k = -1
     for k in range(opts.admm_max_iter):
         b = lam * (y - beta - z + sigma * v)
         if b0 is None:

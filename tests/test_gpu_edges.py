@@ -1,0 +1,95 @@
+"""Edge cases of the fit on the GPU against the FP64 oracle: the smallest n,
+one feature and the largest p, extreme quantile levels, a penalty so large
+that no coefficient is interior (beta then is not unique: only the objective
+and alpha are compared), Phase I skipped, and the on-the-fly operator with
+p beyond the matrix-core path."""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import kernel as okernel
+from oracle import problem as oproblem
+from oracle import solver as osolver
+from paper_2510_07929_amd import inputs, kqr
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[gpu-test]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    kqr.lib()
+    return torch.device("cuda:0")
+
+
+def _fit_and_compare(dev, X, y, tau, lam, kind, gamma, **kw):
+    Xt = torch.from_numpy(X).to(dev)
+    yt = torch.from_numpy(y).to(dev)
+    alpha, beta, info, st = kqr.kqr_fit(Xt, yt, tau, lam, kind, gamma, **kw)
+    assert st == kqr.KQR_OK
+    a = alpha.cpu().numpy()
+    ref = osolver.fit(X, y, tau, lam, kind, gamma, osolver.OracleOptions(tol=1e-10))
+    K = okernel.kernel_matrix(X, kind, gamma)
+    Ka = K @ a
+    obj = oproblem.primal_objective(y - beta - Ka / lam, a, Ka, lam, tau)
+    opt = ref.kkt["obj_p"]
+    rel = abs(obj - opt) / (1 + abs(opt))
+    say(f"  rel_obj={rel:.2e} kkt={info['eta_kkt']:.2e} |E|={info['n_interior']}")
+    assert rel <= 1e-6
+    return a, beta, ref
+
+
+def test_two_points(dev):
+    X = np.array([[0.0], [1.0]], dtype=np.float32)
+    y = np.array([0.0, 1.0])
+    say("n = 2")
+    _fit_and_compare(dev, X, y, 0.3, 0.5, "rbf", 1.0)
+
+
+@pytest.mark.parametrize("p", [1, 64])
+def test_feature_count_limits(dev, p):
+    X, y = inputs.smooth(700, p, (600, p))
+    say("p =", p)
+    _fit_and_compare(dev, X, y, 0.5, 0.7, "rbf", 1.0 / p)
+
+
+@pytest.mark.parametrize("tau", [0.01, 0.99])
+def test_extreme_quantile_levels(dev, tau):
+    X, y = inputs.smooth(800, 5, (601, int(tau * 100)))
+    say("tau =", tau)
+    _fit_and_compare(dev, X, y, tau, 0.8, "rbf", 0.2)
+
+
+def test_no_interior_coefficient(dev):
+    # huge lambda: K alpha / lambda vanishes and every alpha sits on a bound
+    # (tau n integral), so beta is any sample tau-quantile of y
+    n = 400
+    X, y = inputs.smooth(n, 3, (602, 0))
+    tau = 0.25
+    say("no interior coefficient")
+    a, beta, ref = _fit_and_compare(dev, X, y, tau, 1e9, "rbf", 0.3)
+    assert np.all((np.abs(a - tau) < 1e-6) | (np.abs(a - (tau - 1)) < 1e-6))
+    lo, hi = np.sort(y)[int(tau * n) - 1], np.sort(y)[int(tau * n)]
+    assert lo - 1e-6 <= beta <= hi + 1e-6
+
+
+def test_phase_one_skipped(dev):
+    prob = inputs.workload("c0", n=900)
+    say("Phase I skipped")
+    _fit_and_compare(dev, prob.X, prob.y, prob.tau, prob.lam, prob.kernel, prob.gamma, admm_max_iter=0)
+
+
+def test_on_the_fly_rbf_beyond_matrix_core_path(dev):
+    # p = 40 > 32: the on-the-fly RBF apply falls back to the VALU kernel
+    X, y = inputs.smooth(1100, 40, (603, 0))
+    say("on the fly, p = 40")
+    _fit_and_compare(dev, X, y, 0.6, 1.1, "rbf", 1.0 / 40, kmode=kqr.KQR_KMODE_ON_THE_FLY)
