@@ -196,30 +196,44 @@ __global__ __launch_bounds__(64) void chol_diag_kernel(double* __restrict__ C, i
   }
   __syncthreads();
   bool bad = false;
-  for (int j = 0; j < kNb; ++j) {
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-    int k = 0;
-    for (; k + 4 <= j; k += 4) {
-      s0 = fma(A[l][k], A[j][k], s0);
-      s1 = fma(A[l][k + 1], A[j][k + 1], s1);
-      s2 = fma(A[l][k + 2], A[j][k + 2], s2);
-      s3 = fma(A[l][k + 3], A[j][k + 3], s3);
+  // panels of 8 columns: a left-looking update of the panel by all earlier
+  // columns (eight independent dot products per lane), then the panel itself
+  // column by column
+  constexpr int PW = 8;
+  for (int j0 = 0; j0 < kNb; j0 += PW) {
+    double v[PW];
+#pragma unroll
+    for (int c = 0; c < PW; ++c) v[c] = 0.0;
+    for (int k = 0; k < j0; ++k) {
+      const double a = A[l][k];
+#pragma unroll
+      for (int c = 0; c < PW; ++c) v[c] = fma(a, A[j0 + c][k], v[c]);
     }
-    for (; k < j; ++k) s0 = fma(A[l][k], A[j][k], s0);
-    const double v = A[l][j] - ((s0 + s1) + (s2 + s3));
-    if (l == j) {
-      double piv = v;
-      if (!(piv > 0.0) || !isfinite(piv)) {
-        bad = true;
-        piv = 1e-300;
+#pragma unroll
+    for (int c = 0; c < PW; ++c) v[c] = A[l][j0 + c] - v[c];
+#pragma unroll
+    for (int c = 0; c < PW; ++c) {
+      const int j = j0 + c;
+      if (l == j) {
+        double piv = v[c];
+        if (!(piv > 0.0) || !isfinite(piv)) {
+          bad = true;
+          piv = 1e-300;
+        }
+        const double d = sqrt(piv);
+        A[j][j] = d;
+        rdiag = 1.0 / d;
       }
-      const double d = sqrt(piv);
-      A[j][j] = d;
-      rdiag = 1.0 / d;
+      __syncthreads();
+      if (l > j) {
+        v[c] *= rdiag;
+        A[l][j] = v[c];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int c2 = c + 1; c2 < PW; ++c2)
+        if (l > j) v[c2] = fma(-v[c], A[j0 + c2][j], v[c2]);
     }
-    __syncthreads();
-    if (l > j) A[l][j] = v * rdiag;
-    __syncthreads();
   }
   if (bad && nb > 0) flag[0] = 1;
   for (int e = l; e < kNb * kNb; e += 64) {
