@@ -518,17 +518,27 @@ __global__ __launch_bounds__(256) void kapply_otf_mfma_kernel(
     for (int s = 0; s < 2; ++s)
 #pragma unroll
       for (int rr = 0; rr < 4; ++rr) a32[s][rr] = 0.f;
-    for (int t16 = 0; t16 < cnt; t16 += 16) {
+    // Gram blocks of the next 16-column tile are issued to the matrix cores
+    // before the current tile's exponentials, so one wave keeps both busy.
+    auto gram = [&](int t16, f32x4_t& g0, f32x4_t& g1) {
       const int jj = t16 + li;
       float b[NKB];
 #pragma unroll
       for (int kb = 0; kb < NKB; ++kb) b[kb] = xs[jj][4 * kb + lg];
-      f32x4_t g0 = {0.f, 0.f, 0.f, 0.f}, g1 = {0.f, 0.f, 0.f, 0.f};
+      g0 = f32x4_t{0.f, 0.f, 0.f, 0.f};
+      g1 = f32x4_t{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int kb = 0; kb < NKB; ++kb) {
         g0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a[0][kb], b[kb], g0, 0, 0, 0);
         g1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a[1][kb], b[kb], g1, 0, 0, 0);
       }
+    };
+    f32x4_t g0, g1, n0, n1;
+    gram(0, g0, g1);
+    for (int t16 = 0; t16 < cnt; t16 += 16) {
+      const int jj = t16 + li;
+      const bool more = t16 + 16 < cnt;
+      if (more) gram(t16 + 16, n0, n1);
       const float qj = qs[jj];
 #pragma unroll
       for (int rr = 0; rr < 4; ++rr) {
@@ -542,6 +552,10 @@ __global__ __launch_bounds__(256) void kapply_otf_mfma_kernel(
           a32[0][rr] = fmaf(e0, vs[jj], a32[0][rr]);
           a32[1][rr] = fmaf(e1, vs[jj], a32[1][rr]);
         }
+      }
+      if (more) {
+        g0 = n0;
+        g1 = n1;
       }
     }
     if (!EX) {

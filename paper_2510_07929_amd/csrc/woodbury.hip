@@ -65,6 +65,7 @@ __global__ __launch_bounds__(256) void syrk_kernel(const float* __restrict__ F, 
   const int64_t k0 = int64_t(s) * chunk;
   const int64_t k1 = min(nrows, k0 + chunk);
   for (int64_t kb = k0; kb < k1; kb += kSubRows) {
+    #pragma unroll
     for (int e = threadIdx.x; e < kSubRows * kT; e += 256) {
       const int ii = e / kT, k = e % kT;
       const int64_t kk = kb + ii;
@@ -179,17 +180,20 @@ __global__ __launch_bounds__(64) void flag_scatter_kernel(const uint8_t* __restr
 }
 
 // ---------------------------------------------------------------- blocked Cholesky (lower)
-// Diagonal block (nb <= 64), left-looking, one wave: the block sits in LDS
-// and lane l owns row l.  Column j: every lane l >= j forms
-// A[l][j] - sum_{k<j} L[l][k] L[j][k] (its own row against the broadcast row
-// j, four independent partial sums), lane j takes the square root, and the
-// lanes below scale by the broadcast reciprocal.  The loops are not unrolled
-// over j, so the kernel stays small in the instruction cache.
+// Diagonal block (nb <= 64), one wave: the block sits in LDS and lane l owns
+// row l.  Columns go in panels of eight: every lane first forms
+// A[l][j] - sum_{k<j0} L[l][k] L[j][k] for the panel's eight columns j (its
+// own row against eight broadcast rows, eight independent sums), then the
+// panel is finished column by column: lane j takes the square root, the lanes
+// below scale by the broadcast reciprocal and update the panel's later
+// columns.  The loop over panels is not unrolled, so the kernel stays small
+// in the instruction cache.
 __global__ __launch_bounds__(64) void chol_diag_kernel(double* __restrict__ C, int64_t ldc, int kb, int nb,
                                                        int* __restrict__ flag) {
   __shared__ double A[kNb][kNb + 1];
   __shared__ double rdiag;
   const int l = threadIdx.x;
+  #pragma unroll 16
   for (int e = l; e < kNb * kNb; e += 64) {
     const int i = e / kNb, k = e % kNb;
     A[i][k] = (i < nb && k <= i) ? C[int64_t(kb + i) * ldc + kb + k] : (i == k ? 1.0 : 0.0);
@@ -236,6 +240,7 @@ __global__ __launch_bounds__(64) void chol_diag_kernel(double* __restrict__ C, i
     }
   }
   if (bad && nb > 0) flag[0] = 1;
+  #pragma unroll 16
   for (int e = l; e < kNb * kNb; e += 64) {
     const int i = e / kNb, k = e % kNb;
     if (i < nb && k <= i) C[int64_t(kb + i) * ldc + kb + k] = A[i][k];
@@ -249,6 +254,7 @@ __global__ __launch_bounds__(256) void chol_panel_kernel(double* __restrict__ C,
                                                          int R1) {
   __shared__ double Lk[kNb][kNb + 1];
   __shared__ double rinv[kNb];
+  #pragma unroll 16
   for (int e = threadIdx.x; e < kNb * kNb; e += 256) {
     const int i = e / kNb, k = e % kNb;
     const double v = (i < nb && k <= i) ? C[int64_t(kb + i) * ldc + kb + k] : (i == k ? 1.0 : 0.0);
@@ -287,6 +293,7 @@ __global__ __launch_bounds__(256) void chol_update_kernel(double* __restrict__ C
     for (int q = 0; q < 4; ++q) acc[p][q] = 0.0;
   for (int h = 0; h < nb; h += 32) {
     __syncthreads();
+    #pragma unroll
     for (int e = threadIdx.x; e < kT * 32; e += 256) {
       const int a = e / 32, k = e % 32;
       const bool kk = h + k < nb;
@@ -330,6 +337,7 @@ __global__ __launch_bounds__(64) void trinv_diag_kernel(const double* __restrict
   const int kb = blockIdx.x * kNb;
   const int nb = min(kNb, R1 - kb);
   const int j = threadIdx.x;
+  #pragma unroll 16
   for (int e = j; e < kNb * kNb; e += 64) {
     const int i = e / kNb, k = e % kNb;
     Lk[i][k] = (i < nb && k <= i) ? C[int64_t(kb + i) * ldc + kb + k] : (i == k ? 1.0 : 0.0);
@@ -348,6 +356,7 @@ __global__ __launch_bounds__(64) void trinv_diag_kernel(const double* __restrict
     X[i][j] = (i >= j) ? ((s0 + s1) + (s2 + s3)) / Lk[i][i] : 0.0;
   }
   __syncthreads();
+  #pragma unroll 16
   for (int e = j; e < kNb * kNb; e += 64) {
     const int i = e / kNb, k = e % kNb;
     if (i < nb && k < nb) W[int64_t(kb + i) * ldc + kb + k] = X[i][k];
@@ -385,6 +394,7 @@ __global__ __launch_bounds__(256) void trinv_level_kernel(const double* __restri
     for (int q = 0; q < 4; ++q) acc[p][q] = 0.0;
   for (int kb = 0; kb < K; kb += 32) {
     __syncthreads();
+    #pragma unroll
     for (int e = threadIdx.x; e < kT * 32; e += 256) {
       const int a = e / 32, k = e % 32;
       const int row = r0 + a, kk = kb + k;
@@ -394,6 +404,7 @@ __global__ __launch_bounds__(256) void trinv_level_kernel(const double* __restri
       }
       As[a][k] = v;
     }
+    #pragma unroll
     for (int e = threadIdx.x; e < 32 * kT; e += 256) {
       const int k = e / kT, b = e % kT;
       const int kk = kb + k, col = c0 + b;

@@ -26,9 +26,19 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SOURCE = os.path.join(HERE, "csrc", "kmat.hip")
 
 
+SECTION_BEGIN = "// ================================================================= materialised K-apply"
+SECTION_END = "// ================================================================= on-the-fly K-apply"
+
+
 def source_digest(path: str = KERNEL_SOURCE) -> str:
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """Digest of the materialised K-apply's source (its section of kmat.hip:
+    kernels, shape table and launcher)."""
+    with open(path) as f:
+        text = f.read()
+    a, b = text.find(SECTION_BEGIN), text.find(SECTION_END)
+    if a >= 0 and b > a:
+        text = text[a:b]
+    return hashlib.sha256(text.encode()).hexdigest()[:16]
 
 
 def copy_once(gib: float, reps: int) -> None:
