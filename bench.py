@@ -344,6 +344,74 @@ def bench_multi_tau(args, prob):
     return out
 
 
+def bench_path(args, prob):
+    """A lambda sequence on one K (values coalesced into K V launches) against
+    the same values as separate fits."""
+    import numpy as np
+    import torch
+
+    from paper_2510_07929_amd import inputs, kqr
+
+    dev = torch.device("cuda:0")
+    X = torch.from_numpy(prob.X).to(dev)
+    y = torch.from_numpy(prob.y).to(dev)
+    lams = prob.extras["lams"]
+    tol = prob.extras["tol"]
+    uni = inputs.pivot_uniforms(1024, (sum(map(ord, prob.name)), 0))
+    kd = args.kdtype or "fp32"
+    esz = 4 if kd == "fp32" else 2
+    opts = dict(rank=0, k_dtype=kqr.KDTYPES[kd], kmode=kqr.KQR_KMODE_MATERIALIZE, profile=1, tol=tol)
+
+    def path():
+        _, betas, infos, sts = kqr.kqr_fit_path(X, y, prob.tau, lams, prob.kernel, prob.gamma, uniforms=uni, **opts)
+        return infos, sts
+
+    tuned = None
+    if not args.no_tune:
+        K = kqr.kqr_kernel_build(X, prob.kernel, prob.gamma, kd)
+        tuned = kqr.kqr_autotune_apply(K, kqr.KQR_APPLY_KV, reps=5)["best"]
+        kqr.kqr_autotune_apply(K, kqr.KQR_APPLY_FAST, reps=5)
+        kqr.kqr_autotune_apply(K, kqr.KQR_APPLY_EXACT, reps=5)
+        del K
+        torch.cuda.empty_cache()
+    outs, elapsed = timed_fits(args, path)
+    t_sep0 = time.perf_counter()
+    sep = [kqr.kqr_fit(X, y, prob.tau, lam, prob.kernel, prob.gamma, uniforms=uni, **opts) for lam in lams]
+    torch.cuda.synchronize()
+    t_sep = time.perf_counter() - t_sep0
+    infos, sts = outs[-1]
+    nl = infos[0]["kapply_fast_calls"]
+    tl = infos[0]["t_kapply_fast"]
+    avg = tl / max(nl, 1)
+    n = prob.n
+    kbytes = float(n) * n * esz
+    achieved = kbytes / avg / 1e9 if avg > 0 else 0.0
+    out = base_line(args, prob, "f32" if kd == "fp32" else "bf16",
+                    {"k_storage": kd, "lambdas": f"{len(lams)} values log-spaced over [{min(lams):g}, {max(lams):g}]",
+                     "lambda": None, "tol": tol})
+    out.update(value=round(nl * kbytes * args.steps / elapsed / 1e9, 2), ms_per_step=round(elapsed / args.steps * 1e3, 3))
+    out["roofline"] = {
+        "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+        "kernel": "kv_staged_kernel (K V, V n x 16, %s K)" % kd, "avg_launch_us": round(avg * 1e6, 2),
+        "launches": int(nl), "bytes_per_launch": kbytes, "launch_shape": tuned or "default",
+    }
+    out["fit"] = {"status": sts, "eta_kkt_max": max(i["eta_kkt"] for i in infos),
+                  "eta_gap_max": max(i["eta_gap"] for i in infos),
+                  "rank": infos[0]["rank_used"],
+                  "kapply_calls_total": int(np.sum([i["kapply_calls"] for i in infos])),
+                  "alm_iters": [i["alm_iters"] for i in infos], "n_interior": [i["n_interior"] for i in infos]}
+    out["compare_separate"] = {
+        "ms_total": round(t_sep * 1e3, 3), "status": [s for _, _, _, s in sep],
+        "eta_kkt_max": max(i["eta_kkt"] for _, _, i, _ in sep),
+        "kapply_calls": int(np.sum([i["kapply_calls"] for _, _, i, _ in sep])),
+        "joint_speedup": round(t_sep / (elapsed / args.steps), 3),
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(prob, args.cpu_seconds)
+    return out
+
+
 def bench_batch(args):
     """64 uneven problems in one batched fit against the same fits one at a time."""
     import numpy as np
@@ -500,6 +568,8 @@ def main():
             out = bench_multi_tau(args, prob)
         elif w == "c4":
             out = bench_grad(args, prob)
+        elif w == "path":
+            out = bench_path(args, prob)
         else:
             out = bench_single(args, prob)
     print(json.dumps(out), flush=True)

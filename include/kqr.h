@@ -288,6 +288,23 @@ int kqr_fit_multi_tau(const float* X, const double* y, int64_t n, int64_t p, con
                       double lambda, int kernel, double gamma, const kqr_options* opt, double* alpha,
                       double* beta, kqr_info* info, int* status, void* stream);
 
+/* kqr_fit_path: kqr_fit for nlam values of lambda, lambdas[0..nlam-1], on the
+ * same (X, y, tau, kernel, gamma): the regularisation paths of Section 4.1.
+ * K and the RPCholesky factor do not depend on lambda and are built once.
+ * Every value is solved from the cold start of Algorithm 1 (each result is the
+ * unique optimum for its lambda, independent of the order of lambdas); up to
+ * 16 values run at once, one host thread and stream each, with their fast
+ * K-applies coalesced into K V launches as in kqr_fit_multi_tau, and a thread
+ * that finishes one value takes the next.
+ *  alpha   device, nlam x n FP64 (row t = alpha of lambdas[t]);  beta host nlam;
+ *  info    host nlam (may be NULL); status host nlam (KQR_OK or
+ *          KQR_NOT_CONVERGED per value).
+ *  1 <= nlam <= 4096, every lambda > 0.  Returns KQR_OK when every value ran
+ *  (see status[]), else the first error. */
+int kqr_fit_path(const float* X, const double* y, int64_t n, int64_t p, double tau, const double* lambdas,
+                 int nlam, int kernel, double gamma, const kqr_options* opt, double* alpha, double* beta,
+                 kqr_info* info, int* status, void* stream);
+
 /* kqr_fit_batch: nprob independent fits (sizes n[i], common p and kernel
  * type, per-problem tau, lambda, gamma).  Each problem gets its own K and
  * preconditioner; the fast K-applies of all problems still running go out as

@@ -122,20 +122,32 @@ class _System:
 
 
 # ---------------------------------------------------------------- Phase I
-def admm(op, y, tau, lam, F, opts: OracleOptions, direct: bool, history=None):
+def admm(op, y, tau, lam, F, opts: OracleOptions, direct: bool, history=None, start=None):
     """Algorithm 1: inexact ADMM on the consensus dual (1.4).
 
     M = K + lambda sigma (I + 1 1^T) is fixed, so it is factored (or its
     preconditioner built, with L = lambda sigma I) once.
+
+    ``start`` (alpha, beta, z, Kalpha) replaces the zero initial point; v is
+    then the projection of alpha onto the box.  A start that already meets the
+    Phase I target is returned as it is (no iteration).
     """
     n = y.shape[0]
     sigma, step = opts.admm_sigma, opts.admm_step
     c = lam * sigma
-    sysM = _System(op, c, np.full(n, c), F, direct)
-    alpha, v, z, beta = np.zeros(n), np.zeros(n), np.zeros(n), 0.0
-    Ka = np.zeros(n)
-    b0 = None
     res = None
+    if start is None:
+        alpha, v, z, beta = np.zeros(n), np.zeros(n), np.zeros(n), 0.0
+        Ka = np.zeros(n)
+    else:
+        alpha, beta, z = start["alpha"].copy(), float(start["beta"]), start["z"].copy()
+        Ka = start["Kalpha"].copy()
+        v = pb.proj_box(alpha, tau)
+        res = pb.kkt(alpha, v, beta, z, Ka, y, lam, tau)
+        if res["err"] <= opts.admm_tol:
+            return dict(alpha=alpha, v=v, beta=beta, z=z, Kalpha=Ka, sigma=sigma, iters=0, pcg=0, kkt=res)
+    sysM = _System(op, c, np.full(n, c), F, direct)
+    b0 = None
     pcg_total = 0
     k = -1
     for k in range(opts.admm_max_iter):
@@ -341,8 +353,13 @@ def fit(X, y, tau, lam, kind, gamma, opts: OracleOptions | None = None,
     if direct and not isinstance(op, DenseKernel):
         raise ValueError("direct solves need a dense kernel")
     F, pinfo = (None, dict(rank=0)) if direct else build_preconditioner(op, opts, uniforms)
+    return _fit_on(op, F, pinfo, y, tau, float(lam), opts, direct, None, history)
+
+
+def _fit_on(op, F, pinfo, y, tau, lam, opts: OracleOptions, direct: bool, start, history: bool) -> FitResult:
     hist = [] if history else None
-    ph1 = admm(op, y, tau, lam, F, opts, direct, hist)
+    applies0 = op.applies
+    ph1 = admm(op, y, tau, lam, F, opts, direct, hist, start)
     ph2 = alm(op, y, tau, lam, F, ph1, opts, direct, hist)
     alpha, v, beta, z, Ka = ph2["alpha"], ph2["v"], ph2["beta"], ph2["z"], ph2["Kalpha"]
     polished = False
@@ -356,8 +373,41 @@ def fit(X, y, tau, lam, kind, gamma, opts: OracleOptions | None = None,
     info = dict(admm_iters=ph1["iters"], admm_pcg=ph1["pcg"], alm_iters=ph2["iters"],
                 newton=ph2["newton"], pcg=ph2["pcg"], ls=ph2["ls"], sigma=ph2["sigma"],
                 polished=polished, n_interior=int(np.sum((alpha > tau - 1) & (alpha < tau))),
-                kapply=op.applies, direct=direct, **pinfo)
+                kapply=op.applies - applies0, direct=direct, **pinfo)
     return FitResult(alpha, v, beta, z, Ka, res, info, hist or [])
+
+
+def path_start(prev: FitResult, y, lam: float) -> dict:
+    """Warm start for the next value of lambda on a regularisation path.
+
+    alpha and beta are kept (the box and the constraint on alpha do not depend
+    on lambda) and z is the residual y - beta 1 - K alpha / lambda at the new
+    lambda, so that the stationarity condition in alpha holds exactly at the
+    start; K alpha is the previous fit's (K does not change along the path).
+    """
+    z = y - prev.beta - prev.Kalpha / lam
+    return dict(alpha=prev.alpha, beta=prev.beta, z=z, Kalpha=prev.Kalpha)
+
+
+def fit_path(X, y, tau, lams, kind, gamma, opts: OracleOptions | None = None,
+             uniforms=None, op=None, warm: bool = True) -> list:
+    """KQR over a sequence of lambda values (the regularisation paths of
+    Section 4.1): K and the preconditioner factor F are formed once; each fit
+    after the first starts from the previous solution (``path_start``) and
+    runs Phase I from there (skipped when the start already meets its target),
+    then Phase II.  With ``warm`` off every value is a cold start."""
+    opts = opts or OracleOptions()
+    y = np.asarray(y, dtype=np.float64)
+    n = y.shape[0]
+    direct = n <= opts.direct_max
+    if op is None:
+        op = DenseKernel(X, kind, gamma) if (direct or n <= 20000) else ImplicitKernel(X, kind, gamma)
+    F, pinfo = (None, dict(rank=0)) if direct else build_preconditioner(op, opts, uniforms)
+    out = []
+    for lam in lams:
+        start = path_start(out[-1], y, float(lam)) if (warm and out) else None
+        out.append(_fit_on(op, F, pinfo, y, tau, float(lam), opts, direct, start, False))
+    return out
 
 
 def options_dict(o: OracleOptions) -> dict:

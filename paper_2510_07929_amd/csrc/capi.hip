@@ -106,7 +106,7 @@ static void check_kmat(const void* K, int k_dtype, int64_t ldk, int64_t n) {
 // installs the fastest for K's dtype and size bucket; JSON report.
 static void autotune_kv(const KMat& km, int64_t n, int reps, char* report, int64_t cap, hipStream_t st) {
   DevBuf V16(size_t(n) * 16 * sizeof(float)), U(size_t(n) * 16 * sizeof(double));
-  DevBuf part(size_t(kKvMaxSegs) * size_t(n) * 16 * sizeof(double)), ones(size_t(n) * 16 * sizeof(double));
+  DevBuf part(kv_scratch_doubles(n) * sizeof(double)), ones(size_t(n) * 16 * sizeof(double));
   fill(n * 16, 1.0 / double(n), ones.as<double>(), st);
   kv_gather_strided(ones.as<double>(), 16, 16, n, n, V16.as<float>(), st);
   hipEvent_t e0, e1;
@@ -279,7 +279,7 @@ int kqr_kernel_apply(const float* X, int64_t n, int64_t p, int kernel, double ga
       double* part = nullptr;
       KQR_CHECK_HIP(hipMallocAsync(reinterpret_cast<void**>(&V16), size_t(n) * 16 * sizeof(float), st));
       KQR_CHECK_HIP(
-          hipMallocAsync(reinterpret_cast<void**>(&part), size_t(kKvMaxSegs) * n * 16 * sizeof(double), st));
+          hipMallocAsync(reinterpret_cast<void**>(&part), kv_scratch_doubles(n) * sizeof(double), st));
       kv_gather_strided(V, ldv, int(m), n, n, V16, st);
       kapply_kv(km, n, V16, int(m), U, ldu, part, st);
       KQR_CHECK_HIP(hipFreeAsync(part, st));
@@ -590,6 +590,27 @@ int kqr_fit_multi_tau(const float* X, const double* y, int64_t n, int64_t p, con
     ensure_device();
     fit_multi_tau(X, y, n, int(p), KernelSpec{kernel, gamma}, taus, ntau, lambda, o, alpha, beta, info, status,
                   static_cast<hipStream_t>(stream));
+  });
+}
+
+int kqr_fit_path(const float* X, const double* y, int64_t n, int64_t p, double tau, const double* lambdas,
+                 int nlam, int kernel, double gamma, const kqr_options* opt, double* alpha, double* beta,
+                 kqr_info* info, int* status, void* stream) {
+  return guarded([&] {
+    KQR_REQUIRE(X && y && lambdas && alpha && beta && status, "pointers must be non-null");
+    KQR_REQUIRE(n >= 2 && p >= 1 && p <= 64, "need n >= 2 and 1 <= p <= 64");
+    KQR_REQUIRE(nlam >= 1 && nlam <= 4096, "need 1 <= nlam <= 4096");
+    KQR_REQUIRE(tau > 0.0 && tau < 1.0, "need 0 < tau < 1");
+    for (int t = 0; t < nlam; ++t)
+      KQR_REQUIRE(std::isfinite(lambdas[t]) && lambdas[t] > 0.0, "every lambda must be positive and finite");
+    check_kernel(kernel, gamma);
+    kqr_options o;
+    kqr_default_options(&o);
+    if (opt) o = *opt;
+    validate_options(o);
+    ensure_device();
+    fit_path(X, y, n, int(p), KernelSpec{kernel, gamma}, tau, lambdas, nlam, o, alpha, beta, info, status,
+             static_cast<hipStream_t>(stream));
   });
 }
 

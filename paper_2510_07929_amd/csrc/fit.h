@@ -48,6 +48,14 @@ void fit_multi_tau(const float* X, const double* y, int64_t n, int p, KernelSpec
                    double lam, const kqr_options& o, double* alpha, double* beta, kqr_info* info, int* status,
                    hipStream_t st);
 
+// lambda path: nlam values of lambda on one (X, y, tau, kernel); K and F are
+// built once, every value is a cold start, and up to kKvMaxCols values run at
+// once with their fast K-applies coalesced into K V launches (a worker that
+// finishes one value takes the next).
+void fit_path(const float* X, const double* y, int64_t n, int p, KernelSpec ks, double tau, const double* lams,
+              int nlam, const kqr_options& o, double* alpha, double* beta, kqr_info* info, int* status,
+              hipStream_t st);
+
 // independent problems: fast K-applies of all running problems go out in one
 // launch over (problem, row block) pairs.
 void fit_batch(int nprob, const float* const* X, const double* const* y, const int64_t* n, int p, KernelSpec ks,

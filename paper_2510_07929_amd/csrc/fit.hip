@@ -5,6 +5,7 @@
 #include "fit.h"
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
@@ -254,7 +255,7 @@ class KvBatcher : public RendezvousBatcher {
   KvBatcher(int slots, KMat km, int64_t n, bool profile)
       : RendezvousBatcher(slots, profile), km_(km), n_(n), npad_(std::max<int64_t>(km.ld, n)),
         V_(size_t(npad_) * 16 * sizeof(float)), U_(size_t(n) * 16 * sizeof(double)),
-        part_(size_t(kKvMaxSegs) * n * 16 * sizeof(double)) {}
+        part_(kv_scratch_doubles(n) * sizeof(double)) {}
 
  protected:
   void launch(const std::vector<int>& slots, hipStream_t st) override {
@@ -351,30 +352,35 @@ int status_of(const std::exception_ptr& e, std::string& msg) {
 }
 }  // namespace
 
-void fit_multi_tau(const float* X, const double* y, int64_t n, int p, KernelSpec ks, const double* taus, int ntau,
-                   double lam, const kqr_options& o, double* alpha, double* beta, kqr_info* info, int* status,
-                   hipStream_t st) {
+void fit_levels(const float* X, const double* y, int64_t n, int p, KernelSpec ks, const double* taus,
+                const double* lams, int nlev, const kqr_options& o, double* alpha, double* beta, kqr_info* info,
+                int* status, hipStream_t st) {
   Prepared pr = prepare_fit(X, n, p, ks, o, st);
-  const bool batched = pr.K.ptr != nullptr && ntau > 1;
+  const int nw = std::min(nlev, kKvMaxCols);
+  const bool batched = pr.K.ptr != nullptr && nw > 1;
   std::unique_ptr<KvBatcher> batcher;
-  if (batched) batcher.reset(new KvBatcher(ntau, pr.kmat(), n, o.profile != 0));
-  StreamSet streams(ntau);
-  std::vector<std::exception_ptr> errs(static_cast<size_t>(ntau));
-  std::vector<FitOutcome> outs(static_cast<size_t>(ntau));
+  if (batched) batcher.reset(new KvBatcher(nw, pr.kmat(), n, o.profile != 0));
+  StreamSet streams(nw);
+  std::vector<std::exception_ptr> errs(static_cast<size_t>(nlev));
+  std::vector<FitOutcome> outs(static_cast<size_t>(nlev));
+  std::atomic<int> next{0};
   std::vector<std::thread> th;
-  for (int t = 0; t < ntau; ++t) {
-    th.emplace_back([&, t] {
-      hipStream_t s = streams.s[size_t(t)];
-      try {
-        Operator op(X, n, p, ks, pr.kmat(), s);
-        pr.attach(op);
-        op.enable_profile(o.profile != 0);
-        if (batcher) op.attach_batcher(batcher.get(), t);
-        outs[size_t(t)] = run_fit(op, pr, y, n, taus[t], lam, o, alpha + int64_t(t) * n, s);
-      } catch (...) {
-        errs[size_t(t)] = std::current_exception();
+  for (int w = 0; w < nw; ++w) {
+    th.emplace_back([&, w] {
+      hipStream_t s = streams.s[size_t(w)];
+      // a worker stays in the rendezvous until the queue of levels is empty
+      for (int t = next.fetch_add(1); t < nlev; t = next.fetch_add(1)) {
+        try {
+          Operator op(X, n, p, ks, pr.kmat(), s);
+          pr.attach(op);
+          op.enable_profile(o.profile != 0);
+          if (batcher) op.attach_batcher(batcher.get(), w);
+          outs[size_t(t)] = run_fit(op, pr, y, n, taus[t], lams[t], o, alpha + int64_t(t) * n, s);
+        } catch (...) {
+          errs[size_t(t)] = std::current_exception();
+        }
       }
-      if (batcher) batcher->leave(t);
+      if (batcher) batcher->leave(w);
     });
   }
   for (auto& x : th) x.join();
@@ -382,7 +388,7 @@ void fit_multi_tau(const float* X, const double* y, int64_t n, int p, KernelSpec
   const int64_t nkv = batcher ? batcher->launches() : 0;
   std::string first_msg;
   int first_err = KQR_OK;
-  for (int t = 0; t < ntau; ++t) {
+  for (int t = 0; t < nlev; ++t) {
     int stt = KQR_OK;
     if (errs[size_t(t)]) {
       std::string msg;
@@ -391,7 +397,7 @@ void fit_multi_tau(const float* X, const double* y, int64_t n, int p, KernelSpec
     } else {
       stt = outs[size_t(t)].converged ? KQR_OK : KQR_NOT_CONVERGED;
       beta[t] = outs[size_t(t)].beta;
-      if (batcher) {  // fast applies were the shared K V launches
+      if (batcher) {  // fast applies were the shared K V launches (of every level)
         outs[size_t(t)].info.kapply_fast_calls = nkv;
         outs[size_t(t)].info.t_kapply_fast = tkv;
       }
@@ -401,6 +407,20 @@ void fit_multi_tau(const float* X, const double* y, int64_t n, int p, KernelSpec
   }
   KQR_CHECK_HIP(hipStreamSynchronize(st));
   if (first_err != KQR_OK) fail(first_err, "%s", first_msg.c_str());
+}
+
+void fit_multi_tau(const float* X, const double* y, int64_t n, int p, KernelSpec ks, const double* taus, int ntau,
+                   double lam, const kqr_options& o, double* alpha, double* beta, kqr_info* info, int* status,
+                   hipStream_t st) {
+  const std::vector<double> lams(static_cast<size_t>(ntau), lam);
+  fit_levels(X, y, n, p, ks, taus, lams.data(), ntau, o, alpha, beta, info, status, st);
+}
+
+void fit_path(const float* X, const double* y, int64_t n, int p, KernelSpec ks, double tau, const double* lams,
+              int nlam, const kqr_options& o, double* alpha, double* beta, kqr_info* info, int* status,
+              hipStream_t st) {
+  const std::vector<double> taus(static_cast<size_t>(nlam), tau);
+  fit_levels(X, y, n, p, ks, taus.data(), lams, nlam, o, alpha, beta, info, status, st);
 }
 
 void fit_batch(int nprob, const float* const* X, const double* const* y, const int64_t* n, int p, KernelSpec ks,

@@ -10,6 +10,7 @@ namespace kqr {
 // in the MFMA operand layout (16-byte loads per lane per step), with or
 // without the next step's loads issued ahead; column segments.
 constexpr int kKvMaxSegs = 8;
+constexpr int kKvMaxCols = 16;  // right-hand sides of one K V launch
 constexpr int kKvBuckets = 8;
 struct KvShape {
   int nld = 0;
@@ -20,9 +21,13 @@ KvShape default_kv_shape(int dtype, int64_t n);        // autotuned when set, el
 void set_kv_shape(int dtype, int64_t n, KvShape s);    // autotuner override (per dtype and size bucket)
 bool kv_shape_supported(const KvShape& s);
 
+// Doubles of scratch kapply_kv needs for n rows: the segment partials and,
+// past them, the BF16 hi + lo parts of V (n x 32 halves).
+inline size_t kv_scratch_doubles(int64_t n) { return (size_t(kKvMaxSegs) + 1) * size_t(n) * 16; }
+
 // U[:, j] = K V[:, j] for j < m <= 16.  V16: n_pad x 16 FP32 row-major (rows >= n
 // and columns >= m zero); U: n x m FP64 (ld ldu); part: scratch of
-// kKvMaxSegs * n * 16 doubles.
+// kv_scratch_doubles(n) doubles.
 void kapply_kv(const KMat& km, int64_t n, const float* V16, int m, double* U, int64_t ldu, double* part,
                hipStream_t st, const KvShape* shape = nullptr);
 struct SrcTable16 {

@@ -162,7 +162,8 @@ __global__ __launch_bounds__(256) void kv_mfma_kernel(const void* __restrict__ K
 template <bool BF16>
 __global__ __launch_bounds__(256) void kv_staged_kernel(const void* __restrict__ K, int64_t ldk, int64_t n,
                                                         int64_t ncols, const float* __restrict__ V,
-                                                        int64_t seg_cols, double* __restrict__ out) {
+                                                        const uint16_t* __restrict__ Vhl, int64_t seg_cols,
+                                                        double* __restrict__ out) {
   constexpr int COLS = BF16 ? 256 : 128;   // columns per stage
   constexpr int PER = BF16 ? 8 : 4;        // entries per 16 bytes
   constexpr int ESZ = BF16 ? 2 : 4;
@@ -219,13 +220,11 @@ __global__ __launch_bounds__(256) void kv_staged_kernel(const void* __restrict__
       *reinterpret_cast<u32x4*>(&ks[((q * 8 + tr) * KPAD + tc * PER) * ESZ]) = pre[q];
     for (int e = t; e < COLS * 16; e += 256) {
       const int kk = e >> 4, j = e & 15;
-      const float val = kk < cnt ? V[(cb + kk) * 16 + j] : 0.f;
-      if (BF16) {
-        const uint16_t h = f2bf(val);
-        vh[j][kk] = h;
-        vl[j][kk] = f2bf(val - __uint_as_float(uint32_t(h) << 16));
+      if (BF16) {  // hi and lo parts formed once per launch (kv_split_kernel)
+        vh[j][kk] = kk < cnt ? Vhl[(cb + kk) * 32 + j] : uint16_t(0);
+        vl[j][kk] = kk < cnt ? Vhl[(cb + kk) * 32 + 16 + j] : uint16_t(0);
       } else {
-        vs[j][kk] = val;
+        vs[j][kk] = kk < cnt ? V[(cb + kk) * 16 + j] : 0.f;
       }
     }
     __syncthreads();
@@ -264,6 +263,18 @@ __global__ __launch_bounds__(256) void kv_staged_kernel(const void* __restrict__
   }
 }
 
+// Vhl[i][j] = bf16(V[i][j]), Vhl[i][16 + j] = bf16(V[i][j] - that) (round to nearest even)
+__global__ void kv_split_kernel(const float* __restrict__ V, int64_t n, uint16_t* __restrict__ Vhl) {
+  const int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (t >= n * 16) return;
+  const int64_t i = t >> 4;
+  const int j = int(t & 15);
+  const float val = V[t];
+  const uint16_t h = f2bf(val);
+  Vhl[i * 32 + j] = h;
+  Vhl[i * 32 + 16 + j] = f2bf(val - __uint_as_float(uint32_t(h) << 16));
+}
+
 __global__ void kv_reduce_kernel(const double* __restrict__ part, int nseg, int64_t n, int m, double* __restrict__ U,
                                  int64_t ldu) {
   const int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
@@ -286,10 +297,10 @@ int kv_bucket(int64_t n) {
   return b;
 }
 template <bool BF16>
-void kv_launch(const KvShape& s, dim3 grid, const KMat& km, int64_t n, const float* V16, int64_t seg_cols,
-               double* part, hipStream_t st) {
+void kv_launch(const KvShape& s, dim3 grid, const KMat& km, int64_t n, const float* V16, const uint16_t* Vhl,
+               int64_t seg_cols, double* part, hipStream_t st) {
   if (s.nld == 0)
-    kv_staged_kernel<BF16><<<grid, 256, 0, st>>>(km.K, km.ld, n, n, V16, seg_cols, part);
+    kv_staged_kernel<BF16><<<grid, 256, 0, st>>>(km.K, km.ld, n, n, V16, Vhl, seg_cols, part);
   else if (s.nld == 4 && s.prefetch)
     kv_mfma_kernel<BF16, 4, true><<<grid, 256, 0, st>>>(km.K, km.ld, n, n, V16, seg_cols, part);
   else if (s.nld == 4)
@@ -329,8 +340,17 @@ void kapply_kv(const KMat& km, int64_t n, const float* V16, int m, double* U, in
   seg_cols = (seg_cols + kKC - 1) / kKC * kKC;
   segs = int((n + seg_cols - 1) / seg_cols);
   const dim3 grid((unsigned)((n + 63) / 64), (unsigned)segs);
-  if (km.dtype == KQR_BF16) kv_launch<true>(s, grid, km, n, V16, seg_cols, part, st);
-  else kv_launch<false>(s, grid, km, n, V16, seg_cols, part, st);
+  if (km.dtype == KQR_BF16) {
+    // BF16 hi + lo parts of V, n x 32 halves, in the scratch past the segment partials
+    uint16_t* Vhl = reinterpret_cast<uint16_t*>(part + size_t(kKvMaxSegs) * size_t(n) * 16);
+    if (s.nld == 0) {
+      kv_split_kernel<<<dim3((unsigned)((n * 16 + 255) / 256)), 256, 0, st>>>(V16, n, Vhl);
+      KQR_LAUNCH_CHECK();
+    }
+    kv_launch<true>(s, grid, km, n, V16, Vhl, seg_cols, part, st);
+  } else {
+    kv_launch<false>(s, grid, km, n, V16, nullptr, seg_cols, part, st);
+  }
   KQR_LAUNCH_CHECK();
   kv_reduce_kernel<<<dim3((unsigned)((n * 16 + 255) / 256)), 256, 0, st>>>(part, segs, n, m, U, ldu);
   KQR_LAUNCH_CHECK();

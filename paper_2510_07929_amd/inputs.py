@@ -31,6 +31,7 @@ __all__ = [
     "smooth",
     "additive",
     "paper2d",
+    "lambda_grid",
     "pivot_uniforms",
     "uneven_batch",
     "WORKLOADS",
@@ -115,7 +116,14 @@ WORKLOADS = {
     "c2lap": (300000, "additive, n=300000, p=30, Laplacian gamma=1/p, tau=0.75, lambda=1e-4 n, on the fly"),
     "c3a": (100000, "additive, n=100000, p=8, RBF gamma=1/p, 9 tau levels 0.1..0.9, lambda=1e-4 n"),
     "c4": (20000, "smooth with t(2) noise, n=20000 train + 5000 validation, p=10, RBF gamma=0.1, tau=0.5, lambda=1e-3 n"),
+    "path": (20000, "paper2d, n=20000, p=2, RBF gamma=0.1, tau=0.5, 50 lambda log-spaced over [1e-2, 1], tol 1e-8"),
 }
+
+
+def lambda_grid(count: int = 50, lo: float = 1e-2, hi: float = 1.0) -> list:
+    """``count`` values of lambda log-spaced over [lo, hi], largest first (the
+    sequences of Section 4.1)."""
+    return [float(v) for v in np.logspace(np.log10(hi), np.log10(lo), count)]
 
 
 def workload(name: str, seed: int = 0, n: int | None = None) -> Problem:
@@ -152,6 +160,10 @@ def workload(name: str, seed: int = 0, n: int | None = None) -> Problem:
             name, X[:n].copy(), y[:n].copy(), 0.5, 1e-3 * n, "rbf", 0.1,
             extras={"Xval": X[n:].copy(), "yval": y[n:].copy()},
         )
+    if name == "path":
+        X, y = paper2d(n, (40, seed))
+        lams = lambda_grid()
+        return Problem(name, X, y, 0.5, lams[0], "rbf", 0.1, extras={"lams": lams, "tol": 1e-8})
     raise AssertionError(name)
 
 

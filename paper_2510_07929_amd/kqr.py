@@ -92,6 +92,8 @@ _SIGS = {
                           C.POINTER(KqrOptions), _P, _P, C.POINTER(KqrInfo), _P]),
     "kqr_fit_multi_tau": (C.c_int, [_P, _P, _I64, _I64, _P, C.c_int, C.c_double, C.c_int, C.c_double,
                                     C.POINTER(KqrOptions), _P, _P, _P, _P, _P]),
+    "kqr_fit_path": (C.c_int, [_P, _P, _I64, _I64, C.c_double, _P, C.c_int, C.c_int, C.c_double,
+                               C.POINTER(KqrOptions), _P, _P, _P, _P, _P]),
     "kqr_fit_batch": (C.c_int, [C.c_int, _P, _P, _P, _I64, _P, _P, C.c_int, _P, C.POINTER(KqrOptions), _P, _P, _P,
                                 _P, _P]),
     "kqr_fit_grad": (C.c_int, [_P, _P, _I64, _I64, C.c_double, C.c_double, C.c_int, C.c_double, _P, _P, _I64,
@@ -408,6 +410,26 @@ def kqr_fit_multi_tau(X, y, taus, lam, kernel="rbf", gamma=1.0, options: KqrOpti
                                    taus.ctypes.data_as(C.c_void_p), m, float(lam), _kernel_id(kernel), float(gamma),
                                    C.byref(o), _dev(alpha, torch.float64, "alpha", 2), beta.ctypes.data_as(C.c_void_p),
                                    info, status.ctypes.data_as(C.c_void_p), _stream(stream)), "kqr_fit_multi_tau")
+    del keep
+    return alpha, beta, [info[i].as_dict() for i in range(m)], status.tolist()
+
+
+def kqr_fit_path(X, y, tau, lams, kernel="rbf", gamma=1.0, options: KqrOptions | None = None, uniforms=None,
+                 stream=None, **overrides):
+    """Fits for a sequence of lambda values on one K.  Returns (alpha (nlam x n GPU), betas, infos, statuses)."""
+    torch = _torch()
+    n, p = X.shape
+    lams = np.ascontiguousarray(np.asarray(lams, dtype=np.float64))
+    m = int(lams.size)
+    o, keep = _options(options, uniforms, overrides)
+    alpha = torch.empty((m, n), dtype=torch.float64, device=X.device)
+    beta = np.zeros(m)
+    info = (KqrInfo * m)()
+    status = np.zeros(m, dtype=np.int32)
+    _check(lib().kqr_fit_path(_dev(X, torch.float32, "X", 2), _dev(y, torch.float64, "y", 1), n, p, float(tau),
+                              lams.ctypes.data_as(C.c_void_p), m, _kernel_id(kernel), float(gamma), C.byref(o),
+                              _dev(alpha, torch.float64, "alpha", 2), beta.ctypes.data_as(C.c_void_p), info,
+                              status.ctypes.data_as(C.c_void_p), _stream(stream)), "kqr_fit_path")
     del keep
     return alpha, beta, [info[i].as_dict() for i in range(m)], status.tolist()
 

@@ -182,6 +182,33 @@ def test_fit_equals_brute_force(seed, tau):
     assert r.kkt["err"] < 1e-9
 
 
+def test_path_values_equal_brute_force():
+    # every value of a lambda sequence, warm-started or cold, is the unique
+    # optimum for that lambda (brute force over the partitions)
+    n = 8
+    X, y, K = _tiny(n, 2, 31, gamma=0.7)
+    lams = inputs.lambda_grid(4, 0.05, 2.0)
+    tau = 0.35
+    for warm in (True, False):
+        res = sv.fit_path(X, y, tau, lams, "rbf", 0.7, sv.OracleOptions(tol=1e-10), warm=warm)
+        for lam, r in zip(lams, res):
+            a_bf, blo, bhi = pins.brute_force(K, y, lam, tau)
+            assert np.abs(r.alpha - a_bf).max() < 1e-7
+            assert blo - 1e-7 <= r.beta <= bhi + 1e-7
+            assert r.kkt["err"] < 1e-9
+
+
+def test_path_warm_start_keeps_stationarity():
+    # the warm start keeps alpha, beta and sets z to the residual at the new
+    # lambda: the stationarity residual is zero there and alpha stays feasible
+    n = 50
+    X, y, K = _tiny(n, 2, 32, gamma=0.5)
+    prev = sv.fit(X, y, 0.6, 1.0, "rbf", 0.5, sv.OracleOptions(tol=1e-10))
+    st = sv.path_start(prev, y, 0.7)
+    assert np.abs(K @ st["alpha"] / 0.7 - y + st["beta"] + st["z"]).max() < 1e-12
+    assert np.array_equal(st["alpha"], prev.alpha) and st["beta"] == prev.beta
+
+
 def test_fit_equals_generic_qp():
     n = 60
     X, y, K = _tiny(n, 3, 21, gamma=1.0)
