@@ -412,6 +412,61 @@ def bench_path(args, prob):
     return out
 
 
+def bench_ablation(args, prob):
+    """The two-phase method against each phase alone and against plain CG
+    (no preconditioner), on one problem, with per-iteration traces."""
+    import torch
+
+    from paper_2510_07929_amd import inputs, kqr
+
+    dev = torch.device("cuda:0")
+    X = torch.from_numpy(prob.X).to(dev)
+    y = torch.from_numpy(prob.y).to(dev)
+    tol = prob.extras["tol"]
+    uni = inputs.pivot_uniforms(1024, (sum(map(ord, prob.name)), 0))
+    variants = {
+        "palm": {},
+        "admm_alone": dict(admm_tol=tol, admm_max_iter=1000, alm_max_iter=0),
+        "ssn_alm_alone": dict(admm_max_iter=0, alm_max_iter=1000),
+        "palm_plain_cg": dict(rank=-1),
+    }
+    base = dict(tol=tol, rank=0, kmode=kqr.KQR_KMODE_MATERIALIZE, profile=1)
+    res = {}
+    t_palm = None
+    for name, kw in variants.items():
+        opts = dict(base, **kw)
+        for _ in range(args.warmup if name == "palm" else 0):
+            kqr.kqr_fit(X, y, prob.tau, prob.lam, prob.kernel, prob.gamma, uniforms=uni, **opts)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        reps = args.steps if name == "palm" else 1
+        for _ in range(reps):
+            _, beta, info, st = kqr.kqr_fit(X, y, prob.tau, prob.lam, prob.kernel, prob.gamma, uniforms=uni,
+                                            trace=4000, **opts)
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t0) / reps
+        if name == "palm":
+            t_palm = el
+        tr = info.pop("trace")
+        step = max(1, len(tr) // 60)
+        res[name] = {
+            "s": round(el, 4), "status": st, "err": max(info["eta_kkt"], info["eta_gap"]),
+            "admm_iters": info["admm_iters"], "alm_iters": info["alm_iters"], "newton_iters": info["newton_iters"],
+            "pcg_iters": info["admm_pcg_iters"] + info["pcg_iters"], "kapply_calls": info["kapply_calls"],
+            "rank": info["rank_used"],
+            "trace_every": step,
+            "trace": [[int(r[0]), int(r[1]), float("%.3e" % r[2]), round(float(r[3]), 4)] for r in tr[::step]]
+                     + ([[int(tr[-1][0]), int(tr[-1][1]), float("%.3e" % tr[-1][2]), round(float(tr[-1][3]), 4)]]
+                        if len(tr) and (len(tr) - 1) % step else []),
+        }
+    out = base_line(args, prob, "f32", {"k_storage": "fp32", "tol": tol})
+    out.update(value=None, ms_per_step=round(t_palm * 1e3, 3))
+    out["ablation"] = res
+    out["note"] = ("value is null: this line compares solver variants on one problem; K-apply rates are "
+                   "on the c1 line")
+    return out
+
+
 def bench_batch(args):
     """64 uneven problems in one batched fit against the same fits one at a time."""
     import numpy as np
@@ -570,6 +625,8 @@ def main():
             out = bench_grad(args, prob)
         elif w == "path":
             out = bench_path(args, prob)
+        elif w == "ablation":
+            out = bench_ablation(args, prob)
         else:
             out = bench_single(args, prob)
     print(json.dumps(out), flush=True)

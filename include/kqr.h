@@ -113,6 +113,12 @@ typedef struct kqr_options {
                           (1+||y||) max(ssn_rel tol, min(ssn_adapt e_{k-1}, 1)), e_{k-1} =
                           max(eta_kkt, eta_gap) of the previous outer iterate (Phase I's for k = 0);
                           0 = always ssn_rel tol.  0.3 */
+  double* trace;       /* host, 4 * trace_cap doubles, or NULL: kqr_fit and kqr_fit_grad write one
+                          record per outer iteration (Phase I ADMM iteration, Phase II ALM
+                          iteration): {phase (1 or 2), iteration, max(eta_kkt, eta_gap) at that
+                          iterate, seconds since the fit started}; records beyond trace_cap are
+                          dropped.  The batched entry points ignore it.  NULL */
+  int trace_cap;       /* records trace holds; 0 */
 } kqr_options;
 
 /* ---------------------------------------------------------------- report */
@@ -130,6 +136,7 @@ typedef struct kqr_info {
   /* with opt->profile: summed device time of the K-apply kernels (seconds) */
   int64_t kapply_fast_calls, kapply_exact_calls;
   double t_kapply_fast, t_kapply_exact;
+  int trace_len;                /* records written to opt->trace */
 } kqr_info;
 
 /* Fills *opt with the defaults listed above.  Returns KQR_OK or KQR_EINVAL (opt NULL). */

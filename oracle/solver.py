@@ -237,7 +237,11 @@ def alm(op, y, tau, lam, F, start: dict, opts: OracleOptions, direct: bool, hist
     e_prev = start["kkt"]["err"] if start.get("kkt") else np.inf
     tot = dict(newton=0, pcg=0, ls=0)
     res, v = None, start.get("v", alpha).copy()
-    k = 0
+    # a start that already meets the final target (Phase I run alone) is kept
+    res = pb.kkt(alpha, v, beta, z, Ka, y, lam, tau)
+    if res["err"] <= opts.tol:
+        return dict(alpha=alpha, v=v, beta=beta, z=z, Kalpha=Ka, sigma=sigma, iters=0, kkt=res, **tot)
+    k = -1
     for k in range(opts.alm_max_iter):
         stop = scale * max(opts.ssn_rel * opts.tol, min(opts.ssn_adapt * e_prev, 1.0))
         alpha, v, Ka, info = ssn(op, y, tau, lam, beta, z, sigma, alpha, Ka, F, opts, direct, stop)

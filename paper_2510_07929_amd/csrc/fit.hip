@@ -55,6 +55,7 @@ void validate_options(const kqr_options& o) {
   KQR_OPT_REQUIRE(o.sigma_factor >= 1.0 && o.sigma_max >= o.admm_sigma,
                   "need sigma_factor >= 1, sigma_max >= admm_sigma");
   KQR_OPT_REQUIRE(o.ssn_max_iter >= 1 && o.ls_max >= 1 && o.ssn_rel > 0.0, "need ssn_max_iter, ls_max >= 1");
+  KQR_OPT_REQUIRE(o.trace_cap >= 0 && (o.trace || o.trace_cap == 0), "trace_cap needs a trace buffer");
 }
 
 Prepared prepare_fit(const float* X, int64_t n, int p, KernelSpec ks, const kqr_options& o, hipStream_t st) {
@@ -353,8 +354,11 @@ int status_of(const std::exception_ptr& e, std::string& msg) {
 }  // namespace
 
 void fit_levels(const float* X, const double* y, int64_t n, int p, KernelSpec ks, const double* taus,
-                const double* lams, int nlev, const kqr_options& o, double* alpha, double* beta, kqr_info* info,
+                const double* lams, int nlev, const kqr_options& o_in, double* alpha, double* beta, kqr_info* info,
                 int* status, hipStream_t st) {
+  kqr_options o = o_in;
+  o.trace = nullptr;  // one trace buffer cannot serve several concurrent fits
+  o.trace_cap = 0;
   Prepared pr = prepare_fit(X, n, p, ks, o, st);
   const int nw = std::min(nlev, kKvMaxCols);
   const bool batched = pr.K.ptr != nullptr && nw > 1;
@@ -424,8 +428,11 @@ void fit_path(const float* X, const double* y, int64_t n, int p, KernelSpec ks, 
 }
 
 void fit_batch(int nprob, const float* const* X, const double* const* y, const int64_t* n, int p, KernelSpec ks,
-               const double* tau, const double* lam, const double* gamma, const kqr_options& o,
+               const double* tau, const double* lam, const double* gamma, const kqr_options& o_in,
                double* const* alpha, double* beta, kqr_info* info, int* status, hipStream_t st) {
+  kqr_options o = o_in;
+  o.trace = nullptr;  // one trace buffer cannot serve several concurrent fits
+  o.trace_cap = 0;
   std::vector<Prepared> prs;
   prs.reserve(size_t(nprob));
   std::vector<KMat> kms;

@@ -117,6 +117,7 @@ class Solver {
   void ssn(double stop, kqr_info& info);
   Kkt kkt_from_sums(const double* s) const;
   Kkt update_and_kkt(double beta_new, double sigma, double step, bool update);
+  void record(int phase, int it, double err);
   double sum_of(const double* x);
   double read_scalar(const double* dev, hipStream_t st);
   void read_scalars(const double* dev, int cnt, double* out, hipStream_t st);
@@ -134,6 +135,8 @@ class Solver {
   DevBuf rf_r_, rf_dx_, rf_kdx_;  // refinement workspace (BF16 storage)
   std::unique_ptr<Woodbury> P_;
   double beta_ = 0.0, sigma_ = 1.0, ynorm_ = 0.0, eta_d_prev_ = 1.0;
+  double t_start_ = 0.0;
+  int ntrace_ = 0;
   Kkt last_;
   bool converged_ = false;
 };

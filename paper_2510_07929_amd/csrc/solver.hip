@@ -177,6 +177,10 @@ PcgStats Pcg::solve(double c, const double* L, Woodbury* P, const double* b, dou
   return stats;
 }
 
+static double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
 // ================================================================= solver
 Solver::Solver(Operator& op, const double* y, int64_t n, double tau, double lam, const kqr_options& o,
                const float* F, int64_t rank, int64_t ldf, hipStream_t st)
@@ -190,6 +194,17 @@ Solver::Solver(Operator& op, const double* y, int64_t n, double tau, double lam,
   read_scalars(red_.as<double>(), 3, t3, st);
   ynorm_ = std::sqrt(t3[2]);
   if (!std::isfinite(ynorm_)) fail(KQR_ENUMERIC, "y contains NaN or Inf");
+  t_start_ = now_s();
+}
+
+void Solver::record(int phase, int it, double err) {
+  if (!o_.trace || ntrace_ >= o_.trace_cap) return;
+  double* r = o_.trace + 4 * int64_t(ntrace_);
+  r[0] = phase;
+  r[1] = it;
+  r[2] = err;
+  r[3] = now_s() - t_start_;
+  ++ntrace_;
 }
 
 Kkt Solver::kkt_from_sums(const double* s) const {
@@ -219,10 +234,6 @@ Kkt Solver::update_and_kkt(double beta_new, double sigma, double step, bool upda
                  step, tau_, lam_, update, ws_, red_.as<double>(), st_);
   read_scalars(red_.as<double>(), kKktSums, s, st_);
   return kkt_from_sums(s);
-}
-
-static double now_s() {
-  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
 // Linear solve of (K + c 1 1^T + diag(L)) x = b to ||b - A x|| <= tol, with K x
@@ -327,6 +338,13 @@ void Solver::phase1(kqr_info& info) {
       fprintf(stderr, "[kqr] admm %3d pcg %3d eta_p %.2e eta_d %.2e eta_c %.2e gap %.2e\n", it + 1, ps.iters,
               k.eta_p, k.eta_d, k.eta_c, k.eta_gap);
     if (!std::isfinite(k.err)) fail(KQR_ENUMERIC, "non-finite residual in Phase I");
+    if (k.err <= o_.admm_tol && o_.admm_tol <= o_.tol) {
+      // Phase I is the whole solve here: confirm with an exact K alpha (the
+      // tracked products carry FP32 rounding) before stopping
+      op_.apply_exact(alpha_.as<double>(), Ka_.as<double>(), st_);
+      k = update_and_kkt(beta_, sigma, step, false);
+    }
+    record(1, it + 1, k.err);
     if (k.err <= o_.admm_tol) { ++it; break; }
   }
   info.admm_iters = it;
@@ -399,7 +417,12 @@ void Solver::phase2(kqr_info& info) {
   double e_prev = last_.err;
   int it = 0;
   bool done = false;
-  for (it = 0; it < o_.alm_max_iter; ++it) {
+  if (k.err <= o_.tol) {  // Phase I already met the final target (ADMM run alone): confirm exactly
+    op_.apply_exact(alpha_.as<double>(), Ka_.as<double>(), st_);
+    k = update_and_kkt(beta_, sigma_, 1.0, false);
+    done = k.err <= o_.tol;
+  }
+  for (it = 0; !done && it < o_.alm_max_iter; ++it) {
     const double stop = scale * std::max(o_.ssn_rel * o_.tol, std::min(o_.ssn_adapt * e_prev, 1.0));
     op_.apply_exact(alpha_.as<double>(), Ka_.as<double>(), st_);  // reset drift of the tracked K alpha
     ssn(stop, info);
@@ -407,6 +430,7 @@ void Solver::phase2(kqr_info& info) {
     const double beta_new = beta_ + sigma_ * sa;
     k = update_and_kkt(beta_new, sigma_, 1.0, true);
     beta_ = beta_new;
+    record(2, it + 1, k.err);
     if (o_.verbose)
       fprintf(stderr, "[kqr] alm %3d sigma %.1e eta_p %.2e eta_d %.2e eta_c %.2e gap %.2e\n", it + 1, sigma_,
               k.eta_p, k.eta_d, k.eta_c, k.eta_gap);
@@ -441,6 +465,7 @@ void Solver::finish(kqr_info& info) {
   info.obj_p = k.obj_p;
   info.obj_d = k.obj_d;
   info.sigma = sigma_;
+  info.trace_len = ntrace_;
   count_interior(n_, alpha_.as<double>(), tau_, ws_, red_.as<double>(), st_);
   info.n_interior = int64_t(read_scalar(red_.as<double>(), st_));
   converged_ = converged_ && k.err <= o_.tol;

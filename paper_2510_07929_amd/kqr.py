@@ -44,6 +44,7 @@ class KqrOptions(C.Structure):
         ("k_dtype", C.c_int), ("kmode", C.c_int), ("refine", C.c_int),
         ("pivot_uniforms", C.POINTER(C.c_double)), ("seed", C.c_uint64), ("verbose", C.c_int),
         ("profile", C.c_int), ("exact_k", C.c_int), ("ssn_adapt", C.c_double),
+        ("trace", C.POINTER(C.c_double)), ("trace_cap", C.c_int),
     ]
 
 
@@ -60,6 +61,7 @@ class KqrInfo(C.Structure):
         ("t_alm", C.c_double), ("t_total", C.c_double),
         ("kapply_fast_calls", C.c_int64), ("kapply_exact_calls", C.c_int64),
         ("t_kapply_fast", C.c_double), ("t_kapply_exact", C.c_double),
+        ("trace_len", C.c_int),
     ]
 
     def as_dict(self):
@@ -361,8 +363,11 @@ def kqr_ssn_gradient(tau, lam, beta, sigma, alpha, Kalpha, y, z, tau1=0.1, tau2=
 
 
 def kqr_fit(X, y, tau, lam, kernel="rbf", gamma=1.0, options: KqrOptions | None = None, uniforms=None,
-            stream=None, **overrides):
-    """PALM-KQR fit on the GPU.  Returns (alpha (GPU float64), beta, info dict, status)."""
+            stream=None, trace: int = 0, **overrides):
+    """PALM-KQR fit on the GPU.  Returns (alpha (GPU float64), beta, info dict, status).
+
+    ``trace`` > 0 records up to that many outer iterations; info["trace"] is
+    then an array of rows (phase, iteration, max(eta_kkt, eta_gap), seconds)."""
     torch = _torch()
     n, p = X.shape
     o = options if options is not None else kqr_default_options()
@@ -372,6 +377,11 @@ def kqr_fit(X, y, tau, lam, kernel="rbf", gamma=1.0, options: KqrOptions | None 
     if uniforms is not None:
         keep = np.ascontiguousarray(np.asarray(uniforms, dtype=np.float64))
         o.pivot_uniforms = keep.ctypes.data_as(C.POINTER(C.c_double))
+    tbuf = None
+    if trace > 0:
+        tbuf = np.zeros((int(trace), 4))
+        o.trace = tbuf.ctypes.data_as(C.POINTER(C.c_double))
+        o.trace_cap = int(trace)
     alpha = torch.empty(n, dtype=torch.float64, device=X.device)
     beta = C.c_double(0.0)
     info = KqrInfo()
@@ -380,7 +390,11 @@ def kqr_fit(X, y, tau, lam, kernel="rbf", gamma=1.0, options: KqrOptions | None 
                        C.byref(beta), C.byref(info), _stream(stream))
     _check(st, "kqr_fit", allow=(KQR_OK, KQR_NOT_CONVERGED))
     del keep
-    return alpha, float(beta.value), info.as_dict(), st
+    out = info.as_dict()
+    if tbuf is not None:
+        out["trace"] = tbuf[: info.trace_len].copy()
+        o.trace, o.trace_cap = None, 0
+    return alpha, float(beta.value), out, st
 
 
 def _options(options, uniforms, overrides):

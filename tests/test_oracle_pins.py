@@ -198,6 +198,23 @@ def test_path_values_equal_brute_force():
             assert r.kkt["err"] < 1e-9
 
 
+def test_phase1_alone_and_phase2_alone_equal_brute_force():
+    # the ablations of Section 4.1 reach the same optimum
+    n = 8
+    X, y, K = _tiny(n, 2, 33, gamma=0.7)
+    lam, tau = 0.3, 0.6
+    a_bf, blo, bhi = pins.brute_force(K, y, lam, tau)
+    only1 = sv.OracleOptions(tol=1e-10, admm_tol=1e-10, admm_max_iter=200000, alm_max_iter=0, polish=False)
+    only2 = sv.OracleOptions(tol=1e-10, admm_max_iter=0, polish=False)
+    for o in (only1, only2):
+        r = sv.fit(X, y, tau, lam, "rbf", 0.7, o)
+        assert r.kkt["err"] <= 1e-10
+        assert np.abs(r.alpha - a_bf).max() < 1e-7
+        assert blo - 1e-7 <= r.beta <= bhi + 1e-7
+    r1 = sv.fit(X, y, tau, lam, "rbf", 0.7, only1)
+    assert r1.info["alm_iters"] == 0 and r1.info["admm_iters"] > 0
+
+
 def test_path_warm_start_keeps_stationarity():
     # the warm start keeps alpha, beta and sets z to the residual at the new
     # lambda: the stationarity residual is zero there and alpha stays feasible
