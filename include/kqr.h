@@ -93,7 +93,7 @@ typedef struct kqr_options {
   double sigma_stall;  /* ... when eta_d > sigma_stall * previous eta_d; 0.25 */
   double sigma_max;    /* 1e8 */
   int rank;            /* preconditioner rank: >0 fixed, 0 adaptive (Section 3), <0 none; 0 */
-  double xi;           /* adaptive-rank threshold (Section 3); 1e-3 */
+  double xi;           /* adaptive-rank threshold (Section 3); 1e-7 */
   int pcg_max_iter;    /* per linear solve; 2000 */
   int k_dtype;         /* KQR_FP32 or KQR_BF16 storage of a materialised K; KQR_FP32 */
   int kmode;           /* KQR_KMODE_*; KQR_KMODE_AUTO */

@@ -47,7 +47,7 @@ class OracleOptions:
     sigma_stall: float = 0.25
     sigma_max: float = 1e8
     rank: int = 0                 # >0 fixed rank, 0 adaptive (Section 3 heuristic), <0 no preconditioner
-    xi: float = 1e-3              # adaptive-rank threshold
+    xi: float = 1e-7              # adaptive-rank threshold
     pcg_max_iter: int = 2000
     direct_max: int = 5000        # exact dense solves up to this n
     polish: bool = True

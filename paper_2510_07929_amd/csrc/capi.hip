@@ -191,7 +191,7 @@ int kqr_default_options(kqr_options* o) {
   o->sigma_stall = 0.25;
   o->sigma_max = 1e8;
   o->rank = 0;
-  o->xi = 1e-3;
+  o->xi = 1e-7;
   o->pcg_max_iter = 2000;
   o->k_dtype = KQR_FP32;
   o->kmode = KQR_KMODE_AUTO;
