@@ -58,6 +58,7 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the CPU oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="skip the K-apply shape sweep before the warm-up")
+    ap.add_argument("--no-packed", action="store_true", help="single fits: skip the packed-layout comparison")
     ap.add_argument("--traffic", default=None,
                     help="counter summary (profiles/*_traffic.md) with the measured HBM bytes per K-apply launch")
     ap.add_argument("--fd", action="store_true", help="c4: also time central differences of the gradient")
@@ -100,16 +101,18 @@ def cpu_baseline(prob, budget_s):
     }
 
 
-def measured_traffic(args, prob, kdtype):
+def measured_traffic(args, prob, kdtype, layout=0):
     """HBM bytes per launch of the fast K-apply from the committed counter
     summary of this workload (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy
     calibrated), or None when there is none or the kernel source changed
     since the counters were taken."""
     from paper_2510_07929_amd import traffic as tr
 
-    path = args.traffic or os.path.join(ROOT, "profiles", f"kapply_rows_{prob.name}_{kdtype}_traffic.md")
+    kind = "packed" if layout == 1 else "rows"
+    default = os.path.join(ROOT, "profiles", f"kapply_{kind}_{prob.name}_{kdtype}_traffic.md")
+    path = (args.traffic if layout == 0 else None) or default
     got = tr.read_summary(path)
-    if got is None or got[1] != tr.source_digest():
+    if got is None or got[1] != tr.source_digest(tr.source_for(kind)):
         return None
     return got[0]
 
@@ -162,8 +165,9 @@ def timed_fits(args, one_fit):
     return outs, time.perf_counter() - t0
 
 
-def run_materialised(args, prob, kdtype, tune, **extra):
-    """Timed single-problem fits with K stored (fp32 or bf16); returns (line pieces)."""
+def run_materialised(args, prob, kdtype, tune, layout=0, **extra):
+    """Timed single-problem fits with K stored (fp32 or bf16; full rows or the
+    symmetric packed tiles); returns (line pieces)."""
     import torch
 
     from paper_2510_07929_amd import inputs, kqr
@@ -175,14 +179,22 @@ def run_materialised(args, prob, kdtype, tune, **extra):
     rank = prob.rank if prob.rank > 0 else 0
     uni = inputs.pivot_uniforms(1024, (sum(map(ord, prob.name)), 0))
     opts = dict(rank=rank, k_dtype=kqr.KDTYPES[kdtype], kmode=kqr.KQR_KMODE_MATERIALIZE, profile=1,
-                verbose=1 if args.verbose else 0, **extra)
+                verbose=1 if args.verbose else 0, k_layout=layout, **extra)
 
     def one_fit():
         _, beta, info, st = kqr.kqr_fit(X, y, prob.tau, prob.lam, prob.kernel, prob.gamma, uniforms=uni, **opts)
         return info, st
 
     tuned = {}
-    if tune:
+    if tune and layout == 1:
+        # untimed: pick the packed K-apply shape on this problem's own packed K
+        Kp = kqr.kqr_kernel_build_packed(X, prob.kernel, prob.gamma, kdtype)
+        modes = [(kqr.KQR_APPLY_FAST, "fast")] + ([(kqr.KQR_APPLY_EXACT, "exact")] if kdtype == "fp32" else [])
+        for mode, name in modes:
+            tuned[name] = kqr.kqr_autotune_packed(Kp, prob.n, mode, reps=3)["best"]
+        del Kp
+        torch.cuda.empty_cache()
+    if tune and layout == 0:
         # untimed: pick the K-apply tile shapes on this problem's own K
         K = kqr.kqr_kernel_build(X, prob.kernel, prob.gamma, kdtype)
         modes = [(kqr.KQR_APPLY_FAST, "fast")]
@@ -195,18 +207,20 @@ def run_materialised(args, prob, kdtype, tune, **extra):
         torch.cuda.empty_cache()
     outs, elapsed = timed_fits(args, one_fit)
     n = prob.n
-    kbytes = float(n) * n * esz
+    kbytes = float(n) * n * esz if layout == 0 else float(kqr.kqr_packed_bytes(n, kdtype))
     nfast = sum(i["kapply_fast_calls"] for i, _ in outs)
     tfast = sum(i["t_kapply_fast"] for i, _ in outs)
     value = nfast * kbytes / elapsed / 1e9
     avg = tfast / max(nfast, 1)
     achieved = kbytes / avg / 1e9 if avg > 0 else 0.0
-    traffic = measured_traffic(args, prob, kdtype)
+    traffic = measured_traffic(args, prob, kdtype, layout)
     last, st = outs[-1]
+    kname = ("kapply_rows_kernel (fast, materialised %s K)" % kdtype if layout == 0 else
+             "kapply_packed_*_kernel + packed_reduce_kernel (fast, %s K, symmetric packed tiles)" % kdtype)
     roof = {
         "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-        "kernel": "kapply_rows_kernel (fast, materialised %s K)" % kdtype,
+        "kernel": kname,
         "avg_launch_us": round(avg * 1e6, 2), "launches": int(nfast),
         "bytes_per_launch": kbytes, "tile_shapes": tuned or "default",
     }
@@ -220,6 +234,12 @@ def bench_single(args, prob):
     value, ms, roof, fit = run_materialised(args, prob, kdtype, not args.no_tune)
     out = base_line(args, prob, "f32" if kdtype == "fp32" else "bf16", {"k_storage": kdtype, "rank": fit["rank"]})
     out.update(value=round(value, 2), ms_per_step=round(ms, 3), roofline=roof, fit=fit)
+    if not args.no_packed:
+        # the same fit with K stored once (symmetric packed tiles): half the bytes per apply
+        pv, pms, proof, pfit = run_materialised(args, prob, kdtype, not args.no_tune, layout=1)
+        out["compare_packed"] = {"k_storage": kdtype + ", symmetric packed tiles", "value": round(pv, 2),
+                                 "ms_per_step": round(pms, 3), "roofline": proof, "fit": pfit,
+                                 "speedup_vs_full": round(ms / pms, 3)}
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(prob, args.cpu_seconds)
     return out

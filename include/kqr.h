@@ -119,6 +119,10 @@ typedef struct kqr_options {
                           iterate, seconds since the fit started}; records beyond trace_cap are
                           dropped.  The batched entry points ignore it.  NULL */
   int trace_cap;       /* records trace holds; 0 */
+  int k_layout;        /* storage of a materialised K: 0 = full n x ld rows; 1 = K's symmetry used:
+                          only the upper triangle of 128 x 128 tiles is stored (about half the
+                          bytes, so half the HBM traffic per K-apply; see kqr_kernel_build_packed).
+                          kqr_fit and kqr_fit_grad only; the joint and batched fits need 0.  0 */
 } kqr_options;
 
 /* ---------------------------------------------------------------- report */
@@ -160,6 +164,38 @@ int kqr_device_count(void);
  *  diagonal set to exactly 0, so K_ii = 1.  Asynchronous on `stream`. */
 int kqr_kernel_build(const float* X, int64_t n, int64_t p, int kernel, double gamma,
                      int k_dtype, void* K, int64_t ldk, void* stream);
+
+/* Symmetric packed layout (kqr_options.k_layout = 1).  K is symmetric
+ * (Section 1), so only the tiles (I, J), I <= J, of a tiling by 128 x 128
+ * blocks are stored: tile-row by tile-row, tile (I, J) at tile index
+ * I nt - I (I - 1) / 2 + (J - I) with nt = ceil(n / 128), each tile row-major
+ * (128 x 128 entries, zero beyond n).  A K-apply reads about half the bytes of
+ * the full layout.
+ * kqr_packed_bytes: bytes of that layout for n rows and k_dtype, or -1 for
+ *  invalid arguments.
+ * kqr_kernel_build_packed: X device n x p FP32; K device, kqr_packed_bytes
+ *  bytes (entries as in kqr_kernel_build).  Asynchronous on `stream`.
+ * kqr_kernel_apply_packed: u = K v.  v, u device n FP64 (v 16-byte aligned);
+ *  mode KQR_APPLY_FAST (v rounded to FP32, FP32 products, FP64 sums across
+ *  16-byte chunks and tiles) or KQR_APPLY_EXACT (FP64 v, products and sums).
+ *  Asynchronous on `stream`; allocates its partial sums (stream-ordered). */
+int64_t kqr_packed_bytes(int64_t n, int k_dtype);
+/* kqr_autotune_packed: times every launch shape of the packed K-apply (thread
+ * map 0 = a tile row read contiguously by 256-thread workgroups, 2 = the same
+ * with 512 threads (half the loads per lane), 1 = each wave owns 32 columns of
+ * a tile; strip = tiles per workgroup, 1..16) on the packed K (device, from
+ * kqr_kernel_build_packed) for mode KQR_APPLY_FAST or KQR_APPLY_EXACT, and
+ * installs the fastest for k_dtype and that mode (all later packed applies of
+ * the process use it).  report: host buffer of cap bytes for a JSON summary,
+ * or NULL.  Blocks until the timing is done.
+ * kqr_set_packed_shape: installs a shape directly (map 0, 1 or 2, 1 <= strip <= 32). */
+int kqr_autotune_packed(const void* K, int k_dtype, int64_t n, int mode, int reps, char* report, int64_t cap,
+                        void* stream);
+int kqr_set_packed_shape(int k_dtype, int mode, int map, int strip);
+int kqr_kernel_build_packed(const float* X, int64_t n, int64_t p, int kernel, double gamma, int k_dtype, void* K,
+                            void* stream);
+int kqr_kernel_apply_packed(const void* K, int k_dtype, int64_t n, const double* v, double* u, int mode,
+                            void* stream);
 
 /* kqr_kernel_apply: U = K(X, X) V (the operator K v of (1.2)-(3.1)).
  *  K      device matrix from kqr_kernel_build (type k_dtype, ld ldk), or NULL to

@@ -161,6 +161,63 @@ static void autotune_kv(const KMat& km, int64_t n, int reps, char* report, int64
   }
 }
 
+// Times every supported packed K-apply shape (map x strip, with the reduction)
+// on a packed K and installs the fastest for K's dtype and the mode; JSON report.
+static void autotune_packed(const KMat& km, int64_t n, bool exact, int reps, char* report, int64_t cap,
+                            hipStream_t st) {
+  DevBuf v64(size_t(n) * sizeof(double)), v32(size_t(n) * sizeof(float)), u(size_t(n) * sizeof(double));
+  DevBuf scratch(packed_scratch_doubles(n, 1) * sizeof(double));  // strip 1 needs the most
+  fill(n, 1.0 / double(n), v64.as<double>(), st);
+  to_f32(v64.as<double>(), n, 1, 1, v32.as<float>(), 1, st);
+  hipEvent_t e0, e1;
+  KQR_CHECK_HIP(hipEventCreate(&e0));
+  KQR_CHECK_HIP(hipEventCreate(&e1));
+  std::string rep = "{\"n\": " + std::to_string(n) + ", \"k_dtype\": " + std::to_string(km.dtype) +
+                    ", \"exact\": " + std::to_string(int(exact)) + ", \"shapes\": [";
+  PackedShape best;
+  double best_us = 1e300;
+  bool first = true;
+  try {
+    for (int map : {0, 1, 2})
+      for (int strip : {1, 2, 4, 8, 16}) {
+        const PackedShape s{map, strip};
+        kapply_packed(km, n, v32.as<float>(), v64.as<double>(), u.as<double>(), 1, exact, st, &s,
+                      scratch.as<double>());  // warm-up
+        KQR_CHECK_HIP(hipEventRecord(e0, st));
+        for (int k = 0; k < reps; ++k)
+          kapply_packed(km, n, v32.as<float>(), v64.as<double>(), u.as<double>(), 1, exact, st, &s,
+                        scratch.as<double>());
+        KQR_CHECK_HIP(hipEventRecord(e1, st));
+        KQR_CHECK_HIP(hipEventSynchronize(e1));
+        float ms = 0.f;
+        KQR_CHECK_HIP(hipEventElapsedTime(&ms, e0, e1));
+        const double us = 1e3 * ms / reps;
+        char buf[128];
+        snprintf(buf, sizeof(buf), "%s{\"map\": %d, \"strip\": %d, \"us\": %.2f}", first ? "" : ", ", map, strip,
+                 us);
+        first = false;
+        rep += buf;
+        if (us < best_us) { best_us = us; best = s; }
+      }
+  } catch (...) {
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    throw;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  set_packed_shape(km.dtype, exact, best);
+  char buf[160];
+  snprintf(buf, sizeof(buf), "], \"best\": {\"map\": %d, \"strip\": %d, \"us\": %.2f}}", best.map, best.strip,
+           best_us);
+  rep += buf;
+  if (report && cap > 0) {
+    const size_t nb = std::min<size_t>(size_t(cap) - 1, rep.size());
+    memcpy(report, rep.data(), nb);
+    report[nb] = '\0';
+  }
+}
+
 }  // namespace kqr
 
 using namespace kqr;
@@ -306,6 +363,74 @@ int kqr_kernel_apply(const float* X, int64_t n, int64_t p, int kernel, double ga
     }
     if (sqn) KQR_CHECK_HIP(hipFreeAsync(sqn, st));
     KQR_CHECK_HIP(hipFreeAsync(tmp, st));
+  });
+}
+
+int64_t kqr_packed_bytes(int64_t n, int k_dtype) {
+  if (n < 1 || (k_dtype != KQR_FP32 && k_dtype != KQR_BF16)) return -1;
+  return int64_t(packed_bytes(n, k_dtype));
+}
+
+int kqr_kernel_build_packed(const float* X, int64_t n, int64_t p, int kernel, double gamma, int k_dtype, void* K,
+                            void* stream) {
+  return guarded([&] {
+    KQR_REQUIRE(X && K, "pointers must be non-null");
+    KQR_REQUIRE(n >= 1 && p >= 1 && p <= 64, "need n >= 1 and 1 <= p <= 64");
+    KQR_REQUIRE(k_dtype == KQR_FP32 || k_dtype == KQR_BF16, "k_dtype must be KQR_FP32 or KQR_BF16");
+    check_kernel(kernel, gamma);
+    ensure_device();
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    float* sqn = nullptr;
+    KQR_CHECK_HIP(hipMallocAsync(reinterpret_cast<void**>(&sqn), size_t(n) * sizeof(float), st));
+    row_sqnorms(X, n, int(p), sqn, st);
+    kbuild_packed(X, sqn, n, int(p), KernelSpec{kernel, gamma}, k_dtype, K, st);
+    KQR_CHECK_HIP(hipFreeAsync(sqn, st));
+  });
+}
+
+int kqr_kernel_apply_packed(const void* K, int k_dtype, int64_t n, const double* v, double* u, int mode,
+                            void* stream) {
+  return guarded([&] {
+    KQR_REQUIRE(K && v && u, "pointers must be non-null");
+    KQR_REQUIRE(n >= 1, "need n >= 1");
+    KQR_REQUIRE(k_dtype == KQR_FP32 || k_dtype == KQR_BF16, "k_dtype must be KQR_FP32 or KQR_BF16");
+    KQR_REQUIRE(mode == KQR_APPLY_FAST || mode == KQR_APPLY_EXACT, "mode must be KQR_APPLY_FAST or KQR_APPLY_EXACT");
+    KQR_REQUIRE((reinterpret_cast<uintptr_t>(v) & 15) == 0, "v must be 16-byte aligned");
+    ensure_device();
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const KMat km{K, k_dtype, packed_tiles_per_side(n), 1};
+    if (mode == KQR_APPLY_EXACT) {
+      kapply_packed(km, n, nullptr, v, u, 1, true, st);
+    } else {
+      float* v32 = nullptr;
+      KQR_CHECK_HIP(hipMallocAsync(reinterpret_cast<void**>(&v32), size_t(n) * sizeof(float), st));
+      to_f32(v, n, 1, 1, v32, 1, st);
+      kapply_packed(km, n, v32, nullptr, u, 1, false, st);
+      KQR_CHECK_HIP(hipFreeAsync(v32, st));
+    }
+  });
+}
+
+int kqr_autotune_packed(const void* K, int k_dtype, int64_t n, int mode, int reps, char* report, int64_t cap,
+                        void* stream) {
+  return guarded([&] {
+    KQR_REQUIRE(K != nullptr, "K must be non-null");
+    KQR_REQUIRE(n >= 1 && reps >= 1, "need n >= 1 and reps >= 1");
+    KQR_REQUIRE(k_dtype == KQR_FP32 || k_dtype == KQR_BF16, "k_dtype must be KQR_FP32 or KQR_BF16");
+    KQR_REQUIRE(mode == KQR_APPLY_FAST || mode == KQR_APPLY_EXACT, "mode must be KQR_APPLY_FAST or KQR_APPLY_EXACT");
+    ensure_device();
+    autotune_packed(KMat{K, k_dtype, packed_tiles_per_side(n), 1}, n, mode == KQR_APPLY_EXACT, reps, report, cap,
+                    static_cast<hipStream_t>(stream));
+  });
+}
+
+int kqr_set_packed_shape(int k_dtype, int mode, int map, int strip) {
+  return guarded([&] {
+    KQR_REQUIRE(k_dtype == KQR_FP32 || k_dtype == KQR_BF16, "k_dtype must be KQR_FP32 or KQR_BF16");
+    KQR_REQUIRE(mode == KQR_APPLY_FAST || mode == KQR_APPLY_EXACT, "mode must be KQR_APPLY_FAST or KQR_APPLY_EXACT");
+    const PackedShape s{map, strip};
+    KQR_REQUIRE(packed_shape_supported(s), "need map 0, 1 or 2 and 1 <= strip <= 32");
+    set_packed_shape(k_dtype, mode == KQR_APPLY_EXACT, s);
   });
 }
 

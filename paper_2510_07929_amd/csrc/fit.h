@@ -14,13 +14,14 @@ struct Prepared {
   DevBuf K;
   int64_t ldk = 0;
   int dtype = KQR_FP32;
+  int layout = 0;  // 0 full n x ldk; 1 upper-triangle tiles (ldk = tiles per side)
   DevBuf K32;  // FP32 copy beside a BF16 K (exact applies), when requested
   DevBuf F;
   int64_t ldf = 4;
   int64_t rank = 0;
   double t_kbuild = 0.0, t_precond = 0.0;
-  KMat kmat() const { return KMat{K.ptr, dtype, ldk}; }
-  KMat kmat_exact() const { return KMat{K32.ptr, KQR_FP32, ldk}; }
+  KMat kmat() const { return KMat{K.ptr, dtype, ldk, layout}; }
+  KMat kmat_exact() const { return KMat{K32.ptr, KQR_FP32, ldk, layout}; }
   // Operator over this K (and its FP32 copy for the exact applies, if any).
   void attach(Operator& op) const {
     if (K32.ptr) op.set_exact(kmat_exact());

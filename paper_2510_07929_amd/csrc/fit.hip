@@ -56,15 +56,17 @@ void validate_options(const kqr_options& o) {
                   "need sigma_factor >= 1, sigma_max >= admm_sigma");
   KQR_OPT_REQUIRE(o.ssn_max_iter >= 1 && o.ls_max >= 1 && o.ssn_rel > 0.0, "need ssn_max_iter, ls_max >= 1");
   KQR_OPT_REQUIRE(o.trace_cap >= 0 && (o.trace || o.trace_cap == 0), "trace_cap needs a trace buffer");
+  KQR_OPT_REQUIRE(o.k_layout == 0 || o.k_layout == 1, "k_layout must be 0 (full) or 1 (packed)");
 }
 
 Prepared prepare_fit(const float* X, int64_t n, int p, KernelSpec ks, const kqr_options& o, hipStream_t st) {
   Prepared pr;
   const double t0 = wall_seconds();
   pr.dtype = o.k_dtype;
+  pr.layout = o.k_layout;
   const int esz = o.k_dtype == KQR_BF16 ? 2 : 4;
-  pr.ldk = (n + 63) / 64 * 64;
-  const size_t kbytes = size_t(n) * size_t(pr.ldk) * esz;
+  pr.ldk = pr.layout == 1 ? packed_tiles_per_side(n) : (n + 63) / 64 * 64;
+  const size_t kbytes = pr.layout == 1 ? packed_bytes(n, o.k_dtype) : size_t(n) * size_t(pr.ldk) * esz;
   bool materialize = o.kmode == KQR_KMODE_MATERIALIZE;
   if (o.kmode == KQR_KMODE_AUTO) {
     size_t freeb = 0, totalb = 0;
@@ -73,7 +75,14 @@ Prepared prepare_fit(const float* X, int64_t n, int p, KernelSpec ks, const kqr_
   }
   DevBuf sqn(size_t(n) * sizeof(float));
   row_sqnorms(X, n, p, sqn.as<float>(), st);
-  if (materialize) {
+  if (materialize && pr.layout == 1) {
+    pr.K.alloc(kbytes);
+    kbuild_packed(X, sqn.as<float>(), n, p, ks, o.k_dtype, pr.K.ptr, st);
+    if (o.k_dtype == KQR_BF16 && o.exact_k == 1) {
+      pr.K32.alloc(packed_bytes(n, KQR_FP32));
+      kbuild_packed(X, sqn.as<float>(), n, p, ks, KQR_FP32, pr.K32.ptr, st);
+    }
+  } else if (materialize) {
     pr.K.alloc(kbytes);
     kbuild(X, sqn.as<float>(), n, p, ks, o.k_dtype, pr.K.ptr, pr.ldk, st);
     if (o.k_dtype == KQR_BF16 && o.exact_k == 1) {
@@ -359,6 +368,7 @@ void fit_levels(const float* X, const double* y, int64_t n, int p, KernelSpec ks
   kqr_options o = o_in;
   o.trace = nullptr;  // one trace buffer cannot serve several concurrent fits
   o.trace_cap = 0;
+  if (o.k_layout != 0) fail(KQR_EINVAL, "joint fits stream K in the full layout (k_layout = 0)");
   Prepared pr = prepare_fit(X, n, p, ks, o, st);
   const int nw = std::min(nlev, kKvMaxCols);
   const bool batched = pr.K.ptr != nullptr && nw > 1;
@@ -433,6 +443,7 @@ void fit_batch(int nprob, const float* const* X, const double* const* y, const i
   kqr_options o = o_in;
   o.trace = nullptr;  // one trace buffer cannot serve several concurrent fits
   o.trace_cap = 0;
+  if (o.k_layout != 0) fail(KQR_EINVAL, "batched problems stream K in the full layout (k_layout = 0)");
   std::vector<Prepared> prs;
   prs.reserve(size_t(nprob));
   std::vector<KMat> kms;

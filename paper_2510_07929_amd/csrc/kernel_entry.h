@@ -5,6 +5,9 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cstddef>
+#include <cstdint>
+
 namespace kqr {
 
 constexpr float kLog2e = 1.4426950408889634f;
@@ -36,6 +39,22 @@ __device__ __forceinline__ float pair_dist_dyn(const float* __restrict__ xi, flo
   float g = 0.f;
   for (int k = 0; k < p; ++k) g = fmaf(xi[k], xj[k], g);
   return fmaxf(qi + qj - 2.f * g, 0.f);
+}
+
+// Symmetric K stored once as the upper triangle of kPkT x kPkT tiles, tile
+// (I, J), I <= J, at tile index I nt - I (I - 1) / 2 + (J - I) (nt tiles per
+// side), each tile row-major.
+constexpr int kPkT = 128;
+
+__host__ __device__ __forceinline__ int64_t pk_tile_index(int64_t I, int64_t J, int64_t nt) {
+  return I * nt - I * (I - 1) / 2 + (J - I);
+}
+
+// Element offset of K[i][j] in that layout.
+__host__ __device__ __forceinline__ size_t pk_offset(int64_t i, int64_t j, int64_t nt) {
+  const int64_t I = i / kPkT, J = j / kPkT;
+  return J >= I ? size_t(pk_tile_index(I, J, nt)) * kPkT * kPkT + size_t(i % kPkT) * kPkT + size_t(j % kPkT)
+                : size_t(pk_tile_index(J, I, nt)) * kPkT * kPkT + size_t(j % kPkT) * kPkT + size_t(i % kPkT);
 }
 
 }  // namespace kqr

@@ -299,7 +299,7 @@ bool apply_shape_supported(const ApplyShape& s) {
 template <int ROWS, int UNROLL>
 static void kapply_rows_launch(const KMat& km, int64_t nrows, int64_t ncols, const float* v32,
                                const double* v64, double* u, int64_t ldu, bool exact, int segs,
-                               hipStream_t st) {
+                               hipStream_t st, double* scratch, size_t scratch_doubles) {
   const int vec = km.dtype == KQR_BF16 ? 8 : 4;
   const int64_t nchunk = ncols / vec;
   segs = int(std::max<int64_t>(1, std::min<int64_t>(segs, nchunk / 64)));
@@ -310,7 +310,9 @@ static void kapply_rows_launch(const KMat& km, int64_t nrows, int64_t ncols, con
   const int64_t waves = (nrows + ROWS - 1) / ROWS;
   const dim3 grid((unsigned)((waves + 3) / 4), (unsigned)segs);
   double* part = nullptr;
-  if (segs > 1)
+  const bool own = segs > 1 && !(scratch && scratch_doubles >= size_t(segs) * size_t(nrows));
+  if (segs > 1) part = scratch;
+  if (own)
     KQR_CHECK_HIP(hipMallocAsync(reinterpret_cast<void**>(&part), size_t(segs) * nrows * sizeof(double), st));
   const bool bf = km.dtype == KQR_BF16;
   if (exact && bf)
@@ -329,25 +331,33 @@ static void kapply_rows_launch(const KMat& km, int64_t nrows, int64_t ncols, con
   if (part) {
     kapply_seg_reduce<<<dim3((unsigned)((nrows + 255) / 256)), 256, 0, st>>>(part, segs, nrows, u, ldu);
     KQR_LAUNCH_CHECK();
-    KQR_CHECK_HIP(hipFreeAsync(part, st));
+    if (own) KQR_CHECK_HIP(hipFreeAsync(part, st));
   }
 }
 
 void kapply_dense(const KMat& km, int64_t nrows, int64_t ncols, const float* v32, const double* v64,
-                  double* u, int64_t ldu, bool exact, hipStream_t st, const ApplyShape* shape) {
+                  double* u, int64_t ldu, bool exact, hipStream_t st, const ApplyShape* shape, double* scratch,
+                  size_t scratch_doubles) {
   if (nrows <= 0) return;
+  if (km.layout == 1) {  // symmetric upper-triangle tiles (kpacked.hip)
+    if (nrows != ncols) fail(KQR_EINVAL, "the packed layout holds square K only");
+    const PackedShape ps = default_packed_shape(km.dtype, exact);
+    const bool fits = scratch && scratch_doubles >= packed_scratch_doubles(nrows, ps.strip);
+    kapply_packed(km, nrows, v32, v64, u, ldu, exact, st, &ps, fits ? scratch : nullptr);
+    return;
+  }
   const ApplyShape s = shape ? *shape : default_apply_shape(km.dtype, exact, nrows);
   const int key = s.rows * 100 + s.unroll;
   switch (key) {
-    case 201: kapply_rows_launch<2, 1>(km, nrows, ncols, v32, v64, u, ldu, exact, s.segs, st); break;
-    case 202: kapply_rows_launch<2, 2>(km, nrows, ncols, v32, v64, u, ldu, exact, s.segs, st); break;
-    case 204: kapply_rows_launch<2, 4>(km, nrows, ncols, v32, v64, u, ldu, exact, s.segs, st); break;
-    case 401: kapply_rows_launch<4, 1>(km, nrows, ncols, v32, v64, u, ldu, exact, s.segs, st); break;
-    case 402: kapply_rows_launch<4, 2>(km, nrows, ncols, v32, v64, u, ldu, exact, s.segs, st); break;
-    case 404: kapply_rows_launch<4, 4>(km, nrows, ncols, v32, v64, u, ldu, exact, s.segs, st); break;
-    case 801: kapply_rows_launch<8, 1>(km, nrows, ncols, v32, v64, u, ldu, exact, s.segs, st); break;
-    case 802: kapply_rows_launch<8, 2>(km, nrows, ncols, v32, v64, u, ldu, exact, s.segs, st); break;
-    case 804: kapply_rows_launch<8, 4>(km, nrows, ncols, v32, v64, u, ldu, exact, s.segs, st); break;
+    case 201: kapply_rows_launch<2, 1>(km, nrows, ncols, v32, v64, u, ldu, exact, s.segs, st, scratch, scratch_doubles); break;
+    case 202: kapply_rows_launch<2, 2>(km, nrows, ncols, v32, v64, u, ldu, exact, s.segs, st, scratch, scratch_doubles); break;
+    case 204: kapply_rows_launch<2, 4>(km, nrows, ncols, v32, v64, u, ldu, exact, s.segs, st, scratch, scratch_doubles); break;
+    case 401: kapply_rows_launch<4, 1>(km, nrows, ncols, v32, v64, u, ldu, exact, s.segs, st, scratch, scratch_doubles); break;
+    case 402: kapply_rows_launch<4, 2>(km, nrows, ncols, v32, v64, u, ldu, exact, s.segs, st, scratch, scratch_doubles); break;
+    case 404: kapply_rows_launch<4, 4>(km, nrows, ncols, v32, v64, u, ldu, exact, s.segs, st, scratch, scratch_doubles); break;
+    case 801: kapply_rows_launch<8, 1>(km, nrows, ncols, v32, v64, u, ldu, exact, s.segs, st, scratch, scratch_doubles); break;
+    case 802: kapply_rows_launch<8, 2>(km, nrows, ncols, v32, v64, u, ldu, exact, s.segs, st, scratch, scratch_doubles); break;
+    case 804: kapply_rows_launch<8, 4>(km, nrows, ncols, v32, v64, u, ldu, exact, s.segs, st, scratch, scratch_doubles); break;
     default: fail(KQR_EINVAL, "unsupported K-apply shape rows=%d unroll=%d", s.rows, s.unroll);
   }
 }
@@ -665,6 +675,10 @@ static void krow_p(const float* X, const float* q, int64_t n, int p, KernelSpec 
 
 void kernel_row(const KMat& km, const float* X, const float* sqn, int64_t n, int p, KernelSpec ks,
                 int64_t s, double* out, hipStream_t st) {
+  if (km.K && km.layout == 1) {
+    kernel_row_packed(km, n, s, out, st);
+    return;
+  }
   if (km.K) {
     const dim3 grid((unsigned)((n + 255) / 256));
     if (km.dtype == KQR_BF16) krow_from_mat_kernel<true><<<grid, 256, 0, st>>>(km.K, km.ld, n, s, out);

@@ -74,7 +74,8 @@ struct KernelSpec {
 struct KMat {
   const void* K = nullptr;  // nullptr: on the fly
   int dtype = KQR_FP32;
-  int64_t ld = 0;
+  int64_t ld = 0;           // layout 0: row stride; layout 1: tiles per side
+  int layout = 0;           // 0: n x ld row-major; 1: upper-triangle tiles (kpacked.hip)
 };
 
 // Tile shape of the materialised K-apply: rows per wave, 16-byte chunks per
@@ -95,8 +96,13 @@ void kbuild(const float* X, const float* sqn, int64_t n, int p, KernelSpec ks, i
 void row_sqnorms(const float* X, int64_t n, int p, float* sqn, hipStream_t st);
 
 // u = K v (materialised, rows [0, nrows), cols [0, ncols)).  exact: v64 + FP64; else v32.
+// scratch (scratch_doubles long, or null) holds the partial sums when it is
+// large enough (kapply_scratch_doubles); otherwise they are allocated on st.
 void kapply_dense(const KMat& km, int64_t nrows, int64_t ncols, const float* v32, const double* v64,
-                  double* u, int64_t ldu, bool exact, hipStream_t st, const ApplyShape* shape = nullptr);
+                  double* u, int64_t ldu, bool exact, hipStream_t st, const ApplyShape* shape = nullptr,
+                  double* scratch = nullptr, size_t scratch_doubles = 0);
+// Doubles of scratch that cover every launch shape of kapply_dense on an n x n K.
+size_t kapply_scratch_doubles(const KMat& km, int64_t n);
 // u = shift + scale K(Xr, Xc) v computed on the fly from FP32 entries.
 // exact = false: v rounded to FP32, FP32 products summed in FP32 over tiles
 // of 64 columns, FP64 across tiles; exact = true: FP64 v, products and sums.
@@ -110,6 +116,29 @@ void gemv_skinny(const float* A, int64_t lda, int64_t nrows, int64_t ncols, cons
 // One row of K: out[j] = k(x_s, x_j) in FP64 (from a materialised row or from X).
 void kernel_row(const KMat& km, const float* X, const float* sqn, int64_t n, int p, KernelSpec ks,
                 int64_t s, double* out, hipStream_t st);
+
+// Symmetric K as upper-triangle tiles (layout 1, tile side kPkT = 128).
+int64_t packed_tile_count(int64_t n);
+size_t packed_bytes(int64_t n, int dtype);
+int64_t packed_tiles_per_side(int64_t n);
+void kbuild_packed(const float* X, const float* sqn, int64_t n, int p, KernelSpec ks, int dtype, void* K,
+                   hipStream_t st);
+// Doubles of scratch kapply_packed needs (strip partials + column partials).
+size_t packed_scratch_doubles(int64_t n, int strip);
+// Launch shape of the packed K-apply: thread map (0 rows / 256 threads,
+// 1 columns, 2 rows / 512 threads) and tiles per workgroup strip.
+constexpr int kPkMaxStrip = 32;
+struct PackedShape {
+  int map = 2;
+  int strip = 4;
+};
+PackedShape default_packed_shape(int dtype, int exact);  // tuned when set, else {2, 4}
+void set_packed_shape(int dtype, int exact, PackedShape s);
+bool packed_shape_supported(const PackedShape& s);
+// u = K v with K in layout 1 (n x n); scratch may be null (then allocated on st).
+void kapply_packed(const KMat& km, int64_t n, const float* v32, const double* v64, double* u, int64_t ldu,
+                   bool exact, hipStream_t st, const PackedShape* shape = nullptr, double* scratch = nullptr);
+void kernel_row_packed(const KMat& km, int64_t n, int64_t s, double* out, hipStream_t st);
 
 // FP64 -> FP32 copy (for the fast apply), strided rows.
 void to_f32(const double* src, int64_t n, int m, int64_t lds, float* dst, int64_t ldd, hipStream_t st);

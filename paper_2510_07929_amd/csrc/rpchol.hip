@@ -158,9 +158,10 @@ __global__ __launch_bounds__(256) void rpc_update_kernel(const KMat km, const fl
   } else {
     auto kentry = [&](int64_t j) -> double {
       if (km.K) {
+        const size_t off = km.layout == 1 ? pk_offset(s, j, km.ld) : size_t(s * km.ld + j);
         if (km.dtype == KQR_BF16)
-          return double(__uint_as_float(uint32_t(static_cast<const uint16_t*>(km.K)[s * km.ld + j]) << 16));
-        return double(static_cast<const float*>(km.K)[s * km.ld + j]);
+          return double(__uint_as_float(uint32_t(static_cast<const uint16_t*>(km.K)[off]) << 16));
+        return double(static_cast<const float*>(km.K)[off]);
       }
       float dd = pair_dist_dyn(X + s * p, q ? q[s] : 0.f, X + j * p, q ? q[j] : 0.f, p, lap != 0);
       if (j == s) dd = 0.f;
@@ -188,10 +189,11 @@ __global__ void rpc_diag_kernel(const KMat km, int64_t n, double* __restrict__ d
   const int64_t j = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
   if (j >= n) return;
   if (!km.K) { d[j] = 1.0; return; }  // k(x, x) = exp(0) for both kernels
+  const size_t off = km.layout == 1 ? pk_offset(j, j, km.ld) : size_t(j * km.ld + j);
   if (km.dtype == KQR_BF16)
-    d[j] = __uint_as_float(uint32_t(static_cast<const uint16_t*>(km.K)[j * km.ld + j]) << 16);
+    d[j] = __uint_as_float(uint32_t(static_cast<const uint16_t*>(km.K)[off]) << 16);
   else
-    d[j] = static_cast<const float*>(km.K)[j * km.ld + j];
+    d[j] = static_cast<const float*>(km.K)[off];
 }
 
 std::vector<int64_t> rpcholesky(const KMat& km, const float* X, const float* sqn, int64_t n, int p, KernelSpec ks,

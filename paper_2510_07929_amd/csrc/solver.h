@@ -55,6 +55,8 @@ class Operator {
   KMat km_;
   KMat kexact_;
   DevBuf sqn_, v32_;
+  DevBuf scr_;  // partial sums of the materialised applies (allocated on first use)
+  double* scratch(const KMat& k, size_t& doubles);
   int64_t calls_ = 0;
   bool profile_ = false;
   std::vector<Span> spans_;

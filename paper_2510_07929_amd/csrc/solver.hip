@@ -53,6 +53,15 @@ void Operator::profile_totals(int64_t& nfast, double& tfast, int64_t& nexact, do
   }
 }
 
+double* Operator::scratch(const KMat& k, size_t& doubles) {
+  doubles = kapply_scratch_doubles(k, n_);
+  if (scr_.bytes < doubles * sizeof(double)) {
+    scr_ = DevBuf();
+    scr_.alloc(doubles * sizeof(double));
+  }
+  return scr_.as<double>();
+}
+
 void Operator::apply_fast(const double* v, const float* v32, double* u, hipStream_t st) {
   ++calls_;
   if (batcher_) {
@@ -64,8 +73,10 @@ void Operator::apply_fast(const double* v, const float* v32, double* u, hipStrea
       to_f32(v, n_, 1, 1, v32_.as<float>(), 1, st);
       v32 = v32_.as<float>();
     }
+    size_t nd = 0;
+    double* scr = scratch(km_, nd);
     mark(true, true, st);
-    kapply_dense(km_, n_, n_, v32, nullptr, u, 1, false, st);
+    kapply_dense(km_, n_, n_, v32, nullptr, u, 1, false, st, nullptr, scr, nd);
     mark(false, true, st);
   } else {
     mark(true, true, st);
@@ -76,11 +87,13 @@ void Operator::apply_fast(const double* v, const float* v32, double* u, hipStrea
 
 void Operator::apply_exact(const double* v, double* u, hipStream_t st) {
   ++calls_;
+  size_t nd = 0;
+  double* scr = km_.K ? scratch(km_.dtype == KQR_FP32 || !kexact_.K ? km_ : kexact_, nd) : nullptr;
   mark(true, false, st);
   if (km_.K && km_.dtype == KQR_FP32) {
-    kapply_dense(km_, n_, n_, nullptr, v, u, 1, true, st);
+    kapply_dense(km_, n_, n_, nullptr, v, u, 1, true, st, nullptr, scr, nd);
   } else if (kexact_.K) {
-    kapply_dense(kexact_, n_, n_, nullptr, v, u, 1, true, st);
+    kapply_dense(kexact_, n_, n_, nullptr, v, u, 1, true, st, nullptr, scr, nd);
   } else {
     // BF16 storage is not the exact operator: recompute FP32 entries from X.
     kapply_otf(X_, sqn_.as<float>(), n_, X_, sqn_.as<float>(), n_, p_, ks_, v, u, 1, 1.0, 0.0, st, true);

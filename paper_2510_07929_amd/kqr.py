@@ -9,6 +9,7 @@ the library has not been built, every call raises.
 from __future__ import annotations
 
 import ctypes as C
+import json
 import math
 import os
 import threading
@@ -44,7 +45,7 @@ class KqrOptions(C.Structure):
         ("k_dtype", C.c_int), ("kmode", C.c_int), ("refine", C.c_int),
         ("pivot_uniforms", C.POINTER(C.c_double)), ("seed", C.c_uint64), ("verbose", C.c_int),
         ("profile", C.c_int), ("exact_k", C.c_int), ("ssn_adapt", C.c_double),
-        ("trace", C.POINTER(C.c_double)), ("trace_cap", C.c_int),
+        ("trace", C.POINTER(C.c_double)), ("trace_cap", C.c_int), ("k_layout", C.c_int),
     ]
 
 
@@ -96,6 +97,11 @@ _SIGS = {
                                     C.POINTER(KqrOptions), _P, _P, _P, _P, _P]),
     "kqr_fit_path": (C.c_int, [_P, _P, _I64, _I64, C.c_double, _P, C.c_int, C.c_int, C.c_double,
                                C.POINTER(KqrOptions), _P, _P, _P, _P, _P]),
+    "kqr_packed_bytes": (C.c_int64, [_I64, C.c_int]),
+    "kqr_kernel_build_packed": (C.c_int, [_P, _I64, _I64, C.c_int, C.c_double, C.c_int, _P, _P]),
+    "kqr_kernel_apply_packed": (C.c_int, [_P, C.c_int, _I64, _P, _P, C.c_int, _P]),
+    "kqr_autotune_packed": (C.c_int, [_P, C.c_int, _I64, C.c_int, C.c_int, C.c_char_p, _I64, _P]),
+    "kqr_set_packed_shape": (C.c_int, [C.c_int, C.c_int, C.c_int, C.c_int]),
     "kqr_fit_batch": (C.c_int, [C.c_int, _P, _P, _P, _I64, _P, _P, C.c_int, _P, C.POINTER(KqrOptions), _P, _P, _P,
                                 _P, _P]),
     "kqr_fit_grad": (C.c_int, [_P, _P, _I64, _I64, C.c_double, C.c_double, C.c_int, C.c_double, _P, _P, _I64,
@@ -218,6 +224,49 @@ def kqr_kernel_build(X, kernel, gamma, k_dtype="fp32", K=None, stream=None):
     return K
 
 
+def kqr_packed_bytes(n, k_dtype="fp32"):
+    return int(lib().kqr_packed_bytes(int(n), _kdtype_id(k_dtype)))
+
+
+def kqr_kernel_build_packed(X, kernel, gamma, k_dtype="fp32", stream=None):
+    """Materialise K in the symmetric packed layout (upper-triangle tiles); returns a flat GPU tensor."""
+    torch = _torch()
+    n, p = X.shape
+    kd = _kdtype_id(k_dtype)
+    tdt = torch.float32 if kd == KQR_FP32 else torch.bfloat16
+    nb = kqr_packed_bytes(n, kd)
+    K = torch.empty(nb // (4 if kd == KQR_FP32 else 2), dtype=tdt, device=X.device)
+    _check(lib().kqr_kernel_build_packed(_dev(X, torch.float32, "X", 2), n, p, _kernel_id(kernel), float(gamma), kd,
+                                         _dev(K, tdt, "K", 1), _stream(stream)), "kqr_kernel_build_packed")
+    return K
+
+
+def kqr_kernel_apply_packed(v, K, n, mode=KQR_APPLY_FAST, u=None, stream=None):
+    """u = K v for K from kqr_kernel_build_packed and v (n,) float64 on the GPU."""
+    torch = _torch()
+    kd = KQR_FP32 if K.dtype == torch.float32 else KQR_BF16
+    if u is None:
+        u = torch.empty(n, dtype=torch.float64, device=v.device)
+    _check(lib().kqr_kernel_apply_packed(_dev(K, K.dtype, "K", 1), kd, int(n), _dev(v, torch.float64, "v", 1),
+                                         _dev(u, torch.float64, "u", 1), int(mode), _stream(stream)),
+           "kqr_kernel_apply_packed")
+    return u
+
+
+def kqr_autotune_packed(K, n, mode=KQR_APPLY_FAST, reps=5, stream=None):
+    """Sweep the packed K-apply shapes on K and install the fastest; returns the report dict."""
+    torch = _torch()
+    kd = KQR_FP32 if K.dtype == torch.float32 else KQR_BF16
+    buf = C.create_string_buffer(8192)
+    _check(lib().kqr_autotune_packed(_dev(K, K.dtype, "K", 1), kd, int(n), int(mode), int(reps), buf, 8192,
+                                     _stream(stream)), "kqr_autotune_packed")
+    return json.loads(buf.value.decode())
+
+
+def kqr_set_packed_shape(k_dtype, mode, map, strip):
+    _check(lib().kqr_set_packed_shape(_kdtype_id(k_dtype), int(mode), int(map), int(strip)), "kqr_set_packed_shape")
+
+
 def kqr_kernel_apply(V, X=None, kernel="rbf", gamma=1.0, K=None, mode=KQR_APPLY_FAST, U=None, stream=None):
     """U = K V for V (n,) or (n, m) float64 on the GPU; K materialised or None (on the fly)."""
     torch = _torch()
@@ -293,8 +342,6 @@ def kqr_adaptive_rank(F0, r0, xi=1e-3, stream=None):
 
 def kqr_autotune_apply(K, mode=KQR_APPLY_FAST, reps=5, stream=None):
     """Sweep the K-apply tile shapes on K (GPU, from kqr_kernel_build); returns the JSON report (dict)."""
-    import json
-
     torch = _torch()
     kd = KQR_FP32 if K.dtype == torch.float32 else KQR_BF16
     buf = C.create_string_buffer(1 << 16)

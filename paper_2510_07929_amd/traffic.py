@@ -10,7 +10,9 @@
         it reads for the copy of known size.
 
 `bench.py` reports the summary's figure as roofline.traffic when the
-summary's recorded source digest matches the current kernel source.
+summary's recorded source digest matches the current kernel source
+(`--layout rows`: the materialised section of csrc/kmat.hip; `--layout
+packed`: csrc/kpacked.hip).
 """
 from __future__ import annotations
 
@@ -24,6 +26,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SOURCE = os.path.join(HERE, "csrc", "kmat.hip")
+PACKED_SOURCE = os.path.join(HERE, "csrc", "kpacked.hip")
 
 
 SECTION_BEGIN = "// ================================================================= materialised K-apply"
@@ -31,14 +34,18 @@ SECTION_END = "// ==============================================================
 
 
 def source_digest(path: str = KERNEL_SOURCE) -> str:
-    """Digest of the materialised K-apply's source (its section of kmat.hip:
-    kernels, shape table and launcher)."""
+    """Digest of a K-apply's source: the materialised section of kmat.hip
+    (kernels, shape table and launcher), or all of kpacked.hip."""
     with open(path) as f:
         text = f.read()
     a, b = text.find(SECTION_BEGIN), text.find(SECTION_END)
     if a >= 0 and b > a:
         text = text[a:b]
     return hashlib.sha256(text.encode()).hexdigest()[:16]
+
+
+def source_for(layout: str) -> str:
+    return PACKED_SOURCE if layout == "packed" else KERNEL_SOURCE
 
 
 def copy_once(gib: float, reps: int) -> None:
@@ -109,7 +116,7 @@ def summarize(args) -> None:
         f"algorithmic bytes per dispatch: {args.algorithmic:.6g}",
         "",
         f"traffic_bytes_per_launch: {rd + wr:.6g}",
-        f"source_digest: {source_digest()}",
+        f"source_digest: {source_digest(source_for(args.layout))}",
     ]
     with open(args.out, "w") as f:
         f.write("\n".join(lines) + "\n")
@@ -150,6 +157,8 @@ def main(argv=None):
     s.add_argument("--title", default="")
     s.add_argument("--command", action="append", default=[])
     s.add_argument("--out", required=True)
+    s.add_argument("--layout", default="rows", choices=["rows", "packed"],
+                   help="which K-apply source the summary is tied to")
     args = ap.parse_args(argv)
     if args.cmd == "copy":
         copy_once(args.gib, args.reps)

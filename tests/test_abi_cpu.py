@@ -126,3 +126,14 @@ def test_valid_calls_without_device_report_no_device():
     beta = C.c_double()
     assert lib.kqr_fit(P, P, 10, 3, 0.5, 1.0, 0, 1.0, None, P, C.byref(beta), None, None) == kqr.KQR_ENODEVICE
     assert lib.kqr_predict(P, 10, 3, P, 0.0, 1.0, 0, 1.0, P, 5, P, None) == kqr.KQR_ENODEVICE
+
+
+def test_packed_layout_size():
+    # upper triangle of ceil(n/128)^2 tiles of 128 x 128 entries (host-only call)
+    lib = kqr.lib()
+    for n, kd, esz in ((1, 0, 4), (128, 0, 4), (129, 0, 4), (1000, 1, 2), (50000, 0, 4)):
+        nt = -(-n // 128)
+        assert lib.kqr_packed_bytes(n, kd) == nt * (nt + 1) // 2 * 128 * 128 * esz
+    assert lib.kqr_packed_bytes(0, 0) == -1 and lib.kqr_packed_bytes(10, 5) == -1
+    # about half of the full layout at scale
+    assert lib.kqr_packed_bytes(50000, 0) / (50000 * 50048 * 4) < 0.51
