@@ -258,6 +258,13 @@ def bench_c2(args, prob):
                                      "fit": fit16c, "speedup_vs_fp32": round(ms32 / ms16c, 3)}
     out["compare_fp32"] = {"value": round(v32, 2), "ms_per_step": round(ms32, 3), "roofline": roof32, "fit": fit32,
                            "bf16_speedup": round(ms32 / ms16, 3)}
+    if not args.no_packed:
+        # K stored once through its symmetry: BF16 tiles for the inner solves
+        # and FP32 tiles for the exact applies (22.5 + 45 GB)
+        vp, msp, roofp, fitp = run_materialised(args, prob, "bf16", not args.no_tune, layout=1, exact_k=1)
+        out["compare_packed_bf16_fp32_copy"] = {
+            "k_storage": "bf16 packed tiles (inner) + FP32 packed tiles (exact applies)", "value": round(vp, 2),
+            "ms_per_step": round(msp, 3), "roofline": roofp, "fit": fitp, "speedup_vs_fp32": round(ms32 / msp, 3)}
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(prob, args.cpu_seconds)
     return out
