@@ -48,8 +48,14 @@ enum {
   KQR_ENUMERIC = -5      /* NaN/Inf in inputs or a numerical breakdown */
 };
 
-/* kernels of Section 1 */
-enum { KQR_RBF = 0, KQR_LAPLACIAN = 1 };
+/* kernels: RBF exp(-gamma ||x - x'||_2^2) and Laplacian exp(-gamma ||x - x'||_1)
+ * (Section 1); linear x^T x' (Table 2; gamma unused, pass any positive value).
+ * The linear kernel is never materialised: K v = X (X^T v) in FP64 on the FP32
+ * entries of X, and the preconditioner factor is X itself (K = X X^T has
+ * rank <= p, so RPCholesky would return X's column space exactly after p
+ * steps).  Entry points that take a materialised K, RPCholesky and the
+ * gradient (K_EE is singular once |E| > p) reject it with KQR_EINVAL. */
+enum { KQR_RBF = 0, KQR_LAPLACIAN = 1, KQR_LINEAR = 2 };
 
 /* storage type of a materialised kernel matrix */
 enum { KQR_FP32 = 0, KQR_BF16 = 1 };

@@ -5,18 +5,19 @@ RBF  k(x, x') = exp(-gamma ||x - x'||_2^2) and
 Laplacian k(x, x') = exp(-gamma ||x - x'||_1).
 The oracle sums coordinate differences directly (never the norm expansion
 ||x||^2 + ||x'||^2 - 2 x.x'), so that it does not share a formula with the
-GPU path.
+GPU path.  The linear kernel of Table 2, k(x, x') = x^T x', is the plain
+product X X^T.
 """
 from __future__ import annotations
 
 import numpy as np
 
-KINDS = ("rbf", "laplacian")
+KINDS = ("rbf", "laplacian", "linear")
 
 
 def distance_block(Xa: np.ndarray, Xb: np.ndarray, kind: str) -> np.ndarray:
     """Squared Euclidean (rbf) or L1 (laplacian) distances, (ma, mb) float64."""
-    if kind not in KINDS:
+    if kind not in ("rbf", "laplacian"):
         raise ValueError(kind)
     Xa = np.asarray(Xa, dtype=np.float64)
     Xb = np.asarray(Xb, dtype=np.float64)
@@ -31,7 +32,10 @@ def distance_block(Xa: np.ndarray, Xb: np.ndarray, kind: str) -> np.ndarray:
 
 
 def kernel_block(Xa, Xb, kind: str, gamma: float) -> np.ndarray:
-    """K(Xa, Xb) in float64 (Section 1, the two kernels)."""
+    """K(Xa, Xb) in float64: the RBF and Laplacian kernels of Section 1, or
+    the linear kernel k(x, x') = x^T x' of Table 2 (gamma unused)."""
+    if kind == "linear":
+        return np.asarray(Xa, dtype=np.float64) @ np.asarray(Xb, dtype=np.float64).T
     return np.exp(-gamma * distance_block(Xa, Xb, kind))
 
 
@@ -100,4 +104,6 @@ class ImplicitKernel:
         return kernel_block(self.X, self.X[j : j + 1], self.kind, self.gamma)[:, 0]
 
     def diag(self) -> np.ndarray:
-        return np.ones(self.n)  # both kernels have k(x, x) = exp(0) = 1
+        if self.kind == "linear":
+            return (self.X * self.X).sum(1)
+        return np.ones(self.n)  # RBF and Laplacian have k(x, x) = exp(0) = 1

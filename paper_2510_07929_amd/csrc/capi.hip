@@ -90,8 +90,11 @@ static int guarded(Fn&& fn) {
     if (!(cond)) fail(KQR_EINVAL, __VA_ARGS__); \
   } while (0)
 
-static void check_kernel(int kernel, double gamma) {
-  KQR_REQUIRE(kernel == KQR_RBF || kernel == KQR_LAPLACIAN, "kernel must be KQR_RBF or KQR_LAPLACIAN");
+static void check_kernel(int kernel, double gamma, bool linear_ok = true) {
+  KQR_REQUIRE(kernel == KQR_RBF || kernel == KQR_LAPLACIAN || kernel == KQR_LINEAR,
+              "kernel must be KQR_RBF, KQR_LAPLACIAN or KQR_LINEAR");
+  KQR_REQUIRE(linear_ok || kernel != KQR_LINEAR,
+              "the linear kernel is used in factored form only (no materialised K, RPCholesky or gradient)");
   KQR_REQUIRE(std::isfinite(gamma) && gamma > 0.0, "gamma must be positive and finite");
 }
 
@@ -289,7 +292,7 @@ int kqr_kernel_build(const float* X, int64_t n, int64_t p, int kernel, double ga
   return guarded([&] {
     KQR_REQUIRE(X && K, "X and K must be non-null");
     KQR_REQUIRE(n >= 1 && p >= 1 && p <= 64, "need n >= 1 and 1 <= p <= 64");
-    check_kernel(kernel, gamma);
+    check_kernel(kernel, gamma, false);
     check_kmat(K, k_dtype, ldk, n);
     ensure_device();
     hipStream_t st = static_cast<hipStream_t>(stream);
@@ -327,7 +330,10 @@ int kqr_kernel_apply(const float* X, int64_t n, int64_t p, int kernel, double ga
     double* v64 = static_cast<double*>(tmp);
     float* v32 = reinterpret_cast<float*>(static_cast<char*>(tmp) + ((size_t(n) * sizeof(double) + 255) / 256) * 256);
     float* sqn = nullptr;
-    if (!K) {
+    double* lscr = nullptr;
+    if (!K && kernel == KQR_LINEAR) {
+      KQR_CHECK_HIP(hipMallocAsync(reinterpret_cast<void**>(&lscr), lin_scratch_doubles(int(p)) * sizeof(double), st));
+    } else if (!K) {
       KQR_CHECK_HIP(hipMallocAsync(reinterpret_cast<void**>(&sqn), size_t(n) * sizeof(float), st));
       row_sqnorms(X, n, int(p), sqn, st);
     }
@@ -357,11 +363,14 @@ int kqr_kernel_apply(const float* X, int64_t n, int64_t p, int kernel, double ga
           to_f32(col, n, 1, 1, v32, 1, st);
           kapply_dense(km, n, n, v32, nullptr, U + j, ldu, false, st);
         }
+      } else if (lscr) {
+        lin_apply(X, n, int(p), col, U + j, ldu, lscr, st);
       } else {
         kapply_otf(X, sqn, n, X, sqn, n, int(p), ks, col, U + j, ldu, 1.0, 0.0, st);
       }
     }
     if (sqn) KQR_CHECK_HIP(hipFreeAsync(sqn, st));
+    if (lscr) KQR_CHECK_HIP(hipFreeAsync(lscr, st));
     KQR_CHECK_HIP(hipFreeAsync(tmp, st));
   });
 }
@@ -377,7 +386,7 @@ int kqr_kernel_build_packed(const float* X, int64_t n, int64_t p, int kernel, do
     KQR_REQUIRE(X && K, "pointers must be non-null");
     KQR_REQUIRE(n >= 1 && p >= 1 && p <= 64, "need n >= 1 and 1 <= p <= 64");
     KQR_REQUIRE(k_dtype == KQR_FP32 || k_dtype == KQR_BF16, "k_dtype must be KQR_FP32 or KQR_BF16");
-    check_kernel(kernel, gamma);
+    check_kernel(kernel, gamma, false);
     ensure_device();
     hipStream_t st = static_cast<hipStream_t>(stream);
     float* sqn = nullptr;
@@ -444,6 +453,13 @@ int kqr_predict(const float* Xtrain, int64_t n, int64_t p, const double* alpha, 
     check_kernel(kernel, gamma);
     ensure_device();
     hipStream_t st = static_cast<hipStream_t>(stream);
+    if (kernel == KQR_LINEAR) {  // f = beta + Xnew (Xtrain^T alpha) / lambda
+      double* scr = nullptr;
+      KQR_CHECK_HIP(hipMallocAsync(reinterpret_cast<void**>(&scr), lin_scratch_doubles(int(p)) * sizeof(double), st));
+      lin_predict(Xtrain, n, int(p), alpha, Xnew, m, 1.0 / lambda, beta, f, scr, st);
+      KQR_CHECK_HIP(hipFreeAsync(scr, st));
+      return;
+    }
     float* sq = nullptr;
     KQR_CHECK_HIP(hipMallocAsync(reinterpret_cast<void**>(&sq), size_t(n + m) * sizeof(float), st));
     row_sqnorms(Xtrain, n, int(p), sq, st);
@@ -466,7 +482,7 @@ int kqr_rpcholesky(const float* X, int64_t n, int64_t p, int kernel, double gamm
     if (!K) {
       KQR_REQUIRE(X != nullptr, "X must be non-null when K is NULL");
       KQR_REQUIRE(p >= 1 && p <= 64, "need 1 <= p <= 64");
-      check_kernel(kernel, gamma);
+      check_kernel(kernel, gamma, false);
     }
     check_kmat(K, k_dtype, ldk, n);
     ensure_device();
@@ -746,7 +762,8 @@ int kqr_fit_batch(int nprob, const float* const* X, const double* const* y, cons
     KQR_REQUIRE(X && y && n && tau && lambda && gamma && alpha && beta && status, "pointers must be non-null");
     KQR_REQUIRE(nprob >= 1 && nprob <= 256, "need 1 <= nprob <= 256");
     KQR_REQUIRE(p >= 1 && p <= 64, "need 1 <= p <= 64");
-    KQR_REQUIRE(kernel == KQR_RBF || kernel == KQR_LAPLACIAN, "kernel must be KQR_RBF or KQR_LAPLACIAN");
+    KQR_REQUIRE(kernel == KQR_RBF || kernel == KQR_LAPLACIAN || kernel == KQR_LINEAR,
+                "kernel must be KQR_RBF, KQR_LAPLACIAN or KQR_LINEAR");
     for (int i = 0; i < nprob; ++i) {
       KQR_REQUIRE(X[i] && y[i] && alpha[i], "per-problem pointers must be non-null");
       KQR_REQUIRE(n[i] >= 2, "need n_i >= 2");
@@ -775,7 +792,7 @@ int kqr_fit_grad(const float* X, const double* y, int64_t n, int64_t p, double t
     KQR_REQUIRE(nval >= 1, "need nval >= 1");
     KQR_REQUIRE(tau > 0.0 && tau < 1.0, "need 0 < tau < 1");
     KQR_REQUIRE(std::isfinite(lambda) && lambda > 0.0, "lambda must be positive and finite");
-    check_kernel(kernel, gamma);
+    check_kernel(kernel, gamma, false);
     kqr_options o;
     kqr_default_options(&o);
     if (opt) o = *opt;

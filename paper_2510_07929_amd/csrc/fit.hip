@@ -61,6 +61,20 @@ void validate_options(const kqr_options& o) {
 
 Prepared prepare_fit(const float* X, int64_t n, int p, KernelSpec ks, const kqr_options& o, hipStream_t st) {
   Prepared pr;
+  if (ks.kind == KQR_LINEAR) {
+    // K = X X^T is applied in factored form and X is its exact factor: the
+    // preconditioner (3.2) takes F = X (rank p), or none when rank < 0
+    const double t1 = wall_seconds();
+    if (o.rank >= 0) {
+      pr.rank = p;
+      pr.ldf = std::max<int64_t>(4, (p + 3) / 4 * 4);
+      pr.F.alloc(size_t(n) * pr.ldf * sizeof(float));
+      lin_factor(X, n, p, pr.F.as<float>(), pr.ldf, st);
+    }
+    KQR_CHECK_HIP(hipStreamSynchronize(st));
+    pr.t_precond = wall_seconds() - t1;
+    return pr;
+  }
   const double t0 = wall_seconds();
   pr.dtype = o.k_dtype;
   pr.layout = o.k_layout;

@@ -66,7 +66,7 @@ void ensure_device();  // throws KQR_ENODEVICE when no device is usable
 
 // ----------------------------------------------------------------- kernel matrix ops
 struct KernelSpec {
-  int kind;      // KQR_RBF / KQR_LAPLACIAN
+  int kind;      // KQR_RBF / KQR_LAPLACIAN / KQR_LINEAR
   double gamma;
 };
 
@@ -139,6 +139,17 @@ bool packed_shape_supported(const PackedShape& s);
 void kapply_packed(const KMat& km, int64_t n, const float* v32, const double* v64, double* u, int64_t ldu,
                    bool exact, hipStream_t st, const PackedShape* shape = nullptr, double* scratch = nullptr);
 void kernel_row_packed(const KMat& km, int64_t n, int64_t s, double* out, hipStream_t st);
+
+// Linear kernel k(x, x') = x^T x' in factored form (klinear.hip).  scratch:
+// lin_scratch_doubles(p) doubles.
+size_t lin_scratch_doubles(int p);
+void lin_apply(const float* X, int64_t n, int p, const double* v, double* u, int64_t ldu, double* scratch,
+               hipStream_t st);
+// f = shift + scale * Xnew (Xtr^T alpha)
+void lin_predict(const float* Xtr, int64_t n, int p, const double* alpha, const float* Xnew, int64_t m, double scale,
+                 double shift, double* f, double* scratch, hipStream_t st);
+// F = X padded to ldf columns (the exact factor of X X^T)
+void lin_factor(const float* X, int64_t n, int p, float* F, int64_t ldf, hipStream_t st);
 
 // FP64 -> FP32 copy (for the fast apply), strided rows.
 void to_f32(const double* src, int64_t n, int m, int64_t lds, float* dst, int64_t ldd, hipStream_t st);

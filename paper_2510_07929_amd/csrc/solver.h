@@ -56,6 +56,7 @@ class Operator {
   KMat kexact_;
   DevBuf sqn_, v32_;
   DevBuf scr_;  // partial sums of the materialised applies (allocated on first use)
+  DevBuf lin_;  // linear kernel: block partials and X^T v
   double* scratch(const KMat& k, size_t& doubles);
   int64_t calls_ = 0;
   bool profile_ = false;

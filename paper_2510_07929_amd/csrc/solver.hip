@@ -17,6 +17,10 @@ namespace kqr {
 Operator::Operator(const float* X, int64_t n, int p, KernelSpec ks, KMat km, hipStream_t st)
     : X_(X), n_(n), p_(p), ks_(ks), km_(km), sqn_(size_t(std::max<int64_t>(n, 1)) * sizeof(float)),
       v32_(size_t(std::max<int64_t>(n, 1)) * sizeof(float)) {
+  if (ks.kind == KQR_LINEAR) {
+    if (km.K) fail(KQR_EINVAL, "the linear kernel is applied in factored form (no materialised K)");
+    lin_.alloc(lin_scratch_doubles(p) * sizeof(double));
+  }
   row_sqnorms(X, n, p, sqn_.as<float>(), st);
 }
 
@@ -68,6 +72,12 @@ void Operator::apply_fast(const double* v, const float* v32, double* u, hipStrea
     batcher_->submit(slot_, v, u, st);
     return;
   }
+  if (ks_.kind == KQR_LINEAR) {  // X (X^T v), FP64: the fast and the exact operator coincide
+    mark(true, true, st);
+    lin_apply(X_, n_, p_, v, u, 1, lin_.as<double>(), st);
+    mark(false, true, st);
+    return;
+  }
   if (km_.K) {
     if (!v32) {
       to_f32(v, n_, 1, 1, v32_.as<float>(), 1, st);
@@ -90,7 +100,9 @@ void Operator::apply_exact(const double* v, double* u, hipStream_t st) {
   size_t nd = 0;
   double* scr = km_.K ? scratch(km_.dtype == KQR_FP32 || !kexact_.K ? km_ : kexact_, nd) : nullptr;
   mark(true, false, st);
-  if (km_.K && km_.dtype == KQR_FP32) {
+  if (ks_.kind == KQR_LINEAR) {
+    lin_apply(X_, n_, p_, v, u, 1, lin_.as<double>(), st);
+  } else if (km_.K && km_.dtype == KQR_FP32) {
     kapply_dense(km_, n_, n_, nullptr, v, u, 1, true, st, nullptr, scr, nd);
   } else if (kexact_.K) {
     kapply_dense(kexact_, n_, n_, nullptr, v, u, 1, true, st, nullptr, scr, nd);

@@ -22,12 +22,12 @@ _lib_lock = threading.Lock()
 
 KQR_OK, KQR_NOT_CONVERGED = 0, 1
 KQR_EINVAL, KQR_ENOMEM, KQR_ENODEVICE, KQR_EHIP, KQR_ENUMERIC = -1, -2, -3, -4, -5
-KQR_RBF, KQR_LAPLACIAN = 0, 1
+KQR_RBF, KQR_LAPLACIAN, KQR_LINEAR = 0, 1, 2
 KQR_FP32, KQR_BF16 = 0, 1
 KQR_KMODE_AUTO, KQR_KMODE_MATERIALIZE, KQR_KMODE_ON_THE_FLY = 0, 1, 2
 KQR_APPLY_FAST, KQR_APPLY_EXACT, KQR_APPLY_KV = 0, 1, 2
 
-KERNELS = {"rbf": KQR_RBF, "laplacian": KQR_LAPLACIAN}
+KERNELS = {"rbf": KQR_RBF, "laplacian": KQR_LAPLACIAN, "linear": KQR_LINEAR}
 KDTYPES = {"fp32": KQR_FP32, "bf16": KQR_BF16}
 
 

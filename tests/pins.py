@@ -7,6 +7,9 @@ None of these follows the paper's algorithms:
   dual QP (1.3) has a box- and sign-consistent solution (exact, n <= 9).
 * ``slsqp_dual``: hand the dual QP (1.3) to SciPy's generic SLSQP solver.
 * ``identity_kernel_solution``: closed form when K = I.
+* ``linear_primal_qp``: the primal (1.1) with the linear kernel, i.e. linear
+  quantile regression with a ridge penalty on the slope, as a generic QP in
+  (beta, w, residual parts) for SciPy's SLSQP.
 * ``sample_quantile_interval``: the textbook set of tau-quantiles of a sample.
 """
 from __future__ import annotations
@@ -95,3 +98,34 @@ def sample_quantile_interval(y, tau):
         return ys[k - 1], ys[k]
     j = int(np.floor(k))
     return ys[j], ys[j]
+
+
+def linear_primal_qp(X, y, lam, tau):
+    """min_{beta, w} sum rho_tau(y_i - beta - x_i^T w) + lam/2 ||w||^2 as a QP:
+    y - beta - X w = up - um with up, um >= 0.  Returns (objective, beta, w)."""
+    X = np.asarray(X, dtype=np.float64)
+    n, p = X.shape
+    # variables: [beta, w (p), up (n), um (n)]
+    def fun(z):
+        w, up, um = z[1:1 + p], z[1 + p:1 + p + n], z[1 + p + n:]
+        return tau * up.sum() + (1 - tau) * um.sum() + 0.5 * lam * (w @ w)
+
+    def jac(z):
+        g = np.zeros_like(z)
+        g[1:1 + p] = lam * z[1:1 + p]
+        g[1 + p:1 + p + n] = tau
+        g[1 + p + n:] = 1 - tau
+        return g
+
+    A = np.zeros((n, 1 + p + 2 * n))
+    A[:, 0] = 1.0
+    A[:, 1:1 + p] = X
+    A[:, 1 + p:1 + p + n] = np.eye(n)
+    A[:, 1 + p + n:] = -np.eye(n)
+    cons = [dict(type="eq", fun=lambda z: A @ z - y, jac=lambda z: A)]
+    r0 = y - np.median(y)
+    z0 = np.r_[np.median(y), np.zeros(p), np.maximum(r0, 0), np.maximum(-r0, 0)]
+    bounds = [(None, None)] * (1 + p) + [(0, None)] * (2 * n)
+    res = minimize(fun, z0, jac=jac, bounds=bounds, constraints=cons, method="SLSQP",
+                   options=dict(ftol=1e-15, maxiter=5000))
+    return res.fun, res.x[0], res.x[1:1 + p]

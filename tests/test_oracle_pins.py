@@ -238,6 +238,30 @@ def test_fit_equals_generic_qp():
     assert np.abs(r.alpha - a_qp).max() < 1e-4
 
 
+@pytest.mark.parametrize("tau,lam", [(0.3, 0.5), (0.5, 5.0), (0.8, 0.05)])
+def test_linear_kernel_equals_primal_qp(tau, lam):
+    # k(x, x') = x^T x' (Table 2): the dual (1.3) solves linear quantile
+    # regression with a ridge penalty, f(x) = w^T x with w = X^T alpha / lambda
+    n = 40
+    X, y = inputs.paper2d(n, (46, int(100 * tau)))
+    Xd = X.astype(np.float64)
+    f_qp, b_qp, w_qp = pins.linear_primal_qp(Xd, y, lam, tau)
+    r = sv.fit(X, y, tau, lam, "linear", 1.0, sv.OracleOptions(tol=1e-11))
+    assert r.kkt["err"] < 1e-9
+    assert r.kkt["obj_p"] == pytest.approx(f_qp, rel=1e-7, abs=1e-8)
+    assert r.kkt["obj_p"] <= f_qp + 1e-9
+    w = Xd.T @ r.alpha / lam
+    assert np.abs(w - w_qp).max() < 1e-4 * (1 + np.abs(w_qp).max())
+
+
+def test_linear_kernel_matrix_is_gram():
+    X = np.random.default_rng(2).standard_normal((7, 3))
+    K = kn.kernel_matrix(X, "linear", 1.0)
+    assert np.array_equal(K, X @ X.T)
+    op = kn.DenseKernel(X, "linear", 1.0)
+    assert np.allclose(op.diag(), (X * X).sum(1), rtol=0, atol=1e-14)
+
+
 def test_identity_kernel_closed_form():
     # Points 100 apart with gamma = 1: exp(-1e4) underflows, K = I exactly.
     n = 40
