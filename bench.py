@@ -439,6 +439,58 @@ def bench_path(args, prob):
     return out
 
 
+def bench_linear(args, prob):
+    """The lambda sequence of Table 2's linear-kernel rows: K = X X^T applied in
+    factored form (O(n p) per apply), X as the preconditioner factor; the
+    sequence as one call against the same values as separate fits."""
+    import numpy as np
+    import torch
+
+    from paper_2510_07929_amd import kqr
+
+    dev = torch.device("cuda:0")
+    X = torch.from_numpy(prob.X).to(dev)
+    y = torch.from_numpy(prob.y).to(dev)
+    lams = prob.extras["lams"]
+    tol = prob.extras["tol"]
+    opts = dict(tol=tol, profile=1)
+
+    def path():
+        _, betas, infos, sts = kqr.kqr_fit_path(X, y, prob.tau, lams, "linear", 1.0, **opts)
+        return infos, sts
+
+    outs, elapsed = timed_fits(args, path)
+    t0 = time.perf_counter()
+    sep = [kqr.kqr_fit(X, y, prob.tau, lam, "linear", 1.0, **opts) for lam in lams]
+    torch.cuda.synchronize()
+    t_sep = time.perf_counter() - t0
+    infos, sts = outs[-1]
+    n, p = prob.n, prob.p
+    napp = sum(i["kapply_fast_calls"] for i in infos)
+    tapp = sum(i["t_kapply_fast"] for i in infos)
+    avg = tapp / max(napp, 1)
+    abytes = 2.0 * n * p * 4 + 2.0 * n * 8  # X read twice, v read, u written
+    achieved = abytes / avg / 1e9 if avg > 0 else 0.0
+    out = base_line(args, prob, "f64", {"k_storage": "none (factored X X^T)", "lambda": None, "tol": tol,
+                                        "lambdas": f"{len(lams)} values log-spaced over [{min(lams):g}, {max(lams):g}]"})
+    out.update(value=None, ms_per_step=round(elapsed / args.steps * 1e3, 3))
+    out["roofline"] = {
+        "bound": "hbm", "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 6), "traffic": None,
+        "kernel": "lin_xtv_kernel + finalize + lin_xt_kernel (X (X^T v), latency-bound at this size)",
+        "avg_launch_us": round(avg * 1e6, 2), "launches": int(napp), "bytes_per_launch": abytes,
+    }
+    out["fit"] = {"status": sts, "eta_kkt_max": max(i["eta_kkt"] for i in infos),
+                  "eta_gap_max": max(i["eta_gap"] for i in infos), "rank": infos[0]["rank_used"],
+                  "kapply_calls_total": int(np.sum([i["kapply_calls"] for i in infos])),
+                  "pcg_iters_total": int(np.sum([i["pcg_iters"] + i["admm_pcg_iters"] for i in infos])),
+                  "alm_iters": [i["alm_iters"] for i in infos], "n_interior": [i["n_interior"] for i in infos]}
+    out["compare_separate"] = {"ms_total": round(t_sep * 1e3, 3), "status": [s for _, _, _, s in sep],
+                               "joint_speedup": round(t_sep / (elapsed / args.steps), 3)}
+    out["note"] = "value is null: the linear kernel's apply is O(n p); the line reports the time of the sequence"
+    return out
+
+
 def bench_ablation(args, prob):
     """The two-phase method against each phase alone and against plain CG
     (no preconditioner), on one problem, with per-iteration traces."""
@@ -654,6 +706,8 @@ def main():
             out = bench_path(args, prob)
         elif w == "ablation":
             out = bench_ablation(args, prob)
+        elif w == "linear":
+            out = bench_linear(args, prob)
         else:
             out = bench_single(args, prob)
     print(json.dumps(out), flush=True)

@@ -117,6 +117,7 @@ WORKLOADS = {
     "c3a": (100000, "additive, n=100000, p=8, RBF gamma=1/p, 9 tau levels 0.1..0.9, lambda=1e-4 n"),
     "c4": (20000, "smooth with t(2) noise, n=20000 train + 5000 validation, p=10, RBF gamma=0.1, tau=0.5, lambda=1e-3 n"),
     "ablation": (10000, "paper2d, n=10000, p=2, RBF gamma=1e-3, tau=0.1, lambda=10, tol 1e-8"),
+    "linear": (20000, "paper2d, n=20000, p=2, linear kernel x^T x', tau=0.5, 50 lambda log-spaced over [1e-2, 1], tol 1e-8"),
     "path": (20000, "paper2d, n=20000, p=2, RBF gamma=0.1, tau=0.5, 50 lambda log-spaced over [1e-2, 1], tol 1e-8"),
 }
 
@@ -164,6 +165,10 @@ def workload(name: str, seed: int = 0, n: int | None = None) -> Problem:
     if name == "ablation":
         X, y = paper2d(n, (44, seed))
         return Problem(name, X, y, 0.1, 10.0, "rbf", 1e-3, extras={"tol": 1e-8})
+    if name == "linear":
+        X, y = paper2d(n, (47, seed))
+        lams = lambda_grid()
+        return Problem(name, X, y, 0.5, lams[0], "linear", 1.0, extras={"lams": lams, "tol": 1e-8})
     if name == "path":
         X, y = paper2d(n, (40, seed))
         lams = lambda_grid()
