@@ -205,7 +205,11 @@ int kqr_kernel_apply_packed(const void* K, int k_dtype, int64_t n, const double*
 
 /* kqr_kernel_apply: U = K(X, X) V (the operator K v of (1.2)-(3.1)).
  *  K      device matrix from kqr_kernel_build (type k_dtype, ld ldk), or NULL to
- *         compute entries on the fly from X (FP32 entries).
+ *         compute entries on the fly from X (FP32 entries; Laplacian: the L1
+ *         distance is the exact integer distance of X in 32-bit fixed point,
+ *         round((x_ik - min_k) 2^s) with s <= 23 the largest scale whose sums
+ *         fit 32 bits, one v_sad_u32 per coordinate, used when s >= 20; the
+ *         call then blocks while it reads the column ranges).
  *  V      device, n x m FP64 row-major (ld ldv >= m);  U device, n x m FP64 (ld ldu >= m).
  *  mode   KQR_APPLY_FAST or KQR_APPLY_EXACT (m == 1 only; m > 1 uses FP32 products
  *         with FP32 accumulation on the matrix cores).

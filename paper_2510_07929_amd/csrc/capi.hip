@@ -331,11 +331,17 @@ int kqr_kernel_apply(const float* X, int64_t n, int64_t p, int kernel, double ga
     float* v32 = reinterpret_cast<float*>(static_cast<char*>(tmp) + ((size_t(n) * sizeof(double) + 255) / 256) * 256);
     float* sqn = nullptr;
     double* lscr = nullptr;
+    DevBuf xq;
+    int shift = -1;
     if (!K && kernel == KQR_LINEAR) {
       KQR_CHECK_HIP(hipMallocAsync(reinterpret_cast<void**>(&lscr), lin_scratch_doubles(int(p)) * sizeof(double), st));
     } else if (!K) {
       KQR_CHECK_HIP(hipMallocAsync(reinterpret_cast<void**>(&sqn), size_t(n) * sizeof(float), st));
       row_sqnorms(X, n, int(p), sqn, st);
+      if (kernel == KQR_LAPLACIAN) {  // exact integer L1 distances of fixed-point X, as in the fits
+        xq.alloc(size_t(n) * size_t(p) * sizeof(uint32_t));
+        shift = quantize_columns(X, n, int(p), xq.as<uint32_t>(), st);
+      }
     }
     if (K && m > 1) {  // all columns in one pass over K on the matrix cores
       float* V16 = nullptr;
@@ -365,6 +371,8 @@ int kqr_kernel_apply(const float* X, int64_t n, int64_t p, int kernel, double ga
         }
       } else if (lscr) {
         lin_apply(X, n, int(p), col, U + j, ldu, lscr, st);
+      } else if (shift >= 20) {
+        kapply_otf_l1q(xq.as<uint32_t>(), n, int(p), gamma, shift, col, U + j, ldu, mode == KQR_APPLY_EXACT, st);
       } else {
         kapply_otf(X, sqn, n, X, sqn, n, int(p), ks, col, U + j, ldu, 1.0, 0.0, st);
       }

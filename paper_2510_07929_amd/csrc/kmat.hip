@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <cmath>
 #include <mutex>
+#include <vector>
 
 namespace kqr {
 
@@ -458,6 +459,185 @@ static void kapply_otf_p(const float* Xr, const float* qr, int64_t nr, const flo
   otf_reduce_kernel<<<dim3((unsigned)((nr + 255) / 256)), 256, 0, st>>>(part, int(nslice), nr, u, ldu, scale, shift);
   KQR_LAUNCH_CHECK();
   KQR_CHECK_HIP(hipFreeAsync(part, st));
+}
+
+// Laplacian on the fly from fixed-point coordinates.  Column k of X is
+// stored as q_ik = round((x_ik - min_k) 2^s) in 32 bits (computed in FP64, so
+// the only error is that rounding, at most 2^-(s+1) per coordinate), and the
+// L1 distance sum_k |q_ik - q_jk| is an exact integer formed by one
+// v_sad_u32 (|a - b| + c) per coordinate, against two FP32 operations per
+// coordinate in the float form; s is chosen so that the sum cannot exceed
+// 2^32 - 1.  The entry is exp2(-gamma log2(e) 2^-s float(d)), the rest as in
+// kapply_otf_kernel.
+__device__ __forceinline__ uint32_t sad_u32(uint32_t a, uint32_t b, uint32_t c) {
+  uint32_t r;
+  asm("v_sad_u32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+  return r;
+}
+
+template <int PMAX, int R, bool EX>
+__global__ __launch_bounds__(256) void kapply_otf_l1q_kernel(const uint32_t* __restrict__ Xq, int64_t n, int p,
+                                                             float ngs, const double* __restrict__ v,
+                                                             int64_t cols_per_slice, double* __restrict__ part) {
+  // a thread owns R rows (256 R per block), so each LDS read of x_j serves R pairs
+  static_assert(PMAX % 4 == 0, "coordinates are read from LDS four at a time");
+  __shared__ __align__(16) uint32_t xs[kOtfTile][PMAX];
+  __shared__ float vs[kOtfTile];
+  __shared__ double vd[kOtfTile];
+  const int64_t i0 = int64_t(blockIdx.x) * 256 * R + threadIdx.x;
+  uint32_t xi[R][PMAX];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int64_t i = i0 + 256 * r;
+#pragma unroll
+    for (int k = 0; k < PMAX; ++k) xi[r][k] = (i < n && k < p) ? Xq[i * p + k] : 0u;
+  }
+  const int64_t c0 = int64_t(blockIdx.y) * cols_per_slice;
+  const int64_t c1 = min(n, c0 + cols_per_slice);
+  double acc[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) acc[r] = 0.0;
+  for (int64_t jb = c0; jb < c1; jb += kOtfTile) {
+    const int cnt = int(min<int64_t>(kOtfTile, c1 - jb));
+    __syncthreads();
+    for (int t = threadIdx.x; t < kOtfTile * PMAX; t += 256) {
+      const int jj = t / PMAX, k = t % PMAX;
+      xs[jj][k] = (jj < cnt && k < p) ? Xq[(jb + jj) * p + k] : 0u;
+    }
+    if (threadIdx.x < kOtfTile) {
+      const int jj = threadIdx.x;
+      const double vj = jj < cnt ? v[jb + jj] : 0.0;
+      if (EX) vd[jj] = vj;
+      else vs[jj] = float(vj);
+    }
+    __syncthreads();
+    float a32[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) a32[r] = 0.f;
+    for (int jj = 0; jj < cnt; ++jj) {
+      uint32_t d[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) d[r] = 0u;
+      const uint4* xr = reinterpret_cast<const uint4*>(xs[jj]);  // broadcast 16-byte LDS reads
+#pragma unroll
+      for (int k4 = 0; k4 < PMAX / 4; ++k4) {
+        const uint4 c = xr[k4];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          d[r] = sad_u32(xi[r][4 * k4], c.x, d[r]);
+          d[r] = sad_u32(xi[r][4 * k4 + 1], c.y, d[r]);
+          d[r] = sad_u32(xi[r][4 * k4 + 2], c.z, d[r]);
+          d[r] = sad_u32(xi[r][4 * k4 + 3], c.w, d[r]);
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const float e = exp2f(ngs * float(d[r]));
+        if (EX) acc[r] = fma(double(e), vd[jj], acc[r]);
+        else a32[r] = fmaf(e, vs[jj], a32[r]);
+      }
+    }
+    if (!EX) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) acc[r] += double(a32[r]);
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int64_t i = i0 + 256 * r;
+    if (i < n) part[int64_t(blockIdx.y) * n + i] = acc[r];
+  }
+}
+
+template <int PMAX>
+static void kapply_otf_l1q_p(const uint32_t* Xq, int64_t n, int p, float ngs, const double* v, double* u, int64_t ldu,
+                             bool exact, hipStream_t st) {
+  // rows per thread: 4 up to 32 coordinates, 2 beyond (registers)
+  constexpr int R = PMAX <= 32 ? 4 : 2;
+  const int64_t rblk = (n + 256 * R - 1) / (256 * R);
+  int64_t nslice = std::max<int64_t>(1, std::min<int64_t>(2048 / std::max<int64_t>(rblk, 1), (n + 1023) / 1024));
+  nslice = std::min<int64_t>(nslice, 65535);
+  int64_t per = (n + nslice - 1) / nslice;
+  per = (per + kOtfTile - 1) / kOtfTile * kOtfTile;
+  nslice = (n + per - 1) / per;
+  double* part = nullptr;
+  KQR_CHECK_HIP(hipMallocAsync(reinterpret_cast<void**>(&part), size_t(nslice) * size_t(n) * sizeof(double), st));
+  const dim3 grid((unsigned)rblk, (unsigned)nslice);
+  if (exact) kapply_otf_l1q_kernel<PMAX, R, true><<<grid, 256, 0, st>>>(Xq, n, p, ngs, v, per, part);
+  else kapply_otf_l1q_kernel<PMAX, R, false><<<grid, 256, 0, st>>>(Xq, n, p, ngs, v, per, part);
+  KQR_LAUNCH_CHECK();
+  otf_reduce_kernel<<<dim3((unsigned)((n + 255) / 256)), 256, 0, st>>>(part, int(nslice), n, u, ldu, 1.0, 0.0);
+  KQR_LAUNCH_CHECK();
+  KQR_CHECK_HIP(hipFreeAsync(part, st));
+}
+
+void kapply_otf_l1q(const uint32_t* Xq, int64_t n, int p, double gamma, int shift, const double* v, double* u,
+                    int64_t ldu, bool exact, hipStream_t st) {
+  if (n <= 0) return;
+  const float ngs = float(-gamma * double(kLog2e) * std::ldexp(1.0, -shift));
+  KQR_DISPATCH_P(p, kapply_otf_l1q_p, Xq, n, p, ngs, v, u, ldu, exact, st);
+}
+
+// Per-column minimum and maximum of X (FP32 values, exact); mm: 2 p floats.
+__global__ void col_minmax_kernel(const float* __restrict__ X, int64_t n, int p, float* __restrict__ mm) {
+  const int k = blockIdx.x;
+  float lo = INFINITY, hi = -INFINITY;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+    const float x = X[i * p + k];
+    lo = fminf(lo, x);
+    hi = fmaxf(hi, x);
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    lo = fminf(lo, __shfl_xor(lo, off));
+    hi = fmaxf(hi, __shfl_xor(hi, off));
+  }
+  __shared__ float sl[4], sh[4];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) { sl[wave] = lo; sh[wave] = hi; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    mm[2 * k] = fminf(fminf(sl[0], sl[1]), fminf(sl[2], sl[3]));
+    mm[2 * k + 1] = fmaxf(fmaxf(sh[0], sh[1]), fmaxf(sh[2], sh[3]));
+  }
+}
+
+__global__ void quantize_kernel(const float* __restrict__ X, int64_t n, int p, const float* __restrict__ mm,
+                                double scale, uint32_t* __restrict__ Xq) {
+  const int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (t >= n * p) return;
+  const int k = int(t % p);
+  Xq[t] = uint32_t(llrint((double(X[t]) - double(mm[2 * k])) * scale));
+}
+
+int quantize_columns(const float* X, int64_t n, int p, uint32_t* Xq, hipStream_t st) {
+  if (n <= 0 || p <= 0) return -1;
+  float* mm = nullptr;
+  KQR_CHECK_HIP(hipMallocAsync(reinterpret_cast<void**>(&mm), size_t(2 * p) * sizeof(float), st));
+  col_minmax_kernel<<<dim3((unsigned)p), 256, 0, st>>>(X, n, p, mm);
+  KQR_LAUNCH_CHECK();
+  std::vector<float> h(size_t(2 * p));
+  KQR_CHECK_HIP(hipMemcpyAsync(h.data(), mm, h.size() * sizeof(float), hipMemcpyDeviceToHost, st));
+  KQR_CHECK_HIP(hipStreamSynchronize(st));
+  double range = 0.0;
+  for (int k = 0; k < p; ++k) {
+    const double r = double(h[size_t(2 * k + 1)]) - double(h[size_t(2 * k)]);
+    if (!std::isfinite(r)) {
+      KQR_CHECK_HIP(hipFreeAsync(mm, st));
+      return -1;
+    }
+    range = std::max(range, r);
+  }
+  // largest s <= 23 with p * range * 2^s + p <= 2^32 - 1 (sum of rounded coordinates)
+  int s = 23;
+  while (s >= 0 && double(p) * (range * std::ldexp(1.0, s) + 1.0) > 4294967295.0) --s;
+  if (s >= 0) {
+    const int64_t tot = n * p;
+    quantize_kernel<<<dim3((unsigned)((tot + 255) / 256)), 256, 0, st>>>(X, n, p, mm, std::ldexp(1.0, s), Xq);
+    KQR_LAUNCH_CHECK();
+  }
+  KQR_CHECK_HIP(hipFreeAsync(mm, st));
+  return s;
 }
 
 // RBF on the fly with the Gram term on the matrix cores: a wave owns two

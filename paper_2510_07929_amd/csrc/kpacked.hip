@@ -35,6 +35,27 @@ __device__ __forceinline__ float pk_elem(const pk_u32x4& w, int e) {
   return __uint_as_float(w[e]);
 }
 
+// Strips of `strip` tiles over tile-rows I = 0..nt-1, row I holding nt - I
+// tiles: T(M) = sum_{m=1..M} ceil(m / strip) strips over the last M rows.
+__host__ __device__ __forceinline__ int64_t pk_strips_tail(int64_t M, int64_t strip) {
+  const int64_t q = M / strip, r = M % strip;
+  return strip * q * (q + 1) / 2 + r * (q + 1);
+}
+
+// Workgroup b of the 1-D strip grid -> (tile-row I, strip k within the row):
+// rows before I hold pk_strips_tail(nt) - pk_strips_tail(nt - I) strips.
+__device__ __forceinline__ void pk_strip_coords(int64_t b, int64_t nt, int64_t strip, int64_t& I, int64_t& k) {
+  const int64_t total = pk_strips_tail(nt, strip);
+  int64_t lo = 0, hi = nt - 1;  // largest I whose first strip index is <= b
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) / 2;
+    if (total - pk_strips_tail(nt - mid, strip) <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  I = lo;
+  k = b - (total - pk_strips_tail(nt - lo, strip));
+}
+
 }  // namespace
 
 int64_t packed_tile_count(int64_t n) {
@@ -129,8 +150,8 @@ void kbuild_packed(const float* X, const float* sqn, int64_t n, int p, KernelSpe
 }
 
 // ================================================================= apply
-// Workgroup (k, I) walks the strip of tiles J = I + k*strip ... of tile-row
-// I; every off-diagonal tile feeds its rows (K_IJ v_J) and its columns
+// Workgroup b walks strip k of tile-row I (b -> (I, k) by pk_strip_coords),
+// the tiles J = I + k*strip ...; every off-diagonal tile feeds its rows (K_IJ v_J) and its columns
 // (K_IJ^T v_I).  Row sums stay in registers across the strip (the same rows
 // of every tile), column sums are written as one partial per tile.  Thread
 // mappings (tuned per dtype):
@@ -159,9 +180,9 @@ __global__ __launch_bounds__(NT) void kapply_packed_rows_kernel(const void* __re
   typedef typename std::conditional<EXACT, double, float>::type acc_t;
   __shared__ acc_t cs[2][RPS][kPkT + 1];
 
-  const int64_t I = blockIdx.y;
-  const int64_t J0 = I + int64_t(blockIdx.x) * strip;
-  if (J0 >= nt) return;
+  int64_t I, kstrip;
+  pk_strip_coords(blockIdx.x, nt, strip, I, kstrip);
+  const int64_t J0 = I + kstrip * strip;
   const int64_t J1 = std::min<int64_t>(nt, J0 + strip);
   const int tid = threadIdx.x;
   const int cl = tid % LPR, rg = tid / LPR;
@@ -236,7 +257,7 @@ __global__ __launch_bounds__(NT) void kapply_packed_rows_kernel(const void* __re
 #pragma unroll
     for (int off = LPR / 2; off >= 1; off >>= 1) racc[s] += __shfl_xor(racc[s], off);
   if (cl == 0) {
-    double* rp = rowpart + (size_t(I) * nsx + blockIdx.x) * kPkT;
+    double* rp = rowpart + (size_t(I) * nsx + kstrip) * kPkT;
 #pragma unroll
     for (int s = 0; s < STEPS; ++s) rp[rg + RPS * s] = racc[s];
   }
@@ -258,9 +279,9 @@ __global__ __launch_bounds__(256) void kapply_packed_cols_kernel(const void* __r
   typedef typename std::conditional<EXACT, double, float>::type acc_t;
   __shared__ double rs_lds[4][kPkT];
 
-  const int64_t I = blockIdx.y;
-  const int64_t J0 = I + int64_t(blockIdx.x) * strip;
-  if (J0 >= nt) return;
+  int64_t I, kstrip;
+  pk_strip_coords(blockIdx.x, nt, strip, I, kstrip);
+  const int64_t J0 = I + kstrip * strip;
   const int64_t J1 = std::min<int64_t>(nt, J0 + strip);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int c = lane % LPW, g = lane / LPW;
@@ -323,7 +344,7 @@ __global__ __launch_bounds__(256) void kapply_packed_cols_kernel(const void* __r
   __syncthreads();
   if (threadIdx.x < kPkT) {
     const int r = threadIdx.x;
-    rowpart[(size_t(I) * nsx + blockIdx.x) * kPkT + r] = ((rs_lds[0][r] + rs_lds[1][r]) + rs_lds[2][r]) + rs_lds[3][r];
+    rowpart[(size_t(I) * nsx + kstrip) * kPkT + r] = ((rs_lds[0][r] + rs_lds[1][r]) + rs_lds[2][r]) + rs_lds[3][r];
   }
 }
 
@@ -431,7 +452,7 @@ void kapply_packed(const KMat& km, int64_t n, const float* v32, const double* v6
   if (!buf) KQR_CHECK_HIP(hipMallocAsync(reinterpret_cast<void**>(&buf), need * sizeof(double), st));
   double* rowpart = buf;
   double* colpart = buf + size_t(nt) * nsx * kPkT;
-  const dim3 grid((unsigned)nsx, (unsigned)nt);
+  const dim3 grid((unsigned)pk_strips_tail(nt, strip));  // exactly the strips (no idle workgroups)
   const bool bf = km.dtype == KQR_BF16;
   if (exact && bf) packed_launch<true, true>(sh.map, grid, km.K, n, nt, strip, nsx, v32, v64, rowpart, colpart, st);
   else if (exact) packed_launch<false, true>(sh.map, grid, km.K, n, nt, strip, nsx, v32, v64, rowpart, colpart, st);

@@ -109,6 +109,14 @@ size_t kapply_scratch_doubles(const KMat& km, int64_t n);
 void kapply_otf(const float* Xr, const float* sqr, int64_t nr, const float* Xc, const float* sqc,
                 int64_t nc, int p, KernelSpec ks, const double* v64, double* u, int64_t ldu,
                 double out_scale, double out_shift, hipStream_t st, bool exact = false);
+// Laplacian on the fly from fixed-point coordinates (exact integer L1
+// distances, one v_sad_u32 per coordinate).  quantize_columns fills Xq
+// (n x p, stride p) with round((x - min_k) 2^s) and returns s (or -1 when X
+// holds non-finite values); kapply_otf_l1q applies K(X, X) with entries
+// exp(-gamma 2^-s d).
+int quantize_columns(const float* X, int64_t n, int p, uint32_t* Xq, hipStream_t st);
+void kapply_otf_l1q(const uint32_t* Xq, int64_t n, int p, double gamma, int shift, const double* v, double* u,
+                    int64_t ldu, bool exact, hipStream_t st);
 // y = A x for a skinny FP32 matrix A (nrows x ncols, ncols <= 1024, lda a
 // multiple of 4) and FP64 x, y; FP64 products and sums.
 void gemv_skinny(const float* A, int64_t lda, int64_t nrows, int64_t ncols, const double* x, double* y,

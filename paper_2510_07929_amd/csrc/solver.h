@@ -57,6 +57,8 @@ class Operator {
   DevBuf sqn_, v32_;
   DevBuf scr_;  // partial sums of the materialised applies (allocated on first use)
   DevBuf lin_;  // linear kernel: block partials and X^T v
+  DevBuf xq_;   // Laplacian: fixed-point X (entries recomputed on every apply)
+  int shift_ = -1;
   double* scratch(const KMat& k, size_t& doubles);
   int64_t calls_ = 0;
   bool profile_ = false;

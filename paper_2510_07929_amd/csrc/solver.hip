@@ -22,6 +22,17 @@ Operator::Operator(const float* X, int64_t n, int p, KernelSpec ks, KMat km, hip
     lin_.alloc(lin_scratch_doubles(p) * sizeof(double));
   }
   row_sqnorms(X, n, p, sqn_.as<float>(), st);
+  // Laplacian entries recomputed on every apply (on the fly, or the exact
+  // operator beside a BF16 K): exact integer L1 distances of fixed-point X
+  // when the quantum 2^-s keeps the entries at FP32 accuracy (s >= 20)
+  if (ks.kind == KQR_LAPLACIAN && !(km.K && km.dtype == KQR_FP32) && n > 0) {
+    xq_.alloc(size_t(n) * size_t(p) * sizeof(uint32_t));
+    shift_ = quantize_columns(X, n, p, xq_.as<uint32_t>(), st);
+    if (shift_ < 20) {
+      xq_ = DevBuf();
+      shift_ = -1;
+    }
+  }
 }
 
 Operator::~Operator() {
@@ -88,6 +99,10 @@ void Operator::apply_fast(const double* v, const float* v32, double* u, hipStrea
     mark(true, true, st);
     kapply_dense(km_, n_, n_, v32, nullptr, u, 1, false, st, nullptr, scr, nd);
     mark(false, true, st);
+  } else if (xq_.ptr) {
+    mark(true, true, st);
+    kapply_otf_l1q(xq_.as<uint32_t>(), n_, p_, ks_.gamma, shift_, v, u, 1, false, st);
+    mark(false, true, st);
   } else {
     mark(true, true, st);
     kapply_otf(X_, sqn_.as<float>(), n_, X_, sqn_.as<float>(), n_, p_, ks_, v, u, 1, 1.0, 0.0, st);
@@ -106,6 +121,8 @@ void Operator::apply_exact(const double* v, double* u, hipStream_t st) {
     kapply_dense(km_, n_, n_, nullptr, v, u, 1, true, st, nullptr, scr, nd);
   } else if (kexact_.K) {
     kapply_dense(kexact_, n_, n_, nullptr, v, u, 1, true, st, nullptr, scr, nd);
+  } else if (xq_.ptr) {
+    kapply_otf_l1q(xq_.as<uint32_t>(), n_, p_, ks_.gamma, shift_, v, u, 1, true, st);
   } else {
     // BF16 storage is not the exact operator: recompute FP32 entries from X.
     kapply_otf(X_, sqn_.as<float>(), n_, X_, sqn_.as<float>(), n_, p_, ks_, v, u, 1, 1.0, 0.0, st, true);
