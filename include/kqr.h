@@ -211,8 +211,10 @@ int kqr_kernel_apply_packed(const void* K, int k_dtype, int64_t n, const double*
  *         fit 32 bits, one v_sad_u32 per coordinate, used when s >= 20; the
  *         call then blocks while it reads the column ranges).
  *  V      device, n x m FP64 row-major (ld ldv >= m);  U device, n x m FP64 (ld ldu >= m).
- *  mode   KQR_APPLY_FAST or KQR_APPLY_EXACT (m == 1 only; m > 1 uses FP32 products
- *         with FP32 accumulation on the matrix cores).
+ *  mode   KQR_APPLY_FAST or KQR_APPLY_EXACT.  m > 1: FAST uses FP32 products with
+ *         FP32 accumulation on the matrix cores; EXACT with an FP32 K and m <= 4
+ *         forms all columns in FP64 (vectors, products, sums) from one pass over
+ *         K; otherwise column by column.
  *  Needs 1 <= m <= 16.  Asynchronous on `stream`; uses an internal device
  *  workspace (allocated on first use, reused after). */
 int kqr_kernel_apply(const float* X, int64_t n, int64_t p, int kernel, double gamma,

@@ -343,6 +343,34 @@ int kqr_kernel_apply(const float* X, int64_t n, int64_t p, int kernel, double ga
         shift = quantize_columns(X, n, int(p), xq.as<uint32_t>(), st);
       }
     }
+    if (K && m > 1 && mode == KQR_APPLY_EXACT && k_dtype == KQR_FP32 && m <= kKvMaxExact) {
+      // exact columns (FP64 vectors, products and sums) from one pass over K
+      double* cols = nullptr;
+      double* part = nullptr;
+      KQR_CHECK_HIP(hipMallocAsync(reinterpret_cast<void**>(&cols), size_t(2 * m) * size_t(n) * sizeof(double), st));
+      KQR_CHECK_HIP(
+          hipMallocAsync(reinterpret_cast<void**>(&part), kv_scratch_doubles(n) * sizeof(double), st));
+      float* V16 = nullptr;  // no fast columns: zeros for the matrix-core half of the pass
+      KQR_CHECK_HIP(hipMallocAsync(reinterpret_cast<void**>(&V16), size_t(n) * 16 * sizeof(float), st));
+      KQR_CHECK_HIP(hipMemsetAsync(V16, 0, size_t(n) * 16 * sizeof(float), st));
+      SrcTable16 xs{};
+      DstTable16 xd{};
+      for (int64_t j = 0; j < m; ++j) {
+        double* cj = cols + size_t(j) * size_t(n);
+        KQR_CHECK_HIP(hipMemcpy2DAsync(cj, sizeof(double), V + j, size_t(ldv) * sizeof(double), sizeof(double),
+                                       size_t(n), hipMemcpyDeviceToDevice, st));
+        xs.p[j] = cj;
+        xd.p[j] = cols + size_t(m + j) * size_t(n);
+      }
+      kapply_kv_mixed(km, n, V16, 0, nullptr, 16, xs, int(m), xd, part, st);
+      for (int64_t j = 0; j < m; ++j)
+        KQR_CHECK_HIP(hipMemcpy2DAsync(U + j, size_t(ldu) * sizeof(double), xd.p[j], sizeof(double), sizeof(double),
+                                       size_t(n), hipMemcpyDeviceToDevice, st));
+      KQR_CHECK_HIP(hipFreeAsync(V16, st));
+      KQR_CHECK_HIP(hipFreeAsync(part, st));
+      KQR_CHECK_HIP(hipFreeAsync(cols, st));
+      m = 0;  // done
+    }
     if (K && m > 1) {  // all columns in one pass over K on the matrix cores
       float* V16 = nullptr;
       double* part = nullptr;

@@ -179,10 +179,10 @@ class RendezvousBatcher : public ApplyBatcher {
     (void)hipEventDestroy(done_);
     (void)hipStreamDestroy(bst_);
   }
-  void submit(int slot, const double* v, double* out, hipStream_t st) override {
+  void submit(int slot, const double* v, double* out, hipStream_t st, bool exact) override {
     std::unique_lock<std::mutex> lk(mu_);
     KQR_CHECK_HIP(hipEventRecord(ready_[size_t(slot)], st));
-    req_[size_t(slot)] = Req{v, out, true};
+    req_[size_t(slot)] = Req{v, out, true, exact};
     ++pending_;
     const uint64_t my_gen = gen_;
     if (pending_ == active_) {
@@ -223,6 +223,7 @@ class RendezvousBatcher : public ApplyBatcher {
     const double* v;
     double* out;
     bool live;
+    bool exact;
   };
   virtual void launch(const std::vector<int>& slots, hipStream_t st) = 0;
   std::vector<Req> req_;
@@ -274,25 +275,52 @@ class RendezvousBatcher : public ApplyBatcher {
 };
 
 // Shared K: gather the requests into V (n x 16 FP32), one K V launch, scatter.
+// With an FP32 K, requests for the exact operator (up to kKvMaxExact per
+// launch) are served by the same pass over K in FP64.
 class KvBatcher : public RendezvousBatcher {
  public:
   KvBatcher(int slots, KMat km, int64_t n, bool profile)
       : RendezvousBatcher(slots, profile), km_(km), n_(n), npad_(std::max<int64_t>(km.ld, n)),
         V_(size_t(npad_) * 16 * sizeof(float)), U_(size_t(n) * 16 * sizeof(double)),
         part_(kv_scratch_doubles(n) * sizeof(double)) {}
+  bool exact_ok() const override { return km_.dtype == KQR_FP32 && km_.layout == 0; }
 
  protected:
   void launch(const std::vector<int>& slots, hipStream_t st) override {
-    const int m = int(slots.size());
-    SrcTable16 src{};
-    DstTable16 dst{};
-    for (int j = 0; j < m; ++j) {
-      src.p[j] = req_[size_t(slots[size_t(j)])].v;
-      dst.p[j] = req_[size_t(slots[size_t(j)])].out;
+    SrcTable16 src{}, xsrc{};
+    DstTable16 dst{}, xdst{};
+    int m = 0;
+    std::vector<int> ex;
+    for (int s : slots) {
+      const Req& r = req_[size_t(s)];
+      if (r.exact) {
+        ex.push_back(s);
+      } else {
+        src.p[m] = r.v;
+        dst.p[m] = r.out;
+        ++m;
+      }
     }
-    kv_gather(src, m, n_, npad_, V_.as<float>(), st);
-    kapply_kv(km_, n_, V_.as<float>(), m, U_.as<double>(), 16, part_.as<double>(), st);
-    kv_scatter(U_.as<double>(), m, n_, dst, st);
+    if (m > 0) kv_gather(src, m, n_, npad_, V_.as<float>(), st);
+    size_t e = 0;
+    if (ex.empty()) {
+      kapply_kv(km_, n_, V_.as<float>(), m, U_.as<double>(), 16, part_.as<double>(), st);
+    } else {
+      // the fast columns with the first exact ones, then any further exact ones
+      bool first = true;
+      while (e < ex.size()) {
+        const int mx = int(std::min<size_t>(kKvMaxExact, ex.size() - e));
+        for (int j = 0; j < mx; ++j) {
+          xsrc.p[j] = req_[size_t(ex[e + size_t(j)])].v;
+          xdst.p[j] = req_[size_t(ex[e + size_t(j)])].out;
+        }
+        kapply_kv_mixed(km_, n_, V_.as<float>(), first ? m : 0, U_.as<double>(), 16, xsrc, mx, xdst,
+                        part_.as<double>(), st);
+        first = false;
+        e += size_t(mx);
+      }
+    }
+    if (m > 0) kv_scatter(U_.as<double>(), m, n_, dst, st);
   }
 
  private:

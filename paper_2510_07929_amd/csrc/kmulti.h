@@ -11,6 +11,7 @@ namespace kqr {
 // without the next step's loads issued ahead; column segments.
 constexpr int kKvMaxSegs = 8;
 constexpr int kKvMaxCols = 16;  // right-hand sides of one K V launch
+constexpr int kKvMaxExact = 4;  // exact (FP64) columns that ride along in one launch
 constexpr int kKvBuckets = 8;
 struct KvShape {
   int nld = 0;
@@ -21,9 +22,12 @@ KvShape default_kv_shape(int dtype, int64_t n);        // autotuned when set, el
 void set_kv_shape(int dtype, int64_t n, KvShape s);    // autotuner override (per dtype and size bucket)
 bool kv_shape_supported(const KvShape& s);
 
-// Doubles of scratch kapply_kv needs for n rows: the segment partials and,
-// past them, the BF16 hi + lo parts of V (n x 32 halves).
-inline size_t kv_scratch_doubles(int64_t n) { return (size_t(kKvMaxSegs) + 1) * size_t(n) * 16; }
+// Doubles of scratch kapply_kv / kapply_kv_mixed need for n rows: the segment
+// partials and, past them, the BF16 hi + lo parts of V (n x 32 halves); then
+// the exact columns' segment partials and their FP64 copy (n x 4).
+inline size_t kv_scratch_doubles(int64_t n) {
+  return (size_t(kKvMaxSegs) + 1) * size_t(n) * 16 + (size_t(kKvMaxSegs) + 1) * size_t(n) * 4;
+}
 
 // U[:, j] = K V[:, j] for j < m <= 16.  V16: n_pad x 16 FP32 row-major (rows >= n
 // and columns >= m zero); U: n x m FP64 (ld ldu); part: scratch of
@@ -36,6 +40,11 @@ struct SrcTable16 {
 struct DstTable16 {
   double* p[16];
 };
+// U[:, j] = K V16[:, j] (j < m, as kapply_kv, m may be 0) and, from the same
+// pass over K, dst.p[j] = K src.p[j] for j < mx <= 4 with FP64 vectors,
+// products and sums (the exact operator).  K: FP32, full layout.
+void kapply_kv_mixed(const KMat& km, int64_t n, const float* V16, int m, double* U, int64_t ldu, SrcTable16 xsrc,
+                     int mx, DstTable16 xdst, double* part, hipStream_t st);
 // V16[i][j] = float(src.p[j][i]) for j < m, zero elsewhere (rows up to n_pad)
 void kv_gather(SrcTable16 src, int m, int64_t n, int64_t n_pad, float* V16, hipStream_t st);
 // V16[i][j] = float(V[i ldv + j]) for j < m, zero elsewhere

@@ -159,11 +159,18 @@ __global__ __launch_bounds__(256) void kv_mfma_kernel(const void* __restrict__ K
 // tile is loaded into registers while the current one is multiplied.  Lane
 // group g of a strip takes the columns [g C/4, (g+1) C/4) of the stage, so
 // every lane reads contiguous 16-byte pieces of K and V from LDS.
-template <bool BF16>
+// With MX = 4 (FP32 K only) the same staged tile also serves up to four exact
+// columns: thread t forms, for rows 4 (t/16) .. +3 of the tile and the
+// columns [8 (t%16), 8 (t%16) + 8) of the stage, FP64 products of the FP32
+// entries with FP64 Vx (n x 4) and FP64 sums (the exact operator), so exact
+// applies cost no extra pass over K.
+template <bool BF16, int MX>
 __global__ __launch_bounds__(256) void kv_staged_kernel(const void* __restrict__ K, int64_t ldk, int64_t n,
                                                         int64_t ncols, const float* __restrict__ V,
                                                         const uint16_t* __restrict__ Vhl, int64_t seg_cols,
-                                                        double* __restrict__ out) {
+                                                        double* __restrict__ out, const double* __restrict__ Vx,
+                                                        double* __restrict__ outx) {
+  static_assert(MX == 0 || (MX == 4 && !BF16), "exact columns ride on FP32 stages only");
   constexpr int COLS = BF16 ? 256 : 128;   // columns per stage
   constexpr int PER = BF16 ? 8 : 4;        // entries per 16 bytes
   constexpr int ESZ = BF16 ? 2 : 4;
@@ -173,6 +180,9 @@ __global__ __launch_bounds__(256) void kv_staged_kernel(const void* __restrict__
   __shared__ __attribute__((aligned(16))) float vs[BF16 ? 1 : 16][BF16 ? 4 : COLS + 4];
   __shared__ __attribute__((aligned(16))) uint16_t vh[BF16 ? 16 : 1][BF16 ? COLS + 8 : 8];
   __shared__ __attribute__((aligned(16))) uint16_t vl[BF16 ? 16 : 1][BF16 ? COLS + 8 : 8];
+  // exact columns transposed, 8 columns per 16-lane slice padded to 10 (the
+  // 16 lanes' 16-byte reads then start on distinct banks)
+  __shared__ __attribute__((aligned(16))) double vxs[MX > 0 ? MX : 1][MX > 0 ? 16 * 10 : 2];
   const int t = threadIdx.x;
   const int lane = t & 63, wave = t >> 6;
   const int li = lane & 15, lg = lane >> 4;
@@ -209,6 +219,11 @@ __global__ __launch_bounds__(256) void kv_staged_kernel(const void* __restrict__
     }
   };
   double acc64[4] = {0.0, 0.0, 0.0, 0.0};
+  double accx[4][MX > 0 ? MX : 1];
+#pragma unroll
+  for (int rr = 0; rr < 4; ++rr)
+#pragma unroll
+    for (int j = 0; j < (MX > 0 ? MX : 1); ++j) accx[rr][j] = 0.0;
   u32x4 pre[8];
   if (c0 < c1) load_stage(c0, pre);
   const int srow = 16 * wave + li;  // this lane's row in the tile (MFMA A operand)
@@ -227,8 +242,38 @@ __global__ __launch_bounds__(256) void kv_staged_kernel(const void* __restrict__
         vs[j][kk] = kk < cnt ? V[(cb + kk) * 16 + j] : 0.f;
       }
     }
+    if (MX > 0) {
+      for (int e = t; e < COLS * MX; e += 256) {
+        const int kk = e / (MX > 0 ? MX : 1), j = e % (MX > 0 ? MX : 1);
+        vxs[j][(kk >> 3) * 10 + (kk & 7)] = kk < cnt ? Vx[(cb + kk) * MX + j] : 0.0;
+      }
+    }
     __syncthreads();
     if (cb + COLS < c1) load_stage(cb + COLS, pre);
+    if (MX > 0) {  // exact columns: rows 4 (t/16) .. +3, columns [8 (t%16), 8 (t%16) + 8) of the stage
+      const int xg = t >> 4, xs = t & 15;
+      f32x4 kq[4][2];  // this thread's 4 x 8 block of the staged K
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) {
+        const float* krow = reinterpret_cast<const float*>(ks) + (4 * xg + rr) * KPAD + xs * 8;
+        kq[rr][0] = *reinterpret_cast<const f32x4*>(krow);
+        kq[rr][1] = *reinterpret_cast<const f32x4*>(krow + 4);
+      }
+#pragma unroll
+      for (int j = 0; j < (MX > 0 ? MX : 1); ++j) {
+        double vx[8];
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+          const double2 w = *reinterpret_cast<const double2*>(&vxs[j][xs * 10 + 2 * h]);
+          vx[2 * h] = w.x;
+          vx[2 * h + 1] = w.y;
+        }
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr)
+#pragma unroll
+          for (int e = 0; e < 8; ++e) accx[rr][j] = fma(double(kq[rr][e >> 2][e & 3]), vx[e], accx[rr][j]);
+      }
+    }
     f32x4 accA = {0.f, 0.f, 0.f, 0.f}, accB = {0.f, 0.f, 0.f, 0.f};
     if (BF16) {
       const uint16_t* arow = reinterpret_cast<const uint16_t*>(ks) + srow * KPAD + lg * QCOL;
@@ -261,6 +306,44 @@ __global__ __launch_bounds__(256) void kv_staged_kernel(const void* __restrict__
     const int64_t row = row0 + 4 * lg + r;
     if (row < n) out[(int64_t(blockIdx.y) * n + row) * 16 + li] = acc64[r];
   }
+  if (MX > 0) {  // the 16 column slices of a row group sit in adjacent lanes
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr)
+#pragma unroll
+      for (int j = 0; j < (MX > 0 ? MX : 1); ++j)
+#pragma unroll
+        for (int off = 1; off < 16; off <<= 1) accx[rr][j] += __shfl_xor(accx[rr][j], off);
+    if ((t & 15) == 0) {
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) {
+        const int64_t row = row_base + 4 * (t >> 4) + rr;
+        if (row < n) {
+#pragma unroll
+          for (int j = 0; j < (MX > 0 ? MX : 1); ++j) outx[(int64_t(blockIdx.y) * n + row) * MX + j] = accx[rr][j];
+        }
+      }
+    }
+  }
+}
+
+__global__ void kv_reduce_x_kernel(const double* __restrict__ part, int nseg, int64_t n, int mx, DstTable16 dst) {
+  const int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (t >= n * 4) return;
+  const int64_t i = t >> 2;
+  const int j = int(t & 3);
+  if (j >= mx) return;
+  double s = 0.0;
+  for (int k = 0; k < nseg; ++k) s += part[int64_t(k) * n * 4 + t];
+  dst.p[j][i] = s;
+}
+
+// Vx[i][j] = src.p[j][i] for j < mx, 0 for mx <= j < 4
+__global__ void kv_gather_x_kernel(SrcTable16 src, int mx, int64_t n, double* __restrict__ Vx) {
+  const int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (t >= n * 4) return;
+  const int64_t i = t >> 2;
+  const int j = int(t & 3);
+  Vx[t] = j < mx ? src.p[j][i] : 0.0;
 }
 
 // Vhl[i][j] = bf16(V[i][j]), Vhl[i][16 + j] = bf16(V[i][j] - that) (round to nearest even)
@@ -300,7 +383,7 @@ template <bool BF16>
 void kv_launch(const KvShape& s, dim3 grid, const KMat& km, int64_t n, const float* V16, const uint16_t* Vhl,
                int64_t seg_cols, double* part, hipStream_t st) {
   if (s.nld == 0)
-    kv_staged_kernel<BF16><<<grid, 256, 0, st>>>(km.K, km.ld, n, n, V16, Vhl, seg_cols, part);
+    kv_staged_kernel<BF16, 0><<<grid, 256, 0, st>>>(km.K, km.ld, n, n, V16, Vhl, seg_cols, part, nullptr, nullptr);
   else if (s.nld == 4 && s.prefetch)
     kv_mfma_kernel<BF16, 4, true><<<grid, 256, 0, st>>>(km.K, km.ld, n, n, V16, seg_cols, part);
   else if (s.nld == 4)
@@ -353,6 +436,33 @@ void kapply_kv(const KMat& km, int64_t n, const float* V16, int m, double* U, in
   }
   KQR_LAUNCH_CHECK();
   kv_reduce_kernel<<<dim3((unsigned)((n * 16 + 255) / 256)), 256, 0, st>>>(part, segs, n, m, U, ldu);
+  KQR_LAUNCH_CHECK();
+}
+
+void kapply_kv_mixed(const KMat& km, int64_t n, const float* V16, int m, double* U, int64_t ldu, SrcTable16 xsrc,
+                     int mx, DstTable16 xdst, double* part, hipStream_t st) {
+  if (n <= 0) return;
+  if (km.dtype != KQR_FP32 || km.layout != 0 || mx < 1 || mx > kKvMaxExact)
+    fail(KQR_EINVAL, "exact columns need an FP32 K in the full layout and 1..%d of them", kKvMaxExact);
+  int segs = default_kv_shape(km.dtype, n).segs;
+  int64_t seg_cols = (n + segs - 1) / segs;
+  seg_cols = (seg_cols + kKC - 1) / kKC * kKC;
+  segs = int((n + seg_cols - 1) / seg_cols);
+  // scratch: [segment partials 16 n][BF16 V parts 16 n] per kv_scratch_doubles, then
+  // [exact partials kKvMaxSegs 4 n][Vx 4 n]
+  double* partx = part + (size_t(kKvMaxSegs) + 1) * size_t(n) * 16;
+  double* Vx = partx + size_t(kKvMaxSegs) * size_t(n) * 4;
+  kv_gather_x_kernel<<<dim3((unsigned)((n * 4 + 255) / 256)), 256, 0, st>>>(xsrc, mx, n, Vx);
+  KQR_LAUNCH_CHECK();
+  const dim3 grid((unsigned)((n + 63) / 64), (unsigned)segs);
+  kv_staged_kernel<false, kKvMaxExact><<<grid, 256, 0, st>>>(km.K, km.ld, n, n, V16, nullptr, seg_cols, part, Vx,
+                                                               partx);
+  KQR_LAUNCH_CHECK();
+  if (m > 0) {
+    kv_reduce_kernel<<<dim3((unsigned)((n * 16 + 255) / 256)), 256, 0, st>>>(part, segs, n, m, U, ldu);
+    KQR_LAUNCH_CHECK();
+  }
+  kv_reduce_x_kernel<<<dim3((unsigned)((n * 4 + 255) / 256)), 256, 0, st>>>(partx, segs, n, mx, xdst);
   KQR_LAUNCH_CHECK();
 }
 

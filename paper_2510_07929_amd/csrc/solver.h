@@ -13,8 +13,11 @@ namespace kqr {
 class ApplyBatcher {
  public:
   virtual ~ApplyBatcher() = default;
-  virtual void submit(int slot, const double* v, double* out, hipStream_t st) = 0;
+  // exact: the request wants the exact operator (FP64 vector, products and
+  // sums); only when exact_ok().
+  virtual void submit(int slot, const double* v, double* out, hipStream_t st, bool exact) = 0;
   virtual void leave(int slot) = 0;
+  virtual bool exact_ok() const { return false; }
 };
 
 // The kernel operator K v: materialised (FP32 / BF16 storage) or on the fly.

@@ -80,7 +80,7 @@ double* Operator::scratch(const KMat& k, size_t& doubles) {
 void Operator::apply_fast(const double* v, const float* v32, double* u, hipStream_t st) {
   ++calls_;
   if (batcher_) {
-    batcher_->submit(slot_, v, u, st);
+    batcher_->submit(slot_, v, u, st, false);
     return;
   }
   if (ks_.kind == KQR_LINEAR) {  // X (X^T v), FP64: the fast and the exact operator coincide
@@ -112,6 +112,10 @@ void Operator::apply_fast(const double* v, const float* v32, double* u, hipStrea
 
 void Operator::apply_exact(const double* v, double* u, hipStream_t st) {
   ++calls_;
+  if (batcher_ && batcher_->exact_ok()) {  // rides along in the shared pass over K
+    batcher_->submit(slot_, v, u, st, true);
+    return;
+  }
   size_t nd = 0;
   double* scr = km_.K ? scratch(km_.dtype == KQR_FP32 || !kexact_.K ? km_ : kexact_, nd) : nullptr;
   mark(true, false, st);

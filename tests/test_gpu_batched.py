@@ -99,6 +99,30 @@ def test_kv_every_launch_shape_and_autotuner(dev, kd):
         kqr.kqr_set_kv_shape(kd, n, 6, 0, 1)
 
 
+@pytest.mark.parametrize("n,m", [(3001, 4), (700, 2), (129, 3)])
+def test_exact_multi_column_apply(dev, n, m):
+    # exact columns from one pass over an FP32 K (the path the joint fits use
+    # for their exact applies) against column-by-column exact applies and the
+    # oracle: FP64 products of the same FP32 entries, so only summation order
+    # separates the two GPU forms
+    p = 8
+    X, _ = inputs.additive(n, p, (131, n))
+    gamma = 1.0 / p
+    V = np.random.default_rng(m).standard_normal((n, m))
+    say("exact multi-column", n, m)
+    K = kqr.kqr_kernel_build(torch.from_numpy(X).to(dev), "rbf", gamma, "fp32")
+    Vt = torch.from_numpy(V).to(dev)
+    U = kqr.kqr_kernel_apply(Vt, K=K, mode=kqr.KQR_APPLY_EXACT).cpu().numpy()
+    cols = np.stack([kqr.kqr_kernel_apply(Vt[:, j].contiguous(), K=K, mode=kqr.KQR_APPLY_EXACT).cpu().numpy().ravel()
+                     for j in range(m)], axis=1)
+    Kf = K.cpu().numpy().astype(np.float64)[:, :n]
+    scale = np.abs(Kf) @ np.abs(V)
+    assert np.all(np.abs(U - cols) <= 1e-13 * scale)
+    assert np.all(np.abs(U - Kf @ V) <= 1e-13 * scale)
+    Kref, Kb = entry_bound(X, gamma)
+    assert np.all(np.abs(U - Kref @ V) <= Kb @ np.abs(V) + 1e-13 * scale)
+
+
 def _oracle_obj(prob, tau, alpha, beta):
     K = okernel.kernel_matrix(prob.X, prob.kernel, prob.gamma)
     Ka = K @ alpha
