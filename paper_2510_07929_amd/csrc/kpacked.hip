@@ -171,7 +171,7 @@ __global__ __launch_bounds__(NT) void kapply_packed_rows_kernel(const void* __re
                                                                 int strip, int64_t nsx, const float* __restrict__ v32,
                                                                 const double* __restrict__ v64,
                                                                 double* __restrict__ rowpart,
-                                                                double* __restrict__ colpart) {
+                                                                double* __restrict__ colpart, int64_t nstrips) {
   constexpr int VEC = BF16 ? 8 : 4;     // entries per 16-byte load
   constexpr int LPR = kPkT / VEC;       // lanes per tile row (32 or 16)
   constexpr int RPS = NT / LPR;         // rows per step
@@ -180,8 +180,10 @@ __global__ __launch_bounds__(NT) void kapply_packed_rows_kernel(const void* __re
   typedef typename std::conditional<EXACT, double, float>::type acc_t;
   __shared__ acc_t cs[2][RPS][kPkT + 1];
 
+  // one strip per workgroup, or (persistent launch) strips b, b + gridDim.x, ...
+  for (int64_t sb = blockIdx.x; sb < nstrips; sb += gridDim.x) {
   int64_t I, kstrip;
-  pk_strip_coords(blockIdx.x, nt, strip, I, kstrip);
+  pk_strip_coords(sb, nt, strip, I, kstrip);
   const int64_t J0 = I + kstrip * strip;
   const int64_t J1 = std::min<int64_t>(nt, J0 + strip);
   const int tid = threadIdx.x;
@@ -260,6 +262,8 @@ __global__ __launch_bounds__(NT) void kapply_packed_rows_kernel(const void* __re
     double* rp = rowpart + (size_t(I) * nsx + kstrip) * kPkT;
 #pragma unroll
     for (int s = 0; s < STEPS; ++s) rp[rg + RPS * s] = racc[s];
+  }
+  __syncthreads();  // LDS of this strip read by every thread before the next strip writes it
   }
 }
 
@@ -404,12 +408,15 @@ bool g_pk_set[2][2] = {};
 template <bool BF16, bool EXACT>
 void packed_launch(int map, dim3 grid, const void* K, int64_t n, int64_t nt, int strip, int64_t nsx, const float* v32,
                    const double* v64, double* rowpart, double* colpart, hipStream_t st) {
-  // map 2 with BF16 entries and FP64 sums would stage 66 KB of column sums
-  // in LDS; it runs as map 0
+  // maps 2 and 3 with BF16 entries and FP64 sums would stage 66 KB of column
+  // sums in LDS; they run as map 0
+  const int64_t nstrips = grid.x;
   if constexpr (!(BF16 && EXACT)) {
-    if (map == 2) {
-      kapply_packed_rows_kernel<BF16, EXACT, 512><<<grid, 512, 0, st>>>(K, n, nt, strip, nsx, v32, v64, rowpart,
-                                                                         colpart);
+    if (map == 2 || map == 3) {
+      // map 3: persistent, four workgroups per CU walk the strips
+      const dim3 g(map == 3 ? unsigned(std::min<int64_t>(nstrips, 1024)) : grid.x);
+      kapply_packed_rows_kernel<BF16, EXACT, 512><<<g, 512, 0, st>>>(K, n, nt, strip, nsx, v32, v64, rowpart, colpart,
+                                                                      nstrips);
       return;
     }
   }
@@ -417,7 +424,7 @@ void packed_launch(int map, dim3 grid, const void* K, int64_t n, int64_t nt, int
     kapply_packed_cols_kernel<BF16, EXACT><<<grid, 256, 0, st>>>(K, n, nt, strip, nsx, v32, v64, rowpart, colpart);
   else
     kapply_packed_rows_kernel<BF16, EXACT, 256><<<grid, 256, 0, st>>>(K, n, nt, strip, nsx, v32, v64, rowpart,
-                                                                       colpart);
+                                                                       colpart, nstrips);
 }
 }  // namespace
 
@@ -425,7 +432,9 @@ PackedShape default_packed_shape(int dtype, int exact) {
   std::lock_guard<std::mutex> lk(g_pk_mu);
   const int d = dtype == KQR_BF16, e = exact != 0;
   if (g_pk_set[d][e]) return g_pk_shape[d][e];
-  return PackedShape{2, 4};  // fastest on the c1 shape (n = 50,000, FP32) when swept
+  // fastest when swept on the c1 shape (n = 50,000): FP32 map 2 / strip 4
+  // (873 us), BF16 map 0 / strip 8 (524 us)
+  return d ? PackedShape{0, 8} : PackedShape{2, 4};
 }
 
 void set_packed_shape(int dtype, int exact, PackedShape s) {
@@ -436,7 +445,7 @@ void set_packed_shape(int dtype, int exact, PackedShape s) {
 }
 
 bool packed_shape_supported(const PackedShape& s) {
-  return s.map >= 0 && s.map <= 2 && s.strip >= 1 && s.strip <= kPkMaxStrip;
+  return s.map >= 0 && s.map <= 3 && s.strip >= 1 && s.strip <= kPkMaxStrip;
 }
 
 void kapply_packed(const KMat& km, int64_t n, const float* v32, const double* v64, double* u, int64_t ldu,

@@ -134,13 +134,14 @@ void kbuild_packed(const float* X, const float* sqn, int64_t n, int p, KernelSpe
 // Doubles of scratch kapply_packed needs (strip partials + column partials).
 size_t packed_scratch_doubles(int64_t n, int strip);
 // Launch shape of the packed K-apply: thread map (0 rows / 256 threads,
-// 1 columns, 2 rows / 512 threads) and tiles per workgroup strip.
+// 1 columns, 2 rows / 512 threads, 3 = 2 on a persistent grid) and tiles per
+// workgroup strip.
 constexpr int kPkMaxStrip = 32;
 struct PackedShape {
   int map = 2;
   int strip = 4;
 };
-PackedShape default_packed_shape(int dtype, int exact);  // tuned when set, else {2, 4}
+PackedShape default_packed_shape(int dtype, int exact);  // tuned when set, else FP32 {2, 4}, BF16 {0, 8}
 void set_packed_shape(int dtype, int exact, PackedShape s);
 bool packed_shape_supported(const PackedShape& s);
 // u = K v with K in layout 1 (n x n); scratch may be null (then allocated on st).

@@ -116,16 +116,16 @@ def test_every_packed_shape_and_autotuner(dev, kd):
     ref = kqr.kqr_kernel_apply_packed(v, Kp, n, kqr.KQR_APPLY_EXACT).cpu().numpy()
     scale = np.abs(v.cpu().numpy()).sum()
     for mode in (kqr.KQR_APPLY_FAST, kqr.KQR_APPLY_EXACT):
-        for mp in (0, 1, 2):
+        for mp in (0, 1, 2, 3):
             for strip in (1, 2, 3, 4, 8, 16, 32):
                 kqr.kqr_set_packed_shape(kd, mode, mp, strip)
                 u = kqr.kqr_kernel_apply_packed(v, Kp, n, mode).cpu().numpy()
                 tol = (1e-13 if mode == kqr.KQR_APPLY_EXACT else 300 * U32) * scale
                 assert np.abs(u - ref).max() <= tol, (mode, mp, strip)
         rep = kqr.kqr_autotune_packed(Kp, n, mode, reps=2)
-        assert len(rep["shapes"]) == 15 and rep["best"]["map"] in (0, 1, 2) and 1 <= rep["best"]["strip"] <= 16
+        assert len(rep["shapes"]) == 20 and rep["best"]["map"] in (0, 1, 2, 3) and 1 <= rep["best"]["strip"] <= 16
     with pytest.raises(kqr.KqrError):
-        kqr.kqr_set_packed_shape(kd, kqr.KQR_APPLY_FAST, 3, 4)
+        kqr.kqr_set_packed_shape(kd, kqr.KQR_APPLY_FAST, 4, 4)
     with pytest.raises(kqr.KqrError):
         kqr.kqr_set_packed_shape(kd, kqr.KQR_APPLY_FAST, 0, 33)
 
