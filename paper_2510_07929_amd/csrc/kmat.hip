@@ -376,6 +376,15 @@ void kapply_dense(const KMat& km, int64_t nrows, int64_t ncols, const float* v32
 // kernel.
 constexpr int kOtfTile = 64;
 
+// Column slices of an on-the-fly launch: about 8192 workgroups in all (many
+// rounds of the blocks the chip holds at once, so the last round is a small
+// tail), each slice at least 1024 columns.  Every slice writes one partial
+// per row, added in slice order by otf_reduce_kernel.
+static int64_t otf_slices(int64_t rblk, int64_t nc) {
+  const int64_t want = (8192 + std::max<int64_t>(rblk, 1) - 1) / std::max<int64_t>(rblk, 1);
+  return std::max<int64_t>(1, std::min<int64_t>(want, (nc + 1023) / 1024));
+}
+
 template <int PMAX, bool LAP, bool EX>
 __global__ __launch_bounds__(256) void kapply_otf_kernel(
     const float* __restrict__ Xr, const float* __restrict__ qr, int64_t nr,
@@ -440,8 +449,7 @@ static void kapply_otf_p(const float* Xr, const float* qr, int64_t nr, const flo
                          const float* qc, int64_t nc, int p, KernelSpec ks, const double* v, double* u,
                          int64_t ldu, double scale, double shift, bool exact, hipStream_t st) {
   const int64_t rblk = (nr + 255) / 256;
-  // enough column slices for ~2048 blocks, each slice at least 1024 columns
-  int64_t nslice = std::max<int64_t>(1, std::min<int64_t>(2048 / std::max<int64_t>(rblk, 1), (nc + 1023) / 1024));
+  int64_t nslice = otf_slices(rblk, nc);
   nslice = std::min<int64_t>(nslice, 65535);
   int64_t per = (nc + nslice - 1) / nslice;
   per = (per + kOtfTile - 1) / kOtfTile * kOtfTile;
@@ -555,7 +563,7 @@ static void kapply_otf_l1q_p(const uint32_t* Xq, int64_t n, int p, float ngs, co
   // rows per thread: 4 up to 32 coordinates, 2 beyond (registers)
   constexpr int R = PMAX <= 32 ? 4 : 2;
   const int64_t rblk = (n + 256 * R - 1) / (256 * R);
-  int64_t nslice = std::max<int64_t>(1, std::min<int64_t>(2048 / std::max<int64_t>(rblk, 1), (n + 1023) / 1024));
+  int64_t nslice = otf_slices(rblk, n);
   nslice = std::min<int64_t>(nslice, 65535);
   int64_t per = (n + nslice - 1) / nslice;
   per = (per + kOtfTile - 1) / kOtfTile * kOtfTile;
@@ -776,12 +784,159 @@ __global__ __launch_bounds__(256) void kapply_otf_mfma_kernel(
   }
 }
 
+// The same with the Gram term in BF16 on the matrix cores: every FP32
+// coordinate is split exactly into three BF16 parts x = h + m + l (round to
+// nearest even at each step; 3 x 8 significand bits hold FP32's 24), and
+// G = hh + hm + mh + hl + lh + mm (the dropped ml, lm, ll are below 2^-24 of
+// |x_i| |x_j| per coordinate) is formed by six v_mfma_f32_16x16x32_bf16 per
+// 16 x 16 block (p <= 32, padded to 32), against eight 16x16x4 FP32 MFMAs
+// that take 5x the matrix-core time at p = 32.  FP32 sums inside the MFMA.
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef uint16_t u16x8_t __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ void split3_bf16(float x, uint16_t& h, uint16_t& m, uint16_t& l) {
+  h = f32_to_bf16(x);
+  const float r1 = x - bf16_to_f32(h);  // exact
+  m = f32_to_bf16(r1);
+  const float r2 = r1 - bf16_to_f32(m);  // exact, at most 8 significant bits
+  l = f32_to_bf16(r2);
+}
+
+constexpr int kB3Row = 40;  // LDS row of 32 BF16 coordinates, padded (16-byte aligned, rows spread over banks)
+
+template <bool EX>
+__global__ __launch_bounds__(256) void kapply_otf_mfma3_kernel(
+    const float* __restrict__ Xr, const float* __restrict__ qr, int64_t nr,
+    const float* __restrict__ Xc, const float* __restrict__ qc, int64_t nc, int p, float ng,
+    const double* __restrict__ v, int64_t cols_per_slice, double* __restrict__ part) {
+  __shared__ __align__(16) uint16_t bh[kMfmaCols][kB3Row];
+  __shared__ __align__(16) uint16_t bm[kMfmaCols][kB3Row];
+  __shared__ __align__(16) uint16_t bl[kMfmaCols][kB3Row];
+  __shared__ float qs[kMfmaCols];
+  __shared__ float vs[kMfmaCols];
+  __shared__ double vd[kMfmaCols];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lg = lane >> 4;
+  const int64_t row0 = int64_t(blockIdx.x) * 128 + wave * 32;
+  bf16x8_t ah[2], am[2], al[2];
+  float qi[2][4];
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    const int64_t r = row0 + 16 * s + li;
+    u16x8_t h, m, l;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int k = 8 * lg + e;
+      const float x = (r < nr && k < p) ? Xr[r * p + k] : 0.f;
+      uint16_t hh, mm, ll;
+      split3_bf16(x, hh, mm, ll);
+      h[e] = hh;
+      m[e] = mm;
+      l[e] = ll;
+    }
+    ah[s] = __builtin_bit_cast(bf16x8_t, h);
+    am[s] = __builtin_bit_cast(bf16x8_t, m);
+    al[s] = __builtin_bit_cast(bf16x8_t, l);
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) {
+      const int64_t ro = row0 + 16 * s + 4 * lg + rr;
+      qi[s][rr] = ro < nr ? qr[ro] : 0.f;
+    }
+  }
+  const int64_t c0 = int64_t(blockIdx.y) * cols_per_slice;
+  const int64_t c1 = min(nc, c0 + cols_per_slice);
+  double acc[2][4];
+#pragma unroll
+  for (int s = 0; s < 2; ++s)
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) acc[s][rr] = 0.0;
+  for (int64_t jb = c0; jb < c1; jb += kMfmaCols) {
+    const int cnt = int(min<int64_t>(kMfmaCols, c1 - jb));
+    __syncthreads();
+    for (int t = threadIdx.x; t < kMfmaCols * 32; t += 256) {
+      const int jj = t >> 5, k = t & 31;
+      const float x = (jj < cnt && k < p) ? Xc[(jb + jj) * p + k] : 0.f;
+      uint16_t hh, mm, ll;
+      split3_bf16(x, hh, mm, ll);
+      bh[jj][k] = hh;
+      bm[jj][k] = mm;
+      bl[jj][k] = ll;
+    }
+    if (threadIdx.x < kMfmaCols) {
+      const int jj = threadIdx.x;
+      qs[jj] = jj < cnt ? qc[jb + jj] : 0.f;
+      const double vj = jj < cnt ? v[jb + jj] : 0.0;
+      if (EX) vd[jj] = vj;
+      else vs[jj] = float(vj);
+    }
+    __syncthreads();
+    float a32[2][4];
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) a32[s][rr] = 0.f;
+    for (int t16 = 0; t16 < cnt; t16 += 16) {
+      const int jj = t16 + li;
+      const bf16x8_t b_h = *reinterpret_cast<const bf16x8_t*>(&bh[jj][8 * lg]);
+      const bf16x8_t b_m = *reinterpret_cast<const bf16x8_t*>(&bm[jj][8 * lg]);
+      const bf16x8_t b_l = *reinterpret_cast<const bf16x8_t*>(&bl[jj][8 * lg]);
+      f32x4_t g[2];
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {  // smallest products first
+        f32x4_t c = f32x4_t{0.f, 0.f, 0.f, 0.f};
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am[s], b_m, c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[s], b_l, c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[s], b_h, c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[s], b_m, c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am[s], b_h, c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[s], b_h, c, 0, 0, 0);
+        g[s] = c;
+      }
+      const float qj = qs[jj];
+#pragma unroll
+      for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+          const float d = fmaxf(qi[s][rr] + qj - 2.f * g[s][rr], 0.f);
+          const float e = exp2f(ng * d);
+          if (EX) acc[s][rr] = fma(double(e), vd[jj], acc[s][rr]);
+          else a32[s][rr] = fmaf(e, vs[jj], a32[s][rr]);
+        }
+    }
+    if (!EX) {
+#pragma unroll
+      for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) acc[s][rr] += double(a32[s][rr]);
+    }
+  }
+  // sum over the 16 column lanes of each row group (lane bits 0..3)
+#pragma unroll
+  for (int s = 0; s < 2; ++s)
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) {
+      double x = acc[s][rr];
+#pragma unroll
+      for (int off = 1; off < 16; off <<= 1) x += __shfl_xor(x, off);
+      acc[s][rr] = x;
+    }
+  if (li == 0) {
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) {
+        const int64_t ro = row0 + 16 * s + 4 * lg + rr;
+        if (ro < nr) part[int64_t(blockIdx.y) * nr + ro] = acc[s][rr];
+      }
+  }
+}
+
 template <int KP>
 static void kapply_otf_mfma_p(const float* Xr, const float* qr, int64_t nr, const float* Xc, const float* qc,
                               int64_t nc, int p, KernelSpec ks, const double* v, double* u, int64_t ldu, double scale,
                               double shift, bool exact, hipStream_t st) {
   const int64_t rblk = (nr + 127) / 128;
-  int64_t nslice = std::max<int64_t>(1, std::min<int64_t>(2048 / std::max<int64_t>(rblk, 1), (nc + 1023) / 1024));
+  int64_t nslice = otf_slices(rblk, nc);
   nslice = std::min<int64_t>(nslice, 65535);
   int64_t per = (nc + nslice - 1) / nslice;
   per = (per + kMfmaCols - 1) / kMfmaCols * kMfmaCols;
@@ -790,8 +945,14 @@ static void kapply_otf_mfma_p(const float* Xr, const float* qr, int64_t nr, cons
   KQR_CHECK_HIP(hipMallocAsync(reinterpret_cast<void**>(&part), size_t(nslice) * size_t(nr) * sizeof(double), st));
   const dim3 grid((unsigned)rblk, (unsigned)nslice);
   const float ng = -float(ks.gamma) * kLog2e;
-  if (exact) kapply_otf_mfma_kernel<KP, true><<<grid, 256, 0, st>>>(Xr, qr, nr, Xc, qc, nc, p, ng, v, per, part);
-  else kapply_otf_mfma_kernel<KP, false><<<grid, 256, 0, st>>>(Xr, qr, nr, Xc, qc, nc, p, ng, v, per, part);
+  if (KP > 16) {  // BF16x3 Gram: 6 MFMAs of K = 32 against KP/4 FP32 ones
+    if (exact) kapply_otf_mfma3_kernel<true><<<grid, 256, 0, st>>>(Xr, qr, nr, Xc, qc, nc, p, ng, v, per, part);
+    else kapply_otf_mfma3_kernel<false><<<grid, 256, 0, st>>>(Xr, qr, nr, Xc, qc, nc, p, ng, v, per, part);
+  } else if (exact) {
+    kapply_otf_mfma_kernel<KP, true><<<grid, 256, 0, st>>>(Xr, qr, nr, Xc, qc, nc, p, ng, v, per, part);
+  } else {
+    kapply_otf_mfma_kernel<KP, false><<<grid, 256, 0, st>>>(Xr, qr, nr, Xc, qc, nc, p, ng, v, per, part);
+  }
   KQR_LAUNCH_CHECK();
   otf_reduce_kernel<<<dim3((unsigned)((nr + 255) / 256)), 256, 0, st>>>(part, int(nslice), nr, u, ldu, scale, shift);
   KQR_LAUNCH_CHECK();
