@@ -29,19 +29,23 @@ KERNEL_SOURCE = os.path.join(HERE, "csrc", "kmat.hip")
 PACKED_SOURCE = os.path.join(HERE, "csrc", "kpacked.hip")
 
 
-SECTION_BEGIN = "// ================================================================= materialised K-apply"
-SECTION_END = "// ================================================================= on-the-fly K-apply"
+RULE = "// ================================================================= "
+SECTIONS = {
+    KERNEL_SOURCE: (RULE + "materialised K-apply", RULE + "on-the-fly K-apply"),
+    PACKED_SOURCE: (RULE + "apply", RULE + "one row"),
+}
 
 
 def source_digest(path: str = KERNEL_SOURCE) -> str:
-    """Digest of a K-apply's source: the materialised section of kmat.hip
-    (kernels, shape table and launcher), or all of kpacked.hip."""
+    """Digest of a K-apply's source: the section of kmat.hip or kpacked.hip
+    that holds its kernels, shape table and launcher."""
     with open(path) as f:
         text = f.read()
-    a, b = text.find(SECTION_BEGIN), text.find(SECTION_END)
-    if a >= 0 and b > a:
-        text = text[a:b]
-    return hashlib.sha256(text.encode()).hexdigest()[:16]
+    begin, end = SECTIONS[path]
+    a, b = text.find(begin + "\n"), text.find(end + "\n")
+    if a < 0 or b <= a:
+        raise ValueError(f"K-apply section markers not found in {path}")
+    return hashlib.sha256(text[a:b].encode()).hexdigest()[:16]
 
 
 def source_for(layout: str) -> str:
