@@ -12,6 +12,15 @@ namespace kqr {
 
 constexpr float kLog2e = 1.4426950408889634f;
 
+// 2^x on the transcendental unit (one v_exp_f32, about 1 ulp).  Results below
+// the smallest normal FP32, 2^-126, may come out as zero: a kernel entry that
+// small is far below the rounding of any sum it enters.  In the normal range
+// this is the instruction exp2f is built on, without exp2f's rescaling of
+// subnormal results (five more lane operations per entry).  Every kernel that
+// forms k(x_i, x_j) from X uses it, so stored and recomputed entries agree
+// bit for bit.
+__device__ __forceinline__ float kexp2(float x) { return __builtin_amdgcn_exp2f(x); }
+
 // Distance of row x_i (norm q_i) to x_j (norm q_j), fixed padded dimension.
 template <int PMAX, bool LAP>
 __device__ __forceinline__ float pair_dist(const float* xi, float qi, const float* xj, float qj) {

@@ -3,7 +3,7 @@
 //
 // K_ij = exp(-gamma d_ij) with d the squared Euclidean distance (RBF) or the
 // L1 distance (Laplacian) (Section 1).  exp is evaluated as exp2 of
-// -gamma log2(e) d with the device exp2f.
+// -gamma log2(e) d on the transcendental unit (kexp2).
 #include "kernel_entry.h"
 #include "kqr_internal.h"
 
@@ -77,7 +77,7 @@ __global__ __launch_bounds__(256) void kbuild_kernel(const float* __restrict__ X
     if (valid) {
       float d = pair_dist<PMAX, LAP>(xs[r], qs[r], xj, qj);
       if (i == j) d = 0.f;
-      val = exp2f(ng * d);
+      val = kexp2(ng * d);
     }
     if (BF16) {
       __builtin_nontemporal_store(f32_to_bf16(val), static_cast<uint16_t*>(Kout) + i * ldk + j);
@@ -421,13 +421,13 @@ __global__ __launch_bounds__(256) void kapply_otf_kernel(
     if (EX) {
       for (int jj = 0; jj < cnt; ++jj) {
         const float d = pair_dist<PMAX, LAP>(xs[jj], qs[jj], xi, qi);
-        acc = fma(double(exp2f(ng * d)), vd[jj], acc);
+        acc = fma(double(kexp2(ng * d)), vd[jj], acc);
       }
     } else {
       float a32 = 0.f;
       for (int jj = 0; jj < cnt; ++jj) {
         const float d = pair_dist<PMAX, LAP>(xs[jj], qs[jj], xi, qi);
-        a32 = fmaf(exp2f(ng * d), vs[jj], a32);
+        a32 = fmaf(kexp2(ng * d), vs[jj], a32);
       }
       acc += double(a32);
     }
@@ -540,7 +540,7 @@ __global__ __launch_bounds__(256) void kapply_otf_l1q_kernel(const uint32_t* __r
       }
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        const float e = exp2f(ngs * float(d[r]));
+        const float e = kexp2(ngs * float(d[r]));
         if (EX) acc[r] = fma(double(e), vd[jj], acc[r]);
         else a32[r] = fmaf(e, vs[jj], a32[r]);
       }
@@ -742,7 +742,7 @@ __global__ __launch_bounds__(256) void kapply_otf_mfma_kernel(
       for (int rr = 0; rr < 4; ++rr) {
         const float d0 = fmaxf(qi[0][rr] + qj - 2.f * g0[rr], 0.f);
         const float d1 = fmaxf(qi[1][rr] + qj - 2.f * g1[rr], 0.f);
-        const float e0 = exp2f(ng * d0), e1 = exp2f(ng * d1);
+        const float e0 = kexp2(ng * d0), e1 = kexp2(ng * d1);
         if (EX) {
           acc[0][rr] = fma(double(e0), vd[jj], acc[0][rr]);
           acc[1][rr] = fma(double(e1), vd[jj], acc[1][rr]);
@@ -898,7 +898,7 @@ __global__ __launch_bounds__(256) void kapply_otf_mfma3_kernel(
 #pragma unroll
         for (int rr = 0; rr < 4; ++rr) {
           const float d = fmaxf(qi[s][rr] + qj - 2.f * g[s][rr], 0.f);
-          const float e = exp2f(ng * d);
+          const float e = kexp2(ng * d);
           if (EX) acc[s][rr] = fma(double(e), vd[jj], acc[s][rr]);
           else a32[s][rr] = fmaf(e, vs[jj], a32[s][rr]);
         }
@@ -1001,7 +1001,7 @@ __global__ void krow_from_x_kernel(const float* __restrict__ X, const float* __r
   for (int k = 0; k < PMAX; ++k) xj[k] = k < p ? X[j * p + k] : 0.f;
   float d = pair_dist<PMAX, LAP>(xs, LAP ? 0.f : q[s], xj, LAP ? 0.f : q[j]);
   if (j == s) d = 0.f;
-  out[j] = exp2f(ng * d);
+  out[j] = kexp2(ng * d);
 }
 
 template <int PMAX>

@@ -117,7 +117,7 @@ __global__ __launch_bounds__(256) void kbuild_packed_kernel(const float* __restr
     if (valid && i < n) {
       float d = pair_dist<PMAX, LAP>(xs[r], qs[r], xj, qj);
       if (i == j) d = 0.f;
-      val = exp2f(ng * d);
+      val = kexp2(ng * d);
     }
     const size_t off = base + size_t(r) * kPkT + c;
     if (BF16) __builtin_nontemporal_store(pk_to_bf16(val), static_cast<uint16_t*>(Kout) + off);

@@ -165,7 +165,7 @@ __global__ __launch_bounds__(256) void rpc_update_kernel(const KMat km, const fl
       }
       float dd = pair_dist_dyn(X + s * p, q ? q[s] : 0.f, X + j * p, q ? q[j] : 0.f, p, lap != 0);
       if (j == s) dd = 0.f;
-      return double(exp2f(ng * dd));
+      return double(kexp2(ng * dd));
     };
     const double gs = kentry(s) - (i > 0 ? u[s] : 0.0);
     const double inv = gs > 0.0 ? 1.0 / sqrt(gs) : 0.0;
