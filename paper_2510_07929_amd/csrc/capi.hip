@@ -402,7 +402,7 @@ int kqr_kernel_apply(const float* X, int64_t n, int64_t p, int kernel, double ga
       } else if (shift >= 20) {
         kapply_otf_l1q(xq.as<uint32_t>(), n, int(p), gamma, shift, col, U + j, ldu, mode == KQR_APPLY_EXACT, st);
       } else {
-        kapply_otf(X, sqn, n, X, sqn, n, int(p), ks, col, U + j, ldu, 1.0, 0.0, st);
+        kapply_otf(X, sqn, n, X, sqn, n, int(p), ks, col, U + j, ldu, 1.0, 0.0, st, mode == KQR_APPLY_EXACT);
       }
     }
     if (sqn) KQR_CHECK_HIP(hipFreeAsync(sqn, st));

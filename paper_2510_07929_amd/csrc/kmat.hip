@@ -791,6 +791,14 @@ __global__ __launch_bounds__(256) void kapply_otf_mfma_kernel(
 // |x_i| |x_j| per coordinate) is formed by six v_mfma_f32_16x16x32_bf16 per
 // 16 x 16 block (p <= 32, padded to 32), against eight 16x16x4 FP32 MFMAs
 // that take 5x the matrix-core time at p = 32.  FP32 sums inside the MFMA.
+//
+// The column side is split once per launch into a buffer of three planes
+// per column (kotf_split_cols_kernel), holding -2 x_j (an exact scaling).
+// With p <= 30 the two spare coordinates carry the squared norms: row
+// [x_i, 1, q_i] against column [-2 x_j, q_j, 1], so the matrix cores return
+// d_ij = q_i + q_j - 2 x_i . x_j itself (AUG) and a pair costs the lanes only
+// the clamp, the scale, the exponential and the product with v_j; without
+// AUG the lanes add q_i + q_j.
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef uint16_t u16x8_t __attribute__((ext_vector_type(8)));
 
@@ -802,19 +810,54 @@ __device__ __forceinline__ void split3_bf16(float x, uint16_t& h, uint16_t& m, u
   l = f32_to_bf16(r2);
 }
 
-constexpr int kB3Row = 40;  // LDS row of 32 BF16 coordinates, padded (16-byte aligned, rows spread over banks)
+constexpr int kB3Cols = 128;   // columns per LDS stage
+constexpr int kB3Row = 40;     // LDS row of 32 BF16 coordinates, padded (16-byte aligned, rows spread over banks)
+constexpr int kB3Stride = 96;  // halves per column in the split buffer: the h, m and l planes of 32
 
-template <bool EX>
+// Coordinate k of the padded 32-vector of a row (A) or column (B) side.
+template <bool AUG, bool COL>
+__device__ __forceinline__ float b3_coord(const float* __restrict__ x, float q, int k, int p) {
+  if (k < p) return COL ? -2.f * x[k] : x[k];
+  if (AUG && k == 30) return COL ? q : 1.f;
+  if (AUG && k == 31) return COL ? 1.f : q;
+  return 0.f;
+}
+
+// out[j * 96 + plane * 32 + k]: the parts of column j's coordinate k; one
+// thread per column and 8-coordinate group.
+template <bool AUG>
+__global__ __launch_bounds__(256) void kotf_split_cols_kernel(const float* __restrict__ Xc,
+                                                              const float* __restrict__ qc, int64_t nc, int p,
+                                                              uint16_t* __restrict__ out) {
+  const int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (t >= nc * 4) return;
+  const int64_t j = t >> 2;
+  const int g = int(t & 3);
+  const float q = AUG ? qc[j] : 0.f;
+  u16x8_t h, m, l;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    uint16_t hh, mm, ll;
+    split3_bf16(b3_coord<AUG, true>(Xc + j * p, q, 8 * g + e, p), hh, mm, ll);
+    h[e] = hh;
+    m[e] = mm;
+    l[e] = ll;
+  }
+  uint16_t* o = out + j * kB3Stride + 8 * g;
+  *reinterpret_cast<u16x8_t*>(o) = h;
+  *reinterpret_cast<u16x8_t*>(o + 32) = m;
+  *reinterpret_cast<u16x8_t*>(o + 64) = l;
+}
+
+template <bool EX, bool AUG>
 __global__ __launch_bounds__(256) void kapply_otf_mfma3_kernel(
-    const float* __restrict__ Xr, const float* __restrict__ qr, int64_t nr,
-    const float* __restrict__ Xc, const float* __restrict__ qc, int64_t nc, int p, float ng,
-    const double* __restrict__ v, int64_t cols_per_slice, double* __restrict__ part) {
-  __shared__ __align__(16) uint16_t bh[kMfmaCols][kB3Row];
-  __shared__ __align__(16) uint16_t bm[kMfmaCols][kB3Row];
-  __shared__ __align__(16) uint16_t bl[kMfmaCols][kB3Row];
-  __shared__ float qs[kMfmaCols];
-  __shared__ float vs[kMfmaCols];
-  __shared__ double vd[kMfmaCols];
+    const float* __restrict__ Xr, const float* __restrict__ qr, int64_t nr, const uint16_t* __restrict__ Bc,
+    const float* __restrict__ qc, int64_t nc, int p, float ng, const double* __restrict__ v,
+    int64_t cols_per_slice, double* __restrict__ part) {
+  __shared__ __align__(16) uint16_t bs[3][kB3Cols][kB3Row];
+  __shared__ float qs[AUG ? 1 : kB3Cols];
+  __shared__ float vs[kB3Cols];
+  __shared__ double vd[kB3Cols];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, lg = lane >> 4;
   const int64_t row0 = int64_t(blockIdx.x) * 128 + wave * 32;
@@ -823,11 +866,13 @@ __global__ __launch_bounds__(256) void kapply_otf_mfma3_kernel(
 #pragma unroll
   for (int s = 0; s < 2; ++s) {
     const int64_t r = row0 + 16 * s + li;
+    const bool in = r < nr;
+    const float q = (AUG && in) ? qr[r] : 0.f;
     u16x8_t h, m, l;
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
       const int k = 8 * lg + e;
-      const float x = (r < nr && k < p) ? Xr[r * p + k] : 0.f;
+      const float x = in ? b3_coord<AUG, false>(Xr + r * p, q, k, p) : 0.f;
       uint16_t hh, mm, ll;
       split3_bf16(x, hh, mm, ll);
       h[e] = hh;
@@ -840,7 +885,7 @@ __global__ __launch_bounds__(256) void kapply_otf_mfma3_kernel(
 #pragma unroll
     for (int rr = 0; rr < 4; ++rr) {
       const int64_t ro = row0 + 16 * s + 4 * lg + rr;
-      qi[s][rr] = ro < nr ? qr[ro] : 0.f;
+      qi[s][rr] = (!AUG && ro < nr) ? qr[ro] : 0.f;
     }
   }
   const int64_t c0 = int64_t(blockIdx.y) * cols_per_slice;
@@ -850,21 +895,19 @@ __global__ __launch_bounds__(256) void kapply_otf_mfma3_kernel(
   for (int s = 0; s < 2; ++s)
 #pragma unroll
     for (int rr = 0; rr < 4; ++rr) acc[s][rr] = 0.0;
-  for (int64_t jb = c0; jb < c1; jb += kMfmaCols) {
-    const int cnt = int(min<int64_t>(kMfmaCols, c1 - jb));
+  for (int64_t jb = c0; jb < c1; jb += kB3Cols) {
+    const int cnt = int(min<int64_t>(kB3Cols, c1 - jb));
     __syncthreads();
-    for (int t = threadIdx.x; t < kMfmaCols * 32; t += 256) {
-      const int jj = t >> 5, k = t & 31;
-      const float x = (jj < cnt && k < p) ? Xc[(jb + jj) * p + k] : 0.f;
-      uint16_t hh, mm, ll;
-      split3_bf16(x, hh, mm, ll);
-      bh[jj][k] = hh;
-      bm[jj][k] = mm;
-      bl[jj][k] = ll;
+    // 16-byte chunks: column jj, plane pl, coordinates 8g..8g+7
+    for (int t = threadIdx.x; t < kB3Cols * 12; t += 256) {
+      const int jj = t / 12, r = t - 12 * (t / 12), pl = r >> 2, g = r & 3;
+      u16x8_t val = u16x8_t{0, 0, 0, 0, 0, 0, 0, 0};
+      if (jj < cnt) val = *reinterpret_cast<const u16x8_t*>(Bc + (jb + jj) * kB3Stride + 32 * pl + 8 * g);
+      *reinterpret_cast<u16x8_t*>(&bs[pl][jj][8 * g]) = val;
     }
-    if (threadIdx.x < kMfmaCols) {
+    if (threadIdx.x < kB3Cols) {
       const int jj = threadIdx.x;
-      qs[jj] = jj < cnt ? qc[jb + jj] : 0.f;
+      if (!AUG) qs[jj] = jj < cnt ? qc[jb + jj] : 0.f;
       const double vj = jj < cnt ? v[jb + jj] : 0.0;
       if (EX) vd[jj] = vj;
       else vs[jj] = float(vj);
@@ -875,12 +918,13 @@ __global__ __launch_bounds__(256) void kapply_otf_mfma3_kernel(
     for (int s = 0; s < 2; ++s)
 #pragma unroll
       for (int rr = 0; rr < 4; ++rr) a32[s][rr] = 0.f;
-    for (int t16 = 0; t16 < cnt; t16 += 16) {
+    // The Gram blocks of the next 16-column tile go to the matrix cores
+    // before the lanes take the current tile's exponentials.
+    auto gram = [&](int t16, f32x4_t* g) {
       const int jj = t16 + li;
-      const bf16x8_t b_h = *reinterpret_cast<const bf16x8_t*>(&bh[jj][8 * lg]);
-      const bf16x8_t b_m = *reinterpret_cast<const bf16x8_t*>(&bm[jj][8 * lg]);
-      const bf16x8_t b_l = *reinterpret_cast<const bf16x8_t*>(&bl[jj][8 * lg]);
-      f32x4_t g[2];
+      const bf16x8_t b_h = *reinterpret_cast<const bf16x8_t*>(&bs[0][jj][8 * lg]);
+      const bf16x8_t b_m = *reinterpret_cast<const bf16x8_t*>(&bs[1][jj][8 * lg]);
+      const bf16x8_t b_l = *reinterpret_cast<const bf16x8_t*>(&bs[2][jj][8 * lg]);
 #pragma unroll
       for (int s = 0; s < 2; ++s) {  // smallest products first
         f32x4_t c = f32x4_t{0.f, 0.f, 0.f, 0.f};
@@ -892,16 +936,32 @@ __global__ __launch_bounds__(256) void kapply_otf_mfma3_kernel(
         c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[s], b_h, c, 0, 0, 0);
         g[s] = c;
       }
-      const float qj = qs[jj];
+    };
+    f32x4_t g[2], gn[2];
+    gram(0, g);
+    for (int t16 = 0; t16 < cnt; t16 += 16) {
+      const int jj = t16 + li;
+      // the last tile's successor is a dummy in-bounds tile, never used
+      gram(min(t16 + 16, kB3Cols - 16), gn);
+      const float qj = AUG ? 0.f : qs[jj];
 #pragma unroll
       for (int s = 0; s < 2; ++s)
 #pragma unroll
         for (int rr = 0; rr < 4; ++rr) {
-          const float d = fmaxf(qi[s][rr] + qj - 2.f * g[s][rr], 0.f);
-          const float e = kexp2(ng * d);
+          // ng < 0: min(ng d, 0) = ng max(d, 0)
+          const float d = AUG ? g[s][rr] : qi[s][rr] + qj + g[s][rr];
+          const float e = kexp2(fminf(ng * d, 0.f));
           if (EX) acc[s][rr] = fma(double(e), vd[jj], acc[s][rr]);
           else a32[s][rr] = fmaf(e, vs[jj], a32[s][rr]);
         }
+      // interleave: one MFMA, then a few lane operations, twelve times
+#pragma unroll
+      for (int k = 0; k < 12; ++k) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+        __builtin_amdgcn_sched_group_barrier(0x002, 4, 0);
+      }
+      g[0] = gn[0];
+      g[1] = gn[1];
     }
     if (!EX) {
 #pragma unroll
@@ -939,15 +999,27 @@ static void kapply_otf_mfma_p(const float* Xr, const float* qr, int64_t nr, cons
   int64_t nslice = otf_slices(rblk, nc);
   nslice = std::min<int64_t>(nslice, 65535);
   int64_t per = (nc + nslice - 1) / nslice;
-  per = (per + kMfmaCols - 1) / kMfmaCols * kMfmaCols;
+  const int64_t stage = KP > 16 ? kB3Cols : kMfmaCols;
+  per = (per + stage - 1) / stage * stage;
   nslice = (nc + per - 1) / per;
-  double* part = nullptr;
-  KQR_CHECK_HIP(hipMallocAsync(reinterpret_cast<void**>(&part), size_t(nslice) * size_t(nr) * sizeof(double), st));
+  const size_t part_bytes = (size_t(nslice) * size_t(nr) * sizeof(double) + 255) / 256 * 256;
+  const size_t split_bytes = KP > 16 ? size_t(nc) * kB3Stride * sizeof(uint16_t) : 0;
+  char* buf = nullptr;
+  KQR_CHECK_HIP(hipMallocAsync(reinterpret_cast<void**>(&buf), part_bytes + split_bytes, st));
+  double* part = reinterpret_cast<double*>(buf);
   const dim3 grid((unsigned)rblk, (unsigned)nslice);
   const float ng = -float(ks.gamma) * kLog2e;
   if (KP > 16) {  // BF16x3 Gram: 6 MFMAs of K = 32 against KP/4 FP32 ones
-    if (exact) kapply_otf_mfma3_kernel<true><<<grid, 256, 0, st>>>(Xr, qr, nr, Xc, qc, nc, p, ng, v, per, part);
-    else kapply_otf_mfma3_kernel<false><<<grid, 256, 0, st>>>(Xr, qr, nr, Xc, qc, nc, p, ng, v, per, part);
+    uint16_t* bc = reinterpret_cast<uint16_t*>(buf + part_bytes);
+    const bool aug = p <= 30;
+    const dim3 sgrid((unsigned)((nc * 4 + 255) / 256));
+    if (aug) kotf_split_cols_kernel<true><<<sgrid, 256, 0, st>>>(Xc, qc, nc, p, bc);
+    else kotf_split_cols_kernel<false><<<sgrid, 256, 0, st>>>(Xc, qc, nc, p, bc);
+    KQR_LAUNCH_CHECK();
+    if (aug && exact) kapply_otf_mfma3_kernel<true, true><<<grid, 256, 0, st>>>(Xr, qr, nr, bc, qc, nc, p, ng, v, per, part);
+    else if (aug) kapply_otf_mfma3_kernel<false, true><<<grid, 256, 0, st>>>(Xr, qr, nr, bc, qc, nc, p, ng, v, per, part);
+    else if (exact) kapply_otf_mfma3_kernel<true, false><<<grid, 256, 0, st>>>(Xr, qr, nr, bc, qc, nc, p, ng, v, per, part);
+    else kapply_otf_mfma3_kernel<false, false><<<grid, 256, 0, st>>>(Xr, qr, nr, bc, qc, nc, p, ng, v, per, part);
   } else if (exact) {
     kapply_otf_mfma_kernel<KP, true><<<grid, 256, 0, st>>>(Xr, qr, nr, Xc, qc, nc, p, ng, v, per, part);
   } else {
@@ -956,7 +1028,7 @@ static void kapply_otf_mfma_p(const float* Xr, const float* qr, int64_t nr, cons
   KQR_LAUNCH_CHECK();
   otf_reduce_kernel<<<dim3((unsigned)((nr + 255) / 256)), 256, 0, st>>>(part, int(nslice), nr, u, ldu, scale, shift);
   KQR_LAUNCH_CHECK();
-  KQR_CHECK_HIP(hipFreeAsync(part, st));
+  KQR_CHECK_HIP(hipFreeAsync(buf, st));
 }
 
 void kapply_otf(const float* Xr, const float* sqr, int64_t nr, const float* Xc, const float* sqc,

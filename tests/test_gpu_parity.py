@@ -117,15 +117,18 @@ def test_kernel_apply_materialised(dev, kd, mode, n):
     assert np.all(err <= bound), float((err / bound).max())
 
 
+# p = 10: FP32 matrix-core Gram; 20 and 30: BF16x3 Gram with the norms in the
+# spare coordinates; 32: BF16x3 Gram, norms added by the lanes
 @pytest.mark.parametrize("kind", ["rbf", "laplacian"])
-@pytest.mark.parametrize("n,p", [(1337, 10), (3000, 30)])
-def test_kernel_apply_on_the_fly(dev, kind, n, p):
+@pytest.mark.parametrize("mode", [kqr.KQR_APPLY_FAST, kqr.KQR_APPLY_EXACT])
+@pytest.mark.parametrize("n,p", [(1337, 10), (1500, 20), (3000, 30), (2100, 32)])
+def test_kernel_apply_on_the_fly(dev, kind, mode, n, p):
     X, _ = inputs.additive(n, p, (104, n))
     v = np.random.default_rng(1).standard_normal(n)
     gamma = 1.0 / p
-    say("kernel_apply otf", kind, n, p)
+    say("kernel_apply otf", kind, mode, n, p)
     u = kqr.kqr_kernel_apply(torch.from_numpy(v).to(dev), X=torch.from_numpy(X).to(dev), kernel=kind,
-                             gamma=gamma).cpu().numpy()
+                             gamma=gamma, mode=mode).cpu().numpy()
     Kref, Kb = entry_bound(X, kind, gamma)
     bound = _apply_bound(Kb, Kref, v, kqr.KQR_APPLY_FAST, otf=True)
     err = np.abs(u - Kref @ v)
