@@ -793,12 +793,14 @@ __global__ __launch_bounds__(256) void kapply_otf_mfma_kernel(
 // that take 5x the matrix-core time at p = 32.  FP32 sums inside the MFMA.
 //
 // The column side is split once per launch into a buffer of three planes
-// per column (kotf_split_cols_kernel), holding -2 x_j (an exact scaling).
-// With p <= 30 the two spare coordinates carry the squared norms: row
-// [x_i, 1, q_i] against column [-2 x_j, q_j, 1], so the matrix cores return
-// d_ij = q_i + q_j - 2 x_i . x_j itself (AUG) and a pair costs the lanes only
-// the clamp, the scale, the exponential and the product with v_j; without
-// AUG the lanes add q_i + q_j.
+// per column (kotf_split_cols_kernel).  With p <= 30 (AUG) the two spare
+// coordinates carry the squared norms and the column side the exponent's
+// scale c = -gamma log2(e): row [x_i, 1, q_i] against column
+// [-2 c x_j, c q_j, c] (each product rounded once in FP32 before the split),
+// so the matrix cores return c d_ij = c (q_i + q_j - 2 x_i . x_j) itself and
+// a pair costs the lanes only the clamp at 0, the exponential and the
+// product with v_j.  Without AUG the column holds -2 x_j (exact) and the
+// lanes add q_i + q_j and scale.
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef uint16_t u16x8_t __attribute__((ext_vector_type(8)));
 
@@ -814,12 +816,13 @@ constexpr int kB3Cols = 128;   // columns per LDS stage
 constexpr int kB3Row = 40;     // LDS row of 32 BF16 coordinates, padded (16-byte aligned, rows spread over banks)
 constexpr int kB3Stride = 96;  // halves per column in the split buffer: the h, m and l planes of 32
 
-// Coordinate k of the padded 32-vector of a row (A) or column (B) side.
+// Coordinate k of the padded 32-vector of a row (A) or column (B) side;
+// c: the column side's scale (AUG), else 1.
 template <bool AUG, bool COL>
-__device__ __forceinline__ float b3_coord(const float* __restrict__ x, float q, int k, int p) {
-  if (k < p) return COL ? -2.f * x[k] : x[k];
-  if (AUG && k == 30) return COL ? q : 1.f;
-  if (AUG && k == 31) return COL ? 1.f : q;
+__device__ __forceinline__ float b3_coord(const float* __restrict__ x, float q, int k, int p, float c) {
+  if (k < p) return COL ? (-2.f * c) * x[k] : x[k];
+  if (AUG && k == 30) return COL ? c * q : 1.f;
+  if (AUG && k == 31) return COL ? c : q;
   return 0.f;
 }
 
@@ -828,7 +831,7 @@ __device__ __forceinline__ float b3_coord(const float* __restrict__ x, float q, 
 template <bool AUG>
 __global__ __launch_bounds__(256) void kotf_split_cols_kernel(const float* __restrict__ Xc,
                                                               const float* __restrict__ qc, int64_t nc, int p,
-                                                              uint16_t* __restrict__ out) {
+                                                              float ng, uint16_t* __restrict__ out) {
   const int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
   if (t >= nc * 4) return;
   const int64_t j = t >> 2;
@@ -838,7 +841,7 @@ __global__ __launch_bounds__(256) void kotf_split_cols_kernel(const float* __res
 #pragma unroll
   for (int e = 0; e < 8; ++e) {
     uint16_t hh, mm, ll;
-    split3_bf16(b3_coord<AUG, true>(Xc + j * p, q, 8 * g + e, p), hh, mm, ll);
+    split3_bf16(b3_coord<AUG, true>(Xc + j * p, q, 8 * g + e, p, AUG ? ng : 1.f), hh, mm, ll);
     h[e] = hh;
     m[e] = mm;
     l[e] = ll;
@@ -872,7 +875,7 @@ __global__ __launch_bounds__(256) void kapply_otf_mfma3_kernel(
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
       const int k = 8 * lg + e;
-      const float x = in ? b3_coord<AUG, false>(Xr + r * p, q, k, p) : 0.f;
+      const float x = in ? b3_coord<AUG, false>(Xr + r * p, q, k, p, 1.f) : 0.f;
       uint16_t hh, mm, ll;
       split3_bf16(x, hh, mm, ll);
       h[e] = hh;
@@ -918,8 +921,9 @@ __global__ __launch_bounds__(256) void kapply_otf_mfma3_kernel(
     for (int s = 0; s < 2; ++s)
 #pragma unroll
       for (int rr = 0; rr < 4; ++rr) a32[s][rr] = 0.f;
-    // The Gram blocks of the next 16-column tile go to the matrix cores
-    // before the lanes take the current tile's exponentials.
+    // Gram blocks of one 16-column tile (issuing the next tile's MFMAs ahead
+    // of these exponentials measured slower: the other waves of the SIMD
+    // already fill the matrix-core latency)
     auto gram = [&](int t16, f32x4_t* g) {
       const int jj = t16 + li;
       const bf16x8_t b_h = *reinterpret_cast<const bf16x8_t*>(&bs[0][jj][8 * lg]);
@@ -937,31 +941,21 @@ __global__ __launch_bounds__(256) void kapply_otf_mfma3_kernel(
         g[s] = c;
       }
     };
-    f32x4_t g[2], gn[2];
-    gram(0, g);
+    f32x4_t g[2];
     for (int t16 = 0; t16 < cnt; t16 += 16) {
       const int jj = t16 + li;
-      // the last tile's successor is a dummy in-bounds tile, never used
-      gram(min(t16 + 16, kB3Cols - 16), gn);
+      gram(t16, g);
       const float qj = AUG ? 0.f : qs[jj];
 #pragma unroll
       for (int s = 0; s < 2; ++s)
 #pragma unroll
         for (int rr = 0; rr < 4; ++rr) {
           // ng < 0: min(ng d, 0) = ng max(d, 0)
-          const float d = AUG ? g[s][rr] : qi[s][rr] + qj + g[s][rr];
-          const float e = kexp2(fminf(ng * d, 0.f));
+          const float a = AUG ? g[s][rr] : ng * (qi[s][rr] + qj + g[s][rr]);
+          const float e = kexp2(fminf(a, 0.f));
           if (EX) acc[s][rr] = fma(double(e), vd[jj], acc[s][rr]);
           else a32[s][rr] = fmaf(e, vs[jj], a32[s][rr]);
         }
-      // interleave: one MFMA, then a few lane operations, twelve times
-#pragma unroll
-      for (int k = 0; k < 12; ++k) {
-        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-        __builtin_amdgcn_sched_group_barrier(0x002, 4, 0);
-      }
-      g[0] = gn[0];
-      g[1] = gn[1];
     }
     if (!EX) {
 #pragma unroll
@@ -1013,8 +1007,8 @@ static void kapply_otf_mfma_p(const float* Xr, const float* qr, int64_t nr, cons
     uint16_t* bc = reinterpret_cast<uint16_t*>(buf + part_bytes);
     const bool aug = p <= 30;
     const dim3 sgrid((unsigned)((nc * 4 + 255) / 256));
-    if (aug) kotf_split_cols_kernel<true><<<sgrid, 256, 0, st>>>(Xc, qc, nc, p, bc);
-    else kotf_split_cols_kernel<false><<<sgrid, 256, 0, st>>>(Xc, qc, nc, p, bc);
+    if (aug) kotf_split_cols_kernel<true><<<sgrid, 256, 0, st>>>(Xc, qc, nc, p, ng, bc);
+    else kotf_split_cols_kernel<false><<<sgrid, 256, 0, st>>>(Xc, qc, nc, p, ng, bc);
     KQR_LAUNCH_CHECK();
     if (aug && exact) kapply_otf_mfma3_kernel<true, true><<<grid, 256, 0, st>>>(Xr, qr, nr, bc, qc, nc, p, ng, v, per, part);
     else if (aug) kapply_otf_mfma3_kernel<false, true><<<grid, 256, 0, st>>>(Xr, qr, nr, bc, qc, nc, p, ng, v, per, part);
