@@ -17,9 +17,12 @@ __global__ __launch_bounds__(256) void lin_xtv_kernel(const float* __restrict__ 
   for (int k = 0; k < PMAX; ++k) acc[k] = 0.0;
   for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) {
     const double vi = v[i];
+    float x[PMAX];
+#pragma unroll
+    for (int k = 0; k < PMAX; ++k) x[k] = X[i * p + min(k, p - 1)];  // every load issued, then used
 #pragma unroll
     for (int k = 0; k < PMAX; ++k)
-      if (k < p) acc[k] = fma(double(X[i * p + k]), vi, acc[k]);
+      if (k < p) acc[k] = fma(double(x[k]), vi, acc[k]);
   }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll

@@ -10,7 +10,8 @@
 //    (1/l_in - 1/l_out) U_E^T U_E with G_all = U^T U formed once per fit; a
 //    Newton step then only sums over the |E| interior rows.
 //  * C = Lc Lc^T by a blocked right-looking Cholesky (64-column panels; the
-//    diagonal block is factored by one wave with one row per lane);
+//    diagonal block is factored by one wave, one row per lane, with the
+//    panel columns finished in registers);
 //    W = Lc^{-1} is formed explicitly by recursive doubling
 //    (W21 = -W22 L21 W11), so an application needs two triangular mat-vecs
 //    over many workgroups instead of sequential substitutions, and
@@ -27,6 +28,7 @@ namespace {
 constexpr int kT = 64;        // SYRK / update / GEMM tile edge
 constexpr int kSubRows = 32;  // rows staged per LDS step of the SYRK
 constexpr int kNb = 64;       // Cholesky panel width = inverse leaf block
+constexpr int kLt = 32;       // output tile edge of the Cholesky update and the doubling GEMMs
 constexpr int kGtBlocks = 512;
 constexpr int kGtStage = 256;
 }  // namespace
@@ -45,6 +47,14 @@ __device__ __forceinline__ void tile_coords(int t, int& ta, int& tb) {
   tb = t - a * (a + 1) / 2;
 }
 
+// *p if ok, else 0, with the load issued unconditionally (p must be a valid
+// address either way): a load under a data-dependent branch is followed by a
+// full wait, so a loop of them runs one memory latency per element.
+__device__ __forceinline__ double load_or_zero(const double* p, bool ok) {
+  const double v = *p;
+  return ok ? v : 0.0;
+}
+
 // part[s][tile][64x64] = sum over rows of chunk s of w_i U_ia U_ib, where the
 // rows are idx[k] (or k itself when idx is null) and w_i = 1/L_i (or 1).
 __global__ __launch_bounds__(256) void syrk_kernel(const float* __restrict__ F, int64_t nrows, int r,
@@ -53,6 +63,8 @@ __global__ __launch_bounds__(256) void syrk_kernel(const float* __restrict__ F, 
                                                    double* __restrict__ part) {
   __shared__ double A[kSubRows][kT + 1];
   __shared__ double B[kSubRows][kT + 1];
+  __shared__ int64_t rows[kSubRows];
+  __shared__ double wts[kSubRows];
   int ta, tb;
   tile_coords(blockIdx.x, ta, tb);
   const int s = blockIdx.y;
@@ -65,19 +77,39 @@ __global__ __launch_bounds__(256) void syrk_kernel(const float* __restrict__ F, 
   const int64_t k0 = int64_t(s) * chunk;
   const int64_t k1 = min(nrows, k0 + chunk);
   for (int64_t kb = k0; kb < k1; kb += kSubRows) {
-    #pragma unroll
-    for (int e = threadIdx.x; e < kSubRows * kT; e += 256) {
-      const int ii = e / kT, k = e % kT;
-      const int64_t kk = kb + ii;
-      double av = 0.0, bv = 0.0;
-      if (kk < k1) {
-        const int64_t i = idx ? int64_t(idx[kk]) : kk;
-        const double w = L ? 1.0 / L[i] : 1.0;
-        av = u_at(F, ldf, r, i, ta * kT + k) * w;
-        bv = u_at(F, ldf, r, i, tb * kT + k);
+    // the stage's rows and weights first (one lane per row), then every
+    // element load issued unconditionally at a clamped address
+    if (threadIdx.x < kSubRows) {
+      const int64_t kk = kb + threadIdx.x;
+      const int64_t i = kk < k1 ? (idx ? int64_t(idx[kk]) : kk) : -1;
+      rows[threadIdx.x] = i;
+      wts[threadIdx.x] = i < 0 ? 0.0 : (L ? 1.0 / L[i] : 1.0);
+    }
+    __syncthreads();
+    double fa[kSubRows * kT / 256], fb[kSubRows * kT / 256];
+    if (r > 0) {  // the same in every lane; an empty factor (r = 0, F may be null) is never read
+#pragma unroll
+      for (int t = 0; t < kSubRows * kT / 256; ++t) {
+        const int e = int(threadIdx.x) + 256 * t;
+        const int ii = e / kT, k = e % kT;
+        const int64_t ic = rows[ii] < 0 ? 0 : rows[ii];
+        fa[t] = double(F[ic * ldf + min(ta * kT + k, r - 1)]);
+        fb[t] = double(F[ic * ldf + min(tb * kT + k, r - 1)]);
       }
-      A[ii][k] = av;
-      B[ii][k] = bv;
+    } else {
+#pragma unroll
+      for (int t = 0; t < kSubRows * kT / 256; ++t) fa[t] = fb[t] = 0.0;
+    }
+#pragma unroll
+    for (int t = 0; t < kSubRows * kT / 256; ++t) {
+      const int e = int(threadIdx.x) + 256 * t;
+      const int ii = e / kT, k = e % kT;
+      const int64_t i = rows[ii];
+      const int ca = ta * kT + k, cb = tb * kT + k;
+      const double ua = ca < r ? fa[t] : (ca == r ? 1.0 : 0.0);
+      const double ub = cb < r ? fb[t] : (cb == r ? 1.0 : 0.0);
+      A[ii][k] = i < 0 ? 0.0 : ua * wts[ii];
+      B[ii][k] = i < 0 ? 0.0 : ub;
     }
     __syncthreads();
 #pragma unroll 4
@@ -180,87 +212,111 @@ __global__ __launch_bounds__(64) void flag_scatter_kernel(const uint8_t* __restr
 }
 
 // ---------------------------------------------------------------- blocked Cholesky (lower)
-// Diagonal block (nb <= 64), one wave: the block sits in LDS and lane l owns
-// row l.  Columns go in panels of eight: every lane first forms
-// A[l][j] - sum_{k<j0} L[l][k] L[j][k] for the panel's eight columns j (its
-// own row against eight broadcast rows, eight independent sums), then the
-// panel is finished column by column: lane j takes the square root, the lanes
-// below scale by the broadcast reciprocal and update the panel's later
-// columns.  The loop over panels is not unrolled, so the kernel stays small
-// in the instruction cache.
+__device__ __forceinline__ double readlane_f64(double x, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(x), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(x), lane);
+  return __hiloint2double(hi, lo);
+}
+
+// 1 / sqrt(a) for a normal a > 0: v_rsq_f64 and two Newton steps
+// y <- y + y (1 - a y^2) / 2.
+__device__ __forceinline__ double rsqrt_f64(double a) {
+  double y = __builtin_amdgcn_rsq(a);
+  y = fma(0.5 * y, fma(-a * y, y, 1.0), y);
+  y = fma(0.5 * y, fma(-a * y, y, 1.0), y);
+  return y;
+}
+
+// Diagonal block (nb <= 64), one wave.  The block sits in LDS column-major
+// (Ac[k][i] = A[i][k]) and lane l owns row l.  Columns go in panels of
+// eight: every lane first subtracts sum_{k<j0} L[l][k] L[j][k] from its row's
+// eight panel entries (per earlier column k: its own L[l][k], a
+// conflict-free read, and the panel rows' L[j0..j0+7][k], contiguous
+// broadcast reads), then finishes the panel in registers column by column:
+// the pivot comes from lane j (readlane), its reciprocal square root from
+// rsqrt_f64, and the multipliers L[j0+c2][j] of the later panel columns from
+// their lanes, so the panel needs no LDS traffic and no barrier until it is
+// written back.  The loop over panels is not unrolled, so the kernel stays
+// small in the instruction cache.
 __global__ __launch_bounds__(64) void chol_diag_kernel(double* __restrict__ C, int64_t ldc, int kb, int nb,
                                                        int* __restrict__ flag) {
-  __shared__ double A[kNb][kNb + 1];
-  __shared__ double rdiag;
+  __shared__ __align__(16) double Ac[kNb][kNb + 2];  // row stride 528 bytes: 16-byte aligned, banks spread
   const int l = threadIdx.x;
-  #pragma unroll 16
-  for (int e = l; e < kNb * kNb; e += 64) {
-    const int i = e / kNb, k = e % kNb;
-    A[i][k] = (i < nb && k <= i) ? C[int64_t(kb + i) * ldc + kb + k] : (i == k ? 1.0 : 0.0);
+  // coalesced: one row of the block per step, lane l reads column l (the
+  // address clamped into the block's lower triangle, so all 64 loads are in
+  // flight at once)
+  {
+    double t[kNb];
+#pragma unroll
+    for (int i = 0; i < kNb; ++i) {
+      const int ic = min(i, nb - 1);
+      t[i] = C[int64_t(kb + ic) * ldc + kb + min(l, ic)];
+    }
+#pragma unroll
+    for (int i = 0; i < kNb; ++i) Ac[l][i] = (i < nb && l <= i) ? t[i] : (i == l ? 1.0 : 0.0);
   }
   __syncthreads();
   bool bad = false;
-  // panels of 8 columns: a left-looking update of the panel by all earlier
-  // columns (eight independent dot products per lane), then the panel itself
-  // column by column
   constexpr int PW = 8;
   for (int j0 = 0; j0 < kNb; j0 += PW) {
     double v[PW];
 #pragma unroll
-    for (int c = 0; c < PW; ++c) v[c] = 0.0;
+    for (int c = 0; c < PW; ++c) v[c] = Ac[j0 + c][l];
+#pragma unroll 4
     for (int k = 0; k < j0; ++k) {
-      const double a = A[l][k];
-#pragma unroll
-      for (int c = 0; c < PW; ++c) v[c] = fma(a, A[j0 + c][k], v[c]);
+      const double a = Ac[k][l];
+      const double2 b01 = *reinterpret_cast<const double2*>(&Ac[k][j0]);
+      const double2 b23 = *reinterpret_cast<const double2*>(&Ac[k][j0 + 2]);
+      const double2 b45 = *reinterpret_cast<const double2*>(&Ac[k][j0 + 4]);
+      const double2 b67 = *reinterpret_cast<const double2*>(&Ac[k][j0 + 6]);
+      v[0] = fma(-a, b01.x, v[0]);
+      v[1] = fma(-a, b01.y, v[1]);
+      v[2] = fma(-a, b23.x, v[2]);
+      v[3] = fma(-a, b23.y, v[3]);
+      v[4] = fma(-a, b45.x, v[4]);
+      v[5] = fma(-a, b45.y, v[5]);
+      v[6] = fma(-a, b67.x, v[6]);
+      v[7] = fma(-a, b67.y, v[7]);
     }
-#pragma unroll
-    for (int c = 0; c < PW; ++c) v[c] = A[l][j0 + c] - v[c];
 #pragma unroll
     for (int c = 0; c < PW; ++c) {
       const int j = j0 + c;
-      if (l == j) {
-        double piv = v[c];
-        if (!(piv > 0.0) || !isfinite(piv)) {
-          bad = true;
-          piv = 1e-300;
-        }
-        const double d = sqrt(piv);
-        A[j][j] = d;
-        rdiag = 1.0 / d;
+      double piv = readlane_f64(v[c], j);
+      if (!(piv > 0.0) || !isfinite(piv)) {  // the same in every lane
+        bad = true;
+        piv = 1e-300;
       }
-      __syncthreads();
-      if (l > j) {
-        v[c] *= rdiag;
-        A[l][j] = v[c];
-      }
-      __syncthreads();
+      const double y = rsqrt_f64(piv);
+      v[c] = (l == j) ? piv * y : v[c] * y;  // rows above j hold unused entries
 #pragma unroll
-      for (int c2 = c + 1; c2 < PW; ++c2)
-        if (l > j) v[c2] = fma(-v[c], A[j0 + c2][j], v[c2]);
+      for (int c2 = c + 1; c2 < PW; ++c2) v[c2] = fma(-v[c], readlane_f64(v[c], j0 + c2), v[c2]);
     }
+#pragma unroll
+    for (int c = 0; c < PW; ++c) Ac[j0 + c][l] = v[c];
+    __syncthreads();
   }
-  if (bad && nb > 0) flag[0] = 1;
-  #pragma unroll 16
-  for (int e = l; e < kNb * kNb; e += 64) {
-    const int i = e / kNb, k = e % kNb;
-    if (i < nb && k <= i) C[int64_t(kb + i) * ldc + kb + k] = A[i][k];
-  }
+  if (bad && l == 0) flag[0] = 1;
+  for (int i = 0; i < nb; ++i)
+    if (l <= i) C[int64_t(kb + i) * ldc + kb + l] = Ac[l][i];
 }
 
 // Panel: rows i >= kb+nb solve x L_kk^T = C[i, kb:kb+nb].  One wave per row,
 // lane k owns x_k; column j is finished by lane j (times the reciprocal of
-// the pivot) and broadcast.
+// the pivot) and broadcast by readlane.
 __global__ __launch_bounds__(256) void chol_panel_kernel(double* __restrict__ C, int64_t ldc, int kb, int nb,
                                                          int R1) {
   __shared__ double Lk[kNb][kNb + 1];
   __shared__ double rinv[kNb];
-  #pragma unroll 16
-  for (int e = threadIdx.x; e < kNb * kNb; e += 256) {
+#pragma unroll
+  for (int t = 0; t < kNb * kNb / 256; ++t) {
+    const int e = int(threadIdx.x) + 256 * t;
     const int i = e / kNb, k = e % kNb;
-    const double v = (i < nb && k <= i) ? C[int64_t(kb + i) * ldc + kb + k] : (i == k ? 1.0 : 0.0);
-    Lk[i][k] = v;
-    if (i == k) rinv[i] = 1.0 / v;
+    const int ic = min(i, nb - 1);
+    const double v = load_or_zero(C + int64_t(kb + ic) * ldc + kb + min(k, ic), i < nb && k <= i);
+    Lk[i][k] = (i >= nb && i == k) ? 1.0 : v;
   }
+  __syncthreads();
+  if (threadIdx.x < kNb) rinv[threadIdx.x] = 1.0 / Lk[threadIdx.x][threadIdx.x];
   __syncthreads();
   const int k = threadIdx.x & 63;
   const int64_t i = int64_t(kb) + nb + int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
@@ -269,98 +325,141 @@ __global__ __launch_bounds__(256) void chol_panel_kernel(double* __restrict__ C,
   double x = (ok && k < nb) ? row[k] : 0.0;
   for (int j = 0; j < kNb; ++j) {
     if (k == j) x *= rinv[j];
-    const double xj = __shfl(x, j);
+    const double xj = readlane_f64(x, j);
     if (k > j) x = fma(-xj, Lk[k][j], x);
   }
   if (ok && k < nb) row[k] = x;
 }
 
 // Trailing update of the lower part: C[i][j] -= sum_k P[i][k] P[j][k], j <= i,
-// with the 64-wide panel staged 32 columns at a time.
+// over the 64-wide panel P.  One workgroup per 32 x 32 lower tile (2 x 2
+// outputs per thread), K in two chunks of 32: the second chunk's global loads
+// are in flight while the first is multiplied.
 __global__ __launch_bounds__(256) void chol_update_kernel(double* __restrict__ C, int64_t ldc, int kb, int nb,
                                                           int R1) {
-  __shared__ double Pi[kT][33];
-  __shared__ double Pj[kT][33];
+  __shared__ double Pi[2][kLt][kLt + 1];  // Pi[buf][a][k] = P[i0 + a][k]
+  __shared__ double Pj[2][kLt][kLt + 1];  // Pj[buf][k][b] = P[j0 + b][k]
   int ta, tb;
   tile_coords(blockIdx.x, ta, tb);
   const int base = kb + nb;
-  const int i0 = base + ta * kT, j0 = base + tb * kT;
+  const int i0 = base + ta * kLt, j0 = base + tb * kLt;
   const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-  double acc[4][4];
-#pragma unroll
-  for (int p = 0; p < 4; ++p)
-#pragma unroll
-    for (int q = 0; q < 4; ++q) acc[p][q] = 0.0;
-  for (int h = 0; h < nb; h += 32) {
-    __syncthreads();
-    #pragma unroll
-    for (int e = threadIdx.x; e < kT * 32; e += 256) {
-      const int a = e / 32, k = e % 32;
-      const bool kk = h + k < nb;
-      Pi[a][k] = (i0 + a < R1 && kk) ? C[int64_t(i0 + a) * ldc + kb + h + k] : 0.0;
-      Pj[a][k] = (j0 + a < R1 && kk) ? C[int64_t(j0 + a) * ldc + kb + h + k] : 0.0;
-    }
-    __syncthreads();
-#pragma unroll 4
-    for (int k = 0; k < 32; ++k) {
-      double av[4], bv[4];
-#pragma unroll
-      for (int p = 0; p < 4; ++p) av[p] = Pi[ty * 4 + p][k];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) bv[q] = Pj[tx * 4 + q][k];
-#pragma unroll
-      for (int p = 0; p < 4; ++p)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) acc[p][q] = fma(av[p], bv[q], acc[p][q]);
-    }
-  }
-#pragma unroll
-  for (int p = 0; p < 4; ++p)
+  double ri[4], rj[4];
+  auto load = [&](int h) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const int i = i0 + ty * 4 + p, j = j0 + tx * 4 + q;
+      const int e = threadIdx.x + 256 * q;
+      const int a = e >> 5, k = e & 31;  // row a of the tile, column h + k of the panel
+      const bool kk = h + k < nb;
+      const int kc = kb + min(h + k, nb - 1);
+      ri[q] = load_or_zero(C + int64_t(min(i0 + a, R1 - 1)) * ldc + kc, i0 + a < R1 && kk);
+      rj[q] = load_or_zero(C + int64_t(min(j0 + a, R1 - 1)) * ldc + kc, j0 + a < R1 && kk);
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = threadIdx.x + 256 * q;
+      const int a = e >> 5, k = e & 31;
+      Pi[buf][a][k] = ri[q];
+      Pj[buf][k][a] = rj[q];
+    }
+  };
+  double acc[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
+  load(0);
+  store(0);
+  __syncthreads();
+  int buf = 0;
+  for (int h = 0; h < nb; h += kLt, buf ^= 1) {
+    const bool next = h + kLt < nb;
+    if (next) load(h + kLt);
+#pragma unroll 8
+    for (int k = 0; k < kLt; ++k) {
+      const double a0 = Pi[buf][ty * 2][k], a1 = Pi[buf][ty * 2 + 1][k];
+      const double b0 = Pj[buf][k][tx * 2], b1 = Pj[buf][k][tx * 2 + 1];
+      acc[0][0] = fma(a0, b0, acc[0][0]);
+      acc[0][1] = fma(a0, b1, acc[0][1]);
+      acc[1][0] = fma(a1, b0, acc[1][0]);
+      acc[1][1] = fma(a1, b1, acc[1][1]);
+    }
+    if (next) store(buf ^ 1);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int p = 0; p < 2; ++p)
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int i = i0 + ty * 2 + p, j = j0 + tx * 2 + q;
       if (i < R1 && j <= i) C[int64_t(i) * ldc + j] -= acc[p][q];
     }
 }
 
 // ---------------------------------------------------------------- W = Lc^{-1}
-// Inverse of each 64 x 64 diagonal block by forward substitution: lane j
-// forms column j of the inverse in LDS, reading the factor's rows as LDS
-// broadcasts (four independent partial sums per entry; entries above the
-// diagonal are zero, so every lane runs the same trip counts).  Blocks are
-// independent (one workgroup each).  W must be zero outside the blocks
-// written here before the doubling steps run.
+// Inverse of each 64 x 64 diagonal block: lane j forms column j of the
+// inverse, X[i][j] = (delta_ij - sum_{k<i} L[i][k] X[k][j]) / L[i][i], in
+// panels of eight rows: every lane first subtracts the earlier rows'
+// contributions (per earlier row k: its own X[k][j], a conflict-free read,
+// and the panel rows' L[i0..i0+7][k] from the transposed factor, contiguous
+// broadcast reads), then finishes the panel in registers.  Entries above the
+// diagonal come out as exact zeros.  Blocks are independent (one workgroup
+// each).  W must be zero outside the blocks written here before the doubling
+// steps run.
 __global__ __launch_bounds__(64) void trinv_diag_kernel(const double* __restrict__ C, int64_t ldc, int R1,
                                                         double* __restrict__ W) {
-  __shared__ double Lk[kNb][kNb + 1];
-  __shared__ double X[kNb][kNb + 1];
+  __shared__ __align__(16) double Lt[kNb][kNb + 2];  // Lt[k][i] = L[i][k]
+  __shared__ __align__(16) double X[kNb][kNb];
+  __shared__ double rinv[kNb];
   const int kb = blockIdx.x * kNb;
   const int nb = min(kNb, R1 - kb);
   const int j = threadIdx.x;
-  #pragma unroll 16
-  for (int e = j; e < kNb * kNb; e += 64) {
-    const int i = e / kNb, k = e % kNb;
-    Lk[i][k] = (i < nb && k <= i) ? C[int64_t(kb + i) * ldc + kb + k] : (i == k ? 1.0 : 0.0);
-  }
-  __syncthreads();
-  for (int i = 0; i < kNb; ++i) {
-    double s0 = (i == j) ? 1.0 : 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-    int k = 0;
-    for (; k + 4 <= i; k += 4) {
-      s0 = fma(-Lk[i][k], X[k][j], s0);
-      s1 = fma(-Lk[i][k + 1], X[k + 1][j], s1);
-      s2 = fma(-Lk[i][k + 2], X[k + 2][j], s2);
-      s3 = fma(-Lk[i][k + 3], X[k + 3][j], s3);
+  // coalesced: one row of the block per step, lane j reads column j (the
+  // address clamped into the block's lower triangle, so all 64 loads are in
+  // flight at once)
+  {
+    double t[kNb];
+#pragma unroll
+    for (int i = 0; i < kNb; ++i) {
+      const int ic = min(i, nb - 1);
+      t[i] = C[int64_t(kb + ic) * ldc + kb + min(j, ic)];
     }
-    for (; k < i; ++k) s0 = fma(-Lk[i][k], X[k][j], s0);
-    X[i][j] = (i >= j) ? ((s0 + s1) + (s2 + s3)) / Lk[i][i] : 0.0;
+#pragma unroll
+    for (int i = 0; i < kNb; ++i) Lt[j][i] = (i < nb && j <= i) ? t[i] : (i == j ? 1.0 : 0.0);
   }
   __syncthreads();
-  #pragma unroll 16
-  for (int e = j; e < kNb * kNb; e += 64) {
-    const int i = e / kNb, k = e % kNb;
-    if (i < nb && k < nb) W[int64_t(kb + i) * ldc + kb + k] = X[i][k];
+  rinv[j] = 1.0 / Lt[j][j];
+  __syncthreads();
+  constexpr int PW = 8;
+  for (int i0 = 0; i0 < kNb; i0 += PW) {
+    double x[PW];
+#pragma unroll
+    for (int c = 0; c < PW; ++c) x[c] = (i0 + c == j) ? 1.0 : 0.0;
+#pragma unroll 4
+    for (int k = 0; k < i0; ++k) {
+      const double xk = X[k][j];
+      const double2 l01 = *reinterpret_cast<const double2*>(&Lt[k][i0]);
+      const double2 l23 = *reinterpret_cast<const double2*>(&Lt[k][i0 + 2]);
+      const double2 l45 = *reinterpret_cast<const double2*>(&Lt[k][i0 + 4]);
+      const double2 l67 = *reinterpret_cast<const double2*>(&Lt[k][i0 + 6]);
+      x[0] = fma(-l01.x, xk, x[0]);
+      x[1] = fma(-l01.y, xk, x[1]);
+      x[2] = fma(-l23.x, xk, x[2]);
+      x[3] = fma(-l23.y, xk, x[3]);
+      x[4] = fma(-l45.x, xk, x[4]);
+      x[5] = fma(-l45.y, xk, x[5]);
+      x[6] = fma(-l67.x, xk, x[6]);
+      x[7] = fma(-l67.y, xk, x[7]);
+    }
+#pragma unroll
+    for (int c = 0; c < PW; ++c) {
+#pragma unroll
+      for (int c1 = 0; c1 < c; ++c1) x[c] = fma(-Lt[i0 + c1][i0 + c], x[c1], x[c]);
+      x[c] *= rinv[i0 + c];
+    }
+#pragma unroll
+    for (int c = 0; c < PW; ++c) X[i0 + c][j] = x[c];  // the lane's own column: no barrier needed
   }
+  if (j < nb)
+    for (int i = 0; i < nb; ++i) W[int64_t(kb + i) * ldc + kb + j] = X[i][j];
 }
 
 // One doubling level with blocks of s rows: for every pair (top = [i0, i0+s),
@@ -368,70 +467,77 @@ __global__ __launch_bounds__(64) void trinv_diag_kernel(const double* __restrict
 // alpha * A[bottom, A-cols] * B[B-rows, top] where
 //   stage 0: A = Lc[bottom, top]   (K = s),        B = W[top, top],   Out = T
 //   stage 1: A = W[bottom, bottom] (K = |bottom|),  B = T[bottom, top], Out = W (alpha = -1)
-// Grid: (pair, output tile); 64 x 64 tiles, K staged 32 at a time.
+// Grid: (pair, 32 x 32 output tile), 2 x 2 outputs per thread; K goes in
+// chunks of 32 with the next chunk's global loads in flight while the
+// current one is multiplied (double-buffered LDS).
 __global__ __launch_bounds__(256) void trinv_level_kernel(const double* __restrict__ Lc, const double* __restrict__ W,
                                                           const double* __restrict__ T, double* __restrict__ out,
                                                           int64_t ldc, int R1, int s, int stage, int tiles_per_pair) {
-  __shared__ double As[kT][33];
-  __shared__ double Bs[32][kT + 1];
+  __shared__ double As[2][kLt][kLt + 1];  // As[buf][row][k]
+  __shared__ double Bs[2][kLt][kLt + 1];  // Bs[buf][k][col]
   const int pair = blockIdx.x / tiles_per_pair;
   const int tile = blockIdx.x % tiles_per_pair;
   const int i0 = pair * 2 * s;
   const int bot0 = i0 + s;
   const int bot_len = min(s, R1 - bot0);
   if (bot_len <= 0) return;
-  const int tiles_n = s / kT;  // columns of the output block (top) in tiles
+  const int tiles_n = s / kLt;  // columns of the output block (top) in tiles
   const int tm = tile / tiles_n, tn = tile % tiles_n;
-  const int r0 = tm * kT;  // row offset inside bottom
-  const int c0 = tn * kT;  // column offset inside top
+  const int r0 = tm * kLt;  // row offset inside bottom
+  const int c0 = tn * kLt;  // column offset inside top
   if (r0 >= bot_len) return;
   const int K = stage == 0 ? s : bot_len;
   const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-  double acc[4][4];
+  double ra[4], rb[4];
+  auto load = [&](int kb) {
 #pragma unroll
-  for (int p = 0; p < 4; ++p)
+    for (int q = 0; q < 4; ++q) {
+      const int e = threadIdx.x + 256 * q;
+      const int hi = e >> 5, lo = e & 31;
+      // A: row hi of the tile, column kb + lo;  B: row kb + hi, column lo of the tile
+      const int row = r0 + hi, ka = kb + lo, kbr = kb + hi, col = c0 + lo;
+      const int rowc = min(row, bot_len - 1), kac = min(ka, K - 1), kbc = min(kbr, K - 1);
+      const double* pa = stage == 0 ? Lc + int64_t(bot0 + rowc) * ldc + i0 + kac
+                                    : W + int64_t(bot0 + rowc) * ldc + bot0 + kac;
+      const double* pb = stage == 0 ? W + int64_t(i0 + kbc) * ldc + i0 + col : T + int64_t(bot0 + kbc) * ldc + i0 + col;
+      ra[q] = load_or_zero(pa, row < bot_len && ka < K);
+      rb[q] = load_or_zero(pb, kbr < K);
+    }
+  };
+  auto store = [&](int buf) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) acc[p][q] = 0.0;
-  for (int kb = 0; kb < K; kb += 32) {
+    for (int q = 0; q < 4; ++q) {
+      const int e = threadIdx.x + 256 * q;
+      As[buf][e >> 5][e & 31] = ra[q];
+      Bs[buf][e >> 5][e & 31] = rb[q];
+    }
+  };
+  double acc[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
+  load(0);
+  store(0);
+  __syncthreads();
+  int buf = 0;
+  for (int kb = 0; kb < K; kb += kLt, buf ^= 1) {
+    const bool next = kb + kLt < K;
+    if (next) load(kb + kLt);
+#pragma unroll 8
+    for (int k = 0; k < kLt; ++k) {
+      const double a0 = As[buf][ty * 2][k], a1 = As[buf][ty * 2 + 1][k];
+      const double b0 = Bs[buf][k][tx * 2], b1 = Bs[buf][k][tx * 2 + 1];
+      acc[0][0] = fma(a0, b0, acc[0][0]);
+      acc[0][1] = fma(a0, b1, acc[0][1]);
+      acc[1][0] = fma(a1, b0, acc[1][0]);
+      acc[1][1] = fma(a1, b1, acc[1][1]);
+    }
+    if (next) store(buf ^ 1);
     __syncthreads();
-    #pragma unroll
-    for (int e = threadIdx.x; e < kT * 32; e += 256) {
-      const int a = e / 32, k = e % 32;
-      const int row = r0 + a, kk = kb + k;
-      double v = 0.0;
-      if (row < bot_len && kk < K) {
-        v = stage == 0 ? Lc[int64_t(bot0 + row) * ldc + i0 + kk] : W[int64_t(bot0 + row) * ldc + bot0 + kk];
-      }
-      As[a][k] = v;
-    }
-    #pragma unroll
-    for (int e = threadIdx.x; e < 32 * kT; e += 256) {
-      const int k = e / kT, b = e % kT;
-      const int kk = kb + k, col = c0 + b;
-      double v = 0.0;
-      if (kk < K) v = stage == 0 ? W[int64_t(i0 + kk) * ldc + i0 + col] : T[int64_t(bot0 + kk) * ldc + i0 + col];
-      Bs[k][b] = v;
-    }
-    __syncthreads();
-#pragma unroll 4
-    for (int k = 0; k < 32; ++k) {
-      double av[4], bv[4];
-#pragma unroll
-      for (int p = 0; p < 4; ++p) av[p] = As[ty * 4 + p][k];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) bv[q] = Bs[k][tx * 4 + q];
-#pragma unroll
-      for (int p = 0; p < 4; ++p)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) acc[p][q] = fma(av[p], bv[q], acc[p][q]);
-    }
   }
   const double alpha = stage == 0 ? 1.0 : -1.0;
 #pragma unroll
-  for (int p = 0; p < 4; ++p)
+  for (int p = 0; p < 2; ++p)
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int row = r0 + ty * 4 + p, col = c0 + tx * 4 + q;
+    for (int q = 0; q < 2; ++q) {
+      const int row = r0 + ty * 2 + p, col = c0 + tx * 2 + q;
       if (row < bot_len) out[int64_t(bot0 + row) * ldc + i0 + col] = alpha * acc[p][q];
     }
 }
@@ -622,7 +728,7 @@ void spd_factor_inverse(double* C, int64_t ldc, int R1, double* W, double* WT, d
     if (rest > 0) {
       chol_panel_kernel<<<(rest + 3) / 4, 256, 0, st>>>(C, ldc, kb, nb, R1);
       KQR_LAUNCH_CHECK();
-      const int mt = (rest + kT - 1) / kT;
+      const int mt = (rest + kLt - 1) / kLt;
       chol_update_kernel<<<mt * (mt + 1) / 2, 256, 0, st>>>(C, ldc, kb, nb, R1);
       KQR_LAUNCH_CHECK();
     }
@@ -634,7 +740,7 @@ void spd_factor_inverse(double* C, int64_t ldc, int R1, double* W, double* WT, d
   KQR_LAUNCH_CHECK();
   for (int s = kNb; s < R1; s *= 2) {
     const int pairs = (R1 + 2 * s - 1) / (2 * s);
-    const int tiles = (s / kT) * (s / kT);
+    const int tiles = (s / kLt) * (s / kLt);
     for (int stage = 0; stage < 2; ++stage) {
       double* out = stage == 0 ? T : W;
       trinv_level_kernel<<<pairs * tiles, 256, 0, st>>>(C, W, T, out, ldc, R1, s, stage, tiles);
