@@ -199,16 +199,20 @@ def test_rpcholesky_matches_oracle(dev, materialised):
 
 
 # --------------------------------------------------------------------- Woodbury
-@pytest.mark.parametrize("lmin", [1e-2, 1e-7])
-def test_woodbury_apply(dev, lmin):
-    n, r = 1111, 60
+# r + 1 = 61: one 64-column block of the core factorisation; 64 / 65 and
+# 128 / 129: block edges; 301: five blocks and a ragged one, two doubling
+# levels of the inverse; 512: eight full blocks, three levels.
+@pytest.mark.parametrize("lmin,r", [(1e-2, 60), (1e-7, 60), (1e-2, 63), (1e-2, 64), (1e-2, 127), (1e-2, 128),
+                                    (1e-2, 300), (1e-2, 511)])
+def test_woodbury_apply(dev, lmin, r):
+    n = 1111
     g = np.random.default_rng(8)
     F = (g.standard_normal((n, r)) * 0.3).astype(np.float32)
     L = g.uniform(lmin, 2.0, n)
     L[::7] = lmin
     w = g.standard_normal(n)
     c = 0.7
-    say("woodbury", lmin)
+    say("woodbury", lmin, r)
     Ft = torch.zeros((n, (r + 3) // 4 * 4), dtype=torch.float32)
     Ft[:, :r] = torch.from_numpy(F)
     out = kqr.kqr_woodbury_apply(Ft.to(dev), r, c, torch.from_numpy(L).to(dev), torch.from_numpy(w).to(dev)).cpu().numpy()
