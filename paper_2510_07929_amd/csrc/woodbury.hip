@@ -559,15 +559,24 @@ __global__ void transpose_lower_kernel(const double* __restrict__ W, int64_t ldc
 }
 
 // ---------------------------------------------------------------- apply
-// g = w / L ; part[blk][a] = sum_{rows of this block} U_ia g_i
+// g = w / L ; part[blk][a] = sum_{rows of this block} U_ia g_i.  Thread t owns
+// the columns a = t + 256 q (R1 <= 1024) and reads eight rows of each per
+// step, all loads issued before any is used (columns past r read column
+// r - 1 and are dropped), so enough bytes are in flight to stream F.
+template <int NQ>  // NQ = ceil(R1 / 256)
 __global__ __launch_bounds__(256) void wood_gt_kernel(const float* __restrict__ F, int64_t n, int r,
                                                       int64_t ldf, int R1, const double* __restrict__ L,
                                                       const double* __restrict__ w, double* __restrict__ g,
                                                       int64_t chunk, double* __restrict__ part) {
+  constexpr int RU = 8;  // rows per step
+  constexpr int nq = NQ;
   __shared__ double gs[kGtStage];
   const int64_t i0 = int64_t(blockIdx.x) * chunk;
   const int64_t i1 = min(n, i0 + chunk);
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};  // columns a = tid + 256 q (R1 <= 1024)
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};  // column a = tid + 256 q
+  int col[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) col[q] = min(int(threadIdx.x) + 256 * q, max(r - 1, 0));
   for (int64_t sb = i0; sb < i1; sb += kGtStage) {
     const int cnt = int(min<int64_t>(kGtStage, i1 - sb));
     __syncthreads();
@@ -577,27 +586,39 @@ __global__ __launch_bounds__(256) void wood_gt_kernel(const float* __restrict__ 
       gs[k] = gi;
     }
     __syncthreads();
+    double s[4][2];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) s[q][0] = s[q][1] = 0.0;
+    if (r > 0) {  // the same in every lane; an empty factor (F may be null) is never read
+      const float* base = F + sb * ldf;
+      int k = 0;
+      for (; k + RU <= cnt; k += RU) {
+        float f[4][RU];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          if (q < nq)
+#pragma unroll
+            for (int u = 0; u < RU; ++u) f[q][u] = base[int64_t(k + u) * ldf + col[q]];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          if (q < nq)
+#pragma unroll
+            for (int u = 0; u < RU; ++u) s[q][u & 1] = fma(double(f[q][u]), gs[k + u], s[q][u & 1]);
+      }
+      for (; k < cnt; ++k)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          if (q < nq) s[q][0] = fma(double(base[int64_t(k) * ldf + col[q]]), gs[k], s[q][0]);
+    }
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int a = threadIdx.x + 256 * q;
       if (a < r) {
-        const float* col = F + sb * ldf + a;
-        int k = 0;
-        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-        for (; k + 4 <= cnt; k += 4) {
-          const float f0 = col[(k + 0) * ldf], f1 = col[(k + 1) * ldf];
-          const float f2 = col[(k + 2) * ldf], f3 = col[(k + 3) * ldf];
-          s0 = fma(double(f0), gs[k + 0], s0);
-          s1 = fma(double(f1), gs[k + 1], s1);
-          s2 = fma(double(f2), gs[k + 2], s2);
-          s3 = fma(double(f3), gs[k + 3], s3);
-        }
-        for (; k < cnt; ++k) s0 = fma(double(col[k * ldf]), gs[k], s0);
-        acc[q] += (s0 + s1) + (s2 + s3);
+        acc[q] += s[q][0] + s[q][1];
       } else if (a == r) {
-        double s = 0.0;
-        for (int k = 0; k < cnt; ++k) s += gs[k];
-        acc[q] += s;
+        double t = 0.0;
+        for (int k = 0; k < cnt; ++k) t += gs[k];
+        acc[q] += t;
       }
     }
   }
@@ -835,8 +856,16 @@ void Woodbury::apply(const double* w, double* out, const double* dot_with, doubl
                      hipStream_t st) {
   const int R1 = int(R1_);
   const int64_t chunk = (n_ + kGtBlocks - 1) / kGtBlocks;
-  wood_gt_kernel<<<kGtBlocks, 256, 0, st>>>(F_, n_, int(r_), ldf_, R1, L_, w, g_.as<double>(), chunk,
-                                            part_.as<double>());
+  switch ((R1 + 255) / 256) {
+    case 1: wood_gt_kernel<1><<<kGtBlocks, 256, 0, st>>>(F_, n_, int(r_), ldf_, R1, L_, w, g_.as<double>(), chunk,
+                                                         part_.as<double>()); break;
+    case 2: wood_gt_kernel<2><<<kGtBlocks, 256, 0, st>>>(F_, n_, int(r_), ldf_, R1, L_, w, g_.as<double>(), chunk,
+                                                         part_.as<double>()); break;
+    case 3: wood_gt_kernel<3><<<kGtBlocks, 256, 0, st>>>(F_, n_, int(r_), ldf_, R1, L_, w, g_.as<double>(), chunk,
+                                                         part_.as<double>()); break;
+    default: wood_gt_kernel<4><<<kGtBlocks, 256, 0, st>>>(F_, n_, int(r_), ldf_, R1, L_, w, g_.as<double>(), chunk,
+                                                          part_.as<double>()); break;
+  }
   KQR_LAUNCH_CHECK();
   wood_treduce_kernel<<<(R1 + 63) / 64, 1024, 0, st>>>(part_.as<double>(), kGtBlocks, R1, t_.as<double>());
   KQR_LAUNCH_CHECK();
