@@ -218,14 +218,81 @@ __global__ __launch_bounds__(256) void kv_staged_kernel(const void* __restrict__
       }
     }
   };
+  // The stage's rows of V (and of the exact columns' Vx) in 16-byte pieces at
+  // clamped rows, loaded one stage ahead with K; rows past the segment are
+  // zeroed when written to LDS.  FP32: thread t takes half h = t & 1 of row
+  // t / 2 (8 floats); BF16: all 64 bytes of row t (16 hi + 16 lo halves);
+  // exact: threads t < 128 take the 4 doubles of row t.
+  constexpr int NV = BF16 ? 4 : 2;
+  auto load_v = [&](int64_t cb, u32x4 (&pv)[NV], u32x4 (&px)[2]) {
+    const int cnt = int(min<int64_t>(COLS, c1 - cb));
+    const int kk = BF16 ? t : (t >> 1);
+    const int64_t row = cb + min(kk, cnt - 1);
+    if constexpr (BF16) {
+      const u32x4* src = reinterpret_cast<const u32x4*>(Vhl + row * 32);
+#pragma unroll
+      for (int i = 0; i < NV; ++i) pv[i] = src[i];
+    } else {
+      const u32x4* src = reinterpret_cast<const u32x4*>(V + row * 16 + 8 * (t & 1));
+#pragma unroll
+      for (int i = 0; i < NV; ++i) pv[i] = src[i];
+    }
+    if constexpr (MX > 0) {
+      const u32x4* src = reinterpret_cast<const u32x4*>(Vx + (cb + min(t & 127, cnt - 1)) * MX);
+      px[0] = src[0];
+      px[1] = src[1];
+    }
+  };
+  auto store_v = [&](int cnt, const u32x4 (&pv)[NV], const u32x4 (&px)[2]) {
+    if constexpr (BF16) {
+      const bool ok = t < cnt;
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const uint32_t w = ok ? pv[i][e] : 0u;
+          const int j = 8 * (i & 1) + 2 * e;  // halves 2e, 2e + 1 of piece i: columns j, j + 1
+          if (i < 2) {
+            vh[j][t] = uint16_t(w & 0xffffu);
+            vh[j + 1][t] = uint16_t(w >> 16);
+          } else {
+            vl[j][t] = uint16_t(w & 0xffffu);
+            vl[j + 1][t] = uint16_t(w >> 16);
+          }
+        }
+    } else {
+      const int kk = t >> 1, h = t & 1;
+      const bool ok = kk < cnt;
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) vs[8 * h + 4 * i + e][kk] = ok ? __uint_as_float(pv[i][e]) : 0.f;
+    }
+    if constexpr (MX > 0) {
+      if (t < 128) {  // one thread per row of the stage
+        const bool ok = t < cnt;
+        const int slot = (t >> 3) * 10 + (t & 7);
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+          const uint64_t lo = (uint64_t(px[i][1]) << 32) | px[i][0];
+          const uint64_t hi = (uint64_t(px[i][3]) << 32) | px[i][2];
+          vxs[2 * i][slot] = ok ? __longlong_as_double(int64_t(lo)) : 0.0;
+          vxs[2 * i + 1][slot] = ok ? __longlong_as_double(int64_t(hi)) : 0.0;
+        }
+      }
+    }
+  };
   double acc64[4] = {0.0, 0.0, 0.0, 0.0};
   double accx[4][MX > 0 ? MX : 1];
 #pragma unroll
   for (int rr = 0; rr < 4; ++rr)
 #pragma unroll
     for (int j = 0; j < (MX > 0 ? MX : 1); ++j) accx[rr][j] = 0.0;
-  u32x4 pre[8];
-  if (c0 < c1) load_stage(c0, pre);
+  u32x4 pre[8], prev[NV], prex[2];
+  if (c0 < c1) {
+    load_stage(c0, pre);
+    load_v(c0, prev, prex);
+  }
   const int srow = 16 * wave + li;  // this lane's row in the tile (MFMA A operand)
   for (int64_t cb = c0; cb < c1; cb += COLS) {
     const int cnt = int(min<int64_t>(COLS, c1 - cb));
@@ -233,23 +300,12 @@ __global__ __launch_bounds__(256) void kv_staged_kernel(const void* __restrict__
 #pragma unroll
     for (int q = 0; q < 8; ++q)
       *reinterpret_cast<u32x4*>(&ks[((q * 8 + tr) * KPAD + tc * PER) * ESZ]) = pre[q];
-    for (int e = t; e < COLS * 16; e += 256) {
-      const int kk = e >> 4, j = e & 15;
-      if (BF16) {  // hi and lo parts formed once per launch (kv_split_kernel)
-        vh[j][kk] = kk < cnt ? Vhl[(cb + kk) * 32 + j] : uint16_t(0);
-        vl[j][kk] = kk < cnt ? Vhl[(cb + kk) * 32 + 16 + j] : uint16_t(0);
-      } else {
-        vs[j][kk] = kk < cnt ? V[(cb + kk) * 16 + j] : 0.f;
-      }
-    }
-    if (MX > 0) {
-      for (int e = t; e < COLS * MX; e += 256) {
-        const int kk = e / (MX > 0 ? MX : 1), j = e % (MX > 0 ? MX : 1);
-        vxs[j][(kk >> 3) * 10 + (kk & 7)] = kk < cnt ? Vx[(cb + kk) * MX + j] : 0.0;
-      }
-    }
+    store_v(cnt, prev, prex);
     __syncthreads();
-    if (cb + COLS < c1) load_stage(cb + COLS, pre);
+    if (cb + COLS < c1) {
+      load_stage(cb + COLS, pre);
+      load_v(cb + COLS, prev, prex);
+    }
     if (MX > 0) {  // exact columns: rows 4 (t/16) .. +3, columns [8 (t%16), 8 (t%16) + 8) of the stage
       const int xg = t >> 4, xs = t & 15;
       f32x4 kq[4][2];  // this thread's 4 x 8 block of the staged K
