@@ -137,3 +137,18 @@ def test_packed_layout_size():
     assert lib.kqr_packed_bytes(0, 0) == -1 and lib.kqr_packed_bytes(10, 5) == -1
     # about half of the full layout at scale
     assert lib.kqr_packed_bytes(50000, 0) / (50000 * 50048 * 4) < 0.51
+
+
+def test_traffic_summaries_are_tied_to_kernel_sources():
+    # bench.py reports a measured HBM traffic figure only while the digest in
+    # its rocprofv3 summary matches the K-apply source it was measured on
+    from paper_2510_07929_amd import traffic
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    for layout, name in (("rows", "kapply_rows_c1_fp32_traffic.md"), ("packed", "kapply_packed_c1_fp32_traffic.md")):
+        dig = traffic.source_digest(traffic.source_for(layout))
+        assert len(dig) == 16 and int(dig, 16) >= 0
+        got = traffic.read_summary(os.path.join(root, "profiles", name))
+        assert got is not None
+        val, recorded = got
+        assert recorded == dig, f"{name} was measured on another version of the {layout} K-apply"
+        assert 1e9 < val < 2e10
