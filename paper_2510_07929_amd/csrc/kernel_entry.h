@@ -66,4 +66,26 @@ __host__ __device__ __forceinline__ size_t pk_offset(int64_t i, int64_t j, int64
                 : size_t(pk_tile_index(J, I, nt)) * kPkT * kPkT + size_t(j % kPkT) * kPkT + size_t(i % kPkT);
 }
 
+// Strips of `strip` tiles over tile-rows I = 0..nt-1 of the upper triangle,
+// row I holding nt - I tiles: T(M) = sum_{m=1..M} ceil(m / strip) strips over
+// the last M rows.
+__host__ __device__ __forceinline__ int64_t pk_strips_tail(int64_t M, int64_t strip) {
+  const int64_t q = M / strip, r = M % strip;
+  return strip * q * (q + 1) / 2 + r * (q + 1);
+}
+
+// Workgroup b of the 1-D strip grid -> (tile-row I, strip k within the row):
+// rows before I hold pk_strips_tail(nt) - pk_strips_tail(nt - I) strips.
+__device__ __forceinline__ void pk_strip_coords(int64_t b, int64_t nt, int64_t strip, int64_t& I, int64_t& k) {
+  const int64_t total = pk_strips_tail(nt, strip);
+  int64_t lo = 0, hi = nt - 1;  // largest I whose first strip index is <= b
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) / 2;
+    if (total - pk_strips_tail(nt - mid, strip) <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  I = lo;
+  k = b - (total - pk_strips_tail(nt - lo, strip));
+}
+
 }  // namespace kqr

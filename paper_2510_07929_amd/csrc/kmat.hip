@@ -483,107 +483,192 @@ __device__ __forceinline__ uint32_t sad_u32(uint32_t a, uint32_t b, uint32_t c) 
   return r;
 }
 
-template <int PMAX, int R, bool EX>
-__global__ __launch_bounds__(256) void kapply_otf_l1q_kernel(const uint32_t* __restrict__ Xq, int64_t n, int p,
-                                                             float ngs, const double* __restrict__ v,
-                                                             int64_t cols_per_slice, double* __restrict__ part) {
-  // a thread owns R rows (256 R per block), so each LDS read of x_j serves R pairs
+// K is symmetric (Section 1), so each pair is evaluated once: over the
+// upper-triangle tiles of kPkT x kPkT entries of the packed geometry.
+// Workgroup b takes strip k of tile-row I (pk_strip_coords), the tiles
+// J = I + k strip, ... of that row.  Thread t owns the four rows
+// I kPkT + t % 32 + 32 r (fixed-point coordinates in registers, v_i) and in
+// every tile the sixteen columns t / 32 + 8 c, so the two column groups of a
+// wave read adjacent LDS rows (distinct banks) and every 16-byte read of
+// x_j serves four pairs.  Per pair: the distance (one v_sad_u32 per
+// coordinate), the entry, its product with v_j into the row sum and, off
+// the diagonal tile, with v_i into the column sum.  Row sums stay in
+// registers over the strip and are added over the eight column groups at its
+// end (one partial per strip and row); the column sums of a tile are added
+// over the 32 row groups in LDS (one partial per tile and column); a
+// diagonal tile feeds its rows only.  packed_reduce adds the partials in a
+// fixed order.  Fast: FP32 products and sums within a tile, FP64 beyond;
+// exact: FP64 products and sums.
+template <int PMAX, bool EX>
+__global__ __launch_bounds__(256) void kapply_otf_l1q_sym_kernel(const uint32_t* __restrict__ Xq, int64_t n, int p,
+                                                                 float ngs, const double* __restrict__ v, int64_t nt,
+                                                                 int strip, int64_t nsx, double* __restrict__ rowpart,
+                                                                 double* __restrict__ colpart) {
   static_assert(PMAX % 4 == 0, "coordinates are read from LDS four at a time");
-  __shared__ __align__(16) uint32_t xs[kOtfTile][PMAX];
-  __shared__ float vs[kOtfTile];
-  __shared__ double vd[kOtfTile];
-  const int64_t i0 = int64_t(blockIdx.x) * 256 * R + threadIdx.x;
+  constexpr int T = kPkT;
+  constexpr int R = 4;     // rows per thread
+  constexpr int RG = 32;   // row groups: T / R
+  constexpr int CPT = 16;  // columns per thread and tile: T / (256 / RG)
+  __shared__ __align__(16) uint32_t xs[T][PMAX];
+  __shared__ double vs[T];
+  __shared__ double red[RG][T + 1];
+  const int t = threadIdx.x;
+  const int rg = t & (RG - 1), cg = t >> 5;
+  int64_t I, k;
+  pk_strip_coords(blockIdx.x, nt, strip, I, k);
+  const int64_t J0 = I + k * strip, J1 = min(nt, J0 + strip);
+  // Rows past n keep the coordinates of row n - 1 and v_i = 0: their row sums
+  // are never read and their column contributions vanish.  Every load is
+  // issued before any is used (a load whose use is conditional per lane would
+  // be moved under the condition and waited for one at a time).
   uint32_t xi[R][PMAX];
+  double vi[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    const int64_t i = i0 + 256 * r;
+    const int64_t ic = min(I * T + rg + RG * r, n - 1);
 #pragma unroll
-    for (int k = 0; k < PMAX; ++k) xi[r][k] = (i < n && k < p) ? Xq[i * p + k] : 0u;
+    for (int kk = 0; kk < PMAX; ++kk) xi[r][kk] = Xq[ic * p + min(kk, p - 1)];
   }
-  const int64_t c0 = int64_t(blockIdx.y) * cols_per_slice;
-  const int64_t c1 = min(n, c0 + cols_per_slice);
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int64_t i = I * T + rg + RG * r;
+    const double vv = v[min(i, n - 1)];
+    vi[r] = i < n ? vv : 0.0;
+#pragma unroll
+    for (int kk = 0; kk < PMAX; ++kk) xi[r][kk] = kk < p ? xi[r][kk] : 0u;  // padded coordinates: 0 on both sides
+  }
   double acc[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) acc[r] = 0.0;
-  for (int64_t jb = c0; jb < c1; jb += kOtfTile) {
-    const int cnt = int(min<int64_t>(kOtfTile, c1 - jb));
-    __syncthreads();
-    for (int t = threadIdx.x; t < kOtfTile * PMAX; t += 256) {
-      const int jj = t / PMAX, k = t % PMAX;
-      xs[jj][k] = (jj < cnt && k < p) ? Xq[(jb + jj) * p + k] : 0u;
+  // The next tile's columns (coordinates of column n - 1 past n, v_j = 0
+  // there) are loaded into registers while the current tile is evaluated.
+  uint32_t xc[T * PMAX / 256];
+  double vc = 0.0;
+  auto load_cols = [&](int64_t J) {
+#pragma unroll
+    for (int q = 0; q < T * PMAX / 256; ++q) {
+      const int e = t + 256 * q;
+      const int jj = e / PMAX, kk = e % PMAX;
+      xc[q] = Xq[min(J * T + jj, n - 1) * p + min(kk, p - 1)];
     }
-    if (threadIdx.x < kOtfTile) {
-      const int jj = threadIdx.x;
-      const double vj = jj < cnt ? v[jb + jj] : 0.0;
-      if (EX) vd[jj] = vj;
-      else vs[jj] = float(vj);
-    }
+    if (t < T) vc = v[min(J * T + t, n - 1)];
+  };
+  load_cols(J0);
+  for (int64_t J = J0; J < J1; ++J) {
+    const bool diag = J == I;
     __syncthreads();
+#pragma unroll
+    for (int q = 0; q < T * PMAX / 256; ++q) {
+      const int e = t + 256 * q;
+      const int jj = e / PMAX, kk = e % PMAX;
+      xs[jj][kk] = kk < p ? xc[q] : 0u;
+    }
+    if (t < T) vs[t] = J * T + t < n ? vc : 0.0;
+    __syncthreads();
+    if (J + 1 < J1) load_cols(J + 1);
     float a32[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) a32[r] = 0.f;
-    for (int jj = 0; jj < cnt; ++jj) {
+#pragma unroll 2
+    for (int c = 0; c < CPT; ++c) {
+      const int jj = cg + 8 * c;
       uint32_t d[R];
 #pragma unroll
       for (int r = 0; r < R; ++r) d[r] = 0u;
-      const uint4* xr = reinterpret_cast<const uint4*>(xs[jj]);  // broadcast 16-byte LDS reads
+      const uint4* xr = reinterpret_cast<const uint4*>(xs[jj]);  // 16-byte LDS reads, two rows per wave
 #pragma unroll
       for (int k4 = 0; k4 < PMAX / 4; ++k4) {
-        const uint4 c = xr[k4];
+        const uint4 cc = xr[k4];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-          d[r] = sad_u32(xi[r][4 * k4], c.x, d[r]);
-          d[r] = sad_u32(xi[r][4 * k4 + 1], c.y, d[r]);
-          d[r] = sad_u32(xi[r][4 * k4 + 2], c.z, d[r]);
-          d[r] = sad_u32(xi[r][4 * k4 + 3], c.w, d[r]);
+          d[r] = sad_u32(xi[r][4 * k4], cc.x, d[r]);
+          d[r] = sad_u32(xi[r][4 * k4 + 1], cc.y, d[r]);
+          d[r] = sad_u32(xi[r][4 * k4 + 2], cc.z, d[r]);
+          d[r] = sad_u32(xi[r][4 * k4 + 3], cc.w, d[r]);
         }
       }
+      float e[R];
 #pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const float e = kexp2(ngs * float(d[r]));
-        if (EX) acc[r] = fma(double(e), vd[jj], acc[r]);
-        else a32[r] = fmaf(e, vs[jj], a32[r]);
+      for (int r = 0; r < R; ++r) e[r] = kexp2(ngs * float(d[r]));
+      const double vj = vs[jj];
+      if (EX) {
+        double cs = 0.0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          acc[r] = fma(double(e[r]), vj, acc[r]);
+          cs = fma(double(e[r]), vi[r], cs);
+        }
+        if (!diag) red[rg][jj] = cs;
+      } else {
+        float cs = 0.f;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          a32[r] = fmaf(e[r], float(vj), a32[r]);
+          cs = fmaf(e[r], float(vi[r]), cs);
+        }
+        if (!diag) red[rg][jj] = double(cs);
       }
     }
     if (!EX) {
 #pragma unroll
       for (int r = 0; r < R; ++r) acc[r] += double(a32[r]);
     }
+    if (!diag) {  // the same in every thread of the block
+      __syncthreads();
+      if (t < T) {
+        double cs = 0.0;
+#pragma unroll 8
+        for (int g = 0; g < RG; ++g) cs += red[g][t];
+        colpart[size_t(pk_tile_index(I, J, nt)) * T + t] = cs;
+      }
+    }
   }
+  __syncthreads();
 #pragma unroll
-  for (int r = 0; r < R; ++r) {
-    const int64_t i = i0 + 256 * r;
-    if (i < n) part[int64_t(blockIdx.y) * n + i] = acc[r];
+  for (int r = 0; r < R; ++r) red[cg][rg + RG * r] = acc[r];
+  __syncthreads();
+  if (t < T) {
+    double rs = 0.0;
+#pragma unroll
+    for (int g = 0; g < 256 / RG; ++g) rs += red[g][t];
+    rowpart[(size_t(I) * nsx + k) * T + t] = rs;
   }
 }
+
+static int otf_l1q_strip(int64_t n) {  // tiles per workgroup
+  const int64_t nt = (n + kPkT - 1) / kPkT;
+  return nt >= 256 ? 16 : (nt >= 64 ? 8 : 2);
+}
+
+size_t otf_l1q_scratch_doubles(int64_t n) { return packed_scratch_doubles(n, otf_l1q_strip(n)); }
 
 template <int PMAX>
 static void kapply_otf_l1q_p(const uint32_t* Xq, int64_t n, int p, float ngs, const double* v, double* u, int64_t ldu,
-                             bool exact, hipStream_t st) {
-  // rows per thread: 4 up to 32 coordinates, 2 beyond (registers)
-  constexpr int R = PMAX <= 32 ? 4 : 2;
-  const int64_t rblk = (n + 256 * R - 1) / (256 * R);
-  int64_t nslice = otf_slices(rblk, n);
-  nslice = std::min<int64_t>(nslice, 65535);
-  int64_t per = (n + nslice - 1) / nslice;
-  per = (per + kOtfTile - 1) / kOtfTile * kOtfTile;
-  nslice = (n + per - 1) / per;
-  double* part = nullptr;
-  KQR_CHECK_HIP(hipMallocAsync(reinterpret_cast<void**>(&part), size_t(nslice) * size_t(n) * sizeof(double), st));
-  const dim3 grid((unsigned)rblk, (unsigned)nslice);
-  if (exact) kapply_otf_l1q_kernel<PMAX, R, true><<<grid, 256, 0, st>>>(Xq, n, p, ngs, v, per, part);
-  else kapply_otf_l1q_kernel<PMAX, R, false><<<grid, 256, 0, st>>>(Xq, n, p, ngs, v, per, part);
+                             bool exact, hipStream_t st, double* scratch, size_t scratch_doubles) {
+  const int64_t nt = (n + kPkT - 1) / kPkT;
+  const int strip = otf_l1q_strip(n);
+  const int64_t nsx = (nt + strip - 1) / strip;
+  const size_t need = packed_scratch_doubles(n, strip);
+  double* buf = scratch && scratch_doubles >= need ? scratch : nullptr;
+  const bool own = buf == nullptr;
+  if (own) KQR_CHECK_HIP(hipMallocAsync(reinterpret_cast<void**>(&buf), need * sizeof(double), st));
+  double* rowpart = buf;
+  double* colpart = buf + size_t(nt) * nsx * kPkT;
+  const dim3 grid((unsigned)pk_strips_tail(nt, strip));
+  if (exact)
+    kapply_otf_l1q_sym_kernel<PMAX, true><<<grid, 256, 0, st>>>(Xq, n, p, ngs, v, nt, strip, nsx, rowpart, colpart);
+  else
+    kapply_otf_l1q_sym_kernel<PMAX, false><<<grid, 256, 0, st>>>(Xq, n, p, ngs, v, nt, strip, nsx, rowpart, colpart);
   KQR_LAUNCH_CHECK();
-  otf_reduce_kernel<<<dim3((unsigned)((n + 255) / 256)), 256, 0, st>>>(part, int(nslice), n, u, ldu, 1.0, 0.0);
-  KQR_LAUNCH_CHECK();
-  KQR_CHECK_HIP(hipFreeAsync(part, st));
+  packed_reduce(rowpart, colpart, n, strip, u, ldu, st);
+  if (own) KQR_CHECK_HIP(hipFreeAsync(buf, st));
 }
 
 void kapply_otf_l1q(const uint32_t* Xq, int64_t n, int p, double gamma, int shift, const double* v, double* u,
-                    int64_t ldu, bool exact, hipStream_t st) {
+                    int64_t ldu, bool exact, hipStream_t st, double* scratch, size_t scratch_doubles) {
   if (n <= 0) return;
   const float ngs = float(-gamma * double(kLog2e) * std::ldexp(1.0, -shift));
-  KQR_DISPATCH_P(p, kapply_otf_l1q_p, Xq, n, p, ngs, v, u, ldu, exact, st);
+  KQR_DISPATCH_P(p, kapply_otf_l1q_p, Xq, n, p, ngs, v, u, ldu, exact, st, scratch, scratch_doubles);
 }
 
 // Per-column minimum and maximum of X (FP32 values, exact); mm: 2 p floats.

@@ -35,27 +35,6 @@ __device__ __forceinline__ float pk_elem(const pk_u32x4& w, int e) {
   return __uint_as_float(w[e]);
 }
 
-// Strips of `strip` tiles over tile-rows I = 0..nt-1, row I holding nt - I
-// tiles: T(M) = sum_{m=1..M} ceil(m / strip) strips over the last M rows.
-__host__ __device__ __forceinline__ int64_t pk_strips_tail(int64_t M, int64_t strip) {
-  const int64_t q = M / strip, r = M % strip;
-  return strip * q * (q + 1) / 2 + r * (q + 1);
-}
-
-// Workgroup b of the 1-D strip grid -> (tile-row I, strip k within the row):
-// rows before I hold pk_strips_tail(nt) - pk_strips_tail(nt - I) strips.
-__device__ __forceinline__ void pk_strip_coords(int64_t b, int64_t nt, int64_t strip, int64_t& I, int64_t& k) {
-  const int64_t total = pk_strips_tail(nt, strip);
-  int64_t lo = 0, hi = nt - 1;  // largest I whose first strip index is <= b
-  while (lo < hi) {
-    const int64_t mid = (lo + hi + 1) / 2;
-    if (total - pk_strips_tail(nt - mid, strip) <= b) lo = mid;
-    else hi = mid - 1;
-  }
-  I = lo;
-  k = b - (total - pk_strips_tail(nt - lo, strip));
-}
-
 }  // namespace
 
 int64_t packed_tile_count(int64_t n) {
@@ -468,9 +447,16 @@ void kapply_packed(const KMat& km, int64_t n, const float* v32, const double* v6
   else if (bf) packed_launch<true, false>(sh.map, grid, km.K, n, nt, strip, nsx, v32, v64, rowpart, colpart, st);
   else packed_launch<false, false>(sh.map, grid, km.K, n, nt, strip, nsx, v32, v64, rowpart, colpart, st);
   KQR_LAUNCH_CHECK();
+  packed_reduce(rowpart, colpart, n, strip, u, ldu, st);
+  if (!scratch) KQR_CHECK_HIP(hipFreeAsync(buf, st));
+}
+
+void packed_reduce(const double* rowpart, const double* colpart, int64_t n, int strip, double* u, int64_t ldu,
+                   hipStream_t st) {
+  const int64_t nt = (n + kPkT - 1) / kPkT;
+  const int64_t nsx = (nt + strip - 1) / strip;
   packed_reduce_kernel<<<dim3((unsigned)nt), kPkT * kRedSplit, 0, st>>>(rowpart, colpart, n, nt, strip, nsx, u, ldu);
   KQR_LAUNCH_CHECK();
-  if (!scratch) KQR_CHECK_HIP(hipFreeAsync(buf, st));
 }
 
 // ================================================================= one row

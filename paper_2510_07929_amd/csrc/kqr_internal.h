@@ -113,10 +113,13 @@ void kapply_otf(const float* Xr, const float* sqr, int64_t nr, const float* Xc, 
 // distances, one v_sad_u32 per coordinate).  quantize_columns fills Xq
 // (n x p, stride p) with round((x - min_k) 2^s) and returns s (or -1 when X
 // holds non-finite values); kapply_otf_l1q applies K(X, X) with entries
-// exp(-gamma 2^-s d).
+// exp(-gamma 2^-s d), each distinct pair evaluated once.  Its partial sums go
+// to scratch when that holds otf_l1q_scratch_doubles(n) doubles, else to
+// memory allocated on st.
 int quantize_columns(const float* X, int64_t n, int p, uint32_t* Xq, hipStream_t st);
+size_t otf_l1q_scratch_doubles(int64_t n);
 void kapply_otf_l1q(const uint32_t* Xq, int64_t n, int p, double gamma, int shift, const double* v, double* u,
-                    int64_t ldu, bool exact, hipStream_t st);
+                    int64_t ldu, bool exact, hipStream_t st, double* scratch = nullptr, size_t scratch_doubles = 0);
 // y = A x for a skinny FP32 matrix A (nrows x ncols, ncols <= 1024, lda a
 // multiple of 4) and FP64 x, y; FP64 products and sums.
 void gemv_skinny(const float* A, int64_t lda, int64_t nrows, int64_t ncols, const double* x, double* y,
@@ -133,6 +136,11 @@ void kbuild_packed(const float* X, const float* sqn, int64_t n, int p, KernelSpe
                    hipStream_t st);
 // Doubles of scratch kapply_packed needs (strip partials + column partials).
 size_t packed_scratch_doubles(int64_t n, int strip);
+// u[i ldu] = the strip partials of i's tile-row (rowpart: nt x ceil(nt/strip)
+// x kPkT) plus the column partials of the tiles above i's diagonal tile
+// (colpart: one kPkT-vector per upper-triangle tile), in a fixed order.
+void packed_reduce(const double* rowpart, const double* colpart, int64_t n, int strip, double* u, int64_t ldu,
+                   hipStream_t st);
 // Launch shape of the packed K-apply: thread map (0 rows / 256 threads,
 // 1 columns, 2 rows / 512 threads, 3 = 2 on a persistent grid) and tiles per
 // workgroup strip.

@@ -58,11 +58,12 @@ class Operator {
   KMat km_;
   KMat kexact_;
   DevBuf sqn_, v32_;
-  DevBuf scr_;  // partial sums of the materialised applies (allocated on first use)
+  DevBuf scr_;  // partial sums of the materialised and symmetric on-the-fly applies (allocated on first use)
   DevBuf lin_;  // linear kernel: block partials and X^T v
   DevBuf xq_;   // Laplacian: fixed-point X (entries recomputed on every apply)
   int shift_ = -1;
   double* scratch(const KMat& k, size_t& doubles);
+  double* scratch(size_t doubles);  // at least that many doubles, kept for later applies
   int64_t calls_ = 0;
   bool profile_ = false;
   std::vector<Span> spans_;

@@ -68,13 +68,17 @@ void Operator::profile_totals(int64_t& nfast, double& tfast, int64_t& nexact, do
   }
 }
 
-double* Operator::scratch(const KMat& k, size_t& doubles) {
-  doubles = kapply_scratch_doubles(k, n_);
+double* Operator::scratch(size_t doubles) {
   if (scr_.bytes < doubles * sizeof(double)) {
     scr_ = DevBuf();
     scr_.alloc(doubles * sizeof(double));
   }
   return scr_.as<double>();
+}
+
+double* Operator::scratch(const KMat& k, size_t& doubles) {
+  doubles = kapply_scratch_doubles(k, n_);
+  return scratch(doubles);
 }
 
 void Operator::apply_fast(const double* v, const float* v32, double* u, hipStream_t st) {
@@ -100,8 +104,10 @@ void Operator::apply_fast(const double* v, const float* v32, double* u, hipStrea
     kapply_dense(km_, n_, n_, v32, nullptr, u, 1, false, st, nullptr, scr, nd);
     mark(false, true, st);
   } else if (xq_.ptr) {
+    const size_t nd = otf_l1q_scratch_doubles(n_);
+    double* scr = scratch(nd);
     mark(true, true, st);
-    kapply_otf_l1q(xq_.as<uint32_t>(), n_, p_, ks_.gamma, shift_, v, u, 1, false, st);
+    kapply_otf_l1q(xq_.as<uint32_t>(), n_, p_, ks_.gamma, shift_, v, u, 1, false, st, scr, nd);
     mark(false, true, st);
   } else {
     mark(true, true, st);
@@ -117,7 +123,9 @@ void Operator::apply_exact(const double* v, double* u, hipStream_t st) {
     return;
   }
   size_t nd = 0;
-  double* scr = km_.K ? scratch(km_.dtype == KQR_FP32 || !kexact_.K ? km_ : kexact_, nd) : nullptr;
+  double* scr = nullptr;
+  if (km_.K) scr = scratch(km_.dtype == KQR_FP32 || !kexact_.K ? km_ : kexact_, nd);
+  else if (xq_.ptr) scr = scratch(nd = otf_l1q_scratch_doubles(n_));
   mark(true, false, st);
   if (ks_.kind == KQR_LINEAR) {
     lin_apply(X_, n_, p_, v, u, 1, lin_.as<double>(), st);
@@ -126,7 +134,7 @@ void Operator::apply_exact(const double* v, double* u, hipStream_t st) {
   } else if (kexact_.K) {
     kapply_dense(kexact_, n_, n_, nullptr, v, u, 1, true, st, nullptr, scr, nd);
   } else if (xq_.ptr) {
-    kapply_otf_l1q(xq_.as<uint32_t>(), n_, p_, ks_.gamma, shift_, v, u, 1, true, st);
+    kapply_otf_l1q(xq_.as<uint32_t>(), n_, p_, ks_.gamma, shift_, v, u, 1, true, st, scr, nd);
   } else {
     // BF16 storage is not the exact operator: recompute FP32 entries from X.
     kapply_otf(X_, sqn_.as<float>(), n_, X_, sqn_.as<float>(), n_, p_, ks_, v, u, 1, 1.0, 0.0, st, true);
