@@ -635,18 +635,18 @@ __global__ __launch_bounds__(256) void kapply_otf_l1q_sym_kernel(const uint32_t*
   }
 }
 
-static int otf_l1q_strip(int64_t n) {  // tiles per workgroup
+static int otf_sym_strip(int64_t n) {  // tiles per workgroup of the symmetric applies
   const int64_t nt = (n + kPkT - 1) / kPkT;
   return nt >= 256 ? 16 : (nt >= 64 ? 8 : 2);
 }
 
-size_t otf_l1q_scratch_doubles(int64_t n) { return packed_scratch_doubles(n, otf_l1q_strip(n)); }
+size_t otf_sym_scratch_doubles(int64_t n) { return packed_scratch_doubles(n, otf_sym_strip(n)); }
 
 template <int PMAX>
 static void kapply_otf_l1q_p(const uint32_t* Xq, int64_t n, int p, float ngs, const double* v, double* u, int64_t ldu,
                              bool exact, hipStream_t st, double* scratch, size_t scratch_doubles) {
   const int64_t nt = (n + kPkT - 1) / kPkT;
-  const int strip = otf_l1q_strip(n);
+  const int strip = otf_sym_strip(n);
   const int64_t nsx = (nt + strip - 1) / strip;
   const size_t need = packed_scratch_doubles(n, strip);
   double* buf = scratch && scratch_doubles >= need ? scratch : nullptr;
@@ -1070,10 +1070,210 @@ __global__ __launch_bounds__(256) void kapply_otf_mfma3_kernel(
   }
 }
 
+// Symmetric form of the BF16x3 apply for the square K(X, X): each distinct
+// pair once, over the upper-triangle 128 x 128 tiles of the packed geometry.
+// A workgroup takes a strip of tiles of tile-row I; its rows are held as in
+// kapply_otf_mfma3_kernel (wave w: rows 32 w .. 32 w + 31 of the tile-row,
+// split once into registers) and each tile J is one 128-column stage.
+// Every entry feeds the row sum (times v_j) and, off the diagonal tile, the
+// column sum (times v_i): a lane adds its eight rows, the four lane groups
+// are added across lanes and the four waves in LDS.  Row sums are added over
+// the 16 column lanes at the end of the strip.  packed_reduce adds the
+// partials in a fixed order.
+template <bool EX, bool AUG>
+__global__ __launch_bounds__(256) void kapply_otf_mfma3_sym_kernel(
+    const float* __restrict__ X, const float* __restrict__ q, int64_t n, const uint16_t* __restrict__ Bc, int p,
+    float ng, const double* __restrict__ v, int64_t nt, int strip, int64_t nsx, double* __restrict__ rowpart,
+    double* __restrict__ colpart) {
+  static_assert(kB3Cols == kPkT, "one stage per tile");
+  __shared__ __align__(16) uint16_t bs[3][kB3Cols][kB3Row];
+  __shared__ float qs[AUG ? 1 : kB3Cols];
+  __shared__ double vd[kB3Cols];
+  __shared__ double red[4][kB3Cols];
+  const int t = threadIdx.x;
+  const int lane = t & 63, wave = t >> 6;
+  const int li = lane & 15, lg = lane >> 4;
+  int64_t I, kst;
+  pk_strip_coords(blockIdx.x, nt, strip, I, kst);
+  const int64_t J0 = I + kst * strip, J1 = min(nt, J0 + strip);
+  const int64_t row0 = I * kPkT + wave * 32;
+  bf16x8_t ah[2], am[2], al[2];
+  float qi[2][4];
+  double vi[2][4];
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    const int64_t r = row0 + 16 * s + li;
+    const bool in = r < n;
+    const float qq = (AUG && in) ? q[r] : 0.f;
+    u16x8_t h, m, l;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int k = 8 * lg + e;
+      const float x = in ? b3_coord<AUG, false>(X + r * p, qq, k, p, 1.f) : 0.f;
+      uint16_t hh, mm, ll;
+      split3_bf16(x, hh, mm, ll);
+      h[e] = hh;
+      m[e] = mm;
+      l[e] = ll;
+    }
+    ah[s] = __builtin_bit_cast(bf16x8_t, h);
+    am[s] = __builtin_bit_cast(bf16x8_t, m);
+    al[s] = __builtin_bit_cast(bf16x8_t, l);
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) {
+      const int64_t ro = row0 + 16 * s + 4 * lg + rr;
+      const int64_t rc = min(ro, n - 1);
+      const float qv = q[rc];
+      const double vv = v[rc];
+      qi[s][rr] = (!AUG && ro < n) ? qv : 0.f;
+      vi[s][rr] = ro < n ? vv : 0.0;  // rows past n add nothing to the column sums
+    }
+  }
+  double acc[2][4];
+#pragma unroll
+  for (int s = 0; s < 2; ++s)
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) acc[s][rr] = 0.0;
+  for (int64_t J = J0; J < J1; ++J) {
+    const bool diag = J == I;
+    const int64_t jb = J * kPkT;
+    const int cnt = int(min<int64_t>(kB3Cols, n - jb));
+    __syncthreads();
+    for (int e = t; e < kB3Cols * 12; e += 256) {
+      const int jj = e / 12, r = e - 12 * (e / 12), pl = r >> 2, g = r & 3;
+      u16x8_t val = u16x8_t{0, 0, 0, 0, 0, 0, 0, 0};
+      if (jj < cnt) val = *reinterpret_cast<const u16x8_t*>(Bc + (jb + jj) * kB3Stride + 32 * pl + 8 * g);
+      *reinterpret_cast<u16x8_t*>(&bs[pl][jj][8 * g]) = val;
+    }
+    if (t < kB3Cols) {
+      if (!AUG) qs[t] = t < cnt ? q[jb + t] : 0.f;
+      vd[t] = t < cnt ? v[jb + t] : 0.0;
+    }
+    __syncthreads();
+    float a32[2][4];
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) a32[s][rr] = 0.f;
+    for (int t16 = 0; t16 < cnt; t16 += 16) {
+      const int jj = t16 + li;
+      const bf16x8_t b_h = *reinterpret_cast<const bf16x8_t*>(&bs[0][jj][8 * lg]);
+      const bf16x8_t b_m = *reinterpret_cast<const bf16x8_t*>(&bs[1][jj][8 * lg]);
+      const bf16x8_t b_l = *reinterpret_cast<const bf16x8_t*>(&bs[2][jj][8 * lg]);
+      f32x4_t g[2];
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {  // smallest products first
+        f32x4_t c = f32x4_t{0.f, 0.f, 0.f, 0.f};
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am[s], b_m, c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[s], b_l, c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[s], b_h, c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[s], b_m, c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am[s], b_h, c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[s], b_h, c, 0, 0, 0);
+        g[s] = c;
+      }
+      const float qj = AUG ? 0.f : qs[jj];
+      const double vj = vd[jj];
+      double cs64 = 0.0;
+      float cs32 = 0.f;
+#pragma unroll
+      for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+          // ng < 0: min(ng d, 0) = ng max(d, 0)
+          const float a = AUG ? g[s][rr] : ng * (qi[s][rr] + qj + g[s][rr]);
+          const float e = kexp2(fminf(a, 0.f));
+          if (EX) {
+            acc[s][rr] = fma(double(e), vj, acc[s][rr]);
+            cs64 = fma(double(e), vi[s][rr], cs64);
+          } else {
+            a32[s][rr] = fmaf(e, float(vj), a32[s][rr]);
+            cs32 = fmaf(e, float(vi[s][rr]), cs32);
+          }
+        }
+      if (!diag) {  // the column's 32 rows of this wave: add the four lane groups
+        double cs = EX ? cs64 : double(cs32);
+        cs += __shfl_xor(cs, 16);
+        cs += __shfl_xor(cs, 32);
+        if (lg == 0) red[wave][jj] = cs;
+      }
+    }
+    if (!EX) {
+#pragma unroll
+      for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) acc[s][rr] += double(a32[s][rr]);
+    }
+    if (!diag) {  // the same in every thread of the block
+      __syncthreads();
+      if (t < kB3Cols)
+        colpart[size_t(pk_tile_index(I, J, nt)) * kPkT + t] = ((red[0][t] + red[1][t]) + red[2][t]) + red[3][t];
+    }
+  }
+  // row sums over the 16 column lanes of each row group (lane bits 0..3)
+#pragma unroll
+  for (int s = 0; s < 2; ++s)
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) {
+      double x = acc[s][rr];
+#pragma unroll
+      for (int off = 1; off < 16; off <<= 1) x += __shfl_xor(x, off);
+      acc[s][rr] = x;
+    }
+  if (li == 0) {
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr)
+        rowpart[(size_t(I) * nsx + kst) * kPkT + wave * 32 + 16 * s + 4 * lg + rr] = acc[s][rr];
+  }
+}
+
+// K(X, X) v with each distinct pair once (p in (16, 32], RBF); u = K v.
+static void kapply_otf_mfma3_sym(const float* X, const float* q, int64_t n, int p, KernelSpec ks, const double* v,
+                                 double* u, int64_t ldu, bool exact, hipStream_t st, double* scratch,
+                                 size_t scratch_doubles) {
+  const int64_t nt = (n + kPkT - 1) / kPkT;
+  const int strip = otf_sym_strip(n);
+  const int64_t nsx = (nt + strip - 1) / strip;
+  const size_t need = packed_scratch_doubles(n, strip);
+  const size_t split_bytes = size_t(n) * kB3Stride * sizeof(uint16_t);
+  double* part = scratch && scratch_doubles >= need ? scratch : nullptr;
+  const size_t part_bytes = part ? 0 : (need * sizeof(double) + 255) / 256 * 256;
+  char* buf = nullptr;
+  KQR_CHECK_HIP(hipMallocAsync(reinterpret_cast<void**>(&buf), part_bytes + split_bytes, st));
+  if (!part) part = reinterpret_cast<double*>(buf);
+  uint16_t* bc = reinterpret_cast<uint16_t*>(buf + part_bytes);
+  double* rowpart = part;
+  double* colpart = part + size_t(nt) * nsx * kPkT;
+  const float ng = -float(ks.gamma) * kLog2e;
+  const bool aug = p <= 30;
+  const dim3 sgrid((unsigned)((n * 4 + 255) / 256));
+  if (aug) kotf_split_cols_kernel<true><<<sgrid, 256, 0, st>>>(X, q, n, p, ng, bc);
+  else kotf_split_cols_kernel<false><<<sgrid, 256, 0, st>>>(X, q, n, p, ng, bc);
+  KQR_LAUNCH_CHECK();
+  const dim3 grid((unsigned)pk_strips_tail(nt, strip));
+  if (aug && exact)
+    kapply_otf_mfma3_sym_kernel<true, true><<<grid, 256, 0, st>>>(X, q, n, bc, p, ng, v, nt, strip, nsx, rowpart, colpart);
+  else if (aug)
+    kapply_otf_mfma3_sym_kernel<false, true><<<grid, 256, 0, st>>>(X, q, n, bc, p, ng, v, nt, strip, nsx, rowpart, colpart);
+  else if (exact)
+    kapply_otf_mfma3_sym_kernel<true, false><<<grid, 256, 0, st>>>(X, q, n, bc, p, ng, v, nt, strip, nsx, rowpart, colpart);
+  else
+    kapply_otf_mfma3_sym_kernel<false, false><<<grid, 256, 0, st>>>(X, q, n, bc, p, ng, v, nt, strip, nsx, rowpart, colpart);
+  KQR_LAUNCH_CHECK();
+  packed_reduce(rowpart, colpart, n, strip, u, ldu, st);
+  KQR_CHECK_HIP(hipFreeAsync(buf, st));
+}
+
 template <int KP>
 static void kapply_otf_mfma_p(const float* Xr, const float* qr, int64_t nr, const float* Xc, const float* qc,
                               int64_t nc, int p, KernelSpec ks, const double* v, double* u, int64_t ldu, double scale,
-                              double shift, bool exact, hipStream_t st) {
+                              double shift, bool exact, hipStream_t st, double* scratch, size_t scratch_doubles) {
+  if (KP > 16 && Xr == Xc && qr == qc && nr == nc && scale == 1.0 && shift == 0.0) {  // square K(X, X): symmetric
+    kapply_otf_mfma3_sym(Xr, qr, nr, p, ks, v, u, ldu, exact, st, scratch, scratch_doubles);
+    return;
+  }
   const int64_t rblk = (nr + 127) / 128;
   int64_t nslice = otf_slices(rblk, nc);
   nslice = std::min<int64_t>(nslice, 65535);
@@ -1112,19 +1312,24 @@ static void kapply_otf_mfma_p(const float* Xr, const float* qr, int64_t nr, cons
 
 void kapply_otf(const float* Xr, const float* sqr, int64_t nr, const float* Xc, const float* sqc,
                 int64_t nc, int p, KernelSpec ks, const double* v64, double* u, int64_t ldu,
-                double out_scale, double out_shift, hipStream_t st, bool exact) {
+                double out_scale, double out_shift, hipStream_t st, bool exact, double* scratch,
+                size_t scratch_doubles) {
   if (nr <= 0) return;
   if (ks.kind == KQR_RBF && p <= 32) {
+#define KQR_OTF_MFMA(KP) \
+  kapply_otf_mfma_p<KP>(Xr, sqr, nr, Xc, sqc, nc, p, ks, v64, u, ldu, out_scale, out_shift, exact, st, scratch, \
+                        scratch_doubles)
     switch ((p + 3) / 4) {
       case 1:
-      case 2: kapply_otf_mfma_p<8>(Xr, sqr, nr, Xc, sqc, nc, p, ks, v64, u, ldu, out_scale, out_shift, exact, st); return;
-      case 3: kapply_otf_mfma_p<12>(Xr, sqr, nr, Xc, sqc, nc, p, ks, v64, u, ldu, out_scale, out_shift, exact, st); return;
-      case 4: kapply_otf_mfma_p<16>(Xr, sqr, nr, Xc, sqc, nc, p, ks, v64, u, ldu, out_scale, out_shift, exact, st); return;
-      case 5: kapply_otf_mfma_p<20>(Xr, sqr, nr, Xc, sqc, nc, p, ks, v64, u, ldu, out_scale, out_shift, exact, st); return;
-      case 6: kapply_otf_mfma_p<24>(Xr, sqr, nr, Xc, sqc, nc, p, ks, v64, u, ldu, out_scale, out_shift, exact, st); return;
-      case 7: kapply_otf_mfma_p<28>(Xr, sqr, nr, Xc, sqc, nc, p, ks, v64, u, ldu, out_scale, out_shift, exact, st); return;
-      default: kapply_otf_mfma_p<32>(Xr, sqr, nr, Xc, sqc, nc, p, ks, v64, u, ldu, out_scale, out_shift, exact, st); return;
+      case 2: KQR_OTF_MFMA(8); return;
+      case 3: KQR_OTF_MFMA(12); return;
+      case 4: KQR_OTF_MFMA(16); return;
+      case 5: KQR_OTF_MFMA(20); return;
+      case 6: KQR_OTF_MFMA(24); return;
+      case 7: KQR_OTF_MFMA(28); return;
+      default: KQR_OTF_MFMA(32); return;
     }
+#undef KQR_OTF_MFMA
   }
   KQR_DISPATCH_P(p, kapply_otf_p, Xr, sqr, nr, Xc, sqc, nc, p, ks, v64, u, ldu, out_scale, out_shift, exact, st);
 }

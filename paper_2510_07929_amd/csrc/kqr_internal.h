@@ -106,18 +106,22 @@ size_t kapply_scratch_doubles(const KMat& km, int64_t n);
 // u = shift + scale K(Xr, Xc) v computed on the fly from FP32 entries.
 // exact = false: v rounded to FP32, FP32 products summed in FP32 over tiles
 // of 64 columns, FP64 across tiles; exact = true: FP64 v, products and sums.
+// The square apply K(X, X) v (Xr == Xc, scale 1, shift 0) of the RBF with
+// 16 < p <= 32 evaluates each distinct pair once; its partial sums go to
+// scratch when that holds otf_sym_scratch_doubles(n) doubles.
 void kapply_otf(const float* Xr, const float* sqr, int64_t nr, const float* Xc, const float* sqc,
                 int64_t nc, int p, KernelSpec ks, const double* v64, double* u, int64_t ldu,
-                double out_scale, double out_shift, hipStream_t st, bool exact = false);
+                double out_scale, double out_shift, hipStream_t st, bool exact = false, double* scratch = nullptr,
+                size_t scratch_doubles = 0);
 // Laplacian on the fly from fixed-point coordinates (exact integer L1
 // distances, one v_sad_u32 per coordinate).  quantize_columns fills Xq
 // (n x p, stride p) with round((x - min_k) 2^s) and returns s (or -1 when X
 // holds non-finite values); kapply_otf_l1q applies K(X, X) with entries
 // exp(-gamma 2^-s d), each distinct pair evaluated once.  Its partial sums go
-// to scratch when that holds otf_l1q_scratch_doubles(n) doubles, else to
+// to scratch when that holds otf_sym_scratch_doubles(n) doubles, else to
 // memory allocated on st.
 int quantize_columns(const float* X, int64_t n, int p, uint32_t* Xq, hipStream_t st);
-size_t otf_l1q_scratch_doubles(int64_t n);
+size_t otf_sym_scratch_doubles(int64_t n);  // partial sums of a symmetric on-the-fly apply
 void kapply_otf_l1q(const uint32_t* Xq, int64_t n, int p, double gamma, int shift, const double* v, double* u,
                     int64_t ldu, bool exact, hipStream_t st, double* scratch = nullptr, size_t scratch_doubles = 0);
 // y = A x for a skinny FP32 matrix A (nrows x ncols, ncols <= 1024, lda a

@@ -104,7 +104,7 @@ void Operator::apply_fast(const double* v, const float* v32, double* u, hipStrea
     kapply_dense(km_, n_, n_, v32, nullptr, u, 1, false, st, nullptr, scr, nd);
     mark(false, true, st);
   } else if (xq_.ptr) {
-    const size_t nd = otf_l1q_scratch_doubles(n_);
+    const size_t nd = otf_sym_scratch_doubles(n_);
     double* scr = scratch(nd);
     mark(true, true, st);
     kapply_otf_l1q(xq_.as<uint32_t>(), n_, p_, ks_.gamma, shift_, v, u, 1, false, st, scr, nd);
@@ -125,7 +125,7 @@ void Operator::apply_exact(const double* v, double* u, hipStream_t st) {
   size_t nd = 0;
   double* scr = nullptr;
   if (km_.K) scr = scratch(km_.dtype == KQR_FP32 || !kexact_.K ? km_ : kexact_, nd);
-  else if (xq_.ptr) scr = scratch(nd = otf_l1q_scratch_doubles(n_));
+  else if (xq_.ptr) scr = scratch(nd = otf_sym_scratch_doubles(n_));
   mark(true, false, st);
   if (ks_.kind == KQR_LINEAR) {
     lin_apply(X_, n_, p_, v, u, 1, lin_.as<double>(), st);
@@ -137,7 +137,8 @@ void Operator::apply_exact(const double* v, double* u, hipStream_t st) {
     kapply_otf_l1q(xq_.as<uint32_t>(), n_, p_, ks_.gamma, shift_, v, u, 1, true, st, scr, nd);
   } else {
     // BF16 storage is not the exact operator: recompute FP32 entries from X.
-    kapply_otf(X_, sqn_.as<float>(), n_, X_, sqn_.as<float>(), n_, p_, ks_, v, u, 1, 1.0, 0.0, st, true);
+    scr = scratch(nd = otf_sym_scratch_doubles(n_));
+    kapply_otf(X_, sqn_.as<float>(), n_, X_, sqn_.as<float>(), n_, p_, ks_, v, u, 1, 1.0, 0.0, st, true, scr, nd);
   }
   mark(false, false, st);
 }
