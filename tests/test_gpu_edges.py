@@ -96,3 +96,23 @@ def test_on_the_fly_rbf_beyond_matrix_core_path(dev):
     X, y = inputs.smooth(1100, 40, (603, 0))
     say("on the fly, p = 40")
     _fit_and_compare(dev, X, y, 0.6, 1.1, "rbf", 1.0 / 40, kmode=kqr.KQR_KMODE_ON_THE_FLY)
+
+
+# The square on-the-fly applies evaluate each distinct pair once over
+# 128 x 128 upper-triangle tiles: one point, a partial single tile, exactly
+# one tile, one tile and one column, and two tiles with a one-row tail.
+@pytest.mark.parametrize("kind,p", [("laplacian", 30), ("rbf", 30), ("rbf", 32)])
+@pytest.mark.parametrize("n", [1, 5, 127, 128, 129, 257])
+@pytest.mark.parametrize("mode", [kqr.KQR_APPLY_FAST, kqr.KQR_APPLY_EXACT])
+def test_on_the_fly_symmetric_apply_tile_edges(dev, kind, p, n, mode):
+    X, _ = inputs.additive(n, p, (611, n))
+    v = np.random.default_rng(n).standard_normal(n)
+    gamma = 1.0 / p
+    say("otf tile edges", kind, p, n, mode)
+    u = kqr.kqr_kernel_apply(torch.from_numpy(v).to(dev), X=torch.from_numpy(X).to(dev), kernel=kind,
+                             gamma=gamma, mode=mode).cpu().numpy()
+    from tests.test_gpu_parity import _apply_bound, entry_bound  # the FP32 entry and sum bounds
+    Kref, Kb = entry_bound(X, kind, gamma)
+    bound = _apply_bound(Kb, Kref, v, mode, otf=True)
+    err = np.abs(u - Kref @ v)
+    assert np.all(err <= bound), float((err / bound).max())
