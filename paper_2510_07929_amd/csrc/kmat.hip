@@ -1229,30 +1229,175 @@ __global__ __launch_bounds__(256) void kapply_otf_mfma3_sym_kernel(
   }
 }
 
-// K(X, X) v with each distinct pair once (p in (16, 32], RBF); u = K v.
-static void kapply_otf_mfma3_sym(const float* X, const float* q, int64_t n, int p, KernelSpec ks, const double* v,
-                                 double* u, int64_t ldu, bool exact, hipStream_t st, double* scratch,
-                                 size_t scratch_doubles) {
+// The same for p <= 16 with the Gram term on v_mfma_f32_16x16x4f32 (FP32
+// operands, as kapply_otf_mfma_kernel): each distinct pair of the square
+// K(X, X) once, in the strip and tile geometry above.
+template <int KP, bool EX>
+__global__ __launch_bounds__(256) void kapply_otf_mfma_sym_kernel(
+    const float* __restrict__ X, const float* __restrict__ q, int64_t n, int p, float ng,
+    const double* __restrict__ v, int64_t nt, int strip, int64_t nsx, double* __restrict__ rowpart,
+    double* __restrict__ colpart) {
+  constexpr int NKB = KP / 4;
+  constexpr int T = kPkT;
+  __shared__ float xs[T][KP + 1];
+  __shared__ float qs[T];
+  __shared__ double vd[T];
+  __shared__ double red[4][T];
+  const int t = threadIdx.x;
+  const int lane = t & 63, wave = t >> 6;
+  const int li = lane & 15, lg = lane >> 4;
+  int64_t I, kst;
+  pk_strip_coords(blockIdx.x, nt, strip, I, kst);
+  const int64_t J0 = I + kst * strip, J1 = min(nt, J0 + strip);
+  const int64_t row0 = I * T + wave * 32;
+  float a[2][NKB];
+  float qi[2][4];
+  double vi[2][4];
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    const int64_t r = row0 + 16 * s + li;
+#pragma unroll
+    for (int kb = 0; kb < NKB; ++kb) {
+      const int k = 4 * kb + lg;
+      a[s][kb] = (r < n && k < p) ? X[r * p + k] : 0.f;
+    }
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) {
+      const int64_t ro = row0 + 16 * s + 4 * lg + rr;
+      const int64_t rc = min(ro, n - 1);
+      const float qv = q[rc];
+      const double vv = v[rc];
+      qi[s][rr] = ro < n ? qv : 0.f;
+      vi[s][rr] = ro < n ? vv : 0.0;  // rows past n add nothing to the column sums
+    }
+  }
+  double acc[2][4];
+#pragma unroll
+  for (int s = 0; s < 2; ++s)
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) acc[s][rr] = 0.0;
+  for (int64_t J = J0; J < J1; ++J) {
+    const bool diag = J == I;
+    const int64_t jb = J * T;
+    const int cnt = int(min<int64_t>(T, n - jb));
+    __syncthreads();
+    for (int e = t; e < T * KP; e += 256) {
+      const int jj = e / KP, k = e % KP;
+      xs[jj][k] = (jj < cnt && k < p) ? X[(jb + jj) * p + k] : 0.f;
+    }
+    if (t < T) {
+      qs[t] = t < cnt ? q[jb + t] : 0.f;
+      vd[t] = t < cnt ? v[jb + t] : 0.0;
+    }
+    __syncthreads();
+    float a32[2][4];
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) a32[s][rr] = 0.f;
+    for (int t16 = 0; t16 < cnt; t16 += 16) {
+      const int jj = t16 + li;
+      float b[NKB];
+#pragma unroll
+      for (int kb = 0; kb < NKB; ++kb) b[kb] = xs[jj][4 * kb + lg];
+      f32x4_t g0 = f32x4_t{0.f, 0.f, 0.f, 0.f}, g1 = f32x4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int kb = 0; kb < NKB; ++kb) {
+        g0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a[0][kb], b[kb], g0, 0, 0, 0);
+        g1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a[1][kb], b[kb], g1, 0, 0, 0);
+      }
+      const float qj = qs[jj];
+      const double vj = vd[jj];
+      double cs64 = 0.0;
+      float cs32 = 0.f;
+#pragma unroll
+      for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+          const float gg = s == 0 ? g0[rr] : g1[rr];
+          const float d = fmaxf(qi[s][rr] + qj - 2.f * gg, 0.f);
+          const float e = kexp2(ng * d);
+          if (EX) {
+            acc[s][rr] = fma(double(e), vj, acc[s][rr]);
+            cs64 = fma(double(e), vi[s][rr], cs64);
+          } else {
+            a32[s][rr] = fmaf(e, float(vj), a32[s][rr]);
+            cs32 = fmaf(e, float(vi[s][rr]), cs32);
+          }
+        }
+      if (!diag) {  // the column's 32 rows of this wave: add the four lane groups
+        double cs = EX ? cs64 : double(cs32);
+        cs += __shfl_xor(cs, 16);
+        cs += __shfl_xor(cs, 32);
+        if (lg == 0) red[wave][jj] = cs;
+      }
+    }
+    if (!EX) {
+#pragma unroll
+      for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) acc[s][rr] += double(a32[s][rr]);
+    }
+    if (!diag) {  // the same in every thread of the block
+      __syncthreads();
+      if (t < T) colpart[size_t(pk_tile_index(I, J, nt)) * T + t] = ((red[0][t] + red[1][t]) + red[2][t]) + red[3][t];
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < 2; ++s)
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) {
+      double x = acc[s][rr];
+#pragma unroll
+      for (int off = 1; off < 16; off <<= 1) x += __shfl_xor(x, off);
+      acc[s][rr] = x;
+    }
+  if (li == 0) {
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr)
+        rowpart[(size_t(I) * nsx + kst) * T + wave * 32 + 16 * s + 4 * lg + rr] = acc[s][rr];
+  }
+}
+
+// K(X, X) v with each distinct pair once (RBF, p <= 32; KP = p rounded up to
+// 4, the BF16x3 Gram above 16); u = K v.
+template <int KP>
+static void kapply_otf_mfma_sym(const float* X, const float* q, int64_t n, int p, KernelSpec ks, const double* v,
+                                double* u, int64_t ldu, bool exact, hipStream_t st, double* scratch,
+                                size_t scratch_doubles) {
   const int64_t nt = (n + kPkT - 1) / kPkT;
   const int strip = otf_sym_strip(n);
   const int64_t nsx = (nt + strip - 1) / strip;
   const size_t need = packed_scratch_doubles(n, strip);
-  const size_t split_bytes = size_t(n) * kB3Stride * sizeof(uint16_t);
+  const size_t split_bytes = KP > 16 ? size_t(n) * kB3Stride * sizeof(uint16_t) : 0;
   double* part = scratch && scratch_doubles >= need ? scratch : nullptr;
   const size_t part_bytes = part ? 0 : (need * sizeof(double) + 255) / 256 * 256;
   char* buf = nullptr;
-  KQR_CHECK_HIP(hipMallocAsync(reinterpret_cast<void**>(&buf), part_bytes + split_bytes, st));
+  if (part_bytes + split_bytes > 0)
+    KQR_CHECK_HIP(hipMallocAsync(reinterpret_cast<void**>(&buf), part_bytes + split_bytes, st));
   if (!part) part = reinterpret_cast<double*>(buf);
-  uint16_t* bc = reinterpret_cast<uint16_t*>(buf + part_bytes);
   double* rowpart = part;
   double* colpart = part + size_t(nt) * nsx * kPkT;
   const float ng = -float(ks.gamma) * kLog2e;
+  const dim3 grid((unsigned)pk_strips_tail(nt, strip));
+  if (KP <= 16) {
+    if (exact)
+      kapply_otf_mfma_sym_kernel<KP, true><<<grid, 256, 0, st>>>(X, q, n, p, ng, v, nt, strip, nsx, rowpart, colpart);
+    else
+      kapply_otf_mfma_sym_kernel<KP, false><<<grid, 256, 0, st>>>(X, q, n, p, ng, v, nt, strip, nsx, rowpart, colpart);
+    KQR_LAUNCH_CHECK();
+    packed_reduce(rowpart, colpart, n, strip, u, ldu, st);
+    if (buf) KQR_CHECK_HIP(hipFreeAsync(buf, st));
+    return;
+  }
+  uint16_t* bc = reinterpret_cast<uint16_t*>(buf + part_bytes);
   const bool aug = p <= 30;
   const dim3 sgrid((unsigned)((n * 4 + 255) / 256));
   if (aug) kotf_split_cols_kernel<true><<<sgrid, 256, 0, st>>>(X, q, n, p, ng, bc);
   else kotf_split_cols_kernel<false><<<sgrid, 256, 0, st>>>(X, q, n, p, ng, bc);
   KQR_LAUNCH_CHECK();
-  const dim3 grid((unsigned)pk_strips_tail(nt, strip));
   if (aug && exact)
     kapply_otf_mfma3_sym_kernel<true, true><<<grid, 256, 0, st>>>(X, q, n, bc, p, ng, v, nt, strip, nsx, rowpart, colpart);
   else if (aug)
@@ -1270,8 +1415,8 @@ template <int KP>
 static void kapply_otf_mfma_p(const float* Xr, const float* qr, int64_t nr, const float* Xc, const float* qc,
                               int64_t nc, int p, KernelSpec ks, const double* v, double* u, int64_t ldu, double scale,
                               double shift, bool exact, hipStream_t st, double* scratch, size_t scratch_doubles) {
-  if (KP > 16 && Xr == Xc && qr == qc && nr == nc && scale == 1.0 && shift == 0.0) {  // square K(X, X): symmetric
-    kapply_otf_mfma3_sym(Xr, qr, nr, p, ks, v, u, ldu, exact, st, scratch, scratch_doubles);
+  if (Xr == Xc && qr == qc && nr == nc && scale == 1.0 && shift == 0.0) {  // square K(X, X): symmetric
+    kapply_otf_mfma_sym<KP>(Xr, qr, nr, p, ks, v, u, ldu, exact, st, scratch, scratch_doubles);
     return;
   }
   const int64_t rblk = (nr + 127) / 128;

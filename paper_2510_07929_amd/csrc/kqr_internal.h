@@ -107,7 +107,7 @@ size_t kapply_scratch_doubles(const KMat& km, int64_t n);
 // exact = false: v rounded to FP32, FP32 products summed in FP32 over tiles
 // of 64 columns, FP64 across tiles; exact = true: FP64 v, products and sums.
 // The square apply K(X, X) v (Xr == Xc, scale 1, shift 0) of the RBF with
-// 16 < p <= 32 evaluates each distinct pair once; its partial sums go to
+// p <= 32 evaluates each distinct pair once; its partial sums go to
 // scratch when that holds otf_sym_scratch_doubles(n) doubles.
 void kapply_otf(const float* Xr, const float* sqr, int64_t nr, const float* Xc, const float* sqc,
                 int64_t nc, int p, KernelSpec ks, const double* v64, double* u, int64_t ldu,

@@ -110,8 +110,10 @@ void Operator::apply_fast(const double* v, const float* v32, double* u, hipStrea
     kapply_otf_l1q(xq_.as<uint32_t>(), n_, p_, ks_.gamma, shift_, v, u, 1, false, st, scr, nd);
     mark(false, true, st);
   } else {
+    const size_t nd = otf_sym_scratch_doubles(n_);
+    double* scr = scratch(nd);
     mark(true, true, st);
-    kapply_otf(X_, sqn_.as<float>(), n_, X_, sqn_.as<float>(), n_, p_, ks_, v, u, 1, 1.0, 0.0, st);
+    kapply_otf(X_, sqn_.as<float>(), n_, X_, sqn_.as<float>(), n_, p_, ks_, v, u, 1, 1.0, 0.0, st, false, scr, nd);
     mark(false, true, st);
   }
 }

@@ -100,8 +100,10 @@ def test_on_the_fly_rbf_beyond_matrix_core_path(dev):
 
 # The square on-the-fly applies evaluate each distinct pair once over
 # 128 x 128 upper-triangle tiles: one point, a partial single tile, exactly
-# one tile, one tile and one column, and two tiles with a one-row tail.
-@pytest.mark.parametrize("kind,p", [("laplacian", 30), ("rbf", 30), ("rbf", 32)])
+# one tile, one tile and one column, and two tiles with a one-row tail
+# (RBF p = 10: FP32 matrix-core Gram; 30 and 32: BF16x3 with and without the
+# folded norms).
+@pytest.mark.parametrize("kind,p", [("laplacian", 30), ("rbf", 10), ("rbf", 30), ("rbf", 32)])
 @pytest.mark.parametrize("n", [1, 5, 127, 128, 129, 257])
 @pytest.mark.parametrize("mode", [kqr.KQR_APPLY_FAST, kqr.KQR_APPLY_EXACT])
 def test_on_the_fly_symmetric_apply_tile_edges(dev, kind, p, n, mode):
