@@ -637,7 +637,7 @@ __global__ __launch_bounds__(256) void kapply_otf_l1q_sym_kernel(const uint32_t*
 
 static int otf_sym_strip(int64_t n) {  // tiles per workgroup of the symmetric applies
   const int64_t nt = (n + kPkT - 1) / kPkT;
-  return nt >= 256 ? 16 : (nt >= 64 ? 8 : 2);
+  return nt >= 1024 ? 32 : (nt >= 256 ? 16 : (nt >= 64 ? 8 : 2));
 }
 
 size_t otf_sym_scratch_doubles(int64_t n) { return packed_scratch_doubles(n, otf_sym_strip(n)); }
