@@ -199,6 +199,14 @@ int64_t kqr_packed_bytes(int64_t n, int k_dtype);
 int kqr_autotune_packed(const void* K, int k_dtype, int64_t n, int mode, int reps, char* report, int64_t cap,
                         void* stream);
 int kqr_set_packed_shape(int k_dtype, int mode, int map, int strip);
+
+/* kqr_set_otf_symmetric_limit: the square on-the-fly apply K(X, X) v (RBF
+ * with p <= 32, Laplacian in fixed point) evaluates each distinct pair once
+ * (K is symmetric, Section 1) and keeps one FP64 partial sum per 128 x 128
+ * tile and column, about n^2 / 32 bytes of device memory.  bytes (>= 0,
+ * default 32 GiB) bounds that buffer for the whole process; at larger n the
+ * applies stream all n^2 pairs with O(n) partial sums instead.  Host-only. */
+int kqr_set_otf_symmetric_limit(int64_t bytes);
 int kqr_kernel_build_packed(const float* X, int64_t n, int64_t p, int kernel, double gamma, int k_dtype, void* K,
                             void* stream);
 int kqr_kernel_apply_packed(const void* K, int k_dtype, int64_t n, const double* v, double* u, int mode,

@@ -479,6 +479,13 @@ int kqr_set_packed_shape(int k_dtype, int mode, int map, int strip) {
   });
 }
 
+int kqr_set_otf_symmetric_limit(int64_t bytes) {
+  return guarded([&] {
+    KQR_REQUIRE(bytes >= 0, "bytes must be >= 0");
+    set_otf_sym_budget(bytes);
+  });
+}
+
 int kqr_predict(const float* Xtrain, int64_t n, int64_t p, const double* alpha, double beta, double lambda,
                 int kernel, double gamma, const float* Xnew, int64_t m, double* f, void* stream) {
   return guarded([&] {

@@ -8,6 +8,7 @@
 #include "kqr_internal.h"
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <mutex>
 #include <vector>
@@ -483,6 +484,107 @@ __device__ __forceinline__ uint32_t sad_u32(uint32_t a, uint32_t b, uint32_t c) 
   return r;
 }
 
+// Row-streamed form over all n^2 pairs (used when the symmetric form's
+// partial sums would exceed the budget below): a workgroup owns 256 R rows and a
+// slice of the columns; one partial per slice and row, added by
+// otf_reduce_kernel.
+template <int PMAX, int R, bool EX>
+__global__ __launch_bounds__(256) void kapply_otf_l1q_kernel(const uint32_t* __restrict__ Xq, int64_t n, int p,
+                                                             float ngs, const double* __restrict__ v,
+                                                             int64_t cols_per_slice, double* __restrict__ part) {
+  // a thread owns R rows (256 R per block), so each LDS read of x_j serves R pairs
+  static_assert(PMAX % 4 == 0, "coordinates are read from LDS four at a time");
+  __shared__ __align__(16) uint32_t xs[kOtfTile][PMAX];
+  __shared__ float vs[kOtfTile];
+  __shared__ double vd[kOtfTile];
+  const int64_t i0 = int64_t(blockIdx.x) * 256 * R + threadIdx.x;
+  uint32_t xi[R][PMAX];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int64_t i = i0 + 256 * r;
+#pragma unroll
+    for (int k = 0; k < PMAX; ++k) xi[r][k] = (i < n && k < p) ? Xq[i * p + k] : 0u;
+  }
+  const int64_t c0 = int64_t(blockIdx.y) * cols_per_slice;
+  const int64_t c1 = min(n, c0 + cols_per_slice);
+  double acc[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) acc[r] = 0.0;
+  for (int64_t jb = c0; jb < c1; jb += kOtfTile) {
+    const int cnt = int(min<int64_t>(kOtfTile, c1 - jb));
+    __syncthreads();
+    for (int t = threadIdx.x; t < kOtfTile * PMAX; t += 256) {
+      const int jj = t / PMAX, k = t % PMAX;
+      xs[jj][k] = (jj < cnt && k < p) ? Xq[(jb + jj) * p + k] : 0u;
+    }
+    if (threadIdx.x < kOtfTile) {
+      const int jj = threadIdx.x;
+      const double vj = jj < cnt ? v[jb + jj] : 0.0;
+      if (EX) vd[jj] = vj;
+      else vs[jj] = float(vj);
+    }
+    __syncthreads();
+    float a32[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) a32[r] = 0.f;
+    for (int jj = 0; jj < cnt; ++jj) {
+      uint32_t d[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) d[r] = 0u;
+      const uint4* xr = reinterpret_cast<const uint4*>(xs[jj]);  // broadcast 16-byte LDS reads
+#pragma unroll
+      for (int k4 = 0; k4 < PMAX / 4; ++k4) {
+        const uint4 c = xr[k4];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          d[r] = sad_u32(xi[r][4 * k4], c.x, d[r]);
+          d[r] = sad_u32(xi[r][4 * k4 + 1], c.y, d[r]);
+          d[r] = sad_u32(xi[r][4 * k4 + 2], c.z, d[r]);
+          d[r] = sad_u32(xi[r][4 * k4 + 3], c.w, d[r]);
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const float e = kexp2(ngs * float(d[r]));
+        if (EX) acc[r] = fma(double(e), vd[jj], acc[r]);
+        else a32[r] = fmaf(e, vs[jj], a32[r]);
+      }
+    }
+    if (!EX) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) acc[r] += double(a32[r]);
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int64_t i = i0 + 256 * r;
+    if (i < n) part[int64_t(blockIdx.y) * n + i] = acc[r];
+  }
+}
+
+template <int PMAX>
+static void kapply_otf_l1q_rows_p(const uint32_t* Xq, int64_t n, int p, float ngs, const double* v, double* u,
+                                  int64_t ldu, bool exact, hipStream_t st) {
+  // rows per thread: 4 up to 32 coordinates, 2 beyond (registers)
+  constexpr int R = PMAX <= 32 ? 4 : 2;
+  const int64_t rblk = (n + 256 * R - 1) / (256 * R);
+  int64_t nslice = otf_slices(rblk, n);
+  nslice = std::min<int64_t>(nslice, 65535);
+  int64_t per = (n + nslice - 1) / nslice;
+  per = (per + kOtfTile - 1) / kOtfTile * kOtfTile;
+  nslice = (n + per - 1) / per;
+  double* part = nullptr;
+  KQR_CHECK_HIP(hipMallocAsync(reinterpret_cast<void**>(&part), size_t(nslice) * size_t(n) * sizeof(double), st));
+  const dim3 grid((unsigned)rblk, (unsigned)nslice);
+  if (exact) kapply_otf_l1q_kernel<PMAX, R, true><<<grid, 256, 0, st>>>(Xq, n, p, ngs, v, per, part);
+  else kapply_otf_l1q_kernel<PMAX, R, false><<<grid, 256, 0, st>>>(Xq, n, p, ngs, v, per, part);
+  KQR_LAUNCH_CHECK();
+  otf_reduce_kernel<<<dim3((unsigned)((n + 255) / 256)), 256, 0, st>>>(part, int(nslice), n, u, ldu, 1.0, 0.0);
+  KQR_LAUNCH_CHECK();
+  KQR_CHECK_HIP(hipFreeAsync(part, st));
+}
+
+
 // K is symmetric (Section 1), so each pair is evaluated once: over the
 // upper-triangle tiles of kPkT x kPkT entries of the packed geometry.
 // Workgroup b takes strip k of tile-row I (pk_strip_coords), the tiles
@@ -640,11 +742,29 @@ static int otf_sym_strip(int64_t n) {  // tiles per workgroup of the symmetric a
   return nt >= 1024 ? 32 : (nt >= 256 ? 16 : (nt >= 64 ? 8 : 2));
 }
 
-size_t otf_sym_scratch_doubles(int64_t n) { return packed_scratch_doubles(n, otf_sym_strip(n)); }
+// The symmetric applies keep one FP64 partial per tile and column, about
+// n^2 / 32 bytes (3 GB at n = 300,000, 31 GB at n = 10^6).  Beyond a
+// budget (32 GiB unless set) the row-streamed forms run instead (all n^2
+// pairs, O(n) partials).
+std::atomic<int64_t> g_otf_sym_budget{int64_t(32) << 30};
+
+void set_otf_sym_budget(int64_t bytes) { g_otf_sym_budget.store(bytes); }
+
+static bool otf_sym_fits(int64_t n) {
+  return int64_t(packed_scratch_doubles(n, otf_sym_strip(n)) * sizeof(double)) <= g_otf_sym_budget.load();
+}
+
+size_t otf_sym_scratch_doubles(int64_t n) {
+  return otf_sym_fits(n) ? packed_scratch_doubles(n, otf_sym_strip(n)) : 0;
+}
 
 template <int PMAX>
 static void kapply_otf_l1q_p(const uint32_t* Xq, int64_t n, int p, float ngs, const double* v, double* u, int64_t ldu,
                              bool exact, hipStream_t st, double* scratch, size_t scratch_doubles) {
+  if (!otf_sym_fits(n)) {
+    kapply_otf_l1q_rows_p<PMAX>(Xq, n, p, ngs, v, u, ldu, exact, st);
+    return;
+  }
   const int64_t nt = (n + kPkT - 1) / kPkT;
   const int strip = otf_sym_strip(n);
   const int64_t nsx = (nt + strip - 1) / strip;
@@ -1415,7 +1535,7 @@ template <int KP>
 static void kapply_otf_mfma_p(const float* Xr, const float* qr, int64_t nr, const float* Xc, const float* qc,
                               int64_t nc, int p, KernelSpec ks, const double* v, double* u, int64_t ldu, double scale,
                               double shift, bool exact, hipStream_t st, double* scratch, size_t scratch_doubles) {
-  if (Xr == Xc && qr == qc && nr == nc && scale == 1.0 && shift == 0.0) {  // square K(X, X): symmetric
+  if (Xr == Xc && qr == qc && nr == nc && scale == 1.0 && shift == 0.0 && otf_sym_fits(nr)) {  // square: symmetric
     kapply_otf_mfma_sym<KP>(Xr, qr, nr, p, ks, v, u, ldu, exact, st, scratch, scratch_doubles);
     return;
   }

@@ -121,7 +121,8 @@ void kapply_otf(const float* Xr, const float* sqr, int64_t nr, const float* Xc, 
 // to scratch when that holds otf_sym_scratch_doubles(n) doubles, else to
 // memory allocated on st.
 int quantize_columns(const float* X, int64_t n, int p, uint32_t* Xq, hipStream_t st);
-size_t otf_sym_scratch_doubles(int64_t n);  // partial sums of a symmetric on-the-fly apply
+size_t otf_sym_scratch_doubles(int64_t n);  // partial sums of a symmetric on-the-fly apply (0: too large)
+void set_otf_sym_budget(int64_t bytes);     // largest such buffer; beyond it the row-streamed forms run
 void kapply_otf_l1q(const uint32_t* Xq, int64_t n, int p, double gamma, int shift, const double* v, double* u,
                     int64_t ldu, bool exact, hipStream_t st, double* scratch = nullptr, size_t scratch_doubles = 0);
 // y = A x for a skinny FP32 matrix A (nrows x ncols, ncols <= 1024, lda a

@@ -102,6 +102,7 @@ _SIGS = {
     "kqr_kernel_apply_packed": (C.c_int, [_P, C.c_int, _I64, _P, _P, C.c_int, _P]),
     "kqr_autotune_packed": (C.c_int, [_P, C.c_int, _I64, C.c_int, C.c_int, C.c_char_p, _I64, _P]),
     "kqr_set_packed_shape": (C.c_int, [C.c_int, C.c_int, C.c_int, C.c_int]),
+    "kqr_set_otf_symmetric_limit": (C.c_int, [C.c_int64]),
     "kqr_fit_batch": (C.c_int, [C.c_int, _P, _P, _P, _I64, _P, _P, C.c_int, _P, C.POINTER(KqrOptions), _P, _P, _P,
                                 _P, _P]),
     "kqr_fit_grad": (C.c_int, [_P, _P, _I64, _I64, C.c_double, C.c_double, C.c_int, C.c_double, _P, _P, _I64,
@@ -265,6 +266,11 @@ def kqr_autotune_packed(K, n, mode=KQR_APPLY_FAST, reps=5, stream=None):
 
 def kqr_set_packed_shape(k_dtype, mode, map, strip):
     _check(lib().kqr_set_packed_shape(_kdtype_id(k_dtype), int(mode), int(map), int(strip)), "kqr_set_packed_shape")
+
+
+def kqr_set_otf_symmetric_limit(nbytes):
+    """Bound the partial-sum buffer of the symmetric on-the-fly applies (bytes); larger n stream all pairs."""
+    _check(lib().kqr_set_otf_symmetric_limit(int(nbytes)), "kqr_set_otf_symmetric_limit")
 
 
 def kqr_kernel_apply(V, X=None, kernel="rbf", gamma=1.0, K=None, mode=KQR_APPLY_FAST, U=None, stream=None):

@@ -118,3 +118,29 @@ def test_on_the_fly_symmetric_apply_tile_edges(dev, kind, p, n, mode):
     bound = _apply_bound(Kb, Kref, v, mode, otf=True)
     err = np.abs(u - Kref @ v)
     assert np.all(err <= bound), float((err / bound).max())
+
+
+@pytest.mark.parametrize("kind,p", [("laplacian", 30), ("rbf", 10), ("rbf", 30)])
+@pytest.mark.parametrize("mode", [kqr.KQR_APPLY_FAST, kqr.KQR_APPLY_EXACT])
+def test_on_the_fly_row_streamed_beyond_symmetric_limit(dev, kind, p, mode):
+    # with no room for the symmetric form's partial sums the applies stream all
+    # n^2 pairs; both forms agree with the oracle and with each other
+    n = 1300
+    X, _ = inputs.additive(n, p, (612, n))
+    v = np.random.default_rng(3).standard_normal(n)
+    gamma = 1.0 / p
+    Xt, vt = torch.from_numpy(X).to(dev), torch.from_numpy(v).to(dev)
+    say("otf row-streamed", kind, p, mode)
+    sym = kqr.kqr_kernel_apply(vt, X=Xt, kernel=kind, gamma=gamma, mode=mode).cpu().numpy()
+    try:
+        kqr.kqr_set_otf_symmetric_limit(0)
+        rows = kqr.kqr_kernel_apply(vt, X=Xt, kernel=kind, gamma=gamma, mode=mode).cpu().numpy()
+    finally:
+        kqr.kqr_set_otf_symmetric_limit(32 << 30)
+    from tests.test_gpu_parity import _apply_bound, entry_bound
+    Kref, Kb = entry_bound(X, kind, gamma)
+    bound = _apply_bound(Kb, Kref, v, mode, otf=True)
+    for u in (sym, rows):
+        err = np.abs(u - Kref @ v)
+        assert np.all(err <= bound), float((err / bound).max())
+    assert np.all(np.abs(sym - rows) <= 2 * bound)
