@@ -334,25 +334,25 @@ class ProblemBatcher : public RendezvousBatcher {
  public:
   ProblemBatcher(int slots, std::vector<KMat> km, std::vector<int64_t> n, bool profile)
       : RendezvousBatcher(slots, profile), km_(std::move(km)), n_(std::move(n)),
-        tasks_(size_t(km_.size()) * sizeof(ProblemTask)), first_(size_t(km_.size() + 1) * sizeof(int)),
-        v32_(std::vector<DevBuf>()) {
-    for (size_t i = 0; i < km_.size(); ++i) v32_.emplace_back(size_t(n_[i]) * sizeof(float));
-  }
+        tasks_(size_t(km_.size()) * sizeof(ProblemTask)), first_(size_t(km_.size() + 1) * sizeof(int)) {}
 
  protected:
   void launch(const std::vector<int>& slots, hipStream_t st) override {
     std::vector<ProblemTask> tasks;
     std::vector<int> first;
     int total = 0;
-    for (int s : slots) {
+    // largest problems first: their workgroups (the longest rows) start
+    // early, so the launch does not end on a tail of long workgroups
+    std::vector<int> order(slots);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return n_[size_t(a)] > n_[size_t(b)]; });
+    for (int s : order) {
       const Req& r = req_[size_t(s)];
-      to_f32(r.v, n_[size_t(s)], 1, 1, v32_[size_t(s)].as<float>(), 1, st);
       ProblemTask t;
       t.K = km_[size_t(s)].K;
       t.ld = km_[size_t(s)].ld;
       t.n = n_[size_t(s)];
       t.dtype = km_[size_t(s)].dtype;
-      t.v = v32_[size_t(s)].as<float>();
+      t.v = r.v;
       t.u = r.out;
       tasks.push_back(t);
       first.push_back(total);
@@ -369,7 +369,6 @@ class ProblemBatcher : public RendezvousBatcher {
   std::vector<KMat> km_;
   std::vector<int64_t> n_;
   DevBuf tasks_, first_;
-  std::vector<DevBuf> v32_;
 };
 
 // ================================================================= drivers

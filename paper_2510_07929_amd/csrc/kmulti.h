@@ -58,7 +58,7 @@ struct ProblemTask {
   int64_t ld;
   int64_t n;
   int dtype;
-  const float* v;  // n (FP32)
+  const double* v;  // n (FP64; rounded to FP32 in the kernel, as every fast apply rounds v)
   double* u;       // n (FP64)
 };
 int problem_blocks(int64_t n);  // workgroups one problem needs

@@ -565,7 +565,7 @@ void kv_scatter(const double* U16, int m, int64_t n, DstTable16 dst, hipStream_t
 }
 
 // ----------------------------------------------------------------- many problems, one launch
-// Task t: K_t (n_t x ld_t, FP32 or BF16), v_t (FP32, n_t), u_t (FP64, n_t).
+// Task t: K_t (n_t x ld_t, FP32 or BF16), v_t (FP64, n_t, rounded to FP32 here), u_t (FP64, n_t).
 // first_block[t] = prefix sum of row blocks (8 rows per wave, 4 waves per block).
 __global__ __launch_bounds__(256) void kapply_problems_kernel(const ProblemTask* __restrict__ tasks, int ntasks,
                                                               const int* __restrict__ first_block) {
@@ -592,12 +592,12 @@ __global__ __launch_bounds__(256) void kapply_problems_kernel(const ProblemTask*
   const int64_t rstride = tk.ld * (bf ? 2 : 4);
   for (int64_t c = lane; c < nchunk; c += 64) {
     float vv[8];
-    const float* vp = tk.v + c * vec;
-    const float4 t0 = *reinterpret_cast<const float4*>(vp);
-    vv[0] = t0.x; vv[1] = t0.y; vv[2] = t0.z; vv[3] = t0.w;
+    const double* vp = tk.v + c * vec;  // 8-byte loads: v may sit at any double offset
+#pragma unroll
+    for (int e = 0; e < 4; ++e) vv[e] = float(vp[e]);
     if (bf) {
-      const float4 t1 = *reinterpret_cast<const float4*>(vp + 4);
-      vv[4] = t1.x; vv[5] = t1.y; vv[6] = t1.z; vv[7] = t1.w;
+#pragma unroll
+      for (int e = 4; e < 8; ++e) vv[e] = float(vp[e]);
     }
     u32x4 kk[ROWS];
 #pragma unroll
@@ -623,7 +623,7 @@ __global__ __launch_bounds__(256) void kapply_problems_kernel(const ProblemTask*
   }
   const int64_t col = nchunk * vec + lane;
   if (col < tk.n) {
-    const double ve = tk.v[col];
+    const double ve = double(float(tk.v[col]));
 #pragma unroll
     for (int r = 0; r < ROWS; ++r) {
       const int64_t rr = min(row0 + r, tk.n - 1);
