@@ -224,8 +224,8 @@ int kqr_kernel_apply_packed(const void* K, int k_dtype, int64_t n, const double*
  *         FP32 accumulation on the matrix cores; EXACT with an FP32 K and m <= 4
  *         forms all columns in FP64 (vectors, products, sums) from one pass over
  *         K; otherwise column by column.
- *  Needs 1 <= m <= 16.  Asynchronous on `stream`; uses an internal device
- *  workspace (allocated on first use, reused after). */
+ *  Needs 1 <= m <= 16.  Asynchronous on `stream`; allocates its device
+ *  workspace on `stream` (stream-ordered) and frees it before returning. */
 int kqr_kernel_apply(const float* X, int64_t n, int64_t p, int kernel, double gamma,
                      const void* K, int k_dtype, int64_t ldk, const double* V, int64_t m,
                      int64_t ldv, double* U, int64_t ldu, int mode, void* stream);
