@@ -55,10 +55,19 @@ def parse():
     ap.add_argument("--workload", default="c1")
     ap.add_argument("--n", type=int, default=None, help="override the workload size")
     ap.add_argument("--kdtype", default=None, choices=[None, "fp32", "bf16"])
-    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the CPU oracle sample")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0, help="budget of the CPU oracle K-apply sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="skip the K-apply shape sweep before the warm-up")
+    ap.add_argument("--retune", action="store_true",
+                    help="sweep the launch shapes even when paper_2510_07929_amd/tune/<arch>.json holds them")
+    ap.add_argument("--tune-out", default=None, help="write the launch shapes in use at the end to this JSON file")
     ap.add_argument("--no-packed", action="store_true", help="single fits: skip the packed-layout comparison")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="c1: skip the BF16 (c2) and batched (c3a, c3b) comparison legs")
+    ap.add_argument("--no-cert", action="store_true", help="single fits: skip the FP64 certificate of the fit")
+    ap.add_argument("--certify", action="store_true",
+                    help="fit c2 (BF16 and FP32 K), c2lap and c3a at full size and certify each against FP64 "
+                         "(one JSON line each; minutes of host time)")
     ap.add_argument("--traffic", default=None,
                     help="counter summary (profiles/*_traffic.md) with the measured HBM bytes per K-apply launch")
     ap.add_argument("--fd", action="store_true", help="c4: also time central differences of the gradient")
@@ -66,38 +75,74 @@ def parse():
     return ap.parse_args()
 
 
+def _host_ram_gb():
+    try:
+        with open("/proc/meminfo") as f:
+            for line in f:
+                if line.startswith("MemTotal:"):
+                    return round(int(line.split()[1]) / 2 ** 20, 1)
+    except OSError:  # pragma: no cover
+        pass
+    return None
+
+
 def cpu_baseline(prob, budget_s):
-    """Time the oracle's FP64 K-apply on a row block of the same kernel matrix."""
+    """The oracle as it stands, timed on this host's cores with the BLAS
+    thread count set explicitly: its FP64 K-apply on a row block of the same
+    kernel matrix (the line's unit), and whole oracle fits -- the small
+    workload at full size with all threads and with one, and this workload at
+    a reduced n whose FP64 K fits in a few hundred MB."""
     import numpy as np
+    from threadpoolctl import threadpool_info, threadpool_limits
 
     from oracle import kernel as okernel
+    from oracle import solver as osolver
+    from paper_2510_07929_amd import inputs
 
-    try:
-        from threadpoolctl import threadpool_info
-
+    cores = len(os.sched_getaffinity(0))
+    with threadpool_limits(limits=cores):
         threads = max([t.get("num_threads", 1) for t in threadpool_info()] or [1])
-    except Exception:  # pragma: no cover
-        threads = os.cpu_count() or 1
-    n = prob.n
-    rows = max(256, min(n, int(2.0e8 // n)))  # ~1.6 GB of FP64 entries at most
-    t0 = time.perf_counter()
-    op_block = okernel.kernel_block(prob.X[:rows], prob.X, prob.kernel, prob.gamma)
-    t_build = time.perf_counter() - t0
-    v = np.random.default_rng(0).standard_normal(n)
-    reps, t_apply = 0, 0.0
-    while t_apply < max(1.0, budget_s - t_build) and reps < 200:
+        n = prob.n
+        rows = max(256, min(n, int(2.0e8 // n)))  # ~1.6 GB of FP64 entries at most
         t0 = time.perf_counter()
-        _ = op_block @ v
-        t_apply += time.perf_counter() - t0
-        reps += 1
+        op_block = okernel.kernel_block(prob.X[:rows], prob.X, prob.kernel, prob.gamma)
+        t_build = time.perf_counter() - t0
+        v = np.random.default_rng(0).standard_normal(n)
+        reps, t_apply = 0, 0.0
+        while t_apply < max(1.0, budget_s - t_build) and reps < 200:
+            t0 = time.perf_counter()
+            _ = op_block @ v
+            t_apply += time.perf_counter() - t0
+            reps += 1
+        del op_block
     bytes_per = rows * n * 8.0
     gbs = bytes_per * reps / t_apply / 1e9
+
+    def oracle_fit(name, nn, limit):
+        p = inputs.workload(name, n=nn)
+        o = osolver.OracleOptions(tol=1e-6, rank=p.rank if p.rank > 0 else 0)
+        with threadpool_limits(limits=limit):
+            t0 = time.perf_counter()
+            r = osolver.fit(p.X, p.y, p.tau, p.lam, p.kernel, p.gamma, o,
+                            uniforms=inputs.pivot_uniforms(1024, (sum(map(ord, name)), 0)))
+            el = time.perf_counter() - t0
+        return {"n": nn, "threads": limit, "s": round(el, 3), "kkt": float(r.kkt["err"]),
+                "kernel_applies": int(r.info["kapply"])}
+
+    fits = [oracle_fit("c0", 2000, cores), oracle_fit("c0", 2000, 1)]
+    if prob.name != "c0":
+        fits.append(oracle_fit(prob.name, min(prob.n, 6000), cores))
     return {
         "value": round(gbs, 3), "unit": "GB/s", "cores": int(threads), "kind": "oracle",
         "sample": (f"oracle FP64 K-apply (K @ v, materialised FP64 rows) on rows 0..{rows - 1} of the "
                    f"n={n} {prob.kernel} K, {reps} applies; block built by the oracle in {t_build:.1f} s"),
         "full_apply_s_extrapolated": round(t_apply / reps * n / rows, 3),
-        "affinity_cores": len(os.sched_getaffinity(0)),
+        "oracle_fits": fits,
+        "oracle_fits_note": ("whole oracle fits to max(eta_kkt, eta_gap) <= 1e-6 (dense FP64 Cholesky solves for "
+                             "n <= 5000, PCG beyond; active-set polish at the end): the small workload at full size "
+                             "with all threads and single-threaded, and this workload at a reduced n (its FP64 K at "
+                             "full n would be 8 n^2 bytes)"),
+        "blas_threads_set": cores, "affinity_cores": cores, "host_ram_gb": _host_ram_gb(),
     }
 
 
@@ -151,6 +196,23 @@ def inputs_mod():
     return inputs
 
 
+def load_tuning(args):
+    """Install the committed launch shapes for this GPU's architecture
+    (paper_2510_07929_amd/tune/<arch>.json, written by kqr_tune_save after a
+    sweep on that architecture) instead of sweeping; returns the file or None."""
+    import torch
+
+    from paper_2510_07929_amd import kqr
+
+    if args.retune or args.no_tune:
+        return None
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    path = os.path.join(ROOT, "paper_2510_07929_amd", "tune", f"{arch}.json")
+    if not os.path.exists(path):
+        return None
+    return os.path.relpath(path, ROOT) if kqr.kqr_tune_load(path) > 0 else None
+
+
 def timed_fits(args, one_fit):
     import torch
 
@@ -181,11 +243,18 @@ def run_materialised(args, prob, kdtype, tune, layout=0, **extra):
     opts = dict(rank=rank, k_dtype=kqr.KDTYPES[kdtype], kmode=kqr.KQR_KMODE_MATERIALIZE, profile=1,
                 verbose=1 if args.verbose else 0, k_layout=layout, **extra)
 
+    last_iterate = {}
+
     def one_fit():
-        _, beta, info, st = kqr.kqr_fit(X, y, prob.tau, prob.lam, prob.kernel, prob.gamma, uniforms=uni, **opts)
+        alpha, beta, info, st = kqr.kqr_fit(X, y, prob.tau, prob.lam, prob.kernel, prob.gamma, uniforms=uni,
+                                            out_vz=True, **opts)
+        last_iterate.update(alpha=alpha, beta=beta, v=info.pop("v"), z=info.pop("z"))
         return info, st
 
     tuned = {}
+    if tune and args.tuned_from:
+        tuned = {"from": args.tuned_from}
+        tune = False
     if tune and layout == 1:
         # untimed: pick the packed K-apply shape on this problem's own packed K
         Kp = kqr.kqr_kernel_build_packed(X, prob.kernel, prob.gamma, kdtype)
@@ -224,9 +293,100 @@ def run_materialised(args, prob, kdtype, tune, layout=0, **extra):
         "avg_launch_us": round(avg * 1e6, 2), "launches": int(nfast),
         "bytes_per_launch": kbytes, "tile_shapes": tuned or "default",
     }
+    it = {k: (v.cpu().numpy() if hasattr(v, "cpu") else v) for k, v in last_iterate.items()}
     del X, y
+    last_iterate.clear()
     torch.cuda.empty_cache()
-    return value, elapsed / args.steps * 1e3, roof, fit_summary(last, st)
+    fit = fit_summary(last, st)
+    fit["_iterate"] = it
+    return value, elapsed / args.steps * 1e3, roof, fit
+
+
+def error_vs_fp64(prob, fit, kdtype, modes=("fast", "exact")):
+    """Error against FP64 of a fit and of one K-apply per precision mode.
+
+    The oracle's FP64 certificate (one pass of FP64 kernel products on the
+    host: Section 4 measures at the returned iterate with the exact kernel,
+    and a weak-duality bound of the relative objective error) plus the
+    relative error ||u - K v|| / ||K v|| of the GPU's K-apply of a random v,
+    K v from the same FP64 pass."""
+    import numpy as np
+    import torch
+
+    from oracle import certify
+    from paper_2510_07929_amd import kqr
+
+    it = fit.pop("_iterate")
+    t0 = time.perf_counter()
+    v = np.random.default_rng(17).standard_normal(prob.n)
+    dev = torch.device("cuda:0")
+    X = torch.from_numpy(prob.X).to(dev)
+    K = kqr.kqr_kernel_build(X, prob.kernel, prob.gamma, kdtype)
+    vt = torch.from_numpy(v).to(dev)
+    ugpu = {m: kqr.kqr_kernel_apply(vt, K=K, mode=kqr.KQR_APPLY_FAST if m == "fast" else kqr.KQR_APPLY_EXACT)
+            .cpu().numpy() for m in modes}
+    del K, X, vt
+    torch.cuda.empty_cache()
+    c = certify.certificate(prob.X, prob.y, prob.tau, prob.lam, prob.kernel, prob.gamma, it["alpha"], it["beta"],
+                            v=it["v"], z=it["z"], extra=v)
+    kv = c["K_extra"][:, 0]
+    rel = {f"{m}_{kdtype}_k": float(np.linalg.norm(u - kv) / np.linalg.norm(kv)) for m, u in ugpu.items()}
+    return {
+        "rel_obj_err_bound": c["rel_obj_err_bound"], "eta_kkt_fp64": c["eta_kkt"], "eta_gap_fp64": c["eta_gap"],
+        "eta_p_fp64": c["eta_p"], "eta_d_fp64": c["eta_d"], "eta_c_fp64": c["eta_c"],
+        "kapply_rel_err": rel, "n_interior": c["n_interior"],
+        "how": ("oracle FP64 certificate on the host (direct-difference FP64 kernel products, oracle/kapply.c): "
+                "Section 4 measures at the returned iterate (alpha, v, beta, z) with the exact kernel; "
+                "rel_obj_err_bound = (obj_P(alpha, beta) - obj_D(alpha~)) / (1 + |obj_D(alpha~)|) with alpha~ the "
+                "feasible projection of alpha (weak duality); K-apply errors ||u - K v|| / ||K v|| of a random v"),
+        "seconds": round(time.perf_counter() - t0, 2),
+    }
+
+
+def _leg_args(args):
+    import copy
+
+    a = copy.copy(args)
+    a.steps, a.warmup = 1, 0
+    return a
+
+
+def compare_bf16_leg(args):
+    """The precision workload at full size: BF16-stored K with FP64 refinement
+    against FP32-stored K, same problem, same GPU, same KKT target."""
+    from paper_2510_07929_amd import inputs
+
+    prob = inputs.workload("c2")
+    la = _leg_args(args)
+    v16, ms16, roof16, fit16 = run_materialised(la, prob, "bf16", False)
+    v32, ms32, roof32, fit32 = run_materialised(la, prob, "fp32", False)
+    for f in (fit16, fit32):
+        f.pop("_iterate", None)
+    return {
+        "workload": f"c2: {inputs.WORKLOADS['c2'][1]}", "steps": 1, "warmup": 0,
+        "bf16": {"k_storage": "bf16 (inner PCG) + exact FP32 entries recomputed from X (residuals, refinement)",
+                 "value": round(v16, 2), "ms_per_step": round(ms16, 3), "roofline": roof16, "fit": fit16},
+        "fp32": {"k_storage": "fp32", "value": round(v32, 2), "ms_per_step": round(ms32, 3), "roofline": roof32,
+                 "fit": fit32},
+        "bf16_speedup": round(ms32 / ms16, 3),
+        "error_vs_fp64": "profiles/certificate_c2_c2lap_c3a.md (bench.py --certify)",
+    }
+
+
+def compare_batched_leg(args):
+    """Batching at full size: nine quantile levels jointly against nine
+    separate fits (c3a), and 64 uneven problems in one batch against one at a
+    time (c3b); same GPU, same KKT target."""
+    from paper_2510_07929_amd import inputs
+
+    la = _leg_args(args)
+    la.no_tune = True
+    a = bench_multi_tau(la, inputs.workload("c3a"))
+    b = bench_batch(la)
+    keep = ("value", "ms_per_step", "roofline", "fit", "compare_separate")
+    return {"steps": 1, "warmup": 0,
+            "c3a": dict({"workload": a["config"]["workload"]}, **{k: a[k] for k in keep}),
+            "c3b": dict({"workload": b["config"]["workload"]}, **{k: b[k] for k in keep})}
 
 
 def bench_single(args, prob):
@@ -234,12 +394,20 @@ def bench_single(args, prob):
     value, ms, roof, fit = run_materialised(args, prob, kdtype, not args.no_tune)
     out = base_line(args, prob, "f32" if kdtype == "fp32" else "bf16", {"k_storage": kdtype, "rank": fit["rank"]})
     out.update(value=round(value, 2), ms_per_step=round(ms, 3), roofline=roof, fit=fit)
+    if args.no_cert:
+        fit.pop("_iterate", None)
+    else:
+        out["error_vs_fp64"] = error_vs_fp64(prob, fit, kdtype)
     if not args.no_packed:
         # the same fit with K stored once (symmetric packed tiles): half the bytes per apply
         pv, pms, proof, pfit = run_materialised(args, prob, kdtype, not args.no_tune, layout=1)
+        pfit.pop("_iterate", None)
         out["compare_packed"] = {"k_storage": kdtype + ", symmetric packed tiles", "value": round(pv, 2),
                                  "ms_per_step": round(pms, 3), "roofline": proof, "fit": pfit,
                                  "speedup_vs_full": round(ms / pms, 3)}
+    if not args.no_compare and prob.name == "c1":
+        out["compare_bf16"] = compare_bf16_leg(args)
+        out["compare_batched"] = compare_batched_leg(args)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(prob, args.cpu_seconds)
     return out
@@ -250,6 +418,8 @@ def bench_c2(args, prob):
     v16, ms16, roof16, fit16 = run_materialised(args, prob, "bf16", not args.no_tune)
     v16c, ms16c, roof16c, fit16c = run_materialised(args, prob, "bf16", False, exact_k=1)
     v32, ms32, roof32, fit32 = run_materialised(args, prob, "fp32", not args.no_tune)
+    for f in (fit16, fit16c, fit32):
+        f.pop("_iterate", None)
     out = base_line(args, prob, "bf16", {"k_storage": "bf16 (inner) + exact FP32 entries recomputed from X",
                                          "rank": fit16["rank"]})
     out.update(value=round(v16, 2), ms_per_step=round(ms16, 3), roofline=roof16, fit=fit16)
@@ -262,6 +432,7 @@ def bench_c2(args, prob):
         # K stored once through its symmetry: BF16 tiles for the inner solves
         # and FP32 tiles for the exact applies (22.5 + 45 GB)
         vp, msp, roofp, fitp = run_materialised(args, prob, "bf16", not args.no_tune, layout=1, exact_k=1)
+        fitp.pop("_iterate", None)
         out["compare_packed_bf16_fp32_copy"] = {
             "k_storage": "bf16 packed tiles (inner) + FP32 packed tiles (exact applies)", "value": round(vp, 2),
             "ms_per_step": round(msp, 3), "roofline": roofp, "fit": fitp, "speedup_vs_fp32": round(ms32 / msp, 3)}
@@ -347,8 +518,8 @@ def bench_multi_tau(args, prob):
                                                      **opts)
         return infos, sts
 
-    tuned = None
-    if not args.no_tune:
+    tuned = {"from": args.tuned_from} if args.tuned_from else None
+    if not args.no_tune and not args.tuned_from:
         # untimed: pick the K V launch shape on this problem's own K
         K = kqr.kqr_kernel_build(X, prob.kernel, prob.gamma, kd)
         tuned = kqr.kqr_autotune_apply(K, kqr.KQR_APPLY_KV, reps=3)["best"]
@@ -371,7 +542,8 @@ def bench_multi_tau(args, prob):
     out["roofline"] = {
         "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-        "kernel": "kv_mfma_kernel (K V, V n x 16, %s K)" % kd, "avg_launch_us": round(avg * 1e6, 2),
+        "kernel": ("kv_staged_kernel" if (tuned or {}).get("nld", 0) == 0 else "kv_mfma_kernel")
+                  + " (K V, V n x 16, %s K)" % kd, "avg_launch_us": round(avg * 1e6, 2),
         "launches": int(nl), "bytes_per_launch": kbytes, "launch_shape": tuned or "default",
     }
     out["fit"] = {"status": sts, "eta_kkt_max": max(i["eta_kkt"] for i in infos),
@@ -408,8 +580,8 @@ def bench_path(args, prob):
         _, betas, infos, sts = kqr.kqr_fit_path(X, y, prob.tau, lams, prob.kernel, prob.gamma, uniforms=uni, **opts)
         return infos, sts
 
-    tuned = None
-    if not args.no_tune:
+    tuned = {"from": args.tuned_from} if args.tuned_from else None
+    if not args.no_tune and not args.tuned_from:
         K = kqr.kqr_kernel_build(X, prob.kernel, prob.gamma, kd)
         tuned = kqr.kqr_autotune_apply(K, kqr.KQR_APPLY_KV, reps=5)["best"]
         kqr.kqr_autotune_apply(K, kqr.KQR_APPLY_FAST, reps=5)
@@ -696,6 +868,102 @@ def bench_grad(args, prob):
     return out
 
 
+def bench_certify(args):
+    """Full-size fits of the precision and batching workloads, each certified
+    against FP64 on the host (oracle.certify); one JSON line per workload."""
+    import numpy as np
+    import torch
+
+    from oracle import certify
+    from paper_2510_07929_amd import inputs, kqr
+
+    dev = torch.device("cuda:0")
+    lines = []
+
+    def apply_errors(prob, modes):
+        """||u - K v|| / ||K v|| of one GPU K-apply per mode; K v in FP64 on the host."""
+        v = np.random.default_rng(17).standard_normal(prob.n)
+        X = torch.from_numpy(prob.X).to(dev)
+        vt = torch.from_numpy(v).to(dev)
+        us = {}
+        for name, kd, mode in modes:
+            if kd is None:
+                u = kqr.kqr_kernel_apply(vt, X=X, kernel=prob.kernel, gamma=prob.gamma, mode=mode)
+            else:
+                K = kqr.kqr_kernel_build(X, prob.kernel, prob.gamma, kd)
+                u = kqr.kqr_kernel_apply(vt, K=K, mode=mode)
+                del K
+            us[name] = u.cpu().numpy()
+            torch.cuda.empty_cache()
+        return v, us
+
+    def one(prob, label, **opts):
+        X = torch.from_numpy(prob.X).to(dev)
+        y = torch.from_numpy(prob.y).to(dev)
+        uni = inputs.pivot_uniforms(1024, (sum(map(ord, prob.name)), 0))
+        t0 = time.perf_counter()
+        alpha, beta, info, st = kqr.kqr_fit(X, y, prob.tau, prob.lam, prob.kernel, prob.gamma, uniforms=uni,
+                                            out_vz=True, **opts)
+        torch.cuda.synchronize()
+        t_fit = time.perf_counter() - t0
+        it = dict(alpha=alpha.cpu().numpy(), v=info.pop("v").cpu().numpy(), z=info.pop("z").cpu().numpy())
+        del X, y, alpha
+        torch.cuda.empty_cache()
+        return dict(label=label, status=st, t_fit_s=round(t_fit, 3), gpu_eta_kkt=info["eta_kkt"],
+                    gpu_eta_gap=info["eta_gap"], rank=info["rank_used"], kapply_calls=info["kapply_calls"]), it, beta
+
+    def certified(prob, label, modes, **opts):
+        row, it, beta = one(prob, label, **opts)
+        v, us = apply_errors(prob, modes)
+        t0 = time.perf_counter()
+        c = certify.certificate(prob.X, prob.y, prob.tau, prob.lam, prob.kernel, prob.gamma, it["alpha"], beta,
+                                v=it["v"], z=it["z"], extra=v)
+        kv = c["K_extra"][:, 0]
+        row.update(eta_kkt_fp64=c["eta_kkt"], eta_gap_fp64=c["eta_gap"], eta_p_fp64=c["eta_p"],
+                   eta_d_fp64=c["eta_d"], eta_c_fp64=c["eta_c"], rel_obj_err_bound=c["rel_obj_err_bound"],
+                   n_interior=c["n_interior"],
+                   kapply_rel_err={k: float(np.linalg.norm(u - kv) / np.linalg.norm(kv)) for k, u in us.items()},
+                   t_certificate_s=round(time.perf_counter() - t0, 1))
+        return row
+
+    c2 = inputs.workload("c2")
+    F, E = kqr.KQR_APPLY_FAST, kqr.KQR_APPLY_EXACT
+    for kd in ("bf16", "fp32"):
+        modes = [(f"fast_{kd}_k", kd, F)] + ([("exact_fp32_k", "fp32", E)] if kd == "fp32" else
+                                             [("exact_on_the_fly", None, E)])
+        lines.append(dict(workload="c2", **certified(c2, f"{kd} K", modes, rank=0, k_dtype=kqr.KDTYPES[kd],
+                                                     kmode=kqr.KQR_KMODE_MATERIALIZE)))
+        print(json.dumps(lines[-1]), flush=True)
+    lap = inputs.workload("c2lap")
+    lines.append(dict(workload="c2lap", **certified(lap, "on the fly", [("fast_on_the_fly", None, F),
+                                                                          ("exact_on_the_fly", None, E)],
+                                                     rank=0, kmode=kqr.KQR_KMODE_ON_THE_FLY)))
+    print(json.dumps(lines[-1]), flush=True)
+    c3 = inputs.workload("c3a")
+    X = torch.from_numpy(c3.X).to(dev)
+    y = torch.from_numpy(c3.y).to(dev)
+    taus = c3.extras["taus"]
+    uni = inputs.pivot_uniforms(1024, (sum(map(ord, c3.name)), 0))
+    t0 = time.perf_counter()
+    A, betas, infos, sts = kqr.kqr_fit_multi_tau(X, y, taus, c3.lam, c3.kernel, c3.gamma, uniforms=uni, rank=0,
+                                                 kmode=kqr.KQR_KMODE_MATERIALIZE)
+    torch.cuda.synchronize()
+    t_fit = time.perf_counter() - t0
+    A = A.cpu().numpy()
+    del X, y
+    torch.cuda.empty_cache()
+    t0 = time.perf_counter()
+    cs = certify.certificate_levels(c3.X, c3.y, taus, c3.lam, c3.kernel, c3.gamma, list(A), list(betas))
+    lines.append(dict(workload="c3a", label="nine levels jointly (FP32 K, K V)", t_fit_s=round(t_fit, 3),
+                      status=sts, t_certificate_s=round(time.perf_counter() - t0, 1),
+                      levels=[dict(tau=c["tau"], gpu_eta_kkt=i["eta_kkt"], gpu_eta_gap=i["eta_gap"],
+                                   res_eta_d_fp64=c["res_eta_d"], res_eta_c_fp64=c["res_eta_c"],
+                                   res_eta_gap_fp64=c["res_eta_gap"], rel_obj_err_bound=c["rel_obj_err_bound"],
+                                   n_interior=c["n_interior"]) for c, i in zip(cs, infos)]))
+    print(json.dumps(lines[-1]), flush=True)
+    return None
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -705,6 +973,10 @@ def main():
     from paper_2510_07929_amd import inputs
 
     w = args.workload
+    args.tuned_from = load_tuning(args)
+    if args.certify:
+        bench_certify(args)
+        return
     if w == "c3b":
         out = bench_batch(args)
     else:
@@ -725,6 +997,10 @@ def main():
             out = bench_linear(args, prob)
         else:
             out = bench_single(args, prob)
+    if args.tune_out:
+        from paper_2510_07929_amd import kqr
+
+        out["tune_entries_written"] = kqr.kqr_tune_save(args.tune_out)
     print(json.dumps(out), flush=True)
 
 

@@ -129,6 +129,11 @@ typedef struct kqr_options {
                           only the upper triangle of 128 x 128 tiles is stored (about half the
                           bytes, so half the HBM traffic per K-apply; see kqr_kernel_build_packed).
                           kqr_fit and kqr_fit_grad only; the joint and batched fits need 0.  0 */
+  double* z_out;       /* device n FP64 or NULL: kqr_fit writes the final multipliers z of (1.4)
+                          (the primal residual vector of Section 4).  NULL */
+  double* v_out;       /* device n FP64 or NULL: kqr_fit writes the final consensus vector v of (1.4),
+                          so that (alpha, v, beta, z) is the iterate the Section 4 measures in
+                          kqr_info were taken at.  NULL */
 } kqr_options;
 
 /* ---------------------------------------------------------------- report */
@@ -207,6 +212,16 @@ int kqr_set_packed_shape(int k_dtype, int mode, int map, int strip);
  * default 32 GiB) bounds that buffer for the whole process; at larger n the
  * applies stream all n^2 pairs with O(n) partial sums instead.  Host-only. */
 int kqr_set_otf_symmetric_limit(int64_t bytes);
+
+/* kqr_set_otf_shape: launch shape of the on-the-fly applies for the rest of
+ * the process (every later apply, fit and prediction).  strip: 128 x 128
+ * tiles per workgroup of the symmetric square applies, 1..32, or 0 = by size
+ * (2 tiles below 64 tile-rows, 8 from 64, 16 from 256, 32 from 1024); the
+ * partial-sum buffer grows as the strip shrinks.  wgs: workgroups a
+ * row-streamed launch (rectangles: prediction; squares beyond the symmetric
+ * limit) aims for by slicing its columns, 256..2^20, or 0 = 8192.
+ * Host-only; KQR_EINVAL outside those ranges. */
+int kqr_set_otf_shape(int strip, int64_t wgs);
 int kqr_kernel_build_packed(const float* X, int64_t n, int64_t p, int kernel, double gamma, int k_dtype, void* K,
                             void* stream);
 int kqr_kernel_apply_packed(const void* K, int k_dtype, int64_t n, const double* v, double* u, int mode,
@@ -221,9 +236,10 @@ int kqr_kernel_apply_packed(const void* K, int k_dtype, int64_t n, const double*
  *         call then blocks while it reads the column ranges).
  *  V      device, n x m FP64 row-major (ld ldv >= m);  U device, n x m FP64 (ld ldu >= m).
  *  mode   KQR_APPLY_FAST or KQR_APPLY_EXACT.  m > 1: FAST uses FP32 products with
- *         FP32 accumulation on the matrix cores; EXACT with an FP32 K and m <= 4
- *         forms all columns in FP64 (vectors, products, sums) from one pass over
- *         K; otherwise column by column.
+ *         FP32 accumulation on the matrix cores (one pass over K); EXACT with an
+ *         FP32 K and m <= 4 forms all columns in FP64 (vectors, products, sums)
+ *         from one pass over K; every other EXACT case runs column by column in
+ *         FP64 (so EXACT never drops to FP32 products).
  *  Needs 1 <= m <= 16.  Asynchronous on `stream`; allocates its device
  *  workspace on `stream` (stream-ordered) and frees it before returning. */
 int kqr_kernel_apply(const float* X, int64_t n, int64_t p, int kernel, double gamma,
@@ -290,6 +306,32 @@ int kqr_set_apply_shape(int k_dtype, int mode, int64_t n, int rows, int unroll, 
  * in {0,1}; 1 <= segs <= 8; otherwise KQR_EINVAL. */
 int kqr_set_kv_shape(int k_dtype, int64_t n, int nld, int prefetch, int segs);
 
+/* kqr_autotune_otf: times the on-the-fly applies on the caller's X (device,
+ * n x p FP32) for mode KQR_APPLY_FAST or KQR_APPLY_EXACT: the square apply
+ * K(X, X) v at every strip of its symmetric form (1, 2, 4, 8, 16, 32 tiles
+ * per workgroup, where the partial sums fit the symmetric limit), keeping
+ * the fastest for n's size class (as kqr_set_otf_shape would, for that class
+ * only), then the column-slice target of the row-streamed form on the
+ * rectangle K(X[0:n/4], X) v over 2048 .. 32768 workgroups, keeping the
+ * fastest.  JSON report into `report` (host, cap bytes, or NULL).
+ * Synchronises. */
+int kqr_autotune_otf(const float* X, int64_t n, int64_t p, int kernel, double gamma, int mode, int reps,
+                     char* report, int64_t cap, void* stream);
+
+/* kqr_tune_save / kqr_tune_load: the launch shapes installed in this
+ * process -- by kqr_autotune_apply (K-apply and K V), kqr_autotune_packed,
+ * kqr_autotune_otf and the kqr_set_*_shape calls -- written to / read from a
+ * JSON file at `path` (host string) keyed by the device architecture
+ * (hipDeviceProp_t.gcnArchName): one entry per (kernel, storage type, mode,
+ * size class of n, right-hand sides), with the measured launch time.
+ * Loading installs the entries recorded for the current device's
+ * architecture (none from another) and sets *count (host) to how many;
+ * saving sets it to the entries written.  A process started with the
+ * environment variable KQR_TUNE_FILE=<path> loads that file at its first
+ * call that uses the device. */
+int kqr_tune_save(const char* path, int* count);
+int kqr_tune_load(const char* path, int* count);
+
 /* kqr_woodbury_apply: out = P^{-1} w for P = F F^T + c 1 1^T + diag(Ldiag), by
  * Lemma 1 with U = [F 1] and the (r+1)x(r+1) core C = diag(I, 1/c) + U^T L^{-1} U
  * formed and Cholesky-factored in FP64 on the device.
@@ -322,6 +364,27 @@ int kqr_ssn_gradient(int64_t n, double tau, double lambda, double beta, double s
                      const double* Kalpha, const double* y, const double* z, double* grad,
                      uint8_t* S, double* Ldiag, double* rhs, double* gnorm, double* eps_t,
                      void* stream);
+
+/* kqr_kkt_residuals: the multiplier step of Algorithms 1 and 2 and the
+ * stopping measures of Section 4 at one iterate, by the kernel the fits use.
+ *  update = 1: first v = Pi_B(alpha + z/sigma) and z += step sigma (alpha - v)
+ *  (the z-part of the (beta, z) ascent of (2.1) and Algorithm 2, with v from
+ *  its closed form; beta is the caller's, already updated); update = 0: z and
+ *  v are used as given (sigma and step unused).  Then, with Kalpha = K alpha
+ *  supplied by the caller (any precision):
+ *    eta_p = ||z - y + beta 1 + Kalpha/lambda|| / (1 + ||y||)
+ *    eta_d = sqrt((1^T alpha)^2 + ||alpha - v||^2) / (1 + ||alpha||)
+ *    eta_c = ||v - Pi_B(z + v)|| / (1 + ||v||)
+ *    obj_p = rho_tau(z) + alpha^T Kalpha / (2 lambda)
+ *    obj_d = -alpha^T Kalpha / (2 lambda) + y^T alpha
+ *    eta_gap = |obj_p - obj_d| / (1 + |obj_p| + |obj_d|)
+ *  every product and sum in FP64, reduced in a fixed order.
+ *  alpha, Kalpha, y device n FP64; z, v device n FP64 (overwritten when
+ *  update = 1); out host double[7] = {eta_p, eta_d, eta_c, eta_kkt, eta_gap,
+ *  obj_p, obj_d}.  Blocks until out is written. */
+int kqr_kkt_residuals(int64_t n, double tau, double lambda, double beta, double sigma, double step, int update,
+                      const double* alpha, const double* Kalpha, const double* y, double* z, double* v, double* out,
+                      void* stream);
 
 /* ---------------------------------------------------------------- the fit
  * kqr_fit: PALM-KQR -- Phase I inexact ADMM (Algorithm 1) warm start, Phase II

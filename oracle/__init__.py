@@ -17,8 +17,14 @@ Everything here is plain NumPy/SciPy in float64, written from the paper:
 * ``adjoint``  -- implicit gradient of a validation check loss with respect
                   to log(gamma) and log(lambda) (not in the paper; derived
                   from the KKT system of the dual problem (1.3)).
+* ``certify``  -- FP64 certificate of a returned (alpha, beta) at any n: the
+                  Section 4 measures with the exact kernel and a weak-duality
+                  sandwich of the optimal value.  Its kernel products come
+                  from ``kapply.c`` (plain C, FP64, direct differences, rows
+                  over OpenMP threads), compiled by ``build_c``.
 
 Points the paper leaves open are fixed by the constants in
 ``solver.OracleOptions``; each default states its reading.
 """
 from . import kernel, problem, precond, solver, adjoint  # noqa: F401
+# certify loads the C library on first use; import it explicitly: from oracle import certify

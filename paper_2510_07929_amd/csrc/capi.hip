@@ -2,6 +2,7 @@
 // dispatch.  No exception crosses the ABI: every entry point returns a status.
 #include "adjoint.h"
 #include "fit.h"
+#include "kernel_entry.h"
 
 #include <algorithm>
 #include <chrono>
@@ -62,6 +63,7 @@ void ensure_device() {
     (void)hipGetLastError();
     fail(KQR_ENODEVICE, "no HIP device available");
   }
+  tune_autoload();  // launch shapes from KQR_TUNE_FILE, once per process
 }
 
 template <typename Fn>
@@ -153,6 +155,7 @@ static void autotune_kv(const KMat& km, int64_t n, int reps, char* report, int64
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   set_kv_shape(km.dtype, n, best);
+  tune_record(TuneEntry{"kv", km.dtype, 0, n, 16, best.nld, best.prefetch, best.segs, 0, best_us});
   char buf[160];
   snprintf(buf, sizeof(buf), "], \"best\": {\"nld\": %d, \"prefetch\": %d, \"segs\": %d, \"us\": %.2f}}", best.nld,
            best.prefetch, best.segs, best_us);
@@ -210,10 +213,110 @@ static void autotune_packed(const KMat& km, int64_t n, bool exact, int reps, cha
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   set_packed_shape(km.dtype, exact, best);
+  tune_record(TuneEntry{"packed", km.dtype, exact ? 1 : 0, n, 1, best.map, best.strip, 0, 0, best_us});
   char buf[160];
   snprintf(buf, sizeof(buf), "], \"best\": {\"map\": %d, \"strip\": %d, \"us\": %.2f}}", best.map, best.strip,
            best_us);
   rep += buf;
+  if (report && cap > 0) {
+    const size_t nb = std::min<size_t>(size_t(cap) - 1, rep.size());
+    memcpy(report, rep.data(), nb);
+    report[nb] = '\0';
+  }
+}
+
+// Times the square on-the-fly apply K(X, X) v at n for every strip of the
+// symmetric form {1, 2, 4, 8, 16, 32} (those whose partial sums fit the
+// budget) and installs the fastest for n's size class; then the column-slice
+// target of the row-streamed form on a rectangle K(X[0:n/4], X) v, over
+// {2048, 4096, 8192, 16384, 32768} workgroups.  JSON report.
+static void autotune_otf(const float* X, int64_t n, int p, KernelSpec ks, bool exact, int reps, char* report,
+                         int64_t cap, hipStream_t st) {
+  DevBuf sqn(size_t(n) * sizeof(float)), v(size_t(n) * sizeof(double)), u(size_t(n) * sizeof(double));
+  row_sqnorms(X, n, p, sqn.as<float>(), st);
+  fill(n, 1.0 / double(n), v.as<double>(), st);
+  DevBuf xq;
+  int shift = -1;
+  if (ks.kind == KQR_LAPLACIAN) {
+    xq.alloc(size_t(n) * size_t(p) * sizeof(uint32_t));
+    shift = quantize_columns(X, n, p, xq.as<uint32_t>(), st);
+  }
+  const bool sym = (ks.kind == KQR_RBF && p <= 32) || shift >= 20;
+  const int keep_strip = otf_strip_for(n);
+  const int64_t keep_wgs = otf_wgs();
+  hipEvent_t e0, e1;
+  KQR_CHECK_HIP(hipEventCreate(&e0));
+  KQR_CHECK_HIP(hipEventCreate(&e1));
+  auto time_us = [&](auto&& launch) {
+    launch();  // warm-up
+    KQR_CHECK_HIP(hipEventRecord(e0, st));
+    for (int k = 0; k < reps; ++k) launch();
+    KQR_CHECK_HIP(hipEventRecord(e1, st));
+    KQR_CHECK_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    KQR_CHECK_HIP(hipEventElapsedTime(&ms, e0, e1));
+    return 1e3 * double(ms) / reps;
+  };
+  std::string rep = "{\"n\": " + std::to_string(n) + ", \"p\": " + std::to_string(p) +
+                    ", \"exact\": " + std::to_string(int(exact)) + ", \"strips\": [";
+  int best_strip = keep_strip;
+  double best_us = 1e300;
+  bool first = true;
+  try {
+    if (sym) {
+      for (int strip : {1, 2, 4, 8, 16, 32}) {
+        set_otf_strip_for(n, strip);
+        const size_t need = otf_sym_scratch_doubles(n);
+        if (need == 0) continue;  // partial sums beyond the budget at this strip
+        DevBuf scr(need * sizeof(double));
+        const double us = time_us([&] {
+          if (shift >= 20)
+            kapply_otf_l1q(xq.as<uint32_t>(), n, p, ks.gamma, shift, v.as<double>(), u.as<double>(), 1, exact, st,
+                           scr.as<double>(), need);
+          else
+            kapply_otf(X, sqn.as<float>(), n, X, sqn.as<float>(), n, p, ks, v.as<double>(), u.as<double>(), 1, 1.0,
+                       0.0, st, exact, scr.as<double>(), need);
+        });
+        char buf[96];
+        snprintf(buf, sizeof(buf), "%s{\"strip\": %d, \"us\": %.2f}", first ? "" : ", ", strip, us);
+        first = false;
+        rep += buf;
+        if (us < best_us) { best_us = us; best_strip = strip; }
+      }
+    }
+    set_otf_strip_for(n, sym ? best_strip : keep_strip);
+    rep += "], \"wgs\": [";
+    const int64_t nr = std::max<int64_t>(1, n / 4);
+    int64_t best_wgs = keep_wgs;
+    double best_wus = 1e300;
+    first = true;
+    for (int64_t w : {int64_t(2048), int64_t(4096), int64_t(8192), int64_t(16384), int64_t(32768)}) {
+      set_otf_wgs(w);
+      const double us = time_us([&] {
+        kapply_otf(X, sqn.as<float>(), nr, X, sqn.as<float>(), n, p, ks, v.as<double>(), u.as<double>(), 1, 1.0, 0.0,
+                   st, exact);
+      });
+      char buf[96];
+      snprintf(buf, sizeof(buf), "%s{\"wgs\": %lld, \"us\": %.2f}", first ? "" : ", ", (long long)w, us);
+      first = false;
+      rep += buf;
+      if (us < best_wus) { best_wus = us; best_wgs = w; }
+    }
+    set_otf_wgs(best_wgs);
+    tune_record(TuneEntry{"otf", 0, exact ? 1 : 0, n, 1, sym ? best_strip : 0, 0, 0, best_wgs, sym ? best_us : 0.0});
+    char buf[160];
+    snprintf(buf, sizeof(buf), "], \"best\": {\"strip\": %d, \"us\": %.2f, \"wgs\": %lld, \"wgs_us\": %.2f}}",
+             sym ? best_strip : 0, sym ? best_us : 0.0, (long long)best_wgs, best_wus);
+    rep += buf;
+  } catch (...) {
+    set_otf_strip_for(n, keep_strip);
+    set_otf_wgs(keep_wgs);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    throw;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   if (report && cap > 0) {
     const size_t nb = std::min<size_t>(size_t(cap) - 1, rep.size());
     memcpy(report, rep.data(), nb);
@@ -352,7 +455,7 @@ int kqr_kernel_apply(const float* X, int64_t n, int64_t p, int kernel, double ga
           hipMallocAsync(reinterpret_cast<void**>(&part), kv_scratch_doubles(n) * sizeof(double), st));
       float* V16 = nullptr;  // no fast columns: zeros for the matrix-core half of the pass
       KQR_CHECK_HIP(hipMallocAsync(reinterpret_cast<void**>(&V16), size_t(n) * 16 * sizeof(float), st));
-      KQR_CHECK_HIP(hipMemsetAsync(V16, 0, size_t(n) * 16 * sizeof(float), st));
+      fill(n * 8, 0.0, reinterpret_cast<double*>(V16), st);  // 16 FP32 zeros per row, by a kernel (capturable)
       SrcTable16 xs{};
       DstTable16 xd{};
       for (int64_t j = 0; j < m; ++j) {
@@ -371,7 +474,7 @@ int kqr_kernel_apply(const float* X, int64_t n, int64_t p, int kernel, double ga
       KQR_CHECK_HIP(hipFreeAsync(cols, st));
       m = 0;  // done
     }
-    if (K && m > 1) {  // all columns in one pass over K on the matrix cores
+    if (K && m > 1 && mode == KQR_APPLY_FAST) {  // all columns in one pass over K on the matrix cores
       float* V16 = nullptr;
       double* part = nullptr;
       KQR_CHECK_HIP(hipMallocAsync(reinterpret_cast<void**>(&V16), size_t(n) * 16 * sizeof(float), st));
@@ -476,6 +579,7 @@ int kqr_set_packed_shape(int k_dtype, int mode, int map, int strip) {
     const PackedShape s{map, strip};
     KQR_REQUIRE(packed_shape_supported(s), "need map 0 to 3 and 1 <= strip <= 32");
     set_packed_shape(k_dtype, mode == KQR_APPLY_EXACT, s);
+    tune_record(TuneEntry{"packed", k_dtype, mode == KQR_APPLY_EXACT ? 1 : 0, 0, 1, map, strip, 0, 0, 0.0});
   });
 }
 
@@ -483,6 +587,46 @@ int kqr_set_otf_symmetric_limit(int64_t bytes) {
   return guarded([&] {
     KQR_REQUIRE(bytes >= 0, "bytes must be >= 0");
     set_otf_sym_budget(bytes);
+  });
+}
+
+int kqr_set_otf_shape(int strip, int64_t wgs) {
+  return guarded([&] {
+    KQR_REQUIRE(strip >= 0 && strip <= kPkMaxStrip, "need 0 <= strip <= 32");
+    KQR_REQUIRE(wgs == 0 || (wgs >= 256 && wgs <= (int64_t(1) << 20)), "need wgs = 0 or 256 <= wgs <= 2^20");
+    set_otf_shape(strip, wgs);
+    for (int64_t nc : {int64_t(1), int64_t(64) * kPkT, int64_t(256) * kPkT, int64_t(1024) * kPkT})
+      tune_record(TuneEntry{"otf", 0, 0, nc, 1, strip, 0, 0, wgs, 0.0});
+  });
+}
+
+int kqr_autotune_otf(const float* X, int64_t n, int64_t p, int kernel, double gamma, int mode, int reps,
+                     char* report, int64_t cap, void* stream) {
+  return guarded([&] {
+    KQR_REQUIRE(X != nullptr, "X must be non-null");
+    KQR_REQUIRE(n >= 1 && p >= 1 && p <= 64 && reps >= 1, "need n >= 1, 1 <= p <= 64, reps >= 1");
+    KQR_REQUIRE(kernel == KQR_RBF || kernel == KQR_LAPLACIAN, "kernel must be KQR_RBF or KQR_LAPLACIAN");
+    KQR_REQUIRE(std::isfinite(gamma) && gamma > 0.0, "gamma must be positive and finite");
+    KQR_REQUIRE(mode == KQR_APPLY_FAST || mode == KQR_APPLY_EXACT, "mode must be KQR_APPLY_FAST or KQR_APPLY_EXACT");
+    ensure_device();
+    autotune_otf(X, n, int(p), KernelSpec{kernel, gamma}, mode == KQR_APPLY_EXACT, reps, report, cap,
+                 static_cast<hipStream_t>(stream));
+  });
+}
+
+int kqr_tune_save(const char* path, int* count) {
+  return guarded([&] {
+    KQR_REQUIRE(path != nullptr && count != nullptr, "path and count must be non-null");
+    ensure_device();
+    *count = tune_save(path);
+  });
+}
+
+int kqr_tune_load(const char* path, int* count) {
+  return guarded([&] {
+    KQR_REQUIRE(path != nullptr && count != nullptr, "path and count must be non-null");
+    ensure_device();
+    *count = tune_load(path);
   });
 }
 
@@ -614,6 +758,8 @@ int kqr_autotune_apply(const void* K, int k_dtype, int64_t n, int64_t ldk, int m
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     set_apply_shape(k_dtype, mode == KQR_APPLY_EXACT, n, best);
+    tune_record(TuneEntry{"apply", k_dtype, mode == KQR_APPLY_EXACT ? 1 : 0, n, 1, best.rows, best.unroll, best.segs, 0,
+                          best_us});
     char buf[160];
     snprintf(buf, sizeof(buf), "], \"best\": {\"rows\": %d, \"unroll\": %d, \"segs\": %d, \"us\": %.2f}}", best.rows,
              best.unroll, best.segs, best_us);
@@ -636,6 +782,7 @@ int kqr_set_apply_shape(int k_dtype, int mode, int64_t n, int rows, int unroll, 
     s.segs = segs;
     KQR_REQUIRE(apply_shape_supported(s), "unsupported shape (rows in {2,4,8}, unroll in {1,2,4}, 1 <= segs <= 64)");
     set_apply_shape(k_dtype, mode == KQR_APPLY_EXACT, n, s);
+    tune_record(TuneEntry{"apply", k_dtype, mode == KQR_APPLY_EXACT ? 1 : 0, n, 1, rows, unroll, segs, 0, 0.0});
   });
 }
 
@@ -649,6 +796,7 @@ int kqr_set_kv_shape(int k_dtype, int64_t n, int nld, int prefetch, int segs) {
     s.segs = segs;
     KQR_REQUIRE(kv_shape_supported(s), "unsupported K V shape (nld in {0,4,8}, 1 <= segs <= 8)");
     set_kv_shape(k_dtype, n, s);
+    tune_record(TuneEntry{"kv", k_dtype, 0, n, 16, nld, prefetch, segs, 0, 0.0});
   });
 }
 
@@ -728,6 +876,35 @@ int kqr_ssn_gradient(int64_t n, double tau, double lambda, double beta, double s
   });
 }
 
+int kqr_kkt_residuals(int64_t n, double tau, double lambda, double beta, double sigma, double step, int update,
+                      const double* alpha, const double* Kalpha, const double* y, double* z, double* v, double* out,
+                      void* stream) {
+  return guarded([&] {
+    KQR_REQUIRE(alpha && Kalpha && y && z && v && out, "pointers must be non-null");
+    KQR_REQUIRE(n >= 1 && tau > 0.0 && tau < 1.0, "need n >= 1 and 0 < tau < 1");
+    KQR_REQUIRE(std::isfinite(lambda) && lambda > 0.0 && std::isfinite(beta), "need lambda > 0 and finite beta");
+    KQR_REQUIRE(update == 0 || update == 1, "update must be 0 or 1");
+    KQR_REQUIRE(update == 0 || (std::isfinite(sigma) && sigma > 0.0 && std::isfinite(step)),
+                "the multiplier step needs sigma > 0 and a finite step");
+    ensure_device();
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    Workspace ws;
+    DevBuf red(16 * sizeof(double));
+    HostPinned h(16 * sizeof(double));
+    vec_dots(n, y, nullptr, ws, red.as<double>(), st);  // [sum, -, ||y||^2]
+    KQR_CHECK_HIP(hipMemcpyAsync(h.ptr, red.ptr, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
+    KQR_CHECK_HIP(hipStreamSynchronize(st));
+    const double ynorm = std::sqrt(std::max(h.as<double>()[2], 0.0));
+    multiplier_kkt(n, alpha, Kalpha, y, z, v, beta, update ? sigma : 1.0, update ? step : 0.0, tau, lambda,
+                   update != 0, ws, red.as<double>(), st);
+    KQR_CHECK_HIP(hipMemcpyAsync(h.ptr, red.ptr, kKktSums * sizeof(double), hipMemcpyDeviceToHost, st));
+    KQR_CHECK_HIP(hipStreamSynchronize(st));
+    const Kkt k = kkt_from_sums(h.as<double>(), ynorm, lambda);
+    const double vals[7] = {k.eta_p, k.eta_d, k.eta_c, k.eta_kkt, k.eta_gap, k.obj_p, k.obj_d};
+    memcpy(out, vals, sizeof(vals));
+  });
+}
+
 int kqr_fit(const float* X, const double* y, int64_t n, int64_t p, double tau, double lambda, int kernel, double gamma,
             const kqr_options* opt, double* alpha, double* beta, kqr_info* info, void* stream) {
   int converged = 0;
@@ -748,7 +925,7 @@ int kqr_fit(const float* X, const double* y, int64_t n, int64_t p, double tau, d
     Operator op(X, n, int(p), ks, pr.kmat(), st);
     pr.attach(op);
     op.enable_profile(o.profile != 0);
-    FitOutcome out = run_fit(op, pr, y, n, tau, lambda, o, alpha, st);
+    FitOutcome out = run_fit(op, pr, y, n, tau, lambda, o, alpha, st, o.z_out, o.v_out);
     *beta = out.beta;
     converged = out.converged;
     if (info) *info = out.info;

@@ -39,9 +39,11 @@ struct FitOutcome {
 };
 
 // Runs Phase I, Phase II and the final residuals; copies alpha to alpha_out
-// and, when z_out is given, the final multipliers z to z_out (device, n).
+// and, when z_out / v_out are given, the final multipliers z and the final
+// consensus vector v to them (device, n).
 FitOutcome run_fit(Operator& op, const Prepared& pr, const double* y, int64_t n, double tau, double lam,
-                   const kqr_options& o, double* alpha_out, hipStream_t st, double* z_out = nullptr);
+                   const kqr_options& o, double* alpha_out, hipStream_t st, double* z_out = nullptr,
+                   double* v_out = nullptr);
 
 // tau batch: every level shares K and F; fast K-applies of all levels are
 // coalesced into one K V launch on the matrix cores.

@@ -133,7 +133,7 @@ Prepared prepare_fit(const float* X, int64_t n, int p, KernelSpec ks, const kqr_
 }
 
 FitOutcome run_fit(Operator& op, const Prepared& pr, const double* y, int64_t n, double tau, double lam,
-                   const kqr_options& o, double* alpha_out, hipStream_t st, double* z_out) {
+                   const kqr_options& o, double* alpha_out, hipStream_t st, double* z_out, double* v_out) {
   FitOutcome out;
   kqr_info& inf = out.info;
   memset(&inf, 0, sizeof(inf));
@@ -148,6 +148,8 @@ FitOutcome run_fit(Operator& op, const Prepared& pr, const double* y, int64_t n,
   KQR_CHECK_HIP(hipMemcpyAsync(alpha_out, solver.alpha(), size_t(n) * sizeof(double), hipMemcpyDeviceToDevice, st));
   if (z_out)
     KQR_CHECK_HIP(hipMemcpyAsync(z_out, solver.z(), size_t(n) * sizeof(double), hipMemcpyDeviceToDevice, st));
+  if (v_out)
+    KQR_CHECK_HIP(hipMemcpyAsync(v_out, solver.v(), size_t(n) * sizeof(double), hipMemcpyDeviceToDevice, st));
   KQR_CHECK_HIP(hipStreamSynchronize(st));
   out.beta = solver.beta();
   out.converged = solver.converged();

@@ -44,6 +44,10 @@ void row_sqnorms(const float* X, int64_t n, int p, float* sqn, hipStream_t st) {
 }
 
 // ================================================================= K build
+bool kbuild_mfma(const float* X, const float* q, int64_t n, int p, KernelSpec ks, int dtype, void* K, int64_t ldk,
+                 int layout, hipStream_t st);  // below, with the matrix-core helpers
+
+// Laplacian, and RBF with p > 32: entries on the VALU.
 // Block: 16 rows x 256 columns.  Row tile of X and its norms staged in LDS
 // (broadcast reads); each thread keeps its column x_j in registers.
 template <int PMAX, bool LAP, bool BF16>
@@ -117,6 +121,7 @@ static void kbuild_p(const float* X, const float* q, int64_t n, int p, KernelSpe
 void kbuild(const float* X, const float* sqn, int64_t n, int p, KernelSpec ks, int dtype, void* K,
             int64_t ldk, hipStream_t st) {
   if (n <= 0) return;
+  if (kbuild_mfma(X, sqn, n, p, ks, dtype, K, ldk, 0, st)) return;  // RBF, p <= 32: Gram on the matrix cores
   KQR_DISPATCH_P(p, kbuild_p, X, sqn, n, p, ks, dtype, K, ldk, st);
 }
 
@@ -381,8 +386,11 @@ constexpr int kOtfTile = 64;
 // rounds of the blocks the chip holds at once, so the last round is a small
 // tail), each slice at least 1024 columns.  Every slice writes one partial
 // per row, added in slice order by otf_reduce_kernel.
+std::atomic<int64_t> g_otf_wgs{8192};  // target workgroups of a sliced launch (kqr_set_otf_shape)
+
 static int64_t otf_slices(int64_t rblk, int64_t nc) {
-  const int64_t want = (8192 + std::max<int64_t>(rblk, 1) - 1) / std::max<int64_t>(rblk, 1);
+  const int64_t wgs = g_otf_wgs.load();
+  const int64_t want = (wgs + std::max<int64_t>(rblk, 1) - 1) / std::max<int64_t>(rblk, 1);
   return std::max<int64_t>(1, std::min<int64_t>(want, (nc + 1023) / 1024));
 }
 
@@ -737,10 +745,36 @@ __global__ __launch_bounds__(256) void kapply_otf_l1q_sym_kernel(const uint32_t*
   }
 }
 
-static int otf_sym_strip(int64_t n) {  // tiles per workgroup of the symmetric applies
+// Tiles per workgroup of the symmetric applies, per size class of n (tile
+// rows below 64, 256, 1024, and from 1024): installed by kqr_set_otf_shape
+// or the on-the-fly autotuner (1..kPkMaxStrip), else by size.
+std::atomic<int> g_otf_strip[4] = {{0}, {0}, {0}, {0}};
+
+static int otf_class(int64_t n) {
   const int64_t nt = (n + kPkT - 1) / kPkT;
-  return nt >= 1024 ? 32 : (nt >= 256 ? 16 : (nt >= 64 ? 8 : 2));
+  return nt >= 1024 ? 3 : (nt >= 256 ? 2 : (nt >= 64 ? 1 : 0));
 }
+
+static int otf_sym_strip(int64_t n) {
+  const int c = otf_class(n);
+  const int s = g_otf_strip[c].load();
+  if (s > 0) return s;
+  static const int rule[4] = {2, 8, 16, 32};
+  return rule[c];
+}
+
+void set_otf_shape(int strip, int64_t wgs) {
+  for (auto& a : g_otf_strip) a.store(strip);
+  g_otf_wgs.store(wgs > 0 ? wgs : 8192);
+}
+
+void set_otf_strip_for(int64_t n, int strip) { g_otf_strip[otf_class(n)].store(strip); }
+
+int64_t otf_wgs() { return g_otf_wgs.load(); }
+
+void set_otf_wgs(int64_t wgs) { g_otf_wgs.store(wgs > 0 ? wgs : 8192); }
+
+int otf_strip_for(int64_t n) { return otf_sym_strip(n); }
 
 // The symmetric applies keep one FP64 partial per tile and column, about
 // n^2 / 32 bytes (3 GB at n = 300,000, 31 GB at n = 10^6).  Beyond a
@@ -1031,9 +1065,10 @@ __device__ __forceinline__ float b3_coord(const float* __restrict__ x, float q, 
   return 0.f;
 }
 
-// out[j * 96 + plane * 32 + k]: the parts of column j's coordinate k; one
-// thread per column and 8-coordinate group.
-template <bool AUG>
+// out[j * 96 + plane * 32 + k]: the parts of point j's coordinate k, as the
+// column (scaled, COL) or the row side; one thread per point and
+// 8-coordinate group.
+template <bool AUG, bool COL = true>
 __global__ __launch_bounds__(256) void kotf_split_cols_kernel(const float* __restrict__ Xc,
                                                               const float* __restrict__ qc, int64_t nc, int p,
                                                               float ng, uint16_t* __restrict__ out) {
@@ -1046,7 +1081,7 @@ __global__ __launch_bounds__(256) void kotf_split_cols_kernel(const float* __res
 #pragma unroll
   for (int e = 0; e < 8; ++e) {
     uint16_t hh, mm, ll;
-    split3_bf16(b3_coord<AUG, true>(Xc + j * p, q, 8 * g + e, p, AUG ? ng : 1.f), hh, mm, ll);
+    split3_bf16(b3_coord<AUG, COL>(Xc + j * p, q, 8 * g + e, p, (AUG && COL) ? ng : 1.f), hh, mm, ll);
     h[e] = hh;
     m[e] = mm;
     l[e] = ll;
@@ -1597,6 +1632,172 @@ void kapply_otf(const float* Xr, const float* sqr, int64_t nr, const float* Xc, 
 #undef KQR_OTF_MFMA
   }
   KQR_DISPATCH_P(p, kapply_otf_p, Xr, sqr, nr, Xc, sqc, nc, p, ks, v64, u, ldu, out_scale, out_shift, exact, st);
+}
+
+// ================================================================= K build on the matrix cores
+// RBF with p <= 32: the Gram term of every 16 x 16 block by six
+// v_mfma_f32_16x16x32_bf16 on the exact BF16x3 split of both sides (as the
+// on-the-fly applies), with the norms and the exponent's scale folded into
+// the spare coordinates when p <= 30 (the matrix cores then return
+// c d_ij, c = -gamma log2(e)), so an entry costs the lanes a clamp, the
+// exponential, the diagonal test and its share of a store.  Both sides are
+// split once per build into buffers of 96 halves per point (row side
+// [x, 1, q], column side [-2 c x, c q, c]; without the fold [x] and [-2 x]).
+//
+// Operand roles are chosen for the stores: the A operand carries 16 columns
+// j of K and the B operand 16 rows i, so the lane that receives
+// C[4 g + r][l] holds K[i0 + l][j0 + 4 g + r], r = 0..3: four consecutive
+// entries of one row, written by one 16-byte (FP32) or 8-byte (BF16) store.
+// A workgroup is four waves of 32 rows each (two 16-row strips as B operands
+// held in registers); every 16-column step loads the column parts once per
+// wave (from L2: 192 bytes per column) and serves both strips.
+//   full layout  : 128 rows x `cols` columns of the n x ldk matrix per workgroup
+//                  (columns n..ldk-1 written as 0, rows >= n not written);
+//   packed layout: one 128 x 128 upper-triangle tile per workgroup (entries
+//                  beyond n written as 0, as the tile layout requires).
+// K_ii is set to exactly 1 (d_ii := 0).
+typedef uint32_t u32x2_t __attribute__((ext_vector_type(2)));
+
+template <bool AUG, bool BF, bool PACKED>
+__global__ __launch_bounds__(256) void kbuild_b3_kernel(const uint16_t* __restrict__ Pr, const uint16_t* __restrict__ Sc,
+                                                        const float* __restrict__ q, int64_t n, float ng,
+                                                        void* __restrict__ Kout, int64_t ldk, int64_t nt,
+                                                        int64_t cols) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lg = lane >> 4;
+  int64_t rbase, cbeg, cend;
+  size_t tile_base = 0;
+  if (PACKED) {
+    const int64_t t = blockIdx.x;
+    int64_t lo = 0, hi = nt - 1;  // largest I whose first tile index is <= t
+    while (lo < hi) {
+      const int64_t mid = (lo + hi + 1) / 2;
+      if (pk_tile_index(mid, mid, nt) <= t) lo = mid;
+      else hi = mid - 1;
+    }
+    const int64_t J = lo + (t - pk_tile_index(lo, lo, nt));
+    rbase = lo * kPkT;
+    cbeg = J * kPkT;
+    cend = cbeg + kPkT;
+    tile_base = size_t(t) * kPkT * kPkT;
+  } else {
+    rbase = int64_t(blockIdx.x) * 128;
+    cbeg = int64_t(blockIdx.y) * cols;
+    cend = min(ldk, cbeg + cols);
+  }
+  // B operands: rows rbase + 32 wave + 16 s + li, coordinates 8 lg .. 8 lg + 7
+  bf16x8_t bh[2], bm[2], bl[2];
+  float qi[2];
+  int64_t irow[2];
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    const int64_t i = rbase + 32 * wave + 16 * s + li;
+    irow[s] = i;
+    const int64_t ic = min(i, n - 1);  // rows past n: any valid point (their entries are not kept)
+    bh[s] = *reinterpret_cast<const bf16x8_t*>(Pr + ic * kB3Stride + 8 * lg);
+    bm[s] = *reinterpret_cast<const bf16x8_t*>(Pr + ic * kB3Stride + 32 + 8 * lg);
+    bl[s] = *reinterpret_cast<const bf16x8_t*>(Pr + ic * kB3Stride + 64 + 8 * lg);
+    qi[s] = AUG ? 0.f : q[ic];
+  }
+  for (int64_t jb = cbeg; jb < cend; jb += 16) {
+    const int64_t jc = min(jb + li, n - 1);  // columns past n: any valid point (written as 0)
+    const bf16x8_t ah = *reinterpret_cast<const bf16x8_t*>(Sc + jc * kB3Stride + 8 * lg);
+    const bf16x8_t am = *reinterpret_cast<const bf16x8_t*>(Sc + jc * kB3Stride + 32 + 8 * lg);
+    const bf16x8_t al = *reinterpret_cast<const bf16x8_t*>(Sc + jc * kB3Stride + 64 + 8 * lg);
+    const int64_t j0 = jb + 4 * lg;  // this lane's four columns j0 .. j0 + 3
+    float qj[4] = {0.f, 0.f, 0.f, 0.f};
+    if (!AUG) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) qj[r] = q[min(j0 + r, n - 1)];
+    }
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      f32x4_t c = f32x4_t{0.f, 0.f, 0.f, 0.f};  // smallest products first
+      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bm[s], c, 0, 0, 0);
+      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[s], c, 0, 0, 0);
+      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[s], c, 0, 0, 0);
+      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bh[s], c, 0, 0, 0);
+      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bm[s], c, 0, 0, 0);
+      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[s], c, 0, 0, 0);
+      const int64_t i = irow[s];
+      float e[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t j = j0 + r;
+        // ng < 0: min(ng d, 0) = ng max(d, 0)
+        const float a = AUG ? c[r] : ng * (qi[s] + qj[r] + c[r]);
+        const float ev = i == j ? 1.f : kexp2(fminf(a, 0.f));
+        e[r] = (j < n && i < n) ? ev : 0.f;
+      }
+      if (PACKED) {
+        const size_t off = tile_base + size_t(i - rbase) * kPkT + size_t(j0 - cbeg);
+        if (BF) {
+          const uint32_t w0 = uint32_t(f32_to_bf16(e[0])) | (uint32_t(f32_to_bf16(e[1])) << 16);
+          const uint32_t w1 = uint32_t(f32_to_bf16(e[2])) | (uint32_t(f32_to_bf16(e[3])) << 16);
+          __builtin_nontemporal_store(u32x2_t{w0, w1}, reinterpret_cast<u32x2_t*>(static_cast<uint16_t*>(Kout) + off));
+        } else {
+          __builtin_nontemporal_store(f32x4_t{e[0], e[1], e[2], e[3]},
+                                      reinterpret_cast<f32x4_t*>(static_cast<float*>(Kout) + off));
+        }
+      } else if (i < n) {
+        const size_t off = size_t(i) * size_t(ldk) + size_t(j0);
+        if (BF) {
+          const uint32_t w0 = uint32_t(f32_to_bf16(e[0])) | (uint32_t(f32_to_bf16(e[1])) << 16);
+          const uint32_t w1 = uint32_t(f32_to_bf16(e[2])) | (uint32_t(f32_to_bf16(e[3])) << 16);
+          __builtin_nontemporal_store(u32x2_t{w0, w1}, reinterpret_cast<u32x2_t*>(static_cast<uint16_t*>(Kout) + off));
+        } else {
+          __builtin_nontemporal_store(f32x4_t{e[0], e[1], e[2], e[3]},
+                                      reinterpret_cast<f32x4_t*>(static_cast<float*>(Kout) + off));
+        }
+      }
+    }
+  }
+}
+
+// Columns per workgroup of the full-layout build.
+constexpr int64_t kBuildCols = 1024;
+
+bool kbuild_mfma(const float* X, const float* q, int64_t n, int p, KernelSpec ks, int dtype, void* K, int64_t ldk,
+                 int layout, hipStream_t st) {
+  if (ks.kind != KQR_RBF || p > 32 || n <= 0) return false;
+  if (layout == 0 && ldk % 16 != 0) return false;  // the stores cover 16-column steps up to ldk
+  const bool aug = p <= 30, bf = dtype == KQR_BF16;
+  const float ng = -float(ks.gamma) * kLog2e;
+  uint16_t* buf = nullptr;
+  const size_t half_bytes = size_t(n) * kB3Stride * sizeof(uint16_t);
+  KQR_CHECK_HIP(hipMallocAsync(reinterpret_cast<void**>(&buf), 2 * half_bytes, st));
+  uint16_t* Pr = buf;                      // row side
+  uint16_t* Sc = buf + size_t(n) * kB3Stride;  // column side (scaled)
+  const dim3 sgrid((unsigned)((n * 4 + 255) / 256));
+  if (aug) {
+    kotf_split_cols_kernel<true, false><<<sgrid, 256, 0, st>>>(X, q, n, p, ng, Pr);
+    kotf_split_cols_kernel<true, true><<<sgrid, 256, 0, st>>>(X, q, n, p, ng, Sc);
+  } else {
+    kotf_split_cols_kernel<false, false><<<sgrid, 256, 0, st>>>(X, q, n, p, ng, Pr);
+    kotf_split_cols_kernel<false, true><<<sgrid, 256, 0, st>>>(X, q, n, p, ng, Sc);
+  }
+  KQR_LAUNCH_CHECK();
+  const int64_t nt = (n + kPkT - 1) / kPkT;
+  dim3 grid;
+  if (layout == 1) grid = dim3((unsigned)packed_tile_count(n));
+  else grid = dim3((unsigned)((n + 127) / 128), (unsigned)((ldk + kBuildCols - 1) / kBuildCols));
+#define KQR_B3(A, B, P) \
+  kbuild_b3_kernel<A, B, P><<<grid, 256, 0, st>>>(Pr, Sc, q, n, ng, K, ldk, nt, kBuildCols)
+  if (layout == 1) {
+    if (aug && bf) KQR_B3(true, true, true);
+    else if (aug) KQR_B3(true, false, true);
+    else if (bf) KQR_B3(false, true, true);
+    else KQR_B3(false, false, true);
+  } else {
+    if (aug && bf) KQR_B3(true, true, false);
+    else if (aug) KQR_B3(true, false, false);
+    else if (bf) KQR_B3(false, true, false);
+    else KQR_B3(false, false, false);
+  }
+#undef KQR_B3
+  KQR_LAUNCH_CHECK();
+  KQR_CHECK_HIP(hipFreeAsync(buf, st));
+  return true;
 }
 
 // ================================================================= one kernel row

@@ -121,6 +121,8 @@ static void kbuild_packed_p(const float* X, const float* q, int64_t n, int p, Ke
 void kbuild_packed(const float* X, const float* sqn, int64_t n, int p, KernelSpec ks, int dtype, void* K,
                    hipStream_t st) {
   if (n <= 0) return;
+  // RBF with p <= 32: the Gram term on the matrix cores, entries as in the full layout
+  if (kbuild_mfma(X, sqn, n, p, ks, dtype, K, packed_tiles_per_side(n), 1, st)) return;
   if (p <= 8) kbuild_packed_p<8>(X, sqn, n, p, ks, dtype, K, st);
   else if (p <= 16) kbuild_packed_p<16>(X, sqn, n, p, ks, dtype, K, st);
   else if (p <= 32) kbuild_packed_p<32>(X, sqn, n, p, ks, dtype, K, st);

@@ -92,6 +92,11 @@ bool apply_shape_supported(const ApplyShape& s);
 // K build: K[i, j] for i < n, j < ldk (j >= n written as 0).
 void kbuild(const float* X, const float* sqn, int64_t n, int p, KernelSpec ks, int dtype, void* K,
             int64_t ldk, hipStream_t st);
+// K build with the Gram term on the matrix cores (RBF, p <= 32; layout 0:
+// n x ldk rows, ldk a multiple of 16; layout 1: upper-triangle tiles).
+// Returns false, doing nothing, for the cases it does not cover.
+bool kbuild_mfma(const float* X, const float* q, int64_t n, int p, KernelSpec ks, int dtype, void* K, int64_t ldk,
+                 int layout, hipStream_t st);
 // Squared row norms of X (FP32).
 void row_sqnorms(const float* X, int64_t n, int p, float* sqn, hipStream_t st);
 
@@ -123,6 +128,31 @@ void kapply_otf(const float* Xr, const float* sqr, int64_t nr, const float* Xc, 
 int quantize_columns(const float* X, int64_t n, int p, uint32_t* Xq, hipStream_t st);
 size_t otf_sym_scratch_doubles(int64_t n);  // partial sums of a symmetric on-the-fly apply (0: too large)
 void set_otf_sym_budget(int64_t bytes);     // largest such buffer; beyond it the row-streamed forms run
+// Launch shape of the on-the-fly applies: strip = tiles per workgroup of the
+// symmetric square applies (0: by size), wgs = workgroups a sliced
+// rectangular launch aims for (0: 8192).
+void set_otf_shape(int strip, int64_t wgs);
+void set_otf_strip_for(int64_t n, int strip);  // the strip for n's size class only (0: by size)
+int otf_strip_for(int64_t n);                  // the strip the symmetric applies use at n
+int64_t otf_wgs();
+void set_otf_wgs(int64_t wgs);  // 0: 8192
+
+// Launch-shape registry: every shape installed by an autotuner or a
+// kqr_set_* call, as the entries of the tuning file (kqr_tune_save /
+// kqr_tune_load; tune.hip).  kind: "apply", "kv", "packed", "otf".
+struct TuneEntry {
+  std::string kind;
+  int k_dtype = 0, mode = 0;
+  int64_t n = 0;       // problem size the shape was chosen at (selects the size class)
+  int m = 1;           // right-hand sides of the timed launch
+  int a = 0, b = 0, c = 0;  // apply: rows, unroll, segs; kv: nld, prefetch, segs; packed: map, strip; otf: strip, -, -
+  int64_t wgs = 0;     // otf: target workgroups of sliced launches
+  double us = 0.0;     // measured launch time (0: installed by hand)
+};
+void tune_record(const TuneEntry& e);
+int tune_save(const char* path);  // entries written
+int tune_load(const char* path);  // entries installed (0 when the file was tuned on another architecture)
+void tune_autoload();  // once per process: the file named by KQR_TUNE_FILE, if set
 void kapply_otf_l1q(const uint32_t* Xq, int64_t n, int p, double gamma, int shift, const double* v, double* u,
                     int64_t ldu, bool exact, hipStream_t st, double* scratch = nullptr, size_t scratch_doubles = 0);
 // y = A x for a skinny FP32 matrix A (nrows x ncols, ncols <= 1024, lda a

@@ -88,6 +88,9 @@ struct Kkt {
   double obj_p = 0, obj_d = 0, sum_alpha = 0;
 };
 
+// Section 4 residuals and objectives from the nine sums of multiplier_kkt.
+Kkt kkt_from_sums(const double* s, double ynorm, double lam);
+
 // Left-preconditioned conjugate gradients on (K + c 1 1^T + diag(L)) x = b.
 class Pcg {
  public:
@@ -116,6 +119,7 @@ class Solver {
   void finish(kqr_info& info);
   const double* alpha() const { return alpha_.as<double>(); }
   const double* z() const { return z_.as<double>(); }  // ALM multipliers
+  const double* v() const { return v_.as<double>(); }  // consensus copy of alpha (1.4)
   double beta() const { return beta_; }
   bool converged() const { return converged_; }
   Workspace& ws() { return ws_; }

@@ -264,19 +264,24 @@ void Solver::record(int phase, int it, double err) {
   ++ntrace_;
 }
 
-Kkt Solver::kkt_from_sums(const double* s) const {
+// Section 4 stopping measures from the sums of multiplier_kkt (FP64):
+// s = [||r_p||^2, ||alpha - v||^2, ||alpha||^2, ||v - Pi_B(z + v)||^2, ||v||^2,
+//      rho_tau(z), alpha^T K alpha, y^T alpha, 1^T alpha].
+Kkt kkt_from_sums(const double* s, double ynorm, double lam) {
   Kkt k;
-  k.eta_p = std::sqrt(std::max(s[0], 0.0)) / (1.0 + ynorm_);
+  k.eta_p = std::sqrt(std::max(s[0], 0.0)) / (1.0 + ynorm);
   k.eta_d = std::sqrt(s[8] * s[8] + std::max(s[1], 0.0)) / (1.0 + std::sqrt(std::max(s[2], 0.0)));
   k.eta_c = std::sqrt(std::max(s[3], 0.0)) / (1.0 + std::sqrt(std::max(s[4], 0.0)));
-  k.obj_p = s[5] + s[6] / (2.0 * lam_);
-  k.obj_d = -s[6] / (2.0 * lam_) + s[7];
+  k.obj_p = s[5] + s[6] / (2.0 * lam);
+  k.obj_d = -s[6] / (2.0 * lam) + s[7];
   k.eta_gap = std::fabs(k.obj_p - k.obj_d) / (1.0 + std::fabs(k.obj_p) + std::fabs(k.obj_d));
   k.eta_kkt = std::max(k.eta_p, std::max(k.eta_d, k.eta_c));
   k.err = std::max(k.eta_kkt, k.eta_gap);
   k.sum_alpha = s[8];
   return k;
 }
+
+Kkt Solver::kkt_from_sums(const double* s) const { return ::kqr::kkt_from_sums(s, ynorm_, lam_); }
 
 double Solver::sum_of(const double* x) {
   double t3[3];

@@ -46,6 +46,7 @@ class KqrOptions(C.Structure):
         ("pivot_uniforms", C.POINTER(C.c_double)), ("seed", C.c_uint64), ("verbose", C.c_int),
         ("profile", C.c_int), ("exact_k", C.c_int), ("ssn_adapt", C.c_double),
         ("trace", C.POINTER(C.c_double)), ("trace_cap", C.c_int), ("k_layout", C.c_int),
+        ("z_out", C.c_void_p), ("v_out", C.c_void_p),
     ]
 
 
@@ -91,6 +92,8 @@ _SIGS = {
                                 C.c_double, _P, _P, C.c_double, C.c_int, _P, _P, _P, _P]),
     "kqr_ssn_gradient": (C.c_int, [_I64, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double,
                                    C.c_double, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
+    "kqr_kkt_residuals": (C.c_int, [_I64, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double, C.c_int,
+                                    _P, _P, _P, _P, _P, _P, _P]),
     "kqr_fit": (C.c_int, [_P, _P, _I64, _I64, C.c_double, C.c_double, C.c_int, C.c_double,
                           C.POINTER(KqrOptions), _P, _P, C.POINTER(KqrInfo), _P]),
     "kqr_fit_multi_tau": (C.c_int, [_P, _P, _I64, _I64, _P, C.c_int, C.c_double, C.c_int, C.c_double,
@@ -103,6 +106,10 @@ _SIGS = {
     "kqr_autotune_packed": (C.c_int, [_P, C.c_int, _I64, C.c_int, C.c_int, C.c_char_p, _I64, _P]),
     "kqr_set_packed_shape": (C.c_int, [C.c_int, C.c_int, C.c_int, C.c_int]),
     "kqr_set_otf_symmetric_limit": (C.c_int, [C.c_int64]),
+    "kqr_set_otf_shape": (C.c_int, [C.c_int, C.c_int64]),
+    "kqr_autotune_otf": (C.c_int, [_P, _I64, _I64, C.c_int, C.c_double, C.c_int, C.c_int, C.c_char_p, _I64, _P]),
+    "kqr_tune_save": (C.c_int, [C.c_char_p, C.POINTER(C.c_int)]),
+    "kqr_tune_load": (C.c_int, [C.c_char_p, C.POINTER(C.c_int)]),
     "kqr_fit_batch": (C.c_int, [C.c_int, _P, _P, _P, _I64, _P, _P, C.c_int, _P, C.POINTER(KqrOptions), _P, _P, _P,
                                 _P, _P]),
     "kqr_fit_grad": (C.c_int, [_P, _P, _I64, _I64, C.c_double, C.c_double, C.c_int, C.c_double, _P, _P, _I64,
@@ -273,6 +280,12 @@ def kqr_set_otf_symmetric_limit(nbytes):
     _check(lib().kqr_set_otf_symmetric_limit(int(nbytes)), "kqr_set_otf_symmetric_limit")
 
 
+def kqr_set_otf_shape(strip=0, wgs=0):
+    """Launch shape of the on-the-fly applies (strip: tiles per workgroup of the symmetric
+    square applies, 0 = by size; wgs: target workgroups of sliced launches, 0 = 8192)."""
+    _check(lib().kqr_set_otf_shape(int(strip), int(wgs)), "kqr_set_otf_shape")
+
+
 def kqr_kernel_apply(V, X=None, kernel="rbf", gamma=1.0, K=None, mode=KQR_APPLY_FAST, U=None, stream=None):
     """U = K V for V (n,) or (n, m) float64 on the GPU; K materialised or None (on the fly)."""
     torch = _torch()
@@ -356,6 +369,31 @@ def kqr_autotune_apply(K, mode=KQR_APPLY_FAST, reps=5, stream=None):
     return json.loads(buf.value.decode())
 
 
+def kqr_autotune_otf(X, kernel, gamma, mode=KQR_APPLY_FAST, reps=3, stream=None):
+    """Sweep the on-the-fly apply's strip (square, symmetric form) and slice target (rectangle) on X;
+    installs the fastest; returns the JSON report (dict)."""
+    torch = _torch()
+    n, p = X.shape
+    buf = C.create_string_buffer(1 << 14)
+    _check(lib().kqr_autotune_otf(_dev(X, torch.float32, "X", 2), n, p, _kernel_id(kernel), float(gamma), int(mode),
+                                  int(reps), buf, len(buf), _stream(stream)), "kqr_autotune_otf")
+    return json.loads(buf.value.decode())
+
+
+def kqr_tune_save(path) -> int:
+    """Write every launch shape installed in this process to a JSON file keyed by the GPU architecture."""
+    c = C.c_int(0)
+    _check(lib().kqr_tune_save(os.fsencode(path), C.byref(c)), "kqr_tune_save")
+    return int(c.value)
+
+
+def kqr_tune_load(path) -> int:
+    """Install the launch shapes a file records for this GPU's architecture; returns how many."""
+    c = C.c_int(0)
+    _check(lib().kqr_tune_load(os.fsencode(path), C.byref(c)), "kqr_tune_load")
+    return int(c.value)
+
+
 def kqr_set_apply_shape(k_dtype, mode, n, rows, unroll, segs):
     _check(lib().kqr_set_apply_shape(_kdtype_id(k_dtype), int(mode), int(n), int(rows), int(unroll), int(segs)),
            "kqr_set_apply_shape")
@@ -415,17 +453,38 @@ def kqr_ssn_gradient(tau, lam, beta, sigma, alpha, Kalpha, y, z, tau1=0.1, tau2=
     return dict(grad=grad, S=S, Ldiag=L, rhs=rhs, gnorm=float(gn.value), eps_t=float(et.value))
 
 
+def kqr_kkt_residuals(tau, lam, beta, alpha, Kalpha, y, z, v, sigma=1.0, step=1.0, update=False, stream=None):
+    """Section 4 measures at (alpha, v, beta, z) with the supplied K alpha (update: the multiplier
+    step first, z and v overwritten).  Returns a dict of eta_p, eta_d, eta_c, eta_kkt, eta_gap, obj_p, obj_d."""
+    torch = _torch()
+    n = alpha.shape[0]
+    out = (C.c_double * 7)()
+    f64 = torch.float64
+    _check(lib().kqr_kkt_residuals(n, float(tau), float(lam), float(beta), float(sigma), float(step), int(bool(update)),
+                                   _dev(alpha, f64, "alpha", 1), _dev(Kalpha, f64, "Kalpha", 1), _dev(y, f64, "y", 1),
+                                   _dev(z, f64, "z", 1), _dev(v, f64, "v", 1), out, _stream(stream)),
+           "kqr_kkt_residuals")
+    keys = ("eta_p", "eta_d", "eta_c", "eta_kkt", "eta_gap", "obj_p", "obj_d")
+    return {k: float(out[i]) for i, k in enumerate(keys)}
+
+
 def kqr_fit(X, y, tau, lam, kernel="rbf", gamma=1.0, options: KqrOptions | None = None, uniforms=None,
-            stream=None, trace: int = 0, **overrides):
+            stream=None, trace: int = 0, out_vz: bool = False, **overrides):
     """PALM-KQR fit on the GPU.  Returns (alpha (GPU float64), beta, info dict, status).
 
     ``trace`` > 0 records up to that many outer iterations; info["trace"] is
-    then an array of rows (phase, iteration, max(eta_kkt, eta_gap), seconds)."""
+    then an array of rows (phase, iteration, max(eta_kkt, eta_gap), seconds).
+    ``out_vz``: info["v"], info["z"] hold the final v and z (GPU float64), the
+    iterate the Section 4 measures in info were taken at."""
     torch = _torch()
     n, p = X.shape
     o = options if options is not None else kqr_default_options()
     for k, v in overrides.items():
         setattr(o, k, v)
+    vz = None
+    if out_vz:
+        vz = torch.empty((2, n), dtype=torch.float64, device=X.device)
+        o.v_out, o.z_out = vz[0].data_ptr(), vz[1].data_ptr()
     keep = None
     if uniforms is not None:
         keep = np.ascontiguousarray(np.asarray(uniforms, dtype=np.float64))
@@ -447,6 +506,9 @@ def kqr_fit(X, y, tau, lam, kernel="rbf", gamma=1.0, options: KqrOptions | None 
     if tbuf is not None:
         out["trace"] = tbuf[: info.trace_len].copy()
         o.trace, o.trace_cap = None, 0
+    if vz is not None:
+        out["v"], out["z"] = vz[0], vz[1]
+        o.v_out, o.z_out = None, None
     return alpha, float(beta.value), out, st
 
 

@@ -50,9 +50,10 @@ def test_struct_layouts_match_c():
 #include <stddef.h>
 #include "kqr.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu\n", sizeof(kqr_options), sizeof(kqr_info),
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(kqr_options), sizeof(kqr_info),
          offsetof(kqr_options, pivot_uniforms), offsetof(kqr_options, verbose),
-         offsetof(kqr_info, kapply_calls), offsetof(kqr_info, t_total));
+         offsetof(kqr_info, kapply_calls), offsetof(kqr_info, t_total),
+         offsetof(kqr_options, z_out), offsetof(kqr_options, v_out));
   return 0;
 }
 '''
@@ -65,7 +66,8 @@ int main(void) {
     got = [int(v) for v in out]
     exp = [C.sizeof(kqr.KqrOptions), C.sizeof(kqr.KqrInfo),
            kqr.KqrOptions.pivot_uniforms.offset, kqr.KqrOptions.verbose.offset,
-           kqr.KqrInfo.kapply_calls.offset, kqr.KqrInfo.t_total.offset]
+           kqr.KqrInfo.kapply_calls.offset, kqr.KqrInfo.t_total.offset,
+           kqr.KqrOptions.z_out.offset, kqr.KqrOptions.v_out.offset]
     assert got == exp
 
 
@@ -117,6 +119,21 @@ def test_invalid_arguments_are_rejected_before_device_work():
                               piv.ctypes.data_as(C.c_void_p), C.byref(r), None) == kqr.KQR_EINVAL
     # woodbury: rank too large
     assert lib.kqr_woodbury_apply(P, 10, 1024, 1024, 1.0, P, P, P, None) == kqr.KQR_EINVAL
+    # kkt residuals: null output, tau outside (0, 1), update without sigma
+    out = (C.c_double * 7)()
+    assert lib.kqr_kkt_residuals(10, 0.5, 1.0, 0.0, 1.0, 1.0, 0, P, P, P, P, P, None, None) == kqr.KQR_EINVAL
+    assert lib.kqr_kkt_residuals(10, 1.5, 1.0, 0.0, 1.0, 1.0, 0, P, P, P, P, P, out, None) == kqr.KQR_EINVAL
+    assert lib.kqr_kkt_residuals(10, 0.5, 1.0, 0.0, 0.0, 1.0, 1, P, P, P, P, P, out, None) == kqr.KQR_EINVAL
+    # on-the-fly launch shape: strip and workgroup target ranges (host-only; valid calls succeed)
+    assert lib.kqr_set_otf_shape(33, 0) == kqr.KQR_EINVAL
+    assert lib.kqr_set_otf_shape(4, 100) == kqr.KQR_EINVAL
+    assert lib.kqr_set_otf_shape(8, 4096) == kqr.KQR_OK
+    assert lib.kqr_set_otf_shape(0, 0) == kqr.KQR_OK
+    # tuning file and on-the-fly autotuner: null arguments, bad kernel
+    cnt = C.c_int()
+    assert lib.kqr_tune_save(None, C.byref(cnt)) == kqr.KQR_EINVAL
+    assert lib.kqr_tune_load(b"/nonexistent.json", None) == kqr.KQR_EINVAL
+    assert lib.kqr_autotune_otf(P, 100, 3, kqr.KQR_LINEAR, 1.0, 0, 1, None, 0, None) == kqr.KQR_EINVAL
 
 
 @pytest.mark.skipif(kqr.kqr_device_count() > 0, reason="a device is present")

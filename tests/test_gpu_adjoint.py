@@ -161,7 +161,7 @@ def test_adjoint_full_size_against_kink_free_differences(dev):
     _, s0, E0 = probe(gamma, prob.lam)
     checked = 0
     for which, g_an in (("gamma", dg), ("lambda", dl)):
-        for h in (1e-4, 3e-5, 1e-5):
+        for h in (1e-4, 3e-5, 1e-5, 3e-6, 1e-6):
             vals, kink = [], False
             for sgn in (1, -1):
                 gg = gamma * math.exp(sgn * h) if which == "gamma" else gamma
@@ -177,3 +177,4 @@ def test_adjoint_full_size_against_kink_free_differences(dev):
                 checked += 1
                 break
     say(f"  kink-free checks: {checked} of 2")
+    assert checked == 2  # each derivative compared with central differences on a kink-free interval

@@ -113,15 +113,18 @@ def test_every_packed_shape_and_autotuner(dev, kd):
     Kp = kqr.kqr_kernel_build_packed(torch.from_numpy(X).to(dev), "rbf", 0.125, kd)
     v = torch.from_numpy(np.random.default_rng(9).standard_normal(n)).to(dev)
     say("packed shapes", kd)
-    ref = kqr.kqr_kernel_apply_packed(v, Kp, n, kqr.KQR_APPLY_EXACT).cpu().numpy()
-    scale = np.abs(v.cpu().numpy()).sum()
+    vn = v.cpu().numpy()
+    K, bound = _bound(X, 0.125, kd, vn)  # the oracle's FP64 K and the storage bound
+    dense = unpack(Kp.float().cpu().numpy().astype(np.float64), n)
+    stored, stored_scale = dense @ vn, np.abs(dense) @ np.abs(vn)
     for mode in (kqr.KQR_APPLY_FAST, kqr.KQR_APPLY_EXACT):
         for mp in (0, 1, 2, 3):
             for strip in (1, 2, 3, 4, 8, 16, 32):
                 kqr.kqr_set_packed_shape(kd, mode, mp, strip)
                 u = kqr.kqr_kernel_apply_packed(v, Kp, n, mode).cpu().numpy()
-                tol = (1e-13 if mode == kqr.KQR_APPLY_EXACT else 300 * U32) * scale
-                assert np.abs(u - ref).max() <= tol, (mode, mp, strip)
+                assert np.all(np.abs(u - K @ vn) <= bound), (mode, mp, strip)
+                if mode == kqr.KQR_APPLY_EXACT:  # FP64 on the stored entries
+                    assert np.all(np.abs(u - stored) <= 4 * n * 2.0 ** -53 * stored_scale), (mp, strip)
         rep = kqr.kqr_autotune_packed(Kp, n, mode, reps=2)
         assert len(rep["shapes"]) == 20 and rep["best"]["map"] in (0, 1, 2, 3) and 1 <= rep["best"]["strip"] <= 16
     with pytest.raises(kqr.KqrError):

@@ -309,6 +309,32 @@ def oracle_fit(prob, **kw):
     return _ORACLE[key]
 
 
+def alpha_tolerance(Kref, Kb, ref, lam, tau, y, level):
+    """How far the GPU's alpha may lie from the FP64 optimum alpha*, to first
+    order, relative to 1 + ||alpha*||.
+
+    The GPU solves the problem with FP32 kernel entries, each within Kb of
+    the FP64 one, to a KKT level `level`.  On a stable partition (L, E, R) of
+    the optimum, alpha_N sits on its bounds and (alpha_E, beta) solve the
+    bordered system G [alpha_E; beta] = [y_E - K_EN alpha_N / lambda;
+    -1^T alpha_N] with G = [K_EE / lambda, 1; 1^T, 0] (the KKT conditions of
+    (1.3)), so both the entry error and the residual the solver leaves move
+    alpha_E by at most ||G^-1|| times their size on E: ||(Kb |alpha*|)_E|| /
+    lambda for the entries, level (1 + ||y||) for the residual."""
+    a = ref.alpha
+    E = np.flatnonzero((a > tau - 1 + 1e-9) & (a < tau - 1e-9))
+    if E.size == 0:
+        return 0.0  # alpha* is fixed by the partition
+    m = E.size
+    G = np.zeros((m + 1, m + 1))
+    G[:m, :m] = Kref[np.ix_(E, E)] / lam
+    G[:m, m] = 1.0
+    G[m, :m] = 1.0
+    ginv = np.linalg.norm(np.linalg.inv(G), 2)
+    r = np.linalg.norm(Kb[E] @ np.abs(a)) / lam + level * (1.0 + np.linalg.norm(y))
+    return ginv * r / (1.0 + np.linalg.norm(a))
+
+
 def certificate(prob, alpha, beta):
     """FP64 residuals of a returned (alpha, beta) with exact K: z = y - beta - K alpha/lambda, v = Pi_B(alpha)."""
     K = okernel.kernel_matrix(prob.X, prob.kernel, prob.gamma)
@@ -325,7 +351,7 @@ def test_fit_matches_oracle(dev, name, n, rank):
     X = torch.from_numpy(prob.X).to(dev)
     y = torch.from_numpy(prob.y).to(dev)
     alpha, beta, info, st = kqr.kqr_fit(X, y, prob.tau, prob.lam, prob.kernel, prob.gamma, rank=rank,
-                                        uniforms=inputs.pivot_uniforms(max(rank, 64), (n, 5)))
+                                        uniforms=inputs.pivot_uniforms(max(rank, 64), (n, 5)), out_vz=True)
     a = alpha.cpu().numpy()
     say("  gpu info", {k: info[k] for k in ("eta_kkt", "eta_gap", "admm_iters", "alm_iters", "newton_iters",
                                             "pcg_iters", "kapply_calls", "rank_used", "t_total")})
@@ -336,13 +362,25 @@ def test_fit_matches_oracle(dev, name, n, rank):
     cert = certificate(prob, a, beta)
     rel_obj = abs(cert["obj_p"] - opt) / (1 + abs(opt))
     alpha_err = np.linalg.norm(a - ref.alpha) / (1 + np.linalg.norm(ref.alpha))
-    say(f"  rel_obj={rel_obj:.2e} alpha_err={alpha_err:.2e} cert_kkt={cert['eta_kkt']:.2e} "
-        f"cert_gap={cert['eta_gap']:.2e} beta={beta:.6f} beta*={ref.beta:.6f}")
+    # the Section 4 measures at the returned iterate (alpha, v, beta, z) with
+    # the FP64 kernel: the fit's target, up to the FP32 entry error of K alpha
+    Kref, Kb = entry_bound(prob.X, prob.kernel, prob.gamma)
+    a_tol = alpha_tolerance(Kref, Kb, ref, prob.lam, prob.tau, prob.y, max(info["eta_kkt"], info["eta_gap"]))
+    Ka = Kref @ a
+    m64 = oproblem.kkt(a, info["v"].cpu().numpy(), beta, info["z"].cpu().numpy(), Ka, prob.y, prob.lam, prob.tau)
+    dKa = Kb @ np.abs(a)
+    shift_p = np.linalg.norm(dKa) / prob.lam / (1 + np.linalg.norm(prob.y))
+    shift_gap = (np.abs(a) @ dKa / prob.lam) / (1 + abs(m64["obj_p"]) + abs(m64["obj_d"]))
+    say(f"  rel_obj={rel_obj:.2e} alpha_err={alpha_err:.2e} (first-order bound {a_tol:.2e}) "
+        f"FP64 eta_kkt={m64['eta_kkt']:.2e} eta_gap={m64['eta_gap']:.2e} beta={beta:.6f} beta*={ref.beta:.6f}")
     assert rel_obj <= 1e-6
-    # independent FP64 certificate of the returned point: dual feasibility and
-    # complementarity of (alpha, beta) with exact K, and the gap it closes
-    assert cert["eta_d"] <= 2e-6 and cert["eta_c"] <= 1e-5
-    assert abs(a.sum()) <= 1e-5 * (1 + np.abs(a).sum())
+    # alpha* is unique (K positive definite): within the first-order bound of
+    # the FP32 entry error and the solver's residual (factor 2 for second
+    # order), or the 1e-6 bar, whichever is larger
+    assert alpha_err <= max(1e-6, 2 * a_tol)
+    assert m64["eta_p"] <= 1e-6 + shift_p
+    assert m64["eta_d"] <= 1e-6 and m64["eta_c"] <= 1e-6
+    assert m64["eta_gap"] <= 1e-6 + shift_gap
 
 
 def test_fit_is_deterministic(dev):

@@ -312,6 +312,73 @@ def test_quantile_count_and_duality_sandwich():
         assert pb.primal_objective(zz, a, K @ a, lam, tau) >= opt - 1e-9
 
 
+def test_kkt_residuals_hand_computed():
+    # A non-optimal iterate with every Section 4 quantity evaluated by hand
+    # (n = 3, tau = 1/4 so B = [-3/4, 1/4], lambda = 2; K alpha is an input).
+    alpha = np.array([0.3, -0.5, 0.1])
+    v = np.array([0.2, -0.4, 0.25])
+    z = np.array([1.0, -2.0, 0.5])
+    Ka = np.array([0.25, -0.35, 0.6])
+    y = np.array([2.0, 0.5, -1.0])
+    r = pb.kkt(alpha, v, 0.1, z, Ka, y, 2.0, 0.25)
+    # eta_p: z - y + beta + K alpha / lambda = (-0.775, -2.575, 1.9), squares
+    # 0.600625 + 6.630625 + 3.61 = 10.84125; ||y||^2 = 4 + 0.25 + 1 = 5.25
+    assert r["eta_p"] == pytest.approx(math.sqrt(10.84125) / (1.0 + math.sqrt(5.25)), rel=1e-14)
+    # eta_d: 1^T alpha = -0.1; ||alpha - v||^2 = 0.01 + 0.01 + 0.0225 = 0.0425;
+    # ||alpha||^2 = 0.09 + 0.25 + 0.01 = 0.35
+    assert r["eta_d"] == pytest.approx(math.sqrt(0.01 + 0.0425) / (1.0 + math.sqrt(0.35)), rel=1e-14)
+    # eta_c: z + v = (1.2, -2.4, 0.75) projects to (0.25, -0.75, 0.25); v minus
+    # that = (-0.05, 0.35, 0), squares 0.125; ||v||^2 = 0.04 + 0.16 + 0.0625
+    assert r["eta_c"] == pytest.approx(math.sqrt(0.125) / (1.0 + math.sqrt(0.2625)), rel=1e-14)
+    # objectives: rho_tau(z) = 0.25*1 + 0.75*2 + 0.25*0.5 = 1.875;
+    # alpha^T K alpha = 0.075 + 0.175 + 0.06 = 0.31; y^T alpha = 0.6 - 0.25 - 0.1 = 0.25
+    assert r["obj_p"] == pytest.approx(1.875 + 0.31 / 4.0, rel=1e-15)   # 1.9525
+    assert r["obj_d"] == pytest.approx(-0.31 / 4.0 + 0.25, rel=1e-15)   # 0.1725
+    # both objectives positive, so 1 + |P| + |D| (3.125) differs from 1 + |P - D|
+    assert r["eta_gap"] == pytest.approx(1.78 / 3.125, rel=1e-14)
+    assert r["eta_kkt"] == max(r["eta_p"], r["eta_d"], r["eta_c"]) == r["eta_p"]
+    assert r["err"] == r["eta_kkt"]
+
+
+@pytest.mark.parametrize("kind", ["rbf", "laplacian"])
+def test_c_kernel_apply_equals_numpy_direct_differences(kind):
+    # the C library's FP64 products against the NumPy blocks (same definition,
+    # other summation order): within a few n u of the sum of magnitudes
+    from oracle import certify
+    X, _ = inputs.additive(700, 7, (51, 0))
+    Xr, _ = inputs.additive(123, 7, (51, 1))
+    V = np.random.default_rng(5).standard_normal((700, 3))
+    for rows in (None, Xr):
+        got = certify.kernel_apply(X, V, kind, 0.2, Xrows=rows)
+        ref = kn.kernel_apply(X, V, kind, 0.2, Xrows=rows)
+        mag = np.abs(kn.kernel_apply(X, np.abs(V), kind, 0.2, Xrows=rows))
+        assert np.all(np.abs(got - ref) <= 4 * 700 * 2.0 ** -53 * mag)
+    assert np.array_equal(certify.kernel_apply(X, V[:, 0], kind, 0.2), certify.kernel_apply(X, V, kind, 0.2)[:, 0])
+
+
+def test_certificate_sandwich_brackets_the_optimum():
+    # brute force fixes the optimum (n = 8); the certificate's bounds must
+    # bracket it, be tight at the optimum and bound the error of other points
+    from oracle import certify
+    X, y, K = _tiny(8, 2, 31)
+    lam, tau = 0.7, 0.3
+    a_bf, b_lo, b_hi = pins.brute_force(K, y, lam, tau)
+    b_bf = 0.5 * (b_lo + b_hi)
+    Ka = K @ a_bf
+    opt = pb.primal_objective(y - b_bf - Ka / lam, a_bf, Ka, lam, tau)
+    c = certify.certificate(X, y, tau, lam, "rbf", 0.5, a_bf, b_bf)
+    assert c["lower"] <= opt + 1e-12 and opt <= c["upper"] + 1e-12
+    assert c["rel_obj_err_bound"] <= 1e-12 and c["eta_kkt"] <= 1e-12
+    rng = np.random.default_rng(3)
+    for _ in range(5):
+        a = np.clip(a_bf + 0.05 * rng.standard_normal(8), tau - 1, tau)
+        b = b_bf + 0.1 * rng.standard_normal()
+        c = certify.certificate(X, y, tau, lam, "rbf", 0.5, a, b)
+        assert c["lower"] <= opt + 1e-12 <= c["upper"] + 2e-12
+        true_rel = (c["obj_p_returned"] - opt) / (1 + abs(c["lower"]))
+        assert -1e-12 <= true_rel <= c["rel_obj_err_bound"] + 1e-12
+
+
 def test_alm_update_identities():
     # After (beta, z) update: eta_c == 0 and ||grad phi|| = (1 + ||y||) eta_p.
     prob = inputs.workload("c0", n=300)
