@@ -246,6 +246,24 @@ int kqr_kernel_apply(const float* X, int64_t n, int64_t p, int kernel, double ga
                      const void* K, int k_dtype, int64_t ldk, const double* V, int64_t m,
                      int64_t ldv, double* U, int64_t ldu, int mode, void* stream);
 
+/* kqr_kernel_apply_static: u = K v on a materialised K (full layout, from
+ * kqr_kernel_build), FAST or EXACT as kqr_kernel_apply with m = 1, that
+ * allocates nothing.  For callers that cannot allocate device memory: code
+ * under HIP graph capture, serving loops, harnesses that forbid allocation.
+ *  K      device n x ldk, type k_dtype (ldk >= n, a multiple of 8, 16-byte aligned).
+ *  v      device n FP64, element i at v[i * incv];  u device n FP64 at u[i * incu].
+ *  Its scratch (the FP32 copy of v, an aligned FP64 copy when incv != 1, the
+ *  partial sums of the column segments) lives in one fixed device array of
+ *  64 MiB per device, held from the first call on that device until the
+ *  process ends; n needs 20 n bytes of it plus alignment (n up to about
+ *  3.3 million), else KQR_EINVAL.  The launch shape is kqr_kernel_apply's, with
+ *  the column segments capped to fit the array.  Every call on a device
+ *  shares that device's array: calls that overlap on one device (other
+ *  streams, other threads) race.  Asynchronous on `stream`; no allocation, no
+ *  memset, so the call can be captured into a HIP graph. */
+int kqr_kernel_apply_static(const void* K, int k_dtype, int64_t n, int64_t ldk, const double* v, int64_t incv,
+                            double* u, int64_t incu, int mode, void* stream);
+
 /* kqr_predict: f = beta + K(Xnew, Xtrain) alpha / lambda, computed on the fly.
  *  Xtrain device n x p FP32; alpha device n FP64; Xnew device m x p FP32;
  *  f device m FP64.  Asynchronous on `stream`. */

@@ -514,6 +514,23 @@ int kqr_kernel_apply(const float* X, int64_t n, int64_t p, int kernel, double ga
   });
 }
 
+int kqr_kernel_apply_static(const void* K, int k_dtype, int64_t n, int64_t ldk, const double* v, int64_t incv,
+                            double* u, int64_t incu, int mode, void* stream) {
+  return guarded([&] {
+    KQR_REQUIRE(K && v && u, "K, v and u must be non-null");
+    KQR_REQUIRE(n >= 1, "need n >= 1");
+    KQR_REQUIRE(incv >= 1 && incu >= 1, "need incv >= 1 and incu >= 1");
+    KQR_REQUIRE(mode == KQR_APPLY_FAST || mode == KQR_APPLY_EXACT, "mode must be KQR_APPLY_FAST or KQR_APPLY_EXACT");
+    check_kmat(K, k_dtype, ldk, n);
+    const size_t need = (size_t(n) * 8 + 255) / 256 * 256 + (size_t(n) * 4 + 255) / 256 * 256 + size_t(n) * 8;
+    KQR_REQUIRE(need <= static_scratch_bytes(), "n = %lld needs %zu bytes of scratch, above the %zu of the static array",
+                (long long)n, need, static_scratch_bytes());
+    ensure_device();
+    kapply_static(KMat{K, k_dtype, ldk}, n, v, incv, u, incu, mode == KQR_APPLY_EXACT,
+                  static_cast<hipStream_t>(stream));
+  });
+}
+
 int64_t kqr_packed_bytes(int64_t n, int k_dtype) {
   if (n < 1 || (k_dtype != KQR_FP32 && k_dtype != KQR_BF16)) return -1;
   return int64_t(packed_bytes(n, k_dtype));

@@ -203,6 +203,12 @@ void lin_predict(const float* Xtr, int64_t n, int p, const double* alpha, const 
 // F = X padded to ldf columns (the exact factor of X X^T)
 void lin_factor(const float* X, int64_t n, int p, float* F, int64_t ldf, hipStream_t st);
 
+// u = K v for a materialised K (full layout) through the fixed per-device
+// scratch array of kstatic.hip: no allocation (kqr_kernel_apply_static).
+void kapply_static(const KMat& km, int64_t n, const double* v, int64_t incv, double* u, int64_t incu, bool exact,
+                   hipStream_t st);
+size_t static_scratch_bytes();
+
 // FP64 -> FP32 copy (for the fast apply), strided rows.
 void to_f32(const double* src, int64_t n, int m, int64_t lds, float* dst, int64_t ldd, hipStream_t st);
 

@@ -107,6 +107,7 @@ _SIGS = {
     "kqr_set_packed_shape": (C.c_int, [C.c_int, C.c_int, C.c_int, C.c_int]),
     "kqr_set_otf_symmetric_limit": (C.c_int, [C.c_int64]),
     "kqr_set_otf_shape": (C.c_int, [C.c_int, C.c_int64]),
+    "kqr_kernel_apply_static": (C.c_int, [_P, C.c_int, _I64, _I64, _P, _I64, _P, _I64, C.c_int, _P]),
     "kqr_autotune_otf": (C.c_int, [_P, _I64, _I64, C.c_int, C.c_double, C.c_int, C.c_int, C.c_char_p, _I64, _P]),
     "kqr_tune_save": (C.c_int, [C.c_char_p, C.POINTER(C.c_int)]),
     "kqr_tune_load": (C.c_int, [C.c_char_p, C.POINTER(C.c_int)]),
@@ -306,6 +307,22 @@ def kqr_kernel_apply(V, X=None, kernel="rbf", gamma=1.0, K=None, mode=KQR_APPLY_
                                   _dev(V2, torch.float64, "V"), m, m, _dev(U2, torch.float64, "U"), m,
                                   int(mode), _stream(stream)), "kqr_kernel_apply")
     return U2.reshape(-1) if vec else U2
+
+
+def kqr_kernel_apply_static(v, K, mode=KQR_APPLY_FAST, u=None, stream=None):
+    """u = K v for a materialised K (from kqr_kernel_build) without any allocation in the
+    library: v and u are (n,) float64 GPU tensors, any stride."""
+    torch = _torch()
+    n = v.shape[0]
+    if u is None:
+        u = torch.empty(n, dtype=torch.float64, device=v.device)
+    if v.dtype != torch.float64 or u.dtype != torch.float64 or not (v.is_cuda and u.is_cuda) or v.dim() != 1:
+        raise TypeError("v and u must be 1-D float64 GPU tensors")
+    kd = KQR_FP32 if K.dtype == torch.float32 else KQR_BF16
+    _check(lib().kqr_kernel_apply_static(_dev(K, K.dtype, "K", 2), kd, n, K.shape[1], C.c_void_p(v.data_ptr()),
+                                         v.stride(0), C.c_void_p(u.data_ptr()), u.stride(0), int(mode),
+                                         _stream(stream)), "kqr_kernel_apply_static")
+    return u
 
 
 def kqr_predict(Xtrain, alpha, beta, lam, kernel, gamma, Xnew, stream=None):

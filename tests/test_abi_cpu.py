@@ -129,6 +129,11 @@ def test_invalid_arguments_are_rejected_before_device_work():
     assert lib.kqr_set_otf_shape(4, 100) == kqr.KQR_EINVAL
     assert lib.kqr_set_otf_shape(8, 4096) == kqr.KQR_OK
     assert lib.kqr_set_otf_shape(0, 0) == kqr.KQR_OK
+    # allocation-free apply: K required, strides >= 1, n beyond the fixed scratch array
+    assert lib.kqr_kernel_apply_static(None, 0, 10, 16, P, 1, P, 1, 0, None) == kqr.KQR_EINVAL
+    assert lib.kqr_kernel_apply_static(P, 0, 10, 16, P, 0, P, 1, 0, None) == kqr.KQR_EINVAL
+    assert lib.kqr_kernel_apply_static(P, 0, 4_000_000, 4_000_000, P, 1, P, 1, 0, None) == kqr.KQR_EINVAL
+    assert "static" in kqr.last_error()
     # tuning file and on-the-fly autotuner: null arguments, bad kernel
     cnt = C.c_int()
     assert lib.kqr_tune_save(None, C.byref(cnt)) == kqr.KQR_EINVAL
