@@ -979,9 +979,11 @@ __global__ __launch_bounds__(256) void kapply_otf_mfma_kernel(
       const float qj = qs[jj];
 #pragma unroll
       for (int rr = 0; rr < 4; ++rr) {
-        const float d0 = fmaxf(qi[0][rr] + qj - 2.f * g0[rr], 0.f);
-        const float d1 = fmaxf(qi[1][rr] + qj - 2.f * g1[rr], 0.f);
-        const float e0 = kexp2(ng * d0), e1 = kexp2(ng * d1);
+        // ng < 0, d >= 0: exp2(ng max(d, 0)) = min(exp2(ng d), 1), clamped by the output modifier
+        const float d0 = qi[0][rr] + qj - 2.f * g0[rr];
+        const float d1 = qi[1][rr] + qj - 2.f * g1[rr];
+        const float e0 = __builtin_amdgcn_fmed3f(kexp2(ng * d0), 0.f, 1.f);
+        const float e1 = __builtin_amdgcn_fmed3f(kexp2(ng * d1), 0.f, 1.f);
         if (EX) {
           acc[0][rr] = fma(double(e0), vd[jj], acc[0][rr]);
           acc[1][rr] = fma(double(e1), vd[jj], acc[1][rr]);
@@ -1190,9 +1192,10 @@ __global__ __launch_bounds__(256) void kapply_otf_mfma3_kernel(
       for (int s = 0; s < 2; ++s)
 #pragma unroll
         for (int rr = 0; rr < 4; ++rr) {
-          // ng < 0: min(ng d, 0) = ng max(d, 0)
+          // ng < 0 and d >= 0: exp2(min(ng d, 0)) = min(exp2(ng d), 1), the clamp
+          // to [0, 1] being the exponential's output modifier
           const float a = AUG ? g[s][rr] : ng * (qi[s][rr] + qj + g[s][rr]);
-          const float e = kexp2(fminf(a, 0.f));
+          const float e = __builtin_amdgcn_fmed3f(kexp2(a), 0.f, 1.f);
           if (EX) acc[s][rr] = fma(double(e), vd[jj], acc[s][rr]);
           else a32[s][rr] = fmaf(e, vs[jj], a32[s][rr]);
         }
@@ -1335,9 +1338,10 @@ __global__ __launch_bounds__(256) void kapply_otf_mfma3_sym_kernel(
       for (int s = 0; s < 2; ++s)
 #pragma unroll
         for (int rr = 0; rr < 4; ++rr) {
-          // ng < 0: min(ng d, 0) = ng max(d, 0)
+          // ng < 0 and d >= 0: exp2(min(ng d, 0)) = min(exp2(ng d), 1), the clamp
+          // to [0, 1] being the exponential's output modifier
           const float a = AUG ? g[s][rr] : ng * (qi[s][rr] + qj + g[s][rr]);
-          const float e = kexp2(fminf(a, 0.f));
+          const float e = __builtin_amdgcn_fmed3f(kexp2(a), 0.f, 1.f);
           if (EX) {
             acc[s][rr] = fma(double(e), vj, acc[s][rr]);
             cs64 = fma(double(e), vi[s][rr], cs64);
@@ -1470,8 +1474,8 @@ __global__ __launch_bounds__(256) void kapply_otf_mfma_sym_kernel(
 #pragma unroll
         for (int rr = 0; rr < 4; ++rr) {
           const float gg = s == 0 ? g0[rr] : g1[rr];
-          const float d = fmaxf(qi[s][rr] + qj - 2.f * gg, 0.f);
-          const float e = kexp2(ng * d);
+          // ng < 0, d >= 0: exp2(ng max(d, 0)) = min(exp2(ng d), 1), clamped by the output modifier
+          const float e = __builtin_amdgcn_fmed3f(kexp2(ng * (qi[s][rr] + qj - 2.f * gg)), 0.f, 1.f);
           if (EX) {
             acc[s][rr] = fma(double(e), vj, acc[s][rr]);
             cs64 = fma(double(e), vi[s][rr], cs64);
@@ -1644,26 +1648,40 @@ void kapply_otf(const float* Xr, const float* sqr, int64_t nr, const float* Xc, 
 // split once per build into buffers of 96 halves per point (row side
 // [x, 1, q], column side [-2 c x, c q, c]; without the fold [x] and [-2 x]).
 //
-// Operand roles are chosen for the stores: the A operand carries 16 columns
-// j of K and the B operand 16 rows i, so the lane that receives
-// C[4 g + r][l] holds K[i0 + l][j0 + 4 g + r], r = 0..3: four consecutive
-// entries of one row, written by one 16-byte (FP32) or 8-byte (BF16) store.
-// A workgroup is four waves of 32 rows each (two 16-row strips as B operands
-// held in registers); every 16-column step loads the column parts once per
-// wave (from L2: 192 bytes per column) and serves both strips.
+// Operand roles: the A operand carries 16 columns j of K and the B operand
+// 16 rows i, so the lane that receives C[4 g + r][l] holds K[i0 + l][j0 +
+// 4 g + r], r = 0..3.  A workgroup is four waves of 32 rows each (two 16-row
+// strips as B operands held in registers); a step covers 64 columns (four
+// 16-column blocks, whose column parts each wave loads once from L2, 192
+// bytes per column, and uses for both strips).  The step's 32 x 64 entries of
+// a wave go through its own LDS slab and leave as whole rows: 16-byte stores,
+// 256 contiguous bytes per row (FP32) or 128 (BF16), so every store writes
+// full 128-byte lines (the MFMA layout alone would give 64- or 32-byte pieces
+// per row and instruction).
 //   full layout  : 128 rows x `cols` columns of the n x ldk matrix per workgroup
-//                  (columns n..ldk-1 written as 0, rows >= n not written);
+//                  (columns n..ldk-1 written as 0, rows >= n not written;
+//                  ldk and `cols` multiples of 64);
 //   packed layout: one 128 x 128 upper-triangle tile per workgroup (entries
 //                  beyond n written as 0, as the tile layout requires).
 // K_ii is set to exactly 1 (d_ii := 0).
 typedef uint32_t u32x2_t __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+
+constexpr int kBuildStep = 64;               // columns per step
+constexpr int kBuildSlab = kBuildStep + 4;   // LDS row of a wave's slab (floats), padded against bank conflicts
 
 template <bool AUG, bool BF, bool PACKED>
 __global__ __launch_bounds__(256) void kbuild_b3_kernel(const uint16_t* __restrict__ Pr, const uint16_t* __restrict__ Sc,
                                                         const float* __restrict__ q, int64_t n, float ng,
                                                         void* __restrict__ Kout, int64_t ldk, int64_t nt,
                                                         int64_t cols) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  // a wave's slab: 32 rows x 64 entries, FP32 or (BF16 storage) the rounded BF16 values
+  __shared__ __align__(16) float slab[4][32][kBuildSlab];
+  typedef uint16_t bslab_row[2 * kBuildSlab];
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform: block tests branch on scalars
   const int li = lane & 15, lg = lane >> 4;
   int64_t rbase, cbeg, cend;
   size_t tile_base = 0;
@@ -1685,72 +1703,125 @@ __global__ __launch_bounds__(256) void kbuild_b3_kernel(const uint16_t* __restri
     cbeg = int64_t(blockIdx.y) * cols;
     cend = min(ldk, cbeg + cols);
   }
-  // B operands: rows rbase + 32 wave + 16 s + li, coordinates 8 lg .. 8 lg + 7
+  const int64_t wrow = rbase + 32 * wave;  // this wave's first row
+  // B operands: rows wrow + 16 s + li, coordinates 8 lg .. 8 lg + 7
   bf16x8_t bh[2], bm[2], bl[2];
   float qi[2];
-  int64_t irow[2];
 #pragma unroll
   for (int s = 0; s < 2; ++s) {
-    const int64_t i = rbase + 32 * wave + 16 * s + li;
-    irow[s] = i;
-    const int64_t ic = min(i, n - 1);  // rows past n: any valid point (their entries are not kept)
+    const int64_t ic = min(wrow + 16 * s + li, n - 1);  // rows past n: any valid point (entries not kept)
     bh[s] = *reinterpret_cast<const bf16x8_t*>(Pr + ic * kB3Stride + 8 * lg);
     bm[s] = *reinterpret_cast<const bf16x8_t*>(Pr + ic * kB3Stride + 32 + 8 * lg);
     bl[s] = *reinterpret_cast<const bf16x8_t*>(Pr + ic * kB3Stride + 64 + 8 * lg);
     qi[s] = AUG ? 0.f : q[ic];
   }
-  for (int64_t jb = cbeg; jb < cend; jb += 16) {
-    const int64_t jc = min(jb + li, n - 1);  // columns past n: any valid point (written as 0)
-    const bf16x8_t ah = *reinterpret_cast<const bf16x8_t*>(Sc + jc * kB3Stride + 8 * lg);
-    const bf16x8_t am = *reinterpret_cast<const bf16x8_t*>(Sc + jc * kB3Stride + 32 + 8 * lg);
-    const bf16x8_t al = *reinterpret_cast<const bf16x8_t*>(Sc + jc * kB3Stride + 64 + 8 * lg);
-    const int64_t j0 = jb + 4 * lg;  // this lane's four columns j0 .. j0 + 3
-    float qj[4] = {0.f, 0.f, 0.f, 0.f};
-    if (!AUG) {
+  float (*sl)[kBuildSlab] = slab[wave];
+  bslab_row* bsl = reinterpret_cast<bslab_row*>(slab[wave]);  // BF16 view: rows of 2 kBuildSlab halves
+  for (int64_t jb = cbeg; jb < cend; jb += kBuildStep) {
+    // the column parts of the whole step are requested at once: one L2 round
+    // trip per step instead of one per 16-column block
+    bf16x8_t ahs[kBuildStep / 16], ams[kBuildStep / 16], als[kBuildStep / 16];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) qj[r] = q[min(j0 + r, n - 1)];
+    for (int blk = 0; blk < kBuildStep / 16; ++blk) {
+      const int64_t jc = min(jb + 16 * blk + li, n - 1);  // columns past n: any valid point (written as 0)
+      ahs[blk] = *reinterpret_cast<const bf16x8_t*>(Sc + jc * kB3Stride + 8 * lg);
+      ams[blk] = *reinterpret_cast<const bf16x8_t*>(Sc + jc * kB3Stride + 32 + 8 * lg);
+      als[blk] = *reinterpret_cast<const bf16x8_t*>(Sc + jc * kB3Stride + 64 + 8 * lg);
     }
+    // Gram blocks: the two strips' product chains interleaved, and the next
+    // block's MFMAs issued before this block's exponentials
+    auto gram = [&](int blk, f32x4_t* c) {
+      const bf16x8_t ah = ahs[blk], am = ams[blk], al = als[blk];
+      c[0] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+      c[1] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+      // smallest products first
+      c[0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bm[0], c[0], 0, 0, 0);
+      c[1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bm[1], c[1], 0, 0, 0);
+      c[0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[0], c[0], 0, 0, 0);
+      c[1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[1], c[1], 0, 0, 0);
+      c[0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[0], c[0], 0, 0, 0);
+      c[1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[1], c[1], 0, 0, 0);
+      c[0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bh[0], c[0], 0, 0, 0);
+      c[1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bh[1], c[1], 0, 0, 0);
+      c[0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bm[0], c[0], 0, 0, 0);
+      c[1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bm[1], c[1], 0, 0, 0);
+      c[0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[0], c[0], 0, 0, 0);
+      c[1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[1], c[1], 0, 0, 0);
+    };
+    f32x4_t cur[2], nxt[2];
+    gram(0, cur);
 #pragma unroll
-    for (int s = 0; s < 2; ++s) {
-      f32x4_t c = f32x4_t{0.f, 0.f, 0.f, 0.f};  // smallest products first
-      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bm[s], c, 0, 0, 0);
-      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[s], c, 0, 0, 0);
-      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[s], c, 0, 0, 0);
-      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bh[s], c, 0, 0, 0);
-      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bm[s], c, 0, 0, 0);
-      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[s], c, 0, 0, 0);
-      const int64_t i = irow[s];
-      float e[4];
+    for (int blk = 0; blk < kBuildStep / 16; ++blk) {
+      if (blk + 1 < kBuildStep / 16) gram(blk + 1, nxt);
+      const int64_t j0 = jb + 16 * blk + 4 * lg;  // this lane's four columns j0 .. j0 + 3
+      float qj[4] = {0.f, 0.f, 0.f, 0.f};
+      if (!AUG) {
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int64_t j = j0 + r;
-        // ng < 0: min(ng d, 0) = ng max(d, 0)
-        const float a = AUG ? c[r] : ng * (qi[s] + qj[r] + c[r]);
-        const float ev = i == j ? 1.f : kexp2(fminf(a, 0.f));
-        e[r] = (j < n && i < n) ? ev : 0.f;
+        for (int r = 0; r < 4; ++r) qj[r] = q[min(j0 + r, n - 1)];
       }
-      if (PACKED) {
-        const size_t off = tile_base + size_t(i - rbase) * kPkT + size_t(j0 - cbeg);
-        if (BF) {
-          const uint32_t w0 = uint32_t(f32_to_bf16(e[0])) | (uint32_t(f32_to_bf16(e[1])) << 16);
-          const uint32_t w1 = uint32_t(f32_to_bf16(e[2])) | (uint32_t(f32_to_bf16(e[3])) << 16);
-          __builtin_nontemporal_store(u32x2_t{w0, w1}, reinterpret_cast<u32x2_t*>(static_cast<uint16_t*>(Kout) + off));
-        } else {
-          __builtin_nontemporal_store(f32x4_t{e[0], e[1], e[2], e[3]},
-                                      reinterpret_cast<f32x4_t*>(static_cast<float*>(Kout) + off));
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        const f32x4_t c = cur[s];
+        const int64_t iblk = wrow + 16 * s, jblk = jb + 16 * blk;
+        f32x4_t e;
+        // ng < 0 and d >= 0, so the entry is exp2(min(ng d, 0)) = min(exp2(ng d), 1): the
+        // clamp to [0, 1] rides on the exponential as its output modifier
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          e[r] = __builtin_amdgcn_fmed3f(kexp2(AUG ? c[r] : ng * (qi[s] + qj[r] + c[r])), 0.f, 1.f);
+        if (iblk == jblk || iblk + 16 > n || jblk + 16 > n) {  // (uniform) diagonal or ragged block
+          const int64_t i = iblk + li;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int64_t j = j0 + r;
+            e[r] = (j < n && i < n) ? (i == j ? 1.f : e[r]) : 0.f;
+          }
         }
-      } else if (i < n) {
-        const size_t off = size_t(i) * size_t(ldk) + size_t(j0);
-        if (BF) {
-          const uint32_t w0 = uint32_t(f32_to_bf16(e[0])) | (uint32_t(f32_to_bf16(e[1])) << 16);
-          const uint32_t w1 = uint32_t(f32_to_bf16(e[2])) | (uint32_t(f32_to_bf16(e[3])) << 16);
-          __builtin_nontemporal_store(u32x2_t{w0, w1}, reinterpret_cast<u32x2_t*>(static_cast<uint16_t*>(Kout) + off));
+        if (BF) {  // round to BF16 here: half the LDS traffic
+          u32x2_t w;
+          w[0] = __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2_t{e[0], e[1]}, bf16x2_t));
+          w[1] = __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2_t{e[2], e[3]}, bf16x2_t));
+          *reinterpret_cast<u32x2_t*>(&bsl[16 * s + li][16 * blk + 4 * lg]) = w;
         } else {
-          __builtin_nontemporal_store(f32x4_t{e[0], e[1], e[2], e[3]},
-                                      reinterpret_cast<f32x4_t*>(static_cast<float*>(Kout) + off));
+          *reinterpret_cast<f32x4_t*>(&sl[16 * s + li][16 * blk + 4 * lg]) = e;
+        }
+      }
+      cur[0] = nxt[0];
+      cur[1] = nxt[1];
+    }
+    __syncthreads();  // the slab is complete (each wave reads only its own)
+    if (BF) {
+      // a row is 64 BF16 = 128 bytes = 8 lanes x 16 bytes; eight rows per store
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int rr = 8 * k + (lane >> 3), cc = 8 * (lane & 7);
+        const u32x4_t w = *reinterpret_cast<const u32x4_t*>(&bsl[rr][cc]);
+        const int64_t i = wrow + rr;
+        if (PACKED) {
+          const size_t off = tile_base + size_t(i - rbase) * kPkT + size_t(jb - cbeg + cc);
+          __builtin_nontemporal_store(w, reinterpret_cast<u32x4_t*>(static_cast<uint16_t*>(Kout) + off));
+        } else if (i < n) {
+          const size_t off = size_t(i) * size_t(ldk) + size_t(jb + cc);
+          __builtin_nontemporal_store(w, reinterpret_cast<u32x4_t*>(static_cast<uint16_t*>(Kout) + off));
+        }
+      }
+    } else {
+      // a row is 64 FP32 = 256 bytes = 16 lanes x 16 bytes; four rows per store
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const int rr = 4 * k + (lane >> 4), cc = 4 * (lane & 15);
+        const f32x4_t x = *reinterpret_cast<const f32x4_t*>(&sl[rr][cc]);
+        const int64_t i = wrow + rr;
+        if (PACKED) {
+          const size_t off = tile_base + size_t(i - rbase) * kPkT + size_t(jb - cbeg + cc);
+          __builtin_nontemporal_store(x, reinterpret_cast<f32x4_t*>(static_cast<float*>(Kout) + off));
+        } else if (i < n) {
+          const size_t off = size_t(i) * size_t(ldk) + size_t(jb + cc);
+          __builtin_nontemporal_store(x, reinterpret_cast<f32x4_t*>(static_cast<float*>(Kout) + off));
         }
       }
     }
+    __syncthreads();  // the slab is free for the next step
   }
 }
 
@@ -1760,7 +1831,7 @@ constexpr int64_t kBuildCols = 1024;
 bool kbuild_mfma(const float* X, const float* q, int64_t n, int p, KernelSpec ks, int dtype, void* K, int64_t ldk,
                  int layout, hipStream_t st) {
   if (ks.kind != KQR_RBF || p > 32 || n <= 0) return false;
-  if (layout == 0 && ldk % 16 != 0) return false;  // the stores cover 16-column steps up to ldk
+  if (layout == 0 && ldk % kBuildStep != 0) return false;  // the stores cover 64-column steps up to ldk
   const bool aug = p <= 30, bf = dtype == KQR_BF16;
   const float ng = -float(ks.gamma) * kLog2e;
   uint16_t* buf = nullptr;
