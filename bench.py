@@ -777,7 +777,7 @@ def bench_batch(args):
     out["roofline"] = {
         "bound": "hbm", "achieved": round(streamed / max(tl, 1e-12) / 1e9, 1) if tl > 0 else None, "peak": HBM_PEAK_GBS,
         "unit": "GB/s", "frac": round(streamed / max(tl, 1e-12) / 1e9 / HBM_PEAK_GBS, 4) if tl > 0 else None,
-        "traffic": None, "kernel": "kapply_problems_kernel (one launch over (problem, row block) pairs)",
+        "traffic": None, "kernel": "kapply_problems_queue_kernel (persistent launch; workgroups take (problem, 32-row block) items from a queue)",
         "launches": int(nl), "avg_launch_us": round(tl / max(nl, 1) * 1e6, 2),
         "note": "achieved = bytes of every problem's K over all its applies / device time of the batched launches; "
                 "K matrices of up to 256 MB sit partly in the 256 MB last-level cache",

@@ -38,10 +38,25 @@ void DevBuf::alloc(size_t b) {
   bytes = b;
 }
 
+// hipFree waits for the whole device; inside a DeferFrees scope the frees
+// wait for the scope's end instead, so a batch of fits running side by side
+// does not drain the GPU whenever one of them releases a buffer.
+static thread_local std::vector<void*>* g_deferred = nullptr;
+
 void DevBuf::release() {
-  if (ptr) (void)hipFree(ptr);
+  if (ptr) {
+    if (g_deferred) g_deferred->push_back(ptr);
+    else (void)hipFree(ptr);
+  }
   ptr = nullptr;
   bytes = 0;
+}
+
+DeferFrees::DeferFrees() : prev_(g_deferred) { g_deferred = &list_; }
+
+DeferFrees::~DeferFrees() {
+  g_deferred = prev_;
+  for (void* p : list_) (void)hipFree(p);
 }
 
 HostPinned::HostPinned(size_t b) {
@@ -694,8 +709,9 @@ int kqr_rpcholesky(const float* X, int64_t n, int64_t p, int kernel, double gamm
     DevBuf sqn(size_t(n) * sizeof(float));
     if (X) row_sqnorms(X, n, int(p), sqn.as<float>(), st);
     KQR_CHECK_HIP(hipMemsetAsync(F, 0, size_t(n) * ldf * sizeof(float), st));
-    std::vector<int64_t> piv = rpcholesky(KMat{K, k_dtype, ldk}, X, sqn.as<float>(), n, int(p), KernelSpec{kernel, gamma},
-                                          rank, uniforms, F, ldf, st);
+    Exec ex(st);
+    std::vector<int64_t> piv = run_sync(rpcholesky(KMat{K, k_dtype, ldk}, X, sqn.as<float>(), n, int(p),
+                                                   KernelSpec{kernel, gamma}, rank, uniforms, F, ldf, ex));
     for (size_t i = 0; i < piv.size(); ++i) pivots[i] = piv[i];
     *rank_out = int64_t(piv.size());
   });
@@ -711,7 +727,8 @@ int kqr_adaptive_rank(const float* F0, int64_t n, int64_t r0, int64_t ldf, doubl
     ensure_device();
     hipStream_t st = static_cast<hipStream_t>(stream);
     double l1 = 0.0;
-    *rank = r0 <= 1 ? r0 : adaptive_rank(F0, n, r0, ldf, xi, st, &l1);
+    Exec ex(st);
+    *rank = r0 <= 1 ? r0 : run_sync(adaptive_rank(F0, n, r0, ldf, xi, ex, &l1));
     if (lambda1) *lambda1 = l1;
   });
 }
@@ -827,8 +844,9 @@ int kqr_woodbury_apply(const float* F, int64_t n, int64_t r, int64_t ldf, double
     ensure_device();
     hipStream_t st = static_cast<hipStream_t>(stream);
     Workspace ws;
+    Exec ex(st);
     Woodbury P(F, n, r, ldf);
-    if (!P.build(Ldiag, c, st)) fail(KQR_ENUMERIC, "Woodbury core is not positive definite");
+    if (!run_sync(P.build(Ldiag, c, ex))) fail(KQR_ENUMERIC, "Woodbury core is not positive definite");
     P.apply(w, out, nullptr, nullptr, ws, st);
     KQR_CHECK_HIP(hipStreamSynchronize(st));
   });
@@ -849,14 +867,15 @@ int kqr_pcg_solve(const float* X, int64_t n, int64_t p, int kernel, double gamma
     hipStream_t st = static_cast<hipStream_t>(stream);
     Operator op(X, n, int(p), KernelSpec{kernel, gamma}, KMat{K, k_dtype, ldk}, st);
     Workspace ws;
-    Pcg pcg(op, ws, n);
+    Exec ex(st);
+    Pcg pcg(op, ws, n, ex);
     std::unique_ptr<Woodbury> P;
     if (r > 0) {
       P.reset(new Woodbury(F, n, r, ldf));
-      if (!P->build(Ldiag, c, st)) fail(KQR_ENUMERIC, "Woodbury core is not positive definite");
+      if (!run_sync(P->build(Ldiag, c, ex))) fail(KQR_ENUMERIC, "Woodbury core is not positive definite");
     }
-    PcgStats s = pcg.solve(c, Ldiag, P.get(), b, x, nullptr, false, tol, maxit, K != nullptr && k_dtype == KQR_FP32,
-                           st);
+    PcgStats s = run_sync(
+        pcg.solve(c, Ldiag, P.get(), b, x, nullptr, false, tol, maxit, K != nullptr && k_dtype == KQR_FP32));
     KQR_CHECK_HIP(hipStreamSynchronize(st));
     *iters = s.iters;
     *resnorm = s.resnorm;
@@ -938,11 +957,12 @@ int kqr_fit(const float* X, const double* y, int64_t n, int64_t p, double tau, d
     ensure_device();
     hipStream_t st = static_cast<hipStream_t>(stream);
     const KernelSpec ks{kernel, gamma};
-    Prepared pr = prepare_fit(X, n, int(p), ks, o, st);
+    Exec ex(st);
+    Prepared pr = run_sync(prepare_fit(X, n, int(p), ks, o, ex));
     Operator op(X, n, int(p), ks, pr.kmat(), st);
     pr.attach(op);
     op.enable_profile(o.profile != 0);
-    FitOutcome out = run_fit(op, pr, y, n, tau, lambda, o, alpha, st, o.z_out, o.v_out);
+    FitOutcome out = run_sync(run_fit(op, pr, y, n, tau, lambda, o, alpha, ex, o.z_out, o.v_out));
     *beta = out.beta;
     converged = out.converged;
     if (info) *info = out.info;
@@ -1041,11 +1061,12 @@ int kqr_fit_grad(const float* X, const double* y, int64_t n, int64_t p, double t
     double b = 0.0;
     kqr_info inf{};
     {
-      Prepared pr = prepare_fit(X, n, int(p), ks, o, st);
+      Exec ex(st);
+      Prepared pr = run_sync(prepare_fit(X, n, int(p), ks, o, ex));
       Operator op(X, n, int(p), ks, pr.kmat(), st);
       pr.attach(op);
       op.enable_profile(o.profile != 0);
-      FitOutcome out = run_fit(op, pr, y, n, tau, lambda, o, alpha, st, z.as<double>());
+      FitOutcome out = run_sync(run_fit(op, pr, y, n, tau, lambda, o, alpha, ex, z.as<double>()));
       b = out.beta;
       converged = out.converged;
       inf = out.info;

@@ -29,8 +29,9 @@ struct Prepared {
 };
 
 // Materialises K (per o.kmode / o.k_dtype) and builds F (fixed rank, the
-// Section 3 heuristic, or none).  `op` is created by the caller afterwards.
-Prepared prepare_fit(const float* X, int64_t n, int p, KernelSpec ks, const kqr_options& o, hipStream_t st);
+// Section 3 heuristic, or none) on ex's stream.  `op` is created by the
+// caller afterwards.
+Co<Prepared> prepare_fit(const float* X, int64_t n, int p, KernelSpec ks, kqr_options o, Exec& ex);
 
 struct FitOutcome {
   bool converged = false;
@@ -38,13 +39,16 @@ struct FitOutcome {
   kqr_info info{};
 };
 
-// Runs Phase I, Phase II and the final residuals; copies alpha to alpha_out
-// and, when z_out / v_out are given, the final multipliers z and the final
-// consensus vector v to them (device, n).
-FitOutcome run_fit(Operator& op, const Prepared& pr, const double* y, int64_t n, double tau, double lam,
-                   const kqr_options& o, double* alpha_out, hipStream_t st, double* z_out = nullptr,
-                   double* v_out = nullptr);
+// Runs Phase I, Phase II and the final residuals on ex's stream; copies
+// alpha to alpha_out and, when z_out / v_out are given, the final multipliers
+// z and the final consensus vector v to them (device, n).
+Co<FitOutcome> run_fit(Operator& op, const Prepared& pr, const double* y, int64_t n, double tau, double lam,
+                       kqr_options o, double* alpha_out, Exec& ex, double* z_out = nullptr,
+                       double* v_out = nullptr);
 
+// Batches run as coroutines on the calling thread (coro.h): one scheduler,
+// a few streams, and one batched launch per round of K-apply requests.
+//
 // tau batch: every level shares K and F; fast K-applies of all levels are
 // coalesced into one K V launch on the matrix cores.
 void fit_multi_tau(const float* X, const double* y, int64_t n, int p, KernelSpec ks, const double* taus, int ntau,

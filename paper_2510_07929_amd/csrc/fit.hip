@@ -1,17 +1,15 @@
 // Fit drivers.  One problem: materialise K, RPCholesky (+ the Section 3 rank
-// rule), Phase I, Phase II, final residuals.  Batches: one host thread and
-// one stream per problem, each running the same driver, with their fast
-// K-applies coalesced by a batcher into single launches.
+// rule), Phase I, Phase II, final residuals.  Batches: the same driver per
+// problem as a coroutine, all of them on the calling thread under one
+// scheduler, spread over a few streams, with their fast K-applies coalesced
+// into single launches.
 #include "fit.h"
 
 #include <algorithm>
-#include <atomic>
 #include <chrono>
 #include <cmath>
-#include <condition_variable>
 #include <cstring>
-#include <mutex>
-#include <thread>
+#include <memory>
 
 namespace kqr {
 
@@ -59,7 +57,8 @@ void validate_options(const kqr_options& o) {
   KQR_OPT_REQUIRE(o.k_layout == 0 || o.k_layout == 1, "k_layout must be 0 (full) or 1 (packed)");
 }
 
-Prepared prepare_fit(const float* X, int64_t n, int p, KernelSpec ks, const kqr_options& o, hipStream_t st) {
+Co<Prepared> prepare_fit(const float* X, int64_t n, int p, KernelSpec ks, kqr_options o, Exec& ex) {
+  const hipStream_t st = ex.st;
   Prepared pr;
   if (ks.kind == KQR_LINEAR) {
     // K = X X^T is applied in factored form and X is its exact factor: the
@@ -71,9 +70,9 @@ Prepared prepare_fit(const float* X, int64_t n, int p, KernelSpec ks, const kqr_
       pr.F.alloc(size_t(n) * pr.ldf * sizeof(float));
       lin_factor(X, n, p, pr.F.as<float>(), pr.ldf, st);
     }
-    KQR_CHECK_HIP(hipStreamSynchronize(st));
+    co_await fence(ex);
     pr.t_precond = wall_seconds() - t1;
-    return pr;
+    co_return pr;
   }
   const double t0 = wall_seconds();
   pr.dtype = o.k_dtype;
@@ -104,7 +103,7 @@ Prepared prepare_fit(const float* X, int64_t n, int p, KernelSpec ks, const kqr_
       kbuild(X, sqn.as<float>(), n, p, ks, KQR_FP32, pr.K32.ptr, pr.ldk, st);
     }
   }
-  KQR_CHECK_HIP(hipStreamSynchronize(st));
+  co_await fence(ex);
   pr.t_kbuild = wall_seconds() - t0;
   const double t1 = wall_seconds();
   int64_t rank = 0;
@@ -120,20 +119,22 @@ Prepared prepare_fit(const float* X, int64_t n, int p, KernelSpec ks, const kqr_
       u = default_uniforms(o.seed, rank);
       uni = u.data();
     }
-    std::vector<int64_t> piv = rpcholesky(pr.kmat(), X, sqn.as<float>(), n, p, ks, rank, uni, pr.F.as<float>(),
-                                          pr.ldf, st);
+    std::vector<int64_t> piv = co_await rpcholesky(pr.kmat(), X, sqn.as<float>(), n, p, ks, rank, uni,
+                                                   pr.F.as<float>(), pr.ldf, ex);
     pr.rank = int64_t(piv.size());
     // Section 3 rule: keep the first r columns (the first r steps of
     // RPCholesky are RPCholesky(K, r) on the same draws)
-    if (o.rank == 0 && pr.rank > 1) pr.rank = adaptive_rank(pr.F.as<float>(), n, pr.rank, pr.ldf, o.xi, st, nullptr);
+    if (o.rank == 0 && pr.rank > 1)
+      pr.rank = co_await adaptive_rank(pr.F.as<float>(), n, pr.rank, pr.ldf, o.xi, ex, nullptr);
   }
-  KQR_CHECK_HIP(hipStreamSynchronize(st));
+  co_await fence(ex);
   pr.t_precond = wall_seconds() - t1;
-  return pr;
+  co_return pr;
 }
 
-FitOutcome run_fit(Operator& op, const Prepared& pr, const double* y, int64_t n, double tau, double lam,
-                   const kqr_options& o, double* alpha_out, hipStream_t st, double* z_out, double* v_out) {
+Co<FitOutcome> run_fit(Operator& op, const Prepared& pr, const double* y, int64_t n, double tau, double lam,
+                       kqr_options o, double* alpha_out, Exec& ex, double* z_out, double* v_out) {
+  const hipStream_t st = ex.st;
   FitOutcome out;
   kqr_info& inf = out.info;
   memset(&inf, 0, sizeof(inf));
@@ -141,162 +142,45 @@ FitOutcome run_fit(Operator& op, const Prepared& pr, const double* y, int64_t n,
   inf.rank_used = int(pr.rank);
   inf.t_kbuild = pr.t_kbuild;
   inf.t_precond = pr.t_precond;
-  Solver solver(op, y, n, tau, lam, o, pr.F.as<float>(), pr.rank, pr.ldf, st);
-  solver.phase1(inf);
-  solver.phase2(inf);
-  solver.finish(inf);
+  Solver solver(op, ex, y, n, tau, lam, o, pr.F.as<float>(), pr.rank, pr.ldf);
+  co_await solver.init();
+  co_await solver.phase1(inf);
+  co_await solver.phase2(inf);
+  co_await solver.finish(inf);
   KQR_CHECK_HIP(hipMemcpyAsync(alpha_out, solver.alpha(), size_t(n) * sizeof(double), hipMemcpyDeviceToDevice, st));
   if (z_out)
     KQR_CHECK_HIP(hipMemcpyAsync(z_out, solver.z(), size_t(n) * sizeof(double), hipMemcpyDeviceToDevice, st));
   if (v_out)
     KQR_CHECK_HIP(hipMemcpyAsync(v_out, solver.v(), size_t(n) * sizeof(double), hipMemcpyDeviceToDevice, st));
-  KQR_CHECK_HIP(hipStreamSynchronize(st));
+  co_await fence(ex);
   out.beta = solver.beta();
   out.converged = solver.converged();
   inf.kapply_calls = op.calls();
   op.profile_totals(inf.kapply_fast_calls, inf.t_kapply_fast, inf.kapply_exact_calls, inf.t_kapply_exact);
   inf.t_total = pr.t_kbuild + pr.t_precond + (wall_seconds() - t0);
-  return out;
+  co_return out;
 }
 
-// ================================================================= batchers
-// Rendezvous: a batch goes out when every solver still running has a request
-// pending.  Requests are read after the requesting stream's event; every
-// requester's stream waits for the batch's completion event.
-class RendezvousBatcher : public ApplyBatcher {
- public:
-  RendezvousBatcher(int slots, bool profile) : active_(slots), req_(size_t(slots)), ready_(size_t(slots)),
-                                                profile_(profile) {
-    KQR_CHECK_HIP(hipStreamCreate(&bst_));
-    KQR_CHECK_HIP(hipEventCreateWithFlags(&done_, hipEventDisableTiming));
-    for (auto& e : ready_) KQR_CHECK_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-  }
-  ~RendezvousBatcher() override {
-    (void)hipStreamSynchronize(bst_);
-    for (auto& s : spans_) {
-      (void)hipEventDestroy(s.first);
-      (void)hipEventDestroy(s.second);
-    }
-    for (auto& e : ready_) (void)hipEventDestroy(e);
-    (void)hipEventDestroy(done_);
-    (void)hipStreamDestroy(bst_);
-  }
-  void submit(int slot, const double* v, double* out, hipStream_t st, bool exact) override {
-    std::unique_lock<std::mutex> lk(mu_);
-    KQR_CHECK_HIP(hipEventRecord(ready_[size_t(slot)], st));
-    req_[size_t(slot)] = Req{v, out, true, exact};
-    ++pending_;
-    const uint64_t my_gen = gen_;
-    if (pending_ == active_) {
-      fire();
-    } else {
-      cv_.wait(lk, [&] { return gen_ != my_gen || failed_; });
-    }
-    if (failed_) fail(KQR_EHIP, "batched K-apply failed");
-    KQR_CHECK_HIP(hipStreamWaitEvent(st, done_, 0));
-  }
-  void leave(int slot) override {
-    std::unique_lock<std::mutex> lk(mu_);
-    (void)slot;
-    --active_;
-    if (pending_ > 0 && pending_ == active_) {
-      try {
-        fire();
-      } catch (...) {
-        failed_ = true;
-        cv_.notify_all();
-      }
-    }
-  }
-  int64_t launches() const { return launches_; }
-  // summed device time of the batched launches (seconds)
-  double device_seconds() {
-    double t = 0.0;
-    for (auto& s : spans_) {
-      (void)hipEventSynchronize(s.second);
-      float ms = 0.f;
-      if (hipEventElapsedTime(&ms, s.first, s.second) == hipSuccess) t += 1e-3 * ms;
-    }
-    return t;
-  }
-
- protected:
-  struct Req {
-    const double* v;
-    double* out;
-    bool live;
-    bool exact;
-  };
-  virtual void launch(const std::vector<int>& slots, hipStream_t st) = 0;
-  std::vector<Req> req_;
-
- private:
-  void fire() {
-    std::vector<int> slots;
-    for (size_t s = 0; s < req_.size(); ++s)
-      if (req_[s].live) {
-        slots.push_back(int(s));
-        KQR_CHECK_HIP(hipStreamWaitEvent(bst_, ready_[s], 0));
-      }
-    hipEvent_t a = nullptr, b = nullptr;
-    if (profile_) {
-      KQR_CHECK_HIP(hipEventCreate(&a));
-      KQR_CHECK_HIP(hipEventCreate(&b));
-      KQR_CHECK_HIP(hipEventRecord(a, bst_));
-    }
-    try {
-      launch(slots, bst_);
-    } catch (...) {
-      failed_ = true;
-      cv_.notify_all();
-      throw;
-    }
-    if (profile_) {
-      KQR_CHECK_HIP(hipEventRecord(b, bst_));
-      spans_.emplace_back(a, b);
-    }
-    KQR_CHECK_HIP(hipEventRecord(done_, bst_));
-    for (int s : slots) req_[size_t(s)].live = false;
-    pending_ = 0;
-    ++launches_;
-    ++gen_;
-    cv_.notify_all();
-  }
-  std::mutex mu_;
-  std::condition_variable cv_;
-  int active_;
-  int pending_ = 0;
-  uint64_t gen_ = 0;
-  bool failed_ = false;
-  std::vector<hipEvent_t> ready_;
-  hipEvent_t done_ = nullptr;
-  hipStream_t bst_ = nullptr;
-  bool profile_;
-  int64_t launches_ = 0;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> spans_;
-};
-
+// ================================================================= batch launchers
 // Shared K: gather the requests into V (n x 16 FP32), one K V launch, scatter.
 // With an FP32 K, requests for the exact operator (up to kKvMaxExact per
 // launch) are served by the same pass over K in FP64.
-class KvBatcher : public RendezvousBatcher {
+class KvLauncher : public BatchLauncher {
  public:
-  KvBatcher(int slots, KMat km, int64_t n, bool profile)
-      : RendezvousBatcher(slots, profile), km_(km), n_(n), npad_(std::max<int64_t>(km.ld, n)),
-        V_(size_t(npad_) * 16 * sizeof(float)), U_(size_t(n) * 16 * sizeof(double)),
-        part_(kv_scratch_doubles(n) * sizeof(double)) {}
+  KvLauncher(KMat km, int64_t n)
+      : km_(km), n_(n), npad_(std::max<int64_t>(km.ld, n)), V_(size_t(npad_) * 16 * sizeof(float)),
+        U_(size_t(n) * 16 * sizeof(double)), part_(kv_scratch_doubles(n) * sizeof(double)) {}
   bool exact_ok() const override { return km_.dtype == KQR_FP32 && km_.layout == 0; }
-
- protected:
-  void launch(const std::vector<int>& slots, hipStream_t st) override {
+  void launch(const std::vector<int>& slots, const std::vector<ApplyReq>& reqs, hipStream_t st) override {
+    (void)slots;
+    if (reqs.size() > size_t(kKvMaxCols)) fail(KQR_EHIP, "internal: %zu requests for one K V launch", reqs.size());
     SrcTable16 src{}, xsrc{};
     DstTable16 dst{}, xdst{};
     int m = 0;
-    std::vector<int> ex;
-    for (int s : slots) {
-      const Req& r = req_[size_t(s)];
+    std::vector<const ApplyReq*> ex;
+    for (const ApplyReq& r : reqs) {
       if (r.exact) {
-        ex.push_back(s);
+        ex.push_back(&r);
       } else {
         src.p[m] = r.v;
         dst.p[m] = r.out;
@@ -313,8 +197,8 @@ class KvBatcher : public RendezvousBatcher {
       while (e < ex.size()) {
         const int mx = int(std::min<size_t>(kKvMaxExact, ex.size() - e));
         for (int j = 0; j < mx; ++j) {
-          xsrc.p[j] = req_[size_t(ex[e + size_t(j)])].v;
-          xdst.p[j] = req_[size_t(ex[e + size_t(j)])].out;
+          xsrc.p[j] = ex[e + size_t(j)]->v;
+          xdst.p[j] = ex[e + size_t(j)]->out;
         }
         kapply_kv_mixed(km_, n_, V_.as<float>(), first ? m : 0, U_.as<double>(), 16, xsrc, mx, xdst,
                         part_.as<double>(), st);
@@ -331,50 +215,45 @@ class KvBatcher : public RendezvousBatcher {
   DevBuf V_, U_, part_;
 };
 
-// Different K_i: one launch over (problem, row block) pairs.
-class ProblemBatcher : public RendezvousBatcher {
+// Different K_i: one launch over (problem, row block) pairs, dealt to the
+// workgroups from a queue (problems_launch).
+class ProblemLauncher : public BatchLauncher {
  public:
-  ProblemBatcher(int slots, std::vector<KMat> km, std::vector<int64_t> n, bool profile)
-      : RendezvousBatcher(slots, profile), km_(std::move(km)), n_(std::move(n)),
-        tasks_(size_t(km_.size()) * sizeof(ProblemTask)), first_(size_t(km_.size() + 1) * sizeof(int)) {}
-
- protected:
-  void launch(const std::vector<int>& slots, hipStream_t st) override {
+  ProblemLauncher(std::vector<KMat> km, std::vector<int64_t> n) : km_(std::move(km)), n_(std::move(n)),
+                                                                   q_(km_.size()) {}
+  void launch(const std::vector<int>& slots, const std::vector<ApplyReq>& reqs, hipStream_t st) override {
+    // largest problems first: their items (the longest rows) are taken
+    // first, so the launch does not end on a tail of long items
+    std::vector<size_t> order(slots.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](size_t a, size_t b) { return n_[size_t(slots[a])] > n_[size_t(slots[b])]; });
     std::vector<ProblemTask> tasks;
-    std::vector<int> first;
-    int total = 0;
-    // largest problems first: their workgroups (the longest rows) start
-    // early, so the launch does not end on a tail of long workgroups
-    std::vector<int> order(slots);
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return n_[size_t(a)] > n_[size_t(b)]; });
-    for (int s : order) {
-      const Req& r = req_[size_t(s)];
+    tasks.reserve(order.size());
+    for (size_t k : order) {
+      const int s = slots[k];
       ProblemTask t;
       t.K = km_[size_t(s)].K;
       t.ld = km_[size_t(s)].ld;
       t.n = n_[size_t(s)];
       t.dtype = km_[size_t(s)].dtype;
-      t.v = r.v;
-      t.u = r.out;
+      t.v = reqs[k].v;
+      t.u = reqs[k].out;
       tasks.push_back(t);
-      first.push_back(total);
-      total += problem_blocks(t.n);
     }
-    first.push_back(total);
-    KQR_CHECK_HIP(hipMemcpyAsync(tasks_.ptr, tasks.data(), tasks.size() * sizeof(ProblemTask), hipMemcpyHostToDevice, st));
-    KQR_CHECK_HIP(hipMemcpyAsync(first_.ptr, first.data(), first.size() * sizeof(int), hipMemcpyHostToDevice, st));
-    KQR_CHECK_HIP(hipStreamSynchronize(st));  // host vectors die at return
-    kapply_problems(tasks_.as<ProblemTask>(), int(tasks.size()), first_.as<int>(), total, st);
+    q_.launch(tasks, st);
   }
 
  private:
   std::vector<KMat> km_;
   std::vector<int64_t> n_;
-  DevBuf tasks_, first_;
+  ProblemQueue q_;
 };
 
 // ================================================================= drivers
 namespace {
+constexpr int kBatchStreams = 4;  // one per hardware queue HIP opens by default
+
 struct StreamSet {
   std::vector<hipStream_t> s;
   explicit StreamSet(int k) : s(size_t(k), nullptr) {
@@ -387,6 +266,8 @@ struct StreamSet {
         (void)hipStreamDestroy(x);
       }
   }
+  StreamSet(const StreamSet&) = delete;
+  StreamSet& operator=(const StreamSet&) = delete;
 };
 
 int status_of(const std::exception_ptr& e, std::string& msg) {
@@ -403,6 +284,51 @@ int status_of(const std::exception_ptr& e, std::string& msg) {
     return KQR_EHIP;
   }
 }
+
+// Result of one fit of a batch: its outcome or the exception that ended it.
+struct Slotted {
+  FitOutcome out;
+  std::exception_ptr err;
+};
+
+// Runs one fit inside a batch; failures stay with that fit.
+Co<Unit> guarded_fit(Operator& op, const Prepared& pr, const double* y, int64_t n, double tau, double lam,
+                     kqr_options o, double* alpha, Exec& ex, Slotted& res) {
+  try {
+    res.out = co_await run_fit(op, pr, y, n, tau, lam, o, alpha, ex);
+  } catch (...) {
+    res.err = std::current_exception();
+  }
+  co_return Unit{};
+}
+
+// Writes beta, info and status of every fit; returns the first failure.
+void collect(std::vector<Slotted>& res, Scheduler& sched, bool batched, double* beta, kqr_info* info, int* status,
+             hipStream_t st) {
+  const double tb = batched ? sched.device_seconds() : 0.0;
+  const int64_t nb = batched ? sched.launches() : 0;
+  std::string first_msg;
+  int first_err = KQR_OK;
+  for (size_t t = 0; t < res.size(); ++t) {
+    int stt = KQR_OK;
+    if (res[t].err) {
+      std::string msg;
+      stt = status_of(res[t].err, msg);
+      if (first_err == KQR_OK) { first_err = stt; first_msg = msg; }
+    } else {
+      stt = res[t].out.converged ? KQR_OK : KQR_NOT_CONVERGED;
+      beta[t] = res[t].out.beta;
+      if (batched) {  // fast applies were the shared batched launches (of every fit)
+        res[t].out.info.kapply_fast_calls = nb;
+        res[t].out.info.t_kapply_fast = tb;
+      }
+      if (info) info[t] = res[t].out.info;
+    }
+    status[t] = stt;
+  }
+  KQR_CHECK_HIP(hipStreamSynchronize(st));
+  if (first_err != KQR_OK) fail(first_err, "%s", first_msg.c_str());
+}
 }  // namespace
 
 void fit_levels(const float* X, const double* y, int64_t n, int p, KernelSpec ks, const double* taus,
@@ -412,58 +338,41 @@ void fit_levels(const float* X, const double* y, int64_t n, int p, KernelSpec ks
   o.trace = nullptr;  // one trace buffer cannot serve several concurrent fits
   o.trace_cap = 0;
   if (o.k_layout != 0) fail(KQR_EINVAL, "joint fits stream K in the full layout (k_layout = 0)");
-  Prepared pr = prepare_fit(X, n, p, ks, o, st);
+  Prepared pr;
+  {
+    Exec ex0(st);
+    pr = run_sync(prepare_fit(X, n, p, ks, o, ex0));
+  }
+  DeferFrees defer;  // the fits' buffers are released after the batch
   const int nw = std::min(nlev, kKvMaxCols);
   const bool batched = pr.K.ptr != nullptr && nw > 1;
-  std::unique_ptr<KvBatcher> batcher;
-  if (batched) batcher.reset(new KvBatcher(nw, pr.kmat(), n, o.profile != 0));
-  StreamSet streams(nw);
-  std::vector<std::exception_ptr> errs(static_cast<size_t>(nlev));
-  std::vector<FitOutcome> outs(static_cast<size_t>(nlev));
-  std::atomic<int> next{0};
-  std::vector<std::thread> th;
-  for (int w = 0; w < nw; ++w) {
-    th.emplace_back([&, w] {
-      hipStream_t s = streams.s[size_t(w)];
-      // a worker stays in the rendezvous until the queue of levels is empty
-      for (int t = next.fetch_add(1); t < nlev; t = next.fetch_add(1)) {
-        try {
-          Operator op(X, n, p, ks, pr.kmat(), s);
-          pr.attach(op);
-          op.enable_profile(o.profile != 0);
-          if (batcher) op.attach_batcher(batcher.get(), w);
-          outs[size_t(t)] = run_fit(op, pr, y, n, taus[t], lams[t], o, alpha + int64_t(t) * n, s);
-        } catch (...) {
-          errs[size_t(t)] = std::current_exception();
-        }
-      }
-      if (batcher) batcher->leave(w);
-    });
-  }
-  for (auto& x : th) x.join();
-  const double tkv = batcher ? batcher->device_seconds() : 0.0;
-  const int64_t nkv = batcher ? batcher->launches() : 0;
-  std::string first_msg;
-  int first_err = KQR_OK;
-  for (int t = 0; t < nlev; ++t) {
-    int stt = KQR_OK;
-    if (errs[size_t(t)]) {
-      std::string msg;
-      stt = status_of(errs[size_t(t)], msg);
-      if (first_err == KQR_OK) { first_err = stt; first_msg = msg; }
-    } else {
-      stt = outs[size_t(t)].converged ? KQR_OK : KQR_NOT_CONVERGED;
-      beta[t] = outs[size_t(t)].beta;
-      if (batcher) {  // fast applies were the shared K V launches (of every level)
-        outs[size_t(t)].info.kapply_fast_calls = nkv;
-        outs[size_t(t)].info.t_kapply_fast = tkv;
-      }
-      if (info) info[t] = outs[size_t(t)].info;
+  std::unique_ptr<KvLauncher> launcher;
+  if (batched) launcher.reset(new KvLauncher(pr.kmat(), n));
+  Scheduler sched(launcher.get(), o.profile != 0);
+  StreamSet streams(std::min(nw, kBatchStreams));
+  KQR_CHECK_HIP(hipStreamSynchronize(st));  // K and F are ready before other streams read them
+  std::vector<std::unique_ptr<Exec>> exs;
+  for (int w = 0; w < nw; ++w) exs.emplace_back(new Exec(streams.s[size_t(w) % streams.s.size()], &sched, w));
+  std::vector<Slotted> res(static_cast<size_t>(nlev));
+  int next = 0;
+  // worker w: takes the next level when it finishes one; the scheduler keeps
+  // it in the lock-step rounds until the queue of levels is empty
+  auto worker = [&](int w) -> Co<Unit> {
+    Exec& ex = *exs[size_t(w)];
+    for (int t = next++; t < nlev; t = next++) {
+      Operator op(X, n, p, ks, pr.kmat(), ex.st);
+      pr.attach(op);
+      op.enable_profile(o.profile != 0);
+      op.attach_batching(batched);
+      co_await guarded_fit(op, pr, y, n, taus[t], lams[t], o, alpha + int64_t(t) * n, ex, res[size_t(t)]);
     }
-    status[t] = stt;
-  }
-  KQR_CHECK_HIP(hipStreamSynchronize(st));
-  if (first_err != KQR_OK) fail(first_err, "%s", first_msg.c_str());
+    co_return Unit{};
+  };
+  std::vector<Co<Unit>> tasks;
+  for (int w = 0; w < nw; ++w) tasks.push_back(worker(w));
+  sched.run(tasks);
+  for (auto& t : tasks) t.result();  // the workers themselves do not fail
+  collect(res, sched, batched, beta, info, status, st);
 }
 
 void fit_multi_tau(const float* X, const double* y, int64_t n, int p, KernelSpec ks, const double* taus, int ntau,
@@ -487,63 +396,52 @@ void fit_batch(int nprob, const float* const* X, const double* const* y, const i
   o.trace = nullptr;  // one trace buffer cannot serve several concurrent fits
   o.trace_cap = 0;
   if (o.k_layout != 0) fail(KQR_EINVAL, "batched problems stream K in the full layout (k_layout = 0)");
-  std::vector<Prepared> prs;
-  prs.reserve(size_t(nprob));
+  StreamSet streams(std::min(nprob, kBatchStreams));
+  // caller's inputs are ready before other streams read them
+  KQR_CHECK_HIP(hipStreamSynchronize(st));
+  DeferFrees defer;  // buffers are released after the batch (hipFree drains the device)
+  // 1. every problem's K and preconditioner, interleaved over the streams
+  std::vector<Prepared> prs(static_cast<size_t>(nprob));
+  {
+    Scheduler prep(nullptr, false);
+    std::vector<std::unique_ptr<Exec>> exs;
+    for (int i = 0; i < nprob; ++i) exs.emplace_back(new Exec(streams.s[size_t(i) % streams.s.size()], &prep, i));
+    std::vector<Co<Prepared>> tasks;
+    for (int i = 0; i < nprob; ++i)
+      tasks.push_back(prepare_fit(X[i], n[i], p, KernelSpec{ks.kind, gamma[i]}, o, *exs[size_t(i)]));
+    prep.run(tasks);
+    for (int i = 0; i < nprob; ++i) prs[size_t(i)] = tasks[size_t(i)].result();
+  }
   std::vector<KMat> kms;
   std::vector<int64_t> ns;
-  for (int i = 0; i < nprob; ++i) {
-    const KernelSpec ksi{ks.kind, gamma[i]};
-    prs.push_back(prepare_fit(X[i], n[i], p, ksi, o, st));
-    kms.push_back(prs.back().kmat());
-    ns.push_back(n[i]);
-  }
   bool all_mat = true;
-  for (auto& k : kms) all_mat = all_mat && k.K != nullptr;
-  std::unique_ptr<ProblemBatcher> batcher;
-  if (all_mat && nprob > 1) batcher.reset(new ProblemBatcher(nprob, kms, ns, o.profile != 0));
-  StreamSet streams(nprob);
-  std::vector<std::exception_ptr> errs(static_cast<size_t>(nprob));
-  std::vector<FitOutcome> outs(static_cast<size_t>(nprob));
-  std::vector<std::thread> th;
   for (int i = 0; i < nprob; ++i) {
-    th.emplace_back([&, i] {
-      hipStream_t s = streams.s[size_t(i)];
-      try {
-        Operator op(X[i], n[i], p, KernelSpec{ks.kind, gamma[i]}, kms[size_t(i)], s);
-        prs[size_t(i)].attach(op);
-        op.enable_profile(o.profile != 0);
-        if (batcher) op.attach_batcher(batcher.get(), i);
-        outs[size_t(i)] = run_fit(op, prs[size_t(i)], y[i], n[i], tau[i], lam[i], o, alpha[i], s);
-      } catch (...) {
-        errs[size_t(i)] = std::current_exception();
-      }
-      if (batcher) batcher->leave(i);
-    });
+    kms.push_back(prs[size_t(i)].kmat());
+    ns.push_back(n[i]);
+    all_mat = all_mat && kms.back().K != nullptr;
   }
-  for (auto& x : th) x.join();
-  const double tb = batcher ? batcher->device_seconds() : 0.0;
-  const int64_t nb = batcher ? batcher->launches() : 0;
-  std::string first_msg;
-  int first_err = KQR_OK;
+  // 2. the fits, their fast K-applies in one launch per round
+  const bool batched = all_mat && nprob > 1;
+  std::unique_ptr<ProblemLauncher> launcher;
+  if (batched) launcher.reset(new ProblemLauncher(kms, ns));
+  Scheduler sched(launcher.get(), o.profile != 0);
+  std::vector<std::unique_ptr<Exec>> exs;
+  std::vector<std::unique_ptr<Operator>> ops;
   for (int i = 0; i < nprob; ++i) {
-    int stt = KQR_OK;
-    if (errs[size_t(i)]) {
-      std::string msg;
-      stt = status_of(errs[size_t(i)], msg);
-      if (first_err == KQR_OK) { first_err = stt; first_msg = msg; }
-    } else {
-      stt = outs[size_t(i)].converged ? KQR_OK : KQR_NOT_CONVERGED;
-      beta[i] = outs[size_t(i)].beta;
-      if (batcher) {
-        outs[size_t(i)].info.kapply_fast_calls = nb;
-        outs[size_t(i)].info.t_kapply_fast = tb;
-      }
-      if (info) info[i] = outs[size_t(i)].info;
-    }
-    status[i] = stt;
+    exs.emplace_back(new Exec(streams.s[size_t(i) % streams.s.size()], &sched, i));
+    ops.emplace_back(new Operator(X[i], n[i], p, KernelSpec{ks.kind, gamma[i]}, kms[size_t(i)], exs.back()->st));
+    prs[size_t(i)].attach(*ops.back());
+    ops.back()->enable_profile(o.profile != 0);
+    ops.back()->attach_batching(batched);
   }
-  KQR_CHECK_HIP(hipStreamSynchronize(st));
-  if (first_err != KQR_OK) fail(first_err, "%s", first_msg.c_str());
+  std::vector<Slotted> res(static_cast<size_t>(nprob));
+  std::vector<Co<Unit>> tasks;
+  for (int i = 0; i < nprob; ++i)
+    tasks.push_back(guarded_fit(*ops[size_t(i)], prs[size_t(i)], y[i], n[i], tau[i], lam[i], o, alpha[i],
+                                *exs[size_t(i)], res[size_t(i)]));
+  sched.run(tasks);
+  for (auto& t : tasks) t.result();
+  collect(res, sched, batched, beta, info, status, st);
 }
 
 }  // namespace kqr

@@ -61,9 +61,31 @@ struct ProblemTask {
   const double* v;  // n (FP64; rounded to FP32 in the kernel, as every fast apply rounds v)
   double* u;       // n (FP64)
 };
-int problem_blocks(int64_t n);  // workgroups one problem needs
-// One launch: u_t = K_t v_t for every task; first_block = exclusive prefix of problem_blocks.
-void kapply_problems(const ProblemTask* tasks_dev, int ntasks, const int* first_block_dev, int total_blocks,
-                     hipStream_t st);
+int problem_blocks(int64_t n);  // 32-row items of one problem
+
+// u_t = K_t v_t for every task in one persistent launch whose workgroups take
+// (problem, 32-row block) items from a device counter.  The task table goes
+// to the device through a ring of pinned staging copies, so a launch does not
+// wait for the host.  Launches must be ordered on one stream.
+class ProblemQueue {
+ public:
+  explicit ProblemQueue(size_t max_tasks);
+  ~ProblemQueue();
+  ProblemQueue(const ProblemQueue&) = delete;
+  ProblemQueue& operator=(const ProblemQueue&) = delete;
+  void launch(const std::vector<ProblemTask>& tasks, hipStream_t st);
+
+ private:
+  static constexpr int kRing = 8;
+  static constexpr int kQueueWgs = 2048;  // resident workgroups: 256 CUs x 8
+  size_t cap_, slot_bytes_;
+  DevBuf table_;
+  HostPinned stage_;
+  DevBuf ctr_;
+  hipEvent_t copied_[kRing] = {};
+  bool used_[kRing] = {};
+  uint64_t base_ = 0;
+  int next_ = 0;
+};
 
 }  // namespace kqr

@@ -8,6 +8,7 @@
 #include "kmulti.h"
 
 #include <algorithm>
+#include <cstring>
 #include <mutex>
 
 namespace kqr {
@@ -565,23 +566,11 @@ void kv_scatter(const double* U16, int m, int64_t n, DstTable16 dst, hipStream_t
 }
 
 // ----------------------------------------------------------------- many problems, one launch
-// Task t: K_t (n_t x ld_t, FP32 or BF16), v_t (FP64, n_t, rounded to FP32 here), u_t (FP64, n_t).
-// first_block[t] = prefix sum of row blocks (8 rows per wave, 4 waves per block).
-__global__ __launch_bounds__(256) void kapply_problems_kernel(const ProblemTask* __restrict__ tasks, int ntasks,
-                                                              const int* __restrict__ first_block) {
-  // locate the task of this block
-  int lo = 0, hi = ntasks - 1;
-  const int b = blockIdx.x;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (first_block[mid] <= b) lo = mid;
-    else hi = mid - 1;
-  }
-  const ProblemTask tk = tasks[lo];
+// Rows [row0, row0 + 8) of task tk, one wave: u = K v with v rounded to FP32
+// (as every fast apply rounds v), FP32 products within a 16-byte chunk, FP64
+// sums across chunks and lanes.
+__device__ __forceinline__ void problem_rows(const ProblemTask& tk, int64_t row0, int lane) {
   constexpr int ROWS = 8;
-  const int lane = threadIdx.x & 63;
-  const int64_t row0 = (int64_t(b - first_block[lo]) * 4 + (threadIdx.x >> 6)) * ROWS;
-  if (row0 >= tk.n) return;
   const bool bf = tk.dtype == KQR_BF16;
   const int vec = bf ? 8 : 4;
   const int64_t nchunk = tk.n / vec;
@@ -641,13 +630,84 @@ __global__ __launch_bounds__(256) void kapply_problems_kernel(const ProblemTask*
     if (lane == r && row0 + r < tk.n) tk.u[row0 + r] = acc[r];
 }
 
+// Persistent launch: every workgroup takes items (32-row blocks: 4 waves of
+// 8 rows) from the counter until the items run out.  Items are numbered in
+// task order (first_block = exclusive prefix of the tasks' block counts).
+// The counter is never reset: this launch's items are the values
+// [base, base + total) it hands out, and each workgroup takes exactly one
+// value beyond them before it stops, so the next launch starts at
+// base + total + gridDim.x.
+__global__ __launch_bounds__(256) void kapply_problems_queue_kernel(const ProblemTask* __restrict__ tasks, int ntasks,
+                                                                    const int* __restrict__ first_block, int total,
+                                                                    unsigned long long* __restrict__ ctr,
+                                                                    unsigned long long base) {
+  __shared__ int item_sh;
+  const int lane = threadIdx.x & 63;
+  for (;;) {
+    if (threadIdx.x == 0) item_sh = int(atomicAdd(ctr, 1ull) - base);
+    __syncthreads();
+    const int item = item_sh;
+    __syncthreads();  // every wave has the item before thread 0 takes the next
+    if (item < 0 || item >= total) break;  // (negative only if launches of one queue overlapped)
+    int lo = 0, hi = ntasks - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (first_block[mid] <= item) lo = mid;
+      else hi = mid - 1;
+    }
+    const ProblemTask tk = tasks[lo];
+    const int64_t row0 = (int64_t(item - first_block[lo]) * 4 + (threadIdx.x >> 6)) * 8;
+    if (row0 < tk.n) problem_rows(tk, row0, lane);
+  }
+}
+
 int problem_blocks(int64_t n) { return int((n + 31) / 32); }
 
-void kapply_problems(const ProblemTask* tasks_dev, int ntasks, const int* first_block_dev, int total_blocks,
-                     hipStream_t st) {
-  if (ntasks <= 0 || total_blocks <= 0) return;
-  kapply_problems_kernel<<<total_blocks, 256, 0, st>>>(tasks_dev, ntasks, first_block_dev);
+namespace {
+size_t queue_table_bytes(size_t cap) {
+  return (cap * sizeof(ProblemTask) + (cap + 1) * sizeof(int) + 255) / 256 * 256;
+}
+}  // namespace
+
+ProblemQueue::ProblemQueue(size_t max_tasks)
+    : cap_(std::max<size_t>(max_tasks, 1)), slot_bytes_(queue_table_bytes(cap_)), table_(kRing * slot_bytes_),
+      stage_(kRing * slot_bytes_), ctr_(sizeof(unsigned long long)) {
+  KQR_CHECK_HIP(hipMemset(ctr_.ptr, 0, sizeof(unsigned long long)));
+  for (auto& e : copied_) KQR_CHECK_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+}
+
+ProblemQueue::~ProblemQueue() {
+  for (auto& e : copied_) (void)hipEventDestroy(e);
+}
+
+void ProblemQueue::launch(const std::vector<ProblemTask>& tasks, hipStream_t st) {
+  if (tasks.empty()) return;
+  if (tasks.size() > cap_) fail(KQR_EHIP, "internal: %zu tasks for a queue of %zu", tasks.size(), cap_);
+  const int k = next_;
+  next_ = (next_ + 1) % kRing;
+  // the staging copy of this ring slot was last read by the copy recorded kRing launches ago
+  if (used_[k]) KQR_CHECK_HIP(hipEventSynchronize(copied_[k]));
+  char* stage = static_cast<char*>(stage_.ptr) + size_t(k) * slot_bytes_;
+  char* table = static_cast<char*>(table_.ptr) + size_t(k) * slot_bytes_;
+  const size_t ntask = tasks.size();
+  memcpy(stage, tasks.data(), ntask * sizeof(ProblemTask));
+  int* first = reinterpret_cast<int*>(stage + ntask * sizeof(ProblemTask));
+  int total = 0;
+  for (size_t t = 0; t < ntask; ++t) {
+    first[t] = total;
+    total += problem_blocks(tasks[t].n);
+  }
+  first[ntask] = total;
+  const size_t bytes = ntask * sizeof(ProblemTask) + (ntask + 1) * sizeof(int);
+  KQR_CHECK_HIP(hipMemcpyAsync(table, stage, bytes, hipMemcpyHostToDevice, st));
+  KQR_CHECK_HIP(hipEventRecord(copied_[k], st));
+  used_[k] = true;
+  const int grid = std::min(total, kQueueWgs);
+  kapply_problems_queue_kernel<<<grid, 256, 0, st>>>(
+      reinterpret_cast<const ProblemTask*>(table), int(ntask),
+      reinterpret_cast<const int*>(table + ntask * sizeof(ProblemTask)), total, ctr_.as<unsigned long long>(), base_);
   KQR_LAUNCH_CHECK();
+  base_ += uint64_t(total) + uint64_t(grid);
 }
 
 }  // namespace kqr

@@ -52,6 +52,20 @@ struct DevBuf {
   template <typename T> T* as() const { return static_cast<T*>(ptr); }
 };
 
+// While alive on a thread, DevBuf releases on that thread are collected and
+// freed when the scope ends (hipFree synchronises the device).
+class DeferFrees {
+ public:
+  DeferFrees();
+  ~DeferFrees();
+  DeferFrees(const DeferFrees&) = delete;
+  DeferFrees& operator=(const DeferFrees&) = delete;
+
+ private:
+  std::vector<void*> list_;
+  std::vector<void*>* prev_;
+};
+
 // Pinned host staging for small device->host reads.
 struct HostPinned {
   void* ptr = nullptr;

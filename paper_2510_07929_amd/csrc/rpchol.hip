@@ -196,10 +196,12 @@ __global__ void rpc_diag_kernel(const KMat km, int64_t n, double* __restrict__ d
     d[j] = static_cast<const float*>(km.K)[off];
 }
 
-std::vector<int64_t> rpcholesky(const KMat& km, const float* X, const float* sqn, int64_t n, int p, KernelSpec ks,
-                                int64_t rank, const double* uniforms, float* F, int64_t ldf, hipStream_t st) {
+Co<std::vector<int64_t>> rpcholesky(KMat km, const float* X, const float* sqn, int64_t n, int p,
+                                    KernelSpec ks, int64_t rank, const double* uniforms, float* F, int64_t ldf,
+                                    Exec& ex) {
+  const hipStream_t st = ex.st;
   std::vector<int64_t> pivots;
-  if (rank <= 0 || n <= 0) return pivots;
+  if (rank <= 0 || n <= 0) co_return pivots;
   rank = std::min<int64_t>(rank, n);
   if (rank > 1024) fail(KQR_EINVAL, "RPCholesky rank %lld exceeds 1024", (long long)rank);
   DevBuf d(size_t(n) * sizeof(double)), u(size_t(n) * sizeof(double)), fs(1024 * sizeof(double));
@@ -228,13 +230,12 @@ std::vector<int64_t> rpcholesky(const KMat& km, const float* X, const float* sqn
     KQR_LAUNCH_CHECK();
   }
   std::vector<int64_t> h(size_t(rank), -1);
-  KQR_CHECK_HIP(hipMemcpyAsync(h.data(), piv.ptr, size_t(rank) * sizeof(int64_t), hipMemcpyDeviceToHost, st));
-  KQR_CHECK_HIP(hipStreamSynchronize(st));
+  co_await read_back(ex, piv.ptr, size_t(rank) * sizeof(int64_t), h.data());
   for (int64_t i = 0; i < rank; ++i) {
     if (h[size_t(i)] < 0) break;
     pivots.push_back(h[size_t(i)]);
   }
-  return pivots;
+  co_return pivots;
 }
 
 // ================================================================= rank heuristic
@@ -358,9 +359,10 @@ __global__ void rank_from_tridiag_kernel(const double* __restrict__ d, const dou
   out[1] = lam1;
 }
 
-int64_t adaptive_rank(const float* F0, int64_t n, int64_t r0, int64_t ldf, double xi, hipStream_t st,
-                      double* lambda1_out) {
-  if (r0 <= 1) return r0;
+Co<int64_t> adaptive_rank(const float* F0, int64_t n, int64_t r0, int64_t ldf, double xi, Exec& ex,
+                          double* lambda1_out) {
+  const hipStream_t st = ex.st;
+  if (r0 <= 1) co_return r0;
   Woodbury W(F0, n, r0, ldf);
   const double* G = W.gram(st);  // (r0+1)^2 lower triangle of [F0 1]^T [F0 1]
   const int m = int(r0);
@@ -372,10 +374,9 @@ int64_t adaptive_rank(const float* F0, int64_t n, int64_t r0, int64_t ldf, doubl
   rank_from_tridiag_kernel<<<1, 64, 0, st>>>(dg.as<double>(), eg.as<double>(), m, xi, out.as<double>());
   KQR_LAUNCH_CHECK();
   double h[2];
-  KQR_CHECK_HIP(hipMemcpyAsync(h, out.ptr, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
-  KQR_CHECK_HIP(hipStreamSynchronize(st));
+  co_await read_back(ex, out.ptr, 2 * sizeof(double), h);
   if (lambda1_out) *lambda1_out = h[1];
-  return int64_t(h[0]);
+  co_return int64_t(h[0]);
 }
 
 }  // namespace kqr

@@ -3,38 +3,26 @@
 
 #include <memory>
 
+#include "coro.h"
 #include "vec.h"
 
 namespace kqr {
-
-// Coalesces the fast K-applies of several solvers running in their own host
-// threads into one launch (see batch.hip).  submit() blocks until the batch
-// holding the request has been enqueued; the caller's stream then waits for it.
-class ApplyBatcher {
- public:
-  virtual ~ApplyBatcher() = default;
-  // exact: the request wants the exact operator (FP64 vector, products and
-  // sums); only when exact_ok().
-  virtual void submit(int slot, const double* v, double* out, hipStream_t st, bool exact) = 0;
-  virtual void leave(int slot) = 0;
-  virtual bool exact_ok() const { return false; }
-};
 
 // The kernel operator K v: materialised (FP32 / BF16 storage) or on the fly.
 class Operator {
  public:
   Operator(const float* X, int64_t n, int p, KernelSpec ks, KMat km, hipStream_t st);
-  // Route fast applies through a batcher (slot = this solver's index).
-  void attach_batcher(ApplyBatcher* b, int slot) {
-    batcher_ = b;
-    slot_ = slot;
-  }
+  // Route the applies through the scheduler's batched launches (fast ones
+  // always, exact ones when the scheduler's launcher serves them).
+  void attach_batching(bool on) { batched_ = on; }
   // FP32 copy of K for the exact applies when the fast operator is stored in BF16.
   void set_exact(KMat k) { kexact_ = k; }
   // Fast apply: FP32 products (from v32 when given, else a rounded copy of v).
-  void apply_fast(const double* v, const float* v32, double* u, hipStream_t st);
+  // In a batch the request goes to ex's scheduler and the returned awaitable
+  // suspends until the batched launch has been enqueued.
+  [[nodiscard]] ApplyAwait apply_fast(const double* v, const float* v32, double* u, Exec& ex);
   // Exact apply: FP32 entries (stored FP32 or recomputed) with FP64 vector and sums.
-  void apply_exact(const double* v, double* u, hipStream_t st);
+  [[nodiscard]] ApplyAwait apply_exact(const double* v, double* u, Exec& ex);
   bool materialized() const { return km_.K != nullptr; }
   int64_t calls() const { return calls_; }
   const KMat& kmat() const { return km_; }
@@ -67,13 +55,11 @@ class Operator {
   int64_t calls_ = 0;
   bool profile_ = false;
   std::vector<Span> spans_;
-  ApplyBatcher* batcher_ = nullptr;
-  int slot_ = -1;
+  bool batched_ = false;
 };
 
 struct PcgBuffers {
   DevBuf r, zz, p, q, Kp, p32, sc;
-  HostPinned hsc;
   explicit PcgBuffers(int64_t n);
 };
 
@@ -94,29 +80,28 @@ Kkt kkt_from_sums(const double* s, double ynorm, double lam);
 // Left-preconditioned conjugate gradients on (K + c 1 1^T + diag(L)) x = b.
 class Pcg {
  public:
-  Pcg(Operator& op, Workspace& ws, int64_t n);
+  Pcg(Operator& op, Workspace& ws, int64_t n, Exec& ex);
   // x holds the start (ignored when x_zero); Kx, when given, holds K x on entry
   // (ignored when x_zero) and is advanced with the same steps as x.
-  PcgStats solve(double c, const double* L, Woodbury* P, const double* b, double* x, double* Kx, bool x_zero,
-                 double tol, int maxit, bool fast, hipStream_t st);
+  Co<PcgStats> solve(double c, const double* L, Woodbury* P, const double* b, double* x, double* Kx, bool x_zero,
+                     double tol, int maxit, bool fast);
 
  private:
-  double read_scalar(const double* dev, hipStream_t st);
-  void read_scalars(const double* dev, int cnt, double* out, hipStream_t st);
   Operator& op_;
   Workspace& ws_;
   int64_t n_;
+  Exec& ex_;
   PcgBuffers pb_;
-  HostPinned hbuf_;
 };
 
 class Solver {
  public:
-  Solver(Operator& op, const double* y, int64_t n, double tau, double lam, const kqr_options& o, const float* F,
-         int64_t rank, int64_t ldf, hipStream_t st);
-  void phase1(kqr_info& info);
-  void phase2(kqr_info& info);
-  void finish(kqr_info& info);
+  Solver(Operator& op, Exec& ex, const double* y, int64_t n, double tau, double lam, const kqr_options& o,
+         const float* F, int64_t rank, int64_t ldf);
+  Co<Unit> init();  // reads ||y|| (fails on non-finite y)
+  Co<Unit> phase1(kqr_info& info);
+  Co<Unit> phase2(kqr_info& info);
+  Co<Unit> finish(kqr_info& info);
   const double* alpha() const { return alpha_.as<double>(); }
   const double* z() const { return z_.as<double>(); }  // ALM multipliers
   const double* v() const { return v_.as<double>(); }  // consensus copy of alpha (1.4)
@@ -125,17 +110,16 @@ class Solver {
   Workspace& ws() { return ws_; }
 
  private:
-  PcgStats linsolve(double c, const double* L, const double* b, double* x, double* Kx, bool x_zero, double tol,
-                    bool refine, kqr_info& info);
-  void ssn(double stop, kqr_info& info);
+  Co<PcgStats> linsolve(double c, const double* L, const double* b, double* x, double* Kx, bool x_zero, double tol,
+                        bool refine, kqr_info& info);
+  Co<Unit> ssn(double stop, kqr_info& info);
   Kkt kkt_from_sums(const double* s) const;
-  Kkt update_and_kkt(double beta_new, double sigma, double step, bool update);
+  Co<Kkt> update_and_kkt(double beta_new, double sigma, double step, bool update);
   void record(int phase, int it, double err);
-  double sum_of(const double* x);
-  double read_scalar(const double* dev, hipStream_t st);
-  void read_scalars(const double* dev, int cnt, double* out, hipStream_t st);
+  Co<double> sum_of(const double* x);
 
   Operator& op_;
+  Exec& ex_;
   const double* y_;
   int64_t n_;
   double tau_, lam_;
@@ -143,7 +127,6 @@ class Solver {
   hipStream_t st_;
   Workspace ws_;
   Pcg pcg_;
-  HostPinned hbuf_;
   DevBuf alpha_, v_, z_, Ka_, b_, L_, grad_, d_, Kd_, S_, red_;
   DevBuf rf_r_, rf_dx_, rf_kdx_;  // refinement workspace (BF16 storage)
   std::unique_ptr<Woodbury> P_;

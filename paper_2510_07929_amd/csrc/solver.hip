@@ -81,17 +81,15 @@ double* Operator::scratch(const KMat& k, size_t& doubles) {
   return scratch(doubles);
 }
 
-void Operator::apply_fast(const double* v, const float* v32, double* u, hipStream_t st) {
+ApplyAwait Operator::apply_fast(const double* v, const float* v32, double* u, Exec& ex) {
   ++calls_;
-  if (batcher_) {
-    batcher_->submit(slot_, v, u, st, false);
-    return;
-  }
+  const hipStream_t st = ex.st;
+  if (batched_) return ApplyAwait{&ex, ApplyReq{v, u, false}};
   if (ks_.kind == KQR_LINEAR) {  // X (X^T v), FP64: the fast and the exact operator coincide
     mark(true, true, st);
     lin_apply(X_, n_, p_, v, u, 1, lin_.as<double>(), st);
     mark(false, true, st);
-    return;
+    return {};
   }
   if (km_.K) {
     if (!v32) {
@@ -116,14 +114,13 @@ void Operator::apply_fast(const double* v, const float* v32, double* u, hipStrea
     kapply_otf(X_, sqn_.as<float>(), n_, X_, sqn_.as<float>(), n_, p_, ks_, v, u, 1, 1.0, 0.0, st, false, scr, nd);
     mark(false, true, st);
   }
+  return {};
 }
 
-void Operator::apply_exact(const double* v, double* u, hipStream_t st) {
+ApplyAwait Operator::apply_exact(const double* v, double* u, Exec& ex) {
   ++calls_;
-  if (batcher_ && batcher_->exact_ok()) {  // rides along in the shared pass over K
-    batcher_->submit(slot_, v, u, st, true);
-    return;
-  }
+  const hipStream_t st = ex.st;
+  if (batched_ && ex.sched->exact_ok()) return ApplyAwait{&ex, ApplyReq{v, u, true}};  // rides along in the shared pass over K
   size_t nd = 0;
   double* scr = nullptr;
   if (km_.K) scr = scratch(km_.dtype == KQR_FP32 || !kexact_.K ? km_ : kexact_, nd);
@@ -143,46 +140,24 @@ void Operator::apply_exact(const double* v, double* u, hipStream_t st) {
     kapply_otf(X_, sqn_.as<float>(), n_, X_, sqn_.as<float>(), n_, p_, ks_, v, u, 1, 1.0, 0.0, st, true, scr, nd);
   }
   mark(false, false, st);
+  return {};
 }
 
 // ================================================================= PCG
 PcgBuffers::PcgBuffers(int64_t n)
     : r(n * sizeof(double)), zz(n * sizeof(double)), p(n * sizeof(double)), q(n * sizeof(double)),
-      Kp(n * sizeof(double)), p32(n * sizeof(float)), sc(16 * sizeof(double)), hsc(16 * sizeof(double)) {}
+      Kp(n * sizeof(double)), p32(n * sizeof(float)), sc(16 * sizeof(double)) {}
 
-Pcg::Pcg(Operator& op, Workspace& ws, int64_t n) : op_(op), ws_(ws), n_(n), pb_(n), hbuf_(16 * sizeof(double)) {}
-
-double Pcg::read_scalar(const double* dev, hipStream_t st) {
-  KQR_CHECK_HIP(hipMemcpyAsync(hbuf_.ptr, dev, sizeof(double), hipMemcpyDeviceToHost, st));
-  KQR_CHECK_HIP(hipStreamSynchronize(st));
-  return *hbuf_.as<double>();
-}
-
-void Pcg::read_scalars(const double* dev, int cnt, double* out, hipStream_t st) {
-  KQR_CHECK_HIP(hipMemcpyAsync(hbuf_.ptr, dev, cnt * sizeof(double), hipMemcpyDeviceToHost, st));
-  KQR_CHECK_HIP(hipStreamSynchronize(st));
-  memcpy(out, hbuf_.ptr, cnt * sizeof(double));
-}
-
-double Solver::read_scalar(const double* dev, hipStream_t st) {
-  KQR_CHECK_HIP(hipMemcpyAsync(hbuf_.ptr, dev, sizeof(double), hipMemcpyDeviceToHost, st));
-  KQR_CHECK_HIP(hipStreamSynchronize(st));
-  return *hbuf_.as<double>();
-}
-
-void Solver::read_scalars(const double* dev, int cnt, double* out, hipStream_t st) {
-  KQR_CHECK_HIP(hipMemcpyAsync(hbuf_.ptr, dev, cnt * sizeof(double), hipMemcpyDeviceToHost, st));
-  KQR_CHECK_HIP(hipStreamSynchronize(st));
-  memcpy(out, hbuf_.ptr, cnt * sizeof(double));
-}
+Pcg::Pcg(Operator& op, Workspace& ws, int64_t n, Exec& ex) : op_(op), ws_(ws), n_(n), ex_(ex), pb_(n) {}
 
 // Solves (K + c 1 1^T + diag(L)) x = b.  x holds the start (ignored when
 // x_zero); Kx, when given, holds K x on entry (ignored when x_zero) and is
 // advanced with the same steps as x, so on return Kx = K x up to rounding
 // without an extra K-apply.
-PcgStats Pcg::solve(double c, const double* L, Woodbury* P, const double* b, double* x, double* Kx,
-                     bool x_zero, double tol, int maxit, bool fast, hipStream_t st) {
+Co<PcgStats> Pcg::solve(double c, const double* L, Woodbury* P, const double* b, double* x, double* Kx,
+                        bool x_zero, double tol, int maxit, bool fast) {
   const int64_t n = n_;
+  const hipStream_t st = ex_.st;
   double* sc = pb_.sc.as<double>();
   enum { RZ0 = 0, RZ1 = 1, PQ = 2, RR = 3, SUMP = 4, SUMX = 5, TMP = 8 };
   if (x_zero) {
@@ -193,15 +168,16 @@ PcgStats Pcg::solve(double c, const double* L, Woodbury* P, const double* b, dou
     vec_dots(n, x, nullptr, ws_, sc + TMP, st);  // sc[TMP] = sum(x)
     const double* Kx0 = Kx;
     if (!Kx0) {
-      op_.apply_exact(x, pb_.Kp.as<double>(), st);
+      co_await op_.apply_exact(x, pb_.Kp.as<double>(), ex_);
       Kx0 = pb_.Kp.as<double>();
     }
     pcg_init_r(n, b, x, Kx0, L, c, sc, TMP, pb_.r.as<double>(), ws_, sc + RR, st);
   }
-  double rr = read_scalar(sc + RR, st);
+  double rr = 0.0;
+  co_await read_back(ex_, sc + RR, sizeof(double), &rr);
   PcgStats stats;
   stats.resnorm = std::sqrt(rr);
-  if (!(stats.resnorm > tol)) return stats;
+  if (!(stats.resnorm > tol)) co_return stats;
   int cur = 0;
   auto precond = [&](int slot) {
     if (P) P->apply(pb_.r.as<double>(), pb_.zz.as<double>(), pb_.r.as<double>(), sc + slot, ws_, st);
@@ -211,13 +187,13 @@ PcgStats Pcg::solve(double c, const double* L, Woodbury* P, const double* b, dou
   precond(RZ0);
   pcg_update_p(n, pb_.zz.as<double>(), pb_.p.as<double>(), p32, sc, RZ0, RZ0, true, ws_, sc + SUMP, st);
   for (int it = 1; it <= maxit; ++it) {
-    if (fast) op_.apply_fast(pb_.p.as<double>(), p32, pb_.Kp.as<double>(), st);
-    else op_.apply_exact(pb_.p.as<double>(), pb_.Kp.as<double>(), st);
+    if (fast) co_await op_.apply_fast(pb_.p.as<double>(), p32, pb_.Kp.as<double>(), ex_);
+    else co_await op_.apply_exact(pb_.p.as<double>(), pb_.Kp.as<double>(), ex_);
     pcg_q(n, pb_.Kp.as<double>(), pb_.p.as<double>(), L, c, sc, SUMP, pb_.q.as<double>(), ws_, sc + PQ, st);
     pcg_xr(n, pb_.p.as<double>(), pb_.q.as<double>(), pb_.Kp.as<double>(), x, pb_.r.as<double>(), Kx, sc,
            cur == 0 ? RZ0 : RZ1, PQ, ws_, sc + RR, st);
     double two[2];
-    read_scalars(sc + PQ, 2, two, st);  // [PQ, RR]
+    co_await read_back(ex_, sc + PQ, 2 * sizeof(double), two);  // [PQ, RR]
     stats.iters = it;
     stats.resnorm = std::sqrt(std::max(two[1], 0.0));
     if (!(two[0] > 0.0)) {  // curvature lost: the step just taken is unreliable, stop here
@@ -231,7 +207,7 @@ PcgStats Pcg::solve(double c, const double* L, Woodbury* P, const double* b, dou
                  nxt == 0 ? RZ0 : RZ1, false, ws_, sc + SUMP, st);
     cur = nxt;
   }
-  return stats;
+  co_return stats;
 }
 
 static double now_s() {
@@ -239,19 +215,23 @@ static double now_s() {
 }
 
 // ================================================================= solver
-Solver::Solver(Operator& op, const double* y, int64_t n, double tau, double lam, const kqr_options& o,
-               const float* F, int64_t rank, int64_t ldf, hipStream_t st)
-    : op_(op), y_(y), n_(n), tau_(tau), lam_(lam), o_(o), st_(st), pcg_(op, ws_, n), hbuf_(64 * sizeof(double)),
+Solver::Solver(Operator& op, Exec& ex, const double* y, int64_t n, double tau, double lam, const kqr_options& o,
+               const float* F, int64_t rank, int64_t ldf)
+    : op_(op), ex_(ex), y_(y), n_(n), tau_(tau), lam_(lam), o_(o), st_(ex.st), pcg_(op, ws_, n, ex),
       alpha_(n * sizeof(double)), v_(n * sizeof(double)), z_(n * sizeof(double)), Ka_(n * sizeof(double)),
       b_(n * sizeof(double)), L_(n * sizeof(double)), grad_(n * sizeof(double)), d_(n * sizeof(double)),
       Kd_(n * sizeof(double)), S_(n), red_(64 * sizeof(double)) {
   if (rank > 0) P_.reset(new Woodbury(F, n, rank, ldf));
+}
+
+Co<Unit> Solver::init() {
   double t3[3];
-  vec_dots(n, y, nullptr, ws_, red_.as<double>(), st);
-  read_scalars(red_.as<double>(), 3, t3, st);
+  vec_dots(n_, y_, nullptr, ws_, red_.as<double>(), st_);
+  co_await read_back(ex_, red_.as<double>(), 3 * sizeof(double), t3);
   ynorm_ = std::sqrt(t3[2]);
   if (!std::isfinite(ynorm_)) fail(KQR_ENUMERIC, "y contains NaN or Inf");
   t_start_ = now_s();
+  co_return Unit{};
 }
 
 void Solver::record(int phase, int it, double err) {
@@ -283,19 +263,19 @@ Kkt kkt_from_sums(const double* s, double ynorm, double lam) {
 
 Kkt Solver::kkt_from_sums(const double* s) const { return ::kqr::kkt_from_sums(s, ynorm_, lam_); }
 
-double Solver::sum_of(const double* x) {
+Co<double> Solver::sum_of(const double* x) {
   double t3[3];
   vec_dots(n_, x, nullptr, ws_, red_.as<double>(), st_);
-  read_scalars(red_.as<double>(), 3, t3, st_);
-  return t3[0];
+  co_await read_back(ex_, red_.as<double>(), 3 * sizeof(double), t3);
+  co_return t3[0];
 }
 
-Kkt Solver::update_and_kkt(double beta_new, double sigma, double step, bool update) {
+Co<Kkt> Solver::update_and_kkt(double beta_new, double sigma, double step, bool update) {
   double s[kKktSums];
   multiplier_kkt(n_, alpha_.as<double>(), Ka_.as<double>(), y_, z_.as<double>(), v_.as<double>(), beta_new, sigma,
                  step, tau_, lam_, update, ws_, red_.as<double>(), st_);
-  read_scalars(red_.as<double>(), kKktSums, s, st_);
-  return kkt_from_sums(s);
+  co_await read_back(ex_, red_.as<double>(), kKktSums * sizeof(double), s);
+  co_return kkt_from_sums(s);
 }
 
 // Linear solve of (K + c 1 1^T + diag(L)) x = b to ||b - A x|| <= tol, with K x
@@ -307,10 +287,10 @@ Kkt Solver::update_and_kkt(double beta_new, double sigma, double step, bool upda
 // to the contraction the previous step achieved, x += dx and K x += K_exact dx.
 // When a refinement step fails to reduce the exact residual by a tenth, the
 // solve finishes with PCG on the exact operator.
-PcgStats Solver::linsolve(double c, const double* L, const double* b, double* x, double* Kx, bool x_zero, double tol,
-                          bool refine, kqr_info& info) {
+Co<PcgStats> Solver::linsolve(double c, const double* L, const double* b, double* x, double* Kx, bool x_zero,
+                              double tol, bool refine, kqr_info& info) {
   if (!(refine && op_.materialized() && op_.kmat().dtype == KQR_BF16 && o_.refine)) {
-    return pcg_.solve(c, L, P_.get(), b, x, Kx, x_zero, tol, o_.pcg_max_iter, true, st_);
+    co_return co_await pcg_.solve(c, L, P_.get(), b, x, Kx, x_zero, tol, o_.pcg_max_iter, true);
   }
   const int64_t n = n_;
   if (!rf_r_.ptr) {
@@ -326,49 +306,49 @@ PcgStats Solver::linsolve(double c, const double* L, const double* b, double* x,
     fill(n, 0.0, Kx, st_);
   }
   double sums[3];
-  auto residual = [&]() -> double {  // r = b - (Kx + c sum(x) + L x); returns ||r||
+  auto residual = [&]() -> Co<double> {  // r = b - (Kx + c sum(x) + L x); returns ||r||
     vec_dots(n, x, nullptr, ws_, red_.as<double>(), st_);
     pcg_init_r(n, b, x, Kx, L, c, red_.as<double>(), 0, r, ws_, red_.as<double>() + 8, st_);
-    read_scalars(red_.as<double>() + 8, 1, sums, st_);
-    return std::sqrt(std::max(sums[0], 0.0));
+    co_await read_back(ex_, red_.as<double>() + 8, sizeof(double), sums);
+    co_return std::sqrt(std::max(sums[0], 0.0));
   };
   PcgStats total;
-  double rn = residual();
+  double rn = co_await residual();
   total.resnorm = rn;
   // relative accuracy of the inner solve: solving far below the contraction
   // the BF16 operator allows only costs iterations
   double inner_rel = 0.05;
   for (int step = 0; step < 30 && rn > tol; ++step) {
     const double inner_tol = std::max(0.5 * tol, inner_rel * rn);
-    PcgStats ps = pcg_.solve(c, L, P_.get(), r, dx, nullptr, true, inner_tol, o_.pcg_max_iter, true, st_);
+    PcgStats ps = co_await pcg_.solve(c, L, P_.get(), r, dx, nullptr, true, inner_tol, o_.pcg_max_iter, true);
     total.iters += ps.iters;
-    op_.apply_exact(dx, kdx, st_);
+    co_await op_.apply_exact(dx, kdx, ex_);
     axpy2(n, 1.0, dx, x, kdx, Kx, st_);
     ++info.refinements;
-    const double rn_new = residual();
+    const double rn_new = co_await residual();
     total.resnorm = rn_new;
     const bool stalled = !(rn_new < 0.9 * rn);
     inner_rel = std::min(0.3, std::max(0.05, 0.5 * rn_new / rn));
     rn = rn_new;
     if (stalled && rn > tol) {  // BF16 operator too far from the exact one here
-      PcgStats pe = pcg_.solve(c, L, P_.get(), b, x, Kx, false, tol, o_.pcg_max_iter, false, st_);
+      PcgStats pe = co_await pcg_.solve(c, L, P_.get(), b, x, Kx, false, tol, o_.pcg_max_iter, false);
       total.iters += pe.iters;
       total.resnorm = pe.resnorm;
       // exact K x after the exact solve (Kx was advanced with exact products)
       break;
     }
   }
-  return total;
+  co_return total;
 }
 
 // Algorithm 1.  M = K + lambda sigma (I + 1 1^T) is fixed, so the Woodbury
 // core (L = lambda sigma I) is formed once.
-void Solver::phase1(kqr_info& info) {
+Co<Unit> Solver::phase1(kqr_info& info) {
   const double t0 = now_s();
   const int64_t n = n_;
   const double sigma = o_.admm_sigma, step = o_.admm_step, c = lam_ * sigma;
   fill(n, c, L_.as<double>(), st_);
-  if (P_ && !P_->build_scaled_identity(L_.as<double>(), c, c, st_))
+  if (P_ && !co_await P_->build_scaled_identity(L_.as<double>(), c, c, ex_))
     fail(KQR_ENUMERIC, "ADMM preconditioner core not positive definite");
   fill(n, 0.0, alpha_.as<double>(), st_);
   fill(n, 0.0, v_.as<double>(), st_);
@@ -383,18 +363,18 @@ void Solver::phase1(kqr_info& info) {
     if (it == 0) {
       double t3[3];
       vec_dots(n, b_.as<double>(), nullptr, ws_, red_.as<double>(), st_);
-      read_scalars(red_.as<double>(), 3, t3, st_);
+      co_await read_back(ex_, red_.as<double>(), 3 * sizeof(double), t3);
       b0 = std::sqrt(t3[2]);
     }
     const double eps_k = o_.admm_eps0 * b0 / std::pow(double(it + 1), 1.5);
     // Phase I is a warm start: with BF16 storage it runs on the BF16 operator
     // alone (K alpha is recomputed exactly when Phase II starts)
-    PcgStats ps = linsolve(c, L_.as<double>(), b_.as<double>(), alpha_.as<double>(), Ka_.as<double>(), it == 0, eps_k,
-                           false, info);
+    PcgStats ps = co_await linsolve(c, L_.as<double>(), b_.as<double>(), alpha_.as<double>(), Ka_.as<double>(),
+                                    it == 0, eps_k, false, info);
     info.admm_pcg_iters += ps.iters;
-    const double sa = sum_of(alpha_.as<double>());
+    const double sa = co_await sum_of(alpha_.as<double>());
     const double beta_new = beta_ + step * sigma * sa;
-    k = update_and_kkt(beta_new, sigma, step, true);
+    k = co_await update_and_kkt(beta_new, sigma, step, true);
     beta_ = beta_new;
     if (o_.verbose)
       fprintf(stderr, "[kqr] admm %3d pcg %3d eta_p %.2e eta_d %.2e eta_c %.2e gap %.2e\n", it + 1, ps.iters,
@@ -403,8 +383,8 @@ void Solver::phase1(kqr_info& info) {
     if (k.err <= o_.admm_tol && o_.admm_tol <= o_.tol) {
       // Phase I is the whole solve here: confirm with an exact K alpha (the
       // tracked products carry FP32 rounding) before stopping
-      op_.apply_exact(alpha_.as<double>(), Ka_.as<double>(), st_);
-      k = update_and_kkt(beta_, sigma, step, false);
+      co_await op_.apply_exact(alpha_.as<double>(), Ka_.as<double>(), ex_);
+      k = co_await update_and_kkt(beta_, sigma, step, false);
     }
     record(1, it + 1, k.err);
     if (k.err <= o_.admm_tol) { ++it; break; }
@@ -413,29 +393,31 @@ void Solver::phase1(kqr_info& info) {
   sigma_ = sigma;
   eta_d_prev_ = k.eta_d;
   last_ = k;
-  KQR_CHECK_HIP(hipStreamSynchronize(st_));
-  info.t_admm = now_s() - t0;
+  info.t_admm = now_s() - t0;  // the last read-back drained the stream
+  co_return Unit{};
 }
 
 // Algorithm 3 on phi_k for the current (beta, z, sigma).
-void Solver::ssn(double stop, kqr_info& info) {
+Co<Unit> Solver::ssn(double stop, kqr_info& info) {
   const int64_t n = n_;
   const double sigma = sigma_, c1 = lam_ * sigma;
   for (int t = 0; t < o_.ssn_max_iter; ++t) {
-    const double sa = sum_of(alpha_.as<double>());
+    const double sa = co_await sum_of(alpha_.as<double>());
     ssn_grad(n, alpha_.as<double>(), Ka_.as<double>(), y_, z_.as<double>(), beta_, sigma, sa, tau_, lam_,
              grad_.as<double>(), S_.as<uint8_t>(), ws_, red_.as<double>(), st_);
-    const double gn = std::sqrt(read_scalar(red_.as<double>(), st_));
+    double gg = 0.0;
+    co_await read_back(ex_, red_.as<double>(), sizeof(double), &gg);
+    const double gn = std::sqrt(gg);
     if (!std::isfinite(gn)) fail(KQR_ENUMERIC, "non-finite gradient in SSN");
     if (gn <= stop) break;
     const double eps_t = std::max(o_.tau1 * std::min(o_.tau2, gn), o_.eps_floor);
     ssn_system(n, S_.as<uint8_t>(), grad_.as<double>(), lam_, sigma, eps_t, L_.as<double>(), b_.as<double>(), st_);
-    if (P_ && !P_->build_two_level(L_.as<double>(), S_.as<uint8_t>(), lam_ * eps_t, lam_ * sigma + lam_ * eps_t, c1,
-                                   st_))
+    if (P_ && !co_await P_->build_two_level(L_.as<double>(), S_.as<uint8_t>(), lam_ * eps_t,
+                                            lam_ * sigma + lam_ * eps_t, c1, ex_))
       fail(KQR_ENUMERIC, "Newton preconditioner core not positive definite");
     const double tol = lam_ * std::min(o_.etabar, std::pow(gn, 1.0 + o_.iota));
-    PcgStats ps =
-        linsolve(c1, L_.as<double>(), b_.as<double>(), d_.as<double>(), Kd_.as<double>(), true, tol, true, info);
+    PcgStats ps = co_await linsolve(c1, L_.as<double>(), b_.as<double>(), d_.as<double>(), Kd_.as<double>(), true,
+                                    tol, true, info);
     info.pcg_iters += ps.iters;
     // Armijo backtracking, kLsTrials step lengths per pass
     const double s0 = sa + beta_ / sigma;
@@ -446,7 +428,7 @@ void Solver::ssn(double stop, kqr_info& info) {
       double s[5 + kLsTrials];
       line_search_sums(n, alpha_.as<double>(), z_.as<double>(), d_.as<double>(), Ka_.as<double>(), Kd_.as<double>(),
                        y_, grad_.as<double>(), sigma, tau_, c0, o_.ls_shrink, ws_, red_.as<double>(), st_);
-      read_scalars(red_.as<double>(), 5 + kLsTrials, s, st_);
+      co_await read_back(ex_, red_.as<double>(), (5 + kLsTrials) * sizeof(double), s);
       const double dKa = s[0], dKd = s[1], yd = s[2], ed = s[3], gd = s[4];
       double cj = c0;
       bool ok = false;
@@ -467,9 +449,10 @@ void Solver::ssn(double stop, kqr_info& info) {
       fprintf(stderr, "[kqr]   newton %2d |grad| %.3e (stop %.1e) pcg %3d res %.2e tol %.2e step %.3g\n", t + 1, gn,
               stop, ps.iters, ps.resnorm, tol, cstep);
   }
+  co_return Unit{};
 }
 
-void Solver::phase2(kqr_info& info) {
+Co<Unit> Solver::phase2(kqr_info& info) {
   const double t0 = now_s();
   // Subproblem accuracy: the summable tolerances of criterion (A) are taken
   // as a fraction of the previous outer residual, floored at the final target
@@ -480,17 +463,17 @@ void Solver::phase2(kqr_info& info) {
   int it = 0;
   bool done = false;
   if (k.err <= o_.tol) {  // Phase I already met the final target (ADMM run alone): confirm exactly
-    op_.apply_exact(alpha_.as<double>(), Ka_.as<double>(), st_);
-    k = update_and_kkt(beta_, sigma_, 1.0, false);
+    co_await op_.apply_exact(alpha_.as<double>(), Ka_.as<double>(), ex_);
+    k = co_await update_and_kkt(beta_, sigma_, 1.0, false);
     done = k.err <= o_.tol;
   }
   for (it = 0; !done && it < o_.alm_max_iter; ++it) {
     const double stop = scale * std::max(o_.ssn_rel * o_.tol, std::min(o_.ssn_adapt * e_prev, 1.0));
-    op_.apply_exact(alpha_.as<double>(), Ka_.as<double>(), st_);  // reset drift of the tracked K alpha
-    ssn(stop, info);
-    const double sa = sum_of(alpha_.as<double>());
+    co_await op_.apply_exact(alpha_.as<double>(), Ka_.as<double>(), ex_);  // reset drift of the tracked K alpha
+    co_await ssn(stop, info);
+    const double sa = co_await sum_of(alpha_.as<double>());
     const double beta_new = beta_ + sigma_ * sa;
-    k = update_and_kkt(beta_new, sigma_, 1.0, true);
+    k = co_await update_and_kkt(beta_new, sigma_, 1.0, true);
     beta_ = beta_new;
     record(2, it + 1, k.err);
     if (o_.verbose)
@@ -499,8 +482,8 @@ void Solver::phase2(kqr_info& info) {
     if (!std::isfinite(k.err)) fail(KQR_ENUMERIC, "non-finite residual in Phase II");
     if (k.err <= o_.tol) {
       // confirm with an exact K alpha (tracked products drift by rounding)
-      op_.apply_exact(alpha_.as<double>(), Ka_.as<double>(), st_);
-      k = update_and_kkt(beta_, sigma_, 1.0, false);
+      co_await op_.apply_exact(alpha_.as<double>(), Ka_.as<double>(), ex_);
+      k = co_await update_and_kkt(beta_, sigma_, 1.0, false);
       if (k.err <= o_.tol) { ++it; done = true; break; }
     }
     if (k.eta_d > o_.sigma_stall * eta_d_prev_) sigma_ = std::min(o_.sigma_factor * sigma_, o_.sigma_max);
@@ -510,14 +493,14 @@ void Solver::phase2(kqr_info& info) {
   info.alm_iters = it;
   converged_ = done;
   last_ = k;
-  KQR_CHECK_HIP(hipStreamSynchronize(st_));
-  info.t_alm = now_s() - t0;
+  info.t_alm = now_s() - t0;  // the last read-back drained the stream
+  co_return Unit{};
 }
 
-void Solver::finish(kqr_info& info) {
+Co<Unit> Solver::finish(kqr_info& info) {
   // final residuals with the exact operator
-  op_.apply_exact(alpha_.as<double>(), Ka_.as<double>(), st_);
-  Kkt k = update_and_kkt(beta_, sigma_, 1.0, false);
+  co_await op_.apply_exact(alpha_.as<double>(), Ka_.as<double>(), ex_);
+  Kkt k = co_await update_and_kkt(beta_, sigma_, 1.0, false);
   last_ = k;
   info.eta_p = k.eta_p;
   info.eta_d = k.eta_d;
@@ -529,8 +512,11 @@ void Solver::finish(kqr_info& info) {
   info.sigma = sigma_;
   info.trace_len = ntrace_;
   count_interior(n_, alpha_.as<double>(), tau_, ws_, red_.as<double>(), st_);
-  info.n_interior = int64_t(read_scalar(red_.as<double>(), st_));
+  double ni = 0.0;
+  co_await read_back(ex_, red_.as<double>(), sizeof(double), &ni);
+  info.n_interior = int64_t(ni);
   converged_ = converged_ && k.err <= o_.tol;
+  co_return Unit{};
 }
 
 }  // namespace kqr

@@ -2,7 +2,7 @@
 // randomly pivoted Cholesky.
 #pragma once
 
-#include "kqr_internal.h"
+#include "coro.h"
 
 namespace kqr {
 
@@ -69,11 +69,11 @@ class Woodbury {
   // Forms C = diag(I, 1/c) + U^T L^{-1} U for a general positive diagonal L,
   // factors it and forms W = Lc^{-1}.  Returns false when a pivot is not
   // positive (the factor is then unusable).
-  bool build(const double* L, double c, hipStream_t st);
+  Co<bool> build(const double* L, double c, Exec& ex);
   // Same for L = l I (Phase I), from the Gram matrix U^T U formed once.
-  bool build_scaled_identity(const double* L, double l, double c, hipStream_t st);
+  Co<bool> build_scaled_identity(const double* L, double l, double c, Exec& ex);
   // Same for the Newton systems: L_i = l_in where S_i = 1, l_out elsewhere.
-  bool build_two_level(const double* L, const uint8_t* S, double l_in, double l_out, double c, hipStream_t st);
+  Co<bool> build_two_level(const double* L, const uint8_t* S, double l_in, double l_out, double c, Exec& ex);
   // out = P^{-1} w.  When dot_with != nullptr also writes dot_with . out to *dot_out (device).
   void apply(const double* w, double* out, const double* dot_with, double* dot_out, Workspace& ws,
              hipStream_t st);
@@ -87,26 +87,25 @@ class Woodbury {
  private:
   void syrk(const double* L, const int* idx, int64_t nrows, double* G, double alpha, double beta, double diag_r,
             double diag_last, double* out, hipStream_t st);
-  bool factor(hipStream_t st);
+  Co<bool> factor(Exec& ex);
   void prepare_gram(hipStream_t st);
   const float* F_;
   int64_t n_, r_, ldf_, R1_;
   int64_t ldc_;
   const double* L_ = nullptr;
   DevBuf C_, W_, WT_, T_, G_, part_, g_, Fs_, t_, y_, s_, flag_, idx_, cnt_;
-  HostPinned hbuf_;
   int nsplit_ = 1;
 };
 
 // ----------------------------------------------------------------- RPCholesky (rpchol.hip)
 // Randomly pivoted Cholesky on K (materialised or from X).  Writes F (n x ldf
 // FP32) and returns the pivots; stops early when sum(d) <= 1e-14 tr(K).
-std::vector<int64_t> rpcholesky(const KMat& km, const float* X, const float* sqn, int64_t n, int p,
-                                KernelSpec ks, int64_t rank, const double* uniforms, float* F, int64_t ldf,
-                                hipStream_t st);
+Co<std::vector<int64_t>> rpcholesky(KMat km, const float* X, const float* sqn, int64_t n, int p,
+                                    KernelSpec ks, int64_t rank, const double* uniforms, float* F, int64_t ldf,
+                                    Exec& ex);
 // Rank heuristic of Section 3 on the r0 columns of F0: smallest r with
 // lambda_r(F0^T F0) <= xi lambda_1 (r0 when none); lambda_1 optional output.
-int64_t adaptive_rank(const float* F0, int64_t n, int64_t r0, int64_t ldf, double xi, hipStream_t st,
-                      double* lambda1_out);
+Co<int64_t> adaptive_rank(const float* F0, int64_t n, int64_t r0, int64_t ldf, double xi, Exec& ex,
+                          double* lambda1_out);
 
 }  // namespace kqr

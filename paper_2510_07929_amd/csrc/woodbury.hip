@@ -696,7 +696,7 @@ __global__ __launch_bounds__(256) void wood_out_kernel(int64_t n, int r, const d
 
 // ---------------------------------------------------------------- class
 Woodbury::Woodbury(const float* F, int64_t n, int64_t r, int64_t ldf)
-    : F_(F), n_(n), r_(r), ldf_(ldf), R1_(r + 1), hbuf_(4 * sizeof(int)) {
+    : F_(F), n_(n), r_(r), ldf_(ldf), R1_(r + 1) {
   if (R1_ > 1024) fail(KQR_EINVAL, "preconditioner rank %lld exceeds 1023", (long long)r);
   ldc_ = R1_;
   const size_t core = size_t(R1_) * ldc_ * sizeof(double);
@@ -795,18 +795,18 @@ void spd_solve(const double* W, const double* WT, int64_t ldc, int R1, const dou
   KQR_LAUNCH_CHECK();
 }
 
-bool Woodbury::factor(hipStream_t st) {
+Co<bool> Woodbury::factor(Exec& ex) {
   spd_factor_inverse(C_.as<double>(), ldc_, int(R1_), W_.as<double>(), WT_.as<double>(), T_.as<double>(),
-                     flag_.as<int>(), st);
-  KQR_CHECK_HIP(hipMemcpyAsync(hbuf_.ptr, flag_.ptr, sizeof(int), hipMemcpyDeviceToHost, st));
-  KQR_CHECK_HIP(hipStreamSynchronize(st));
-  return *hbuf_.as<int>() == 0;
+                     flag_.as<int>(), ex.st);
+  int flag = 1;
+  co_await read_back(ex, flag_.ptr, sizeof(int), &flag);
+  co_return flag == 0;
 }
 
-bool Woodbury::build(const double* L, double c, hipStream_t st) {
+Co<bool> Woodbury::build(const double* L, double c, Exec& ex) {
   L_ = L;
-  syrk(L, nullptr, n_, nullptr, 0.0, 1.0, 1.0, 1.0 / c, C_.as<double>(), st);
-  return factor(st);
+  syrk(L, nullptr, n_, nullptr, 0.0, 1.0, 1.0, 1.0 / c, C_.as<double>(), ex.st);
+  co_return co_await factor(ex);
 }
 
 void Woodbury::prepare_gram(hipStream_t st) {
@@ -815,15 +815,17 @@ void Woodbury::prepare_gram(hipStream_t st) {
   syrk(nullptr, nullptr, n_, nullptr, 0.0, 1.0, 0.0, 0.0, G_.as<double>(), st);
 }
 
-bool Woodbury::build_scaled_identity(const double* L, double l, double c, hipStream_t st) {
+Co<bool> Woodbury::build_scaled_identity(const double* L, double l, double c, Exec& ex) {
+  const hipStream_t st = ex.st;
   prepare_gram(st);
   L_ = L;
   syrk(nullptr, nullptr, 0, G_.as<double>(), 1.0 / l, 0.0, 1.0, 1.0 / c, C_.as<double>(), st);
-  return factor(st);
+  co_return co_await factor(ex);
 }
 
-bool Woodbury::build_two_level(const double* L, const uint8_t* S, double l_in, double l_out, double c,
-                               hipStream_t st) {
+Co<bool> Woodbury::build_two_level(const double* L, const uint8_t* S, double l_in, double l_out, double c,
+                                   Exec& ex) {
+  const hipStream_t st = ex.st;
   L_ = L;
   const int64_t n = n_;
   constexpr int nblk = 256;
@@ -836,12 +838,12 @@ bool Woodbury::build_two_level(const double* L, const uint8_t* S, double l_in, d
   KQR_LAUNCH_CHECK();
   flag_scan_kernel<<<1, 64, 0, st>>>(cnt_.as<int>(), nblk, cnt_.as<int>() + nblk);
   KQR_LAUNCH_CHECK();
-  KQR_CHECK_HIP(hipMemcpyAsync(hbuf_.ptr, cnt_.as<int>() + nblk, sizeof(int), hipMemcpyDeviceToHost, st));
-  KQR_CHECK_HIP(hipStreamSynchronize(st));
-  const int64_t m = *hbuf_.as<int>();
+  int m32 = 0;
+  co_await read_back(ex, cnt_.as<int>() + nblk, sizeof(int), &m32);
+  const int64_t m = m32;
   if (m > n / 2) {  // the interior is most of the data: one weighted pass is cheaper
     syrk(L, nullptr, n, nullptr, 0.0, 1.0, 1.0, 1.0 / c, C_.as<double>(), st);
-    return factor(st);
+    co_return co_await factor(ex);
   }
   prepare_gram(st);
   flag_scatter_kernel<<<nblk, 64, 0, st>>>(S, n, chunk, cnt_.as<int>(), idx_.as<int>());
@@ -849,7 +851,7 @@ bool Woodbury::build_two_level(const double* L, const uint8_t* S, double l_in, d
   // C = diag(I, 1/c) + G_all / l_out + (1/l_in - 1/l_out) U_E^T U_E
   syrk(nullptr, idx_.as<int>(), m, G_.as<double>(), 1.0 / l_out, 1.0 / l_in - 1.0 / l_out, 1.0, 1.0 / c,
        C_.as<double>(), st);
-  return factor(st);
+  co_return co_await factor(ex);
 }
 
 void Woodbury::apply(const double* w, double* out, const double* dot_with, double* dot_out, Workspace& ws,
