@@ -417,12 +417,20 @@ int kqr_fit(const float* X, const double* y, int64_t n, int64_t p, double tau, d
             int kernel, double gamma, const kqr_options* opt, double* alpha, double* beta,
             kqr_info* info, void* stream);
 
-/* kqr_fit_multi_tau: kqr_fit for ntau quantile levels taus[0..ntau-1] on the
+/* Batched fits (kqr_fit_multi_tau, kqr_fit_path, kqr_fit_batch) run every
+ * fit's PALM-KQR iteration as a coroutine: a bounded pool of host threads
+ * (min(fits, 16, host cores); environment variable KQR_BATCH_THREADS = 1..16
+ * overrides), one scheduler and one stream each, resumes the fits between
+ * their read-backs and K-apply requests.  Whenever every fit still running
+ * waits for a K-apply, one batched launch serves them all (lock-step rounds
+ * over the unfinished fits).  Results do not depend on the thread count.
+ *
+ * kqr_fit_multi_tau: kqr_fit for ntau quantile levels taus[0..ntau-1] on the
  * same (X, y, lambda, kernel, gamma), solved jointly.  K and the RPCholesky
- * factor are built once; each level runs its own PALM-KQR iteration (one host
- * thread and stream per level) and the fast K-applies of all levels still
- * running are coalesced into one K V launch on the matrix cores (V: n x up to
- * 16 columns), so one pass over K serves every level.
+ * factor are built once; each level runs its own PALM-KQR iteration and the
+ * fast K-applies of all levels still running are coalesced into one K V
+ * launch on the matrix cores (V: n x up to 16 columns), so one pass over K
+ * serves every level.
  *  alpha   device, ntau x n FP64 (row t = alpha of taus[t]);  beta host ntau;
  *  info    host ntau (may be NULL); for the coalesced applies
  *          kapply_fast_calls / t_kapply_fast count the shared launches;
@@ -438,9 +446,9 @@ int kqr_fit_multi_tau(const float* X, const double* y, int64_t n, int64_t p, con
  * K and the RPCholesky factor do not depend on lambda and are built once.
  * Every value is solved from the cold start of Algorithm 1 (each result is the
  * unique optimum for its lambda, independent of the order of lambdas); up to
- * 16 values run at once, one host thread and stream each, with their fast
- * K-applies coalesced into K V launches as in kqr_fit_multi_tau, and a thread
- * that finishes one value takes the next.
+ * 16 values run at once with their fast K-applies coalesced into K V launches
+ * as in kqr_fit_multi_tau, and a fit slot that finishes one value takes the
+ * next.
  *  alpha   device, nlam x n FP64 (row t = alpha of lambdas[t]);  beta host nlam;
  *  info    host nlam (may be NULL); status host nlam (KQR_OK or
  *          KQR_NOT_CONVERGED per value).
@@ -452,8 +460,10 @@ int kqr_fit_path(const float* X, const double* y, int64_t n, int64_t p, double t
 
 /* kqr_fit_batch: nprob independent fits (sizes n[i], common p and kernel
  * type, per-problem tau, lambda, gamma).  Each problem gets its own K and
- * preconditioner; the fast K-applies of all problems still running go out as
- * one launch whose workgroups are dealt over the (problem, row block) pairs.
+ * preconditioner (built interleaved on the batch's streams); the fast
+ * K-applies of all problems still running go out as one persistent launch
+ * whose workgroups take (problem, 32-row block) items from a device queue,
+ * largest problems first.
  *  X, y, alpha: host arrays of nprob device pointers (n[i] x p FP32, n[i] FP64,
  *  n[i] FP64); tau, lambda, gamma, n: host arrays; beta, status: host nprob;
  *  info: host nprob (may be NULL).  1 <= nprob <= 256. */

@@ -286,6 +286,7 @@ namespace {
 // Deterministic device sums read back to the host.
 struct Dots {
   Workspace ws;
+  explicit Dots(hipStream_t st) : ws(st) {}
   DevBuf dev{8 * sizeof(double)};
   // sum(a) when b is null, else a . b
   double run(int64_t n, const double* a, const double* b, hipStream_t st) {
@@ -348,7 +349,7 @@ GradOutcome adjoint_gradient(const float* X, int64_t n, int p, KernelSpec ks, do
   DevBuf S(static_cast<size_t>(n)), idx(size_t(n) * sizeof(int)), cnt(257 * sizeof(int));
   DevBuf at(size_t(n) * sizeof(double)), Ka(size_t(n) * sizeof(double));
   DevBuf part(size_t(kRedBlocks) * 2 * sizeof(double)), alpha_try(size_t(n) * sizeof(double));
-  Dots dots;
+  Dots dots(st);
   const double ynorm = std::sqrt(dots.run(n, y, y, st));
   InteriorFactor fe;
   DevBuf uE, aE;

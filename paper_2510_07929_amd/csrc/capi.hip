@@ -59,6 +59,11 @@ DeferFrees::~DeferFrees() {
   for (void* p : list_) (void)hipFree(p);
 }
 
+void DeferFrees::hand_to(std::vector<void*>& out) {
+  out.insert(out.end(), list_.begin(), list_.end());
+  list_.clear();
+}
+
 HostPinned::HostPinned(size_t b) {
   hipError_t e = hipHostMalloc(&ptr, b, hipHostMallocDefault);
   if (e != hipSuccess) {
@@ -843,7 +848,7 @@ int kqr_woodbury_apply(const float* F, int64_t n, int64_t r, int64_t ldf, double
     KQR_REQUIRE(std::isfinite(c) && c > 0.0, "c must be positive");
     ensure_device();
     hipStream_t st = static_cast<hipStream_t>(stream);
-    Workspace ws;
+    Workspace ws(st);
     Exec ex(st);
     Woodbury P(F, n, r, ldf);
     if (!run_sync(P.build(Ldiag, c, ex))) fail(KQR_ENUMERIC, "Woodbury core is not positive definite");
@@ -866,7 +871,7 @@ int kqr_pcg_solve(const float* X, int64_t n, int64_t p, int kernel, double gamma
     ensure_device();
     hipStream_t st = static_cast<hipStream_t>(stream);
     Operator op(X, n, int(p), KernelSpec{kernel, gamma}, KMat{K, k_dtype, ldk}, st);
-    Workspace ws;
+    Workspace ws(st);
     Exec ex(st);
     Pcg pcg(op, ws, n, ex);
     std::unique_ptr<Woodbury> P;
@@ -893,7 +898,7 @@ int kqr_ssn_gradient(int64_t n, double tau, double lambda, double beta, double s
                 "need positive lambda, sigma, tau1, tau2");
     ensure_device();
     hipStream_t st = static_cast<hipStream_t>(stream);
-    Workspace ws;
+    Workspace ws(st);
     DevBuf red(8 * sizeof(double));
     HostPinned h(8 * sizeof(double));
     vec_dots(n, alpha, nullptr, ws, red.as<double>(), st);
@@ -924,7 +929,7 @@ int kqr_kkt_residuals(int64_t n, double tau, double lambda, double beta, double 
                 "the multiplier step needs sigma > 0 and a finite step");
     ensure_device();
     hipStream_t st = static_cast<hipStream_t>(stream);
-    Workspace ws;
+    Workspace ws(st);
     DevBuf red(16 * sizeof(double));
     HostPinned h(16 * sizeof(double));
     vec_dots(n, y, nullptr, ws, red.as<double>(), st);  // [sum, -, ||y||^2]

@@ -7,12 +7,16 @@
 // reads synchronously and never suspends, while a batch of fits runs on ONE
 // host thread: the scheduler resumes every fit until it suspends on a read or
 // on a batched K-apply request, waits for the reads, and issues one launch
-// for all pending K-apply requests.  No worker threads, no locks.
+// for all pending K-apply requests.  A batch may be split over a few host
+// threads (one scheduler and one stream each) that meet for the batched
+// launches; the fits themselves never block a thread.
 #pragma once
 
+#include <condition_variable>
 #include <coroutine>
 #include <cstring>
 #include <exception>
+#include <mutex>
 #include <utility>
 
 #include "kqr_internal.h"
@@ -116,17 +120,57 @@ class BatchLauncher {
   virtual bool exact_ok() const { return false; }
 };
 
-// Drives a set of fit coroutines on the calling thread.  A batched launch
-// goes out when no fit can run and none waits on a read, i.e. when every
-// live fit has a K-apply request pending (lock-step over the fits that have
-// not finished).
+// Meeting point of the host threads that drive a batch (one Scheduler per
+// thread): a batched launch goes out when every thread that still has live
+// fits has handed over the K-apply requests of all its fits.  Each thread's
+// streams wait for the launch; the launch waits for the work already
+// enqueued on every requester stream.
+class Rendezvous {
+ public:
+  Rendezvous(BatchLauncher* launcher, int threads, bool profile);
+  ~Rendezvous();
+  Rendezvous(const Rendezvous&) = delete;
+  Rendezvous& operator=(const Rendezvous&) = delete;
+  // Blocks until the launch that carries these requests is enqueued.
+  // ids: the problems' batch-wide indices (BatchLauncher slots).
+  void arrive(const std::vector<hipStream_t>& streams, const std::vector<int>& ids, const std::vector<ApplyReq>& reqs);
+  void leave();  // the calling thread has no live fit left
+  bool exact_ok() const { return launcher_->exact_ok(); }
+  int64_t launches() const { return launches_; }
+  double device_seconds();  // summed time of the batched launches (profile on)
+
+ private:
+  void fire_locked();
+  hipEvent_t stream_event(hipStream_t s);
+  BatchLauncher* launcher_;
+  bool profile_;
+  std::mutex mu_;
+  std::condition_variable cv_;
+  int active_;
+  int arrived_ = 0;
+  uint64_t gen_ = 0;
+  bool failed_ = false;
+  std::vector<int> ids_;
+  std::vector<ApplyReq> reqs_;
+  std::vector<hipStream_t> streams_;
+  std::vector<std::pair<hipStream_t, hipEvent_t>> stream_ev_;
+  hipStream_t bst_ = nullptr;
+  hipEvent_t done_ = nullptr;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> spans_;
+  int64_t launches_ = 0;
+};
+
+// Drives a set of fit coroutines on the calling thread.  When no fit can run
+// and none waits on a read, every live fit has a K-apply request pending:
+// they go to the rendezvous together (lock-step over the fits that have not
+// finished).
 class Scheduler {
  public:
-  Scheduler(BatchLauncher* launcher, bool profile);
-  ~Scheduler();
-  // Runs every task to completion (tasks[i] uses slot i).  Exceptions stay
-  // in the tasks (Co::result rethrows them); a failed batched launch is
-  // thrown from here.
+  // ids[i]: batch-wide index of local slot i (nullptr rendezvous: no batching)
+  Scheduler(Rendezvous* rv, std::vector<int> ids);
+  // Runs every task to completion (tasks[i] uses slot i); leaves the
+  // rendezvous at the end.  Exceptions stay in the tasks (Co::result
+  // rethrows them); a failed batched launch is thrown from here.
   template <typename T>
   void run(std::vector<Co<T>>& tasks) {
     std::vector<std::coroutine_handle<>> tops;
@@ -136,10 +180,7 @@ class Scheduler {
   // parking (called by the awaitables)
   void park_read(int slot, std::coroutine_handle<> h, hipEvent_t ev);
   void park_apply(int slot, std::coroutine_handle<> h, hipStream_t st, ApplyReq r);
-  bool exact_ok() const { return launcher_ && launcher_->exact_ok(); }
-  bool batching() const { return launcher_ != nullptr; }
-  int64_t launches() const { return launches_; }
-  double device_seconds();  // summed time of the batched launches (profile on)
+  bool exact_ok() const { return rv_ && rv_->exact_ok(); }
 
  private:
   enum State { kRun, kRead, kApply, kDone };
@@ -151,15 +192,10 @@ class Scheduler {
     ApplyReq req;
   };
   void run_handles(const std::vector<std::coroutine_handle<>>& tops);
-  void fire();
-  BatchLauncher* launcher_;
-  bool profile_;
+  void hand_over();
+  Rendezvous* rv_;
+  std::vector<int> ids_;
   std::vector<Slot> slots_;
-  hipStream_t bst_ = nullptr;
-  hipEvent_t done_ = nullptr;
-  std::vector<hipEvent_t> stream_ev_;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> spans_;
-  int64_t launches_ = 0;
 };
 
 // co_await read_back(ex, dev, bytes, out): copies `bytes` from device memory

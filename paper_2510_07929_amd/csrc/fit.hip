@@ -1,15 +1,18 @@
 // Fit drivers.  One problem: materialise K, RPCholesky (+ the Section 3 rank
 // rule), Phase I, Phase II, final residuals.  Batches: the same driver per
-// problem as a coroutine, all of them on the calling thread under one
-// scheduler, spread over a few streams, with their fast K-applies coalesced
-// into single launches.
+// problem as a coroutine; a few host threads (one scheduler and one stream
+// each) drive all of them and meet for the batched K-apply launches.
 #include "fit.h"
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
+#include <mutex>
+#include <thread>
 
 namespace kqr {
 
@@ -252,7 +255,21 @@ class ProblemLauncher : public BatchLauncher {
 
 // ================================================================= drivers
 namespace {
-constexpr int kBatchStreams = 4;  // one per hardware queue HIP opens by default
+// Host threads of a batch (one scheduler and one stream each): launches
+// from one thread are issued one after another, and with every fit's small
+// kernels in between the batched launches the host issue rate is what
+// limits a batch of small problems, so several threads issue them.  At most
+// 16 (and the host's core count); KQR_BATCH_THREADS (1..16) overrides.
+int batch_threads(int fits) {
+  static const int limit = [] {
+    const char* e = std::getenv("KQR_BATCH_THREADS");
+    const int v = e ? std::atoi(e) : 0;
+    if (v >= 1 && v <= 16) return v;
+    const int hw = int(std::thread::hardware_concurrency());
+    return std::max(1, std::min(16, hw));
+  }();
+  return std::max(1, std::min(fits, limit));
+}
 
 struct StreamSet {
   std::vector<hipStream_t> s;
@@ -302,11 +319,36 @@ Co<Unit> guarded_fit(Operator& op, const Prepared& pr, const double* y, int64_t 
   co_return Unit{};
 }
 
+// Runs body(g) on threads g = 0 .. T-1 and waits for them.  Buffers released
+// on those threads are freed here afterwards (a free waits for the whole
+// device); the first exception a thread raised is rethrown.
+template <typename Body>
+void on_threads(int T, std::vector<void*>& deferred, Body body) {
+  std::mutex mu;
+  std::exception_ptr first;
+  std::vector<std::thread> th;
+  for (int g = 0; g < T; ++g) {
+    th.emplace_back([&, g] {
+      DeferFrees defer;
+      try {
+        body(g);
+      } catch (...) {
+        std::lock_guard<std::mutex> lk(mu);
+        if (!first) first = std::current_exception();
+      }
+      std::lock_guard<std::mutex> lk(mu);
+      defer.hand_to(deferred);
+    });
+  }
+  for (auto& t : th) t.join();
+  if (first) std::rethrow_exception(first);
+}
+
 // Writes beta, info and status of every fit; returns the first failure.
-void collect(std::vector<Slotted>& res, Scheduler& sched, bool batched, double* beta, kqr_info* info, int* status,
+void collect(std::vector<Slotted>& res, Rendezvous* rv, double* beta, kqr_info* info, int* status,
              hipStream_t st) {
-  const double tb = batched ? sched.device_seconds() : 0.0;
-  const int64_t nb = batched ? sched.launches() : 0;
+  const double tb = rv ? rv->device_seconds() : 0.0;
+  const int64_t nb = rv ? rv->launches() : 0;
   std::string first_msg;
   int first_err = KQR_OK;
   for (size_t t = 0; t < res.size(); ++t) {
@@ -318,7 +360,7 @@ void collect(std::vector<Slotted>& res, Scheduler& sched, bool batched, double* 
     } else {
       stt = res[t].out.converged ? KQR_OK : KQR_NOT_CONVERGED;
       beta[t] = res[t].out.beta;
-      if (batched) {  // fast applies were the shared batched launches (of every fit)
+      if (rv) {  // fast applies were the shared batched launches (of every fit)
         res[t].out.info.kapply_fast_calls = nb;
         res[t].out.info.t_kapply_fast = tb;
       }
@@ -328,6 +370,11 @@ void collect(std::vector<Slotted>& res, Scheduler& sched, bool batched, double* 
   }
   KQR_CHECK_HIP(hipStreamSynchronize(st));
   if (first_err != KQR_OK) fail(first_err, "%s", first_msg.c_str());
+}
+
+void free_all(std::vector<void*>& ptrs) {
+  for (void* p : ptrs) (void)hipFree(p);
+  ptrs.clear();
 }
 }  // namespace
 
@@ -343,36 +390,45 @@ void fit_levels(const float* X, const double* y, int64_t n, int p, KernelSpec ks
     Exec ex0(st);
     pr = run_sync(prepare_fit(X, n, p, ks, o, ex0));
   }
-  DeferFrees defer;  // the fits' buffers are released after the batch
-  const int nw = std::min(nlev, kKvMaxCols);
+  const int nw = std::min(nlev, kKvMaxCols);  // fits running at once (columns of one K V launch)
+  const int T = batch_threads(nw);
   const bool batched = pr.K.ptr != nullptr && nw > 1;
   std::unique_ptr<KvLauncher> launcher;
-  if (batched) launcher.reset(new KvLauncher(pr.kmat(), n));
-  Scheduler sched(launcher.get(), o.profile != 0);
-  StreamSet streams(std::min(nw, kBatchStreams));
-  KQR_CHECK_HIP(hipStreamSynchronize(st));  // K and F are ready before other streams read them
-  std::vector<std::unique_ptr<Exec>> exs;
-  for (int w = 0; w < nw; ++w) exs.emplace_back(new Exec(streams.s[size_t(w) % streams.s.size()], &sched, w));
+  std::unique_ptr<Rendezvous> rv;
+  if (batched) {
+    launcher.reset(new KvLauncher(pr.kmat(), n));
+    rv.reset(new Rendezvous(launcher.get(), T, o.profile != 0));
+  }
+  StreamSet streams(T);
   std::vector<Slotted> res(static_cast<size_t>(nlev));
-  int next = 0;
-  // worker w: takes the next level when it finishes one; the scheduler keeps
-  // it in the lock-step rounds until the queue of levels is empty
-  auto worker = [&](int w) -> Co<Unit> {
-    Exec& ex = *exs[size_t(w)];
-    for (int t = next++; t < nlev; t = next++) {
-      Operator op(X, n, p, ks, pr.kmat(), ex.st);
-      pr.attach(op);
-      op.enable_profile(o.profile != 0);
-      op.attach_batching(batched);
-      co_await guarded_fit(op, pr, y, n, taus[t], lams[t], o, alpha + int64_t(t) * n, ex, res[size_t(t)]);
-    }
-    co_return Unit{};
-  };
-  std::vector<Co<Unit>> tasks;
-  for (int w = 0; w < nw; ++w) tasks.push_back(worker(w));
-  sched.run(tasks);
-  for (auto& t : tasks) t.result();  // the workers themselves do not fail
-  collect(res, sched, batched, beta, info, status, st);
+  std::atomic<int> next{0};
+  std::vector<void*> deferred;
+  on_threads(T, deferred, [&](int g) {
+    // this thread's workers: w = g, g + T, ...; a worker takes the next
+    // level when it finishes one and stays in the lock-step rounds until the
+    // queue of levels is empty
+    std::vector<int> ws;
+    for (int w = g; w < nw; w += T) ws.push_back(w);
+    Scheduler sched(rv.get(), ws);
+    std::vector<std::unique_ptr<Exec>> exs;
+    for (size_t k = 0; k < ws.size(); ++k) exs.emplace_back(new Exec(streams.s[size_t(g)], &sched, int(k)));
+    auto worker = [&](Exec& ex) -> Co<Unit> {
+      for (int t = next++; t < nlev; t = next++) {
+        Operator op(X, n, p, ks, pr.kmat(), ex.st);
+        pr.attach(op);
+        op.enable_profile(o.profile != 0);
+        op.attach_batching(batched);
+        co_await guarded_fit(op, pr, y, n, taus[t], lams[t], o, alpha + int64_t(t) * n, ex, res[size_t(t)]);
+      }
+      co_return Unit{};
+    };
+    std::vector<Co<Unit>> tasks;
+    for (auto& e : exs) tasks.push_back(worker(*e));
+    sched.run(tasks);
+    for (auto& t : tasks) t.result();  // the workers themselves do not fail
+  });
+  free_all(deferred);
+  collect(res, rv.get(), beta, info, status, st);
 }
 
 void fit_multi_tau(const float* X, const double* y, int64_t n, int p, KernelSpec ks, const double* taus, int ntau,
@@ -396,22 +452,40 @@ void fit_batch(int nprob, const float* const* X, const double* const* y, const i
   o.trace = nullptr;  // one trace buffer cannot serve several concurrent fits
   o.trace_cap = 0;
   if (o.k_layout != 0) fail(KQR_EINVAL, "batched problems stream K in the full layout (k_layout = 0)");
-  StreamSet streams(std::min(nprob, kBatchStreams));
-  // caller's inputs are ready before other streams read them
-  KQR_CHECK_HIP(hipStreamSynchronize(st));
-  DeferFrees defer;  // buffers are released after the batch (hipFree drains the device)
-  // 1. every problem's K and preconditioner, interleaved over the streams
-  std::vector<Prepared> prs(static_cast<size_t>(nprob));
+  const int T = batch_threads(nprob);
+  StreamSet streams(T);
+  KQR_CHECK_HIP(hipStreamSynchronize(st));  // the caller's inputs are ready before other streams read them
+  // problems dealt to the threads largest first, each to the thread with the
+  // least work so far (n^2 per problem)
+  std::vector<std::vector<int>> mine(static_cast<size_t>(T));
   {
-    Scheduler prep(nullptr, false);
-    std::vector<std::unique_ptr<Exec>> exs;
-    for (int i = 0; i < nprob; ++i) exs.emplace_back(new Exec(streams.s[size_t(i) % streams.s.size()], &prep, i));
-    std::vector<Co<Prepared>> tasks;
-    for (int i = 0; i < nprob; ++i)
-      tasks.push_back(prepare_fit(X[i], n[i], p, KernelSpec{ks.kind, gamma[i]}, o, *exs[size_t(i)]));
-    prep.run(tasks);
-    for (int i = 0; i < nprob; ++i) prs[size_t(i)] = tasks[size_t(i)].result();
+    std::vector<int> order(static_cast<size_t>(nprob));
+    for (int i = 0; i < nprob; ++i) order[size_t(i)] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return n[a] > n[b]; });
+    std::vector<double> load(static_cast<size_t>(T), 0.0);
+    for (int i : order) {
+      const size_t g = size_t(std::min_element(load.begin(), load.end()) - load.begin());
+      mine[g].push_back(i);
+      load[g] += double(n[i]) * double(n[i]);
+    }
   }
+  std::vector<void*> deferred;
+  // 1. every problem's K and preconditioner
+  std::vector<Prepared> prs(static_cast<size_t>(nprob));
+  on_threads(T, deferred, [&](int g) {
+    const std::vector<int>& ids = mine[size_t(g)];
+    Scheduler sched(nullptr, ids);
+    std::vector<std::unique_ptr<Exec>> exs;
+    std::vector<Co<Prepared>> tasks;
+    for (size_t k = 0; k < ids.size(); ++k) {
+      const int i = ids[k];
+      exs.emplace_back(new Exec(streams.s[size_t(g)], &sched, int(k)));
+      tasks.push_back(prepare_fit(X[i], n[i], p, KernelSpec{ks.kind, gamma[i]}, o, *exs.back()));
+    }
+    sched.run(tasks);
+    for (size_t k = 0; k < ids.size(); ++k) prs[size_t(ids[k])] = tasks[k].result();
+  });
+  free_all(deferred);
   std::vector<KMat> kms;
   std::vector<int64_t> ns;
   bool all_mat = true;
@@ -423,25 +497,33 @@ void fit_batch(int nprob, const float* const* X, const double* const* y, const i
   // 2. the fits, their fast K-applies in one launch per round
   const bool batched = all_mat && nprob > 1;
   std::unique_ptr<ProblemLauncher> launcher;
-  if (batched) launcher.reset(new ProblemLauncher(kms, ns));
-  Scheduler sched(launcher.get(), o.profile != 0);
-  std::vector<std::unique_ptr<Exec>> exs;
-  std::vector<std::unique_ptr<Operator>> ops;
-  for (int i = 0; i < nprob; ++i) {
-    exs.emplace_back(new Exec(streams.s[size_t(i) % streams.s.size()], &sched, i));
-    ops.emplace_back(new Operator(X[i], n[i], p, KernelSpec{ks.kind, gamma[i]}, kms[size_t(i)], exs.back()->st));
-    prs[size_t(i)].attach(*ops.back());
-    ops.back()->enable_profile(o.profile != 0);
-    ops.back()->attach_batching(batched);
+  std::unique_ptr<Rendezvous> rv;
+  if (batched) {
+    launcher.reset(new ProblemLauncher(kms, ns));
+    rv.reset(new Rendezvous(launcher.get(), T, o.profile != 0));
   }
   std::vector<Slotted> res(static_cast<size_t>(nprob));
-  std::vector<Co<Unit>> tasks;
-  for (int i = 0; i < nprob; ++i)
-    tasks.push_back(guarded_fit(*ops[size_t(i)], prs[size_t(i)], y[i], n[i], tau[i], lam[i], o, alpha[i],
-                                *exs[size_t(i)], res[size_t(i)]));
-  sched.run(tasks);
-  for (auto& t : tasks) t.result();
-  collect(res, sched, batched, beta, info, status, st);
+  std::vector<std::unique_ptr<Operator>> ops(static_cast<size_t>(nprob));
+  on_threads(T, deferred, [&](int g) {
+    const std::vector<int>& ids = mine[size_t(g)];
+    Scheduler sched(rv.get(), ids);
+    std::vector<std::unique_ptr<Exec>> exs;
+    std::vector<Co<Unit>> tasks;
+    for (size_t k = 0; k < ids.size(); ++k) {
+      const int i = ids[k];
+      exs.emplace_back(new Exec(streams.s[size_t(g)], &sched, int(k)));
+      ops[size_t(i)].reset(new Operator(X[i], n[i], p, KernelSpec{ks.kind, gamma[i]}, kms[size_t(i)], exs.back()->st));
+      prs[size_t(i)].attach(*ops[size_t(i)]);
+      ops[size_t(i)]->enable_profile(o.profile != 0);
+      ops[size_t(i)]->attach_batching(batched);
+      tasks.push_back(guarded_fit(*ops[size_t(i)], prs[size_t(i)], y[i], n[i], tau[i], lam[i], o, alpha[i],
+                                  *exs.back(), res[size_t(i)]));
+    }
+    sched.run(tasks);
+    for (auto& t : tasks) t.result();
+  });
+  free_all(deferred);
+  collect(res, rv.get(), beta, info, status, st);
 }
 
 }  // namespace kqr

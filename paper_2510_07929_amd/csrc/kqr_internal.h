@@ -60,6 +60,8 @@ class DeferFrees {
   ~DeferFrees();
   DeferFrees(const DeferFrees&) = delete;
   DeferFrees& operator=(const DeferFrees&) = delete;
+  // Moves the collected pointers to out (freed by its owner instead).
+  void hand_to(std::vector<void*>& out);
 
  private:
   std::vector<void*> list_;

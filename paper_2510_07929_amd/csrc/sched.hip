@@ -1,4 +1,5 @@
-// The single-thread scheduler of batched fits (coro.h).
+// Schedulers of batched fits (coro.h): one per host thread, meeting at a
+// rendezvous for the batched K-apply launches.
 #include "coro.h"
 
 #include <algorithm>
@@ -15,23 +16,112 @@ Exec::~Exec() {
 
 void ApplyAwait::await_suspend(std::coroutine_handle<> h) const { ex->sched->park_apply(ex->slot, h, ex->st, req); }
 
-Scheduler::Scheduler(BatchLauncher* launcher, bool profile) : launcher_(launcher), profile_(profile) {
-  if (launcher_) {
-    KQR_CHECK_HIP(hipStreamCreate(&bst_));
-    KQR_CHECK_HIP(hipEventCreateWithFlags(&done_, hipEventDisableTiming));
-  }
+// ================================================================= rendezvous
+Rendezvous::Rendezvous(BatchLauncher* launcher, int threads, bool profile)
+    : launcher_(launcher), profile_(profile), active_(threads) {
+  KQR_CHECK_HIP(hipStreamCreate(&bst_));
+  KQR_CHECK_HIP(hipEventCreateWithFlags(&done_, hipEventDisableTiming));
 }
 
-Scheduler::~Scheduler() {
-  if (bst_) (void)hipStreamSynchronize(bst_);
+Rendezvous::~Rendezvous() {
+  (void)hipStreamSynchronize(bst_);
   for (auto& s : spans_) {
     (void)hipEventDestroy(s.first);
     (void)hipEventDestroy(s.second);
   }
-  for (auto& e : stream_ev_) (void)hipEventDestroy(e);
-  if (done_) (void)hipEventDestroy(done_);
-  if (bst_) (void)hipStreamDestroy(bst_);
+  for (auto& e : stream_ev_) (void)hipEventDestroy(e.second);
+  (void)hipEventDestroy(done_);
+  (void)hipStreamDestroy(bst_);
 }
+
+hipEvent_t Rendezvous::stream_event(hipStream_t s) {
+  for (auto& e : stream_ev_)
+    if (e.first == s) return e.second;
+  hipEvent_t e = nullptr;
+  KQR_CHECK_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  stream_ev_.emplace_back(s, e);
+  return e;
+}
+
+void Rendezvous::arrive(const std::vector<hipStream_t>& streams, const std::vector<int>& ids,
+                        const std::vector<ApplyReq>& reqs) {
+  std::unique_lock<std::mutex> lk(mu_);
+  if (failed_) fail(KQR_EHIP, "batched K-apply failed");
+  for (hipStream_t s : streams) {
+    // this thread's work on s so far (its fits' vectors) precedes the launch
+    KQR_CHECK_HIP(hipEventRecord(stream_event(s), s));
+    streams_.push_back(s);
+  }
+  ids_.insert(ids_.end(), ids.begin(), ids.end());
+  reqs_.insert(reqs_.end(), reqs.begin(), reqs.end());
+  ++arrived_;
+  const uint64_t my_gen = gen_;
+  if (arrived_ == active_) {
+    fire_locked();
+  } else {
+    cv_.wait(lk, [&] { return gen_ != my_gen || failed_; });
+  }
+  if (failed_) fail(KQR_EHIP, "batched K-apply failed");
+  // done_ cannot be recorded again before every thread of this round has
+  // arrived again, and this thread has not
+  for (hipStream_t s : streams) KQR_CHECK_HIP(hipStreamWaitEvent(s, done_, 0));
+}
+
+void Rendezvous::leave() {
+  std::unique_lock<std::mutex> lk(mu_);
+  --active_;
+  if (arrived_ > 0 && arrived_ == active_ && !failed_) {
+    try {
+      fire_locked();
+    } catch (...) {
+      failed_ = true;
+      cv_.notify_all();
+    }
+  }
+}
+
+void Rendezvous::fire_locked() {
+  try {
+    for (hipStream_t s : streams_) KQR_CHECK_HIP(hipStreamWaitEvent(bst_, stream_event(s), 0));
+    hipEvent_t a = nullptr, b = nullptr;
+    if (profile_) {
+      KQR_CHECK_HIP(hipEventCreate(&a));
+      KQR_CHECK_HIP(hipEventCreate(&b));
+      KQR_CHECK_HIP(hipEventRecord(a, bst_));
+    }
+    launcher_->launch(ids_, reqs_, bst_);
+    if (profile_) {
+      KQR_CHECK_HIP(hipEventRecord(b, bst_));
+      spans_.emplace_back(a, b);
+    }
+    KQR_CHECK_HIP(hipEventRecord(done_, bst_));
+  } catch (...) {
+    failed_ = true;
+    cv_.notify_all();
+    throw;
+  }
+  ids_.clear();
+  reqs_.clear();
+  streams_.clear();
+  arrived_ = 0;
+  ++launches_;
+  ++gen_;
+  cv_.notify_all();
+}
+
+double Rendezvous::device_seconds() {
+  double t = 0.0;
+  for (auto& s : spans_) {
+    KQR_CHECK_HIP(hipEventSynchronize(s.second));
+    float ms = 0.f;
+    KQR_CHECK_HIP(hipEventElapsedTime(&ms, s.first, s.second));
+    t += 1e-3 * ms;
+  }
+  return t;
+}
+
+// ================================================================= scheduler
+Scheduler::Scheduler(Rendezvous* rv, std::vector<int> ids) : rv_(rv), ids_(std::move(ids)) {}
 
 void Scheduler::park_read(int slot, std::coroutine_handle<> h, hipEvent_t ev) {
   Slot& s = slots_[size_t(slot)];
@@ -48,56 +138,30 @@ void Scheduler::park_apply(int slot, std::coroutine_handle<> h, hipStream_t st, 
   s.state = kApply;
 }
 
-double Scheduler::device_seconds() {
-  double t = 0.0;
-  for (auto& s : spans_) {
-    KQR_CHECK_HIP(hipEventSynchronize(s.second));
-    float ms = 0.f;
-    KQR_CHECK_HIP(hipEventElapsedTime(&ms, s.first, s.second));
-    t += 1e-3 * ms;
-  }
-  return t;
-}
-
-void Scheduler::fire() {
-  std::vector<int> sl;
-  std::vector<ApplyReq> rq;
-  std::vector<hipStream_t> streams;  // distinct requester streams
+void Scheduler::hand_over() {
+  std::vector<int> ids;
+  std::vector<ApplyReq> reqs;
+  std::vector<hipStream_t> streams;
   for (size_t i = 0; i < slots_.size(); ++i) {
     const Slot& s = slots_[i];
     if (s.state != kApply) continue;
-    sl.push_back(int(i));
-    rq.push_back(s.req);
+    ids.push_back(ids_[i]);
+    reqs.push_back(s.req);
     if (std::find(streams.begin(), streams.end(), s.st) == streams.end()) streams.push_back(s.st);
   }
-  while (stream_ev_.size() < streams.size()) {
-    hipEvent_t e = nullptr;
-    KQR_CHECK_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-    stream_ev_.push_back(e);
-  }
-  // the batch reads every requester's vector: wait for the work enqueued on their streams
-  for (size_t k = 0; k < streams.size(); ++k) {
-    KQR_CHECK_HIP(hipEventRecord(stream_ev_[k], streams[k]));
-    KQR_CHECK_HIP(hipStreamWaitEvent(bst_, stream_ev_[k], 0));
-  }
-  hipEvent_t a = nullptr, b = nullptr;
-  if (profile_) {
-    KQR_CHECK_HIP(hipEventCreate(&a));
-    KQR_CHECK_HIP(hipEventCreate(&b));
-    KQR_CHECK_HIP(hipEventRecord(a, bst_));
-  }
-  launcher_->launch(sl, rq, bst_);
-  if (profile_) {
-    KQR_CHECK_HIP(hipEventRecord(b, bst_));
-    spans_.emplace_back(a, b);
-  }
-  KQR_CHECK_HIP(hipEventRecord(done_, bst_));
-  for (hipStream_t st : streams) KQR_CHECK_HIP(hipStreamWaitEvent(st, done_, 0));
-  for (int i : sl) slots_[size_t(i)].state = kRun;
-  ++launches_;
+  rv_->arrive(streams, ids, reqs);
+  for (auto& s : slots_)
+    if (s.state == kApply) s.state = kRun;
 }
 
 void Scheduler::run_handles(const std::vector<std::coroutine_handle<>>& tops) {
+  if (ids_.size() != tops.size()) fail(KQR_EHIP, "internal: scheduler slots do not match its tasks");
+  struct Leave {  // the other threads must not wait for this one after it stops
+    Rendezvous* rv;
+    ~Leave() {
+      if (rv) rv->leave();
+    }
+  } leave{rv_};
   slots_.assign(tops.size(), Slot{});
   size_t live = 0;
   for (size_t i = 0; i < tops.size(); ++i) {
@@ -133,9 +197,9 @@ void Scheduler::run_handles(const std::vector<std::coroutine_handle<>>& tops) {
       }
     }
     if (!reading) {
-      // every live fit waits for a K-apply: one launch serves them all
-      if (!launcher_) fail(KQR_EHIP, "internal: K-apply request without a batch launcher");
-      fire();
+      // every live fit waits for a K-apply
+      if (!rv_) fail(KQR_EHIP, "internal: K-apply request without a batch launcher");
+      hand_over();
       continue;
     }
     if (!progressed) {

@@ -217,7 +217,7 @@ static double now_s() {
 // ================================================================= solver
 Solver::Solver(Operator& op, Exec& ex, const double* y, int64_t n, double tau, double lam, const kqr_options& o,
                const float* F, int64_t rank, int64_t ldf)
-    : op_(op), ex_(ex), y_(y), n_(n), tau_(tau), lam_(lam), o_(o), st_(ex.st), pcg_(op, ws_, n, ex),
+    : op_(op), ex_(ex), y_(y), n_(n), tau_(tau), lam_(lam), o_(o), st_(ex.st), ws_(ex.st), pcg_(op, ws_, n, ex),
       alpha_(n * sizeof(double)), v_(n * sizeof(double)), z_(n * sizeof(double)), Ka_(n * sizeof(double)),
       b_(n * sizeof(double)), L_(n * sizeof(double)), grad_(n * sizeof(double)), d_(n * sizeof(double)),
       Kd_(n * sizeof(double)), S_(n), red_(64 * sizeof(double)) {

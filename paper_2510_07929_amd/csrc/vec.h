@@ -10,11 +10,13 @@ constexpr int kKktSums = 9;    // sums produced by multiplier_kkt
 constexpr int kLsTrials = 24;  // step lengths evaluated per line-search pass
 constexpr int kMaxPartialQ = 5 + kLsTrials;
 
-// Scratch shared by the reduction kernels of one solve.
+// Scratch shared by the reduction kernels of one solve (per-block partial
+// sums).  Kernels using one Workspace must be ordered (one stream).
 struct Workspace {
   DevBuf part_buf;  // kRedBlocks * kMaxPartialQ doubles
   double* partials = nullptr;
-  Workspace() : part_buf(size_t(kRedBlocks) * kMaxPartialQ * sizeof(double)) {
+  explicit Workspace(hipStream_t st) : part_buf(size_t(kRedBlocks) * kMaxPartialQ * sizeof(double)) {
+    (void)st;
     partials = part_buf.as<double>();
   }
 };

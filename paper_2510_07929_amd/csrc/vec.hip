@@ -1,47 +1,19 @@
 // Fused O(n) vector kernels of the solver, all with deterministic reductions:
-// every kernel that produces sums writes one partial per block (fixed grid,
-// fixed per-thread order) and `reduce_finalize` adds the partials in a fixed
-// order.  Runs are bitwise reproducible.
+// every kernel that produces sums writes one partial per block (the grid
+// depends only on n, each thread sums in a fixed order); a single block
+// writes its sums directly, several are added in a fixed order by
+// `reduce_finalize`.  Runs are bitwise reproducible.
 #include "kqr_internal.h"
+#include "reduce.h"
 #include "solver.h"
+
+#include <algorithm>
 
 namespace kqr {
 
-// ----------------------------------------------------------------- block reduction
-template <int NQ>
-__device__ __forceinline__ void block_partials(double (&v)[NQ], double* __restrict__ partials) {
-  __shared__ double sh[NQ][kRedThreads / 64];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-  for (int q = 0; q < NQ; ++q) {
-    double s = v[q];
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off);
-    if (lane == 0) sh[q][wave] = s;
-  }
-  __syncthreads();
-  if (threadIdx.x < NQ) {
-    double s = 0.0;
-#pragma unroll
-    for (int w = 0; w < kRedThreads / 64; ++w) s += sh[threadIdx.x][w];
-    partials[blockIdx.x * NQ + threadIdx.x] = s;
-  }
-}
-
 __global__ __launch_bounds__(256) void finalize_kernel(const double* __restrict__ partials,
                                                        int nblocks, int nq, double* __restrict__ out) {
-  __shared__ double sh[4];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int q = 0; q < nq; ++q) {
-    double s = 0.0;
-    for (int b = threadIdx.x; b < nblocks; b += 256) s += partials[b * nq + q];
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off);
-    if (lane == 0) sh[wave] = s;
-    __syncthreads();
-    if (threadIdx.x == 0) out[q] = ((sh[0] + sh[1]) + sh[2]) + sh[3];
-    __syncthreads();
-  }
+  finish_sums(partials, nblocks, nq, out);
 }
 
 void reduce_finalize(const double* partials, int nblocks, int nq, double* out, hipStream_t st) {
@@ -52,12 +24,28 @@ void reduce_finalize(const double* partials, int nblocks, int nq, double* out, h
 #define KQR_GRID_STRIDE(i, n) \
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < (n); i += (int64_t)gridDim.x * blockDim.x)
 
-static inline dim3 red_grid() { return dim3(kRedBlocks); }
+// One workgroup up to kOneBlockN elements; beyond, one thread per element up
+// to kRedBlocks workgroups (the partial-sum capacity of a Workspace), then
+// grid-stride.
+static inline dim3 red_grid(int64_t n) {
+  if (n <= kOneBlockN) return dim3(1);
+  return dim3(unsigned(std::min<int64_t>(kRedBlocks, (n + 255) / 256)));
+}
+
+// Elementwise kernels: one thread per element up to kRedBlocks workgroups.
+static inline dim3 ew_grid(int64_t n) {
+  return dim3(unsigned(std::max<int64_t>(1, std::min<int64_t>(kRedBlocks, (n + 255) / 256))));
+}
+
+// The second pass of a reduction over the partials of a grid of g blocks.
+static inline void finish(dim3 g, const double* partials, int nq, double* out, hipStream_t st) {
+  if (g.x > 1) reduce_finalize(partials, int(g.x), nq, out, st);
+}
 
 // ----------------------------------------------------------------- generic sums
 // out partials: [sum x, sum x*y (if y), sum x*x]
 __global__ __launch_bounds__(256) void dots_kernel(int64_t n, const double* __restrict__ x,
-                                                   const double* __restrict__ y, double* partials) {
+                                                   const double* __restrict__ y, double* partials, double* out) {
   double v[3] = {0.0, 0.0, 0.0};
   KQR_GRID_STRIDE(i, n) {
     const double a = x[i];
@@ -65,13 +53,17 @@ __global__ __launch_bounds__(256) void dots_kernel(int64_t n, const double* __re
     if (y) v[1] = fma(a, y[i], v[1]);
     v[2] = fma(a, a, v[2]);
   }
-  block_partials<3>(v, partials);
+  block_sums<3>(v, partials, out);
 }
 
 void vec_dots(int64_t n, const double* x, const double* y, Workspace& ws, double* out3, hipStream_t st) {
-  dots_kernel<<<red_grid(), 256, 0, st>>>(n, x, y, ws.partials);
+  const dim3 g = red_grid(n);
+
+  dots_kernel<<<g, 256, 0, st>>>(n, x, y, ws.partials, out3);
+
   KQR_LAUNCH_CHECK();
-  reduce_finalize(ws.partials, kRedBlocks, 3, out3, st);
+
+  finish(g, ws.partials, 3, out3, st);
 }
 
 // ----------------------------------------------------------------- PCG
@@ -81,7 +73,7 @@ __global__ __launch_bounds__(256) void pcg_init_r_kernel(int64_t n, const double
                                                          const double* __restrict__ Kx,
                                                          const double* __restrict__ L, double c,
                                                          const double* __restrict__ sc, int sum_x_slot,
-                                                         double* __restrict__ r, double* partials) {
+                                                         double* __restrict__ r, double* partials, double* out) {
   const double cs = (x && sum_x_slot >= 0) ? c * sc[sum_x_slot] : 0.0;
   double v[1] = {0.0};
   KQR_GRID_STRIDE(i, n) {
@@ -90,15 +82,19 @@ __global__ __launch_bounds__(256) void pcg_init_r_kernel(int64_t n, const double
     r[i] = ri;
     v[0] = fma(ri, ri, v[0]);
   }
-  block_partials<1>(v, partials);
+  block_sums<1>(v, partials, out);
 }
 
 void pcg_init_r(int64_t n, const double* b, const double* x, const double* Kx, const double* L,
                 double c, const double* sc, int sum_x_slot, double* r, Workspace& ws, double* rr_out,
                 hipStream_t st) {
-  pcg_init_r_kernel<<<red_grid(), 256, 0, st>>>(n, b, x, Kx, L, c, sc, sum_x_slot, r, ws.partials);
+  const dim3 g = red_grid(n);
+
+  pcg_init_r_kernel<<<g, 256, 0, st>>>(n, b, x, Kx, L, c, sc, sum_x_slot, r, ws.partials, rr_out);
+
   KQR_LAUNCH_CHECK();
-  reduce_finalize(ws.partials, kRedBlocks, 1, rr_out, st);
+
+  finish(g, ws.partials, 1, rr_out, st);
 }
 
 // p = zz (+ beta p with beta = sc[rzn]/sc[rz]); p32 = float(p); partial [sum p, r.zz].
@@ -106,7 +102,7 @@ __global__ __launch_bounds__(256) void pcg_p_kernel(int64_t n, const double* __r
                                                     const double* __restrict__ r, double* __restrict__ p,
                                                     float* __restrict__ p32, const double* __restrict__ sc,
                                                     int rz_slot, int rzn_slot, int first,
-                                                    double* partials) {
+                                                    double* partials, double* out) {
   const double beta = first ? 0.0 : sc[rzn_slot] / sc[rz_slot];
   double v[1] = {0.0};
   KQR_GRID_STRIDE(i, n) {
@@ -116,15 +112,19 @@ __global__ __launch_bounds__(256) void pcg_p_kernel(int64_t n, const double* __r
     v[0] += pi;
   }
   (void)r;
-  block_partials<1>(v, partials);
+  block_sums<1>(v, partials, out);
 }
 
 void pcg_update_p(int64_t n, const double* zz, double* p, float* p32, const double* sc, int rz_slot,
                   int rzn_slot, bool first, Workspace& ws, double* sump_out, hipStream_t st) {
-  pcg_p_kernel<<<red_grid(), 256, 0, st>>>(n, zz, nullptr, p, p32, sc, rz_slot, rzn_slot, first ? 1 : 0,
-                                           ws.partials);
+  const dim3 g = red_grid(n);
+
+  pcg_p_kernel<<<g, 256, 0, st>>>(n, zz, nullptr, p, p32, sc, rz_slot, rzn_slot, first ? 1 : 0,
+                                           ws.partials, sump_out);
+
   KQR_LAUNCH_CHECK();
-  reduce_finalize(ws.partials, kRedBlocks, 1, sump_out, st);
+
+  finish(g, ws.partials, 1, sump_out, st);
 }
 
 // q = Kp + c*sum(p) + L p ; partial p.q
@@ -132,7 +132,7 @@ __global__ __launch_bounds__(256) void pcg_q_kernel(int64_t n, const double* __r
                                                     const double* __restrict__ p,
                                                     const double* __restrict__ L, double c,
                                                     const double* __restrict__ sc, int sump_slot,
-                                                    double* __restrict__ q, double* partials) {
+                                                    double* __restrict__ q, double* partials, double* out) {
   const double cs = c * sc[sump_slot];
   double v[1] = {0.0};
   KQR_GRID_STRIDE(i, n) {
@@ -141,14 +141,18 @@ __global__ __launch_bounds__(256) void pcg_q_kernel(int64_t n, const double* __r
     q[i] = qi;
     v[0] = fma(pi, qi, v[0]);
   }
-  block_partials<1>(v, partials);
+  block_sums<1>(v, partials, out);
 }
 
 void pcg_q(int64_t n, const double* Kp, const double* p, const double* L, double c, const double* sc,
            int sump_slot, double* q, Workspace& ws, double* pq_out, hipStream_t st) {
-  pcg_q_kernel<<<red_grid(), 256, 0, st>>>(n, Kp, p, L, c, sc, sump_slot, q, ws.partials);
+  const dim3 g = red_grid(n);
+
+  pcg_q_kernel<<<g, 256, 0, st>>>(n, Kp, p, L, c, sc, sump_slot, q, ws.partials, pq_out);
+
   KQR_LAUNCH_CHECK();
-  reduce_finalize(ws.partials, kRedBlocks, 1, pq_out, st);
+
+  finish(g, ws.partials, 1, pq_out, st);
 }
 
 // a = sc[rz]/sc[pq]; x += a p; r -= a q; Kx += a Kp (if Kx); partial r.r
@@ -157,7 +161,7 @@ __global__ __launch_bounds__(256) void pcg_xr_kernel(int64_t n, const double* __
                                                      const double* __restrict__ Kp, double* __restrict__ x,
                                                      double* __restrict__ r, double* __restrict__ Kx,
                                                      const double* __restrict__ sc, int rz_slot,
-                                                     int pq_slot, double* partials) {
+                                                     int pq_slot, double* partials, double* out) {
   const double a = sc[rz_slot] / sc[pq_slot];
   double v[1] = {0.0};
   KQR_GRID_STRIDE(i, n) {
@@ -167,15 +171,19 @@ __global__ __launch_bounds__(256) void pcg_xr_kernel(int64_t n, const double* __
     if (Kx) Kx[i] = fma(a, Kp[i], Kx[i]);
     v[0] = fma(ri, ri, v[0]);
   }
-  block_partials<1>(v, partials);
+  block_sums<1>(v, partials, out);
 }
 
 void pcg_xr(int64_t n, const double* p, const double* q, const double* Kp, double* x, double* r,
             double* Kx, const double* sc, int rz_slot, int pq_slot, Workspace& ws, double* rr_out,
             hipStream_t st) {
-  pcg_xr_kernel<<<red_grid(), 256, 0, st>>>(n, p, q, Kp, x, r, Kx, sc, rz_slot, pq_slot, ws.partials);
+  const dim3 g = red_grid(n);
+
+  pcg_xr_kernel<<<g, 256, 0, st>>>(n, p, q, Kp, x, r, Kx, sc, rz_slot, pq_slot, ws.partials, rr_out);
+
   KQR_LAUNCH_CHECK();
-  reduce_finalize(ws.partials, kRedBlocks, 1, rr_out, st);
+
+  finish(g, ws.partials, 1, rr_out, st);
 }
 
 // ----------------------------------------------------------------- ADMM / ALM
@@ -189,7 +197,7 @@ __global__ __launch_bounds__(256) void admm_rhs_kernel(int64_t n, const double* 
 
 void admm_rhs(int64_t n, const double* y, const double* z, const double* v, double beta, double sigma,
               double lam, double* b, hipStream_t st) {
-  admm_rhs_kernel<<<red_grid(), 256, 0, st>>>(n, y, z, v, beta, sigma, lam, b);
+  admm_rhs_kernel<<<ew_grid(n), 256, 0, st>>>(n, y, z, v, beta, sigma, lam, b);
   KQR_LAUNCH_CHECK();
 }
 
@@ -201,7 +209,7 @@ void admm_rhs(int64_t n, const double* y, const double* z, const double* v, doub
 __global__ __launch_bounds__(256) void multiplier_kkt_kernel(
     int64_t n, const double* __restrict__ alpha, const double* __restrict__ Ka,
     const double* __restrict__ y, double* __restrict__ z, double* __restrict__ v, double beta_new,
-    double sigma, double step, double tau, double lam, int update, double* partials) {
+    double sigma, double step, double tau, double lam, int update, double* partials, double* out) {
   double s[kKktSums];
 #pragma unroll
   for (int q = 0; q < kKktSums; ++q) s[q] = 0.0;
@@ -233,16 +241,20 @@ __global__ __launch_bounds__(256) void multiplier_kkt_kernel(
     s[7] = fma(y[i], a, s[7]);
     s[8] += a;
   }
-  block_partials<kKktSums>(s, partials);
+  block_sums<kKktSums>(s, partials, out);
 }
 
 void multiplier_kkt(int64_t n, const double* alpha, const double* Ka, const double* y, double* z,
                     double* v, double beta_new, double sigma, double step, double tau, double lam,
                     bool update, Workspace& ws, double* out, hipStream_t st) {
-  multiplier_kkt_kernel<<<red_grid(), 256, 0, st>>>(n, alpha, Ka, y, z, v, beta_new, sigma, step, tau,
-                                                    lam, update ? 1 : 0, ws.partials);
+  const dim3 g = red_grid(n);
+
+  multiplier_kkt_kernel<<<g, 256, 0, st>>>(n, alpha, Ka, y, z, v, beta_new, sigma, step, tau,
+                                                    lam, update ? 1 : 0, ws.partials, out);
+
   KQR_LAUNCH_CHECK();
-  reduce_finalize(ws.partials, kRedBlocks, kKktSums, out, st);
+
+  finish(g, ws.partials, kKktSums, out, st);
 }
 
 // ----------------------------------------------------------------- SSN (Algorithm 3)
@@ -254,7 +266,7 @@ __global__ __launch_bounds__(256) void ssn_grad_kernel(int64_t n, const double* 
                                                        const double* __restrict__ z, double beta,
                                                        double sigma, double sum_alpha, double tau,
                                                        double lam, double* __restrict__ grad,
-                                                       uint8_t* __restrict__ S, double* partials) {
+                                                       uint8_t* __restrict__ S, double* partials, double* out) {
   const double lo = tau - 1.0, hi = tau;
   const double base = beta + sigma * sum_alpha;
   const double inv_lam = 1.0 / lam;
@@ -267,16 +279,20 @@ __global__ __launch_bounds__(256) void ssn_grad_kernel(int64_t n, const double* 
     S[i] = (w > lo && w < hi) ? 1 : 0;
     v[0] = fma(g, g, v[0]);
   }
-  block_partials<1>(v, partials);
+  block_sums<1>(v, partials, out);
 }
 
 void ssn_grad(int64_t n, const double* alpha, const double* Ka, const double* y, const double* z,
               double beta, double sigma, double sum_alpha, double tau, double lam, double* grad,
               uint8_t* S, Workspace& ws, double* gg_out, hipStream_t st) {
-  ssn_grad_kernel<<<red_grid(), 256, 0, st>>>(n, alpha, Ka, y, z, beta, sigma, sum_alpha, tau, lam, grad,
-                                              S, ws.partials);
+  const dim3 g = red_grid(n);
+
+  ssn_grad_kernel<<<g, 256, 0, st>>>(n, alpha, Ka, y, z, beta, sigma, sum_alpha, tau, lam, grad,
+                                              S, ws.partials, gg_out);
+
   KQR_LAUNCH_CHECK();
-  reduce_finalize(ws.partials, kRedBlocks, 1, gg_out, st);
+
+  finish(g, ws.partials, 1, gg_out, st);
 }
 
 // L = lam sigma (1 - S) + lam eps_t ; rhs = -lam grad
@@ -293,7 +309,7 @@ __global__ __launch_bounds__(256) void ssn_system_kernel(int64_t n, const uint8_
 
 void ssn_system(int64_t n, const uint8_t* S, const double* grad, double lam, double sigma, double eps_t,
                 double* L, double* rhs, hipStream_t st) {
-  ssn_system_kernel<<<red_grid(), 256, 0, st>>>(n, S, grad, lam, sigma, eps_t, L, rhs);
+  ssn_system_kernel<<<ew_grid(n), 256, 0, st>>>(n, S, grad, lam, sigma, eps_t, L, rhs);
   KQR_LAUNCH_CHECK();
 }
 
@@ -304,7 +320,7 @@ __global__ __launch_bounds__(256) void line_search_kernel(
     int64_t n, const double* __restrict__ alpha, const double* __restrict__ z,
     const double* __restrict__ d, const double* __restrict__ Ka, const double* __restrict__ Kd,
     const double* __restrict__ y, const double* __restrict__ grad, double sigma, double tau,
-    double c0, double shrink, double* partials) {
+    double c0, double shrink, double* partials, double* out) {
   double s[5 + kLsTrials];
 #pragma unroll
   for (int q = 0; q < 5 + kLsTrials; ++q) s[q] = 0.0;
@@ -327,16 +343,20 @@ __global__ __launch_bounds__(256) void line_search_kernel(
       c *= shrink;
     }
   }
-  block_partials<5 + kLsTrials>(s, partials);
+  block_sums<5 + kLsTrials>(s, partials, out);
 }
 
 void line_search_sums(int64_t n, const double* alpha, const double* z, const double* d, const double* Ka,
                       const double* Kd, const double* y, const double* grad, double sigma, double tau,
                       double c0, double shrink, Workspace& ws, double* out, hipStream_t st) {
-  line_search_kernel<<<red_grid(), 256, 0, st>>>(n, alpha, z, d, Ka, Kd, y, grad, sigma, tau, c0, shrink,
-                                                 ws.partials);
+  const dim3 g = red_grid(n);
+
+  line_search_kernel<<<g, 256, 0, st>>>(n, alpha, z, d, Ka, Kd, y, grad, sigma, tau, c0, shrink,
+                                                 ws.partials, out);
+
   KQR_LAUNCH_CHECK();
-  reduce_finalize(ws.partials, kRedBlocks, 5 + kLsTrials, out, st);
+
+  finish(g, ws.partials, 5 + kLsTrials, out, st);
 }
 
 // x += c d ; Kx += c Kd
@@ -350,24 +370,28 @@ __global__ __launch_bounds__(256) void axpy2_kernel(int64_t n, double c, const d
 }
 
 void axpy2(int64_t n, double c, const double* d, double* x, const double* Kd, double* Kx, hipStream_t st) {
-  axpy2_kernel<<<red_grid(), 256, 0, st>>>(n, c, d, x, Kd, Kx);
+  axpy2_kernel<<<ew_grid(n), 256, 0, st>>>(n, c, d, x, Kd, Kx);
   KQR_LAUNCH_CHECK();
 }
 
 // Non-finite check: partial [count of non-finite entries]
 __global__ __launch_bounds__(256) void nonfinite_kernel(int64_t n, const double* __restrict__ x,
-                                                        double* partials) {
+                                                        double* partials, double* out) {
   double v[1] = {0.0};
   KQR_GRID_STRIDE(i, n) {
     if (!isfinite(x[i])) v[0] += 1.0;
   }
-  block_partials<1>(v, partials);
+  block_sums<1>(v, partials, out);
 }
 
 void count_nonfinite(int64_t n, const double* x, Workspace& ws, double* out, hipStream_t st) {
-  nonfinite_kernel<<<red_grid(), 256, 0, st>>>(n, x, ws.partials);
+  const dim3 g = red_grid(n);
+
+  nonfinite_kernel<<<g, 256, 0, st>>>(n, x, ws.partials, out);
+
   KQR_LAUNCH_CHECK();
-  reduce_finalize(ws.partials, kRedBlocks, 1, out, st);
+
+  finish(g, ws.partials, 1, out, st);
 }
 
 __global__ void fill_kernel(int64_t n, double val, double* __restrict__ x) {
@@ -375,7 +399,7 @@ __global__ void fill_kernel(int64_t n, double val, double* __restrict__ x) {
 }
 
 void fill(int64_t n, double val, double* x, hipStream_t st) {
-  fill_kernel<<<red_grid(), 256, 0, st>>>(n, val, x);
+  fill_kernel<<<ew_grid(n), 256, 0, st>>>(n, val, x);
   KQR_LAUNCH_CHECK();
 }
 
@@ -384,24 +408,28 @@ __global__ void copy_kernel(int64_t n, const double* __restrict__ s, double* __r
 }
 
 void copy(int64_t n, const double* src, double* dst, hipStream_t st) {
-  copy_kernel<<<red_grid(), 256, 0, st>>>(n, src, dst);
+  copy_kernel<<<ew_grid(n), 256, 0, st>>>(n, src, dst);
   KQR_LAUNCH_CHECK();
 }
 
 // count of tau-1 < alpha_i < tau : partial
 __global__ __launch_bounds__(256) void interior_kernel(int64_t n, const double* __restrict__ a, double tau,
-                                                       double* partials) {
+                                                       double* partials, double* out) {
   double v[1] = {0.0};
   KQR_GRID_STRIDE(i, n) {
     if (a[i] > tau - 1.0 && a[i] < tau) v[0] += 1.0;
   }
-  block_partials<1>(v, partials);
+  block_sums<1>(v, partials, out);
 }
 
 void count_interior(int64_t n, const double* a, double tau, Workspace& ws, double* out, hipStream_t st) {
-  interior_kernel<<<red_grid(), 256, 0, st>>>(n, a, tau, ws.partials);
+  const dim3 g = red_grid(n);
+
+  interior_kernel<<<g, 256, 0, st>>>(n, a, tau, ws.partials, out);
+
   KQR_LAUNCH_CHECK();
-  reduce_finalize(ws.partials, kRedBlocks, 1, out, st);
+
+  finish(g, ws.partials, 1, out, st);
 }
 
 }  // namespace kqr
@@ -409,19 +437,23 @@ void count_interior(int64_t n, const double* a, double tau, Workspace& ws, doubl
 namespace kqr {
 // dst = src ; partial src . dst
 __global__ __launch_bounds__(256) void copy_dot_kernel(int64_t n, const double* __restrict__ s,
-                                                       double* __restrict__ d, double* partials) {
+                                                       double* __restrict__ d, double* partials, double* out) {
   double v[1] = {0.0};
   KQR_GRID_STRIDE(i, n) {
     const double a = s[i];
     d[i] = a;
     v[0] = fma(a, a, v[0]);
   }
-  block_partials<1>(v, partials);
+  block_sums<1>(v, partials, out);
 }
 
 void copy_dot(int64_t n, const double* src, double* dst, Workspace& ws, double* out, hipStream_t st) {
-  copy_dot_kernel<<<red_grid(), 256, 0, st>>>(n, src, dst, ws.partials);
+  const dim3 g = red_grid(n);
+
+  copy_dot_kernel<<<g, 256, 0, st>>>(n, src, dst, ws.partials, out);
+
   KQR_LAUNCH_CHECK();
-  reduce_finalize(ws.partials, kRedBlocks, 1, out, st);
+
+  finish(g, ws.partials, 1, out, st);
 }
 }  // namespace kqr

@@ -17,6 +17,7 @@
 //    over many workgroups instead of sequential substitutions, and
 //    s = W^T (W t) stays a symmetric positive definite map.
 //  * U s uses a skinny streamed mat-vec with F as the matrix.
+#include "reduce.h"
 #include "vec.h"
 
 #include <algorithm>
@@ -670,28 +671,54 @@ __global__ __launch_bounds__(256) void trmv_kernel(const double* __restrict__ M,
   if (lane == 0) out[row] = s;
 }
 
-// out_i = g_i - (Fs_i + s_r) / L_i ; optional partial dot_with . out
+// Small cores (R1 <= kFusedCore): t = sum of the wood_gt partials, then
+// s = C^{-1} t = W^T (W t), in one workgroup (t and y = W t in LDS).
+constexpr int kFusedCore = 128;
+__global__ __launch_bounds__(256) void core_solve_kernel(const double* __restrict__ part, int nblk, int R1,
+                                                         const double* __restrict__ W, const double* __restrict__ WT,
+                                                         int64_t ldc, double* __restrict__ s) {
+  __shared__ double red[256];
+  __shared__ double t[kFusedCore], y[kFusedCore];
+  const int a = threadIdx.x & (kFusedCore - 1), h = threadIdx.x / kFusedCore;
+  double acc = 0.0;
+  if (a < R1)
+    for (int b = h; b < nblk; b += 2) acc += part[int64_t(b) * R1 + a];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  const int i = threadIdx.x;
+  if (i < R1) t[i] = red[i] + red[i + kFusedCore];
+  __syncthreads();
+  if (i < R1) {
+    const double* w = W + int64_t(i) * ldc;
+    double sum = 0.0;
+    for (int k = 0; k <= i; ++k) sum = fma(w[k], t[k], sum);
+    y[i] = sum;
+  }
+  __syncthreads();
+  if (i < R1) {
+    const double* w = WT + int64_t(i) * ldc;
+    double sum = 0.0;
+    for (int k = i; k < R1; ++k) sum = fma(w[k], y[k], sum);
+    s[i] = sum;
+  }
+}
+
+// out_i = g_i - (Fs_i + s_r) / L_i ; with dot_with, the sum of dot_with . out
+// (one workgroup up to kOneBlockN rows, else partials for reduce_finalize)
 __global__ __launch_bounds__(256) void wood_out_kernel(int64_t n, int r, const double* __restrict__ L,
                                                        const double* __restrict__ g, const double* __restrict__ Fs,
                                                        const double* __restrict__ s, double* __restrict__ out,
                                                        const double* __restrict__ dot_with,
-                                                       double* __restrict__ partials) {
-  __shared__ double sh[4];
+                                                       double* __restrict__ partials, double* __restrict__ dot_out) {
   const double sr = s[r];
-  double acc = 0.0;
+  double acc[1] = {0.0};
   for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) {
     const double fs = r > 0 ? Fs[i] : 0.0;
     const double o = g[i] - (fs + sr) / L[i];
     out[i] = o;
-    if (dot_with) acc = fma(o, dot_with[i], acc);
+    if (dot_with) acc[0] = fma(o, dot_with[i], acc[0]);
   }
-  if (partials) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off);
-    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
-    __syncthreads();
-    if (threadIdx.x == 0) partials[blockIdx.x] = ((sh[0] + sh[1]) + sh[2]) + sh[3];
-  }
+  if (dot_with) block_sums<1>(acc, partials, dot_out);
 }
 
 // ---------------------------------------------------------------- class
@@ -854,29 +881,40 @@ Co<bool> Woodbury::build_two_level(const double* L, const uint8_t* S, double l_i
   co_return co_await factor(ex);
 }
 
+// Workgroups of the row passes over F: 64 rows each, at most kGtBlocks.
+static int row_blocks(int64_t n) { return int(std::max<int64_t>(1, std::min<int64_t>(kGtBlocks, (n + 63) / 64))); }
+
 void Woodbury::apply(const double* w, double* out, const double* dot_with, double* dot_out, Workspace& ws,
                      hipStream_t st) {
   const int R1 = int(R1_);
-  const int64_t chunk = (n_ + kGtBlocks - 1) / kGtBlocks;
+  const int nblk = row_blocks(n_);
+  const int64_t chunk = (n_ + nblk - 1) / nblk;
   switch ((R1 + 255) / 256) {
-    case 1: wood_gt_kernel<1><<<kGtBlocks, 256, 0, st>>>(F_, n_, int(r_), ldf_, R1, L_, w, g_.as<double>(), chunk,
-                                                         part_.as<double>()); break;
-    case 2: wood_gt_kernel<2><<<kGtBlocks, 256, 0, st>>>(F_, n_, int(r_), ldf_, R1, L_, w, g_.as<double>(), chunk,
-                                                         part_.as<double>()); break;
-    case 3: wood_gt_kernel<3><<<kGtBlocks, 256, 0, st>>>(F_, n_, int(r_), ldf_, R1, L_, w, g_.as<double>(), chunk,
-                                                         part_.as<double>()); break;
-    default: wood_gt_kernel<4><<<kGtBlocks, 256, 0, st>>>(F_, n_, int(r_), ldf_, R1, L_, w, g_.as<double>(), chunk,
-                                                          part_.as<double>()); break;
+    case 1: wood_gt_kernel<1><<<nblk, 256, 0, st>>>(F_, n_, int(r_), ldf_, R1, L_, w, g_.as<double>(), chunk,
+                                                    part_.as<double>()); break;
+    case 2: wood_gt_kernel<2><<<nblk, 256, 0, st>>>(F_, n_, int(r_), ldf_, R1, L_, w, g_.as<double>(), chunk,
+                                                    part_.as<double>()); break;
+    case 3: wood_gt_kernel<3><<<nblk, 256, 0, st>>>(F_, n_, int(r_), ldf_, R1, L_, w, g_.as<double>(), chunk,
+                                                    part_.as<double>()); break;
+    default: wood_gt_kernel<4><<<nblk, 256, 0, st>>>(F_, n_, int(r_), ldf_, R1, L_, w, g_.as<double>(), chunk,
+                                                     part_.as<double>()); break;
   }
   KQR_LAUNCH_CHECK();
-  wood_treduce_kernel<<<(R1 + 63) / 64, 1024, 0, st>>>(part_.as<double>(), kGtBlocks, R1, t_.as<double>());
-  KQR_LAUNCH_CHECK();
-  spd_solve(W_.as<double>(), WT_.as<double>(), ldc_, R1, t_.as<double>(), y_.as<double>(), s_.as<double>(), st);
+  if (R1 <= kFusedCore) {
+    core_solve_kernel<<<1, 256, 0, st>>>(part_.as<double>(), nblk, R1, W_.as<double>(), WT_.as<double>(), ldc_,
+                                         s_.as<double>());
+    KQR_LAUNCH_CHECK();
+  } else {
+    wood_treduce_kernel<<<(R1 + 63) / 64, 1024, 0, st>>>(part_.as<double>(), nblk, R1, t_.as<double>());
+    KQR_LAUNCH_CHECK();
+    spd_solve(W_.as<double>(), WT_.as<double>(), ldc_, R1, t_.as<double>(), y_.as<double>(), s_.as<double>(), st);
+  }
   if (r_ > 0) gemv_skinny(F_, ldf_, n_, r_, s_.as<double>(), Fs_.as<double>(), st);
-  wood_out_kernel<<<kRedBlocks, 256, 0, st>>>(n_, int(r_), L_, g_.as<double>(), Fs_.as<double>(), s_.as<double>(),
-                                              out, dot_with, dot_with ? ws.partials : nullptr);
+  const unsigned grid = n_ <= kOneBlockN ? 1u : unsigned(std::min<int64_t>(kRedBlocks, (n_ + 255) / 256));
+  wood_out_kernel<<<grid, 256, 0, st>>>(n_, int(r_), L_, g_.as<double>(), Fs_.as<double>(), s_.as<double>(), out,
+                                        dot_with, ws.partials, dot_out);
   KQR_LAUNCH_CHECK();
-  if (dot_with) reduce_finalize(ws.partials, kRedBlocks, 1, dot_out, st);
+  if (dot_with && grid > 1) reduce_finalize(ws.partials, int(grid), 1, dot_out, st);
 }
 
 }  // namespace kqr

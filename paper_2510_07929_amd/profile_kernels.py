@@ -6,6 +6,10 @@
         apply K(X, X) v, fast and exact, for the RBF at n = 150,000, p = 30
         (BF16x3 Gram), the RBF at n = 100,000, p = 8 (FP32 Gram) and the
         Laplacian at n = 300,000, p = 30 (fixed point);
+    python -m paper_2510_07929_amd.profile_kernels batch
+        one warm-up and one timed batched fit of the 64 uneven problems
+        (n_i in [500, 8000], p = 10), then the same problems one at a time;
+        prints the wall times;
     python -m paper_2510_07929_amd.profile_kernels summarize --pmc DIR [DIR ...] --out FILE.md
         reads the counter CSVs of rocprofv3 --pmc runs of `run` and writes a
         per-kernel table (averages over its dispatches).
@@ -52,6 +56,33 @@ def run() -> None:
     print("[profile] done", flush=True)
 
 
+def batch() -> None:
+    import time
+
+    import torch
+
+    from paper_2510_07929_amd import inputs, kqr
+
+    dev = torch.device("cuda:0")
+    probs = inputs.uneven_batch()
+    Xs = [torch.from_numpy(p.X).to(dev) for p in probs]
+    ys = [torch.from_numpy(p.y).to(dev) for p in probs]
+    args = ([p.tau for p in probs], [p.lam for p in probs], [p.gamma for p in probs], "rbf")
+    opts = dict(rank=0, kmode=kqr.KQR_KMODE_MATERIALIZE)
+    for label in ("warm-up", "timed"):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, _, infos, sts = kqr.kqr_fit_batch(Xs, ys, *args, **opts)
+        torch.cuda.synchronize()
+        print(f"[profile] batch {label}: {time.perf_counter() - t0:.3f} s, "
+              f"{sum(1 for s in sts if s == 0)}/{len(sts)} converged", flush=True)
+    t0 = time.perf_counter()
+    for i in range(len(probs)):
+        kqr.kqr_fit(Xs[i], ys[i], args[0][i], args[1][i], "rbf", args[2][i], **opts)
+    torch.cuda.synchronize()
+    print(f"[profile] one at a time: {time.perf_counter() - t0:.3f} s", flush=True)
+
+
 def summarize(dirs, out: str, cmd: str) -> None:
     agg = collections.defaultdict(lambda: collections.defaultdict(list))
     meta = {}
@@ -84,6 +115,7 @@ def main() -> None:
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
     sub.add_parser("run")
+    sub.add_parser("batch")
     s = sub.add_parser("summarize")
     s.add_argument("--pmc", nargs="+", required=True)
     s.add_argument("--out", required=True)
@@ -91,6 +123,8 @@ def main() -> None:
     a = ap.parse_args()
     if a.cmd == "run":
         run()
+    elif a.cmd == "batch":
+        batch()
     else:
         summarize(a.pmc, a.out, a.command)
 
