@@ -880,6 +880,9 @@ def bench_certify(args):
     dev = torch.device("cuda:0")
     lines = []
 
+    def progress(done, rows):  # the FP64 passes take minutes at these sizes
+        print(f"[certify] FP64 kernel products: {done}/{rows} rows", file=sys.stderr, flush=True)
+
     def apply_errors(prob, modes):
         """||u - K v|| / ||K v|| of one GPU K-apply per mode; K v in FP64 on the host."""
         v = np.random.default_rng(17).standard_normal(prob.n)
@@ -917,7 +920,7 @@ def bench_certify(args):
         v, us = apply_errors(prob, modes)
         t0 = time.perf_counter()
         c = certify.certificate(prob.X, prob.y, prob.tau, prob.lam, prob.kernel, prob.gamma, it["alpha"], beta,
-                                v=it["v"], z=it["z"], extra=v)
+                                v=it["v"], z=it["z"], extra=v, progress=progress)
         kv = c["K_extra"][:, 0]
         row.update(eta_kkt_fp64=c["eta_kkt"], eta_gap_fp64=c["eta_gap"], eta_p_fp64=c["eta_p"],
                    eta_d_fp64=c["eta_d"], eta_c_fp64=c["eta_c"], rel_obj_err_bound=c["rel_obj_err_bound"],
@@ -953,7 +956,8 @@ def bench_certify(args):
     del X, y
     torch.cuda.empty_cache()
     t0 = time.perf_counter()
-    cs = certify.certificate_levels(c3.X, c3.y, taus, c3.lam, c3.kernel, c3.gamma, list(A), list(betas))
+    cs = certify.certificate_levels(c3.X, c3.y, taus, c3.lam, c3.kernel, c3.gamma, list(A), list(betas),
+                                    progress=progress)
     lines.append(dict(workload="c3a", label="nine levels jointly (FP32 K, K V)", t_fit_s=round(t_fit, 3),
                       status=sts, t_certificate_s=round(time.perf_counter() - t0, 1),
                       levels=[dict(tau=c["tau"], gpu_eta_kkt=i["eta_kkt"], gpu_eta_gap=i["eta_gap"],

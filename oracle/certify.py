@@ -54,8 +54,11 @@ def _lib():
     return _LIB
 
 
-def kernel_apply(X, V, kind: str, gamma: float, Xrows=None) -> np.ndarray:
-    """U = K(Xrows, X) V in FP64 (Xrows defaults to X); V (n,) or (n, m), m <= 16."""
+def kernel_apply(X, V, kind: str, gamma: float, Xrows=None, progress=None) -> np.ndarray:
+    """U = K(Xrows, X) V in FP64 (Xrows defaults to X); V (n,) or (n, m), m <= 16.
+
+    ``progress(rows_done, rows)``, when given, is called after each of 16 row
+    chunks (every row is an independent sum, so chunking changes nothing)."""
     kid = {"rbf": 0, "laplacian": 1}[kind]
     X = np.ascontiguousarray(X, dtype=np.float64)
     Xr = X if Xrows is None else np.ascontiguousarray(Xrows, dtype=np.float64)
@@ -65,11 +68,16 @@ def kernel_apply(X, V, kind: str, gamma: float, Xrows=None) -> np.ndarray:
     n, p = X.shape
     if V2.shape[0] != n or Xr.shape[1] != p or V2.shape[1] > 16:
         raise ValueError("shapes do not match")
-    U = np.empty((Xr.shape[0], V2.shape[1]))
-    rc = _lib().kqr_oracle_kernel_apply(X.ctypes.data, n, p, Xr.ctypes.data, Xr.shape[0], kid, float(gamma),
-                                       V2.ctypes.data, V2.shape[1], U.ctypes.data)
-    if rc != 0:
-        raise ValueError("kqr_oracle_kernel_apply rejected its arguments")
+    m = Xr.shape[0]
+    U = np.empty((m, V2.shape[1]))
+    bounds = np.linspace(0, m, 17 if progress else 2).astype(np.int64)
+    for r0, r1 in zip(bounds[:-1], bounds[1:]):
+        rc = _lib().kqr_oracle_kernel_apply(X.ctypes.data, n, p, Xr[r0:r1].ctypes.data, int(r1 - r0), kid,
+                                           float(gamma), V2.ctypes.data, V2.shape[1], U[r0:r1].ctypes.data)
+        if rc != 0:
+            raise ValueError("kqr_oracle_kernel_apply rejected its arguments")
+        if progress:
+            progress(int(r1), m)
     return U[:, 0] if vec else U
 
 
@@ -88,7 +96,7 @@ def project_feasible(alpha, tau: float, iters: int = 200):
 
 
 def certificate(X, y, tau: float, lam: float, kind: str, gamma: float, alpha, beta: float, v=None, z=None,
-                extra=None) -> dict:
+                extra=None, progress=None) -> dict:
     """Section 4 measures and the duality sandwich of (alpha, beta), FP64.
 
     With ``v`` and ``z`` (the iterate an algorithm returned with alpha and
@@ -104,7 +112,7 @@ def certificate(X, y, tau: float, lam: float, kind: str, gamma: float, alpha, be
     if extra is not None:
         e = np.asarray(extra, dtype=np.float64)
         cols += [e] if e.ndim == 1 else [e[:, j] for j in range(e.shape[1])]
-    KV = kernel_apply(X, np.stack(cols, axis=1), kind, gamma)
+    KV = kernel_apply(X, np.stack(cols, axis=1), kind, gamma, progress=progress)
     Ka, Kat = KV[:, 0], KV[:, 1]
     zr = y - beta - Ka / lam
     res = problem.kkt(alpha, problem.proj_box(alpha, tau), beta, zr, Ka, y, lam, tau)
@@ -135,7 +143,7 @@ def certificate(X, y, tau: float, lam: float, kind: str, gamma: float, alpha, be
     return out
 
 
-def certificate_levels(X, y, taus, lam: float, kind: str, gamma: float, alphas, betas) -> list:
+def certificate_levels(X, y, taus, lam: float, kind: str, gamma: float, alphas, betas, progress=None) -> list:
     """certificate() for several quantile levels on one (X, y, lambda): the K
     alpha of every level in one pass of FP64 products, the K alpha~ in a
     second (at most 16 levels).  Measures in the residual form only."""
@@ -144,8 +152,8 @@ def certificate_levels(X, y, taus, lam: float, kind: str, gamma: float, alphas, 
         raise ValueError("at most 16 levels")
     y = np.asarray(y, dtype=np.float64)
     ats = [project_feasible(a, t) for a, t in zip(alphas, taus)]
-    KA = kernel_apply(X, np.stack(alphas, axis=1), kind, gamma)
-    KT = kernel_apply(X, np.stack(ats, axis=1), kind, gamma)
+    KA = kernel_apply(X, np.stack(alphas, axis=1), kind, gamma, progress=progress)
+    KT = kernel_apply(X, np.stack(ats, axis=1), kind, gamma, progress=progress)
     out = []
     for j, (a, at, t, b) in enumerate(zip(alphas, ats, taus, betas)):
         Ka, Kat = KA[:, j], KT[:, j]

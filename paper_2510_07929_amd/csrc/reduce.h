@@ -23,19 +23,22 @@ __device__ __forceinline__ void finish_sums(const double* __restrict__ partials,
   }
 }
 
-// Vectors up to this length are reduced by a single workgroup (no second
-// pass); longer ones by up to kRedBlocks workgroups whose partials a
-// finishing launch adds.  Workgroups never wait for one another: on a GPU
-// whose L2 is split over several dies, making one workgroup's writes visible
-// to another inside a kernel costs an L2 write-back per workgroup.
-constexpr int64_t kOneBlockN = 8192;
+// Vectors up to this length are reduced by a single workgroup of
+// kOneBlockThreads threads (no second pass); longer ones by up to kRedBlocks
+// workgroups of kRedThreads whose partials a finishing launch adds.
+// Workgroups never wait for one another: on a GPU whose L2 is split over
+// several dies, making one workgroup's writes visible to another inside a
+// kernel costs an L2 write-back per workgroup.
+constexpr int64_t kOneBlockN = 16384;
+constexpr int kOneBlockThreads = 1024;
 
-// Block partials; with a single workgroup they are the result and go to out
-// directly, otherwise reduce_finalize adds them afterwards.
+// Block partials (any block size up to 1024); with a single workgroup they
+// are the result and go to out directly, otherwise reduce_finalize adds them
+// afterwards.
 template <int NQ>
 __device__ __forceinline__ void block_sums(double (&v)[NQ], double* __restrict__ partials, double* __restrict__ out) {
-  __shared__ double sh[NQ][kRedThreads / 64];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __shared__ double sh[NQ][16];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = int(blockDim.x) >> 6;
 #pragma unroll
   for (int q = 0; q < NQ; ++q) {
     double s = v[q];
@@ -46,11 +49,22 @@ __device__ __forceinline__ void block_sums(double (&v)[NQ], double* __restrict__
   __syncthreads();
   if (threadIdx.x < NQ) {
     double s = 0.0;
-#pragma unroll
-    for (int w = 0; w < kRedThreads / 64; ++w) s += sh[threadIdx.x][w];
+    for (int w = 0; w < nw; ++w) s += sh[threadIdx.x][w];
     if (gridDim.x == 1) out[threadIdx.x] = s;
     else partials[blockIdx.x * NQ + threadIdx.x] = s;
   }
+}
+
+// Launch shape of an O(n) reduction: one workgroup of kOneBlockThreads up
+// to kOneBlockN elements, else one kRedThreads-thread workgroup per
+// kRedThreads elements up to kRedBlocks (grid-stride beyond).
+struct RedShape {
+  unsigned blocks, threads;
+};
+inline RedShape red_shape(int64_t n) {
+  if (n <= kOneBlockN) return RedShape{1u, unsigned(kOneBlockThreads)};
+  const int64_t b = (n + kRedThreads - 1) / kRedThreads;
+  return RedShape{unsigned(b < kRedBlocks ? b : kRedBlocks), unsigned(kRedThreads)};
 }
 
 }  // namespace kqr

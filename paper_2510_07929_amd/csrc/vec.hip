@@ -24,27 +24,19 @@ void reduce_finalize(const double* partials, int nblocks, int nq, double* out, h
 #define KQR_GRID_STRIDE(i, n) \
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < (n); i += (int64_t)gridDim.x * blockDim.x)
 
-// One workgroup up to kOneBlockN elements; beyond, one thread per element up
-// to kRedBlocks workgroups (the partial-sum capacity of a Workspace), then
-// grid-stride.
-static inline dim3 red_grid(int64_t n) {
-  if (n <= kOneBlockN) return dim3(1);
-  return dim3(unsigned(std::min<int64_t>(kRedBlocks, (n + 255) / 256)));
-}
-
 // Elementwise kernels: one thread per element up to kRedBlocks workgroups.
 static inline dim3 ew_grid(int64_t n) {
   return dim3(unsigned(std::max<int64_t>(1, std::min<int64_t>(kRedBlocks, (n + 255) / 256))));
 }
 
 // The second pass of a reduction over the partials of a grid of g blocks.
-static inline void finish(dim3 g, const double* partials, int nq, double* out, hipStream_t st) {
-  if (g.x > 1) reduce_finalize(partials, int(g.x), nq, out, st);
+static inline void finish(RedShape g, const double* partials, int nq, double* out, hipStream_t st) {
+  if (g.blocks > 1) reduce_finalize(partials, int(g.blocks), nq, out, st);
 }
 
 // ----------------------------------------------------------------- generic sums
 // out partials: [sum x, sum x*y (if y), sum x*x]
-__global__ __launch_bounds__(256) void dots_kernel(int64_t n, const double* __restrict__ x,
+__global__ __launch_bounds__(1024) void dots_kernel(int64_t n, const double* __restrict__ x,
                                                    const double* __restrict__ y, double* partials, double* out) {
   double v[3] = {0.0, 0.0, 0.0};
   KQR_GRID_STRIDE(i, n) {
@@ -57,9 +49,9 @@ __global__ __launch_bounds__(256) void dots_kernel(int64_t n, const double* __re
 }
 
 void vec_dots(int64_t n, const double* x, const double* y, Workspace& ws, double* out3, hipStream_t st) {
-  const dim3 g = red_grid(n);
+  const RedShape g = red_shape(n);
 
-  dots_kernel<<<g, 256, 0, st>>>(n, x, y, ws.partials, out3);
+  dots_kernel<<<g.blocks, g.threads, 0, st>>>(n, x, y, ws.partials, out3);
 
   KQR_LAUNCH_CHECK();
 
@@ -68,7 +60,7 @@ void vec_dots(int64_t n, const double* x, const double* y, Workspace& ws, double
 
 // ----------------------------------------------------------------- PCG
 // r = b - (Kx + c*sum(x) + L x) (or r = b when x = 0); Kx zeroed when x = 0.
-__global__ __launch_bounds__(256) void pcg_init_r_kernel(int64_t n, const double* __restrict__ b,
+__global__ __launch_bounds__(1024) void pcg_init_r_kernel(int64_t n, const double* __restrict__ b,
                                                          const double* __restrict__ x,
                                                          const double* __restrict__ Kx,
                                                          const double* __restrict__ L, double c,
@@ -88,9 +80,9 @@ __global__ __launch_bounds__(256) void pcg_init_r_kernel(int64_t n, const double
 void pcg_init_r(int64_t n, const double* b, const double* x, const double* Kx, const double* L,
                 double c, const double* sc, int sum_x_slot, double* r, Workspace& ws, double* rr_out,
                 hipStream_t st) {
-  const dim3 g = red_grid(n);
+  const RedShape g = red_shape(n);
 
-  pcg_init_r_kernel<<<g, 256, 0, st>>>(n, b, x, Kx, L, c, sc, sum_x_slot, r, ws.partials, rr_out);
+  pcg_init_r_kernel<<<g.blocks, g.threads, 0, st>>>(n, b, x, Kx, L, c, sc, sum_x_slot, r, ws.partials, rr_out);
 
   KQR_LAUNCH_CHECK();
 
@@ -98,7 +90,7 @@ void pcg_init_r(int64_t n, const double* b, const double* x, const double* Kx, c
 }
 
 // p = zz (+ beta p with beta = sc[rzn]/sc[rz]); p32 = float(p); partial [sum p, r.zz].
-__global__ __launch_bounds__(256) void pcg_p_kernel(int64_t n, const double* __restrict__ zz,
+__global__ __launch_bounds__(1024) void pcg_p_kernel(int64_t n, const double* __restrict__ zz,
                                                     const double* __restrict__ r, double* __restrict__ p,
                                                     float* __restrict__ p32, const double* __restrict__ sc,
                                                     int rz_slot, int rzn_slot, int first,
@@ -117,9 +109,9 @@ __global__ __launch_bounds__(256) void pcg_p_kernel(int64_t n, const double* __r
 
 void pcg_update_p(int64_t n, const double* zz, double* p, float* p32, const double* sc, int rz_slot,
                   int rzn_slot, bool first, Workspace& ws, double* sump_out, hipStream_t st) {
-  const dim3 g = red_grid(n);
+  const RedShape g = red_shape(n);
 
-  pcg_p_kernel<<<g, 256, 0, st>>>(n, zz, nullptr, p, p32, sc, rz_slot, rzn_slot, first ? 1 : 0,
+  pcg_p_kernel<<<g.blocks, g.threads, 0, st>>>(n, zz, nullptr, p, p32, sc, rz_slot, rzn_slot, first ? 1 : 0,
                                            ws.partials, sump_out);
 
   KQR_LAUNCH_CHECK();
@@ -128,7 +120,7 @@ void pcg_update_p(int64_t n, const double* zz, double* p, float* p32, const doub
 }
 
 // q = Kp + c*sum(p) + L p ; partial p.q
-__global__ __launch_bounds__(256) void pcg_q_kernel(int64_t n, const double* __restrict__ Kp,
+__global__ __launch_bounds__(1024) void pcg_q_kernel(int64_t n, const double* __restrict__ Kp,
                                                     const double* __restrict__ p,
                                                     const double* __restrict__ L, double c,
                                                     const double* __restrict__ sc, int sump_slot,
@@ -146,9 +138,9 @@ __global__ __launch_bounds__(256) void pcg_q_kernel(int64_t n, const double* __r
 
 void pcg_q(int64_t n, const double* Kp, const double* p, const double* L, double c, const double* sc,
            int sump_slot, double* q, Workspace& ws, double* pq_out, hipStream_t st) {
-  const dim3 g = red_grid(n);
+  const RedShape g = red_shape(n);
 
-  pcg_q_kernel<<<g, 256, 0, st>>>(n, Kp, p, L, c, sc, sump_slot, q, ws.partials, pq_out);
+  pcg_q_kernel<<<g.blocks, g.threads, 0, st>>>(n, Kp, p, L, c, sc, sump_slot, q, ws.partials, pq_out);
 
   KQR_LAUNCH_CHECK();
 
@@ -156,7 +148,7 @@ void pcg_q(int64_t n, const double* Kp, const double* p, const double* L, double
 }
 
 // a = sc[rz]/sc[pq]; x += a p; r -= a q; Kx += a Kp (if Kx); partial r.r
-__global__ __launch_bounds__(256) void pcg_xr_kernel(int64_t n, const double* __restrict__ p,
+__global__ __launch_bounds__(1024) void pcg_xr_kernel(int64_t n, const double* __restrict__ p,
                                                      const double* __restrict__ q,
                                                      const double* __restrict__ Kp, double* __restrict__ x,
                                                      double* __restrict__ r, double* __restrict__ Kx,
@@ -177,9 +169,9 @@ __global__ __launch_bounds__(256) void pcg_xr_kernel(int64_t n, const double* __
 void pcg_xr(int64_t n, const double* p, const double* q, const double* Kp, double* x, double* r,
             double* Kx, const double* sc, int rz_slot, int pq_slot, Workspace& ws, double* rr_out,
             hipStream_t st) {
-  const dim3 g = red_grid(n);
+  const RedShape g = red_shape(n);
 
-  pcg_xr_kernel<<<g, 256, 0, st>>>(n, p, q, Kp, x, r, Kx, sc, rz_slot, pq_slot, ws.partials, rr_out);
+  pcg_xr_kernel<<<g.blocks, g.threads, 0, st>>>(n, p, q, Kp, x, r, Kx, sc, rz_slot, pq_slot, ws.partials, rr_out);
 
   KQR_LAUNCH_CHECK();
 
@@ -206,7 +198,7 @@ void admm_rhs(int64_t n, const double* y, const double* z, const double* v, doub
 //   [0] ||z - y + beta 1 + K alpha/lam||^2  [1] ||alpha - v||^2  [2] ||alpha||^2
 //   [3] ||v - Pi_B(z + v)||^2  [4] ||v||^2  [5] rho_tau(z)  [6] alpha.Kalpha
 //   [7] y.alpha  [8] 1.alpha
-__global__ __launch_bounds__(256) void multiplier_kkt_kernel(
+__global__ __launch_bounds__(1024) void multiplier_kkt_kernel(
     int64_t n, const double* __restrict__ alpha, const double* __restrict__ Ka,
     const double* __restrict__ y, double* __restrict__ z, double* __restrict__ v, double beta_new,
     double sigma, double step, double tau, double lam, int update, double* partials, double* out) {
@@ -247,9 +239,9 @@ __global__ __launch_bounds__(256) void multiplier_kkt_kernel(
 void multiplier_kkt(int64_t n, const double* alpha, const double* Ka, const double* y, double* z,
                     double* v, double beta_new, double sigma, double step, double tau, double lam,
                     bool update, Workspace& ws, double* out, hipStream_t st) {
-  const dim3 g = red_grid(n);
+  const RedShape g = red_shape(n);
 
-  multiplier_kkt_kernel<<<g, 256, 0, st>>>(n, alpha, Ka, y, z, v, beta_new, sigma, step, tau,
+  multiplier_kkt_kernel<<<g.blocks, g.threads, 0, st>>>(n, alpha, Ka, y, z, v, beta_new, sigma, step, tau,
                                                     lam, update ? 1 : 0, ws.partials, out);
 
   KQR_LAUNCH_CHECK();
@@ -260,7 +252,7 @@ void multiplier_kkt(int64_t n, const double* alpha, const double* Ka, const doub
 // ----------------------------------------------------------------- SSN (Algorithm 3)
 // grad = Ka/lam - y + beta + sigma*sum(alpha) + sigma (w - Pi_B(w)),  w = alpha + z/sigma
 // S = 1 strictly inside (tau-1, tau); partials [||grad||^2]
-__global__ __launch_bounds__(256) void ssn_grad_kernel(int64_t n, const double* __restrict__ alpha,
+__global__ __launch_bounds__(1024) void ssn_grad_kernel(int64_t n, const double* __restrict__ alpha,
                                                        const double* __restrict__ Ka,
                                                        const double* __restrict__ y,
                                                        const double* __restrict__ z, double beta,
@@ -285,9 +277,9 @@ __global__ __launch_bounds__(256) void ssn_grad_kernel(int64_t n, const double* 
 void ssn_grad(int64_t n, const double* alpha, const double* Ka, const double* y, const double* z,
               double beta, double sigma, double sum_alpha, double tau, double lam, double* grad,
               uint8_t* S, Workspace& ws, double* gg_out, hipStream_t st) {
-  const dim3 g = red_grid(n);
+  const RedShape g = red_shape(n);
 
-  ssn_grad_kernel<<<g, 256, 0, st>>>(n, alpha, Ka, y, z, beta, sigma, sum_alpha, tau, lam, grad,
+  ssn_grad_kernel<<<g.blocks, g.threads, 0, st>>>(n, alpha, Ka, y, z, beta, sigma, sum_alpha, tau, lam, grad,
                                               S, ws.partials, gg_out);
 
   KQR_LAUNCH_CHECK();
@@ -316,7 +308,7 @@ void ssn_system(int64_t n, const uint8_t* S, const double* grad, double lam, dou
 // Line search sums for phi(alpha + c d) - phi(alpha) expanded from (2.2):
 //   [0] d.Ka  [1] d.Kd  [2] y.d  [3] 1.d  [4] grad.d
 //   [5 + j] sum_i dist^2(w_i + c_j d_i) - dist^2(w_i),  c_j = c0 shrink^j
-__global__ __launch_bounds__(256) void line_search_kernel(
+__global__ __launch_bounds__(1024) void line_search_kernel(
     int64_t n, const double* __restrict__ alpha, const double* __restrict__ z,
     const double* __restrict__ d, const double* __restrict__ Ka, const double* __restrict__ Kd,
     const double* __restrict__ y, const double* __restrict__ grad, double sigma, double tau,
@@ -349,9 +341,9 @@ __global__ __launch_bounds__(256) void line_search_kernel(
 void line_search_sums(int64_t n, const double* alpha, const double* z, const double* d, const double* Ka,
                       const double* Kd, const double* y, const double* grad, double sigma, double tau,
                       double c0, double shrink, Workspace& ws, double* out, hipStream_t st) {
-  const dim3 g = red_grid(n);
+  const RedShape g = red_shape(n);
 
-  line_search_kernel<<<g, 256, 0, st>>>(n, alpha, z, d, Ka, Kd, y, grad, sigma, tau, c0, shrink,
+  line_search_kernel<<<g.blocks, g.threads, 0, st>>>(n, alpha, z, d, Ka, Kd, y, grad, sigma, tau, c0, shrink,
                                                  ws.partials, out);
 
   KQR_LAUNCH_CHECK();
@@ -375,7 +367,7 @@ void axpy2(int64_t n, double c, const double* d, double* x, const double* Kd, do
 }
 
 // Non-finite check: partial [count of non-finite entries]
-__global__ __launch_bounds__(256) void nonfinite_kernel(int64_t n, const double* __restrict__ x,
+__global__ __launch_bounds__(1024) void nonfinite_kernel(int64_t n, const double* __restrict__ x,
                                                         double* partials, double* out) {
   double v[1] = {0.0};
   KQR_GRID_STRIDE(i, n) {
@@ -385,9 +377,9 @@ __global__ __launch_bounds__(256) void nonfinite_kernel(int64_t n, const double*
 }
 
 void count_nonfinite(int64_t n, const double* x, Workspace& ws, double* out, hipStream_t st) {
-  const dim3 g = red_grid(n);
+  const RedShape g = red_shape(n);
 
-  nonfinite_kernel<<<g, 256, 0, st>>>(n, x, ws.partials, out);
+  nonfinite_kernel<<<g.blocks, g.threads, 0, st>>>(n, x, ws.partials, out);
 
   KQR_LAUNCH_CHECK();
 
@@ -413,7 +405,7 @@ void copy(int64_t n, const double* src, double* dst, hipStream_t st) {
 }
 
 // count of tau-1 < alpha_i < tau : partial
-__global__ __launch_bounds__(256) void interior_kernel(int64_t n, const double* __restrict__ a, double tau,
+__global__ __launch_bounds__(1024) void interior_kernel(int64_t n, const double* __restrict__ a, double tau,
                                                        double* partials, double* out) {
   double v[1] = {0.0};
   KQR_GRID_STRIDE(i, n) {
@@ -423,9 +415,9 @@ __global__ __launch_bounds__(256) void interior_kernel(int64_t n, const double* 
 }
 
 void count_interior(int64_t n, const double* a, double tau, Workspace& ws, double* out, hipStream_t st) {
-  const dim3 g = red_grid(n);
+  const RedShape g = red_shape(n);
 
-  interior_kernel<<<g, 256, 0, st>>>(n, a, tau, ws.partials, out);
+  interior_kernel<<<g.blocks, g.threads, 0, st>>>(n, a, tau, ws.partials, out);
 
   KQR_LAUNCH_CHECK();
 
@@ -436,7 +428,7 @@ void count_interior(int64_t n, const double* a, double tau, Workspace& ws, doubl
 
 namespace kqr {
 // dst = src ; partial src . dst
-__global__ __launch_bounds__(256) void copy_dot_kernel(int64_t n, const double* __restrict__ s,
+__global__ __launch_bounds__(1024) void copy_dot_kernel(int64_t n, const double* __restrict__ s,
                                                        double* __restrict__ d, double* partials, double* out) {
   double v[1] = {0.0};
   KQR_GRID_STRIDE(i, n) {
@@ -448,9 +440,9 @@ __global__ __launch_bounds__(256) void copy_dot_kernel(int64_t n, const double* 
 }
 
 void copy_dot(int64_t n, const double* src, double* dst, Workspace& ws, double* out, hipStream_t st) {
-  const dim3 g = red_grid(n);
+  const RedShape g = red_shape(n);
 
-  copy_dot_kernel<<<g, 256, 0, st>>>(n, src, dst, ws.partials, out);
+  copy_dot_kernel<<<g.blocks, g.threads, 0, st>>>(n, src, dst, ws.partials, out);
 
   KQR_LAUNCH_CHECK();
 

@@ -672,40 +672,54 @@ __global__ __launch_bounds__(256) void trmv_kernel(const double* __restrict__ M,
 }
 
 // Small cores (R1 <= kFusedCore): t = sum of the wood_gt partials, then
-// s = C^{-1} t = W^T (W t), in one workgroup (t and y = W t in LDS).
+// s = C^{-1} t = W^T (W t), in one workgroup of 1024 threads.  Each of the R1
+// columns (and then rows) gets H = 1024 / C threads, C the power of two at or
+// above R1; their H partial sums are added in a fixed order through LDS.
 constexpr int kFusedCore = 128;
-__global__ __launch_bounds__(256) void core_solve_kernel(const double* __restrict__ part, int nblk, int R1,
-                                                         const double* __restrict__ W, const double* __restrict__ WT,
-                                                         int64_t ldc, double* __restrict__ s) {
-  __shared__ double red[256];
+__global__ __launch_bounds__(1024) void core_solve_kernel(const double* __restrict__ part, int nblk, int R1,
+                                                          const double* __restrict__ W,
+                                                          const double* __restrict__ WT, int64_t ldc,
+                                                          double* __restrict__ s) {
+  __shared__ double red[1024];
   __shared__ double t[kFusedCore], y[kFusedCore];
-  const int a = threadIdx.x & (kFusedCore - 1), h = threadIdx.x / kFusedCore;
+  int C = 1;
+  while (C < R1) C <<= 1;
+  const int H = 1024 / C;
+  const int a = threadIdx.x & (C - 1), h = threadIdx.x / C;
+  auto gather = [&](double v, double* dst) {  // dst[a] = sum over h of v(a, h), h in order
+    red[threadIdx.x] = v;
+    __syncthreads();
+    if (threadIdx.x < R1) {
+      double sum = 0.0;
+      for (int k = 0; k < H; ++k) sum += red[k * C + threadIdx.x];
+      dst[threadIdx.x] = sum;
+    }
+    __syncthreads();
+  };
   double acc = 0.0;
   if (a < R1)
-    for (int b = h; b < nblk; b += 2) acc += part[int64_t(b) * R1 + a];
-  red[threadIdx.x] = acc;
-  __syncthreads();
-  const int i = threadIdx.x;
-  if (i < R1) t[i] = red[i] + red[i + kFusedCore];
-  __syncthreads();
-  if (i < R1) {
-    const double* w = W + int64_t(i) * ldc;
-    double sum = 0.0;
-    for (int k = 0; k <= i; ++k) sum = fma(w[k], t[k], sum);
-    y[i] = sum;
+    for (int b = h; b < nblk; b += H) acc += part[int64_t(b) * R1 + a];
+  gather(acc, t);
+  // y = W t (W lower triangular): row a, columns k = h, h + H, ... <= a
+  acc = 0.0;
+  if (a < R1) {
+    const double* w = W + int64_t(a) * ldc;
+    for (int k = h; k <= a; k += H) acc = fma(w[k], t[k], acc);
   }
-  __syncthreads();
-  if (i < R1) {
-    const double* w = WT + int64_t(i) * ldc;
-    double sum = 0.0;
-    for (int k = i; k < R1; ++k) sum = fma(w[k], y[k], sum);
-    s[i] = sum;
+  gather(acc, y);
+  // s = W^T y (WT upper triangular): row a, columns k >= a
+  acc = 0.0;
+  if (a < R1) {
+    const double* w = WT + int64_t(a) * ldc;
+    for (int k = a + h; k < R1; k += H) acc = fma(w[k], y[k], acc);
   }
+  gather(acc, t);
+  if (threadIdx.x < R1) s[threadIdx.x] = t[threadIdx.x];
 }
 
 // out_i = g_i - (Fs_i + s_r) / L_i ; with dot_with, the sum of dot_with . out
 // (one workgroup up to kOneBlockN rows, else partials for reduce_finalize)
-__global__ __launch_bounds__(256) void wood_out_kernel(int64_t n, int r, const double* __restrict__ L,
+__global__ __launch_bounds__(1024) void wood_out_kernel(int64_t n, int r, const double* __restrict__ L,
                                                        const double* __restrict__ g, const double* __restrict__ Fs,
                                                        const double* __restrict__ s, double* __restrict__ out,
                                                        const double* __restrict__ dot_with,
@@ -881,13 +895,13 @@ Co<bool> Woodbury::build_two_level(const double* L, const uint8_t* S, double l_i
   co_return co_await factor(ex);
 }
 
-// Workgroups of the row passes over F: 64 rows each, at most kGtBlocks.
-static int row_blocks(int64_t n) { return int(std::max<int64_t>(1, std::min<int64_t>(kGtBlocks, (n + 63) / 64))); }
+// Workgroups of the U^T g pass: 64 rows of F each, at most kGtBlocks.
+static int gt_blocks(int64_t n) { return int(std::max<int64_t>(1, std::min<int64_t>(kGtBlocks, (n + 63) / 64))); }
 
 void Woodbury::apply(const double* w, double* out, const double* dot_with, double* dot_out, Workspace& ws,
                      hipStream_t st) {
   const int R1 = int(R1_);
-  const int nblk = row_blocks(n_);
+  const int nblk = gt_blocks(n_);
   const int64_t chunk = (n_ + nblk - 1) / nblk;
   switch ((R1 + 255) / 256) {
     case 1: wood_gt_kernel<1><<<nblk, 256, 0, st>>>(F_, n_, int(r_), ldf_, R1, L_, w, g_.as<double>(), chunk,
@@ -901,7 +915,7 @@ void Woodbury::apply(const double* w, double* out, const double* dot_with, doubl
   }
   KQR_LAUNCH_CHECK();
   if (R1 <= kFusedCore) {
-    core_solve_kernel<<<1, 256, 0, st>>>(part_.as<double>(), nblk, R1, W_.as<double>(), WT_.as<double>(), ldc_,
+    core_solve_kernel<<<1, 1024, 0, st>>>(part_.as<double>(), nblk, R1, W_.as<double>(), WT_.as<double>(), ldc_,
                                          s_.as<double>());
     KQR_LAUNCH_CHECK();
   } else {
@@ -910,11 +924,11 @@ void Woodbury::apply(const double* w, double* out, const double* dot_with, doubl
     spd_solve(W_.as<double>(), WT_.as<double>(), ldc_, R1, t_.as<double>(), y_.as<double>(), s_.as<double>(), st);
   }
   if (r_ > 0) gemv_skinny(F_, ldf_, n_, r_, s_.as<double>(), Fs_.as<double>(), st);
-  const unsigned grid = n_ <= kOneBlockN ? 1u : unsigned(std::min<int64_t>(kRedBlocks, (n_ + 255) / 256));
-  wood_out_kernel<<<grid, 256, 0, st>>>(n_, int(r_), L_, g_.as<double>(), Fs_.as<double>(), s_.as<double>(), out,
-                                        dot_with, ws.partials, dot_out);
+  const RedShape g = red_shape(n_);
+  wood_out_kernel<<<g.blocks, g.threads, 0, st>>>(n_, int(r_), L_, g_.as<double>(), Fs_.as<double>(),
+                                                  s_.as<double>(), out, dot_with, ws.partials, dot_out);
   KQR_LAUNCH_CHECK();
-  if (dot_with && grid > 1) reduce_finalize(ws.partials, int(grid), 1, dot_out, st);
+  if (dot_with && g.blocks > 1) reduce_finalize(ws.partials, int(g.blocks), 1, dot_out, st);
 }
 
 }  // namespace kqr
