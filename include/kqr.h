@@ -134,6 +134,16 @@ typedef struct kqr_options {
   double* v_out;       /* device n FP64 or NULL: kqr_fit writes the final consensus vector v of (1.4),
                           so that (alpha, v, beta, z) is the iterate the Section 4 measures in
                           kqr_info were taken at.  NULL */
+  /* Warm start (resume): with warm_alpha non-NULL, kqr_fit and kqr_fit_grad skip
+     Phase I and start Phase II (Algorithm 2) from (alpha, v, beta, z, sigma), the
+     hand-off Algorithm 2 takes from Phase I -- e.g. the alpha, v_out, beta, z_out
+     and kqr_info.sigma of an earlier fit of the same problem.  The batched entry
+     points reject it (KQR_EINVAL). */
+  const double* warm_alpha; /* device n FP64 or NULL (no warm start).  NULL */
+  const double* warm_v;     /* device n FP64, required with warm_alpha.  NULL */
+  const double* warm_z;     /* device n FP64, required with warm_alpha.  NULL */
+  double warm_beta;         /* intercept of the warm start.  0 */
+  double warm_sigma;        /* ALM penalty to resume with (> 0), or 0 = admm_sigma.  0 */
 } kqr_options;
 
 /* ---------------------------------------------------------------- report */
@@ -152,6 +162,9 @@ typedef struct kqr_info {
   int64_t kapply_fast_calls, kapply_exact_calls;
   double t_kapply_fast, t_kapply_exact;
   int trace_len;                /* records written to opt->trace */
+  int core_retries;             /* Woodbury core factorisations repeated after a breakdown (a non-positive
+                                   pivot): Newton systems with a 100x larger eps_t floor, the Phase I core
+                                   with its low-rank part shrunk (both keep P symmetric positive definite) */
 } kqr_info;
 
 /* Fills *opt with the defaults listed above.  Returns KQR_OK or KQR_EINVAL (opt NULL). */
@@ -165,6 +178,13 @@ const char* kqr_last_error(void);
 
 /* Number of HIP devices (0 if none or the runtime is unusable). */
 int kqr_device_count(void);
+
+/* Test hook for the breakdown handling of Section 3's preconditioner core
+ * (kqr_info.core_retries): after `skip` further Woodbury core factorisations,
+ * the next `count` report a non-positive pivot although they ran normally
+ * (process-wide; concurrent fits share the counters).  (0, 0) switches it off.
+ * Returns KQR_OK, or KQR_EINVAL for negative arguments.  Touches no device. */
+int kqr_test_core_breakdowns(int skip, int count);
 
 /* ---------------------------------------------------------------- kernel matrix
  * kqr_kernel_build: materialise K_ij = k(x_i, x_j) (Section 1) into K.
@@ -346,7 +366,9 @@ int kqr_autotune_otf(const float* X, int64_t n, int64_t p, int kernel, double ga
  * architecture (none from another) and sets *count (host) to how many;
  * saving sets it to the entries written.  A process started with the
  * environment variable KQR_TUNE_FILE=<path> loads that file at its first
- * call that uses the device. */
+ * call that uses the device.  kqr_tune_load checks the whole file first
+ * (KQR_EINVAL for an unreadable or malformed file, nothing installed), then
+ * needs a device (KQR_ENODEVICE). */
 int kqr_tune_save(const char* path, int* count);
 int kqr_tune_load(const char* path, int* count);
 

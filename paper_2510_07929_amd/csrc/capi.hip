@@ -401,6 +401,12 @@ const char* kqr_status_string(int s) {
 
 const char* kqr_last_error(void) { return g_last_error.c_str(); }
 
+int kqr_test_core_breakdowns(int skip, int count) {
+  if (skip < 0 || count < 0) return KQR_EINVAL;
+  set_forced_core_breakdowns(skip, count);
+  return KQR_OK;
+}
+
 int kqr_device_count(void) {
   int c = 0;
   if (hipGetDeviceCount(&c) != hipSuccess) {
@@ -662,8 +668,7 @@ int kqr_tune_save(const char* path, int* count) {
 int kqr_tune_load(const char* path, int* count) {
   return guarded([&] {
     KQR_REQUIRE(path != nullptr && count != nullptr, "path and count must be non-null");
-    ensure_device();
-    *count = tune_load(path);
+    *count = tune_load(path);  // checks the file, then the device
   });
 }
 

@@ -58,6 +58,9 @@ void validate_options(const kqr_options& o) {
   KQR_OPT_REQUIRE(o.ssn_max_iter >= 1 && o.ls_max >= 1 && o.ssn_rel > 0.0, "need ssn_max_iter, ls_max >= 1");
   KQR_OPT_REQUIRE(o.trace_cap >= 0 && (o.trace || o.trace_cap == 0), "trace_cap needs a trace buffer");
   KQR_OPT_REQUIRE(o.k_layout == 0 || o.k_layout == 1, "k_layout must be 0 (full) or 1 (packed)");
+  KQR_OPT_REQUIRE(!o.warm_alpha || (o.warm_v && o.warm_z), "a warm start needs warm_alpha, warm_v and warm_z");
+  KQR_OPT_REQUIRE(std::isfinite(o.warm_beta) && std::isfinite(o.warm_sigma) && o.warm_sigma >= 0.0,
+                  "warm_beta must be finite and warm_sigma >= 0");
 }
 
 Co<Prepared> prepare_fit(const float* X, int64_t n, int p, KernelSpec ks, kqr_options o, Exec& ex) {
@@ -147,7 +150,8 @@ Co<FitOutcome> run_fit(Operator& op, const Prepared& pr, const double* y, int64_
   inf.t_precond = pr.t_precond;
   Solver solver(op, ex, y, n, tau, lam, o, pr.F.as<float>(), pr.rank, pr.ldf);
   co_await solver.init();
-  co_await solver.phase1(inf);
+  if (o.warm_alpha) co_await solver.warm_start(inf);  // Phase II from the given iterate
+  else co_await solver.phase1(inf);
   co_await solver.phase2(inf);
   co_await solver.finish(inf);
   KQR_CHECK_HIP(hipMemcpyAsync(alpha_out, solver.alpha(), size_t(n) * sizeof(double), hipMemcpyDeviceToDevice, st));
@@ -385,6 +389,7 @@ void fit_levels(const float* X, const double* y, int64_t n, int p, KernelSpec ks
   o.trace = nullptr;  // one trace buffer cannot serve several concurrent fits
   o.trace_cap = 0;
   if (o.k_layout != 0) fail(KQR_EINVAL, "joint fits stream K in the full layout (k_layout = 0)");
+  if (o.warm_alpha) fail(KQR_EINVAL, "joint fits take no warm start");
   Prepared pr;
   {
     Exec ex0(st);
@@ -452,6 +457,7 @@ void fit_batch(int nprob, const float* const* X, const double* const* y, const i
   o.trace = nullptr;  // one trace buffer cannot serve several concurrent fits
   o.trace_cap = 0;
   if (o.k_layout != 0) fail(KQR_EINVAL, "batched problems stream K in the full layout (k_layout = 0)");
+  if (o.warm_alpha) fail(KQR_EINVAL, "batched fits take no warm start");
   const int T = batch_threads(nprob);
   StreamSet streams(T);
   KQR_CHECK_HIP(hipStreamSynchronize(st));  // the caller's inputs are ready before other streams read them

@@ -100,6 +100,8 @@ class Solver {
          const float* F, int64_t rank, int64_t ldf);
   Co<Unit> init();  // reads ||y|| (fails on non-finite y)
   Co<Unit> phase1(kqr_info& info);
+  // Instead of phase1: (alpha, v, beta, z, sigma) from the options' warm start.
+  Co<Unit> warm_start(kqr_info& info);
   Co<Unit> phase2(kqr_info& info);
   Co<Unit> finish(kqr_info& info);
   const double* alpha() const { return alpha_.as<double>(); }
@@ -131,6 +133,7 @@ class Solver {
   DevBuf rf_r_, rf_dx_, rf_kdx_;  // refinement workspace (BF16 storage)
   std::unique_ptr<Woodbury> P_;
   double beta_ = 0.0, sigma_ = 1.0, ynorm_ = 0.0, eta_d_prev_ = 1.0;
+  double eps_floor_ = 0.0;  // floor of eps_t, raised after a Woodbury core breakdown
   double t_start_ = 0.0;
   int ntrace_ = 0;
   Kkt last_;

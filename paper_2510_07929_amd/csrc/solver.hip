@@ -222,6 +222,7 @@ Solver::Solver(Operator& op, Exec& ex, const double* y, int64_t n, double tau, d
       b_(n * sizeof(double)), L_(n * sizeof(double)), grad_(n * sizeof(double)), d_(n * sizeof(double)),
       Kd_(n * sizeof(double)), S_(n), red_(64 * sizeof(double)) {
   if (rank > 0) P_.reset(new Woodbury(F, n, rank, ldf));
+  eps_floor_ = o.eps_floor;
 }
 
 Co<Unit> Solver::init() {
@@ -348,8 +349,17 @@ Co<Unit> Solver::phase1(kqr_info& info) {
   const int64_t n = n_;
   const double sigma = o_.admm_sigma, step = o_.admm_step, c = lam_ * sigma;
   fill(n, c, L_.as<double>(), st_);
-  if (P_ && !co_await P_->build_scaled_identity(L_.as<double>(), c, c, ex_))
-    fail(KQR_ENUMERIC, "ADMM preconditioner core not positive definite");
+  if (P_) {
+    // a core breakdown (rounding, the core being near singular) is retried
+    // with the low-rank part of P shrunk by 1e2, 1e4, 1e6: P stays
+    // symmetric positive definite, only a weaker preconditioner
+    bool ok = co_await P_->build_scaled_identity(L_.as<double>(), c, c, ex_);
+    for (int k = 1; !ok && k <= 3; ++k) {
+      ++info.core_retries;
+      ok = co_await P_->build_scaled_identity(L_.as<double>(), c, c, ex_, std::pow(10.0, 2.0 * k));
+    }
+    if (!ok) fail(KQR_ENUMERIC, "ADMM preconditioner core not positive definite");
+  }
   fill(n, 0.0, alpha_.as<double>(), st_);
   fill(n, 0.0, v_.as<double>(), st_);
   fill(n, 0.0, z_.as<double>(), st_);
@@ -397,6 +407,25 @@ Co<Unit> Solver::phase1(kqr_info& info) {
   co_return Unit{};
 }
 
+// Warm start: Algorithm 2 begins from the iterate Phase I hands over; here
+// that iterate is given (e.g. a fit stopped at a looser tolerance), so Phase I
+// is skipped.  K alpha is formed exactly and the Section 4 measures of the
+// given point seed the subproblem accuracy of the first outer iteration.
+Co<Unit> Solver::warm_start(kqr_info& info) {
+  const int64_t n = n_;
+  copy(n, o_.warm_alpha, alpha_.as<double>(), st_);
+  copy(n, o_.warm_v, v_.as<double>(), st_);
+  copy(n, o_.warm_z, z_.as<double>(), st_);
+  beta_ = o_.warm_beta;
+  sigma_ = o_.warm_sigma > 0.0 ? o_.warm_sigma : o_.admm_sigma;
+  co_await op_.apply_exact(alpha_.as<double>(), Ka_.as<double>(), ex_);
+  last_ = co_await update_and_kkt(beta_, sigma_, 1.0, false);
+  if (!std::isfinite(last_.err)) fail(KQR_ENUMERIC, "non-finite residual at the warm start");
+  eta_d_prev_ = last_.eta_d;
+  info.admm_iters = 0;
+  co_return Unit{};
+}
+
 // Algorithm 3 on phi_k for the current (beta, z, sigma).
 Co<Unit> Solver::ssn(double stop, kqr_info& info) {
   const int64_t n = n_;
@@ -410,11 +439,25 @@ Co<Unit> Solver::ssn(double stop, kqr_info& info) {
     const double gn = std::sqrt(gg);
     if (!std::isfinite(gn)) fail(KQR_ENUMERIC, "non-finite gradient in SSN");
     if (gn <= stop) break;
-    const double eps_t = std::max(o_.tau1 * std::min(o_.tau2, gn), o_.eps_floor);
+    double eps_t = std::max(o_.tau1 * std::min(o_.tau2, gn), eps_floor_);
     ssn_system(n, S_.as<uint8_t>(), grad_.as<double>(), lam_, sigma, eps_t, L_.as<double>(), b_.as<double>(), st_);
-    if (P_ && !co_await P_->build_two_level(L_.as<double>(), S_.as<uint8_t>(), lam_ * eps_t,
-                                            lam_ * sigma + lam_ * eps_t, c1, ex_))
-      fail(KQR_ENUMERIC, "Newton preconditioner core not positive definite");
+    if (P_) {
+      // a core breakdown: the interior diagonal lambda eps_t is too small for
+      // the core in FP64; raise the eps_t floor 100-fold (for the rest of the
+      // fit) and form the Newton system again, up to four times
+      bool ok = co_await P_->build_two_level(L_.as<double>(), S_.as<uint8_t>(), lam_ * eps_t,
+                                             lam_ * sigma + lam_ * eps_t, c1, ex_);
+      for (int k = 0; !ok && k < 4; ++k) {
+        ++info.core_retries;
+        eps_floor_ = std::max(100.0 * eps_t, 1e-10);
+        eps_t = std::max(eps_t, eps_floor_);
+        ssn_system(n, S_.as<uint8_t>(), grad_.as<double>(), lam_, sigma, eps_t, L_.as<double>(), b_.as<double>(),
+                   st_);
+        ok = co_await P_->build_two_level(L_.as<double>(), S_.as<uint8_t>(), lam_ * eps_t,
+                                          lam_ * sigma + lam_ * eps_t, c1, ex_);
+      }
+      if (!ok) fail(KQR_ENUMERIC, "Newton preconditioner core not positive definite");
+    }
     const double tol = lam_ * std::min(o_.etabar, std::pow(gn, 1.0 + o_.iota));
     PcgStats ps = co_await linsolve(c1, L_.as<double>(), b_.as<double>(), d_.as<double>(), Kd_.as<double>(), true,
                                     tol, true, info);

@@ -146,10 +146,10 @@ int tune_load(const char* path) {
   size_t got;
   while ((got = std::fread(buf, 1, sizeof(buf), f)) > 0) text.append(buf, got);
   std::fclose(f);
+  // the whole file is checked before anything is installed
   std::string file_arch;
   if (!field(text.substr(0, text.find('\n')), "arch", file_arch)) fail(KQR_EINVAL, "%s has no \"arch\"", path);
-  if (file_arch != device_arch()) return 0;  // tuned on another architecture: nothing applies
-  int count = 0;
+  std::vector<TuneEntry> entries;
   size_t pos = text.find('\n');
   while (pos != std::string::npos && pos + 1 < text.size()) {
     const size_t next = text.find('\n', pos + 1);
@@ -171,11 +171,19 @@ int tune_load(const char* path) {
     if (field(line, "us", us)) e.us = std::atof(us.c_str());
     if ((e.k_dtype != KQR_FP32 && e.k_dtype != KQR_BF16) || e.mode < 0 || e.mode > 1)
       fail(KQR_EINVAL, "tuning entry: bad k_dtype or mode");
+    entries.push_back(e);
+  }
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
+    (void)hipGetLastError();
+    fail(KQR_ENODEVICE, "no HIP device available");
+  }
+  if (file_arch != device_arch()) return 0;  // tuned on another architecture: nothing applies
+  for (const TuneEntry& e : entries) {
     install(e);
     tune_record(e);
-    ++count;
   }
-  return count;
+  return int(entries.size());
 }
 
 void tune_autoload() {

@@ -72,8 +72,10 @@ class Woodbury {
   // factors it and forms W = Lc^{-1}.  Returns false when a pivot is not
   // positive (the factor is then unusable).
   Co<bool> build(const double* L, double c, Exec& ex);
-  // Same for L = l I (Phase I), from the Gram matrix U^T U formed once.
-  Co<bool> build_scaled_identity(const double* L, double l, double c, Exec& ex);
+  // Same for L = l I (Phase I), from the Gram matrix U^T U formed once;
+  // shrink > 1 scales the low-rank part of P by 1 / shrink (the core's
+  // diag(I, 1/c) by shrink).
+  Co<bool> build_scaled_identity(const double* L, double l, double c, Exec& ex, double shrink = 1.0);
   // Same for the Newton systems: L_i = l_in where S_i = 1, l_out elsewhere.
   Co<bool> build_two_level(const double* L, const uint8_t* S, double l_in, double l_out, double c, Exec& ex);
   // out = P^{-1} w.  When dot_with != nullptr also writes dot_with . out to *dot_out (device).
@@ -98,6 +100,10 @@ class Woodbury {
   DevBuf C_, W_, WT_, T_, G_, part_, g_, Fs_, t_, y_, s_, flag_, idx_, cnt_;
   int nsplit_ = 1;
 };
+
+// Test hook (kqr_test_core_breakdowns): after `skip` more core
+// factorisations, the next `count` report a non-positive pivot.
+void set_forced_core_breakdowns(int skip, int count);
 
 // ----------------------------------------------------------------- RPCholesky (rpchol.hip)
 // Randomly pivoted Cholesky on K (materialised or from X).  Writes F (n x ldf

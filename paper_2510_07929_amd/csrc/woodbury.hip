@@ -21,6 +21,7 @@
 #include "vec.h"
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 
 namespace kqr {
@@ -836,11 +837,24 @@ void spd_solve(const double* W, const double* WT, int64_t ldc, int R1, const dou
   KQR_LAUNCH_CHECK();
 }
 
+namespace {
+std::atomic<int> g_force_skip{0}, g_force_count{0};
+}  // namespace
+
+void set_forced_core_breakdowns(int skip, int count) {
+  g_force_skip.store(std::max(skip, 0));
+  g_force_count.store(std::max(count, 0));
+}
+
 Co<bool> Woodbury::factor(Exec& ex) {
   spd_factor_inverse(C_.as<double>(), ldc_, int(R1_), W_.as<double>(), WT_.as<double>(), T_.as<double>(),
                      flag_.as<int>(), ex.st);
   int flag = 1;
   co_await read_back(ex, flag_.ptr, sizeof(int), &flag);
+  if (g_force_count.load() > 0) {  // test hook: report a breakdown of a factorisation that ran normally
+    if (g_force_skip.load() > 0) g_force_skip.fetch_sub(1);
+    else if (g_force_count.fetch_sub(1) > 0) flag = 1;
+  }
   co_return flag == 0;
 }
 
@@ -856,11 +870,11 @@ void Woodbury::prepare_gram(hipStream_t st) {
   syrk(nullptr, nullptr, n_, nullptr, 0.0, 1.0, 0.0, 0.0, G_.as<double>(), st);
 }
 
-Co<bool> Woodbury::build_scaled_identity(const double* L, double l, double c, Exec& ex) {
+Co<bool> Woodbury::build_scaled_identity(const double* L, double l, double c, Exec& ex, double shrink) {
   const hipStream_t st = ex.st;
   prepare_gram(st);
   L_ = L;
-  syrk(nullptr, nullptr, 0, G_.as<double>(), 1.0 / l, 0.0, 1.0, 1.0 / c, C_.as<double>(), st);
+  syrk(nullptr, nullptr, 0, G_.as<double>(), 1.0 / l, 0.0, shrink, shrink / c, C_.as<double>(), st);
   co_return co_await factor(ex);
 }
 

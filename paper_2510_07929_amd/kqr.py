@@ -47,6 +47,8 @@ class KqrOptions(C.Structure):
         ("profile", C.c_int), ("exact_k", C.c_int), ("ssn_adapt", C.c_double),
         ("trace", C.POINTER(C.c_double)), ("trace_cap", C.c_int), ("k_layout", C.c_int),
         ("z_out", C.c_void_p), ("v_out", C.c_void_p),
+        ("warm_alpha", C.c_void_p), ("warm_v", C.c_void_p), ("warm_z", C.c_void_p),
+        ("warm_beta", C.c_double), ("warm_sigma", C.c_double),
     ]
 
 
@@ -63,7 +65,7 @@ class KqrInfo(C.Structure):
         ("t_alm", C.c_double), ("t_total", C.c_double),
         ("kapply_fast_calls", C.c_int64), ("kapply_exact_calls", C.c_int64),
         ("t_kapply_fast", C.c_double), ("t_kapply_exact", C.c_double),
-        ("trace_len", C.c_int),
+        ("trace_len", C.c_int), ("core_retries", C.c_int),
     ]
 
     def as_dict(self):
@@ -77,6 +79,7 @@ _SIGS = {
     "kqr_status_string": (C.c_char_p, [C.c_int]),
     "kqr_last_error": (C.c_char_p, []),
     "kqr_device_count": (C.c_int, []),
+    "kqr_test_core_breakdowns": (C.c_int, [C.c_int, C.c_int]),
     "kqr_kernel_build": (C.c_int, [_P, _I64, _I64, C.c_int, C.c_double, C.c_int, _P, _I64, _P]),
     "kqr_kernel_apply": (C.c_int, [_P, _I64, _I64, C.c_int, C.c_double, _P, C.c_int, _I64, _P, _I64, _I64,
                                    _P, _I64, C.c_int, _P]),
@@ -217,6 +220,12 @@ def kqr_default_options(**overrides) -> KqrOptions:
 
 def kqr_device_count() -> int:
     return int(lib().kqr_device_count())
+
+
+def kqr_test_core_breakdowns(skip: int, count: int) -> None:
+    """Test hook: after `skip` more Woodbury core factorisations, the next
+    `count` report a breakdown (kqr_info.core_retries counts the retries)."""
+    _check(lib().kqr_test_core_breakdowns(int(skip), int(count)), "kqr_test_core_breakdowns")
 
 
 def kqr_kernel_build(X, kernel, gamma, k_dtype="fp32", K=None, stream=None):
@@ -486,18 +495,29 @@ def kqr_kkt_residuals(tau, lam, beta, alpha, Kalpha, y, z, v, sigma=1.0, step=1.
 
 
 def kqr_fit(X, y, tau, lam, kernel="rbf", gamma=1.0, options: KqrOptions | None = None, uniforms=None,
-            stream=None, trace: int = 0, out_vz: bool = False, **overrides):
+            stream=None, trace: int = 0, out_vz: bool = False, warm=None, **overrides):
     """PALM-KQR fit on the GPU.  Returns (alpha (GPU float64), beta, info dict, status).
 
     ``trace`` > 0 records up to that many outer iterations; info["trace"] is
     then an array of rows (phase, iteration, max(eta_kkt, eta_gap), seconds).
     ``out_vz``: info["v"], info["z"] hold the final v and z (GPU float64), the
-    iterate the Section 4 measures in info were taken at."""
+    iterate the Section 4 measures in info were taken at.
+    ``warm``: (alpha, v, z, beta, sigma) of an earlier fit of the same problem
+    (GPU float64 vectors, floats): Phase II resumes from it, Phase I is skipped."""
     torch = _torch()
     n, p = X.shape
     o = options if options is not None else kqr_default_options()
     for k, v in overrides.items():
         setattr(o, k, v)
+    warm_keep = None
+    if warm is not None:
+        wa, wv, wz, wb, ws = warm
+        warm_keep = (_dev(wa, torch.float64, "warm alpha", 1), _dev(wv, torch.float64, "warm v", 1),
+                     _dev(wz, torch.float64, "warm z", 1))
+        if any(t.shape[0] != n for t in (wa, wv, wz)):
+            raise ValueError("warm start vectors must have n entries")
+        o.warm_alpha, o.warm_v, o.warm_z = (p_.value for p_ in warm_keep)
+        o.warm_beta, o.warm_sigma = float(wb), float(ws)
     vz = None
     if out_vz:
         vz = torch.empty((2, n), dtype=torch.float64, device=X.device)
@@ -526,6 +546,8 @@ def kqr_fit(X, y, tau, lam, kernel="rbf", gamma=1.0, options: KqrOptions | None 
     if vz is not None:
         out["v"], out["z"] = vz[0], vz[1]
         o.v_out, o.z_out = None, None
+    if warm_keep is not None:
+        o.warm_alpha = o.warm_v = o.warm_z = None
     return alpha, float(beta.value), out, st
 
 

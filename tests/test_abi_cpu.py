@@ -50,10 +50,12 @@ def test_struct_layouts_match_c():
 #include <stddef.h>
 #include "kqr.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(kqr_options), sizeof(kqr_info),
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(kqr_options), sizeof(kqr_info),
          offsetof(kqr_options, pivot_uniforms), offsetof(kqr_options, verbose),
          offsetof(kqr_info, kapply_calls), offsetof(kqr_info, t_total),
-         offsetof(kqr_options, z_out), offsetof(kqr_options, v_out));
+         offsetof(kqr_options, z_out), offsetof(kqr_options, v_out),
+         offsetof(kqr_options, warm_alpha), offsetof(kqr_options, warm_sigma),
+         offsetof(kqr_info, core_retries));
   return 0;
 }
 '''
@@ -67,7 +69,9 @@ int main(void) {
     exp = [C.sizeof(kqr.KqrOptions), C.sizeof(kqr.KqrInfo),
            kqr.KqrOptions.pivot_uniforms.offset, kqr.KqrOptions.verbose.offset,
            kqr.KqrInfo.kapply_calls.offset, kqr.KqrInfo.t_total.offset,
-           kqr.KqrOptions.z_out.offset, kqr.KqrOptions.v_out.offset]
+           kqr.KqrOptions.z_out.offset, kqr.KqrOptions.v_out.offset,
+           kqr.KqrOptions.warm_alpha.offset, kqr.KqrOptions.warm_sigma.offset,
+           kqr.KqrInfo.core_retries.offset]
     assert got == exp
 
 
@@ -105,6 +109,19 @@ def test_invalid_arguments_are_rejected_before_device_work():
     o = kqr.kqr_default_options(admm_step=1.7)
     assert lib.kqr_fit(P, P, 10, 3, 0.5, 1.0, 0, 1.0, C.byref(o), alpha, C.byref(beta), None, None) == kqr.KQR_EINVAL
     assert "admm_step" in kqr.last_error()
+    # a warm start needs all three vectors, a finite beta and sigma >= 0
+    o = kqr.kqr_default_options()
+    o.warm_alpha = 4096
+    assert lib.kqr_fit(P, P, 10, 3, 0.5, 1.0, 0, 1.0, C.byref(o), alpha, C.byref(beta), None, None) == kqr.KQR_EINVAL
+    assert "warm" in kqr.last_error()
+    o.warm_v = o.warm_z = 4096
+    o.warm_sigma = -1.0
+    assert lib.kqr_fit(P, P, 10, 3, 0.5, 1.0, 0, 1.0, C.byref(o), alpha, C.byref(beta), None, None) == kqr.KQR_EINVAL
+    o.warm_sigma, o.warm_beta = 1.0, float("nan")
+    assert lib.kqr_fit(P, P, 10, 3, 0.5, 1.0, 0, 1.0, C.byref(o), alpha, C.byref(beta), None, None) == kqr.KQR_EINVAL
+    # the breakdown test hook: negative counts rejected, (0, 0) accepted without a device
+    assert lib.kqr_test_core_breakdowns(-1, 0) == kqr.KQR_EINVAL
+    assert lib.kqr_test_core_breakdowns(0, 0) == kqr.KQR_OK
     # kernel apply: m out of range, bad ld, misaligned K
     assert lib.kqr_kernel_apply(P, 10, 3, 0, 1.0, None, 0, 0, P, 17, 17, P, 17, 0, None) == kqr.KQR_EINVAL
     assert lib.kqr_kernel_apply(P, 10, 3, 0, 1.0, P, 0, 12, P, 1, 1, P, 1, 0, None) == kqr.KQR_EINVAL

@@ -1,0 +1,117 @@
+"""GPU: resuming a fit from a given iterate (warm start) and the retries after
+a breakdown of the preconditioner core, each checked against the FP64 oracle.
+
+The breakdowns are forced from the host (kqr_test_core_breakdowns makes a
+factorisation that ran normally report a non-positive pivot), so every kernel
+runs to its normal end.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import kernel as okernel
+from oracle import problem as oproblem
+from oracle import solver as osolver
+from paper_2510_07929_amd import inputs, kqr
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[gpu-test]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def setup():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    kqr.lib()
+    dev = torch.device("cuda:0")
+    prob = inputs.workload("c0", n=1500)
+    ref = osolver.fit(prob.X, prob.y, prob.tau, prob.lam, "rbf", prob.gamma, osolver.OracleOptions(tol=1e-10))
+    K = okernel.kernel_matrix(prob.X, "rbf", prob.gamma)
+    X = torch.from_numpy(prob.X).to(dev)
+    y = torch.from_numpy(prob.y).to(dev)
+    return prob, ref, K, X, y
+
+
+def rel_obj(prob, K, a, beta, ref):
+    """Relative difference of the primal objective (1.2) at (alpha, beta) from the oracle optimum."""
+    a = a.cpu().numpy()
+    Ka = K @ a
+    z = prob.y - beta - Ka / prob.lam
+    obj = oproblem.primal_objective(z, a, Ka, prob.lam, prob.tau)
+    return abs(obj - ref.kkt["obj_p"]) / (1.0 + abs(ref.kkt["obj_p"]))
+
+
+def fit(setup, **kw):
+    prob, _, _, X, y = setup
+    return kqr.kqr_fit(X, y, prob.tau, prob.lam, "rbf", prob.gamma, **kw)
+
+
+def test_warm_start_from_a_loose_fit_reaches_the_oracle_optimum(setup):
+    prob, ref, K, _, _ = setup
+    a1, b1, i1, s1 = fit(setup, tol=1e-3, out_vz=True)
+    say("loose fit", s1, i1["eta_kkt"], i1["alm_iters"], i1["kapply_calls"])
+    a2, b2, i2, s2 = fit(setup, warm=(a1, i1["v"], i1["z"], b1, i1["sigma"]))
+    a3, b3, i3, s3 = fit(setup)
+    say("warm", s2, i2["eta_kkt"], i2["eta_gap"], i2["alm_iters"], i2["kapply_calls"], "cold", i3["kapply_calls"])
+    assert s2 == kqr.KQR_OK and s3 == kqr.KQR_OK
+    assert i2["admm_iters"] == 0  # Phase I skipped
+    assert max(i2["eta_kkt"], i2["eta_gap"]) <= 1e-6
+    assert rel_obj(prob, K, a2, b2, ref) <= 1e-6
+    # the resumed fit does not repeat Phase I's work
+    assert i2["kapply_calls"] < i3["kapply_calls"]
+
+
+def test_warm_start_at_the_optimum_needs_no_outer_iteration(setup):
+    prob, ref, K, _, _ = setup
+    a1, b1, i1, s1 = fit(setup, out_vz=True)
+    a2, b2, i2, s2 = fit(setup, warm=(a1, i1["v"], i1["z"], b1, i1["sigma"]))
+    say("resume at optimum", s2, i2["alm_iters"], i2["newton_iters"], i2["eta_kkt"])
+    assert s2 == kqr.KQR_OK
+    assert i2["alm_iters"] == 0 and i2["newton_iters"] == 0
+    assert max(i2["eta_kkt"], i2["eta_gap"]) <= 1e-6
+    assert rel_obj(prob, K, a2, b2, ref) <= 1e-6
+
+
+def test_warm_start_rejected_by_the_batched_fits(setup):
+    prob, _, _, X, y = setup
+    a1, b1, i1, _ = fit(setup, tol=1e-3, out_vz=True)
+    o = kqr.kqr_default_options()
+    o.warm_alpha, o.warm_v, o.warm_z = a1.data_ptr(), i1["v"].data_ptr(), i1["z"].data_ptr()
+    with pytest.raises(kqr.KqrError) as e:
+        kqr.kqr_fit_multi_tau(X, y, [0.25, 0.75], prob.lam, "rbf", prob.gamma, options=o)
+    assert e.value.status == kqr.KQR_EINVAL
+
+
+@pytest.mark.parametrize("skip,count,phase", [(0, 1, "Phase I core"), (1, 2, "first Newton cores")])
+def test_core_breakdown_is_retried(setup, skip, count, phase):
+    prob, ref, K, _, _ = setup
+    kqr.kqr_test_core_breakdowns(skip, count)
+    try:
+        a, b, info, st = fit(setup)
+    finally:
+        kqr.kqr_test_core_breakdowns(0, 0)
+    say(phase, "status", st, "retries", info["core_retries"], "eta", info["eta_kkt"], info["eta_gap"])
+    assert st == kqr.KQR_OK
+    assert info["core_retries"] == count
+    assert max(info["eta_kkt"], info["eta_gap"]) <= 1e-6
+    assert rel_obj(prob, K, a, b, ref) <= 1e-6
+
+
+def test_core_breakdown_that_persists_fails_cleanly(setup):
+    kqr.kqr_test_core_breakdowns(0, 4)  # the Phase I core and its three retries
+    try:
+        with pytest.raises(kqr.KqrError) as e:
+            fit(setup)
+    finally:
+        kqr.kqr_test_core_breakdowns(0, 0)
+    assert e.value.status == kqr.KQR_ENUMERIC
+    # the library is usable afterwards
+    a, b, info, st = fit(setup)
+    assert st == kqr.KQR_OK and info["core_retries"] == 0
