@@ -439,10 +439,15 @@ int kqr_fit(const float* X, const double* y, int64_t n, int64_t p, double tau, d
             int kernel, double gamma, const kqr_options* opt, double* alpha, double* beta,
             kqr_info* info, void* stream);
 
+/* Host threads the batched fits use from now on (process-wide): 1..16, or 0
+ * for the default (min(16, host cores), or KQR_BATCH_THREADS when set).
+ * Returns KQR_OK or KQR_EINVAL.  Touches no device. */
+int kqr_set_batch_threads(int threads);
+
 /* Batched fits (kqr_fit_multi_tau, kqr_fit_path, kqr_fit_batch) run every
  * fit's PALM-KQR iteration as a coroutine: a bounded pool of host threads
  * (min(fits, 16, host cores); environment variable KQR_BATCH_THREADS = 1..16
- * overrides), one scheduler and one stream each, resumes the fits between
+ * or kqr_set_batch_threads overrides), one scheduler and one stream each, resumes the fits between
  * their read-backs and K-apply requests.  Whenever every fit still running
  * waits for a K-apply, one batched launch serves them all (lock-step rounds
  * over the unfinished fits).  Results do not depend on the thread count.

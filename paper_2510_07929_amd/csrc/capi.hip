@@ -401,6 +401,12 @@ const char* kqr_status_string(int s) {
 
 const char* kqr_last_error(void) { return g_last_error.c_str(); }
 
+int kqr_set_batch_threads(int threads) {
+  if (threads < 0 || threads > 16) return KQR_EINVAL;
+  set_batch_threads(threads);
+  return KQR_OK;
+}
+
 int kqr_test_core_breakdowns(int skip, int count) {
   if (skip < 0 || count < 0) return KQR_EINVAL;
   set_forced_core_breakdowns(skip, count);

@@ -70,6 +70,7 @@ void fit_batch(int nprob, const float* const* X, const double* const* y, const i
                double* const* alpha, double* beta, kqr_info* info, int* status, hipStream_t st);
 
 std::vector<double> default_uniforms(uint64_t seed, int64_t count);
+void set_batch_threads(int t);  // host threads of the batched fits (0: min(16, cores))
 double wall_seconds();
 
 }  // namespace kqr

@@ -263,15 +263,20 @@ namespace {
 // from one thread are issued one after another, and with every fit's small
 // kernels in between the batched launches the host issue rate is what
 // limits a batch of small problems, so several threads issue them.  At most
-// 16 (and the host's core count); KQR_BATCH_THREADS (1..16) overrides.
+// 16 (and the host's core count); KQR_BATCH_THREADS (1..16) or
+// kqr_set_batch_threads overrides.
+std::atomic<int> g_batch_threads{-1};  // -1: not read yet; 0: default
+
 int batch_threads(int fits) {
-  static const int limit = [] {
+  int limit = g_batch_threads.load();
+  if (limit < 0) {
     const char* e = std::getenv("KQR_BATCH_THREADS");
     const int v = e ? std::atoi(e) : 0;
-    if (v >= 1 && v <= 16) return v;
-    const int hw = int(std::thread::hardware_concurrency());
-    return std::max(1, std::min(16, hw));
-  }();
+    int expected = -1;
+    g_batch_threads.compare_exchange_strong(expected, v >= 1 && v <= 16 ? v : 0);
+    limit = g_batch_threads.load();
+  }
+  if (limit == 0) limit = std::max(1, std::min(16, int(std::thread::hardware_concurrency())));
   return std::max(1, std::min(fits, limit));
 }
 
@@ -381,6 +386,8 @@ void free_all(std::vector<void*>& ptrs) {
   ptrs.clear();
 }
 }  // namespace
+
+void set_batch_threads(int t) { g_batch_threads.store(t); }
 
 void fit_levels(const float* X, const double* y, int64_t n, int p, KernelSpec ks, const double* taus,
                 const double* lams, int nlev, const kqr_options& o_in, double* alpha, double* beta, kqr_info* info,

@@ -80,6 +80,7 @@ _SIGS = {
     "kqr_last_error": (C.c_char_p, []),
     "kqr_device_count": (C.c_int, []),
     "kqr_test_core_breakdowns": (C.c_int, [C.c_int, C.c_int]),
+    "kqr_set_batch_threads": (C.c_int, [C.c_int]),
     "kqr_kernel_build": (C.c_int, [_P, _I64, _I64, C.c_int, C.c_double, C.c_int, _P, _I64, _P]),
     "kqr_kernel_apply": (C.c_int, [_P, _I64, _I64, C.c_int, C.c_double, _P, C.c_int, _I64, _P, _I64, _I64,
                                    _P, _I64, C.c_int, _P]),
@@ -220,6 +221,11 @@ def kqr_default_options(**overrides) -> KqrOptions:
 
 def kqr_device_count() -> int:
     return int(lib().kqr_device_count())
+
+
+def kqr_set_batch_threads(threads: int) -> None:
+    """Host threads of the batched fits (1..16; 0 = default)."""
+    _check(lib().kqr_set_batch_threads(int(threads)), "kqr_set_batch_threads")
 
 
 def kqr_test_core_breakdowns(skip: int, count: int) -> None:

@@ -122,6 +122,10 @@ def test_invalid_arguments_are_rejected_before_device_work():
     # the breakdown test hook: negative counts rejected, (0, 0) accepted without a device
     assert lib.kqr_test_core_breakdowns(-1, 0) == kqr.KQR_EINVAL
     assert lib.kqr_test_core_breakdowns(0, 0) == kqr.KQR_OK
+    # batch threads: 0 (default) .. 16
+    assert lib.kqr_set_batch_threads(17) == kqr.KQR_EINVAL
+    assert lib.kqr_set_batch_threads(-1) == kqr.KQR_EINVAL
+    assert lib.kqr_set_batch_threads(0) == kqr.KQR_OK
     # kernel apply: m out of range, bad ld, misaligned K
     assert lib.kqr_kernel_apply(P, 10, 3, 0, 1.0, None, 0, 0, P, 17, 17, P, 17, 0, None) == kqr.KQR_EINVAL
     assert lib.kqr_kernel_apply(P, 10, 3, 0, 1.0, P, 0, 12, P, 1, 1, P, 1, 0, None) == kqr.KQR_EINVAL

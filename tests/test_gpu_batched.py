@@ -193,3 +193,33 @@ def test_batched_entry_points_validate(dev):
     with pytest.raises(kqr.KqrError) as e:
         kqr.kqr_fit_multi_tau(X, y, [0.5] * 17, prob.lam, "rbf", prob.gamma)
     assert e.value.status == kqr.KQR_EINVAL
+
+
+def test_batched_results_do_not_depend_on_host_threads(dev):
+    """The batched launches of a round carry the same requests whatever the
+    number of host threads, and every fit issues the same kernels in the same
+    order: the results are bitwise the same."""
+    probs = inputs.uneven_batch(count=12, lo=300, hi=2500, seed=5)
+    Xs = [torch.from_numpy(p.X).to(dev) for p in probs]
+    ys = [torch.from_numpy(p.y).to(dev) for p in probs]
+    path = inputs.workload("c0", n=1500)
+    Xp = torch.from_numpy(path.X).to(dev)
+    yp = torch.from_numpy(path.y).to(dev)
+    lams = list(np.geomspace(0.3, 30.0, 7) * path.lam)
+    runs = {}
+    try:
+        for T in (1, 5):
+            kqr.kqr_set_batch_threads(T)
+            a, b, inf, st = kqr.kqr_fit_batch(Xs, ys, [p.tau for p in probs], [p.lam for p in probs],
+                                              [p.gamma for p in probs], uniforms=inputs.pivot_uniforms(64, (5, 2)))
+            ap, bp, infp, stp = kqr.kqr_fit_path(Xp, yp, path.tau, lams, "rbf", path.gamma,
+                                                 uniforms=inputs.pivot_uniforms(64, (5, 3)))
+            assert all(s == kqr.KQR_OK for s in st + stp)
+            runs[T] = ([x.cpu() for x in a], list(b), [i["kapply_calls"] for i in inf], ap.cpu(), list(bp))
+            say("threads", T, "batch kapply calls", sum(runs[T][2]))
+    finally:
+        kqr.kqr_set_batch_threads(0)
+    (a1, b1, k1, p1, q1), (a5, b5, k5, p5, q5) = runs[1], runs[5]
+    assert all(torch.equal(x, y) for x, y in zip(a1, a5))
+    assert b1 == b5 and k1 == k5
+    assert torch.equal(p1, p5) and q1 == q5
