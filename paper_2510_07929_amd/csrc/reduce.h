@@ -55,6 +55,27 @@ __device__ __forceinline__ void block_sums(double (&v)[NQ], double* __restrict__
   }
 }
 
+// Sum of v over the (single) workgroup in block_sums' order, returned to
+// every thread.
+__device__ __forceinline__ double block_sum_all(double v) {
+  __shared__ double sh[16];
+  __shared__ double tot;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = int(blockDim.x) >> 6;
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+  if (lane == 0) sh[wave] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int w = 0; w < nw; ++w) s += sh[w];
+    tot = s;
+  }
+  __syncthreads();
+  const double r = tot;
+  __syncthreads();  // sh and tot are free for the next call
+  return r;
+}
+
 // Launch shape of an O(n) reduction: one workgroup of kOneBlockThreads up
 // to kOneBlockN elements, else one kRedThreads-thread workgroup per
 // kRedThreads elements up to kRedBlocks (grid-stride beyond).

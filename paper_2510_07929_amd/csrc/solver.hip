@@ -179,19 +179,23 @@ Co<PcgStats> Pcg::solve(double c, const double* L, Woodbury* P, const double* b,
   stats.resnorm = std::sqrt(rr);
   if (!(stats.resnorm > tol)) co_return stats;
   int cur = 0;
-  auto precond = [&](int slot) {
-    if (P) P->apply(pb_.r.as<double>(), pb_.zz.as<double>(), pb_.r.as<double>(), sc + slot, ws_, st);
-    else copy_dot(n, pb_.r.as<double>(), pb_.zz.as<double>(), ws_, sc + slot, st);
-  };
   float* p32 = (fast && op_.materialized()) ? pb_.p32.as<float>() : nullptr;
-  precond(RZ0);
-  pcg_update_p(n, pb_.zz.as<double>(), pb_.p.as<double>(), p32, sc, RZ0, RZ0, true, ws_, sc + SUMP, st);
+  // zz = P^{-1} r, sc[rz_new] = r . zz, then p = zz + beta p (beta = sc[rz_new] / sc[rz_old])
+  auto precond_p = [&](int rz_old, int rz_new, bool first) {
+    if (P) {
+      const Woodbury::PUpdate up{pb_.p.as<double>(), p32, sc, rz_old, rz_new, SUMP, first};
+      P->apply(pb_.r.as<double>(), pb_.zz.as<double>(), pb_.r.as<double>(), sc + rz_new, ws_, st, &up);
+    } else {
+      copy_dot(n, pb_.r.as<double>(), pb_.zz.as<double>(), ws_, sc + rz_new, st);
+      pcg_update_p(n, pb_.zz.as<double>(), pb_.p.as<double>(), p32, sc, rz_old, rz_new, first, ws_, sc + SUMP, st);
+    }
+  };
+  precond_p(RZ0, RZ0, true);
   for (int it = 1; it <= maxit; ++it) {
     if (fast) co_await op_.apply_fast(pb_.p.as<double>(), p32, pb_.Kp.as<double>(), ex_);
     else co_await op_.apply_exact(pb_.p.as<double>(), pb_.Kp.as<double>(), ex_);
-    pcg_q(n, pb_.Kp.as<double>(), pb_.p.as<double>(), L, c, sc, SUMP, pb_.q.as<double>(), ws_, sc + PQ, st);
-    pcg_xr(n, pb_.p.as<double>(), pb_.q.as<double>(), pb_.Kp.as<double>(), x, pb_.r.as<double>(), Kx, sc,
-           cur == 0 ? RZ0 : RZ1, PQ, ws_, sc + RR, st);
+    pcg_qxr(n, pb_.Kp.as<double>(), pb_.p.as<double>(), L, c, sc, SUMP, cur == 0 ? RZ0 : RZ1, PQ, RR,
+            pb_.q.as<double>(), x, pb_.r.as<double>(), Kx, ws_, st);
     double two[2];
     co_await read_back(ex_, sc + PQ, 2 * sizeof(double), two);  // [PQ, RR]
     stats.iters = it;
@@ -202,9 +206,7 @@ Co<PcgStats> Pcg::solve(double c, const double* L, Woodbury* P, const double* b,
     }
     if (stats.resnorm <= tol) break;
     const int nxt = 1 - cur;
-    precond(nxt == 0 ? RZ0 : RZ1);
-    pcg_update_p(n, pb_.zz.as<double>(), pb_.p.as<double>(), p32, sc, cur == 0 ? RZ0 : RZ1,
-                 nxt == 0 ? RZ0 : RZ1, false, ws_, sc + SUMP, st);
+    precond_p(cur == 0 ? RZ0 : RZ1, nxt == 0 ? RZ0 : RZ1, false);
     cur = nxt;
   }
   co_return stats;

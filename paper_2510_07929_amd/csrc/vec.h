@@ -31,6 +31,11 @@ void pcg_q(int64_t n, const double* Kp, const double* p, const double* L, double
            int sump_slot, double* q, Workspace& ws, double* pq_out, hipStream_t st);
 void pcg_xr(int64_t n, const double* p, const double* q, const double* Kp, double* x, double* r, double* Kx,
             const double* sc, int rz_slot, int pq_slot, Workspace& ws, double* rr_out, hipStream_t st);
+// pcg_q then pcg_xr (sc[pq_slot] and sc[rr_slot] written); one launch when
+// n <= kOneBlockN.
+void pcg_qxr(int64_t n, const double* Kp, const double* p, const double* L, double c, double* sc, int sump_slot,
+             int rz_slot, int pq_slot, int rr_slot, double* q, double* x, double* r, double* Kx, Workspace& ws,
+             hipStream_t st);
 void admm_rhs(int64_t n, const double* y, const double* z, const double* v, double beta, double sigma,
               double lam, double* b, hipStream_t st);
 void multiplier_kkt(int64_t n, const double* alpha, const double* Ka, const double* y, double* z, double* v,
@@ -79,8 +84,18 @@ class Woodbury {
   // Same for the Newton systems: L_i = l_in where S_i = 1, l_out elsewhere.
   Co<bool> build_two_level(const double* L, const uint8_t* S, double l_in, double l_out, double c, Exec& ex);
   // out = P^{-1} w.  When dot_with != nullptr also writes dot_with . out to *dot_out (device).
+  // With up (PCG's direction update after the preconditioner), also runs
+  // pcg_update_p(out, up->p, ..., old slot, new slot = the slot of dot_out)
+  // -- in the same launch as the last step when n <= kOneBlockN.
+  struct PUpdate {
+    double* p;
+    float* p32;
+    double* sc;
+    int rz_old, rz_new, sump;
+    bool first;
+  };
   void apply(const double* w, double* out, const double* dot_with, double* dot_out, Workspace& ws,
-             hipStream_t st);
+             hipStream_t st, const PUpdate* up = nullptr);
   int64_t rank() const { return r_; }
   // Lower triangle of [F 1]^T [F 1] ((r+1) x (r+1), leading dimension r+1).
   const double* gram(hipStream_t st) {

@@ -50,11 +50,8 @@ __global__ __launch_bounds__(1024) void dots_kernel(int64_t n, const double* __r
 
 void vec_dots(int64_t n, const double* x, const double* y, Workspace& ws, double* out3, hipStream_t st) {
   const RedShape g = red_shape(n);
-
   dots_kernel<<<g.blocks, g.threads, 0, st>>>(n, x, y, ws.partials, out3);
-
   KQR_LAUNCH_CHECK();
-
   finish(g, ws.partials, 3, out3, st);
 }
 
@@ -81,11 +78,8 @@ void pcg_init_r(int64_t n, const double* b, const double* x, const double* Kx, c
                 double c, const double* sc, int sum_x_slot, double* r, Workspace& ws, double* rr_out,
                 hipStream_t st) {
   const RedShape g = red_shape(n);
-
   pcg_init_r_kernel<<<g.blocks, g.threads, 0, st>>>(n, b, x, Kx, L, c, sc, sum_x_slot, r, ws.partials, rr_out);
-
   KQR_LAUNCH_CHECK();
-
   finish(g, ws.partials, 1, rr_out, st);
 }
 
@@ -110,12 +104,9 @@ __global__ __launch_bounds__(1024) void pcg_p_kernel(int64_t n, const double* __
 void pcg_update_p(int64_t n, const double* zz, double* p, float* p32, const double* sc, int rz_slot,
                   int rzn_slot, bool first, Workspace& ws, double* sump_out, hipStream_t st) {
   const RedShape g = red_shape(n);
-
   pcg_p_kernel<<<g.blocks, g.threads, 0, st>>>(n, zz, nullptr, p, p32, sc, rz_slot, rzn_slot, first ? 1 : 0,
                                            ws.partials, sump_out);
-
   KQR_LAUNCH_CHECK();
-
   finish(g, ws.partials, 1, sump_out, st);
 }
 
@@ -139,11 +130,8 @@ __global__ __launch_bounds__(1024) void pcg_q_kernel(int64_t n, const double* __
 void pcg_q(int64_t n, const double* Kp, const double* p, const double* L, double c, const double* sc,
            int sump_slot, double* q, Workspace& ws, double* pq_out, hipStream_t st) {
   const RedShape g = red_shape(n);
-
   pcg_q_kernel<<<g.blocks, g.threads, 0, st>>>(n, Kp, p, L, c, sc, sump_slot, q, ws.partials, pq_out);
-
   KQR_LAUNCH_CHECK();
-
   finish(g, ws.partials, 1, pq_out, st);
 }
 
@@ -170,12 +158,53 @@ void pcg_xr(int64_t n, const double* p, const double* q, const double* Kp, doubl
             double* Kx, const double* sc, int rz_slot, int pq_slot, Workspace& ws, double* rr_out,
             hipStream_t st) {
   const RedShape g = red_shape(n);
-
   pcg_xr_kernel<<<g.blocks, g.threads, 0, st>>>(n, p, q, Kp, x, r, Kx, sc, rz_slot, pq_slot, ws.partials, rr_out);
-
   KQR_LAUNCH_CHECK();
-
   finish(g, ws.partials, 1, rr_out, st);
+}
+
+// One workgroup (n <= kOneBlockN): pcg_q and pcg_xr in one launch, with the
+// same per-thread order and block sums as the two kernels (bitwise the same).
+__global__ __launch_bounds__(1024) void pcg_qxr_one_kernel(int64_t n, const double* __restrict__ Kp,
+                                                          const double* __restrict__ p,
+                                                          const double* __restrict__ L, double c, double* sc,
+                                                          int sump_slot, int rz_slot, int pq_slot, int rr_slot,
+                                                          double* __restrict__ q, double* __restrict__ x,
+                                                          double* __restrict__ r, double* __restrict__ Kx) {
+  const double cs = c * sc[sump_slot];
+  double acc = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+    const double pi = p[i];
+    const double qi = Kp[i] + cs + L[i] * pi;
+    q[i] = qi;
+    acc = fma(pi, qi, acc);
+  }
+  const double pq = block_sum_all(acc);
+  if (threadIdx.x == 0) sc[pq_slot] = pq;
+  const double a = sc[rz_slot] / pq;
+  acc = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {  // q[i] was written by this thread
+    x[i] = fma(a, p[i], x[i]);
+    const double ri = fma(-a, q[i], r[i]);
+    r[i] = ri;
+    if (Kx) Kx[i] = fma(a, Kp[i], Kx[i]);
+    acc = fma(ri, ri, acc);
+  }
+  const double rr = block_sum_all(acc);
+  if (threadIdx.x == 0) sc[rr_slot] = rr;
+}
+
+void pcg_qxr(int64_t n, const double* Kp, const double* p, const double* L, double c, double* sc, int sump_slot,
+             int rz_slot, int pq_slot, int rr_slot, double* q, double* x, double* r, double* Kx, Workspace& ws,
+             hipStream_t st) {
+  if (n <= kOneBlockN) {
+    pcg_qxr_one_kernel<<<1, kOneBlockThreads, 0, st>>>(n, Kp, p, L, c, sc, sump_slot, rz_slot, pq_slot, rr_slot, q,
+                                                       x, r, Kx);
+    KQR_LAUNCH_CHECK();
+    return;
+  }
+  pcg_q(n, Kp, p, L, c, sc, sump_slot, q, ws, sc + pq_slot, st);
+  pcg_xr(n, p, q, Kp, x, r, Kx, sc, rz_slot, pq_slot, ws, sc + rr_slot, st);
 }
 
 // ----------------------------------------------------------------- ADMM / ALM
@@ -240,12 +269,9 @@ void multiplier_kkt(int64_t n, const double* alpha, const double* Ka, const doub
                     double* v, double beta_new, double sigma, double step, double tau, double lam,
                     bool update, Workspace& ws, double* out, hipStream_t st) {
   const RedShape g = red_shape(n);
-
   multiplier_kkt_kernel<<<g.blocks, g.threads, 0, st>>>(n, alpha, Ka, y, z, v, beta_new, sigma, step, tau,
                                                     lam, update ? 1 : 0, ws.partials, out);
-
   KQR_LAUNCH_CHECK();
-
   finish(g, ws.partials, kKktSums, out, st);
 }
 
@@ -278,12 +304,9 @@ void ssn_grad(int64_t n, const double* alpha, const double* Ka, const double* y,
               double beta, double sigma, double sum_alpha, double tau, double lam, double* grad,
               uint8_t* S, Workspace& ws, double* gg_out, hipStream_t st) {
   const RedShape g = red_shape(n);
-
   ssn_grad_kernel<<<g.blocks, g.threads, 0, st>>>(n, alpha, Ka, y, z, beta, sigma, sum_alpha, tau, lam, grad,
                                               S, ws.partials, gg_out);
-
   KQR_LAUNCH_CHECK();
-
   finish(g, ws.partials, 1, gg_out, st);
 }
 
@@ -342,12 +365,9 @@ void line_search_sums(int64_t n, const double* alpha, const double* z, const dou
                       const double* Kd, const double* y, const double* grad, double sigma, double tau,
                       double c0, double shrink, Workspace& ws, double* out, hipStream_t st) {
   const RedShape g = red_shape(n);
-
   line_search_kernel<<<g.blocks, g.threads, 0, st>>>(n, alpha, z, d, Ka, Kd, y, grad, sigma, tau, c0, shrink,
                                                  ws.partials, out);
-
   KQR_LAUNCH_CHECK();
-
   finish(g, ws.partials, 5 + kLsTrials, out, st);
 }
 
@@ -378,11 +398,8 @@ __global__ __launch_bounds__(1024) void nonfinite_kernel(int64_t n, const double
 
 void count_nonfinite(int64_t n, const double* x, Workspace& ws, double* out, hipStream_t st) {
   const RedShape g = red_shape(n);
-
   nonfinite_kernel<<<g.blocks, g.threads, 0, st>>>(n, x, ws.partials, out);
-
   KQR_LAUNCH_CHECK();
-
   finish(g, ws.partials, 1, out, st);
 }
 
@@ -416,11 +433,8 @@ __global__ __launch_bounds__(1024) void interior_kernel(int64_t n, const double*
 
 void count_interior(int64_t n, const double* a, double tau, Workspace& ws, double* out, hipStream_t st) {
   const RedShape g = red_shape(n);
-
   interior_kernel<<<g.blocks, g.threads, 0, st>>>(n, a, tau, ws.partials, out);
-
   KQR_LAUNCH_CHECK();
-
   finish(g, ws.partials, 1, out, st);
 }
 
@@ -441,11 +455,8 @@ __global__ __launch_bounds__(1024) void copy_dot_kernel(int64_t n, const double*
 
 void copy_dot(int64_t n, const double* src, double* dst, Workspace& ws, double* out, hipStream_t st) {
   const RedShape g = red_shape(n);
-
   copy_dot_kernel<<<g.blocks, g.threads, 0, st>>>(n, src, dst, ws.partials, out);
-
   KQR_LAUNCH_CHECK();
-
   finish(g, ws.partials, 1, out, st);
 }
 }  // namespace kqr

@@ -736,6 +736,39 @@ __global__ __launch_bounds__(1024) void wood_out_kernel(int64_t n, int r, const 
   if (dot_with) block_sums<1>(acc, partials, dot_out);
 }
 
+// One workgroup (n <= kOneBlockN): wood_out with its dot product, then PCG's
+// direction update p = out + beta p (beta = the new dot over sc[rz_old]),
+// p32, sum(p) -- the same per-thread order and block sums as wood_out_kernel
+// followed by pcg_p_kernel.
+__global__ __launch_bounds__(1024) void wood_out_p_one_kernel(int64_t n, int r, const double* __restrict__ L,
+                                                             const double* __restrict__ g,
+                                                             const double* __restrict__ Fs,
+                                                             const double* __restrict__ s, double* __restrict__ out,
+                                                             const double* __restrict__ dot_with, double* sc,
+                                                             int rz_old, int rz_new, int sump, int first,
+                                                             double* __restrict__ p, float* __restrict__ p32) {
+  const double sr = s[r];
+  double acc = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+    const double fs = r > 0 ? Fs[i] : 0.0;
+    const double o = g[i] - (fs + sr) / L[i];
+    out[i] = o;
+    acc = fma(o, dot_with[i], acc);
+  }
+  const double rz = block_sum_all(acc);
+  if (threadIdx.x == 0) sc[rz_new] = rz;
+  const double beta = first ? 0.0 : rz / sc[rz_old];
+  acc = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {  // out[i] was written by this thread
+    const double pi = first ? out[i] : fma(beta, p[i], out[i]);
+    p[i] = pi;
+    if (p32) p32[i] = float(pi);
+    acc += pi;
+  }
+  const double sum = block_sum_all(acc);
+  if (threadIdx.x == 0) sc[sump] = sum;
+}
+
 // ---------------------------------------------------------------- class
 Woodbury::Woodbury(const float* F, int64_t n, int64_t r, int64_t ldf)
     : F_(F), n_(n), r_(r), ldf_(ldf), R1_(r + 1) {
@@ -913,7 +946,7 @@ Co<bool> Woodbury::build_two_level(const double* L, const uint8_t* S, double l_i
 static int gt_blocks(int64_t n) { return int(std::max<int64_t>(1, std::min<int64_t>(kGtBlocks, (n + 63) / 64))); }
 
 void Woodbury::apply(const double* w, double* out, const double* dot_with, double* dot_out, Workspace& ws,
-                     hipStream_t st) {
+                     hipStream_t st, const PUpdate* up) {
   const int R1 = int(R1_);
   const int nblk = gt_blocks(n_);
   const int64_t chunk = (n_ + nblk - 1) / nblk;
@@ -938,11 +971,20 @@ void Woodbury::apply(const double* w, double* out, const double* dot_with, doubl
     spd_solve(W_.as<double>(), WT_.as<double>(), ldc_, R1, t_.as<double>(), y_.as<double>(), s_.as<double>(), st);
   }
   if (r_ > 0) gemv_skinny(F_, ldf_, n_, r_, s_.as<double>(), Fs_.as<double>(), st);
+  if (up && dot_with && n_ <= kOneBlockN) {
+    wood_out_p_one_kernel<<<1, kOneBlockThreads, 0, st>>>(n_, int(r_), L_, g_.as<double>(), Fs_.as<double>(),
+                                                          s_.as<double>(), out, dot_with, up->sc, up->rz_old,
+                                                          up->rz_new, up->sump, up->first ? 1 : 0, up->p, up->p32);
+    KQR_LAUNCH_CHECK();
+    return;
+  }
   const RedShape g = red_shape(n_);
   wood_out_kernel<<<g.blocks, g.threads, 0, st>>>(n_, int(r_), L_, g_.as<double>(), Fs_.as<double>(),
                                                   s_.as<double>(), out, dot_with, ws.partials, dot_out);
   KQR_LAUNCH_CHECK();
   if (dot_with && g.blocks > 1) reduce_finalize(ws.partials, int(g.blocks), 1, dot_out, st);
+  if (up)
+    pcg_update_p(n_, out, up->p, up->p32, up->sc, up->rz_old, up->rz_new, up->first, ws, up->sc + up->sump, st);
 }
 
 }  // namespace kqr
