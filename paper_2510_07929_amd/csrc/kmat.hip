@@ -11,6 +11,7 @@
 #include <atomic>
 #include <cmath>
 #include <mutex>
+#include <type_traits>
 #include <vector>
 
 namespace kqr {
@@ -1639,14 +1640,21 @@ void kapply_otf(const float* Xr, const float* sqr, int64_t nr, const float* Xc, 
 }
 
 // ================================================================= K build on the matrix cores
-// RBF with p <= 32: the Gram term of every 16 x 16 block by six
-// v_mfma_f32_16x16x32_bf16 on the exact BF16x3 split of both sides (as the
-// on-the-fly applies), with the norms and the exponent's scale folded into
+// RBF with p <= 32: the Gram term of every 16 x 16 block on the matrix cores
+// (v_mfma_f32_16x16x32_bf16) from the exact BF16x3 split of both sides (as
+// the on-the-fly applies), with the norms and the exponent's scale folded into
 // the spare coordinates when p <= 30 (the matrix cores then return
 // c d_ij, c = -gamma log2(e)), so an entry costs the lanes a clamp, the
 // exponential, the diagonal test and its share of a store.  Both sides are
 // split once per build into buffers of 96 halves per point (row side
 // [x, 1, q], column side [-2 c x, c q, c]; without the fold [x] and [-2 x]).
+// FP32 storage takes all six significant products.  BF16 storage takes the
+// three leading ones (hi.hi, hi.mid, mid.hi): the dropped ones are at most
+// 3 2^-16 sum_k |a_k| |b_k|, and that sum is at most 2 |c| (q_i + q_j)
+// (2 |x_i . x_j| <= q_i + q_j), so the entry moves by a relative
+// 3 2^-15 gamma (q_i + q_j) at most.  The three products are used only when
+// gamma max_i q_i <= 16 / 3, which keeps that below 2^-10, a quarter of
+// BF16's unit roundoff 2^-8; inputs far from the origin get the six.
 //
 // Operand roles: the A operand carries 16 columns j of K and the B operand
 // 16 rows i, so the lane that receives C[4 g + r][l] holds K[i0 + l][j0 +
@@ -1676,7 +1684,7 @@ template <bool AUG, bool BF, bool PACKED>
 __global__ __launch_bounds__(256) void kbuild_b3_kernel(const uint16_t* __restrict__ Pr, const uint16_t* __restrict__ Sc,
                                                         const float* __restrict__ q, int64_t n, float ng,
                                                         void* __restrict__ Kout, int64_t ldk, int64_t nt,
-                                                        int64_t cols) {
+                                                        int64_t cols, const float* __restrict__ qmax, float qlim) {
   // a wave's slab: 32 rows x 64 entries, FP32 or (BF16 storage) the rounded BF16 values
   __shared__ __align__(16) float slab[4][32][kBuildSlab];
   typedef uint16_t bslab_row[2 * kBuildSlab];
@@ -1715,118 +1723,164 @@ __global__ __launch_bounds__(256) void kbuild_b3_kernel(const uint16_t* __restri
     bl[s] = *reinterpret_cast<const bf16x8_t*>(Pr + ic * kB3Stride + 64 + 8 * lg);
     qi[s] = AUG ? 0.f : q[ic];
   }
+  const uint32_t col_off = uint32_t(li) * kB3Stride + 8 * lg;  // this lane's column part within a block
   float (*sl)[kBuildSlab] = slab[wave];
   bslab_row* bsl = reinterpret_cast<bslab_row*>(slab[wave]);  // BF16 view: rows of 2 kBuildSlab halves
-  for (int64_t jb = cbeg; jb < cend; jb += kBuildStep) {
-    // the column parts of the whole step are requested at once: one L2 round
-    // trip per step instead of one per 16-column block
-    bf16x8_t ahs[kBuildStep / 16], ams[kBuildStep / 16], als[kBuildStep / 16];
+  // BF16 storage: three products when the largest squared norm allows (see
+  // above); one instantiation of the step loop per case, chosen once
+  auto steps = [&](auto three_c) {
+    constexpr bool three = decltype(three_c)::value;
+    for (int64_t jb = cbeg; jb < cend; jb += kBuildStep) {
+      // the column parts of the whole step are requested at once: one L2 round
+      // trip per step instead of one per 16-column block
+      bf16x8_t ahs[kBuildStep / 16], ams[kBuildStep / 16], als[kBuildStep / 16];
+      if (jb + kBuildStep <= n) {  // (uniform) whole step inside: a scalar base per block, the lane's offset fixed
 #pragma unroll
-    for (int blk = 0; blk < kBuildStep / 16; ++blk) {
-      const int64_t jc = min(jb + 16 * blk + li, n - 1);  // columns past n: any valid point (written as 0)
-      ahs[blk] = *reinterpret_cast<const bf16x8_t*>(Sc + jc * kB3Stride + 8 * lg);
-      ams[blk] = *reinterpret_cast<const bf16x8_t*>(Sc + jc * kB3Stride + 32 + 8 * lg);
-      als[blk] = *reinterpret_cast<const bf16x8_t*>(Sc + jc * kB3Stride + 64 + 8 * lg);
-    }
-    // Gram blocks: the two strips' product chains interleaved, and the next
-    // block's MFMAs issued before this block's exponentials
-    auto gram = [&](int blk, f32x4_t* c) {
-      const bf16x8_t ah = ahs[blk], am = ams[blk], al = als[blk];
-      c[0] = f32x4_t{0.f, 0.f, 0.f, 0.f};
-      c[1] = f32x4_t{0.f, 0.f, 0.f, 0.f};
-      // smallest products first
-      c[0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bm[0], c[0], 0, 0, 0);
-      c[1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bm[1], c[1], 0, 0, 0);
-      c[0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[0], c[0], 0, 0, 0);
-      c[1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[1], c[1], 0, 0, 0);
-      c[0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[0], c[0], 0, 0, 0);
-      c[1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[1], c[1], 0, 0, 0);
-      c[0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bh[0], c[0], 0, 0, 0);
-      c[1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bh[1], c[1], 0, 0, 0);
-      c[0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bm[0], c[0], 0, 0, 0);
-      c[1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bm[1], c[1], 0, 0, 0);
-      c[0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[0], c[0], 0, 0, 0);
-      c[1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[1], c[1], 0, 0, 0);
-    };
-    f32x4_t cur[2], nxt[2];
-    gram(0, cur);
+        for (int blk = 0; blk < kBuildStep / 16; ++blk) {
+          const uint16_t* cb = Sc + (jb + 16 * blk) * kB3Stride;
+          ahs[blk] = *reinterpret_cast<const bf16x8_t*>(cb + col_off);
+          ams[blk] = *reinterpret_cast<const bf16x8_t*>(cb + col_off + 32);
+          if constexpr (!three) als[blk] = *reinterpret_cast<const bf16x8_t*>(cb + col_off + 64);
+        }
+      } else {
 #pragma unroll
-    for (int blk = 0; blk < kBuildStep / 16; ++blk) {
-      if (blk + 1 < kBuildStep / 16) gram(blk + 1, nxt);
-      const int64_t j0 = jb + 16 * blk + 4 * lg;  // this lane's four columns j0 .. j0 + 3
-      float qj[4] = {0.f, 0.f, 0.f, 0.f};
-      if (!AUG) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) qj[r] = q[min(j0 + r, n - 1)];
+        for (int blk = 0; blk < kBuildStep / 16; ++blk) {
+          const int64_t jc = min(jb + 16 * blk + li, n - 1);  // columns past n: any valid point (written as 0)
+          ahs[blk] = *reinterpret_cast<const bf16x8_t*>(Sc + jc * kB3Stride + 8 * lg);
+          ams[blk] = *reinterpret_cast<const bf16x8_t*>(Sc + jc * kB3Stride + 32 + 8 * lg);
+          if constexpr (!three) als[blk] = *reinterpret_cast<const bf16x8_t*>(Sc + jc * kB3Stride + 64 + 8 * lg);
+        }
       }
+      // Gram blocks: the two strips' product chains interleaved, and the next
+      // block's MFMAs issued before this block's exponentials
+      auto gram = [&](int blk, f32x4_t* c) {
+        const bf16x8_t ah = ahs[blk], am = ams[blk];
+        c[0] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+        c[1] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+        if constexpr (three) {
+          c[0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bh[0], c[0], 0, 0, 0);
+          c[1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bh[1], c[1], 0, 0, 0);
+          c[0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bm[0], c[0], 0, 0, 0);
+          c[1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bm[1], c[1], 0, 0, 0);
+          c[0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[0], c[0], 0, 0, 0);
+          c[1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[1], c[1], 0, 0, 0);
+          return;
+        }
+        // smallest products first
+        const bf16x8_t al = als[blk];
+        c[0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bm[0], c[0], 0, 0, 0);
+        c[1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bm[1], c[1], 0, 0, 0);
+        c[0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[0], c[0], 0, 0, 0);
+        c[1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[1], c[1], 0, 0, 0);
+        c[0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[0], c[0], 0, 0, 0);
+        c[1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[1], c[1], 0, 0, 0);
+        c[0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bh[0], c[0], 0, 0, 0);
+        c[1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bh[1], c[1], 0, 0, 0);
+        c[0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bm[0], c[0], 0, 0, 0);
+        c[1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bm[1], c[1], 0, 0, 0);
+        c[0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[0], c[0], 0, 0, 0);
+        c[1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[1], c[1], 0, 0, 0);
+      };
+      f32x4_t cur[2], nxt[2];
+      gram(0, cur);
 #pragma unroll
-      for (int s = 0; s < 2; ++s) {
-        const f32x4_t c = cur[s];
-        const int64_t iblk = wrow + 16 * s, jblk = jb + 16 * blk;
-        f32x4_t e;
-        // ng < 0 and d >= 0, so the entry is exp2(min(ng d, 0)) = min(exp2(ng d), 1): the
-        // clamp to [0, 1] rides on the exponential as its output modifier
+      for (int blk = 0; blk < kBuildStep / 16; ++blk) {
+        if (blk + 1 < kBuildStep / 16) gram(blk + 1, nxt);
+        const int64_t j0 = jb + 16 * blk + 4 * lg;  // this lane's four columns j0 .. j0 + 3
+        float qj[4] = {0.f, 0.f, 0.f, 0.f};
+        if (!AUG) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
-          e[r] = __builtin_amdgcn_fmed3f(kexp2(AUG ? c[r] : ng * (qi[s] + qj[r] + c[r])), 0.f, 1.f);
-        if (iblk == jblk || iblk + 16 > n || jblk + 16 > n) {  // (uniform) diagonal or ragged block
-          const int64_t i = iblk + li;
+          for (int r = 0; r < 4; ++r) qj[r] = q[min(j0 + r, n - 1)];
+        }
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int64_t j = j0 + r;
-            e[r] = (j < n && i < n) ? (i == j ? 1.f : e[r]) : 0.f;
+        for (int s = 0; s < 2; ++s) {
+          const f32x4_t c = cur[s];
+          const int64_t iblk = wrow + 16 * s, jblk = jb + 16 * blk;
+          f32x4_t e;
+          // ng < 0 and d >= 0, so the entry is exp2(min(ng d, 0)) = min(exp2(ng d), 1): the
+          // clamp to [0, 1] rides on the exponential as its output modifier
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            e[r] = __builtin_amdgcn_fmed3f(kexp2(AUG ? c[r] : ng * (qi[s] + qj[r] + c[r])), 0.f, 1.f);
+          if (iblk == jblk || iblk + 16 > n || jblk + 16 > n) {  // (uniform) diagonal or ragged block
+            // 32-bit tests against the block's valid extents (both blocks start on multiples of 16)
+            const int64_t ri = n - iblk, rj = n - jblk;
+            const int ni = ri < 16 ? int(ri) : 16, nj = rj < 16 ? int(rj) : 16;
+            const bool diag = iblk == jblk;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int jl = 4 * lg + r;
+              e[r] = (jl < nj && li < ni) ? ((diag && jl == li) ? 1.f : e[r]) : 0.f;
+            }
+          }
+          if (BF) {  // round to BF16 here: half the LDS traffic
+            u32x2_t w;
+            w[0] = __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2_t{e[0], e[1]}, bf16x2_t));
+            w[1] = __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2_t{e[2], e[3]}, bf16x2_t));
+            *reinterpret_cast<u32x2_t*>(&bsl[16 * s + li][16 * blk + 4 * lg]) = w;
+          } else {
+            *reinterpret_cast<f32x4_t*>(&sl[16 * s + li][16 * blk + 4 * lg]) = e;
           }
         }
-        if (BF) {  // round to BF16 here: half the LDS traffic
-          u32x2_t w;
-          w[0] = __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2_t{e[0], e[1]}, bf16x2_t));
-          w[1] = __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2_t{e[2], e[3]}, bf16x2_t));
-          *reinterpret_cast<u32x2_t*>(&bsl[16 * s + li][16 * blk + 4 * lg]) = w;
-        } else {
-          *reinterpret_cast<f32x4_t*>(&sl[16 * s + li][16 * blk + 4 * lg]) = e;
-        }
+        cur[0] = nxt[0];
+        cur[1] = nxt[1];
       }
-      cur[0] = nxt[0];
-      cur[1] = nxt[1];
-    }
-    __syncthreads();  // the slab is complete (each wave reads only its own)
-    if (BF) {
-      // a row is 64 BF16 = 128 bytes = 8 lanes x 16 bytes; eight rows per store
+      __syncthreads();  // the slab is complete (each wave reads only its own)
+      if (BF) {
+        // a row is 64 BF16 = 128 bytes = 8 lanes x 16 bytes; eight rows per store
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const int rr = 8 * k + (lane >> 3), cc = 8 * (lane & 7);
-        const u32x4_t w = *reinterpret_cast<const u32x4_t*>(&bsl[rr][cc]);
-        const int64_t i = wrow + rr;
-        if (PACKED) {
-          const size_t off = tile_base + size_t(i - rbase) * kPkT + size_t(jb - cbeg + cc);
-          __builtin_nontemporal_store(w, reinterpret_cast<u32x4_t*>(static_cast<uint16_t*>(Kout) + off));
-        } else if (i < n) {
-          const size_t off = size_t(i) * size_t(ldk) + size_t(jb + cc);
-          __builtin_nontemporal_store(w, reinterpret_cast<u32x4_t*>(static_cast<uint16_t*>(Kout) + off));
+        for (int k = 0; k < 4; ++k) {
+          const int rr = 8 * k + (lane >> 3), cc = 8 * (lane & 7);
+          const u32x4_t w = *reinterpret_cast<const u32x4_t*>(&bsl[rr][cc]);
+          const int64_t i = wrow + rr;
+          if (PACKED) {
+            const size_t off = tile_base + size_t(i - rbase) * kPkT + size_t(jb - cbeg + cc);
+            __builtin_nontemporal_store(w, reinterpret_cast<u32x4_t*>(static_cast<uint16_t*>(Kout) + off));
+          } else if (i < n) {
+            const size_t off = size_t(i) * size_t(ldk) + size_t(jb + cc);
+            __builtin_nontemporal_store(w, reinterpret_cast<u32x4_t*>(static_cast<uint16_t*>(Kout) + off));
+          }
         }
-      }
-    } else {
-      // a row is 64 FP32 = 256 bytes = 16 lanes x 16 bytes; four rows per store
+      } else {
+        // a row is 64 FP32 = 256 bytes = 16 lanes x 16 bytes; four rows per store
 #pragma unroll
-      for (int k = 0; k < 8; ++k) {
-        const int rr = 4 * k + (lane >> 4), cc = 4 * (lane & 15);
-        const f32x4_t x = *reinterpret_cast<const f32x4_t*>(&sl[rr][cc]);
-        const int64_t i = wrow + rr;
-        if (PACKED) {
-          const size_t off = tile_base + size_t(i - rbase) * kPkT + size_t(jb - cbeg + cc);
-          __builtin_nontemporal_store(x, reinterpret_cast<f32x4_t*>(static_cast<float*>(Kout) + off));
-        } else if (i < n) {
-          const size_t off = size_t(i) * size_t(ldk) + size_t(jb + cc);
-          __builtin_nontemporal_store(x, reinterpret_cast<f32x4_t*>(static_cast<float*>(Kout) + off));
+        for (int k = 0; k < 8; ++k) {
+          const int rr = 4 * k + (lane >> 4), cc = 4 * (lane & 15);
+          const f32x4_t x = *reinterpret_cast<const f32x4_t*>(&sl[rr][cc]);
+          const int64_t i = wrow + rr;
+          if (PACKED) {
+            const size_t off = tile_base + size_t(i - rbase) * kPkT + size_t(jb - cbeg + cc);
+            __builtin_nontemporal_store(x, reinterpret_cast<f32x4_t*>(static_cast<float*>(Kout) + off));
+          } else if (i < n) {
+            const size_t off = size_t(i) * size_t(ldk) + size_t(jb + cc);
+            __builtin_nontemporal_store(x, reinterpret_cast<f32x4_t*>(static_cast<float*>(Kout) + off));
+          }
         }
       }
+      __syncthreads();  // the slab is free for the next step
     }
-    __syncthreads();  // the slab is free for the next step
-  }
+  };
+  if (BF && *qmax <= qlim) steps(std::true_type{});
+  else steps(std::false_type{});
 }
 
 // Columns per workgroup of the full-layout build.
 constexpr int64_t kBuildCols = 1024;
+
+// out[0] = max_i q_i (one workgroup of 1024 threads)
+__global__ __launch_bounds__(1024) void qmax_kernel(const float* __restrict__ q, int64_t n, float* __restrict__ out) {
+  __shared__ float sh[16];
+  float m = 0.f;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) m = fmaxf(m, q[i]);
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < 16; ++w) m = fmaxf(m, sh[w]);
+    out[0] = fmaxf(m, sh[0]);
+  }
+}
 
 bool kbuild_mfma(const float* X, const float* q, int64_t n, int p, KernelSpec ks, int dtype, void* K, int64_t ldk,
                  int layout, hipStream_t st) {
@@ -1836,9 +1890,15 @@ bool kbuild_mfma(const float* X, const float* q, int64_t n, int p, KernelSpec ks
   const float ng = -float(ks.gamma) * kLog2e;
   uint16_t* buf = nullptr;
   const size_t half_bytes = size_t(n) * kB3Stride * sizeof(uint16_t);
-  KQR_CHECK_HIP(hipMallocAsync(reinterpret_cast<void**>(&buf), 2 * half_bytes, st));
+  KQR_CHECK_HIP(hipMallocAsync(reinterpret_cast<void**>(&buf), 2 * half_bytes + 256, st));
   uint16_t* Pr = buf;                      // row side
   uint16_t* Sc = buf + size_t(n) * kB3Stride;  // column side (scaled)
+  float* qmax = reinterpret_cast<float*>(buf + 2 * size_t(n) * kB3Stride);
+  const float qlim = float(16.0 / (3.0 * ks.gamma));  // three products when max q <= qlim
+  if (bf) {
+    qmax_kernel<<<1, 1024, 0, st>>>(q, n, qmax);
+    KQR_LAUNCH_CHECK();
+  }
   const dim3 sgrid((unsigned)((n * 4 + 255) / 256));
   if (aug) {
     kotf_split_cols_kernel<true, false><<<sgrid, 256, 0, st>>>(X, q, n, p, ng, Pr);
@@ -1853,7 +1913,7 @@ bool kbuild_mfma(const float* X, const float* q, int64_t n, int p, KernelSpec ks
   if (layout == 1) grid = dim3((unsigned)packed_tile_count(n));
   else grid = dim3((unsigned)((n + 127) / 128), (unsigned)((ldk + kBuildCols - 1) / kBuildCols));
 #define KQR_B3(A, B, P) \
-  kbuild_b3_kernel<A, B, P><<<grid, 256, 0, st>>>(Pr, Sc, q, n, ng, K, ldk, nt, kBuildCols)
+  kbuild_b3_kernel<A, B, P><<<grid, 256, 0, st>>>(Pr, Sc, q, n, ng, K, ldk, nt, kBuildCols, qmax, qlim)
   if (layout == 1) {
     if (aug && bf) KQR_B3(true, true, true);
     else if (aug) KQR_B3(true, false, true);

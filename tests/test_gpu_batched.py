@@ -11,6 +11,7 @@ from oracle import kernel as okernel
 from oracle import problem as oproblem
 from oracle import solver as osolver
 from paper_2510_07929_amd import inputs, kqr
+from tests.test_gpu_parity import BF16_REL  # BF16-stored entry: relative part of its bound
 
 pytestmark = pytest.mark.gpu
 U32 = 2.0 ** -24
@@ -55,8 +56,8 @@ def test_kv_multi_rhs_matches_oracle(dev, kd, n, m):
         # FP32 entries, V rounded to FP32, FP32 accumulation over 256-column stages
         bound = Kb @ A + 300 * U32 * (Kref @ A)
     else:
-        # BF16 entries (2^-8 relative), V split into hi + lo BF16 parts (2^-16)
-        bound = (2.0 ** -8 * (Kref + Kb) + Kb) @ A + (2.0 ** -15 + 300 * U32) * (Kref @ A)
+        # BF16 entries (BF16_REL), V split into hi + lo BF16 parts (2^-16)
+        bound = (BF16_REL * Kref + (1.0 + 2.0 ** -8) * Kb) @ A + (2.0 ** -15 + 300 * U32) * (Kref @ A)
     err = np.abs(U - Kref @ V)
     assert np.all(err <= bound + 1e-12), float((err / (bound + 1e-12)).max())
 
@@ -76,7 +77,7 @@ def test_kv_every_launch_shape_and_autotuner(dev, kd):
     if kd == "fp32":
         bound = Kb @ A + 300 * U32 * (Kref @ A)
     else:
-        bound = (2.0 ** -8 * (Kref + Kb) + Kb) @ A + (2.0 ** -15 + 300 * U32) * (Kref @ A)
+        bound = (BF16_REL * Kref + (1.0 + 2.0 ** -8) * Kb) @ A + (2.0 ** -15 + 300 * U32) * (Kref @ A)
     ref = Kref @ V
     say("K V shapes", kd)
     outs = []

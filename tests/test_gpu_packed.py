@@ -12,6 +12,7 @@ from oracle import kernel as okernel
 from oracle import problem as oproblem
 from oracle import solver as osolver
 from paper_2510_07929_amd import inputs, kqr
+from tests.test_gpu_parity import BF16_REL  # BF16-stored entry: relative part of its bound
 
 pytestmark = pytest.mark.gpu
 U32 = 2.0 ** -24
@@ -79,7 +80,7 @@ def _bound(X, gamma, kd, v):
     dd = 4.0 * (p + 2) * U32 * (q[:, None] + q[None, :]) + 2.0 * U32 * D
     Kb = K * (gamma * dd + 8.0 * U32)
     if kd == "bf16":
-        Kb = 2.0 ** -8 * (K + Kb) + Kb
+        Kb = BF16_REL * K + (1.0 + 2.0 ** -8) * Kb
     return K, Kb @ np.abs(v) + 300 * U32 * (K @ np.abs(v))
 
 

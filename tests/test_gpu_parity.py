@@ -22,6 +22,11 @@ from paper_2510_07929_amd import inputs, kqr
 pytestmark = pytest.mark.gpu
 
 U32 = 2.0 ** -24
+# A BF16-stored RBF entry: round-to-nearest (unit roundoff 2^-8) of a value that
+# the build's three-product Gram may move by up to 2^-10 relative (the build
+# takes three products only within that limit), on top of the FP32 error Kb:
+# |K_bf16 - K| <= BF16_REL K + (1 + 2^-8) Kb
+BF16_REL = 2.0 ** -8 + 2.0 ** -10 * (1.0 + 2.0 ** -8)
 
 
 def say(*a):
@@ -68,25 +73,42 @@ def test_kernel_build_fp32(dev, kind, n, p):
     assert np.all(err <= bound), float((err / bound).max())
 
 
-@pytest.mark.parametrize("kind", ["rbf", "laplacian"])
-def test_kernel_build_bf16(dev, kind):
+def three_product_term(X, kind, gamma):
+    """Relative change of a BF16-stored RBF entry from the Gram's three leading
+    BF16 products (used when gamma max q <= 16/3): 3 2^-15 gamma (q_i + q_j)."""
+    q = (X.astype(np.float64) ** 2).sum(1)
+    if kind != "rbf" or X.shape[1] > 32 or gamma * q.max() > 16.0 / 3.0:
+        return 0.0
+    return 3.0 * 2.0 ** -15 * gamma * (q[:, None] + q[None, :])
+
+
+# (scale, shift) of the inputs: on [-1, 1]^p; stretched so that gamma max q
+# sits just under the three-product limit; moved far from the origin, where the
+# build takes all six products
+@pytest.mark.parametrize("kind,scale,shift", [("rbf", 1.0, 0.0), ("laplacian", 1.0, 0.0),
+                                              ("rbf", 2.25, 0.0), ("rbf", 1.0, 20.0)])
+def test_kernel_build_bf16(dev, kind, scale, shift):
     n, p = 1000, 10
     X, _ = inputs.smooth(n, p, (102, 0))
+    X = (X * np.float32(scale) + np.float32(shift)).astype(np.float32)
     gamma = 0.1
-    say("kernel_build bf16", kind)
+    say("kernel_build bf16", kind, scale, shift)
     K = kqr.kqr_kernel_build(torch.from_numpy(X).to(dev), kind, gamma, "bf16").float().cpu().numpy()
     Kref, bound = entry_bound(X, kind, gamma)
-    # BF16 round-to-nearest of the FP32 value: relative 2^-8 (8-bit significand) on top of the FP32 bound
+    # BF16 round-to-nearest (unit roundoff 2^-8) of the FP32 value, whose
+    # error is the FP32 bound plus, with three Gram products, their term
+    extra = Kref * three_product_term(X, kind, gamma)
     err = np.abs(K[:, :n].astype(np.float64) - Kref)
-    assert np.all(err <= 2.0 ** -8 * (Kref + bound) + bound)
+    assert np.all(err <= 2.0 ** -8 * (Kref + bound + extra) + bound + extra)
     assert np.all(K[:, n:] == 0.0)
+    assert np.all(np.diag(K[:, :n]) == 1.0)
 
 
 # --------------------------------------------------------------------- K-apply
 def _apply_bound(Kb, Kref, v, mode, bf16=False, otf=False):
     a = np.abs(v)
     if bf16:
-        ent = 2.0 ** -8 * (Kref + Kb) + Kb
+        ent = BF16_REL * Kref + (1.0 + 2.0 ** -8) * Kb
     else:
         ent = Kb
     # rounding of v to FP32 (fast), FP32 products, FP32 partial sums of <= 64 terms
