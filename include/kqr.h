@@ -186,6 +186,14 @@ int kqr_device_count(void);
  * Returns KQR_OK, or KQR_EINVAL for negative arguments.  Touches no device. */
 int kqr_test_core_breakdowns(int skip, int count);
 
+/* Test hook for kqr_fit_batch: on = 0 makes the problems' PCG iterations run
+ * their vector and preconditioner kernels one problem at a time after each
+ * batched K-apply instead of in the batched launches (on = 1, the default);
+ * the results are the same either way (process-wide, read when a solve
+ * starts).  Returns KQR_OK, or KQR_EINVAL unless on is 0 or 1.  Touches no
+ * device. */
+int kqr_test_batch_steps(int on);
+
 /* ---------------------------------------------------------------- kernel matrix
  * kqr_kernel_build: materialise K_ij = k(x_i, x_j) (Section 1) into K.
  *  X      device, n x p FP32, row-major (ld = p).
@@ -490,7 +498,11 @@ int kqr_fit_path(const float* X, const double* y, int64_t n, int64_t p, double t
  * preconditioner (built interleaved on the batch's streams); the fast
  * K-applies of all problems still running go out as one persistent launch
  * whose workgroups take (problem, 32-row block) items from a device queue,
- * largest problems first.
+ * largest problems first.  When a K-apply is a PCG iteration's (Algorithm 3's
+ * solves with the Woodbury preconditioner of Lemma 1) of a problem with
+ * n[i] <= 16384 and a preconditioner rank below 128, the same launch sequence
+ * then runs the rest of that iteration for all such problems in five batched
+ * launches (the single-problem kernels' code per problem, so the same results).
  *  X, y, alpha: host arrays of nprob device pointers (n[i] x p FP32, n[i] FP64,
  *  n[i] FP64); tau, lambda, gamma, n: host arrays; beta, status: host nprob;
  *  info: host nprob (may be NULL).  1 <= nprob <= 256. */

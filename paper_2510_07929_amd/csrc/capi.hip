@@ -413,6 +413,12 @@ int kqr_test_core_breakdowns(int skip, int count) {
   return KQR_OK;
 }
 
+int kqr_test_batch_steps(int on) {
+  if (on != 0 && on != 1) return KQR_EINVAL;
+  set_batch_steps(on == 1);
+  return KQR_OK;
+}
+
 int kqr_device_count(void) {
   int c = 0;
   if (hipGetDeviceCount(&c) != hipSuccess) {

@@ -102,12 +102,18 @@ struct Exec {
   Exec& operator=(const Exec&) = delete;
 };
 
+struct PcgStepDesc;
+
 // Batched K-apply request of one fit: out = K v (fast: FP32 products; exact:
-// the exact operator), served by a BatchLauncher.
+// the exact operator), served by a BatchLauncher.  With step (a launcher
+// whose steps_ok() holds), the launch also runs the rest of that fit's PCG
+// iteration after the K-apply (pstep.h); the descriptor lives in the
+// suspended fit until the launch has been enqueued.
 struct ApplyReq {
   const double* v = nullptr;
   double* out = nullptr;
   bool exact = false;
+  const PcgStepDesc* step = nullptr;
 };
 
 // One launch for the K-apply requests of several fits (a shared K: K V; or
@@ -117,7 +123,11 @@ class BatchLauncher {
   virtual ~BatchLauncher() = default;
   // slots[i] asks for reqs[i]; launched on st.
   virtual void launch(const std::vector<int>& slots, const std::vector<ApplyReq>& reqs, hipStream_t st) = 0;
+  // The rest of the PCG iterations of the requests that carry a step (after
+  // launch, on the same stream; launchers whose steps_ok() holds).
+  virtual void launch_steps(const std::vector<ApplyReq>& /*reqs*/, hipStream_t /*st*/) {}
   virtual bool exact_ok() const { return false; }
+  virtual bool steps_ok() const { return false; }  // serves ApplyReq::step
 };
 
 // Meeting point of the host threads that drive a batch (one Scheduler per
@@ -136,6 +146,7 @@ class Rendezvous {
   void arrive(const std::vector<hipStream_t>& streams, const std::vector<int>& ids, const std::vector<ApplyReq>& reqs);
   void leave();  // the calling thread has no live fit left
   bool exact_ok() const { return launcher_->exact_ok(); }
+  bool steps_ok() const { return launcher_->steps_ok(); }
   int64_t launches() const { return launches_; }
   double device_seconds();  // summed time of the batched launches (profile on)
 
@@ -181,6 +192,7 @@ class Scheduler {
   void park_read(int slot, std::coroutine_handle<> h, hipEvent_t ev);
   void park_apply(int slot, std::coroutine_handle<> h, hipStream_t st, ApplyReq r);
   bool exact_ok() const { return rv_ && rv_->exact_ok(); }
+  bool steps_ok() const { return rv_ && rv_->steps_ok(); }
 
  private:
   enum State { kRun, kRead, kApply, kDone };

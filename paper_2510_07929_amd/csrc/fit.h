@@ -71,6 +71,7 @@ void fit_batch(int nprob, const float* const* X, const double* const* y, const i
 
 std::vector<double> default_uniforms(uint64_t seed, int64_t count);
 void set_batch_threads(int t);  // host threads of the batched fits (0: min(16, cores))
+void set_batch_steps(bool on);   // kqr_fit_batch runs PCG iterations' vector work batched (default on)
 double wall_seconds();
 
 }  // namespace kqr

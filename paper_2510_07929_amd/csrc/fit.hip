@@ -222,12 +222,17 @@ class KvLauncher : public BatchLauncher {
   DevBuf V_, U_, part_;
 };
 
+// Whether the problem batches also run their PCG iterations' vector and
+// preconditioner work in batched launches (kqr_test_batch_steps).
+std::atomic<bool> g_batch_steps{true};
+
 // Different K_i: one launch over (problem, row block) pairs, dealt to the
-// workgroups from a queue (problems_launch).
+// workgroups from a queue (problems_launch), then the batched PCG steps.
 class ProblemLauncher : public BatchLauncher {
  public:
   ProblemLauncher(std::vector<KMat> km, std::vector<int64_t> n) : km_(std::move(km)), n_(std::move(n)),
-                                                                   q_(km_.size()) {}
+                                                                   q_(km_.size()), steps_(km_.size()) {}
+  bool steps_ok() const override { return g_batch_steps.load(); }
   void launch(const std::vector<int>& slots, const std::vector<ApplyReq>& reqs, hipStream_t st) override {
     // largest problems first: their items (the longest rows) are taken
     // first, so the launch does not end on a tail of long items
@@ -250,11 +255,19 @@ class ProblemLauncher : public BatchLauncher {
     }
     q_.launch(tasks, st);
   }
+  // the rest of the PCG iterations that came with their K-applies
+  void launch_steps(const std::vector<ApplyReq>& reqs, hipStream_t st) override {
+    std::vector<PcgStepDesc> steps;
+    for (const ApplyReq& r : reqs)
+      if (r.step) steps.push_back(*r.step);
+    steps_.launch(steps, st);
+  }
 
  private:
   std::vector<KMat> km_;
   std::vector<int64_t> n_;
   ProblemQueue q_;
+  PcgStepBatch steps_;
 };
 
 // ================================================================= drivers
@@ -388,6 +401,7 @@ void free_all(std::vector<void*>& ptrs) {
 }  // namespace
 
 void set_batch_threads(int t) { g_batch_threads.store(t); }
+void set_batch_steps(bool on) { g_batch_steps.store(on); }
 
 void fit_levels(const float* X, const double* y, int64_t n, int p, KernelSpec ks, const double* taus,
                 const double* lams, int nlev, const kqr_options& o_in, double* alpha, double* beta, kqr_info* info,

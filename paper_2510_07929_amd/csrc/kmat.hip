@@ -6,6 +6,7 @@
 // -gamma log2(e) d on the transcendental unit (kexp2).
 #include "kernel_entry.h"
 #include "kqr_internal.h"
+#include "pstep.h"
 
 #include <algorithm>
 #include <atomic>
@@ -1987,16 +1988,16 @@ void kernel_row(const KMat& km, const float* X, const float* sqn, int64_t n, int
 // 16 lanes per row (4 rows per wave at a time, 4 such row slots per wave):
 // a lane reads 16-byte pieces of its row 64 columns apart, x sits in LDS, and
 // a 4-step shuffle reduction inside each 16-lane group finishes 4 rows at once.
-__global__ __launch_bounds__(256) void gemv_skinny_kernel(const float* __restrict__ A, int64_t lda, int64_t nrows,
-                                                          int ncols, const double* __restrict__ x,
-                                                          double* __restrict__ y) {
+// (Workgroup blk of the launch; the body also serves the batched PCG steps.)
+__device__ __forceinline__ void gemv_skinny_body(const float* __restrict__ A, int64_t lda, int64_t nrows, int ncols,
+                                                 const double* __restrict__ x, double* __restrict__ y, int blk) {
   __shared__ double xs[1024 + 4];
   for (int k = threadIdx.x; k < ncols; k += 256) xs[k] = x[k];
   for (int k = ncols + threadIdx.x; k < ((ncols + 3) & ~3); k += 256) xs[k] = 0.0;
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int g = lane >> 4, t = lane & 15;
-  const int64_t wrow0 = (int64_t(blockIdx.x) * 4 + wave) * 16;
+  const int64_t wrow0 = (int64_t(blk) * 4 + wave) * 16;
   const int nvec = ncols >> 2;
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   const float* rows[4];
@@ -2034,6 +2035,29 @@ __global__ __launch_bounds__(256) void gemv_skinny_kernel(const float* __restric
     }
   }
 }
+
+__global__ __launch_bounds__(256) void gemv_skinny_kernel(const float* __restrict__ A, int64_t lda, int64_t nrows,
+                                                          int ncols, const double* __restrict__ x,
+                                                          double* __restrict__ y) {
+  gemv_skinny_body(A, lda, nrows, ncols, x, y, int(blockIdx.x));
+}
+
+// Batched PCG steps: Fs = F s_{1..rank} of every fit with rank > 0, each
+// over its range of workgroups (64 rows each).
+__global__ __launch_bounds__(256) void wood_fs_steps_kernel(const PcgStepDesc* __restrict__ d,
+                                                            const int* __restrict__ first, int nf) {
+  const int f = step_of_block(first, nf, int(blockIdx.x));
+  const PcgStepDesc& e = d[f];
+  gemv_skinny_body(e.F, e.ldf, e.n, e.rank, e.s, e.Fs, int(blockIdx.x) - first[f]);
+}
+
+void launch_wood_fs_steps(const PcgStepDesc* d, const int* fs_first, int nf, int total, hipStream_t st) {
+  if (nf <= 0 || total <= 0) return;
+  wood_fs_steps_kernel<<<total, 256, 0, st>>>(d, fs_first, nf);
+  KQR_LAUNCH_CHECK();
+}
+
+int pcg_step_fs_blocks(const PcgStepDesc& d) { return d.rank > 0 ? int((d.n + 63) / 64) : 0; }
 
 void gemv_skinny(const float* A, int64_t lda, int64_t nrows, int64_t ncols, const double* x, double* y,
                  hipStream_t st) {

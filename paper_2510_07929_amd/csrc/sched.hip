@@ -90,10 +90,11 @@ void Rendezvous::fire_locked() {
       KQR_CHECK_HIP(hipEventRecord(a, bst_));
     }
     launcher_->launch(ids_, reqs_, bst_);
-    if (profile_) {
+    if (profile_) {  // the K-apply alone
       KQR_CHECK_HIP(hipEventRecord(b, bst_));
       spans_.emplace_back(a, b);
     }
+    launcher_->launch_steps(reqs_, bst_);
     KQR_CHECK_HIP(hipEventRecord(done_, bst_));
   } catch (...) {
     failed_ = true;

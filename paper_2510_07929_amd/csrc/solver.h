@@ -23,6 +23,11 @@ class Operator {
   [[nodiscard]] ApplyAwait apply_fast(const double* v, const float* v32, double* u, Exec& ex);
   // Exact apply: FP32 entries (stored FP32 or recomputed) with FP64 vector and sums.
   [[nodiscard]] ApplyAwait apply_exact(const double* v, double* u, Exec& ex);
+  // Whether ex's batched launches can also run the rest of a PCG iteration
+  // (pstep.h); then apply_fast_step hands the fast apply u = K v together with
+  // that iteration's descriptor.
+  bool steps_batched(const Exec& ex) const { return batched_ && ex.sched && ex.sched->steps_ok(); }
+  [[nodiscard]] ApplyAwait apply_fast_step(const double* v, double* u, const PcgStepDesc* step, Exec& ex);
   bool materialized() const { return km_.K != nullptr; }
   int64_t calls() const { return calls_; }
   const KMat& kmat() const { return km_; }

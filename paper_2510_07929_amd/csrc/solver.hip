@@ -117,6 +117,12 @@ ApplyAwait Operator::apply_fast(const double* v, const float* v32, double* u, Ex
   return {};
 }
 
+ApplyAwait Operator::apply_fast_step(const double* v, double* u, const PcgStepDesc* step, Exec& ex) {
+  if (!steps_batched(ex)) fail(KQR_EHIP, "internal: batched PCG step without a launcher that runs it");
+  ++calls_;
+  return ApplyAwait{&ex, ApplyReq{v, u, false, step}};
+}
+
 ApplyAwait Operator::apply_exact(const double* v, double* u, Exec& ex) {
   ++calls_;
   const hipStream_t st = ex.st;
@@ -190,12 +196,41 @@ Co<PcgStats> Pcg::solve(double c, const double* L, Woodbury* P, const double* b,
       pcg_update_p(n, pb_.zz.as<double>(), pb_.p.as<double>(), p32, sc, rz_old, rz_new, first, ws_, sc + SUMP, st);
     }
   };
+  // In a batch whose launcher runs the rest of the iteration after the K-apply
+  // (pstep.h), the iteration is one request: K p, then q, x, r, K x and, before
+  // this fit has read rr, the preconditioner and the direction update (dropped
+  // when the solve stops here).  Same kernel bodies, same results.
+  PcgStepDesc step;
+  const bool batched_step = fast && P && op_.steps_batched(ex_) && P->step_desc(step);
+  if (batched_step) {
+    step.n = n;
+    step.Kp = pb_.Kp.as<double>();
+    step.L = L;
+    step.c = c;
+    step.sc = sc;
+    step.sump = SUMP;
+    step.pq = PQ;
+    step.rr = RR;
+    step.q = pb_.q.as<double>();
+    step.x = x;
+    step.r = pb_.r.as<double>();
+    step.Kx = Kx;
+    step.p = pb_.p.as<double>();
+    step.p32 = p32;
+    step.zz = pb_.zz.as<double>();
+  }
   precond_p(RZ0, RZ0, true);
   for (int it = 1; it <= maxit; ++it) {
-    if (fast) co_await op_.apply_fast(pb_.p.as<double>(), p32, pb_.Kp.as<double>(), ex_);
-    else co_await op_.apply_exact(pb_.p.as<double>(), pb_.Kp.as<double>(), ex_);
-    pcg_qxr(n, pb_.Kp.as<double>(), pb_.p.as<double>(), L, c, sc, SUMP, cur == 0 ? RZ0 : RZ1, PQ, RR,
-            pb_.q.as<double>(), x, pb_.r.as<double>(), Kx, ws_, st);
+    if (batched_step) {
+      step.rz = cur == 0 ? RZ0 : RZ1;
+      step.rz_new = cur == 0 ? RZ1 : RZ0;
+      co_await op_.apply_fast_step(pb_.p.as<double>(), pb_.Kp.as<double>(), &step, ex_);
+    } else {
+      if (fast) co_await op_.apply_fast(pb_.p.as<double>(), p32, pb_.Kp.as<double>(), ex_);
+      else co_await op_.apply_exact(pb_.p.as<double>(), pb_.Kp.as<double>(), ex_);
+      pcg_qxr(n, pb_.Kp.as<double>(), pb_.p.as<double>(), L, c, sc, SUMP, cur == 0 ? RZ0 : RZ1, PQ, RR,
+              pb_.q.as<double>(), x, pb_.r.as<double>(), Kx, ws_, st);
+    }
     double two[2];
     co_await read_back(ex_, sc + PQ, 2 * sizeof(double), two);  // [PQ, RR]
     stats.iters = it;
@@ -206,7 +241,7 @@ Co<PcgStats> Pcg::solve(double c, const double* L, Woodbury* P, const double* b,
     }
     if (stats.resnorm <= tol) break;
     const int nxt = 1 - cur;
-    precond_p(cur == 0 ? RZ0 : RZ1, nxt == 0 ? RZ0 : RZ1, false);
+    if (!batched_step) precond_p(cur == 0 ? RZ0 : RZ1, nxt == 0 ? RZ0 : RZ1, false);
     cur = nxt;
   }
   co_return stats;

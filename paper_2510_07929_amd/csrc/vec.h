@@ -3,6 +3,7 @@
 #pragma once
 
 #include "coro.h"
+#include "pstep.h"
 
 namespace kqr {
 
@@ -97,6 +98,9 @@ class Woodbury {
   void apply(const double* w, double* out, const double* dot_with, double* dot_out, Workspace& ws,
              hipStream_t st, const PUpdate* up = nullptr);
   int64_t rank() const { return r_; }
+  // The preconditioner's part of a batched PCG step (pstep.h): false when the
+  // apply does not fit that form (n > kOneBlockN, r + 1 > kFusedCore).
+  bool step_desc(PcgStepDesc& d) const;
   // Lower triangle of [F 1]^T [F 1] ((r+1) x (r+1), leading dimension r+1).
   const double* gram(hipStream_t st) {
     prepare_gram(st);

@@ -4,6 +4,7 @@
 // writes its sums directly, several are added in a fixed order by
 // `reduce_finalize`.  Runs are bitwise reproducible.
 #include "kqr_internal.h"
+#include "pstep.h"
 #include "reduce.h"
 #include "solver.h"
 
@@ -165,12 +166,12 @@ void pcg_xr(int64_t n, const double* p, const double* q, const double* Kp, doubl
 
 // One workgroup (n <= kOneBlockN): pcg_q and pcg_xr in one launch, with the
 // same per-thread order and block sums as the two kernels (bitwise the same).
-__global__ __launch_bounds__(1024) void pcg_qxr_one_kernel(int64_t n, const double* __restrict__ Kp,
-                                                          const double* __restrict__ p,
-                                                          const double* __restrict__ L, double c, double* sc,
-                                                          int sump_slot, int rz_slot, int pq_slot, int rr_slot,
-                                                          double* __restrict__ q, double* __restrict__ x,
-                                                          double* __restrict__ r, double* __restrict__ Kx) {
+// The body also serves the batched PCG steps (one workgroup per fit).
+__device__ __forceinline__ void pcg_qxr_one_body(int64_t n, const double* __restrict__ Kp,
+                                                 const double* __restrict__ p, const double* __restrict__ L,
+                                                 double c, double* sc, int sump_slot, int rz_slot, int pq_slot,
+                                                 int rr_slot, double* __restrict__ q, double* __restrict__ x,
+                                                 double* __restrict__ r, double* __restrict__ Kx) {
   const double cs = c * sc[sump_slot];
   double acc = 0.0;
   for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
@@ -192,6 +193,27 @@ __global__ __launch_bounds__(1024) void pcg_qxr_one_kernel(int64_t n, const doub
   }
   const double rr = block_sum_all(acc);
   if (threadIdx.x == 0) sc[rr_slot] = rr;
+}
+
+__global__ __launch_bounds__(1024) void pcg_qxr_one_kernel(int64_t n, const double* __restrict__ Kp,
+                                                          const double* __restrict__ p,
+                                                          const double* __restrict__ L, double c, double* sc,
+                                                          int sump_slot, int rz_slot, int pq_slot, int rr_slot,
+                                                          double* __restrict__ q, double* __restrict__ x,
+                                                          double* __restrict__ r, double* __restrict__ Kx) {
+  pcg_qxr_one_body(n, Kp, p, L, c, sc, sump_slot, rz_slot, pq_slot, rr_slot, q, x, r, Kx);
+}
+
+// Batched PCG steps: workgroup f runs fit f's pcg_qxr.
+__global__ __launch_bounds__(1024) void pcg_qxr_steps_kernel(const PcgStepDesc* __restrict__ d) {
+  const PcgStepDesc& e = d[blockIdx.x];
+  pcg_qxr_one_body(e.n, e.Kp, e.p, e.L, e.c, e.sc, e.sump, e.rz, e.pq, e.rr, e.q, e.x, e.r, e.Kx);
+}
+
+void launch_pcg_qxr_steps(const PcgStepDesc* d, int nf, hipStream_t st) {
+  if (nf <= 0) return;
+  pcg_qxr_steps_kernel<<<nf, kOneBlockThreads, 0, st>>>(d);
+  KQR_LAUNCH_CHECK();
 }
 
 void pcg_qxr(int64_t n, const double* Kp, const double* p, const double* L, double c, double* sc, int sump_slot,

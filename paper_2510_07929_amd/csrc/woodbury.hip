@@ -17,6 +17,7 @@
 //    over many workgroups instead of sequential substitutions, and
 //    s = W^T (W t) stays a symmetric positive definite map.
 //  * U s uses a skinny streamed mat-vec with F as the matrix.
+#include "pstep.h"
 #include "reduce.h"
 #include "vec.h"
 
@@ -565,15 +566,16 @@ __global__ void transpose_lower_kernel(const double* __restrict__ W, int64_t ldc
 // the columns a = t + 256 q (R1 <= 1024) and reads eight rows of each per
 // step, all loads issued before any is used (columns past r read column
 // r - 1 and are dropped), so enough bytes are in flight to stream F.
+// (Workgroup blk of the pass; the body also serves the batched PCG steps.)
 template <int NQ>  // NQ = ceil(R1 / 256)
-__global__ __launch_bounds__(256) void wood_gt_kernel(const float* __restrict__ F, int64_t n, int r,
-                                                      int64_t ldf, int R1, const double* __restrict__ L,
-                                                      const double* __restrict__ w, double* __restrict__ g,
-                                                      int64_t chunk, double* __restrict__ part) {
+__device__ __forceinline__ void wood_gt_body(const float* __restrict__ F, int64_t n, int r, int64_t ldf, int R1,
+                                             const double* __restrict__ L, const double* __restrict__ w,
+                                             double* __restrict__ g, int64_t chunk, double* __restrict__ part,
+                                             int blk) {
   constexpr int RU = 8;  // rows per step
   constexpr int nq = NQ;
   __shared__ double gs[kGtStage];
-  const int64_t i0 = int64_t(blockIdx.x) * chunk;
+  const int64_t i0 = int64_t(blk) * chunk;
   const int64_t i1 = min(n, i0 + chunk);
   double acc[4] = {0.0, 0.0, 0.0, 0.0};  // column a = tid + 256 q
   int col[4];
@@ -627,8 +629,16 @@ __global__ __launch_bounds__(256) void wood_gt_kernel(const float* __restrict__ 
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int a = threadIdx.x + 256 * q;
-    if (a < R1) part[int64_t(blockIdx.x) * R1 + a] = acc[q];
+    if (a < R1) part[int64_t(blk) * R1 + a] = acc[q];
   }
+}
+
+template <int NQ>
+__global__ __launch_bounds__(256) void wood_gt_kernel(const float* __restrict__ F, int64_t n, int r,
+                                                      int64_t ldf, int R1, const double* __restrict__ L,
+                                                      const double* __restrict__ w, double* __restrict__ g,
+                                                      int64_t chunk, double* __restrict__ part) {
+  wood_gt_body<NQ>(F, n, r, ldf, R1, L, w, g, chunk, part, int(blockIdx.x));
 }
 
 // t[a] = sum_b part[b][a]: a block per 64 columns, 16 thread rows split the
@@ -676,11 +686,9 @@ __global__ __launch_bounds__(256) void trmv_kernel(const double* __restrict__ M,
 // s = C^{-1} t = W^T (W t), in one workgroup of 1024 threads.  Each of the R1
 // columns (and then rows) gets H = 1024 / C threads, C the power of two at or
 // above R1; their H partial sums are added in a fixed order through LDS.
-constexpr int kFusedCore = 128;
-__global__ __launch_bounds__(1024) void core_solve_kernel(const double* __restrict__ part, int nblk, int R1,
-                                                          const double* __restrict__ W,
-                                                          const double* __restrict__ WT, int64_t ldc,
-                                                          double* __restrict__ s) {
+__device__ __forceinline__ void core_solve_body(const double* __restrict__ part, int nblk, int R1,
+                                                const double* __restrict__ W, const double* __restrict__ WT,
+                                                int64_t ldc, double* __restrict__ s) {
   __shared__ double red[1024];
   __shared__ double t[kFusedCore], y[kFusedCore];
   int C = 1;
@@ -718,6 +726,13 @@ __global__ __launch_bounds__(1024) void core_solve_kernel(const double* __restri
   if (threadIdx.x < R1) s[threadIdx.x] = t[threadIdx.x];
 }
 
+__global__ __launch_bounds__(1024) void core_solve_kernel(const double* __restrict__ part, int nblk, int R1,
+                                                          const double* __restrict__ W,
+                                                          const double* __restrict__ WT, int64_t ldc,
+                                                          double* __restrict__ s) {
+  core_solve_body(part, nblk, R1, W, WT, ldc, s);
+}
+
 // out_i = g_i - (Fs_i + s_r) / L_i ; with dot_with, the sum of dot_with . out
 // (one workgroup up to kOneBlockN rows, else partials for reduce_finalize)
 __global__ __launch_bounds__(1024) void wood_out_kernel(int64_t n, int r, const double* __restrict__ L,
@@ -740,13 +755,12 @@ __global__ __launch_bounds__(1024) void wood_out_kernel(int64_t n, int r, const 
 // direction update p = out + beta p (beta = the new dot over sc[rz_old]),
 // p32, sum(p) -- the same per-thread order and block sums as wood_out_kernel
 // followed by pcg_p_kernel.
-__global__ __launch_bounds__(1024) void wood_out_p_one_kernel(int64_t n, int r, const double* __restrict__ L,
-                                                             const double* __restrict__ g,
-                                                             const double* __restrict__ Fs,
-                                                             const double* __restrict__ s, double* __restrict__ out,
-                                                             const double* __restrict__ dot_with, double* sc,
-                                                             int rz_old, int rz_new, int sump, int first,
-                                                             double* __restrict__ p, float* __restrict__ p32) {
+__device__ __forceinline__ void wood_out_p_one_body(int64_t n, int r, const double* __restrict__ L,
+                                                    const double* __restrict__ g, const double* __restrict__ Fs,
+                                                    const double* __restrict__ s, double* __restrict__ out,
+                                                    const double* __restrict__ dot_with, double* sc, int rz_old,
+                                                    int rz_new, int sump, int first, double* __restrict__ p,
+                                                    float* __restrict__ p32) {
   const double sr = s[r];
   double acc = 0.0;
   for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
@@ -767,6 +781,54 @@ __global__ __launch_bounds__(1024) void wood_out_p_one_kernel(int64_t n, int r, 
   }
   const double sum = block_sum_all(acc);
   if (threadIdx.x == 0) sc[sump] = sum;
+}
+
+__global__ __launch_bounds__(1024) void wood_out_p_one_kernel(int64_t n, int r, const double* __restrict__ L,
+                                                             const double* __restrict__ g,
+                                                             const double* __restrict__ Fs,
+                                                             const double* __restrict__ s, double* __restrict__ out,
+                                                             const double* __restrict__ dot_with, double* sc,
+                                                             int rz_old, int rz_new, int sump, int first,
+                                                             double* __restrict__ p, float* __restrict__ p32) {
+  wood_out_p_one_body(n, r, L, g, Fs, s, out, dot_with, sc, rz_old, rz_new, sump, first, p, p32);
+}
+
+// ---------------------------------------------------------------- batched PCG steps
+// The bodies above, one fit per workgroup (core, output) or per range of
+// workgroups (F^T g); zz = P^{-1} r with r as dot_with, then the direction update.
+__global__ __launch_bounds__(256) void wood_gt_steps_kernel(const PcgStepDesc* __restrict__ d,
+                                                            const int* __restrict__ first, int nf) {
+  const int f = step_of_block(first, nf, int(blockIdx.x));
+  const PcgStepDesc& e = d[f];
+  wood_gt_body<1>(e.F, e.n, e.rank, e.ldf, e.R1, e.Lw, e.r, e.g, e.chunk, e.part, int(blockIdx.x) - first[f]);
+}
+
+__global__ __launch_bounds__(1024) void core_solve_steps_kernel(const PcgStepDesc* __restrict__ d) {
+  const PcgStepDesc& e = d[blockIdx.x];
+  core_solve_body(e.part, e.nblk, e.R1, e.W, e.WT, e.ldc, e.s);
+}
+
+__global__ __launch_bounds__(1024) void wood_out_p_steps_kernel(const PcgStepDesc* __restrict__ d) {
+  const PcgStepDesc& e = d[blockIdx.x];
+  wood_out_p_one_body(e.n, e.rank, e.Lw, e.g, e.Fs, e.s, e.zz, e.r, e.sc, e.rz, e.rz_new, e.sump, 0, e.p, e.p32);
+}
+
+void launch_wood_gt_steps(const PcgStepDesc* d, const int* gt_first, int nf, int total, hipStream_t st) {
+  if (nf <= 0 || total <= 0) return;
+  wood_gt_steps_kernel<<<total, 256, 0, st>>>(d, gt_first, nf);
+  KQR_LAUNCH_CHECK();
+}
+
+void launch_core_solve_steps(const PcgStepDesc* d, int nf, hipStream_t st) {
+  if (nf <= 0) return;
+  core_solve_steps_kernel<<<nf, 1024, 0, st>>>(d);
+  KQR_LAUNCH_CHECK();
+}
+
+void launch_wood_out_p_steps(const PcgStepDesc* d, int nf, hipStream_t st) {
+  if (nf <= 0) return;
+  wood_out_p_steps_kernel<<<nf, kOneBlockThreads, 0, st>>>(d);
+  KQR_LAUNCH_CHECK();
 }
 
 // ---------------------------------------------------------------- class
@@ -944,6 +1006,28 @@ Co<bool> Woodbury::build_two_level(const double* L, const uint8_t* S, double l_i
 
 // Workgroups of the U^T g pass: 64 rows of F each, at most kGtBlocks.
 static int gt_blocks(int64_t n) { return int(std::max<int64_t>(1, std::min<int64_t>(kGtBlocks, (n + 63) / 64))); }
+
+int pcg_step_gt_blocks(const PcgStepDesc& d) { return d.nblk; }
+
+bool Woodbury::step_desc(PcgStepDesc& d) const {
+  if (n_ > kOneBlockN || R1_ > kFusedCore || (r_ > 0 && (ldf_ & 3))) return false;
+  const int nblk = gt_blocks(n_);
+  d.Lw = L_;
+  d.F = F_;
+  d.ldf = ldf_;
+  d.rank = int(r_);
+  d.R1 = int(R1_);
+  d.nblk = nblk;
+  d.chunk = (n_ + nblk - 1) / nblk;
+  d.g = g_.as<double>();
+  d.part = part_.as<double>();
+  d.W = W_.as<double>();
+  d.WT = WT_.as<double>();
+  d.ldc = ldc_;
+  d.s = s_.as<double>();
+  d.Fs = Fs_.as<double>();
+  return true;
+}
 
 void Woodbury::apply(const double* w, double* out, const double* dot_with, double* dot_out, Workspace& ws,
                      hipStream_t st, const PUpdate* up) {

@@ -80,6 +80,7 @@ _SIGS = {
     "kqr_last_error": (C.c_char_p, []),
     "kqr_device_count": (C.c_int, []),
     "kqr_test_core_breakdowns": (C.c_int, [C.c_int, C.c_int]),
+    "kqr_test_batch_steps": (C.c_int, [C.c_int]),
     "kqr_set_batch_threads": (C.c_int, [C.c_int]),
     "kqr_kernel_build": (C.c_int, [_P, _I64, _I64, C.c_int, C.c_double, C.c_int, _P, _I64, _P]),
     "kqr_kernel_apply": (C.c_int, [_P, _I64, _I64, C.c_int, C.c_double, _P, C.c_int, _I64, _P, _I64, _I64,
@@ -232,6 +233,12 @@ def kqr_test_core_breakdowns(skip: int, count: int) -> None:
     """Test hook: after `skip` more Woodbury core factorisations, the next
     `count` report a breakdown (kqr_info.core_retries counts the retries)."""
     _check(lib().kqr_test_core_breakdowns(int(skip), int(count)), "kqr_test_core_breakdowns")
+
+
+def kqr_test_batch_steps(on: bool) -> None:
+    """Test hook: whether kqr_fit_batch runs its problems' PCG iterations
+    (vector and preconditioner kernels) in batched launches (default True)."""
+    _check(lib().kqr_test_batch_steps(1 if on else 0), "kqr_test_batch_steps")
 
 
 def kqr_kernel_build(X, kernel, gamma, k_dtype="fp32", K=None, stream=None):

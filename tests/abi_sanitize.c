@@ -89,6 +89,8 @@ int main(int argc, char** argv) {
   /* test hook */
   EXPECT(kqr_test_core_breakdowns(-1, 1), KQR_EINVAL);
   EXPECT(kqr_test_core_breakdowns(0, 0), KQR_OK);
+  EXPECT(kqr_test_batch_steps(-1), KQR_EINVAL);
+  EXPECT(kqr_test_batch_steps(1), KQR_OK);
 
   /* a valid call without a GPU */
   if (kqr_device_count() == 0) {

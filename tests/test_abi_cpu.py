@@ -122,6 +122,9 @@ def test_invalid_arguments_are_rejected_before_device_work():
     # the breakdown test hook: negative counts rejected, (0, 0) accepted without a device
     assert lib.kqr_test_core_breakdowns(-1, 0) == kqr.KQR_EINVAL
     assert lib.kqr_test_core_breakdowns(0, 0) == kqr.KQR_OK
+    # the batched-step test hook: 0 or 1
+    assert lib.kqr_test_batch_steps(2) == kqr.KQR_EINVAL
+    assert lib.kqr_test_batch_steps(1) == kqr.KQR_OK
     # batch threads: 0 (default) .. 16
     assert lib.kqr_set_batch_threads(17) == kqr.KQR_EINVAL
     assert lib.kqr_set_batch_threads(-1) == kqr.KQR_EINVAL

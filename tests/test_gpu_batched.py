@@ -184,6 +184,34 @@ def test_fit_batch_matches_oracle(dev):
         assert rel <= 1e-6
 
 
+def test_batched_pcg_steps_equal_per_problem_kernels(dev):
+    """kqr_fit_batch with the PCG iterations' vector and preconditioner work in
+    batched launches gives bitwise the results of the same work launched per
+    problem (same device code per problem, same order).  Problems with n <=
+    16384 and a preconditioner rank below 128 take the batched form; their F^T g
+    and F s passes span several workgroups each."""
+    probs = inputs.uneven_batch(count=10, lo=300, hi=6000, seed=9)
+    Xs = [torch.from_numpy(p.X).to(dev) for p in probs]
+    ys = [torch.from_numpy(p.y).to(dev) for p in probs]
+    runs = {}
+    try:
+        for on in (True, False):
+            kqr.kqr_test_batch_steps(on)
+            a, b, inf, st = kqr.kqr_fit_batch(Xs, ys, [p.tau for p in probs], [p.lam for p in probs],
+                                              [p.gamma for p in probs], uniforms=inputs.pivot_uniforms(64, (5, 4)))
+            assert all(s == kqr.KQR_OK for s in st), st
+            runs[on] = ([x.cpu() for x in a], list(b), [i["kapply_calls"] for i in inf],
+                        [i["pcg_iters"] + i["admm_pcg_iters"] for i in inf], [i["rank_used"] for i in inf])
+            say("batched steps", on, "ranks", runs[on][4], "pcg iterations", sum(runs[on][3]))
+    finally:
+        kqr.kqr_test_batch_steps(True)
+    (a1, b1, k1, i1, r1), (a0, b0, k0, i0, r0) = runs[True], runs[False]
+    assert any(0 < r < 128 for r in r1)  # the batched form ran
+    assert r1 == r0 and k1 == k0 and i1 == i0
+    assert all(torch.equal(x, y) for x, y in zip(a1, a0))
+    assert b1 == b0
+
+
 def test_batched_entry_points_validate(dev):
     prob = inputs.workload("c0", n=100)
     X = torch.from_numpy(prob.X).to(dev)
