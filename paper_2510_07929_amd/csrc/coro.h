@@ -12,6 +12,7 @@
 // launches; the fits themselves never block a thread.
 #pragma once
 
+#include <atomic>
 #include <condition_variable>
 #include <coroutine>
 #include <cstring>
@@ -135,9 +136,22 @@ class BatchLauncher {
 // fits has handed over the K-apply requests of all its fits.  Each thread's
 // streams wait for the launch; the launch waits for the work already
 // enqueued on every requester stream.
+//
+// Open mode (a launcher that runs whole PCG iterations, steps_ok()): a round
+// goes out as soon as no thread is running a fit and every fit of the last
+// round has been resumed, carrying whatever requests are pending; fits busy
+// between read-backs (Newton systems, line searches, KKT checks) join a later
+// round instead of holding this one.  A served fit resumes once the host has
+// seen the round complete, so no stream waits on the launch on the device.
 class Rendezvous {
  public:
-  Rendezvous(BatchLauncher* launcher, int threads, bool profile);
+  // One open-mode request: out.served is set when a launch carries it.
+  struct Pending {
+    int id;
+    ApplyReq req;
+    std::atomic<int>* served;
+  };
+  Rendezvous(BatchLauncher* launcher, int threads, bool profile, bool open = false);
   ~Rendezvous();
   Rendezvous(const Rendezvous&) = delete;
   Rendezvous& operator=(const Rendezvous&) = delete;
@@ -145,6 +159,14 @@ class Rendezvous {
   // ids: the problems' batch-wide indices (BatchLauncher slots).
   void arrive(const std::vector<hipStream_t>& streams, const std::vector<int>& ids, const std::vector<ApplyReq>& reqs);
   void leave();  // the calling thread has no live fit left
+  // Open mode: the calling thread starts running fits, of which `resumed`
+  // come back from the last round; then hands over the requests its fits
+  // made (their stream's work so far precedes the launch) and stops.
+  void begin_busy(int resumed);
+  void end_busy(const std::vector<hipStream_t>& streams, const std::vector<Pending>& regs);
+  hipEvent_t done_event() const { return done_; }  // completion of the last round (open mode)
+  void check_failed();
+  bool open() const { return open_; }
   bool exact_ok() const { return launcher_->exact_ok(); }
   bool steps_ok() const { return launcher_->steps_ok(); }
   int64_t launches() const { return launches_; }
@@ -152,9 +174,14 @@ class Rendezvous {
 
  private:
   void fire_locked();
+  void launch_locked();
   hipEvent_t stream_event(hipStream_t s);
   BatchLauncher* launcher_;
   bool profile_;
+  bool open_;
+  int busy_ = 0;      // open mode: threads running fits
+  int inflight_ = 0;  // open mode: fits of the last round not yet resumed
+  std::vector<std::atomic<int>*> served_;
   std::mutex mu_;
   std::condition_variable cv_;
   int active_;
@@ -193,9 +220,12 @@ class Scheduler {
   void park_apply(int slot, std::coroutine_handle<> h, hipStream_t st, ApplyReq r);
   bool exact_ok() const { return rv_ && rv_->exact_ok(); }
   bool steps_ok() const { return rv_ && rv_->steps_ok(); }
+  // A fit resumed from a batched K-apply finds the launch complete (open
+  // mode); otherwise only enqueued ahead of its stream's later work.
+  bool complete_on_resume() const { return rv_ && rv_->open(); }
 
  private:
-  enum State { kRun, kRead, kApply, kDone };
+  enum State { kRun, kRead, kApply, kFlight, kDone };
   struct Slot {
     std::coroutine_handle<> h;
     State state = kRun;
@@ -204,6 +234,7 @@ class Scheduler {
     ApplyReq req;
   };
   void run_handles(const std::vector<std::coroutine_handle<>>& tops);
+  void run_open(const std::vector<std::coroutine_handle<>>& tops);
   void hand_over();
   Rendezvous* rv_;
   std::vector<int> ids_;

@@ -527,7 +527,8 @@ void fit_batch(int nprob, const float* const* X, const double* const* y, const i
   std::unique_ptr<Rendezvous> rv;
   if (batched) {
     launcher.reset(new ProblemLauncher(kms, ns));
-    rv.reset(new Rendezvous(launcher.get(), T, o.profile != 0));
+    // open rounds when the launches run whole PCG iterations (no read-back per iteration)
+    rv.reset(new Rendezvous(launcher.get(), T, o.profile != 0, launcher->steps_ok()));
   }
   std::vector<Slotted> res(static_cast<size_t>(nprob));
   std::vector<std::unique_ptr<Operator>> ops(static_cast<size_t>(nprob));

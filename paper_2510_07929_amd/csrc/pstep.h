@@ -56,6 +56,8 @@ struct PcgStepDesc {
   double* s = nullptr;
   double* Fs = nullptr;
   double* zz = nullptr;
+  // optional pinned host pair written with (p . q, r . r) at the end of the step
+  double* status = nullptr;
 };
 
 // Device tables of the batched launches: the descriptors and, per fit, the

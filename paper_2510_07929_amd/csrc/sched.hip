@@ -3,6 +3,8 @@
 #include "coro.h"
 
 #include <algorithm>
+#include <memory>
+#include <thread>
 
 namespace kqr {
 
@@ -17,8 +19,8 @@ Exec::~Exec() {
 void ApplyAwait::await_suspend(std::coroutine_handle<> h) const { ex->sched->park_apply(ex->slot, h, ex->st, req); }
 
 // ================================================================= rendezvous
-Rendezvous::Rendezvous(BatchLauncher* launcher, int threads, bool profile)
-    : launcher_(launcher), profile_(profile), active_(threads) {
+Rendezvous::Rendezvous(BatchLauncher* launcher, int threads, bool profile, bool open)
+    : launcher_(launcher), profile_(profile), open_(open), active_(threads) {
   KQR_CHECK_HIP(hipStreamCreate(&bst_));
   KQR_CHECK_HIP(hipEventCreateWithFlags(&done_, hipEventDisableTiming));
 }
@@ -69,6 +71,7 @@ void Rendezvous::arrive(const std::vector<hipStream_t>& streams, const std::vect
 
 void Rendezvous::leave() {
   std::unique_lock<std::mutex> lk(mu_);
+  if (open_) return;  // open rounds do not count threads
   --active_;
   if (arrived_ > 0 && arrived_ == active_ && !failed_) {
     try {
@@ -80,22 +83,28 @@ void Rendezvous::leave() {
   }
 }
 
+// The launch of the pending requests on bst_ (after the requesters' work so
+// far), ending with done_.
+void Rendezvous::launch_locked() {
+  for (hipStream_t s : streams_) KQR_CHECK_HIP(hipStreamWaitEvent(bst_, stream_event(s), 0));
+  hipEvent_t a = nullptr, b = nullptr;
+  if (profile_) {
+    KQR_CHECK_HIP(hipEventCreate(&a));
+    KQR_CHECK_HIP(hipEventCreate(&b));
+    KQR_CHECK_HIP(hipEventRecord(a, bst_));
+  }
+  launcher_->launch(ids_, reqs_, bst_);
+  if (profile_) {  // the K-apply alone
+    KQR_CHECK_HIP(hipEventRecord(b, bst_));
+    spans_.emplace_back(a, b);
+  }
+  launcher_->launch_steps(reqs_, bst_);
+  KQR_CHECK_HIP(hipEventRecord(done_, bst_));
+}
+
 void Rendezvous::fire_locked() {
   try {
-    for (hipStream_t s : streams_) KQR_CHECK_HIP(hipStreamWaitEvent(bst_, stream_event(s), 0));
-    hipEvent_t a = nullptr, b = nullptr;
-    if (profile_) {
-      KQR_CHECK_HIP(hipEventCreate(&a));
-      KQR_CHECK_HIP(hipEventCreate(&b));
-      KQR_CHECK_HIP(hipEventRecord(a, bst_));
-    }
-    launcher_->launch(ids_, reqs_, bst_);
-    if (profile_) {  // the K-apply alone
-      KQR_CHECK_HIP(hipEventRecord(b, bst_));
-      spans_.emplace_back(a, b);
-    }
-    launcher_->launch_steps(reqs_, bst_);
-    KQR_CHECK_HIP(hipEventRecord(done_, bst_));
+    launch_locked();
   } catch (...) {
     failed_ = true;
     cv_.notify_all();
@@ -108,6 +117,48 @@ void Rendezvous::fire_locked() {
   ++launches_;
   ++gen_;
   cv_.notify_all();
+}
+
+void Rendezvous::begin_busy(int resumed) {
+  std::unique_lock<std::mutex> lk(mu_);
+  if (failed_) fail(KQR_EHIP, "batched K-apply failed");
+  inflight_ -= resumed;
+  ++busy_;
+}
+
+void Rendezvous::end_busy(const std::vector<hipStream_t>& streams, const std::vector<Pending>& regs) {
+  std::unique_lock<std::mutex> lk(mu_);
+  --busy_;
+  if (failed_) fail(KQR_EHIP, "batched K-apply failed");
+  for (hipStream_t s : streams) {
+    // the requesters' work on s so far precedes the launch
+    KQR_CHECK_HIP(hipEventRecord(stream_event(s), s));
+    if (std::find(streams_.begin(), streams_.end(), s) == streams_.end()) streams_.push_back(s);
+  }
+  for (const Pending& p : regs) {
+    ids_.push_back(p.id);
+    reqs_.push_back(p.req);
+    served_.push_back(p.served);
+  }
+  if (busy_ > 0 || inflight_ > 0 || reqs_.empty()) return;
+  try {
+    launch_locked();
+  } catch (...) {
+    failed_ = true;
+    throw;
+  }
+  for (std::atomic<int>* f : served_) f->store(1, std::memory_order_release);
+  inflight_ = int(reqs_.size());
+  ids_.clear();
+  reqs_.clear();
+  streams_.clear();
+  served_.clear();
+  ++launches_;
+}
+
+void Rendezvous::check_failed() {
+  std::unique_lock<std::mutex> lk(mu_);
+  if (failed_) fail(KQR_EHIP, "batched K-apply failed");
 }
 
 double Rendezvous::device_seconds() {
@@ -157,6 +208,10 @@ void Scheduler::hand_over() {
 
 void Scheduler::run_handles(const std::vector<std::coroutine_handle<>>& tops) {
   if (ids_.size() != tops.size()) fail(KQR_EHIP, "internal: scheduler slots do not match its tasks");
+  if (rv_ && rv_->open()) {
+    run_open(tops);
+    return;
+  }
   struct Leave {  // the other threads must not wait for this one after it stops
     Rendezvous* rv;
     ~Leave() {
@@ -210,6 +265,84 @@ void Scheduler::run_handles(const std::vector<std::coroutine_handle<>>& tops) {
           s.state = kRun;
           break;
         }
+    }
+  }
+}
+
+// Open mode: run the runnable fits (the rendezvous counts this thread busy
+// meanwhile), hand over the requests they made, then poll this thread's reads,
+// its requests' rounds and those rounds' completion until a fit can run.
+void Scheduler::run_open(const std::vector<std::coroutine_handle<>>& tops) {
+  slots_.assign(tops.size(), Slot{});
+  std::unique_ptr<std::atomic<int>[]> served(new std::atomic<int>[tops.size()]);
+  size_t live = 0;
+  for (size_t i = 0; i < tops.size(); ++i) {
+    served[i].store(0);
+    slots_[i].h = tops[i];
+    slots_[i].state = tops[i] && !tops[i].done() ? kRun : kDone;
+    if (slots_[i].state == kRun) ++live;
+  }
+  int resumed = 0;
+  while (live > 0) {
+    rv_->begin_busy(resumed);
+    resumed = 0;
+    std::vector<Rendezvous::Pending> regs;
+    std::vector<hipStream_t> streams;
+    try {
+      for (size_t i = 0; i < slots_.size(); ++i) {
+        Slot& s = slots_[i];
+        if (s.state != kRun) continue;
+        s.state = kDone;  // a park below sets the waiting state
+        s.h.resume();
+        if (tops[i].done()) {
+          s.state = kDone;
+          --live;
+        } else if (s.state == kDone) {
+          fail(KQR_EHIP, "internal: a fit suspended outside a read-back or K-apply");
+        } else if (s.state == kApply) {
+          served[i].store(0);
+          regs.push_back(Rendezvous::Pending{ids_[i], s.req, &served[i]});
+          if (std::find(streams.begin(), streams.end(), s.st) == streams.end()) streams.push_back(s.st);
+        }
+      }
+    } catch (...) {
+      try {
+        rv_->end_busy({}, {});
+      } catch (...) {
+      }
+      throw;
+    }
+    rv_->end_busy(streams, regs);
+    if (live == 0) break;
+    for (bool any = false; !any;) {
+      for (size_t i = 0; i < slots_.size(); ++i) {
+        Slot& s = slots_[i];
+        if (s.state == kRead) {
+          const hipError_t e = hipEventQuery(s.ev);
+          if (e == hipSuccess) {
+            s.state = kRun;
+            any = true;
+          } else if (e != hipErrorNotReady) {
+            KQR_CHECK_HIP(e);
+          }
+        } else if (s.state == kApply && served[i].load(std::memory_order_acquire)) {
+          s.state = kFlight;
+        }
+        if (s.state == kFlight) {
+          const hipError_t e = hipEventQuery(rv_->done_event());
+          if (e == hipSuccess) {
+            s.state = kRun;
+            ++resumed;
+            any = true;
+          } else if (e != hipErrorNotReady) {
+            KQR_CHECK_HIP(e);
+          }
+        }
+      }
+      if (!any) {
+        rv_->check_failed();
+        std::this_thread::yield();
+      }
     }
   }
 }

@@ -218,6 +218,8 @@ Co<PcgStats> Pcg::solve(double c, const double* L, Woodbury* P, const double* b,
     step.p = pb_.p.as<double>();
     step.p32 = p32;
     step.zz = pb_.zz.as<double>();
+    // resumed only after the launch has completed: (p . q, r . r) come with it
+    if (ex_.sched->complete_on_resume()) step.status = ex_.hbuf.as<double>();
   }
   precond_p(RZ0, RZ0, true);
   for (int it = 1; it <= maxit; ++it) {
@@ -232,7 +234,8 @@ Co<PcgStats> Pcg::solve(double c, const double* L, Woodbury* P, const double* b,
               pb_.q.as<double>(), x, pb_.r.as<double>(), Kx, ws_, st);
     }
     double two[2];
-    co_await read_back(ex_, sc + PQ, 2 * sizeof(double), two);  // [PQ, RR]
+    if (batched_step && step.status) memcpy(two, step.status, sizeof(two));
+    else co_await read_back(ex_, sc + PQ, 2 * sizeof(double), two);  // [PQ, RR]
     stats.iters = it;
     stats.resnorm = std::sqrt(std::max(two[1], 0.0));
     if (!(two[0] > 0.0)) {  // curvature lost: the step just taken is unreliable, stop here
