@@ -115,6 +115,9 @@ struct ApplyReq {
   double* out = nullptr;
   bool exact = false;
   const PcgStepDesc* step = nullptr;
+  // the fit has enqueued nothing since the batched launch that last served it
+  // (its inputs come from that launch): the next launch need not wait for its stream
+  bool clean = false;
 };
 
 // One launch for the K-apply requests of several fits (a shared K: K V; or
@@ -138,11 +141,13 @@ class BatchLauncher {
 // enqueued on every requester stream.
 //
 // Open mode (a launcher that runs whole PCG iterations, steps_ok()): a round
-// goes out as soon as no thread is running a fit and every fit of the last
-// round has been resumed, carrying whatever requests are pending; fits busy
-// between read-backs (Newton systems, line searches, KKT checks) join a later
-// round instead of holding this one.  A served fit resumes once the host has
-// seen the round complete, so no stream waits on the launch on the device.
+// goes out as soon as every fit of the last round has come back and handed in
+// its next request (or parked on a read-back, or finished), carrying whatever
+// requests are pending; fits busy between read-backs (Newton systems, line
+// searches, KKT checks) join a later round instead of holding this one.  A
+// served fit resumes once the host has seen its part of the round complete
+// (for a PCG step, the completion tag it writes into the fit's pinned buffer;
+// otherwise the round's event), so no stream waits on the launch on the device.
 class Rendezvous {
  public:
   // One open-mode request: out.served is set when a launch carries it.
@@ -159,11 +164,11 @@ class Rendezvous {
   // ids: the problems' batch-wide indices (BatchLauncher slots).
   void arrive(const std::vector<hipStream_t>& streams, const std::vector<int>& ids, const std::vector<ApplyReq>& reqs);
   void leave();  // the calling thread has no live fit left
-  // Open mode: the calling thread starts running fits, of which `resumed`
-  // come back from the last round; then hands over the requests its fits
-  // made (their stream's work so far precedes the launch) and stops.
-  void begin_busy(int resumed);
-  void end_busy(const std::vector<hipStream_t>& streams, const std::vector<Pending>& regs);
+  // Open mode: `resumed` fits of the last round have come back; regs are the
+  // requests they (or fits back from read-backs) made, streams those of them
+  // whose stream work so far must precede the launch.
+  void hand_in(const std::vector<hipStream_t>& streams, const std::vector<Pending>& regs, int resumed);
+  void abort();  // a scheduler failed: the other threads stop
   hipEvent_t done_event() const { return done_; }  // completion of the last round (open mode)
   void check_failed();
   bool open() const { return open_; }
@@ -179,8 +184,7 @@ class Rendezvous {
   BatchLauncher* launcher_;
   bool profile_;
   bool open_;
-  int busy_ = 0;      // open mode: threads running fits
-  int inflight_ = 0;  // open mode: fits of the last round not yet resumed
+  int inflight_ = 0;  // open mode: fits of the last round not yet back
   std::vector<std::atomic<int>*> served_;
   std::mutex mu_;
   std::condition_variable cv_;

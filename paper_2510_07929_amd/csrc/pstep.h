@@ -56,7 +56,9 @@ struct PcgStepDesc {
   double* s = nullptr;
   double* Fs = nullptr;
   double* zz = nullptr;
-  // optional pinned host pair written with (p . q, r . r) at the end of the step
+  // optional pinned host triple: (p . q, r . r) written at the end of the
+  // step, then (after a system-scope fence) 1 into the third entry, which the
+  // fit's host thread has set to 0 before handing the step in
   double* status = nullptr;
 };
 

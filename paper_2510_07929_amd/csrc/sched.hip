@@ -1,6 +1,7 @@
 // Schedulers of batched fits (coro.h): one per host thread, meeting at a
 // rendezvous for the batched K-apply launches.
 #include "coro.h"
+#include "pstep.h"
 
 #include <algorithm>
 #include <memory>
@@ -119,16 +120,9 @@ void Rendezvous::fire_locked() {
   cv_.notify_all();
 }
 
-void Rendezvous::begin_busy(int resumed) {
+void Rendezvous::hand_in(const std::vector<hipStream_t>& streams, const std::vector<Pending>& regs, int resumed) {
   std::unique_lock<std::mutex> lk(mu_);
-  if (failed_) fail(KQR_EHIP, "batched K-apply failed");
   inflight_ -= resumed;
-  ++busy_;
-}
-
-void Rendezvous::end_busy(const std::vector<hipStream_t>& streams, const std::vector<Pending>& regs) {
-  std::unique_lock<std::mutex> lk(mu_);
-  --busy_;
   if (failed_) fail(KQR_EHIP, "batched K-apply failed");
   for (hipStream_t s : streams) {
     // the requesters' work on s so far precedes the launch
@@ -140,7 +134,7 @@ void Rendezvous::end_busy(const std::vector<hipStream_t>& streams, const std::ve
     reqs_.push_back(p.req);
     served_.push_back(p.served);
   }
-  if (busy_ > 0 || inflight_ > 0 || reqs_.empty()) return;
+  if (inflight_ > 0 || reqs_.empty()) return;
   try {
     launch_locked();
   } catch (...) {
@@ -154,6 +148,11 @@ void Rendezvous::end_busy(const std::vector<hipStream_t>& streams, const std::ve
   streams_.clear();
   served_.clear();
   ++launches_;
+}
+
+void Rendezvous::abort() {
+  std::unique_lock<std::mutex> lk(mu_);
+  failed_ = true;
 }
 
 void Rendezvous::check_failed() {
@@ -269,12 +268,14 @@ void Scheduler::run_handles(const std::vector<std::coroutine_handle<>>& tops) {
   }
 }
 
-// Open mode: run the runnable fits (the rendezvous counts this thread busy
-// meanwhile), hand over the requests they made, then poll this thread's reads,
-// its requests' rounds and those rounds' completion until a fit can run.
+// Open mode: resume the fits back from a round first, each handing in its
+// next request at once, then the fits whose read-backs completed; then poll
+// this thread's read-backs, its requests' rounds and their completion until a
+// fit can run again.
 void Scheduler::run_open(const std::vector<std::coroutine_handle<>>& tops) {
   slots_.assign(tops.size(), Slot{});
   std::unique_ptr<std::atomic<int>[]> served(new std::atomic<int>[tops.size()]);
+  std::vector<char> back(tops.size(), 0);  // resumed from a round (not from a read-back)
   size_t live = 0;
   for (size_t i = 0; i < tops.size(); ++i) {
     served[i].store(0);
@@ -282,68 +283,76 @@ void Scheduler::run_open(const std::vector<std::coroutine_handle<>>& tops) {
     slots_[i].state = tops[i] && !tops[i].done() ? kRun : kDone;
     if (slots_[i].state == kRun) ++live;
   }
-  int resumed = 0;
-  while (live > 0) {
-    rv_->begin_busy(resumed);
-    resumed = 0;
-    std::vector<Rendezvous::Pending> regs;
-    std::vector<hipStream_t> streams;
-    try {
-      for (size_t i = 0; i < slots_.size(); ++i) {
-        Slot& s = slots_[i];
-        if (s.state != kRun) continue;
-        s.state = kDone;  // a park below sets the waiting state
-        s.h.resume();
-        if (tops[i].done()) {
-          s.state = kDone;
-          --live;
-        } else if (s.state == kDone) {
-          fail(KQR_EHIP, "internal: a fit suspended outside a read-back or K-apply");
-        } else if (s.state == kApply) {
-          served[i].store(0);
-          regs.push_back(Rendezvous::Pending{ids_[i], s.req, &served[i]});
-          if (std::find(streams.begin(), streams.end(), s.st) == streams.end()) streams.push_back(s.st);
-        }
-      }
-    } catch (...) {
-      try {
-        rv_->end_busy({}, {});
-      } catch (...) {
-      }
-      throw;
-    }
-    rv_->end_busy(streams, regs);
-    if (live == 0) break;
-    for (bool any = false; !any;) {
-      for (size_t i = 0; i < slots_.size(); ++i) {
-        Slot& s = slots_[i];
-        if (s.state == kRead) {
-          const hipError_t e = hipEventQuery(s.ev);
-          if (e == hipSuccess) {
-            s.state = kRun;
-            any = true;
-          } else if (e != hipErrorNotReady) {
-            KQR_CHECK_HIP(e);
+  // a PCG step's completion tag in the fit's pinned buffer (pstep.h)
+  auto tag = [](const Slot& s) -> const volatile double* {
+    return s.req.step && s.req.step->status ? s.req.step->status + 2 : nullptr;
+  };
+  try {
+    while (live > 0) {
+      for (int pass = 0; pass < 2; ++pass) {
+        for (size_t i = 0; i < slots_.size(); ++i) {
+          Slot& s = slots_[i];
+          if (s.state != kRun || (pass == 0) != (back[i] != 0)) continue;
+          const int resumed = back[i] ? 1 : 0;
+          back[i] = 0;
+          s.state = kDone;  // a park below sets the waiting state
+          s.h.resume();
+          std::vector<Rendezvous::Pending> regs;
+          std::vector<hipStream_t> streams;
+          if (tops[i].done()) {
+            s.state = kDone;
+            --live;
+          } else if (s.state == kDone) {
+            fail(KQR_EHIP, "internal: a fit suspended outside a read-back or K-apply");
+          } else if (s.state == kApply) {
+            served[i].store(0);
+            regs.push_back(Rendezvous::Pending{ids_[i], s.req, &served[i]});
+            if (!s.req.clean) streams.push_back(s.st);
           }
-        } else if (s.state == kApply && served[i].load(std::memory_order_acquire)) {
-          s.state = kFlight;
+          if (resumed || !regs.empty()) rv_->hand_in(streams, regs, resumed);
         }
-        if (s.state == kFlight) {
-          const hipError_t e = hipEventQuery(rv_->done_event());
-          if (e == hipSuccess) {
+      }
+      if (live == 0) break;
+      for (bool any = false; !any;) {
+        for (size_t i = 0; i < slots_.size(); ++i) {
+          Slot& s = slots_[i];
+          if (s.state == kRead) {
+            const hipError_t e = hipEventQuery(s.ev);
+            if (e == hipSuccess) {
+              s.state = kRun;
+              any = true;
+            } else if (e != hipErrorNotReady) {
+              KQR_CHECK_HIP(e);
+            }
+          } else if (s.state == kApply && served[i].load(std::memory_order_acquire)) {
+            s.state = kFlight;
+          }
+          if (s.state != kFlight) continue;
+          const volatile double* t = tag(s);
+          bool complete;
+          if (t) {
+            complete = *t != 0.0;
+          } else {
+            const hipError_t e = hipEventQuery(rv_->done_event());
+            if (e != hipSuccess && e != hipErrorNotReady) KQR_CHECK_HIP(e);
+            complete = e == hipSuccess;
+          }
+          if (complete) {
+            std::atomic_thread_fence(std::memory_order_acquire);
             s.state = kRun;
-            ++resumed;
+            back[i] = 1;
             any = true;
-          } else if (e != hipErrorNotReady) {
-            KQR_CHECK_HIP(e);
           }
         }
-      }
-      if (!any) {
-        rv_->check_failed();
-        std::this_thread::yield();
+        if (!any) {
+          rv_->check_failed();
+          std::this_thread::yield();
+        }
       }
     }
+  } catch (...) {
+    rv_->abort();
+    throw;
   }
 }
 

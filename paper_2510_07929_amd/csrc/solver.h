@@ -27,7 +27,8 @@ class Operator {
   // (pstep.h); then apply_fast_step hands the fast apply u = K v together with
   // that iteration's descriptor.
   bool steps_batched(const Exec& ex) const { return batched_ && ex.sched && ex.sched->steps_ok(); }
-  [[nodiscard]] ApplyAwait apply_fast_step(const double* v, double* u, const PcgStepDesc* step, Exec& ex);
+  [[nodiscard]] ApplyAwait apply_fast_step(const double* v, double* u, const PcgStepDesc* step, bool clean,
+                                           Exec& ex);
   bool materialized() const { return km_.K != nullptr; }
   int64_t calls() const { return calls_; }
   const KMat& kmat() const { return km_; }

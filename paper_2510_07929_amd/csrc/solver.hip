@@ -117,10 +117,10 @@ ApplyAwait Operator::apply_fast(const double* v, const float* v32, double* u, Ex
   return {};
 }
 
-ApplyAwait Operator::apply_fast_step(const double* v, double* u, const PcgStepDesc* step, Exec& ex) {
+ApplyAwait Operator::apply_fast_step(const double* v, double* u, const PcgStepDesc* step, bool clean, Exec& ex) {
   if (!steps_batched(ex)) fail(KQR_EHIP, "internal: batched PCG step without a launcher that runs it");
   ++calls_;
-  return ApplyAwait{&ex, ApplyReq{v, u, false, step}};
+  return ApplyAwait{&ex, ApplyReq{v, u, false, step, clean}};
 }
 
 ApplyAwait Operator::apply_exact(const double* v, double* u, Exec& ex) {
@@ -226,7 +226,10 @@ Co<PcgStats> Pcg::solve(double c, const double* L, Woodbury* P, const double* b,
     if (batched_step) {
       step.rz = cur == 0 ? RZ0 : RZ1;
       step.rz_new = cur == 0 ? RZ1 : RZ0;
-      co_await op_.apply_fast_step(pb_.p.as<double>(), pb_.Kp.as<double>(), &step, ex_);
+      if (step.status) step.status[2] = 0.0;  // the launch sets it when this fit's step is complete
+      // from the second iteration on, nothing of this solve runs on the fit's
+      // stream between two batched steps (the status comes in host memory)
+      co_await op_.apply_fast_step(pb_.p.as<double>(), pb_.Kp.as<double>(), &step, it > 1 && step.status, ex_);
     } else {
       if (fast) co_await op_.apply_fast(pb_.p.as<double>(), p32, pb_.Kp.as<double>(), ex_);
       else co_await op_.apply_exact(pb_.p.as<double>(), pb_.Kp.as<double>(), ex_);

@@ -811,10 +811,15 @@ __global__ __launch_bounds__(1024) void core_solve_steps_kernel(const PcgStepDes
 __global__ __launch_bounds__(1024) void wood_out_p_steps_kernel(const PcgStepDesc* __restrict__ d) {
   const PcgStepDesc& e = d[blockIdx.x];
   wood_out_p_one_body(e.n, e.rank, e.Lw, e.g, e.Fs, e.s, e.zz, e.r, e.sc, e.rz, e.rz_new, e.sump, 0, e.p, e.p32);
-  if (e.status && threadIdx.x == 0) {  // the fit's convergence test reads these on the host
-    e.status[0] = e.sc[e.pq];
-    e.status[1] = e.sc[e.rr];
-    __threadfence_system();
+  if (e.status) {  // the fit's host thread reads these, then resumes the fit
+    __syncthreads();  // every thread's part of the step is written
+    if (threadIdx.x == 0) {
+      __threadfence_system();
+      e.status[0] = e.sc[e.pq];
+      e.status[1] = e.sc[e.rr];
+      __threadfence_system();
+      *static_cast<volatile double*>(e.status + 2) = 1.0;
+    }
   }
 }
 
