@@ -64,9 +64,12 @@ struct ProblemTask {
 int problem_blocks(int64_t n);  // 32-row items of one problem
 
 // u_t = K_t v_t for every task in one persistent launch whose workgroups take
-// (problem, 32-row block) items from a device counter.  The task table goes
+// (problem, 32-row block) items from device counters (one per XCD, items
+// interleaved over them).  The task table goes
 // to the device through a ring of pinned staging copies, so a launch does not
 // wait for the host.  Launches must be ordered on one stream.
+constexpr int kQueueCounters = 8;  // item counters of the problem queue (one per XCD)
+
 class ProblemQueue {
  public:
   explicit ProblemQueue(size_t max_tasks);
@@ -84,7 +87,7 @@ class ProblemQueue {
   DevBuf ctr_;
   hipEvent_t copied_[kRing] = {};
   bool used_[kRing] = {};
-  uint64_t base_ = 0;
+  uint64_t base_[kQueueCounters] = {};
   int next_ = 0;
 };
 

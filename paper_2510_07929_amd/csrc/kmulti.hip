@@ -631,20 +631,32 @@ __device__ __forceinline__ void problem_rows(const ProblemTask& tk, int64_t row0
 }
 
 // Persistent launch: every workgroup takes items (32-row blocks: 4 waves of
-// 8 rows) from the counter until the items run out.  Items are numbered in
-// task order (first_block = exclusive prefix of the tasks' block counts).
-// The counter is never reset: this launch's items are the values
-// [base, base + total) it hands out, and each workgroup takes exactly one
-// value beyond them before it stops, so the next launch starts at
-// base + total + gridDim.x.
+// 8 rows) from a counter until the items run out.  Items are numbered in task
+// order (first_block = exclusive prefix of the tasks' block counts).  Eight
+// counters, one per XCD (workgroups are dealt to the XCDs round-robin in
+// blockIdx order): counter x hands out the items x, x + 8, x + 16, ..., so
+// each XCD still sees an even share of the largest-first order, and the
+// atomics on one address (a few tens of nanoseconds apart at best) are an
+// eighth as many.  The counters are never reset: counter x's items in this
+// launch are its values [base_x, base_x + items_x), and each workgroup on it
+// takes exactly one value beyond them before it stops, so the next launch
+// starts at base_x + items_x + (workgroups on counter x).
+struct QueueBases {
+  unsigned long long b[kQueueCounters];
+};
+
 __global__ __launch_bounds__(256) void kapply_problems_queue_kernel(const ProblemTask* __restrict__ tasks, int ntasks,
                                                                     const int* __restrict__ first_block, int total,
                                                                     unsigned long long* __restrict__ ctr,
-                                                                    unsigned long long base) {
+                                                                    QueueBases base) {
   __shared__ int item_sh;
   const int lane = threadIdx.x & 63;
+  const int x = int(blockIdx.x % kQueueCounters);
   for (;;) {
-    if (threadIdx.x == 0) item_sh = int(atomicAdd(ctr, 1ull) - base);
+    if (threadIdx.x == 0) {
+      const long long k = (long long)(atomicAdd(ctr + x, 1ull) - base.b[x]);
+      item_sh = k < 0 ? -1 : int(min<long long>(k * kQueueCounters + x, total));
+    }
     __syncthreads();
     const int item = item_sh;
     __syncthreads();  // every wave has the item before thread 0 takes the next
@@ -671,8 +683,8 @@ size_t queue_table_bytes(size_t cap) {
 
 ProblemQueue::ProblemQueue(size_t max_tasks)
     : cap_(std::max<size_t>(max_tasks, 1)), slot_bytes_(queue_table_bytes(cap_)), table_(kRing * slot_bytes_),
-      stage_(kRing * slot_bytes_), ctr_(sizeof(unsigned long long)) {
-  KQR_CHECK_HIP(hipMemset(ctr_.ptr, 0, sizeof(unsigned long long)));
+      stage_(kRing * slot_bytes_), ctr_(kQueueCounters * sizeof(unsigned long long)) {
+  KQR_CHECK_HIP(hipMemset(ctr_.ptr, 0, kQueueCounters * sizeof(unsigned long long)));
   for (auto& e : copied_) KQR_CHECK_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
 }
 
@@ -703,11 +715,17 @@ void ProblemQueue::launch(const std::vector<ProblemTask>& tasks, hipStream_t st)
   KQR_CHECK_HIP(hipEventRecord(copied_[k], st));
   used_[k] = true;
   const int grid = std::min(total, kQueueWgs);
+  QueueBases qb;
+  for (int x = 0; x < kQueueCounters; ++x) qb.b[x] = base_[x];
   kapply_problems_queue_kernel<<<grid, 256, 0, st>>>(
       reinterpret_cast<const ProblemTask*>(table), int(ntask),
-      reinterpret_cast<const int*>(table + ntask * sizeof(ProblemTask)), total, ctr_.as<unsigned long long>(), base_);
+      reinterpret_cast<const int*>(table + ntask * sizeof(ProblemTask)), total, ctr_.as<unsigned long long>(), qb);
   KQR_LAUNCH_CHECK();
-  base_ += uint64_t(total) + uint64_t(grid);
+  for (int x = 0; x < kQueueCounters; ++x) {
+    const uint64_t items = x < total ? uint64_t((total - x + kQueueCounters - 1) / kQueueCounters) : 0;
+    const uint64_t wgs = x < grid ? uint64_t((grid - x + kQueueCounters - 1) / kQueueCounters) : 0;
+    base_[x] += items + wgs;
+  }
 }
 
 }  // namespace kqr
