@@ -65,8 +65,8 @@ void Rendezvous::arrive(const std::vector<hipStream_t>& streams, const std::vect
     cv_.wait(lk, [&] { return gen_ != my_gen || failed_; });
   }
   if (failed_) fail(KQR_EHIP, "batched K-apply failed");
-  // done_ cannot be recorded again before every thread of this round has
-  // arrived again, and this thread has not
+  // done_ is recorded again only once every thread served by this launch has
+  // arrived for the next one, which this thread has not yet
   for (hipStream_t s : streams) KQR_CHECK_HIP(hipStreamWaitEvent(s, done_, 0));
 }
 
