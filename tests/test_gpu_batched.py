@@ -212,6 +212,31 @@ def test_batched_pcg_steps_equal_per_problem_kernels(dev):
     assert b1 == b0
 
 
+def test_fit_batch_mixed_sizes_matches_lone_fits(dev):
+    """An uneven batch where one problem is too long for the batched PCG steps
+    (n > 16384: its vector work runs per problem and it resumes on the round's
+    completion event) beside problems that take them: every problem reaches
+    the optimum its lone kqr_fit reaches (the K-apply kernels differ, so the
+    comparison is of objectives and KKT levels, not bits)."""
+    big = inputs.workload("c0", n=17000)
+    small = inputs.uneven_batch(count=4, lo=400, hi=3000, seed=11)
+    probs = [big] + small
+    Xs = [torch.from_numpy(p.X).to(dev) for p in probs]
+    ys = [torch.from_numpy(p.y).to(dev) for p in probs]
+    uni = inputs.pivot_uniforms(64, (5, 6))
+    say("mixed batch", [p.n for p in probs])
+    a, b, inf, st = kqr.kqr_fit_batch(Xs, ys, [p.tau for p in probs], [p.lam for p in probs],
+                                      [p.gamma for p in probs], uniforms=uni)
+    assert all(s == kqr.KQR_OK for s in st), st
+    for i, prob in enumerate(probs):
+        a1, b1, i1, s1 = kqr.kqr_fit(Xs[i], ys[i], prob.tau, prob.lam, "rbf", prob.gamma, uniforms=uni)
+        assert s1 == kqr.KQR_OK
+        rel = abs(inf[i]["obj_p"] - i1["obj_p"]) / (1.0 + abs(i1["obj_p"]))
+        say(f"  n={prob.n} rel_obj={rel:.2e} kkt={inf[i]['eta_kkt']:.2e}/{i1['eta_kkt']:.2e}")
+        assert max(inf[i]["eta_kkt"], inf[i]["eta_gap"]) <= 1e-6
+        assert rel <= 2e-6  # both within 1e-6 of the optimum (each certified by its own KKT level)
+
+
 def test_batched_entry_points_validate(dev):
     prob = inputs.workload("c0", n=100)
     X = torch.from_numpy(prob.X).to(dev)
