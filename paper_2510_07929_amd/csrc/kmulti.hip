@@ -160,18 +160,21 @@ __global__ __launch_bounds__(256) void kv_mfma_kernel(const void* __restrict__ K
 // tile is loaded into registers while the current one is multiplied.  Lane
 // group g of a strip takes the columns [g C/4, (g+1) C/4) of the stage, so
 // every lane reads contiguous 16-byte pieces of K and V from LDS.
-// With MX = 4 (FP32 K only) the same staged tile also serves up to four exact
-// columns: thread t forms, for rows 4 (t/16) .. +3 of the tile and the
+// With MX = 1, 2 or 4 (FP32 K only) the same staged tile also serves that many
+// exact columns: thread t forms, for rows 4 (t/16) .. +3 of the tile and the
 // columns [8 (t%16), 8 (t%16) + 8) of the stage, FP64 products of the FP32
 // entries with FP64 Vx (n x 4) and FP64 sums (the exact operator), so exact
-// applies cost no extra pass over K.
+// applies cost no extra pass over K.  The FP64 work and its registers grow
+// with MX: with one column the kernel keeps three waves per SIMD (as without
+// exact columns), with two or four it runs two.
 template <bool BF16, int MX>
-__global__ __launch_bounds__(256) void kv_staged_kernel(const void* __restrict__ K, int64_t ldk, int64_t n,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MX == 1 ? 3 : 1))) void kv_staged_kernel(const void* __restrict__ K, int64_t ldk, int64_t n,
                                                         int64_t ncols, const float* __restrict__ V,
                                                         const uint16_t* __restrict__ Vhl, int64_t seg_cols,
                                                         double* __restrict__ out, const double* __restrict__ Vx,
                                                         double* __restrict__ outx) {
-  static_assert(MX == 0 || (MX == 4 && !BF16), "exact columns ride on FP32 stages only");
+  static_assert(MX == 0 || ((MX == 1 || MX == 2 || MX == kKvMaxExact) && !BF16),
+                "exact columns (1, 2 or 4) ride on FP32 stages only");
   constexpr int COLS = BF16 ? 256 : 128;   // columns per stage
   constexpr int PER = BF16 ? 8 : 4;        // entries per 16 bytes
   constexpr int ESZ = BF16 ? 2 : 4;
@@ -183,7 +186,7 @@ __global__ __launch_bounds__(256) void kv_staged_kernel(const void* __restrict__
   __shared__ __attribute__((aligned(16))) uint16_t vl[BF16 ? 16 : 1][BF16 ? COLS + 8 : 8];
   // exact columns transposed, 8 columns per 16-lane slice padded to 10 (the
   // 16 lanes' 16-byte reads then start on distinct banks)
-  __shared__ __attribute__((aligned(16))) double vxs[MX > 0 ? MX : 1][MX > 0 ? 16 * 10 : 2];
+  __shared__ __attribute__((aligned(16))) double vxs[MX > 0 ? kKvMaxExact : 1][MX > 0 ? 16 * 10 : 2];
   const int t = threadIdx.x;
   const int lane = t & 63, wave = t >> 6;
   const int li = lane & 15, lg = lane >> 4;
@@ -239,7 +242,7 @@ __global__ __launch_bounds__(256) void kv_staged_kernel(const void* __restrict__
       for (int i = 0; i < NV; ++i) pv[i] = src[i];
     }
     if constexpr (MX > 0) {
-      const u32x4* src = reinterpret_cast<const u32x4*>(Vx + (cb + min(t & 127, cnt - 1)) * MX);
+      const u32x4* src = reinterpret_cast<const u32x4*>(Vx + (cb + min(t & 127, cnt - 1)) * kKvMaxExact);
       px[0] = src[0];
       px[1] = src[1];
     }
@@ -376,7 +379,8 @@ __global__ __launch_bounds__(256) void kv_staged_kernel(const void* __restrict__
         const int64_t row = row_base + 4 * (t >> 4) + rr;
         if (row < n) {
 #pragma unroll
-          for (int j = 0; j < (MX > 0 ? MX : 1); ++j) outx[(int64_t(blockIdx.y) * n + row) * MX + j] = accx[rr][j];
+          for (int j = 0; j < (MX > 0 ? MX : 1); ++j)
+            outx[(int64_t(blockIdx.y) * n + row) * kKvMaxExact + j] = accx[rr][j];
         }
       }
     }
@@ -512,8 +516,14 @@ void kapply_kv_mixed(const KMat& km, int64_t n, const float* V16, int m, double*
   kv_gather_x_kernel<<<dim3((unsigned)((n * 4 + 255) / 256)), 256, 0, st>>>(xsrc, mx, n, Vx);
   KQR_LAUNCH_CHECK();
   const dim3 grid((unsigned)((n + 63) / 64), (unsigned)segs);
-  kv_staged_kernel<false, kKvMaxExact><<<grid, 256, 0, st>>>(km.K, km.ld, n, n, V16, nullptr, seg_cols, part, Vx,
-                                                               partx);
+  // FP64 work for the exact columns asked for (1, 2 or 4): fewer columns, fewer registers
+  if (mx == 1)
+    kv_staged_kernel<false, 1><<<grid, 256, 0, st>>>(km.K, km.ld, n, n, V16, nullptr, seg_cols, part, Vx, partx);
+  else if (mx == 2)
+    kv_staged_kernel<false, 2><<<grid, 256, 0, st>>>(km.K, km.ld, n, n, V16, nullptr, seg_cols, part, Vx, partx);
+  else
+    kv_staged_kernel<false, kKvMaxExact><<<grid, 256, 0, st>>>(km.K, km.ld, n, n, V16, nullptr, seg_cols, part, Vx,
+                                                                 partx);
   KQR_LAUNCH_CHECK();
   if (m > 0) {
     kv_reduce_kernel<<<dim3((unsigned)((n * 16 + 255) / 256)), 256, 0, st>>>(part, segs, n, m, U, ldu);
