@@ -188,10 +188,11 @@ int kqr_test_core_breakdowns(int skip, int count);
 
 /* Test hook for kqr_fit_batch: on = 0 makes the problems' PCG iterations run
  * their vector and preconditioner kernels one problem at a time after each
- * batched K-apply instead of in the batched launches (on = 1, the default);
- * the results are the same either way (process-wide, read when a solve
- * starts).  Returns KQR_OK, or KQR_EINVAL unless on is 0 or 1.  Touches no
- * device. */
+ * batched K-apply instead of in the batched launches, and the batch meet in
+ * lock-step rounds instead of open ones (on = 1, the default); the results
+ * are the same either way (process-wide; read when a batch starts and when a
+ * solve starts).  Returns KQR_OK, or KQR_EINVAL unless on is 0 or 1.  Touches
+ * no device. */
 int kqr_test_batch_steps(int on);
 
 /* ---------------------------------------------------------------- kernel matrix
