@@ -115,3 +115,28 @@ def test_core_breakdown_that_persists_fails_cleanly(setup):
     # the library is usable afterwards
     a, b, info, st = fit(setup)
     assert st == kqr.KQR_OK and info["core_retries"] == 0
+
+
+def test_batch_with_failing_problems_ends_cleanly(setup):
+    """Uneven batch (open rounds) in which every Newton-system core breaks
+    down: each problem fails at its first Newton step, at its own time, while
+    the others are still in batched rounds.  The call ends with KQR_ENUMERIC,
+    and the next batch runs normally."""
+    dev = torch.device("cuda:0")
+    probs = inputs.uneven_batch(count=6, lo=400, hi=2500, seed=13)
+    Xs = [torch.from_numpy(p.X).to(dev) for p in probs]
+    ys = [torch.from_numpy(p.y).to(dev) for p in probs]
+    args = ([p.tau for p in probs], [p.lam for p in probs], [p.gamma for p in probs])
+    uni = inputs.pivot_uniforms(64, (5, 7))
+    # the Phase I cores (one per problem, all built before any Newton step) pass
+    kqr.kqr_test_core_breakdowns(len(probs), 1 << 30)
+    try:
+        with pytest.raises(kqr.KqrError) as e:
+            kqr.kqr_fit_batch(Xs, ys, *args, uniforms=uni)
+    finally:
+        kqr.kqr_test_core_breakdowns(0, 0)
+    say("failing batch:", e.value.status)
+    assert e.value.status == kqr.KQR_ENUMERIC
+    a, b, inf, st = kqr.kqr_fit_batch(Xs, ys, *args, uniforms=uni)
+    assert all(s == kqr.KQR_OK for s in st)
+    assert all(max(i["eta_kkt"], i["eta_gap"]) <= 1e-6 for i in inf)
