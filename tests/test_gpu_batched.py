@@ -237,6 +237,30 @@ def test_fit_batch_mixed_sizes_matches_lone_fits(dev):
         assert rel <= 2e-6  # both within 1e-6 of the optimum (each certified by its own KKT level)
 
 
+def test_fit_batch_bf16_matches_oracle(dev):
+    """An uneven batch with BF16 storage: the inner PCG solves on the BF16 K
+    take the batched steps and open rounds, the refinement residuals use the
+    exact operator per problem; every problem reaches its oracle optimum."""
+    probs = inputs.uneven_batch(count=5, lo=300, hi=1600, seed=17)
+    Xs = [torch.from_numpy(p.X).to(dev) for p in probs]
+    ys = [torch.from_numpy(p.y).to(dev) for p in probs]
+    say("uneven batch, BF16 K", [p.n for p in probs])
+    alphas, betas, infos, st = kqr.kqr_fit_batch(Xs, ys, [p.tau for p in probs], [p.lam for p in probs],
+                                                 [p.gamma for p in probs], k_dtype=kqr.KQR_BF16,
+                                                 kmode=kqr.KQR_KMODE_MATERIALIZE,
+                                                 uniforms=inputs.pivot_uniforms(64, (5, 8)))
+    assert all(s == kqr.KQR_OK for s in st), st
+    assert sum(i["refinements"] for i in infos) > 0
+    for i, prob in enumerate(probs):
+        a = alphas[i].cpu().numpy()
+        ref = osolver.fit(prob.X, prob.y, prob.tau, prob.lam, "rbf", prob.gamma, osolver.OracleOptions(tol=1e-10))
+        opt = ref.kkt["obj_p"]
+        rel = abs(_oracle_obj(prob, prob.tau, a, betas[i]) - opt) / (1 + abs(opt))
+        say(f"  n={prob.n} rel_obj={rel:.2e} kkt={infos[i]['eta_kkt']:.2e} refinements={infos[i]['refinements']}")
+        assert max(infos[i]["eta_kkt"], infos[i]["eta_gap"]) <= 1e-6
+        assert rel <= 1e-6
+
+
 def test_batched_entry_points_validate(dev):
     prob = inputs.workload("c0", n=100)
     X = torch.from_numpy(prob.X).to(dev)
