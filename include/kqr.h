@@ -500,10 +500,11 @@ int kqr_fit_path(const float* X, const double* y, int64_t n, int64_t p, double t
  * K-applies of all problems still running go out as one persistent launch
  * whose workgroups take (problem, 32-row block) items from a device queue,
  * largest problems first.  When a K-apply is a PCG iteration's (Algorithm 3's
- * solves with the Woodbury preconditioner of Lemma 1) of a problem with
- * n[i] <= 16384 and a preconditioner rank below 128, the same launch sequence
- * then runs the rest of that iteration for all such problems in five batched
- * launches (the single-problem kernels' code per problem, so the same results).
+ * solves with the Woodbury preconditioner of Lemma 1) of a problem with a
+ * preconditioner rank below 128, the same launch sequence then runs the rest
+ * of that iteration for all such problems in batched launches (five, and up
+ * to eight more when some n[i] > 16384 need several workgroups per vector;
+ * the single-problem kernels' code per problem, so the same results).
  *  X, y, alpha: host arrays of nprob device pointers (n[i] x p FP32, n[i] FP64,
  *  n[i] FP64); tau, lambda, gamma, n: host arrays; beta, status: host nprob;
  *  info: host nprob (may be NULL).  1 <= nprob <= 256. */

@@ -172,12 +172,20 @@ Co<FitOutcome> run_fit(Operator& op, const Prepared& pr, const double* y, int64_
 // Shared K: gather the requests into V (n x 16 FP32), one K V launch, scatter.
 // With an FP32 K, requests for the exact operator (up to kKvMaxExact per
 // launch) are served by the same pass over K in FP64.
+// Whether the batches also run their PCG iterations' vector and
+// preconditioner work in batched launches (kqr_test_batch_steps).
+std::atomic<bool> g_batch_steps{true};
+
 class KvLauncher : public BatchLauncher {
  public:
   KvLauncher(KMat km, int64_t n)
       : km_(km), n_(n), npad_(std::max<int64_t>(km.ld, n)), V_(size_t(npad_) * 16 * sizeof(float)),
         U_(size_t(n) * 16 * sizeof(double)), part_(kv_scratch_doubles(n) * sizeof(double)) {}
   bool exact_ok() const override { return km_.dtype == KQR_FP32 && km_.layout == 0; }
+  // No batched PCG steps here: in the lock-step rounds of a shared K, the
+  // fits' own step kernels run side by side on their streams, and eleven
+  // batched launches in a row on the launch stream made a lambda path slower
+  // (1.02-1.10 s against 1.01-1.03 s for 50 values at n = 20,000).
   void launch(const std::vector<int>& slots, const std::vector<ApplyReq>& reqs, hipStream_t st) override {
     (void)slots;
     if (reqs.size() > size_t(kKvMaxCols)) fail(KQR_EHIP, "internal: %zu requests for one K V launch", reqs.size());
@@ -221,10 +229,6 @@ class KvLauncher : public BatchLauncher {
   int64_t n_, npad_;
   DevBuf V_, U_, part_;
 };
-
-// Whether the problem batches also run their PCG iterations' vector and
-// preconditioner work in batched launches (kqr_test_batch_steps).
-std::atomic<bool> g_batch_steps{true};
 
 // Different K_i: one launch over (problem, row block) pairs, dealt to the
 // workgroups from a queue (problems_launch), then the batched PCG steps.

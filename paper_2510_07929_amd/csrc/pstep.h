@@ -8,13 +8,15 @@
 //   zz = P^{-1} r  (g = r / L, t = [U 1]^T g, s = C^{-1} t,
 //                   zz = g - (U s_{1..r} + s_{r+1}) / L)     (Woodbury apply)
 //   rz' = r . zz,  p = zz + (rz' / rz) p,  sum(p)           (direction update)
-// For a fit whose vectors fit one workgroup (n <= kOneBlockN) and whose core
-// is small (r + 1 <= kFusedCore), every step above is one launch of a
-// single-fit kernel.  A batch runs the same device bodies once per fit from a
-// table of these descriptors, five launches for every fit of the round, so the
-// sums and their order -- and the results -- are those of the single-fit
-// launches.  The preconditioner runs before the fit has read rr: when rr
-// says the solve has converged (or p . q <= 0), the fit drops zz and p.
+// For a fit whose core is small (r + 1 <= kFusedCore) every step above is a
+// launch or two of single-fit kernels: one launch each when the vectors fit
+// one workgroup (n <= kOneBlockN), else a pass over several workgroups whose
+// partial sums a finishing launch adds.  A batch runs the same device bodies
+// once per fit from a table of these descriptors -- five launches when every
+// fit's vectors fit one workgroup, up to thirteen when some are longer -- so
+// the sums and their order, and the results, are those of the single-fit
+// launches.  The preconditioner runs before the fit has read rr: when rr says
+// the solve has converged (or p . q <= 0), the fit drops zz and p.
 #pragma once
 
 #include <vector>
@@ -56,6 +58,10 @@ struct PcgStepDesc {
   double* s = nullptr;
   double* Fs = nullptr;
   double* zz = nullptr;
+  // vectors longer than one workgroup: the blocks of each pass (red_shape) and
+  // the fit's partial sums (nred = 1: the one-workgroup kernels, no partials)
+  int nred = 1;
+  double* partials = nullptr;
   // optional pinned host triple: (p . q, r . r) written at the end of the
   // step, then (after a system-scope fence) 1 into the third entry, which the
   // fit's host thread has set to 0 before handing the step in
@@ -83,14 +89,22 @@ class PcgStepBatch {
   int next_ = 0;
 };
 
-// The five batched launches (each in the translation unit of its single-fit
+// The batched launches (each in the translation unit of its single-fit
 // kernel).  d: nf device descriptors; gt_first / fs_first: nf + 1 prefix sums
-// of the per-fit workgroup counts.
+// of the per-fit workgroup counts.  The first five serve fits of one workgroup
+// (the Woodbury passes serve every fit).
 void launch_pcg_qxr_steps(const PcgStepDesc* d, int nf, hipStream_t st);
 void launch_wood_gt_steps(const PcgStepDesc* d, const int* gt_first, int nf, int total, hipStream_t st);
 void launch_core_solve_steps(const PcgStepDesc* d, int nf, hipStream_t st);
 void launch_wood_fs_steps(const PcgStepDesc* d, const int* fs_first, int nf, int total, hipStream_t st);
 void launch_wood_out_p_steps(const PcgStepDesc* d, int nf, hipStream_t st);
+// the passes of fits longer than one workgroup (red_first: prefix of their nred)
+void launch_pcg_q_steps(const PcgStepDesc* d, const int* red_first, int nf, int total, hipStream_t st);
+void launch_pcg_xr_steps(const PcgStepDesc* d, const int* red_first, int nf, int total, hipStream_t st);
+void launch_wood_out_steps(const PcgStepDesc* d, const int* red_first, int nf, int total, hipStream_t st);
+void launch_pcg_p_steps(const PcgStepDesc* d, const int* red_first, int nf, int total, hipStream_t st);
+// the finishing sums, one workgroup per fit: which = 0 p.q, 1 r.r, 2 r.zz, 3 sum p (+ status)
+void launch_finalize_steps(const PcgStepDesc* d, int nf, int which, hipStream_t st);
 
 // Workgroup counts of the two multi-workgroup passes for one fit.
 int pcg_step_gt_blocks(const PcgStepDesc& d);

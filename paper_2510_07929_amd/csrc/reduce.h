@@ -34,9 +34,11 @@ constexpr int kOneBlockThreads = 1024;
 
 // Block partials (any block size up to 1024); with a single workgroup they
 // are the result and go to out directly, otherwise reduce_finalize adds them
-// afterwards.
+// afterwards.  block_sums_at takes the block's index and the grid's size
+// explicitly (several grids sharing one launch).
 template <int NQ>
-__device__ __forceinline__ void block_sums(double (&v)[NQ], double* __restrict__ partials, double* __restrict__ out) {
+__device__ __forceinline__ void block_sums_at(double (&v)[NQ], double* __restrict__ partials,
+                                              double* __restrict__ out, int blk, int nblk) {
   __shared__ double sh[NQ][16];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = int(blockDim.x) >> 6;
 #pragma unroll
@@ -50,9 +52,14 @@ __device__ __forceinline__ void block_sums(double (&v)[NQ], double* __restrict__
   if (threadIdx.x < NQ) {
     double s = 0.0;
     for (int w = 0; w < nw; ++w) s += sh[threadIdx.x][w];
-    if (gridDim.x == 1) out[threadIdx.x] = s;
-    else partials[blockIdx.x * NQ + threadIdx.x] = s;
+    if (nblk == 1) out[threadIdx.x] = s;
+    else partials[blk * NQ + threadIdx.x] = s;
   }
+}
+
+template <int NQ>
+__device__ __forceinline__ void block_sums(double (&v)[NQ], double* __restrict__ partials, double* __restrict__ out) {
+  block_sums_at<NQ>(v, partials, out, int(blockIdx.x), int(gridDim.x));
 }
 
 // Sum of v over the (single) workgroup in block_sums' order, returned to

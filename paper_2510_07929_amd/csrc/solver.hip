@@ -4,6 +4,7 @@
 // kernels; the host only sequences launches and reads back the scalars that
 // decide convergence (a few doubles per iteration).
 #include "solver.h"
+#include "reduce.h"
 
 #include <algorithm>
 #include <chrono>
@@ -218,6 +219,8 @@ Co<PcgStats> Pcg::solve(double c, const double* L, Woodbury* P, const double* b,
     step.p = pb_.p.as<double>();
     step.p32 = p32;
     step.zz = pb_.zz.as<double>();
+    step.nred = int(red_shape(n).blocks);
+    step.partials = ws_.partials;
     // resumed only after the launch has completed: (p . q, r . r) come with it
     if (ex_.sched->complete_on_resume()) step.status = ex_.hbuf.as<double>();
   }

@@ -24,6 +24,9 @@ void reduce_finalize(const double* partials, int nblocks, int nq, double* out, h
 
 #define KQR_GRID_STRIDE(i, n) \
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < (n); i += (int64_t)gridDim.x * blockDim.x)
+// The same loop for block blk of a grid of nblk blocks (several grids sharing one launch).
+#define KQR_GRID_STRIDE_AT(i, n, blk, nblk) \
+  for (int64_t i = (blk) * (int64_t)blockDim.x + threadIdx.x; i < (n); i += (int64_t)(nblk) * blockDim.x)
 
 // Elementwise kernels: one thread per element up to kRedBlocks workgroups.
 static inline dim3 ew_grid(int64_t n) {
@@ -84,48 +87,60 @@ void pcg_init_r(int64_t n, const double* b, const double* x, const double* Kx, c
   finish(g, ws.partials, 1, rr_out, st);
 }
 
-// p = zz (+ beta p with beta = sc[rzn]/sc[rz]); p32 = float(p); partial [sum p, r.zz].
-__global__ __launch_bounds__(1024) void pcg_p_kernel(int64_t n, const double* __restrict__ zz,
-                                                    const double* __restrict__ r, double* __restrict__ p,
-                                                    float* __restrict__ p32, const double* __restrict__ sc,
-                                                    int rz_slot, int rzn_slot, int first,
-                                                    double* partials, double* out) {
+// p = zz (+ beta p with beta = sc[rzn]/sc[rz]); p32 = float(p); partial sum p.
+__device__ __forceinline__ void pcg_p_body(int64_t n, const double* __restrict__ zz, double* __restrict__ p,
+                                           float* __restrict__ p32, const double* __restrict__ sc, int rz_slot,
+                                           int rzn_slot, int first, double* partials, double* out, int blk,
+                                           int nblk) {
   const double beta = first ? 0.0 : sc[rzn_slot] / sc[rz_slot];
   double v[1] = {0.0};
-  KQR_GRID_STRIDE(i, n) {
+  KQR_GRID_STRIDE_AT(i, n, blk, nblk) {
     const double pi = first ? zz[i] : fma(beta, p[i], zz[i]);
     p[i] = pi;
     if (p32) p32[i] = float(pi);
     v[0] += pi;
   }
-  (void)r;
-  block_sums<1>(v, partials, out);
+  block_sums_at<1>(v, partials, out, blk, nblk);
+}
+
+__global__ __launch_bounds__(1024) void pcg_p_kernel(int64_t n, const double* __restrict__ zz,
+                                                    double* __restrict__ p, float* __restrict__ p32,
+                                                    const double* __restrict__ sc, int rz_slot, int rzn_slot,
+                                                    int first, double* partials, double* out) {
+  pcg_p_body(n, zz, p, p32, sc, rz_slot, rzn_slot, first, partials, out, int(blockIdx.x), int(gridDim.x));
 }
 
 void pcg_update_p(int64_t n, const double* zz, double* p, float* p32, const double* sc, int rz_slot,
                   int rzn_slot, bool first, Workspace& ws, double* sump_out, hipStream_t st) {
   const RedShape g = red_shape(n);
-  pcg_p_kernel<<<g.blocks, g.threads, 0, st>>>(n, zz, nullptr, p, p32, sc, rz_slot, rzn_slot, first ? 1 : 0,
-                                           ws.partials, sump_out);
+  pcg_p_kernel<<<g.blocks, g.threads, 0, st>>>(n, zz, p, p32, sc, rz_slot, rzn_slot, first ? 1 : 0, ws.partials,
+                                               sump_out);
   KQR_LAUNCH_CHECK();
   finish(g, ws.partials, 1, sump_out, st);
 }
 
 // q = Kp + c*sum(p) + L p ; partial p.q
-__global__ __launch_bounds__(1024) void pcg_q_kernel(int64_t n, const double* __restrict__ Kp,
-                                                    const double* __restrict__ p,
-                                                    const double* __restrict__ L, double c,
-                                                    const double* __restrict__ sc, int sump_slot,
-                                                    double* __restrict__ q, double* partials, double* out) {
+__device__ __forceinline__ void pcg_q_body(int64_t n, const double* __restrict__ Kp, const double* __restrict__ p,
+                                           const double* __restrict__ L, double c, const double* __restrict__ sc,
+                                           int sump_slot, double* __restrict__ q, double* partials, double* out,
+                                           int blk, int nblk) {
   const double cs = c * sc[sump_slot];
   double v[1] = {0.0};
-  KQR_GRID_STRIDE(i, n) {
+  KQR_GRID_STRIDE_AT(i, n, blk, nblk) {
     const double pi = p[i];
     const double qi = Kp[i] + cs + L[i] * pi;
     q[i] = qi;
     v[0] = fma(pi, qi, v[0]);
   }
-  block_sums<1>(v, partials, out);
+  block_sums_at<1>(v, partials, out, blk, nblk);
+}
+
+__global__ __launch_bounds__(1024) void pcg_q_kernel(int64_t n, const double* __restrict__ Kp,
+                                                    const double* __restrict__ p,
+                                                    const double* __restrict__ L, double c,
+                                                    const double* __restrict__ sc, int sump_slot,
+                                                    double* __restrict__ q, double* partials, double* out) {
+  pcg_q_body(n, Kp, p, L, c, sc, sump_slot, q, partials, out, int(blockIdx.x), int(gridDim.x));
 }
 
 void pcg_q(int64_t n, const double* Kp, const double* p, const double* L, double c, const double* sc,
@@ -137,22 +152,30 @@ void pcg_q(int64_t n, const double* Kp, const double* p, const double* L, double
 }
 
 // a = sc[rz]/sc[pq]; x += a p; r -= a q; Kx += a Kp (if Kx); partial r.r
-__global__ __launch_bounds__(1024) void pcg_xr_kernel(int64_t n, const double* __restrict__ p,
-                                                     const double* __restrict__ q,
-                                                     const double* __restrict__ Kp, double* __restrict__ x,
-                                                     double* __restrict__ r, double* __restrict__ Kx,
-                                                     const double* __restrict__ sc, int rz_slot,
-                                                     int pq_slot, double* partials, double* out) {
+__device__ __forceinline__ void pcg_xr_body(int64_t n, const double* __restrict__ p, const double* __restrict__ q,
+                                            const double* __restrict__ Kp, double* __restrict__ x,
+                                            double* __restrict__ r, double* __restrict__ Kx,
+                                            const double* __restrict__ sc, int rz_slot, int pq_slot,
+                                            double* partials, double* out, int blk, int nblk) {
   const double a = sc[rz_slot] / sc[pq_slot];
   double v[1] = {0.0};
-  KQR_GRID_STRIDE(i, n) {
+  KQR_GRID_STRIDE_AT(i, n, blk, nblk) {
     x[i] = fma(a, p[i], x[i]);
     const double ri = fma(-a, q[i], r[i]);
     r[i] = ri;
     if (Kx) Kx[i] = fma(a, Kp[i], Kx[i]);
     v[0] = fma(ri, ri, v[0]);
   }
-  block_sums<1>(v, partials, out);
+  block_sums_at<1>(v, partials, out, blk, nblk);
+}
+
+__global__ __launch_bounds__(1024) void pcg_xr_kernel(int64_t n, const double* __restrict__ p,
+                                                     const double* __restrict__ q,
+                                                     const double* __restrict__ Kp, double* __restrict__ x,
+                                                     double* __restrict__ r, double* __restrict__ Kx,
+                                                     const double* __restrict__ sc, int rz_slot,
+                                                     int pq_slot, double* partials, double* out) {
+  pcg_xr_body(n, p, q, Kp, x, r, Kx, sc, rz_slot, pq_slot, partials, out, int(blockIdx.x), int(gridDim.x));
 }
 
 void pcg_xr(int64_t n, const double* p, const double* q, const double* Kp, double* x, double* r,
@@ -213,6 +236,73 @@ __global__ __launch_bounds__(1024) void pcg_qxr_steps_kernel(const PcgStepDesc* 
 void launch_pcg_qxr_steps(const PcgStepDesc* d, int nf, hipStream_t st) {
   if (nf <= 0) return;
   pcg_qxr_steps_kernel<<<nf, kOneBlockThreads, 0, st>>>(d);
+  KQR_LAUNCH_CHECK();
+}
+
+// Batched PCG steps of fits whose vectors take several workgroups: each
+// fit's nred blocks of kRedThreads, the blocks of fit f starting at first[f];
+// the partial sums of each pass go to the fit's partials and a finishing
+// launch (one workgroup per fit) adds them, as for the single-fit launches.
+__global__ __launch_bounds__(256) void pcg_q_steps_kernel(const PcgStepDesc* __restrict__ d,
+                                                          const int* __restrict__ first, int nf) {
+  const int f = step_of_block(first, nf, int(blockIdx.x));
+  const PcgStepDesc& e = d[f];
+  pcg_q_body(e.n, e.Kp, e.p, e.L, e.c, e.sc, e.sump, e.q, e.partials, e.sc + e.pq, int(blockIdx.x) - first[f],
+             e.nred);
+}
+
+__global__ __launch_bounds__(256) void pcg_xr_steps_kernel(const PcgStepDesc* __restrict__ d,
+                                                           const int* __restrict__ first, int nf) {
+  const int f = step_of_block(first, nf, int(blockIdx.x));
+  const PcgStepDesc& e = d[f];
+  pcg_xr_body(e.n, e.p, e.q, e.Kp, e.x, e.r, e.Kx, e.sc, e.rz, e.pq, e.partials, e.sc + e.rr,
+              int(blockIdx.x) - first[f], e.nred);
+}
+
+__global__ __launch_bounds__(256) void pcg_p_steps_kernel(const PcgStepDesc* __restrict__ d,
+                                                          const int* __restrict__ first, int nf) {
+  const int f = step_of_block(first, nf, int(blockIdx.x));
+  const PcgStepDesc& e = d[f];
+  pcg_p_body(e.n, e.zz, e.p, e.p32, e.sc, e.rz, e.rz_new, 0, e.partials, e.sc + e.sump, int(blockIdx.x) - first[f],
+             e.nred);
+}
+
+// which: 0 p.q, 1 r.r, 2 r.zz (the new rz), 3 sum p -- the last also hands
+// (p.q, r.r) and the completion tag to the fit's status pair when it has one
+__global__ __launch_bounds__(256) void finalize_steps_kernel(const PcgStepDesc* __restrict__ d, int which) {
+  const PcgStepDesc& e = d[blockIdx.x];
+  const int slot = which == 0 ? e.pq : which == 1 ? e.rr : which == 2 ? e.rz_new : e.sump;
+  finish_sums(e.partials, e.nred, 1, e.sc + slot);
+  if (which == 3 && e.status && threadIdx.x == 0) {
+    __threadfence_system();
+    e.status[0] = e.sc[e.pq];
+    e.status[1] = e.sc[e.rr];
+    __threadfence_system();
+    *static_cast<volatile double*>(e.status + 2) = 1.0;
+  }
+}
+
+void launch_pcg_q_steps(const PcgStepDesc* d, const int* first, int nf, int total, hipStream_t st) {
+  if (nf <= 0 || total <= 0) return;
+  pcg_q_steps_kernel<<<total, kRedThreads, 0, st>>>(d, first, nf);
+  KQR_LAUNCH_CHECK();
+}
+
+void launch_pcg_xr_steps(const PcgStepDesc* d, const int* first, int nf, int total, hipStream_t st) {
+  if (nf <= 0 || total <= 0) return;
+  pcg_xr_steps_kernel<<<total, kRedThreads, 0, st>>>(d, first, nf);
+  KQR_LAUNCH_CHECK();
+}
+
+void launch_pcg_p_steps(const PcgStepDesc* d, const int* first, int nf, int total, hipStream_t st) {
+  if (nf <= 0 || total <= 0) return;
+  pcg_p_steps_kernel<<<total, kRedThreads, 0, st>>>(d, first, nf);
+  KQR_LAUNCH_CHECK();
+}
+
+void launch_finalize_steps(const PcgStepDesc* d, int nf, int which, hipStream_t st) {
+  if (nf <= 0) return;
+  finalize_steps_kernel<<<nf, 256, 0, st>>>(d, which);
   KQR_LAUNCH_CHECK();
 }
 

@@ -735,20 +735,29 @@ __global__ __launch_bounds__(1024) void core_solve_kernel(const double* __restri
 
 // out_i = g_i - (Fs_i + s_r) / L_i ; with dot_with, the sum of dot_with . out
 // (one workgroup up to kOneBlockN rows, else partials for reduce_finalize)
-__global__ __launch_bounds__(1024) void wood_out_kernel(int64_t n, int r, const double* __restrict__ L,
-                                                       const double* __restrict__ g, const double* __restrict__ Fs,
-                                                       const double* __restrict__ s, double* __restrict__ out,
-                                                       const double* __restrict__ dot_with,
-                                                       double* __restrict__ partials, double* __restrict__ dot_out) {
+// (Block blk of a grid of nblk; the body also serves the batched PCG steps.)
+__device__ __forceinline__ void wood_out_body(int64_t n, int r, const double* __restrict__ L,
+                                              const double* __restrict__ g, const double* __restrict__ Fs,
+                                              const double* __restrict__ s, double* __restrict__ out,
+                                              const double* __restrict__ dot_with, double* __restrict__ partials,
+                                              double* __restrict__ dot_out, int blk, int nblk) {
   const double sr = s[r];
   double acc[1] = {0.0};
-  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) {
+  for (int64_t i = blk * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(nblk) * blockDim.x) {
     const double fs = r > 0 ? Fs[i] : 0.0;
     const double o = g[i] - (fs + sr) / L[i];
     out[i] = o;
     if (dot_with) acc[0] = fma(o, dot_with[i], acc[0]);
   }
-  if (dot_with) block_sums<1>(acc, partials, dot_out);
+  if (dot_with) block_sums_at<1>(acc, partials, dot_out, blk, nblk);
+}
+
+__global__ __launch_bounds__(1024) void wood_out_kernel(int64_t n, int r, const double* __restrict__ L,
+                                                       const double* __restrict__ g, const double* __restrict__ Fs,
+                                                       const double* __restrict__ s, double* __restrict__ out,
+                                                       const double* __restrict__ dot_with,
+                                                       double* __restrict__ partials, double* __restrict__ dot_out) {
+  wood_out_body(n, r, L, g, Fs, s, out, dot_with, partials, dot_out, int(blockIdx.x), int(gridDim.x));
 }
 
 // One workgroup (n <= kOneBlockN): wood_out with its dot product, then PCG's
@@ -832,6 +841,21 @@ void launch_wood_gt_steps(const PcgStepDesc* d, const int* gt_first, int nf, int
 void launch_core_solve_steps(const PcgStepDesc* d, int nf, hipStream_t st) {
   if (nf <= 0) return;
   core_solve_steps_kernel<<<nf, 1024, 0, st>>>(d);
+  KQR_LAUNCH_CHECK();
+}
+
+// Several workgroups per fit: zz = P^{-1} r and the partials of r . zz.
+__global__ __launch_bounds__(256) void wood_out_steps_kernel(const PcgStepDesc* __restrict__ d,
+                                                             const int* __restrict__ first, int nf) {
+  const int f = step_of_block(first, nf, int(blockIdx.x));
+  const PcgStepDesc& e = d[f];
+  wood_out_body(e.n, e.rank, e.Lw, e.g, e.Fs, e.s, e.zz, e.r, e.partials, e.sc + e.rz_new, int(blockIdx.x) - first[f],
+                e.nred);
+}
+
+void launch_wood_out_steps(const PcgStepDesc* d, const int* first, int nf, int total, hipStream_t st) {
+  if (nf <= 0 || total <= 0) return;
+  wood_out_steps_kernel<<<total, kRedThreads, 0, st>>>(d, first, nf);
   KQR_LAUNCH_CHECK();
 }
 
@@ -1020,7 +1044,7 @@ static int gt_blocks(int64_t n) { return int(std::max<int64_t>(1, std::min<int64
 int pcg_step_gt_blocks(const PcgStepDesc& d) { return d.nblk; }
 
 bool Woodbury::step_desc(PcgStepDesc& d) const {
-  if (n_ > kOneBlockN || R1_ > kFusedCore || (r_ > 0 && (ldf_ & 3))) return false;
+  if (R1_ > kFusedCore || (r_ > 0 && (ldf_ & 3))) return false;
   const int nblk = gt_blocks(n_);
   d.Lw = L_;
   d.F = F_;

@@ -187,9 +187,9 @@ def test_fit_batch_matches_oracle(dev):
 def test_batched_pcg_steps_equal_per_problem_kernels(dev):
     """kqr_fit_batch with the PCG iterations' vector and preconditioner work in
     batched launches gives bitwise the results of the same work launched per
-    problem (same device code per problem, same order).  Problems with n <=
-    16384 and a preconditioner rank below 128 take the batched form; their F^T g
-    and F s passes span several workgroups each."""
+    problem (same device code per problem, same order).  Problems with a
+    preconditioner rank below 128 take the batched form; their F^T g and F s
+    passes span several workgroups each."""
     probs = inputs.uneven_batch(count=10, lo=300, hi=6000, seed=9)
     Xs = [torch.from_numpy(p.X).to(dev) for p in probs]
     ys = [torch.from_numpy(p.y).to(dev) for p in probs]
@@ -212,10 +212,40 @@ def test_batched_pcg_steps_equal_per_problem_kernels(dev):
     assert b1 == b0
 
 
+def test_batched_pcg_steps_on_long_vectors_equal_per_problem_kernels(dev):
+    """An uneven batch with a problem longer than one workgroup (n = 17,000):
+    its PCG iterations' vector work in batched launches (several workgroups
+    per problem, partial sums finished per problem) beside the one-workgroup
+    problems gives bitwise the results of the same work launched per problem."""
+    big = inputs.workload("c0", n=17000)
+    probs = [big] + inputs.uneven_batch(count=3, lo=500, hi=2000, seed=19)
+    Xs = [torch.from_numpy(p.X).to(dev) for p in probs]
+    ys = [torch.from_numpy(p.y).to(dev) for p in probs]
+    uni = inputs.pivot_uniforms(64, (5, 9))
+    runs = {}
+    try:
+        for on in (True, False):
+            kqr.kqr_test_batch_steps(on)
+            # a fixed rank below 128 (the adaptive rule picks 131 for the long problem)
+            a, b, inf, st = kqr.kqr_fit_batch(Xs, ys, [p.tau for p in probs], [p.lam for p in probs],
+                                              [p.gamma for p in probs], rank=64, uniforms=uni)
+            assert all(s == kqr.KQR_OK for s in st), st
+            runs[on] = ([x.cpu() for x in a], list(b), [i["kapply_calls"] for i in inf],
+                        [i["pcg_iters"] + i["admm_pcg_iters"] for i in inf])
+            say("long-vector batched steps", on, "pcg iterations", runs[on][3])
+    finally:
+        kqr.kqr_test_batch_steps(True)
+    (a1, b1, k1, i1), (a0, b0, k0, i0) = runs[True], runs[False]
+    assert k1 == k0 and i1 == i0
+    assert all(torch.equal(x, y) for x, y in zip(a1, a0))
+    assert b1 == b0
+
+
 def test_fit_batch_mixed_sizes_matches_lone_fits(dev):
-    """An uneven batch where one problem is too long for the batched PCG steps
-    (n > 16384: its vector work runs per problem and it resumes on the round's
-    completion event) beside problems that take them: every problem reaches
+    """An uneven batch where one problem's preconditioner core is too large for
+    the batched PCG steps (n = 17,000, adaptive rank 131 >= 128: its vector work
+    runs per problem and it resumes on the round's completion event) beside
+    problems that take them: every problem reaches
     the optimum its lone kqr_fit reaches (the K-apply kernels differ, so the
     comparison is of objectives and KKT levels, not bits)."""
     big = inputs.workload("c0", n=17000)
