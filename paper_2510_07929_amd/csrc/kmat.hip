@@ -351,7 +351,7 @@ void kapply_dense(const KMat& km, int64_t nrows, int64_t ncols, const float* v32
   if (km.layout == 1) {  // symmetric upper-triangle tiles (kpacked.hip)
     if (nrows != ncols) fail(KQR_EINVAL, "the packed layout holds square K only");
     const PackedShape ps = default_packed_shape(km.dtype, exact);
-    const bool fits = scratch && scratch_doubles >= packed_scratch_doubles(nrows, ps.strip);
+    const bool fits = scratch && scratch_doubles >= packed_shape_scratch_doubles(nrows, ps);
     kapply_packed(km, nrows, v32, v64, u, ldu, exact, st, &ps, fits ? scratch : nullptr);
     return;
   }

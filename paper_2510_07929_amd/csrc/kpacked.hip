@@ -333,6 +333,184 @@ __global__ __launch_bounds__(256) void kapply_packed_cols_kernel(const void* __r
   }
 }
 
+// Square blocks of B x B tiles (map 4): workgroup b takes block (BI, BJ),
+// BJ >= BI, of the upper triangle of the block grid (nb = ceil(nt / B) blocks
+// per side) -- tile-rows I = BI B ..  BI B + B - 1 against tile-columns J =
+// BJ B .. BJ B + B - 1, J >= I.  Inside a tile the thread map is that of the
+// columns map (wave w owns 32 columns, LPW lanes per 16-byte row segment, RPS
+// row groups).  Row sums are finished once per tile-row of the block, across
+// lanes and waves through LDS; column sums stay in FP64 per lane across the
+// block's tile-rows and are reduced inside the wave at the end of the block.
+// So a block writes B row partials and B column partials for B^2 tiles,
+// where a strip writes a column partial for every tile: those writes, mixed
+// into the read stream, are what held the other maps back.
+//   rowpart: (I nb + BJ) kPkT + r   (the row sums of tile-row I in block column BJ)
+//   colpart: (BI nt + J) kPkT + c   (the column sums of tile-column J in block row BI)
+template <int CTRL>
+__device__ __forceinline__ double pk_dpp(double x) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, x);
+  const int lo = __builtin_amdgcn_update_dpp(0, int(uint32_t(u)), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, int(uint32_t(u >> 32)), CTRL, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, (uint64_t(uint32_t(hi)) << 32) | uint32_t(lo));
+}
+
+// x + the value of the lane 16 (SWAP16) or 32 lanes away, the same on both lanes
+template <bool SWAP16>
+__device__ __forceinline__ double pk_swap_sum(double x) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, x);
+  const uint32_t l = uint32_t(u), h = uint32_t(u >> 32);
+  uint32_t l0, l1, h0, h1;
+  if constexpr (SWAP16) {
+    const auto a = __builtin_amdgcn_permlane16_swap(l, l, false, false);
+    const auto b = __builtin_amdgcn_permlane16_swap(h, h, false, false);
+    l0 = a[0]; l1 = a[1]; h0 = b[0]; h1 = b[1];
+  } else {
+    const auto a = __builtin_amdgcn_permlane32_swap(l, l, false, false);
+    const auto b = __builtin_amdgcn_permlane32_swap(h, h, false, false);
+    l0 = a[0]; l1 = a[1]; h0 = b[0]; h1 = b[1];
+  }
+  return __builtin_bit_cast(double, (uint64_t(h0) << 32) | l0) + __builtin_bit_cast(double, (uint64_t(h1) << 32) | l1);
+}
+
+template <bool BF16, bool EXACT, int B>
+__global__ __launch_bounds__(256) void kapply_packed_blocks_kernel(const void* __restrict__ Kp, int64_t n,
+                                                                   int64_t nt, int64_t nb,
+                                                                   const float* __restrict__ v32,
+                                                                   const double* __restrict__ v64,
+                                                                   double* __restrict__ rowpart,
+                                                                   double* __restrict__ colpart) {
+  constexpr int VEC = BF16 ? 8 : 4;     // entries per 16-byte load
+  constexpr int LPW = 32 / VEC;         // lanes per row segment of a wave's 32 columns (8 or 4)
+  constexpr int RPS = 64 / LPW;         // rows per wave step (8 or 16)
+  constexpr int STEPS = kPkT / RPS;     // 16 or 8
+  constexpr int ESZ = BF16 ? 2 : 4;
+  constexpr int CHUNKS_PER_ROW = kPkT / VEC;
+  constexpr int NPART = 4 * LPW;        // row partials per row (lanes c of the four waves)
+  typedef typename std::conditional<EXACT, double, float>::type acc_t;
+  __shared__ double rs[NPART][kPkT + 1];
+
+  const int64_t b = blockIdx.x;
+  int64_t BI = 0;
+  {
+    int64_t lo = 0, hi = nb - 1;  // largest BI whose first block is <= b
+    while (lo < hi) {
+      const int64_t mid = (lo + hi + 1) / 2;
+      if (pk_tile_index(mid, mid, nb) <= b) lo = mid;
+      else hi = mid - 1;
+    }
+    BI = lo;
+  }
+  const int64_t BJ = BI + (b - pk_tile_index(BI, BI, nb));
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int c = lane % LPW, g = lane / LPW;
+  const int chunk = w * LPW + c;  // this lane's 16-byte chunk within a tile row
+
+  acc_t vj[B][VEC];
+#pragma unroll
+  for (int jj = 0; jj < B; ++jj)
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) {
+      const int64_t col = (BJ * B + jj) * kPkT + chunk * VEC + e;
+      vj[jj][e] = col < n ? (EXACT ? acc_t(v64[col]) : acc_t(v32[col])) : acc_t(0);
+    }
+  double cold[B][VEC];
+#pragma unroll
+  for (int jj = 0; jj < B; ++jj)
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) cold[jj][e] = 0.0;
+
+  for (int ii = 0; ii < B; ++ii) {
+    const int64_t I = BI * B + ii;
+    if (I >= nt) break;  // the same for the whole workgroup
+    acc_t vi[STEPS];
+#pragma unroll
+    for (int s = 0; s < STEPS; ++s) {
+      const int64_t row = I * kPkT + g + RPS * s;
+      vi[s] = row < n ? (EXACT ? acc_t(v64[row]) : acc_t(v32[row])) : acc_t(0);
+    }
+    double racc[STEPS];
+#pragma unroll
+    for (int s = 0; s < STEPS; ++s) racc[s] = 0.0;
+#pragma unroll
+    for (int jj = 0; jj < B; ++jj) {
+      const int64_t J = BJ * B + jj;
+      if (J < I || J >= nt) continue;  // the same for the whole workgroup
+      const pk_u32x4* tile = reinterpret_cast<const pk_u32x4*>(static_cast<const char*>(Kp) +
+                                                               size_t(pk_tile_index(I, J, nt)) * kPkT * kPkT * ESZ);
+      pk_u32x4 kk[STEPS];
+#pragma unroll
+      for (int s = 0; s < STEPS; ++s) kk[s] = __builtin_nontemporal_load(tile + (g + RPS * s) * CHUNKS_PER_ROW + chunk);
+      acc_t cacc[VEC];
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) cacc[e] = acc_t(0);
+#pragma unroll
+      for (int s = 0; s < STEPS; ++s) {
+        acc_t r = acc_t(0);
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+          const acc_t ke = acc_t(pk_elem<BF16>(kk[s], e));
+          r = fma(ke, vj[jj][e], r);
+          cacc[e] = fma(ke, vi[s], cacc[e]);
+        }
+        racc[s] += double(r);
+      }
+      if (J != I) {  // the diagonal tile feeds its rows only
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) cold[jj][e] += double(cacc[e]);
+      }
+    }
+    // row sums of tile-row I: partials of row g + RPS s in lanes c of every wave
+#pragma unroll
+    for (int s = 0; s < STEPS; ++s) rs[w * LPW + c][g + RPS * s] = racc[s];
+    __syncthreads();
+    {
+      const int row = threadIdx.x >> 1, half = threadIdx.x & 1;
+      double t = 0.0;
+#pragma unroll
+      for (int k = 0; k < NPART / 2; ++k) t += rs[half * (NPART / 2) + k][row];
+      t += pk_dpp<0xB1>(t);  // quad_perm [1, 0, 3, 2]: the other half of the row
+      if (half == 0) rowpart[(size_t(I) * nb + BJ) * kPkT + row] = t;
+    }
+    __syncthreads();  // rs is rewritten by the next tile-row
+  }
+  // column sums: across the RPS row groups of the wave (lane bits above c)
+#pragma unroll
+  for (int jj = 0; jj < B; ++jj) {
+    const int64_t J = BJ * B + jj;
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) {
+      double t = cold[jj][e];
+      if (LPW == 4) t += pk_dpp<0x124>(t);  // row_ror:4
+      t += pk_dpp<0x128>(t);                // row_ror:8
+      t = pk_swap_sum<true>(t);
+      t = pk_swap_sum<false>(t);
+      if (g == 0 && J < nt) colpart[(size_t(BI) * nt + J) * kPkT + chunk * VEC + e] = t;
+    }
+  }
+}
+
+// u_T = the row partials of tile-row T (block columns BT .. nb - 1), then the
+// column partials of tile-column T (block rows 0 .. BT), BT = T / B, each
+// split over four thread groups added in a fixed order.
+__global__ __launch_bounds__(kPkT * 4) void packed_reduce_blocks_kernel(const double* __restrict__ rowpart,
+                                                                       const double* __restrict__ colpart,
+                                                                       int64_t n, int64_t nt, int64_t nb, int B,
+                                                                       double* __restrict__ u, int64_t ldu) {
+  __shared__ double part[4][kPkT];
+  const int64_t T = blockIdx.x;
+  const int r = threadIdx.x % kPkT, h = threadIdx.x / kPkT;
+  const int64_t BT = T / B;
+  const int64_t nrow = nb - BT;
+  const int64_t nterm = nrow + BT + 1;
+  double s = 0.0;
+  for (int64_t k = h; k < nterm; k += 4)
+    s += k < nrow ? rowpart[(size_t(T) * nb + BT + k) * kPkT + r] : colpart[(size_t(k - nrow) * nt + T) * kPkT + r];
+  part[h][r] = s;
+  __syncthreads();
+  const int64_t i = T * kPkT + r;
+  if (h == 0 && i < n) u[i * ldu] = ((part[0][r] + part[1][r]) + part[2][r]) + part[3][r];
+}
+
 // u_i = sum of the strip partials of i's tile-row, then the column partials of
 // the tiles above i's diagonal tile, in that fixed order.  Block I covers the
 // rows of tile-row I with kRedSplit threads per row, each summing every
@@ -381,6 +559,15 @@ size_t packed_scratch_doubles(int64_t n, int strip) {
   return size_t(nt) * nsx * kPkT + size_t(packed_tile_count(n)) * kPkT;
 }
 
+// Map 4 keeps nt x nb row partials and nb x nt column partials (nb = blocks
+// per side); for B >= 2 that is within the strip-1 figure above.
+size_t packed_shape_scratch_doubles(int64_t n, const PackedShape& s) {
+  if (s.map != 4) return packed_scratch_doubles(n, s.strip);
+  const int64_t nt = (n + kPkT - 1) / kPkT;
+  const int64_t nb = (nt + s.strip - 1) / s.strip;
+  return 2 * size_t(nt) * nb * kPkT;
+}
+
 namespace {
 std::mutex g_pk_mu;
 PackedShape g_pk_shape[2][2];  // [bf16][exact]
@@ -407,15 +594,29 @@ void packed_launch(int map, dim3 grid, const void* K, int64_t n, int64_t nt, int
     kapply_packed_rows_kernel<BF16, EXACT, 256><<<grid, 256, 0, st>>>(K, n, nt, strip, nsx, v32, v64, rowpart,
                                                                        colpart, nstrips);
 }
+template <int B>
+void packed_blocks_launch(bool bf, bool exact, dim3 grid, const void* K, int64_t n, int64_t nt, int64_t nb,
+                          const float* v32, const double* v64, double* rowpart, double* colpart, hipStream_t st) {
+  if (bf && exact)
+    kapply_packed_blocks_kernel<true, true, B><<<grid, 256, 0, st>>>(K, n, nt, nb, v32, v64, rowpart, colpart);
+  else if (bf)
+    kapply_packed_blocks_kernel<true, false, B><<<grid, 256, 0, st>>>(K, n, nt, nb, v32, v64, rowpart, colpart);
+  else if (exact)
+    kapply_packed_blocks_kernel<false, true, B><<<grid, 256, 0, st>>>(K, n, nt, nb, v32, v64, rowpart, colpart);
+  else
+    kapply_packed_blocks_kernel<false, false, B><<<grid, 256, 0, st>>>(K, n, nt, nb, v32, v64, rowpart, colpart);
+}
 }  // namespace
 
 PackedShape default_packed_shape(int dtype, int exact) {
   std::lock_guard<std::mutex> lk(g_pk_mu);
   const int d = dtype == KQR_BF16, e = exact != 0;
   if (g_pk_set[d][e]) return g_pk_shape[d][e];
-  // fastest when swept on the c1 shape (n = 50,000): FP32 map 2 / strip 4
-  // (873 us), BF16 map 0 / strip 8 (524 us)
-  return d ? PackedShape{0, 8} : PackedShape{2, 4};
+  // fastest when swept at n = 50,000 (with the reduction): FP32 fast map 4,
+  // blocks of 4 x 4 tiles (818 us), FP32 exact map 0 / strip 4 (870 us), BF16
+  // fast map 0 / strip 8 (525 us), BF16 exact map 0 / strip 16 (532 us)
+  if (d) return e ? PackedShape{0, 16} : PackedShape{0, 8};
+  return e ? PackedShape{0, 4} : PackedShape{4, 4};
 }
 
 void set_packed_shape(int dtype, int exact, PackedShape s) {
@@ -426,6 +627,7 @@ void set_packed_shape(int dtype, int exact, PackedShape s) {
 }
 
 bool packed_shape_supported(const PackedShape& s) {
+  if (s.map == 4) return s.strip == 2 || s.strip == 4;  // block side B
   return s.map >= 0 && s.map <= 3 && s.strip >= 1 && s.strip <= kPkMaxStrip;
 }
 
@@ -437,13 +639,26 @@ void kapply_packed(const KMat& km, int64_t n, const float* v32, const double* v6
   const int strip = sh.strip;
   const int64_t nt = (n + kPkT - 1) / kPkT;
   const int64_t nsx = (nt + strip - 1) / strip;
-  const size_t need = packed_scratch_doubles(n, strip);
+  const size_t need = packed_shape_scratch_doubles(n, sh);
   double* buf = scratch;
   if (!buf) KQR_CHECK_HIP(hipMallocAsync(reinterpret_cast<void**>(&buf), need * sizeof(double), st));
+  const bool bf = km.dtype == KQR_BF16;
+  if (sh.map == 4) {
+    const int64_t nb = (nt + strip - 1) / strip;
+    double* rowpart = buf;
+    double* colpart = buf + size_t(nt) * nb * kPkT;
+    const dim3 grid((unsigned)(nb * (nb + 1) / 2));
+    if (strip == 2) packed_blocks_launch<2>(bf, exact, grid, km.K, n, nt, nb, v32, v64, rowpart, colpart, st);
+    else packed_blocks_launch<4>(bf, exact, grid, km.K, n, nt, nb, v32, v64, rowpart, colpart, st);
+    KQR_LAUNCH_CHECK();
+    packed_reduce_blocks_kernel<<<dim3((unsigned)nt), kPkT * 4, 0, st>>>(rowpart, colpart, n, nt, nb, strip, u, ldu);
+    KQR_LAUNCH_CHECK();
+    if (!scratch) KQR_CHECK_HIP(hipFreeAsync(buf, st));
+    return;
+  }
   double* rowpart = buf;
   double* colpart = buf + size_t(nt) * nsx * kPkT;
   const dim3 grid((unsigned)pk_strips_tail(nt, strip));  // exactly the strips (no idle workgroups)
-  const bool bf = km.dtype == KQR_BF16;
   if (exact && bf) packed_launch<true, true>(sh.map, grid, km.K, n, nt, strip, nsx, v32, v64, rowpart, colpart, st);
   else if (exact) packed_launch<false, true>(sh.map, grid, km.K, n, nt, strip, nsx, v32, v64, rowpart, colpart, st);
   else if (bf) packed_launch<true, false>(sh.map, grid, km.K, n, nt, strip, nsx, v32, v64, rowpart, colpart, st);

@@ -193,14 +193,16 @@ size_t packed_scratch_doubles(int64_t n, int strip);
 void packed_reduce(const double* rowpart, const double* colpart, int64_t n, int strip, double* u, int64_t ldu,
                    hipStream_t st);
 // Launch shape of the packed K-apply: thread map (0 rows / 256 threads,
-// 1 columns, 2 rows / 512 threads, 3 = 2 on a persistent grid) and tiles per
-// workgroup strip.
+// 1 columns, 2 rows / 512 threads, 3 = 2 on a persistent grid, 4 = square
+// blocks of strip x strip tiles, strip 2 or 4) and tiles per workgroup strip.
 constexpr int kPkMaxStrip = 32;
 struct PackedShape {
   int map = 2;
   int strip = 4;
 };
-PackedShape default_packed_shape(int dtype, int exact);  // tuned when set, else FP32 {2, 4}, BF16 {0, 8}
+// Doubles of scratch kapply_packed needs for shape s.
+size_t packed_shape_scratch_doubles(int64_t n, const PackedShape& s);
+PackedShape default_packed_shape(int dtype, int exact);  // tuned when set, else the fastest at n = 50,000
 void set_packed_shape(int dtype, int exact, PackedShape s);
 bool packed_shape_supported(const PackedShape& s);
 // u = K v with K in layout 1 (n x n); scratch may be null (then allocated on st).

@@ -118,20 +118,47 @@ def test_every_packed_shape_and_autotuner(dev, kd):
     K, bound = _bound(X, 0.125, kd, vn)  # the oracle's FP64 K and the storage bound
     dense = unpack(Kp.float().cpu().numpy().astype(np.float64), n)
     stored, stored_scale = dense @ vn, np.abs(dense) @ np.abs(vn)
+    shapes = [(mp, strip) for mp in (0, 1, 2, 3) for strip in (1, 2, 3, 4, 8, 16, 32)] + [(4, 2), (4, 4)]
     for mode in (kqr.KQR_APPLY_FAST, kqr.KQR_APPLY_EXACT):
-        for mp in (0, 1, 2, 3):
-            for strip in (1, 2, 3, 4, 8, 16, 32):
-                kqr.kqr_set_packed_shape(kd, mode, mp, strip)
-                u = kqr.kqr_kernel_apply_packed(v, Kp, n, mode).cpu().numpy()
-                assert np.all(np.abs(u - K @ vn) <= bound), (mode, mp, strip)
-                if mode == kqr.KQR_APPLY_EXACT:  # FP64 on the stored entries
-                    assert np.all(np.abs(u - stored) <= 4 * n * 2.0 ** -53 * stored_scale), (mp, strip)
+        for mp, strip in shapes:
+            kqr.kqr_set_packed_shape(kd, mode, mp, strip)
+            u = kqr.kqr_kernel_apply_packed(v, Kp, n, mode).cpu().numpy()
+            assert np.all(np.abs(u - K @ vn) <= bound), (mode, mp, strip)
+            if mode == kqr.KQR_APPLY_EXACT:  # FP64 on the stored entries
+                assert np.all(np.abs(u - stored) <= 4 * n * 2.0 ** -53 * stored_scale), (mp, strip)
         rep = kqr.kqr_autotune_packed(Kp, n, mode, reps=2)
-        assert len(rep["shapes"]) == 20 and rep["best"]["map"] in (0, 1, 2, 3) and 1 <= rep["best"]["strip"] <= 16
+        assert len(rep["shapes"]) == 22 and rep["best"]["map"] in (0, 1, 2, 3, 4) and 1 <= rep["best"]["strip"] <= 16
     with pytest.raises(kqr.KqrError):
-        kqr.kqr_set_packed_shape(kd, kqr.KQR_APPLY_FAST, 4, 4)
+        kqr.kqr_set_packed_shape(kd, kqr.KQR_APPLY_FAST, 5, 4)
+    with pytest.raises(kqr.KqrError):
+        kqr.kqr_set_packed_shape(kd, kqr.KQR_APPLY_FAST, 4, 3)
     with pytest.raises(kqr.KqrError):
         kqr.kqr_set_packed_shape(kd, kqr.KQR_APPLY_FAST, 0, 33)
+
+
+@pytest.mark.parametrize("kd", ["fp32", "bf16"])
+def test_packed_block_map_ragged_sizes(dev, kd):
+    # map 4 (square blocks of B x B tiles): one tile (n = 1, 100, 128), a
+    # block grid whose last block row and column are partial (n = 129: two
+    # tile-rows; 640: five; 1153: ten), and B = 2 and 4 in both modes, against
+    # the oracle's K and (exact) FP64 on the stored entries
+    p = 5
+    for n in (1, 100, 128, 129, 640, 1153):
+        X, _ = inputs.smooth(n, p, (145, n))
+        Kp = kqr.kqr_kernel_build_packed(torch.from_numpy(X).to(dev), "rbf", 1.0 / p, kd)
+        vn = np.random.default_rng(n + 1).standard_normal(n)
+        v = torch.from_numpy(vn).to(dev)
+        K, bound = _bound(X, 1.0 / p, kd, vn)
+        dense = unpack(Kp.float().cpu().numpy().astype(np.float64), n)
+        stored, stored_scale = dense @ vn, np.abs(dense) @ np.abs(vn)
+        for mode in (kqr.KQR_APPLY_FAST, kqr.KQR_APPLY_EXACT):
+            for B in (2, 4):
+                say("packed blocks", kd, n, mode, B)
+                kqr.kqr_set_packed_shape(kd, mode, 4, B)
+                u = kqr.kqr_kernel_apply_packed(v, Kp, n, mode).cpu().numpy()
+                assert np.all(np.abs(u - K @ vn) <= bound), (n, mode, B)
+                if mode == kqr.KQR_APPLY_EXACT:
+                    assert np.all(np.abs(u - stored) <= 4 * n * 2.0 ** -53 * stored_scale), (n, B)
 
 
 def test_packed_apply_full_size_against_full_layout(dev):
