@@ -285,7 +285,7 @@ def run_materialised(args, prob, kdtype, tune, layout=0, **extra):
     traffic = measured_traffic(args, prob, kdtype, layout)
     last, st = outs[-1]
     kname = ("kapply_rows_kernel (fast, materialised %s K)" % kdtype if layout == 0 else
-             "kapply_packed_*_kernel + packed_reduce_kernel (fast, %s K, symmetric packed tiles)" % kdtype)
+             "kapply_packed_*_kernel + packed_reduce_*_kernel (fast, %s K, symmetric packed tiles)" % kdtype)
     roof = {
         "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
