@@ -224,15 +224,16 @@ int64_t kqr_packed_bytes(int64_t n, int k_dtype);
  * map 0 = a tile row read contiguously by 256-thread workgroups, 2 = the same
  * with 512 threads (half the loads per lane), 3 = map 2 with a persistent grid
  * of 1024 workgroups walking the strips, 1 = each wave owns 32 columns of a
- * tile; strip = tiles per workgroup, 1..16; 4 = each workgroup a square block
- * of strip x strip tiles, strip 2 or 4, with map 1 inside a tile and far fewer
- * partial sums written) on the packed K (device, from
+ * tile; strip = tiles per workgroup, 1..16; 4 and 5 = each workgroup a square
+ * block of strip x strip tiles, strip 2 or 4, with far fewer partial sums
+ * written: each wave owns 32 columns of a tile (4) or 64 columns of half its
+ * rows (5)) on the packed K (device, from
  * kqr_kernel_build_packed) for mode KQR_APPLY_FAST or KQR_APPLY_EXACT, and
  * installs the fastest for k_dtype and that mode (all later packed applies of
  * the process use it).  report: host buffer of cap bytes for a JSON summary,
  * or NULL.  Blocks until the timing is done.
  * kqr_set_packed_shape: installs a shape directly (map 0 to 3 with
- * 1 <= strip <= 32, or map 4 with strip 2 or 4). */
+ * 1 <= strip <= 32, or map 4 or 5 with strip 2 or 4). */
 int kqr_autotune_packed(const void* K, int k_dtype, int64_t n, int mode, int reps, char* report, int64_t cap,
                         void* stream);
 int kqr_set_packed_shape(int k_dtype, int mode, int map, int strip);

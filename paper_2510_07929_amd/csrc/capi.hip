@@ -204,10 +204,10 @@ static void autotune_packed(const KMat& km, int64_t n, bool exact, int reps, cha
   double best_us = 1e300;
   bool first = true;
   try {
-    for (int map : {0, 1, 2, 3, 4})
+    for (int map : {0, 1, 2, 3, 4, 5})
       for (int strip : {1, 2, 4, 8, 16}) {
         const PackedShape s{map, strip};
-        if (!packed_shape_supported(s)) continue;  // map 4: blocks of 2 x 2 or 4 x 4 tiles
+        if (!packed_shape_supported(s)) continue;  // maps 4 and 5: blocks of 2 x 2 or 4 x 4 tiles
         kapply_packed(km, n, v32.as<float>(), v64.as<double>(), u.as<double>(), 1, exact, st, &s,
                       scratch.as<double>());  // warm-up
         KQR_CHECK_HIP(hipEventRecord(e0, st));
@@ -633,7 +633,7 @@ int kqr_set_packed_shape(int k_dtype, int mode, int map, int strip) {
     KQR_REQUIRE(k_dtype == KQR_FP32 || k_dtype == KQR_BF16, "k_dtype must be KQR_FP32 or KQR_BF16");
     KQR_REQUIRE(mode == KQR_APPLY_FAST || mode == KQR_APPLY_EXACT, "mode must be KQR_APPLY_FAST or KQR_APPLY_EXACT");
     const PackedShape s{map, strip};
-    KQR_REQUIRE(packed_shape_supported(s), "need map 0 to 3 with 1 <= strip <= 32, or map 4 with strip 2 or 4");
+    KQR_REQUIRE(packed_shape_supported(s), "need map 0 to 3 with 1 <= strip <= 32, or map 4 or 5 with strip 2 or 4");
     set_packed_shape(k_dtype, mode == KQR_APPLY_EXACT, s);
     tune_record(TuneEntry{"packed", k_dtype, mode == KQR_APPLY_EXACT ? 1 : 0, 0, 1, map, strip, 0, 0, 0.0});
   });

@@ -333,17 +333,21 @@ __global__ __launch_bounds__(256) void kapply_packed_cols_kernel(const void* __r
   }
 }
 
-// Square blocks of B x B tiles (map 4): workgroup b takes block (BI, BJ),
-// BJ >= BI, of the upper triangle of the block grid (nb = ceil(nt / B) blocks
-// per side) -- tile-rows I = BI B ..  BI B + B - 1 against tile-columns J =
-// BJ B .. BJ B + B - 1, J >= I.  Inside a tile the thread map is that of the
-// columns map (wave w owns 32 columns, LPW lanes per 16-byte row segment, RPS
-// row groups).  Row sums are finished once per tile-row of the block, across
-// lanes and waves through LDS; column sums stay in FP64 per lane across the
-// block's tile-rows and are reduced inside the wave at the end of the block.
-// So a block writes B row partials and B column partials for B^2 tiles,
-// where a strip writes a column partial for every tile: those writes, mixed
-// into the read stream, are what held the other maps back.
+// Square blocks of B x B tiles (maps 4 and 5): workgroup b takes block
+// (BI, BJ), BJ >= BI, of the upper triangle of the block grid (nb =
+// ceil(nt / B) blocks per side) -- tile-rows I = BI B ..  BI B + B - 1 against
+// tile-columns J = BJ B .. BJ B + B - 1, J >= I.  Inside a tile, map 4 gives
+// each wave 32 columns of all 128 rows (CW = 4 waves across), map 5 (WIDE)
+// 64 columns of 64 rows (CW = 2 across, RW = 2 down): with BF16 entries a
+// 64-column row segment is a whole 128-byte line, where the 32-column form
+// reads each line in halves from two waves.  LPW lanes cover a wave's row
+// segment, RPS row groups its rows.  Row sums are finished once per tile-row
+// of the block, across lanes and waves through LDS; column sums stay in FP64
+// per lane across the block's tile-rows and are reduced inside the wave at
+// the end of the block (and, for map 5, across the two waves down the rows
+// through LDS).  So a block writes B row partials and B column partials for
+// B^2 tiles, where a strip writes a column partial for every tile: those
+// writes, mixed into the read stream, are what held the strip maps back.
 //   rowpart: (I nb + BJ) kPkT + r   (the row sums of tile-row I in block column BJ)
 //   colpart: (BI nt + J) kPkT + c   (the column sums of tile-column J in block row BI)
 template <int CTRL>
@@ -372,7 +376,7 @@ __device__ __forceinline__ double pk_swap_sum(double x) {
   return __builtin_bit_cast(double, (uint64_t(h0) << 32) | l0) + __builtin_bit_cast(double, (uint64_t(h1) << 32) | l1);
 }
 
-template <bool BF16, bool EXACT, int B>
+template <bool BF16, bool EXACT, int B, bool WIDE>
 __global__ __launch_bounds__(256) void kapply_packed_blocks_kernel(const void* __restrict__ Kp, int64_t n,
                                                                    int64_t nt, int64_t nb,
                                                                    const float* __restrict__ v32,
@@ -380,14 +384,17 @@ __global__ __launch_bounds__(256) void kapply_packed_blocks_kernel(const void* _
                                                                    double* __restrict__ rowpart,
                                                                    double* __restrict__ colpart) {
   constexpr int VEC = BF16 ? 8 : 4;     // entries per 16-byte load
-  constexpr int LPW = 32 / VEC;         // lanes per row segment of a wave's 32 columns (8 or 4)
-  constexpr int RPS = 64 / LPW;         // rows per wave step (8 or 16)
-  constexpr int STEPS = kPkT / RPS;     // 16 or 8
+  constexpr int CW = WIDE ? 2 : 4;      // waves across a tile's columns
+  constexpr int RW = 4 / CW;            // waves down its rows
+  constexpr int LPW = kPkT / CW / VEC;  // lanes per row segment of a wave's columns
+  constexpr int RPS = 64 / LPW;         // rows per wave step
+  constexpr int STEPS = kPkT / RW / RPS;
   constexpr int ESZ = BF16 ? 2 : 4;
   constexpr int CHUNKS_PER_ROW = kPkT / VEC;
-  constexpr int NPART = 4 * LPW;        // row partials per row (lanes c of the four waves)
+  constexpr int NPART = CW * LPW;       // row partials per row (lanes c of the waves sharing the rows)
   typedef typename std::conditional<EXACT, double, float>::type acc_t;
   __shared__ double rs[NPART][kPkT + 1];
+  __shared__ double cs2[RW > 1 ? RW : 1][RW > 1 ? B : 1][kPkT];
 
   const int64_t b = blockIdx.x;
   int64_t BI = 0;
@@ -403,7 +410,9 @@ __global__ __launch_bounds__(256) void kapply_packed_blocks_kernel(const void* _
   const int64_t BJ = BI + (b - pk_tile_index(BI, BI, nb));
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int c = lane % LPW, g = lane / LPW;
-  const int chunk = w * LPW + c;  // this lane's 16-byte chunk within a tile row
+  const int cw = w % CW, rw = w / CW;
+  const int chunk = cw * LPW + c;  // this lane's 16-byte chunk within a tile row
+  const int row0 = rw * (kPkT / RW) + g;  // this lane's rows: row0 + RPS s
 
   acc_t vj[B][VEC];
 #pragma unroll
@@ -425,7 +434,7 @@ __global__ __launch_bounds__(256) void kapply_packed_blocks_kernel(const void* _
     acc_t vi[STEPS];
 #pragma unroll
     for (int s = 0; s < STEPS; ++s) {
-      const int64_t row = I * kPkT + g + RPS * s;
+      const int64_t row = I * kPkT + row0 + RPS * s;
       vi[s] = row < n ? (EXACT ? acc_t(v64[row]) : acc_t(v32[row])) : acc_t(0);
     }
     double racc[STEPS];
@@ -439,7 +448,7 @@ __global__ __launch_bounds__(256) void kapply_packed_blocks_kernel(const void* _
                                                                size_t(pk_tile_index(I, J, nt)) * kPkT * kPkT * ESZ);
       pk_u32x4 kk[STEPS];
 #pragma unroll
-      for (int s = 0; s < STEPS; ++s) kk[s] = __builtin_nontemporal_load(tile + (g + RPS * s) * CHUNKS_PER_ROW + chunk);
+      for (int s = 0; s < STEPS; ++s) kk[s] = __builtin_nontemporal_load(tile + (row0 + RPS * s) * CHUNKS_PER_ROW + chunk);
       acc_t cacc[VEC];
 #pragma unroll
       for (int e = 0; e < VEC; ++e) cacc[e] = acc_t(0);
@@ -459,9 +468,9 @@ __global__ __launch_bounds__(256) void kapply_packed_blocks_kernel(const void* _
         for (int e = 0; e < VEC; ++e) cold[jj][e] += double(cacc[e]);
       }
     }
-    // row sums of tile-row I: partials of row g + RPS s in lanes c of every wave
+    // row sums of tile-row I: partials of row row0 + RPS s in lanes c of the waves sharing it
 #pragma unroll
-    for (int s = 0; s < STEPS; ++s) rs[w * LPW + c][g + RPS * s] = racc[s];
+    for (int s = 0; s < STEPS; ++s) rs[cw * LPW + c][row0 + RPS * s] = racc[s];
     __syncthreads();
     {
       const int row = threadIdx.x >> 1, half = threadIdx.x & 1;
@@ -473,18 +482,31 @@ __global__ __launch_bounds__(256) void kapply_packed_blocks_kernel(const void* _
     }
     __syncthreads();  // rs is rewritten by the next tile-row
   }
-  // column sums: across the RPS row groups of the wave (lane bits above c)
+  // column sums: across the RPS row groups of the wave (lane bits above c),
+  // then (RW = 2) across the two waves down the rows, through LDS
 #pragma unroll
   for (int jj = 0; jj < B; ++jj) {
     const int64_t J = BJ * B + jj;
 #pragma unroll
     for (int e = 0; e < VEC; ++e) {
       double t = cold[jj][e];
-      if (LPW == 4) t += pk_dpp<0x124>(t);  // row_ror:4
-      t += pk_dpp<0x128>(t);                // row_ror:8
+      if (LPW <= 4) t += pk_dpp<0x124>(t);  // row_ror:4
+      if (LPW <= 8) t += pk_dpp<0x128>(t);  // row_ror:8
       t = pk_swap_sum<true>(t);
       t = pk_swap_sum<false>(t);
-      if (g == 0 && J < nt) colpart[(size_t(BI) * nt + J) * kPkT + chunk * VEC + e] = t;
+      if (RW == 1) {
+        if (g == 0 && J < nt) colpart[(size_t(BI) * nt + J) * kPkT + chunk * VEC + e] = t;
+      } else if (g == 0) {
+        cs2[rw][jj][chunk * VEC + e] = t;
+      }
+    }
+  }
+  if (RW > 1) {
+    __syncthreads();
+    for (int k = threadIdx.x; k < B * kPkT; k += 256) {
+      const int jj = k / kPkT, col = k % kPkT;
+      const int64_t J = BJ * B + jj;
+      if (J < nt) colpart[(size_t(BI) * nt + J) * kPkT + col] = cs2[0][jj][col] + cs2[RW > 1 ? 1 : 0][jj][col];
     }
   }
 }
@@ -562,7 +584,7 @@ size_t packed_scratch_doubles(int64_t n, int strip) {
 // Map 4 keeps nt x nb row partials and nb x nt column partials (nb = blocks
 // per side); for B >= 2 that is within the strip-1 figure above.
 size_t packed_shape_scratch_doubles(int64_t n, const PackedShape& s) {
-  if (s.map != 4) return packed_scratch_doubles(n, s.strip);
+  if (s.map != 4 && s.map != 5) return packed_scratch_doubles(n, s.strip);
   const int64_t nt = (n + kPkT - 1) / kPkT;
   const int64_t nb = (nt + s.strip - 1) / s.strip;
   return 2 * size_t(nt) * nb * kPkT;
@@ -594,17 +616,18 @@ void packed_launch(int map, dim3 grid, const void* K, int64_t n, int64_t nt, int
     kapply_packed_rows_kernel<BF16, EXACT, 256><<<grid, 256, 0, st>>>(K, n, nt, strip, nsx, v32, v64, rowpart,
                                                                        colpart, nstrips);
 }
-template <int B>
+template <int B, bool WIDE>
 void packed_blocks_launch(bool bf, bool exact, dim3 grid, const void* K, int64_t n, int64_t nt, int64_t nb,
                           const float* v32, const double* v64, double* rowpart, double* colpart, hipStream_t st) {
   if (bf && exact)
-    kapply_packed_blocks_kernel<true, true, B><<<grid, 256, 0, st>>>(K, n, nt, nb, v32, v64, rowpart, colpart);
+    kapply_packed_blocks_kernel<true, true, B, WIDE><<<grid, 256, 0, st>>>(K, n, nt, nb, v32, v64, rowpart, colpart);
   else if (bf)
-    kapply_packed_blocks_kernel<true, false, B><<<grid, 256, 0, st>>>(K, n, nt, nb, v32, v64, rowpart, colpart);
+    kapply_packed_blocks_kernel<true, false, B, WIDE><<<grid, 256, 0, st>>>(K, n, nt, nb, v32, v64, rowpart, colpart);
   else if (exact)
-    kapply_packed_blocks_kernel<false, true, B><<<grid, 256, 0, st>>>(K, n, nt, nb, v32, v64, rowpart, colpart);
+    kapply_packed_blocks_kernel<false, true, B, WIDE><<<grid, 256, 0, st>>>(K, n, nt, nb, v32, v64, rowpart, colpart);
   else
-    kapply_packed_blocks_kernel<false, false, B><<<grid, 256, 0, st>>>(K, n, nt, nb, v32, v64, rowpart, colpart);
+    kapply_packed_blocks_kernel<false, false, B, WIDE><<<grid, 256, 0, st>>>(K, n, nt, nb, v32, v64, rowpart,
+                                                                             colpart);
 }
 }  // namespace
 
@@ -612,11 +635,11 @@ PackedShape default_packed_shape(int dtype, int exact) {
   std::lock_guard<std::mutex> lk(g_pk_mu);
   const int d = dtype == KQR_BF16, e = exact != 0;
   if (g_pk_set[d][e]) return g_pk_shape[d][e];
-  // fastest when swept at n = 50,000 (with the reduction): FP32 fast map 4,
-  // blocks of 4 x 4 tiles (818 us), FP32 exact map 0 / strip 4 (870 us), BF16
-  // fast map 0 / strip 8 (525 us), BF16 exact map 0 / strip 16 (532 us)
-  if (d) return e ? PackedShape{0, 16} : PackedShape{0, 8};
-  return e ? PackedShape{0, 4} : PackedShape{4, 4};
+  // fastest when swept at n = 50,000 (with the reduction): map 5, blocks of
+  // 4 x 4 tiles, for FP32 fast and exact (817 us each) and BF16 fast
+  // (445 us); BF16 exact map 0 / strip 16 (532 us)
+  if (d && e) return PackedShape{0, 16};
+  return PackedShape{5, 4};
 }
 
 void set_packed_shape(int dtype, int exact, PackedShape s) {
@@ -627,7 +650,7 @@ void set_packed_shape(int dtype, int exact, PackedShape s) {
 }
 
 bool packed_shape_supported(const PackedShape& s) {
-  if (s.map == 4) return s.strip == 2 || s.strip == 4;  // block side B
+  if (s.map == 4 || s.map == 5) return s.strip == 2 || s.strip == 4;  // blocks of strip x strip tiles
   return s.map >= 0 && s.map <= 3 && s.strip >= 1 && s.strip <= kPkMaxStrip;
 }
 
@@ -643,13 +666,16 @@ void kapply_packed(const KMat& km, int64_t n, const float* v32, const double* v6
   double* buf = scratch;
   if (!buf) KQR_CHECK_HIP(hipMallocAsync(reinterpret_cast<void**>(&buf), need * sizeof(double), st));
   const bool bf = km.dtype == KQR_BF16;
-  if (sh.map == 4) {
+  if (sh.map == 4 || sh.map == 5) {
     const int64_t nb = (nt + strip - 1) / strip;
     double* rowpart = buf;
     double* colpart = buf + size_t(nt) * nb * kPkT;
     const dim3 grid((unsigned)(nb * (nb + 1) / 2));
-    if (strip == 2) packed_blocks_launch<2>(bf, exact, grid, km.K, n, nt, nb, v32, v64, rowpart, colpart, st);
-    else packed_blocks_launch<4>(bf, exact, grid, km.K, n, nt, nb, v32, v64, rowpart, colpart, st);
+    const bool wide = sh.map == 5;
+    if (strip == 2 && wide) packed_blocks_launch<2, true>(bf, exact, grid, km.K, n, nt, nb, v32, v64, rowpart, colpart, st);
+    else if (strip == 2) packed_blocks_launch<2, false>(bf, exact, grid, km.K, n, nt, nb, v32, v64, rowpart, colpart, st);
+    else if (wide) packed_blocks_launch<4, true>(bf, exact, grid, km.K, n, nt, nb, v32, v64, rowpart, colpart, st);
+    else packed_blocks_launch<4, false>(bf, exact, grid, km.K, n, nt, nb, v32, v64, rowpart, colpart, st);
     KQR_LAUNCH_CHECK();
     packed_reduce_blocks_kernel<<<dim3((unsigned)nt), kPkT * 4, 0, st>>>(rowpart, colpart, n, nt, nb, strip, u, ldu);
     KQR_LAUNCH_CHECK();

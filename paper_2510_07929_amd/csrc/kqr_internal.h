@@ -193,8 +193,9 @@ size_t packed_scratch_doubles(int64_t n, int strip);
 void packed_reduce(const double* rowpart, const double* colpart, int64_t n, int strip, double* u, int64_t ldu,
                    hipStream_t st);
 // Launch shape of the packed K-apply: thread map (0 rows / 256 threads,
-// 1 columns, 2 rows / 512 threads, 3 = 2 on a persistent grid, 4 = square
-// blocks of strip x strip tiles, strip 2 or 4) and tiles per workgroup strip.
+// 1 columns, 2 rows / 512 threads, 3 = 2 on a persistent grid; 4 and 5 =
+// square blocks of strip x strip tiles, strip 2 or 4, each wave 32 columns
+// of a tile (4) or 64 columns of half its rows (5)) and tiles per strip.
 constexpr int kPkMaxStrip = 32;
 struct PackedShape {
   int map = 2;

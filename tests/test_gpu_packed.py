@@ -118,7 +118,7 @@ def test_every_packed_shape_and_autotuner(dev, kd):
     K, bound = _bound(X, 0.125, kd, vn)  # the oracle's FP64 K and the storage bound
     dense = unpack(Kp.float().cpu().numpy().astype(np.float64), n)
     stored, stored_scale = dense @ vn, np.abs(dense) @ np.abs(vn)
-    shapes = [(mp, strip) for mp in (0, 1, 2, 3) for strip in (1, 2, 3, 4, 8, 16, 32)] + [(4, 2), (4, 4)]
+    shapes = [(mp, strip) for mp in (0, 1, 2, 3) for strip in (1, 2, 3, 4, 8, 16, 32)] + [(4, 2), (4, 4), (5, 2), (5, 4)]
     for mode in (kqr.KQR_APPLY_FAST, kqr.KQR_APPLY_EXACT):
         for mp, strip in shapes:
             kqr.kqr_set_packed_shape(kd, mode, mp, strip)
@@ -127,9 +127,9 @@ def test_every_packed_shape_and_autotuner(dev, kd):
             if mode == kqr.KQR_APPLY_EXACT:  # FP64 on the stored entries
                 assert np.all(np.abs(u - stored) <= 4 * n * 2.0 ** -53 * stored_scale), (mp, strip)
         rep = kqr.kqr_autotune_packed(Kp, n, mode, reps=2)
-        assert len(rep["shapes"]) == 22 and rep["best"]["map"] in (0, 1, 2, 3, 4) and 1 <= rep["best"]["strip"] <= 16
+        assert len(rep["shapes"]) == 24 and rep["best"]["map"] in (0, 1, 2, 3, 4, 5) and 1 <= rep["best"]["strip"] <= 16
     with pytest.raises(kqr.KqrError):
-        kqr.kqr_set_packed_shape(kd, kqr.KQR_APPLY_FAST, 5, 4)
+        kqr.kqr_set_packed_shape(kd, kqr.KQR_APPLY_FAST, 6, 4)
     with pytest.raises(kqr.KqrError):
         kqr.kqr_set_packed_shape(kd, kqr.KQR_APPLY_FAST, 4, 3)
     with pytest.raises(kqr.KqrError):
@@ -138,7 +138,7 @@ def test_every_packed_shape_and_autotuner(dev, kd):
 
 @pytest.mark.parametrize("kd", ["fp32", "bf16"])
 def test_packed_block_map_ragged_sizes(dev, kd):
-    # map 4 (square blocks of B x B tiles): one tile (n = 1, 100, 128), a
+    # maps 4 and 5 (square blocks of B x B tiles): one tile (n = 1, 100, 128), a
     # block grid whose last block row and column are partial (n = 129: two
     # tile-rows; 640: five; 1153: ten), and B = 2 and 4 in both modes, against
     # the oracle's K and (exact) FP64 on the stored entries
@@ -152,13 +152,14 @@ def test_packed_block_map_ragged_sizes(dev, kd):
         dense = unpack(Kp.float().cpu().numpy().astype(np.float64), n)
         stored, stored_scale = dense @ vn, np.abs(dense) @ np.abs(vn)
         for mode in (kqr.KQR_APPLY_FAST, kqr.KQR_APPLY_EXACT):
-            for B in (2, 4):
-                say("packed blocks", kd, n, mode, B)
-                kqr.kqr_set_packed_shape(kd, mode, 4, B)
-                u = kqr.kqr_kernel_apply_packed(v, Kp, n, mode).cpu().numpy()
-                assert np.all(np.abs(u - K @ vn) <= bound), (n, mode, B)
-                if mode == kqr.KQR_APPLY_EXACT:
-                    assert np.all(np.abs(u - stored) <= 4 * n * 2.0 ** -53 * stored_scale), (n, B)
+            for mp in (4, 5):
+                for B in (2, 4):
+                    say("packed blocks", kd, n, mode, mp, B)
+                    kqr.kqr_set_packed_shape(kd, mode, mp, B)
+                    u = kqr.kqr_kernel_apply_packed(v, Kp, n, mode).cpu().numpy()
+                    assert np.all(np.abs(u - K @ vn) <= bound), (n, mode, mp, B)
+                    if mode == kqr.KQR_APPLY_EXACT:
+                        assert np.all(np.abs(u - stored) <= 4 * n * 2.0 ** -53 * stored_scale), (n, mp, B)
 
 
 def test_packed_apply_full_size_against_full_layout(dev):
