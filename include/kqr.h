@@ -230,7 +230,8 @@ int64_t kqr_packed_bytes(int64_t n, int k_dtype);
  * rows (5)) on the packed K (device, from
  * kqr_kernel_build_packed) for mode KQR_APPLY_FAST or KQR_APPLY_EXACT, and
  * installs the fastest for k_dtype and that mode (all later packed applies of
- * the process use it).  report: host buffer of cap bytes for a JSON summary,
+ * the process use it; shapes are tried by map 0 to 5, strips ascending, and
+ * a later shape wins only when at least 2 % faster than the best so far).  report: host buffer of cap bytes for a JSON summary,
  * or NULL.  Blocks until the timing is done.
  * kqr_set_packed_shape: installs a shape directly (map 0 to 3 with
  * 1 <= strip <= 32, or map 4 or 5 with strip 2 or 4). */

@@ -635,11 +635,12 @@ PackedShape default_packed_shape(int dtype, int exact) {
   std::lock_guard<std::mutex> lk(g_pk_mu);
   const int d = dtype == KQR_BF16, e = exact != 0;
   if (g_pk_set[d][e]) return g_pk_shape[d][e];
-  // fastest when swept at n = 50,000 (with the reduction): map 5, blocks of
-  // 4 x 4 tiles, for FP32 fast and exact (817 us each) and BF16 fast
-  // (445 us); BF16 exact map 0 / strip 16 (532 us)
-  if (d && e) return PackedShape{0, 16};
-  return PackedShape{5, 4};
+  // fastest when swept at n = 50,000 (with the reduction; a later shape only
+  // when 2 % faster): FP32 fast map 4, blocks of 4 x 4 tiles (820 us; map 5
+  // 817 us), FP32 exact and BF16 fast map 5, blocks of 4 x 4 tiles (817 and
+  // 445 us), BF16 exact map 0 / strip 16 (532 us)
+  if (d) return e ? PackedShape{0, 16} : PackedShape{5, 4};
+  return e ? PackedShape{5, 4} : PackedShape{4, 4};
 }
 
 void set_packed_shape(int dtype, int exact, PackedShape s) {
