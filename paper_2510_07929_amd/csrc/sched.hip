@@ -283,9 +283,12 @@ void Scheduler::run_open(const std::vector<std::coroutine_handle<>>& tops) {
     slots_[i].state = tops[i] && !tops[i].done() ? kRun : kDone;
     if (slots_[i].state == kRun) ++live;
   }
-  // a PCG step's completion tag in the fit's pinned buffer (pstep.h)
-  auto tag = [](const Slot& s) -> const volatile double* {
-    return s.req.step && s.req.step->status ? s.req.step->status + 2 : nullptr;
+  // a PCG step's completion tag in the fit's pinned buffer (pstep.h): 0.0
+  // until the step's last kernel stores 1.0 there, after the status pair;
+  // read as an acquire load of its bits, which orders the fit's later reads
+  // of the pair after it
+  auto tag = [](const Slot& s) -> const uint64_t* {
+    return s.req.step && s.req.step->status ? reinterpret_cast<const uint64_t*>(s.req.step->status + 2) : nullptr;
   };
   try {
     while (live > 0) {
@@ -328,10 +331,10 @@ void Scheduler::run_open(const std::vector<std::coroutine_handle<>>& tops) {
             s.state = kFlight;
           }
           if (s.state != kFlight) continue;
-          const volatile double* t = tag(s);
+          const uint64_t* t = tag(s);
           bool complete;
           if (t) {
-            complete = *t != 0.0;
+            complete = __atomic_load_n(t, __ATOMIC_ACQUIRE) != 0;
           } else {
             const hipError_t e = hipEventQuery(rv_->done_event());
             if (e != hipSuccess && e != hipErrorNotReady) KQR_CHECK_HIP(e);
