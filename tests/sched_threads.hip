@@ -1,4 +1,4 @@
-// Host-only driver for the batch schedulers (csrc/coro.h, csrc/sched.hip)
+// Host-only test program for the batch schedulers (csrc/coro.h, csrc/sched.hip)
 // under ThreadSanitizer.  Built without the HIP runtime: the stream, event and
 // copy calls the schedulers make are defined here on a "device" thread that
 // runs every enqueued operation in order (one queue for all streams, a valid
@@ -83,7 +83,7 @@ Device* g_dev = nullptr;
 
 }  // namespace
 
-// the opaque runtime types, as this driver models them
+// the opaque runtime types, as this program models them
 struct ihipStream_t {
   int id;
 };

@@ -1,9 +1,9 @@
 """The batch schedulers (csrc/coro.h, csrc/sched.hip) under ThreadSanitizer.
 
 Builds csrc/sched.hip and tests/sched_threads.hip for the host only, with
-ThreadSanitizer and without the HIP runtime (the driver defines the stream,
+ThreadSanitizer and without the HIP runtime (the test program defines the stream,
 event and copy calls on a thread that plays the device), and runs the
-driver: several host threads meet at one rendezvous in lock-step rounds, in
+program: several host threads meet at one rendezvous in lock-step rounds, in
 open rounds and in open rounds whose PCG steps hand their completion through
 the tag in the fit's pinned buffer; every K-apply result is checked, and a
 launch that fails part-way must stop every thread.  A data race makes
