@@ -163,34 +163,56 @@ def test_packed_block_map_ragged_sizes(dev, kd):
 
 
 def test_packed_apply_full_size_against_full_layout(dev):
-    # the c1 shape: n = 50,000, p = 20; exact applies of both layouts use the
-    # same FP32 entries with FP64 products, so they differ by summation order
+    # the c1 shape: n = 50,000, p = 20, in the launch shapes the fits use
+    # (compiled defaults and the tuned table: exact map 5 with blocks of 4 x 4
+    # and 2 x 2 tiles, fast map 4 with 4 x 4) and the strip maps before them;
+    # exact applies of both layouts use the same FP32 entries with FP64
+    # products, so they differ by summation order
     prob = inputs.workload("c1")
     n = prob.n
     Xt = torch.from_numpy(prob.X).to(dev)
     v = torch.from_numpy(np.random.default_rng(7).standard_normal(n)).to(dev)
     say("full-size packed vs full", n)
     Kp = kqr.kqr_kernel_build_packed(Xt, "rbf", prob.gamma, "fp32")
-    up = kqr.kqr_kernel_apply_packed(v, Kp, n, kqr.KQR_APPLY_EXACT)
-    upf = kqr.kqr_kernel_apply_packed(v, Kp, n, kqr.KQR_APPLY_FAST)
+    exact_shapes, fast_shapes = [(5, 4), (5, 2), (0, 4)], [(4, 4), (5, 4), (2, 4)]
+    ups, upfs = [], []
+    for mp, s in exact_shapes:
+        kqr.kqr_set_packed_shape("fp32", kqr.KQR_APPLY_EXACT, mp, s)
+        ups.append(kqr.kqr_kernel_apply_packed(v, Kp, n, kqr.KQR_APPLY_EXACT).cpu().numpy())
+    for mp, s in fast_shapes:
+        kqr.kqr_set_packed_shape("fp32", kqr.KQR_APPLY_FAST, mp, s)
+        upfs.append(kqr.kqr_kernel_apply_packed(v, Kp, n, kqr.KQR_APPLY_FAST).cpu().numpy())
     del Kp
     Kf = kqr.kqr_kernel_build(Xt, "rbf", prob.gamma, "fp32")
-    uf = kqr.kqr_kernel_apply(v, K=Kf, mode=kqr.KQR_APPLY_EXACT)
-    uff = kqr.kqr_kernel_apply(v, K=Kf, mode=kqr.KQR_APPLY_FAST)
+    uf = kqr.kqr_kernel_apply(v, K=Kf, mode=kqr.KQR_APPLY_EXACT).cpu().numpy()
     # sampled rows against the oracle's FP64 entries
     rows = np.random.default_rng(8).choice(n, 64, replace=False)
     Krows = okernel.kernel_block(prob.X[rows], prob.X, "rbf", prob.gamma)
     del Kf
     torch.cuda.empty_cache()
-    up, upf, uf, uff = (t.cpu().numpy() for t in (up, upf, uf, uff))
     scale = np.abs(v.cpu().numpy()).sum()
-    # equal entries up to the mirrored triangle (see the entry test); the
-    # rest is summation order
-    assert np.abs(up - uf).max() <= 8 * U32 * scale
-    assert np.abs(upf - up).max() <= 300 * U32 * scale
     ref = Krows @ v.cpu().numpy()
-    assert np.abs(up[rows] - ref).max() <= 64 * U32 * scale
-    say(f"  max |packed - full| = {np.abs(up - uf).max():.3e}, fast-exact {np.abs(upf - up).max():.3e}")
+    for (mp, s), up in zip(exact_shapes, ups):
+        # equal entries up to the mirrored triangle (see the entry test); the
+        # rest is summation order
+        assert np.abs(up - uf).max() <= 8 * U32 * scale, (mp, s)
+        assert np.abs(up[rows] - ref).max() <= 64 * U32 * scale, (mp, s)
+    for (mp, s), upf in zip(fast_shapes, upfs):
+        assert np.abs(upf - ups[0]).max() <= 300 * U32 * scale, (mp, s)
+        assert np.abs(upf[rows] - ref).max() <= 300 * U32 * scale, (mp, s)
+    say(f"  max |packed - full| = {max(np.abs(u - uf).max() for u in ups):.3e}, "
+        f"fast-exact {max(np.abs(u - ups[0]).max() for u in upfs):.3e}")
+    _install_default_shapes()
+
+
+def _install_default_shapes():
+    """The compiled default packed shapes (what a process uses untuned), so
+    that the fits below run on them after the shape tests above."""
+    F, E = kqr.KQR_APPLY_FAST, kqr.KQR_APPLY_EXACT
+    kqr.kqr_set_packed_shape("fp32", F, 4, 4)
+    kqr.kqr_set_packed_shape("fp32", E, 5, 4)
+    kqr.kqr_set_packed_shape("bf16", F, 5, 4)
+    kqr.kqr_set_packed_shape("bf16", E, 0, 16)
 
 
 @pytest.mark.parametrize("kd", ["fp32", "bf16"])
